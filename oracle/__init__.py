@@ -1,0 +1,2 @@
+"""FP64 CPU oracle (test infrastructure only; never used by the product path)."""
+from . import omniseg_oracle  # noqa: F401

@@ -1,0 +1,696 @@
+"""Plain FP64 CPU oracle of the slide-wise Omni-Seg hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call
+this module; only the tests, the smoke check and the bench's CPU-baseline
+leg do.  It shares no code with the HIP library: its own weight unpacking,
+its own padding, resampling, convolution, head, controller and stitch.
+
+Every step is written as its plain definition, in float64 (integers for the
+integer steps), with numpy matmul as the only library primitive.  The
+paper (arXiv 2305.14566) fixes the pipeline: pad the slide with a colour
+taken from its top-left 2x2 corner (Section 2.1), keep only tissue regions
+(Section 2.1), run the pre-trained dynamic multi-scale network on
+overlapping tiles at several magnifications (Section 2.2), and merge the
+overlapping tile predictions back into a per-tissue whole-slide mask
+(Sections 2.2 and 2.3; constants in Section 3.2).  The paper does not
+define the network, the merge weights, the resampling filter or the tissue
+test.  The readings used here are: a residual U-Net with a
+controller-generated 1x1 dynamic head, a linear-ramp weighted average of
+overlapping tile logits, a box-sum pyramid and a fixed gray threshold on the
+coarsest scale; each function states its reading where it is used.
+
+Parity against the paper's own numbers is unpinned: the paper prints no
+per-pixel values, masks or weights.  The tests pin every function here to
+brute force, closed forms, invariants and independent library routines.
+"""
+
+import math
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# configuration
+# --------------------------------------------------------------------------
+
+
+def make_config(base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
+                stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False):
+    """Oracle configuration.
+
+    scales: log2 downsampling factor of each scale slot (0 = 40x, 1 = 20x,
+    2 = 10x, 3 = 5x); the scale one-hot indexes this list.
+    """
+    return dict(base=int(base), levels=int(levels), head_out=int(head_out),
+                n_classes=int(n_classes), scales=tuple(int(s) for s in scales),
+                tile=int(tile), stride=int(stride), fg_filter=bool(fg_filter),
+                fg_threshold=int(fg_threshold), mask_and_fg=bool(mask_and_fg))
+
+
+def channels(cfg):
+    return [cfg["base"] * 2 ** l for l in range(cfg["levels"])]
+
+
+def head_params(o):
+    """Number of dynamic-head parameters: W1 8x8, W2 8x8, W3 ox8, b1, b2, b3."""
+    return 8 * 8 + 8 * 8 + o * 8 + 8 + 8 + o
+
+
+# --------------------------------------------------------------------------
+# weights: the canonical flat order, unpacked independently of the generator
+# --------------------------------------------------------------------------
+
+
+def unpack_weights(flat, cfg):
+    """Split the canonical flat vector into named float64 arrays.
+
+    Order: encoder levels 0..L-1 (conv_a W, b, conv_b W, b), decoder levels
+    L-2..0 (conv_a W, b, conv_b W, b), precls (only if C_0 != 8), controller
+    W_c (P x (C_{L-1} + n_classes + n_scales)) and b_c.
+    """
+    flat = np.asarray(flat, dtype=np.float64)
+    C = channels(cfg)
+    L = cfg["levels"]
+    pos = [0]
+    out = {}
+
+    def take(name, shape):
+        n = int(np.prod(shape))
+        out[name] = flat[pos[0]:pos[0] + n].reshape(shape)
+        pos[0] += n
+
+    cin = 3
+    for l in range(L):
+        take(f"enc{l}.a.w", (C[l], cin, 3, 3))
+        take(f"enc{l}.a.b", (C[l],))
+        take(f"enc{l}.b.w", (C[l], C[l], 3, 3))
+        take(f"enc{l}.b.b", (C[l],))
+        cin = C[l]
+    for l in range(L - 2, -1, -1):
+        take(f"dec{l}.a.w", (C[l], 3 * C[l], 3, 3))
+        take(f"dec{l}.a.b", (C[l],))
+        take(f"dec{l}.b.w", (C[l], C[l], 3, 3))
+        take(f"dec{l}.b.b", (C[l],))
+    if C[0] != 8:
+        take("precls.w", (8, C[0], 1, 1))
+        take("precls.b", (8,))
+    P = head_params(cfg["head_out"])
+    take("ctrl.w", (P, C[L - 1] + cfg["n_classes"] + len(cfg["scales"])))
+    take("ctrl.b", (P,))
+    if pos[0] != flat.size:
+        raise ValueError(f"weight vector has {flat.size} values, layout needs {pos[0]}")
+    return out
+
+
+def weight_count(cfg):
+    C = channels(cfg)
+    L = cfg["levels"]
+    n = 0
+    cin = 3
+    for l in range(L):
+        n += C[l] * cin * 9 + C[l] + C[l] * C[l] * 9 + C[l]
+        cin = C[l]
+    for l in range(L - 1):
+        n += C[l] * 3 * C[l] * 9 + C[l] + C[l] * C[l] * 9 + C[l]
+    if C[0] != 8:
+        n += 8 * C[0] + 8
+    P = head_params(cfg["head_out"])
+    n += P * (C[L - 1] + cfg["n_classes"] + len(cfg["scales"])) + P
+    return n
+
+
+# --------------------------------------------------------------------------
+# O1  pad colour and padded slide (Section 2.1; Section 3.2)
+# --------------------------------------------------------------------------
+
+
+def pad_colour(rgb):
+    """Per-channel mean of the top-left 2x2 pixels, rounded half up.
+
+    The paper pads every slide with a colour taken as the mean of the 2x2
+    block in its top-left corner (Section 2.1, repeated in Section 3.2).
+    Reading: integer mean with round-half-up, floor((sum + 2) / 4).
+    """
+    rgb = np.asarray(rgb)
+    if rgb.shape[0] < 2 or rgb.shape[1] < 2:
+        raise ValueError("slide must be at least 2x2")
+    s = rgb[:2, :2, :].astype(np.int64).sum(axis=(0, 1))
+    return (s + 2) // 4
+
+
+def padded_slide(rgb, ext_y, ext_x):
+    """The slide extended to (ext_y, ext_x) with the pad colour (int64).
+
+    Reading of the pad extent: the slide's (0, 0) stays the grid origin and
+    the pad reaches right and down only as far as the tiles need.
+    """
+    H, W, _ = rgb.shape
+    if ext_y < H or ext_x < W:
+        raise ValueError("extent smaller than the slide")
+    P = np.empty((ext_y, ext_x, 3), np.int64)
+    P[:, :, :] = pad_colour(rgb)[None, None, :]
+    P[:H, :W, :] = rgb
+    return P
+
+
+# --------------------------------------------------------------------------
+# O2  multi-scale pyramid (Section 2.2: 40x, 10x, 5x from the 40x base)
+# --------------------------------------------------------------------------
+
+
+def level_size(n, k):
+    """Pixels along one axis at scale k (factor 2**k): ceil(n / 2**k)."""
+    f = 2 ** k
+    return (n + f - 1) // f
+
+
+def box_sum(P, f):
+    """S(y, x, c) = sum over a, b < f of P(f y + a, f x + b, c)."""
+    Hp, Wp, C = P.shape
+    if Hp % f or Wp % f:
+        raise ValueError("extent must be a multiple of the factor")
+    return P.reshape(Hp // f, f, Wp // f, f, C).sum(axis=(1, 3))
+
+
+def scale_sums(rgb, k, ext_y, ext_x):
+    """Integer box sums S_k over [0, ext_y) x [0, ext_x) at scale k."""
+    f = 2 ** k
+    P = padded_slide(rgb, max(ext_y * f, rgb.shape[0]), max(ext_x * f, rgb.shape[1]))
+    P = P[:ext_y * f, :ext_x * f]
+    return box_sum(P, f)
+
+
+# --------------------------------------------------------------------------
+# O3  tissue map (Section 2.1 blank-region removal; reading: gray threshold)
+# --------------------------------------------------------------------------
+
+
+def tissue_map(rgb, kc, threshold=220):
+    """Coarse foreground map at scale kc: 1000*gray < 1000*threshold.
+
+    gray*1000 = 299 R + 587 G + 114 B of the box mean; in integers on the
+    box sums: 299 S_R + 587 S_G + 114 S_B < threshold * 1000 * 4**kc.
+    """
+    H, W, _ = rgb.shape
+    Hc, Wc = level_size(H, kc), level_size(W, kc)
+    S = scale_sums(rgb, kc, Hc, Wc)
+    g = 299 * S[..., 0] + 587 * S[..., 1] + 114 * S[..., 2]
+    return g < threshold * 1000 * 4 ** kc
+
+
+# --------------------------------------------------------------------------
+# O4  tile grid and foreground tile list (Section 2.2 overlap tiling)
+# --------------------------------------------------------------------------
+
+
+def grid_count(n_k, T, s):
+    """Tiles along one axis: the origins 0, s, 2s, ... until the tiles cover n_k."""
+    if n_k <= T:
+        return 1
+    return -(-(n_k - T) // s) + 1
+
+
+def grid_extent(n_k, T, s):
+    return (grid_count(n_k, T, s) - 1) * s + T
+
+
+def tile_keeps(fg, kc, k, T, s, jy, jx):
+    """Keep the tile iff a coarse foreground pixel overlaps its 40x footprint.
+
+    Coarse row r covers 40x rows [r f_kc, (r+1) f_kc); the tile covers
+    [jy s f_k, (jy s + T) f_k).  Same on columns.
+    """
+    fk, fc = 2 ** k, 2 ** kc
+    r = np.arange(fg.shape[0])
+    c = np.arange(fg.shape[1])
+    rows = (r * fc < (jy * s + T) * fk) & ((r + 1) * fc > jy * s * fk)
+    cols = (c * fc < (jx * s + T) * fk) & ((c + 1) * fc > jx * s * fk)
+    return bool(fg[np.ix_(rows, cols)].any())
+
+
+def tile_list(slides_hw, cfg, fg_maps=None):
+    """Ordered list of kept tiles (slide, scale slot, jy, jx).
+
+    Order: slide, scale slot ascending, tile row, tile column.
+    """
+    T, s = cfg["tile"], cfg["stride"]
+    kc = max(cfg["scales"])
+    out = []
+    for n, (H, W) in enumerate(slides_hw):
+        for si, k in enumerate(cfg["scales"]):
+            ny = grid_count(level_size(H, k), T, s)
+            nx = grid_count(level_size(W, k), T, s)
+            for jy in range(ny):
+                for jx in range(nx):
+                    if cfg["fg_filter"] and not tile_keeps(fg_maps[n], kc, k, T, s, jy, jx):
+                        continue
+                    out.append((n, si, jy, jx))
+    return out
+
+
+def tile_input(rgb, k, T, s, jy, jx):
+    """The network input of one tile: x = S_k / (255 * 4**k), channels first."""
+    H, W, _ = rgb.shape
+    ey = grid_extent(level_size(H, k), T, s)
+    ex = grid_extent(level_size(W, k), T, s)
+    S = scale_sums(rgb, k, ey, ex)[jy * s:jy * s + T, jx * s:jx * s + T]
+    return np.transpose(S, (2, 0, 1)).astype(np.float64) / (255.0 * 4 ** k)
+
+
+# --------------------------------------------------------------------------
+# O5-O6  residual U-Net backbone
+# --------------------------------------------------------------------------
+
+
+def conv3x3(X, Wt, b):
+    """3x3 cross-correlation, stride 1, zero padding 1.
+
+    Y[o, y, x] = b[o] + sum_{c, i, j} W[o, c, i, j] X[c, y + i - 1, x + j - 1]
+    with X taken as 0 outside the tile.
+    """
+    Cin, H, W = X.shape
+    Xp = np.zeros((Cin, H + 2, W + 2))
+    Xp[:, 1:H + 1, 1:W + 1] = X
+    Y = np.zeros((Wt.shape[0], H * W))
+    for i in range(3):
+        for j in range(3):
+            Y += Wt[:, :, i, j] @ Xp[:, i:i + H, j:j + W].reshape(Cin, H * W)
+    return Y.reshape(-1, H, W) + b[:, None, None]
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+def maxpool2(X):
+    C, H, W = X.shape
+    return X.reshape(C, H // 2, 2, W // 2, 2).max(axis=(2, 4))
+
+
+def up2(X):
+    """Nearest upsampling by 2: up2(D)(y, x) = D(y // 2, x // 2)."""
+    return np.repeat(np.repeat(X, 2, axis=1), 2, axis=2)
+
+
+def unet_forward(x, wts, cfg, keep=False):
+    """Residual U-Net on one tile.
+
+    Encoder level l: A = ReLU(conv_a(X_l)); E_l = ReLU(conv_b(A) + A);
+    X_{l+1} = maxpool2(E_l).  Decoder level l = L-2..0:
+    Z = concat(up2(D_{l+1}), E_l); A = ReLU(conv_a(Z)); D_l = ReLU(conv_b(A) + A),
+    with D_{L-1} = E_{L-1}.  Head input F = ReLU(W_p D_0 + b_p) if C_0 != 8,
+    else D_0.  Returns (F, g) with g the pixel mean of E_{L-1}; with keep,
+    also a dict of every intermediate for the reverse pass.
+    """
+    L = cfg["levels"]
+    C = channels(cfg)
+    saved = {}
+    X = x
+    E = []
+    for l in range(L):
+        if l > 0:
+            X = maxpool2(E[l - 1])
+        A = relu(conv3x3(X, wts[f"enc{l}.a.w"], wts[f"enc{l}.a.b"]))
+        El = relu(conv3x3(A, wts[f"enc{l}.b.w"], wts[f"enc{l}.b.b"]) + A)
+        if keep:
+            saved[f"enc{l}.X"] = X
+            saved[f"enc{l}.A"] = A
+        E.append(El)
+    D = E[L - 1]
+    for l in range(L - 2, -1, -1):
+        Z = np.concatenate([up2(D), E[l]], axis=0)
+        A = relu(conv3x3(Z, wts[f"dec{l}.a.w"], wts[f"dec{l}.a.b"]))
+        D = relu(conv3x3(A, wts[f"dec{l}.b.w"], wts[f"dec{l}.b.b"]) + A)
+        if keep:
+            saved[f"dec{l}.Z"] = Z
+            saved[f"dec{l}.A"] = A
+            saved[f"dec{l}.D"] = D
+    if C[0] != 8:
+        Wp = wts["precls.w"][:, :, 0, 0]
+        pre = np.tensordot(Wp, D, axes=(1, 0)) + wts["precls.b"][:, None, None]
+        F = relu(pre)
+    else:
+        F = D
+    g = E[L - 1].mean(axis=(1, 2))
+    if keep:
+        saved["E"] = E
+        saved["D0"] = D
+        saved["F"] = F
+        saved["g"] = g
+        return F, g, saved
+    return F, g
+
+
+# --------------------------------------------------------------------------
+# O7-O8  controller and dynamic head
+# --------------------------------------------------------------------------
+
+
+def controller_input(g, c, si, n_classes, n_scales):
+    """[g; onehot_C(c); onehot_S(si)]."""
+    v = np.zeros(g.size + n_classes + n_scales)
+    v[:g.size] = g
+    v[g.size + c] = 1.0
+    v[g.size + n_classes + si] = 1.0
+    return v
+
+
+def controller(g, c, si, wts, cfg):
+    """theta = W_c [g; onehot_C(c); onehot_S(si)] + b_c (P head parameters)."""
+    v = controller_input(g, c, si, cfg["n_classes"], len(cfg["scales"]))
+    return wts["ctrl.w"] @ v + wts["ctrl.b"]
+
+
+def split_theta(theta, o):
+    """theta -> W1 (8x8), W2 (8x8), W3 (o x 8), b1 (8), b2 (8), b3 (o)."""
+    p = 0
+    W1 = theta[p:p + 64].reshape(8, 8); p += 64
+    W2 = theta[p:p + 64].reshape(8, 8); p += 64
+    W3 = theta[p:p + 8 * o].reshape(o, 8); p += 8 * o
+    b1 = theta[p:p + 8]; p += 8
+    b2 = theta[p:p + 8]; p += 8
+    b3 = theta[p:p + o]; p += o
+    return W1, W2, W3, b1, b2, b3
+
+
+def head(F, theta, o):
+    """Dynamic head: three 1x1 convs whose weights are theta.
+
+    h1 = ReLU(W1 F + b1); h2 = ReLU(W2 h1 + b2); z = W3 h2 + b3.
+    Logit: z_0 for one output, z_1 - z_0 for two (the foreground
+    probability of a two-way softmax is sigmoid(z_1 - z_0)).
+    """
+    W1, W2, W3, b1, b2, b3 = split_theta(theta, o)
+    h1 = relu(np.tensordot(W1, F, axes=(1, 0)) + b1[:, None, None])
+    h2 = relu(np.tensordot(W2, h1, axes=(1, 0)) + b2[:, None, None])
+    z = np.tensordot(W3, h2, axes=(1, 0)) + b3[:, None, None]
+    return z[0] if o == 1 else z[1] - z[0]
+
+
+def tile_logits(x, wts, cfg, si, classes):
+    """Logits of one tile for the given classes (all at the tile's scale slot)."""
+    F, g = unet_forward(x, wts, cfg)
+    return np.stack([head(F, controller(g, c, si, wts, cfg), cfg["head_out"]) for c in classes])
+
+
+# --------------------------------------------------------------------------
+# O10  overlap-weighted stitch (Sections 2.2-2.3; reading: linear ramp)
+# --------------------------------------------------------------------------
+
+
+def ramp(T):
+    """r(i) = min(i + 1, T - i): positive, peaked in the tile centre."""
+    i = np.arange(T)
+    return np.minimum(i + 1, T - i).astype(np.float64)
+
+
+def stitch(tiles, logits, H_k, W_k, T, s):
+    """Weighted average of overlapping tile logits.
+
+    tiles: list of (jy, jx) of the kept tiles; logits: matching list of TxT
+    arrays.  N(p) = sum_t w_t(p) l_t(p - o_t), D(p) = sum_t w_t(p) with
+    w(i, j) = r(i) r(j); Lambda = N / D where D > 0, else 0.
+    Returns (Lambda, N, D) over [0, H_k) x [0, W_k).
+    """
+    ey, ex = grid_extent(H_k, T, s), grid_extent(W_k, T, s)
+    N = np.zeros((ey, ex))
+    D = np.zeros((ey, ex))
+    w = np.outer(ramp(T), ramp(T))
+    for (jy, jx), l in zip(tiles, logits):
+        N[jy * s:jy * s + T, jx * s:jx * s + T] += w * l
+        D[jy * s:jy * s + T, jx * s:jx * s + T] += w
+    N, D = N[:H_k, :W_k], D[:H_k, :W_k]
+    Lam = np.where(D > 0, N / np.where(D > 0, D, 1.0), 0.0)
+    return Lam, N, D
+
+
+def fg_at_scale(fg, kc, k, H_k, W_k):
+    """Nearest lookup of the coarse map at scale k: fg(y >> (kc-k), x >> (kc-k))."""
+    sh = kc - k
+    ys = np.arange(H_k) >> sh
+    xs = np.arange(W_k) >> sh
+    return fg[np.ix_(ys, xs)]
+
+
+# --------------------------------------------------------------------------
+# whole path
+# --------------------------------------------------------------------------
+
+
+def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False):
+    """Masks and stitched logits for every (slide, pair).
+
+    slides: list of uint8 HWC arrays; pairs: list of (class, scale slot).
+    Returns dict with 'mask'[n][p] (bool H_k x W_k), 'logit'[n][p] (float64),
+    'tiles' (the kept tile list), 'pad' per slide, 'fg' per slide, and with
+    keep_tiles the per-tile logits {(n, si, jy, jx): {class: TxT}}.
+    """
+    wts = unpack_weights(flat_weights, cfg)
+    T, s = cfg["tile"], cfg["stride"]
+    kc = max(cfg["scales"])
+    need_fg = cfg["fg_filter"] or cfg["mask_and_fg"]
+    fgs = [tissue_map(r, kc, cfg["fg_threshold"]) if need_fg else None for r in slides]
+    tl = tile_list([r.shape[:2] for r in slides], cfg, fgs)
+    if tile_subset is not None:
+        tl = [t for t in tl if t in set(tile_subset)]
+    per_tile = {}
+    for (n, si, jy, jx) in tl:
+        classes = [c for (c, sj) in pairs if sj == si]
+        if not classes:
+            continue
+        k = cfg["scales"][si]
+        x = tile_input(slides[n], k, T, s, jy, jx)
+        lg = tile_logits(x, wts, cfg, si, classes)
+        per_tile[(n, si, jy, jx)] = {c: lg[i] for i, c in enumerate(classes)}
+    masks, logits = [], []
+    for n, rgb in enumerate(slides):
+        H, W, _ = rgb.shape
+        mrow, lrow = [], []
+        for (c, si) in pairs:
+            k = cfg["scales"][si]
+            Hk, Wk = level_size(H, k), level_size(W, k)
+            ts = [(jy, jx) for (m, sj, jy, jx) in tl if m == n and sj == si]
+            ls = [per_tile[(n, si, jy, jx)][c] for (jy, jx) in ts]
+            Lam, N, D = stitch(ts, ls, Hk, Wk, T, s)
+            M = (N > 0) & (D > 0)
+            if cfg["mask_and_fg"]:
+                M &= fg_at_scale(fgs[n], kc, k, Hk, Wk)
+            mrow.append(M)
+            lrow.append(Lam)
+        masks.append(mrow)
+        logits.append(lrow)
+    out = dict(mask=masks, logit=logits, tiles=tl, pad=[pad_colour(r) for r in slides], fg=fgs)
+    if keep_tiles:
+        out["tile_logits"] = per_tile
+    return out
+
+
+# --------------------------------------------------------------------------
+# O11  loss and hand-written reverse pass
+# --------------------------------------------------------------------------
+
+
+def sigmoid(x):
+    return 0.5 * (1.0 + np.tanh(0.5 * x))
+
+
+def soft_target(gt_mask, k):
+    """Box mean of the 40x ground-truth mask over each 2**k block (padded with 0)."""
+    f = 2 ** k
+    H, W = gt_mask.shape
+    Hk, Wk = level_size(H, k), level_size(W, k)
+    m = np.zeros((Hk * f, Wk * f))
+    m[:H, :W] = gt_mask
+    return m.reshape(Hk, f, Wk, f).mean(axis=(1, 3))
+
+
+def bce_terms(Lam, y):
+    """max(L, 0) - y L + log1p(exp(-|L|)), the BCE-with-logits term."""
+    return np.maximum(Lam, 0.0) - y * Lam + np.log1p(np.exp(-np.abs(Lam)))
+
+
+def conv3x3_backward(X, Wt, dY):
+    """Gradients of conv3x3 w.r.t. its input, weight and bias."""
+    Cin, H, W = X.shape
+    Cout = Wt.shape[0]
+    Xp = np.zeros((Cin, H + 2, W + 2))
+    Xp[:, 1:H + 1, 1:W + 1] = X
+    dXp = np.zeros_like(Xp)
+    dY2 = dY.reshape(Cout, H * W)
+    dW = np.zeros_like(Wt)
+    for i in range(3):
+        for j in range(3):
+            sl = Xp[:, i:i + H, j:j + W].reshape(Cin, H * W)
+            dW[:, :, i, j] = dY2 @ sl.T
+            dXp[:, i:i + H, j:j + W] += (Wt[:, :, i, j].T @ dY2).reshape(Cin, H, W)
+    return dXp[:, 1:H + 1, 1:W + 1], dW, dY2.sum(axis=1)
+
+
+def maxpool2_backward(X, dY):
+    """Route each gradient to the first maximum of its 2x2 window (row-major)."""
+    C, H, W = X.shape
+    win = X.reshape(C, H // 2, 2, W // 2, 2).transpose(0, 1, 3, 2, 4).reshape(C, H // 2, W // 2, 4)
+    first = np.argmax(win, axis=-1)  # argmax returns the first maximum
+    dwin = np.zeros_like(win)
+    np.put_along_axis(dwin, first[..., None], dY[..., None], axis=-1)
+    return dwin.reshape(C, H // 2, W // 2, 2, 2).transpose(0, 1, 3, 2, 4).reshape(C, H, W)
+
+
+def up2_backward(dY):
+    C, H, W = dY.shape
+    return dY.reshape(C, H // 2, 2, W // 2, 2).sum(axis=(2, 4))
+
+
+def head_backward(F, theta, o, dl):
+    """Gradients of the head logit w.r.t. theta and F, given dL/dlogit (TxT)."""
+    W1, W2, W3, b1, b2, b3 = split_theta(theta, o)
+    h1 = relu(np.tensordot(W1, F, axes=(1, 0)) + b1[:, None, None])
+    h2 = relu(np.tensordot(W2, h1, axes=(1, 0)) + b2[:, None, None])
+    if o == 1:
+        dz = dl[None]
+    else:
+        dz = np.stack([-dl, dl])
+    dW3 = np.tensordot(dz, h2, axes=([1, 2], [1, 2]))
+    db3 = dz.sum(axis=(1, 2))
+    dh2 = np.tensordot(W3, dz, axes=(0, 0)) * (h2 > 0)
+    dW2 = np.tensordot(dh2, h1, axes=([1, 2], [1, 2]))
+    db2 = dh2.sum(axis=(1, 2))
+    dh1 = np.tensordot(W2, dh2, axes=(0, 0)) * (h1 > 0)
+    dW1 = np.tensordot(dh1, F, axes=([1, 2], [1, 2]))
+    db1 = dh1.sum(axis=(1, 2))
+    dF = np.tensordot(W1, dh1, axes=(0, 0))
+    dtheta = np.concatenate([dW1.ravel(), dW2.ravel(), dW3.ravel(), db1, db2, db3])
+    return dtheta, dF
+
+
+def unet_backward(wts, cfg, saved, dF, dg):
+    """Reverse pass of unet_forward; returns a dict of weight gradients."""
+    L = cfg["levels"]
+    C = channels(cfg)
+    grads = {}
+    E = saved["E"]
+    if C[0] != 8:
+        D0 = saved["D0"]
+        F = saved["F"]
+        dpre = dF * (F > 0)
+        grads["precls.w"] = np.tensordot(dpre, D0, axes=([1, 2], [1, 2]))[:, :, None, None]
+        grads["precls.b"] = dpre.sum(axis=(1, 2))
+        dD = np.tensordot(wts["precls.w"][:, :, 0, 0], dpre, axes=(0, 0))
+    else:
+        dD = dF.copy()
+    dE = [np.zeros_like(e) for e in E]
+    hb, wb = E[L - 1].shape[1:]
+    dE[L - 1] += dg[:, None, None] / (hb * wb)
+    for l in range(0, L - 1):
+        Dl = saved[f"dec{l}.D"]
+        A = saved[f"dec{l}.A"]
+        Z = saved[f"dec{l}.Z"]
+        dpre_b = dD * (Dl > 0)
+        dA, grads[f"dec{l}.b.w"], grads[f"dec{l}.b.b"] = conv3x3_backward(A, wts[f"dec{l}.b.w"], dpre_b)
+        dA = dA + dpre_b
+        dpre_a = dA * (A > 0)
+        dZ, grads[f"dec{l}.a.w"], grads[f"dec{l}.a.b"] = conv3x3_backward(Z, wts[f"dec{l}.a.w"], dpre_a)
+        nu = 2 * C[l]
+        dE[l] += dZ[nu:]
+        dD = up2_backward(dZ[:nu])
+    dE[L - 1] += dD
+    for l in range(L - 1, -1, -1):
+        El = E[l]
+        A = saved[f"enc{l}.A"]
+        X = saved[f"enc{l}.X"]
+        dpre_b = dE[l] * (El > 0)
+        dA, grads[f"enc{l}.b.w"], grads[f"enc{l}.b.b"] = conv3x3_backward(A, wts[f"enc{l}.b.w"], dpre_b)
+        dA = dA + dpre_b
+        dpre_a = dA * (A > 0)
+        dX, grads[f"enc{l}.a.w"], grads[f"enc{l}.a.b"] = conv3x3_backward(X, wts[f"enc{l}.a.w"], dpre_a)
+        if l > 0:
+            dE[l - 1] += maxpool2_backward(E[l - 1], dX)
+    return grads
+
+
+def pack_grads(grads, cfg):
+    """Gradients in the canonical flat order (float64)."""
+    C = channels(cfg)
+    L = cfg["levels"]
+    names = []
+    for l in range(L):
+        names += [f"enc{l}.a.w", f"enc{l}.a.b", f"enc{l}.b.w", f"enc{l}.b.b"]
+    for l in range(L - 2, -1, -1):
+        names += [f"dec{l}.a.w", f"dec{l}.a.b", f"dec{l}.b.w", f"dec{l}.b.b"]
+    if C[0] != 8:
+        names += ["precls.w", "precls.b"]
+    names += ["ctrl.w", "ctrl.b"]
+    return np.concatenate([np.asarray(grads[n]).ravel() for n in names])
+
+
+def train_loss(rgb, gt, flat_weights, cfg, pairs, batch, with_grad=True):
+    """BCE loss of the stitched logits over the pixels a tile batch covers.
+
+    batch: list of (scale slot, jy, jx) tiles of one slide.  For each pair
+    (c, si) the batch tiles at scale slot si are stitched; the loss is the
+    mean of the BCE terms over every (pair, pixel) with D > 0 against the
+    soft target (box mean of the 40x mask of class c).  Returns (loss, flat
+    gradient in canonical order or None, dict of per-pair Lambda).
+    """
+    wts = unpack_weights(flat_weights, cfg)
+    T, s = cfg["tile"], cfg["stride"]
+    o = cfg["head_out"]
+    H, W, _ = rgb.shape
+    fwd = {}
+    for (si, jy, jx) in batch:
+        k = cfg["scales"][si]
+        x = tile_input(rgb, k, T, s, jy, jx)
+        F, g, saved = unet_forward(x, wts, cfg, keep=True)
+        fwd[(si, jy, jx)] = (F, g, saved)
+    terms = 0.0
+    n_terms = 0
+    stitched = {}
+    for (c, si) in pairs:
+        k = cfg["scales"][si]
+        Hk, Wk = level_size(H, k), level_size(W, k)
+        ts = [(jy, jx) for (sj, jy, jx) in batch if sj == si]
+        ls = []
+        for (jy, jx) in ts:
+            F, g, _ = fwd[(si, jy, jx)]
+            ls.append(head(F, controller(g, c, si, wts, cfg), o))
+        Lam, N, D = stitch(ts, ls, Hk, Wk, T, s)
+        y = soft_target(gt[c], k)
+        cov = D > 0
+        terms += bce_terms(Lam, y)[cov].sum()
+        n_terms += int(cov.sum())
+        stitched[(c, si)] = (Lam, D, y, cov, ts)
+    loss = terms / n_terms
+    if not with_grad:
+        return loss, None, {p: v[0] for p, v in stitched.items()}
+    w = np.outer(ramp(T), ramp(T))
+    grads = {}
+    dWc = np.zeros_like(wts["ctrl.w"])
+    dbc = np.zeros_like(wts["ctrl.b"])
+    dF_all = {key: np.zeros_like(v[0]) for key, v in fwd.items()}
+    dg_all = {key: np.zeros_like(v[1]) for key, v in fwd.items()}
+    G = channels(cfg)[-1]
+    for (c, si), (Lam, D, y, cov, ts) in stitched.items():
+        k = cfg["scales"][si]
+        dLam = np.where(cov, (sigmoid(Lam) - y) / n_terms, 0.0)
+        ey, ex = grid_extent(Lam.shape[0], T, s), grid_extent(Lam.shape[1], T, s)
+        dL_ext = np.zeros((ey, ex))
+        D_ext = np.ones((ey, ex))
+        dL_ext[:Lam.shape[0], :Lam.shape[1]] = dLam
+        D_ext[:Lam.shape[0], :Lam.shape[1]] = np.where(cov, D, 1.0)
+        for (jy, jx) in ts:
+            F, g, _ = fwd[(si, jy, jx)]
+            sl = (slice(jy * s, jy * s + T), slice(jx * s, jx * s + T))
+            dl = dL_ext[sl] * w / D_ext[sl]
+            theta = controller(g, c, si, wts, cfg)
+            dtheta, dF = head_backward(F, theta, o, dl)
+            v = controller_input(g, c, si, cfg["n_classes"], len(cfg["scales"]))
+            dWc += np.outer(dtheta, v)
+            dbc += dtheta
+            dg_all[(si, jy, jx)] += wts["ctrl.w"][:, :G].T @ dtheta
+            dF_all[(si, jy, jx)] += dF
+    for key, (F, g, saved) in fwd.items():
+        gk = unet_backward(wts, cfg, saved, dF_all[key], dg_all[key])
+        for name, v in gk.items():
+            grads[name] = grads.get(name, 0.0) + v
+    grads["ctrl.w"] = dWc
+    grads["ctrl.b"] = dbc
+    return loss, pack_grads(grads, cfg), {p: v[0] for p, v in stitched.items()}

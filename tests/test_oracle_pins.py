@@ -1,0 +1,540 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks an oracle function against something other than itself:
+the paper's printed tiling constants, brute force on tiny inputs, exact
+integer identities, closed forms and independent torch float64 routines.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as tF
+
+from oracle import omniseg_oracle as O
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- O1 pad colour
+
+def test_pad_colour_half_case_rounds_up():
+    # corner R values 10, 11, 12, 13: mean 11.5, rounds half up to 12
+    img = np.zeros((4, 4, 3), np.uint8)
+    img[0, 0] = (10, 0, 255)
+    img[0, 1] = (11, 1, 255)
+    img[1, 0] = (12, 0, 254)
+    img[1, 1] = (13, 0, 254)
+    img[2:, :] = 77  # outside the corner: must not matter
+    assert list(O.pad_colour(img)) == [12, 0, 255]
+
+
+def test_pad_colour_is_rounded_mean_brute_force():
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        img = rng.integers(0, 256, size=(3, 5, 3)).astype(np.uint8)
+        for c in range(3):
+            m = sum(int(img[y, x, c]) for y in range(2) for x in range(2)) / 4.0
+            want = int(math.floor(m + 0.5))
+            assert O.pad_colour(img)[c] == want
+
+
+# ---------------------------------------------------------------- O2 pyramid
+
+def test_box_sum_nested_equals_direct():
+    rng = np.random.default_rng(6)
+    P = rng.integers(0, 256, size=(32, 48, 3)).astype(np.int64)
+    cur = P
+    for k in range(1, 4):
+        cur = O.box_sum(cur, 2)
+        assert np.array_equal(cur, O.box_sum(P, 2 ** k))
+
+
+def test_scale_sums_constant_and_pad_blocks():
+    img = np.full((20, 13, 3), 200, np.uint8)
+    img[0, 0] = (10, 20, 30)
+    pad = O.pad_colour(img)
+    for k in range(4):
+        f = 2 ** k
+        ey, ex = O.level_size(20, k) + 2, O.level_size(13, k) + 3
+        S = O.scale_sums(img, k, ey, ex)
+        # blocks wholly inside the pad hold 4^k * pad
+        assert np.all(S[-1, :] == 4 ** k * pad)
+        assert np.all(S[:, -1] == 4 ** k * pad)
+        # a block wholly inside the constant part of the slide holds 4^k * 200
+        if 2 * f <= 13:
+            assert np.all(S[1, 1] == 4 ** k * 200)
+        # brute force every block
+        for y in range(ey):
+            for x in range(ex):
+                tot = np.zeros(3, np.int64)
+                for a in range(f):
+                    for b in range(f):
+                        yy, xx = f * y + a, f * x + b
+                        tot += img[yy, xx] if (yy < 20 and xx < 13) else pad
+                assert np.array_equal(S[y, x], tot)
+
+
+def test_tile_input_normalisation():
+    img = np.full((16, 16, 3), 255, np.uint8)
+    for k in range(3):
+        x = O.tile_input(img, k, 8, 4, 0, 0)
+        assert np.allclose(x, 1.0, atol=0, rtol=0)
+
+
+# ---------------------------------------------------------------- O4 tile grid
+
+@pytest.mark.parametrize("n,T,s,want", [
+    (256, 128, 64, 3),      # tiny instance: 3 x 3 = 9 tiles
+    (8192, 256, 128, 63), (4096, 256, 128, 31), (2048, 256, 128, 15), (1024, 256, 128, 7),
+    (1024, 256, 128, 7), (512, 256, 128, 3), (256, 256, 128, 1), (128, 256, 128, 1),
+    (2048, 256, 128, 15), (1024, 256, 128, 7),
+    (64, 32, 16, 3), (32, 32, 16, 1), (257, 128, 64, 4), (100, 128, 64, 1),
+])
+def test_grid_count_closed_form(n, T, s, want):
+    assert O.grid_count(n, T, s) == want
+    # brute force: fewest tiles at origins 0, s, 2s, ... that cover [0, n)
+    m = 1
+    while (m - 1) * s + T < n:
+        m += 1
+    assert m == want
+
+
+def test_config_tile_totals():
+    # the 8192^2 slide at 40/20/10/5x with 256 tiles at stride 128
+    counts = [O.grid_count(O.level_size(8192, k), 256, 128) ** 2 for k in range(4)]
+    assert counts == [3969, 961, 225, 49] and sum(counts) == 5204
+    counts = [O.grid_count(O.level_size(1024, k), 256, 128) ** 2 for k in range(4)]
+    assert counts == [49, 9, 1, 1]
+    cfg = O.make_config(tile=128, stride=64)
+    assert len(O.tile_list([(256, 256)], cfg)) == 9
+
+
+def test_paper_overlap_counts():
+    """Tile 512 at stride 256 gives 2 overlapping tiles per axis; at 64, 8."""
+    with open(os.path.join(GOLDEN, "paper_tiling_constants.json")) as f:
+        g = json.load(f)
+    T = g["tile"]
+    for case in g["cases"]:
+        s = case["stride"]
+        n = 8 * T
+        cnt = O.grid_count(n, T, s)
+        cover = np.zeros(n, int)
+        for j in range(cnt):
+            cover[j * s:j * s + T] += 1
+        interior = cover[T:n - T]
+        assert np.all(interior == case["overlapping_tiles"])
+
+
+def test_tile_keep_rule_brute_force():
+    rng = np.random.default_rng(8)
+    H, W = 96, 80
+    for trial in range(6):
+        kc = 3
+        Hc, Wc = O.level_size(H, kc), O.level_size(W, kc)
+        fg = rng.uniform(size=(Hc, Wc)) < 0.08
+        # rasterise the coarse map onto the 40x grid
+        big = np.zeros((Hc * 8, Wc * 8), bool)
+        for r in range(Hc):
+            for c in range(Wc):
+                big[r * 8:(r + 1) * 8, c * 8:(c + 1) * 8] = fg[r, c]
+        for k in range(4):
+            T, s = 16, 8
+            ny = O.grid_count(O.level_size(H, k), T, s)
+            nx = O.grid_count(O.level_size(W, k), T, s)
+            for jy in range(ny):
+                for jx in range(nx):
+                    f = 2 ** k
+                    y0, y1 = jy * s * f, (jy * s + T) * f
+                    x0, x1 = jx * s * f, (jx * s + T) * f
+                    want = bool(big[y0:min(y1, big.shape[0]), x0:min(x1, big.shape[1])].any())
+                    assert O.tile_keeps(fg, kc, k, T, s, jy, jx) == want
+
+
+def test_tissue_map_against_float_gray():
+    img, _ = synth.strip_slide(3, 256, 384, fg_frac=0.3)
+    for kc in range(4):
+        fg = O.tissue_map(img, kc)
+        f = 2 ** kc
+        Hc, Wc = fg.shape
+        P = O.padded_slide(img, Hc * f, Wc * f).astype(np.float64)
+        mean = P.reshape(Hc, f, Wc, f, 3).mean(axis=(1, 3))
+        gray = 0.299 * mean[..., 0] + 0.587 * mean[..., 1] + 0.114 * mean[..., 2]
+        clear = np.abs(gray - 220) > 1e-6
+        assert np.array_equal(fg[clear], (gray < 220)[clear])
+        assert 0.1 < fg.mean() < 0.8  # the band is tissue, the background is not
+
+
+# ---------------------------------------------------------------- O5 conv
+
+def _conv_brute(X, Wt, b):
+    Cin, H, W = X.shape
+    Cout = Wt.shape[0]
+    Y = np.zeros((Cout, H, W))
+    for o in range(Cout):
+        for y in range(H):
+            for x in range(W):
+                acc = b[o]
+                for c in range(Cin):
+                    for i in range(3):
+                        for j in range(3):
+                            yy, xx = y + i - 1, x + j - 1
+                            if 0 <= yy < H and 0 <= xx < W:
+                                acc += Wt[o, c, i, j] * X[c, yy, xx]
+                Y[o, y, x] = acc
+    return Y
+
+
+def test_conv_brute_force():
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((3, 5, 6))
+    Wt = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    assert np.max(np.abs(O.conv3x3(X, Wt, b) - _conv_brute(X, Wt, b))) < 1e-12
+
+
+def test_conv_against_torch_float64():
+    rng = np.random.default_rng(10)
+    X = rng.standard_normal((7, 9, 11))
+    Wt = rng.standard_normal((5, 7, 3, 3))
+    b = rng.standard_normal(5)
+    ref = tF.conv2d(torch.from_numpy(X)[None], torch.from_numpy(Wt), torch.from_numpy(b), padding=1)[0].numpy()
+    assert np.max(np.abs(O.conv3x3(X, Wt, b) - ref)) < 1e-12
+
+
+# ---------------------------------------------------------------- O6 U-Net, independent torch model
+
+def _torch_unet(x, flat, base, L, n_classes, n_scales, o):
+    """Test-only float64 torch model of the same network (torch ops only)."""
+    lay = synth.weight_layout(base, L, n_classes, n_scales, o)
+    t = torch.from_numpy(np.asarray(flat, np.float64))
+    p, W = 0, {}
+    for name, shape, _ in lay:
+        n = int(np.prod(shape))
+        W[name] = t[p:p + n].reshape(shape)
+        p += n
+    X = torch.from_numpy(x)[None]
+    E = []
+    for l in range(L):
+        if l > 0:
+            X = tF.max_pool2d(E[-1], 2)
+        A = torch.relu(tF.conv2d(X, W[f"enc{l}.a.w"], W[f"enc{l}.a.b"], padding=1))
+        E.append(torch.relu(tF.conv2d(A, W[f"enc{l}.b.w"], W[f"enc{l}.b.b"], padding=1) + A))
+    D = E[-1]
+    for l in range(L - 2, -1, -1):
+        Z = torch.cat([tF.interpolate(D, scale_factor=2, mode="nearest"), E[l]], dim=1)
+        A = torch.relu(tF.conv2d(Z, W[f"dec{l}.a.w"], W[f"dec{l}.a.b"], padding=1))
+        D = torch.relu(tF.conv2d(A, W[f"dec{l}.b.w"], W[f"dec{l}.b.b"], padding=1) + A)
+    F = torch.relu(tF.conv2d(D, W["precls.w"], W["precls.b"])) if base != 8 else D
+    g = E[-1].mean(dim=(2, 3))[0]
+    return F[0], g, W
+
+
+def test_unet_against_torch_float64():
+    rng = np.random.default_rng(11)
+    for base, L in [(4, 3), (8, 2), (6, 4)]:
+        cfg = O.make_config(base=base, levels=L, head_out=2, n_classes=3, scales=(0, 1))
+        flat = synth.he_normal_weights(12, base, L, 3, 2, 2, bias_std=0.1)
+        assert flat.size == O.weight_count(cfg)
+        x = rng.uniform(size=(3, 16, 16))
+        F, g = O.unet_forward(x, O.unpack_weights(flat, cfg), cfg)
+        Ft, gt, _ = _torch_unet(x, flat, base, L, 3, 2, 2)
+        assert np.max(np.abs(F - Ft.numpy())) < 1e-10 * max(1.0, np.abs(F).max())
+        assert np.max(np.abs(g - gt.numpy())) < 1e-10 * max(1.0, np.abs(g).max())
+
+
+def test_bias_only_network_closed_form():
+    """All conv weights zero: every layer is a per-channel constant."""
+    base, L = 8, 3
+    cfg = O.make_config(base=base, levels=L, head_out=1, n_classes=1, scales=(0,))
+    lay = synth.weight_layout(base, L, 1, 1, 1)
+    rng = np.random.default_rng(13)
+    parts = {}
+    for name, shape, fan in lay:
+        parts[name] = np.zeros(shape) if name.endswith(".w") else rng.standard_normal(shape)
+    flat = np.concatenate([parts[n].ravel() for n, _, _ in lay])
+    x = rng.uniform(size=(3, 16, 16))
+    F, g = O.unet_forward(x, O.unpack_weights(flat, cfg), cfg)
+    relu = lambda v: np.maximum(v, 0)
+    # encoder: A = relu(b_a), E = relu(b_b + A)
+    E = []
+    for l in range(L):
+        A = relu(parts[f"enc{l}.a.b"])
+        E.append(relu(parts[f"enc{l}.b.b"] + A))
+    D = E[-1]
+    for l in range(L - 2, -1, -1):
+        A = relu(parts[f"dec{l}.a.b"])
+        D = relu(parts[f"dec{l}.b.b"] + A)
+    assert np.allclose(F, D[:, None, None] * np.ones((1, 16, 16)), atol=0, rtol=1e-15)
+    assert np.allclose(g, E[-1], atol=0, rtol=1e-15)
+
+
+# ---------------------------------------------------------------- O7-O8 controller and head
+
+def test_controller_closed_form_without_gap_columns():
+    base, L, C, S, o = 4, 3, 6, 4, 2
+    cfg = O.make_config(base=base, levels=L, head_out=o, n_classes=C, scales=(0, 1, 2, 3))
+    flat = synth.he_normal_weights(14, base, L, C, S, o, bias_std=0.3)
+    wts = O.unpack_weights(flat, cfg)
+    G = base * 2 ** (L - 1)
+    wts["ctrl.w"][:, :G] = 0.0
+    g = np.random.default_rng(15).standard_normal(G)
+    for c in range(C):
+        for k in range(S):
+            want = wts["ctrl.b"] + wts["ctrl.w"][:, G + c] + wts["ctrl.w"][:, G + C + k]
+            assert np.allclose(O.controller(g, c, k, wts, cfg), want, rtol=0, atol=1e-15)
+
+
+def test_head_closed_form_identity_layers():
+    rng = np.random.default_rng(16)
+    F = rng.standard_normal((8, 5, 7))
+    W3 = rng.standard_normal((2, 8))
+    b3 = rng.standard_normal(2)
+    theta = np.concatenate([np.eye(8).ravel(), np.eye(8).ravel(), W3.ravel(), np.zeros(8), np.zeros(8), b3])
+    want = np.tensordot(W3[1] - W3[0], np.maximum(F, 0), axes=(0, 0)) + (b3[1] - b3[0])
+    assert np.allclose(O.head(F, theta, 2), want, rtol=0, atol=1e-12)
+    # constant feature -> constant logit
+    Fc = np.ones((8, 4, 4)) * rng.standard_normal((8, 1, 1))
+    th = rng.standard_normal(O.head_params(1))
+    l = O.head(Fc, th, 1)
+    assert np.ptp(l) == 0.0
+
+
+def test_head_against_torch_1x1_convs():
+    """The parameter split order W1, W2, W3, b1, b2, b3 as plain 1x1 convs."""
+    rng = np.random.default_rng(17)
+    F = rng.standard_normal((8, 6, 6))
+    W1, W2, W3 = rng.standard_normal((8, 8)), rng.standard_normal((8, 8)), rng.standard_normal((2, 8))
+    b1, b2, b3 = rng.standard_normal(8), rng.standard_normal(8), rng.standard_normal(2)
+    theta = np.concatenate([W1.ravel(), W2.ravel(), W3.ravel(), b1, b2, b3])
+    t = lambda a: torch.from_numpy(a)
+    h = torch.relu(tF.conv2d(t(F)[None], t(W1)[:, :, None, None], t(b1)))
+    h = torch.relu(tF.conv2d(h, t(W2)[:, :, None, None], t(b2)))
+    z = tF.conv2d(h, t(W3)[:, :, None, None], t(b3))[0].numpy()
+    assert np.allclose(O.head(F, theta, 2), z[1] - z[0], rtol=0, atol=1e-12)
+    theta1 = np.concatenate([W1.ravel(), W2.ravel(), W3[0], b1, b2, b3[:1]])
+    assert np.allclose(O.head(F, theta1, 1), z[0], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- O10 stitch
+
+def _full_grid(H, T, s):
+    n = O.grid_count(H, T, s)
+    return [(jy, jx) for jy in range(n) for jx in range(n)]
+
+
+@pytest.mark.parametrize("T,s,m", [(128, 64, 1), (256, 128, 1), (32, 16, 1), (512, 64, 4), (512, 256, 1)])
+def test_stitch_interior_denominator_closed_form(T, s, m):
+    H = 4 * T
+    tiles = _full_grid(H, T, s)
+    _, _, D = O.stitch(tiles, [np.zeros((T, T))] * len(tiles), H, H, T, s)
+    want = m * m * (T // 2 + 1) ** 2
+    assert D[T:H - T, T:H - T].min() == want and D[T:H - T, T:H - T].max() == want
+    if (T, s) == (512, 64):
+        assert want == 1056784
+    if (T, s) == (256, 128):
+        assert want == 16641
+    if (T, s) == (128, 64):
+        assert want == 4225
+
+
+def test_stitch_partition_of_unity_and_constant():
+    rng = np.random.default_rng(18)
+    T, s, H, W = 32, 16, 90, 77
+    ny, nx = O.grid_count(H, T, s), O.grid_count(W, T, s)
+    tiles = [(jy, jx) for jy in range(ny) for jx in range(nx) if rng.uniform() < 0.7]
+    ones = [np.ones((T, T))] * len(tiles)
+    Lam, N, D = O.stitch(tiles, ones, H, W, T, s)
+    cov = D > 0
+    assert np.allclose(Lam[cov], 1.0, rtol=0, atol=1e-15)
+    assert np.all(Lam[~cov] == 0)
+    Lam7, _, _ = O.stitch(tiles, [np.full((T, T), -7.25)] * len(tiles), H, W, T, s)
+    assert np.allclose(Lam7[cov], -7.25, rtol=0, atol=1e-13)
+
+
+def test_stitch_no_overlap_equals_tilewise():
+    rng = np.random.default_rng(19)
+    T, H, W = 16, 48, 40
+    tiles = _full_grid(48, T, T)
+    tiles = [(jy, jx) for (jy, jx) in tiles if jx < O.grid_count(W, T, T)]
+    logits = [rng.standard_normal((T, T)) for _ in tiles]
+    Lam, _, _ = O.stitch(tiles, logits, H, W, T, T)
+    for (jy, jx), l in zip(tiles, logits):
+        blk = Lam[jy * T:jy * T + T, jx * T:jx * T + T]
+        assert np.allclose(blk, l[:blk.shape[0], :blk.shape[1]], rtol=0, atol=1e-15)
+
+
+def test_stitch_single_tile_identity_and_ramp():
+    rng = np.random.default_rng(20)
+    l = rng.standard_normal((8, 8))
+    Lam, N, D = O.stitch([(0, 0)], [l], 8, 8, 8, 4)
+    assert np.allclose(Lam, l, rtol=0, atol=1e-15)
+    r = np.array([1, 2, 3, 4, 4, 3, 2, 1], float)
+    assert np.array_equal(D, np.outer(r, r))
+
+
+# ---------------------------------------------------------------- whole path on the tiny instance
+
+def test_segment_tiny_instance_runs():
+    rgb, gt = synth.ellipse_slide(1)
+    cfg = O.make_config(base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128, stride=64)
+    flat = synth.he_normal_weights(11, 8, 3, 1, 1, 1)
+    out = O.segment([rgb], flat, cfg, [(0, 0)], keep_tiles=True)
+    assert len(out["tiles"]) == 9
+    assert out["mask"][0][0].shape == (256, 256)
+    assert np.isfinite(out["logit"][0][0]).all()
+
+
+# ---------------------------------------------------------------- O11 loss and gradient
+
+def test_bce_at_zero_logit_is_ln2():
+    y = np.random.default_rng(21).uniform(size=100)
+    assert np.allclose(O.bce_terms(np.zeros(100), y), math.log(2), rtol=0, atol=1e-15)
+
+
+def _fd_instance():
+    rgb, gt = synth.tiny_slide(4, 64, 64)
+    cfg = O.make_config(base=4, levels=3, head_out=2, n_classes=6, scales=(0, 1), tile=32, stride=16)
+    flat = synth.he_normal_weights(15, 4, 3, 6, 2, 2, bias_std=0.05).astype(np.float64)
+    pairs = [(c, si) for si in range(2) for c in range(6)]
+    batch = [(si, jy, jx) for (_, si, jy, jx) in O.tile_list([(64, 64)], cfg)]
+    return rgb, gt, cfg, flat, pairs, batch
+
+
+def test_gradient_against_torch_autograd():
+    """The hand-written reverse pass against torch float64 autograd of an
+    independent torch model of the same forward."""
+    rgb, gt, cfg, flat, pairs, batch = _fd_instance()
+    batch = batch[:5]
+    loss, grad, _ = O.train_loss(rgb, gt, flat, cfg, pairs, batch)
+    base, L, C, S, o = 4, 3, 6, 2, 2
+    T, s = 32, 16
+    wt = torch.from_numpy(flat.copy()).requires_grad_(True)
+    lay = synth.weight_layout(base, L, C, S, o)
+    ctrl_pos = sum(int(np.prod(sh)) for n, sh, _ in lay if not n.startswith("ctrl"))
+    P = O.head_params(o)
+    G = base * 2 ** (L - 1)
+    Wc = wt[ctrl_pos:ctrl_pos + P * (G + C + S)].reshape(P, G + C + S)
+    bc = wt[ctrl_pos + P * (G + C + S):]
+    terms, n_terms = 0.0, 0
+    feats = {}
+    for (si, jy, jx) in batch:
+        x = O.tile_input(rgb, cfg["scales"][si], T, s, jy, jx)
+        # rebuild the torch model on the differentiable weight vector
+        pos, W = 0, {}
+        for name, shape, _ in lay:
+            n = int(np.prod(shape))
+            W[name] = wt[pos:pos + n].reshape(shape)
+            pos += n
+        X = torch.from_numpy(x)[None]
+        E = []
+        for l in range(L):
+            if l > 0:
+                X = tF.max_pool2d(E[-1], 2)
+            A = torch.relu(tF.conv2d(X, W[f"enc{l}.a.w"], W[f"enc{l}.a.b"], padding=1))
+            E.append(torch.relu(tF.conv2d(A, W[f"enc{l}.b.w"], W[f"enc{l}.b.b"], padding=1) + A))
+        D = E[-1]
+        for l in range(L - 2, -1, -1):
+            Z = torch.cat([tF.interpolate(D, scale_factor=2, mode="nearest"), E[l]], dim=1)
+            A = torch.relu(tF.conv2d(Z, W[f"dec{l}.a.w"], W[f"dec{l}.a.b"], padding=1))
+            D = torch.relu(tF.conv2d(A, W[f"dec{l}.b.w"], W[f"dec{l}.b.b"], padding=1) + A)
+        F = torch.relu(tF.conv2d(D, W["precls.w"], W["precls.b"]))
+        feats[(si, jy, jx)] = (F[0], E[-1].mean(dim=(2, 3))[0])
+    ramp = torch.from_numpy(O.ramp(T))
+    w = ramp[:, None] * ramp[None, :]
+    for (c, si) in pairs:
+        k = cfg["scales"][si]
+        Hk = O.level_size(64, k)
+        ext = O.grid_extent(Hk, T, s)
+        Nn = torch.zeros(ext, ext, dtype=torch.float64)
+        Dd = torch.zeros(ext, ext, dtype=torch.float64)
+        for (sj, jy, jx) in batch:
+            if sj != si:
+                continue
+            F, g = feats[(sj, jy, jx)]
+            v = torch.zeros(G + C + S, dtype=torch.float64)
+            v = torch.cat([g, torch.nn.functional.one_hot(torch.tensor(c), C).double(),
+                           torch.nn.functional.one_hot(torch.tensor(si), S).double()])
+            th = Wc @ v + bc
+            W1, W2, W3 = th[:64].reshape(8, 8), th[64:128].reshape(8, 8), th[128:144].reshape(2, 8)
+            b1, b2, b3 = th[144:152], th[152:160], th[160:162]
+            h = torch.relu(torch.einsum("oc,chw->ohw", W1, F) + b1[:, None, None])
+            h = torch.relu(torch.einsum("oc,chw->ohw", W2, h) + b2[:, None, None])
+            z = torch.einsum("oc,chw->ohw", W3, h) + b3[:, None, None]
+            lg = z[1] - z[0]
+            Nn[jy * s:jy * s + T, jx * s:jx * s + T] += w * lg
+            Dd[jy * s:jy * s + T, jx * s:jx * s + T] += w
+        Nn, Dd = Nn[:Hk, :Hk], Dd[:Hk, :Hk]
+        cov = Dd > 0
+        Lam = Nn[cov] / Dd[cov]
+        y = torch.from_numpy(O.soft_target(gt[c], k))[cov]
+        terms = terms + tF.binary_cross_entropy_with_logits(Lam, y, reduction="sum")
+        n_terms += int(cov.sum())
+    tloss = terms / n_terms
+    tloss.backward()
+    assert abs(float(tloss.detach()) - loss) < 1e-12 * max(1.0, abs(loss))
+    gref = wt.grad.numpy()
+    assert np.max(np.abs(grad - gref)) <= 1e-9 * np.max(np.abs(gref))
+
+
+def _activation_pattern(rgb, cfg, flat, pairs, batch):
+    """Signs of every ReLU input and the max-pool winners, for kink detection."""
+    wts = O.unpack_weights(flat, cfg)
+    T, s = cfg["tile"], cfg["stride"]
+    bits = []
+    for (si, jy, jx) in batch:
+        x = O.tile_input(rgb, cfg["scales"][si], T, s, jy, jx)
+        F, g, sv = O.unet_forward(x, wts, cfg, keep=True)
+        for key in sorted(k for k in sv if k.endswith((".A", ".D"))):
+            bits.append((sv[key] > 0).ravel())
+        for El in sv["E"]:
+            bits.append((El > 0).ravel())
+            C_, H_, W_ = El.shape
+            if H_ >= 2:
+                win = El.reshape(C_, H_ // 2, 2, W_ // 2, 2).transpose(0, 1, 3, 2, 4).reshape(-1, 4)
+                bits.append(np.argmax(win, axis=-1).astype(np.uint8))
+        bits.append((F > 0).ravel())
+        for (c, sj) in pairs:
+            if sj != si:
+                continue
+            W1, W2, W3, b1, b2, b3 = O.split_theta(O.controller(g, c, si, wts, cfg), cfg["head_out"])
+            h1 = np.tensordot(W1, F, axes=(1, 0)) + b1[:, None, None]
+            h2 = np.tensordot(W2, np.maximum(h1, 0), axes=(1, 0)) + b2[:, None, None]
+            bits.append((h1 > 0).ravel())
+            bits.append((h2 > 0).ravel())
+    return np.concatenate(bits)
+
+
+def test_gradient_central_differences():
+    """FP64 central differences along random directions.
+
+    A direction whose +-eps points differ in any ReLU sign or max-pool winner
+    crosses a kink, where the loss is not differentiable; such directions
+    are skipped and counted.
+    """
+    rgb, gt, cfg, flat, pairs, batch = _fd_instance()
+    loss, grad, _ = O.train_loss(rgb, gt, flat, cfg, pairs, batch)
+    rng = np.random.default_rng(22)
+    # one head pre-activation of this instance lies 3.6e-7 from its kink, so
+    # eps stays below that; FP64 rounding keeps the quotient good to ~1e-9
+    eps = 1e-7
+    checked = skipped = 0
+    for trial in range(12):
+        v = rng.standard_normal(flat.size)
+        v /= np.linalg.norm(v)
+        pp = _activation_pattern(rgb, cfg, flat + eps * v, pairs, batch)
+        pm = _activation_pattern(rgb, cfg, flat - eps * v, pairs, batch)
+        if not np.array_equal(pp, pm):
+            skipped += 1
+            continue
+        lp, _, _ = O.train_loss(rgb, gt, flat + eps * v, cfg, pairs, batch, with_grad=False)
+        lm, _, _ = O.train_loss(rgb, gt, flat - eps * v, cfg, pairs, batch, with_grad=False)
+        fd = (lp - lm) / (2 * eps)
+        an = float(grad @ v)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * np.abs(grad).max()), (trial, fd, an)
+        checked += 1
+    assert checked >= 6, (checked, skipped)
