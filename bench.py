@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the slide-wise segmentation path on one MI355X.
+
+Workload: one seeded synthetic 8192 x 8192 RGB slide at 40x (needle-biopsy
+strip, ~30% tissue), 4 scales (40/20/10/5x), 6 classes (24 class-scale
+pairs), 256 x 256 tiles at stride 128 with foreground-only tile lists, a
+base-64 5-level residual U-Net with a controller-generated 8-8-8-2 dynamic
+head, ramp-weighted stitch into 24 whole-slide masks.
+
+A step is one omniseg_segment_slide call (pad, pyramid, tissue map, tile
+list, backbone, controller, head, stitch) with the slide already in HBM and
+the masks written to HBM.  value = slide pixels x pairs / step time, in
+Mpixel/s per class-scale, for the BF16 backbone; the FP32 backbone is timed
+on the same GPU for the speed-up and the mask agreement.
+
+Prints one JSON line.  --gpus N > 1 is refused: this path runs on one GPU.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "WSI Mpixel/s per class-scale (BF16 batched vs FP32 plain) at ≥0.999 Dice; %MFMA peak"
+UNIT = "Mpixel/s per class-scale"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+HBM_PEAK_GBS = 8000.0
+
+CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 1, 2, 3), tile=256, stride=128,
+           fg_filter=True)
+
+
+def conv_symbol(prec, stage, cout_p, width):
+    """Kernel symbol (as rocprofv3 prints it) that a conv launch uses."""
+    t = "unsigned short" if prec == "bf16" else "float"
+    loader, epi = {"enc_a": (1, 0), "enc_b": (0, 1), "dec_a": (2, 0), "dec_b": (0, 1)}[stage]
+    bn = 64 if cout_p % 64 == 0 else 32
+    wn = 2 if bn >= 64 else 1
+    bx = 16 if width % 16 == 0 else 8
+    return f"omniseg::k_conv3x3<{t}, 8, {bx}, {bn}, {4 // wn}, {wn}, {loader}, {epi}>"
+
+
+def roofline(records, prec):
+    """Aggregate the profile by kernel symbol; report the dominant conv kernel."""
+    T = CFG["tile"]
+    groups = {}
+    for r in records:
+        if r["stage"] not in ("enc_a", "enc_b", "dec_a", "dec_b"):
+            continue
+        l = r["level"]
+        cout = CFG["base"] << l
+        sym = conv_symbol(prec, r["stage"], ((cout + 31) // 32) * 32, T >> l)
+        g = groups.setdefault(sym, dict(n=0, flops=0.0, ms=0.0, bytes=0.0))
+        g["n"] += 1
+        g["flops"] += r["flops"]
+        g["ms"] += r["ms"]
+        g["bytes"] += r["bytes"]
+    sym, g = max(groups.items(), key=lambda kv: kv[1]["ms"])
+    achieved = g["flops"] / (g["ms"] * 1e-3) / 1e12
+    conv_ms = sum(v["ms"] for v in groups.values())
+    conv_flops = sum(v["flops"] for v in groups.values())
+    return dict(bound="mfma", kernel=sym, launches=g["n"],
+                flops_per_launch=g["flops"] / g["n"], avg_launch_ms=g["ms"] / g["n"],
+                achieved=achieved, peak=PEAK_TFLOPS[prec], unit="TFLOP/s",
+                frac=achieved / PEAK_TFLOPS[prec], traffic=None,
+                all_convs_tflops=conv_flops / (conv_ms * 1e-3) / 1e12,
+                all_convs_frac=conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec])
+
+
+def stage_summary(records):
+    out = {}
+    for r in records:
+        s = out.setdefault(r["stage"], dict(ms=0.0, flops=0.0, bytes=0.0, launches=0))
+        s["ms"] += r["ms"]
+        s["flops"] += r["flops"]
+        s["bytes"] += r["bytes"]
+        s["launches"] += 1
+    for s in out.values():
+        s["tflops"] = s["flops"] / max(s["ms"], 1e-9) / 1e9
+        s["gbs"] = s["bytes"] / max(s["ms"], 1e-9) / 1e6
+    return out
+
+
+def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles):
+    plan = om.Plan(base=CFG["base"], levels=CFG["levels"], head_out=CFG["head_out"],
+                   n_classes=CFG["n_classes"], scales=CFG["scales"], tile=CFG["tile"],
+                   stride=CFG["stride"], fg_filter=CFG["fg_filter"],
+                   precision=om.BF16 if prec == "bf16" else om.FP32, emit_logits=False,
+                   batch_tiles=batch_tiles)
+    packed = plan.pack(flat_dev)
+    ws = torch.empty(plan.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
+    outs = plan.alloc_outputs([dslide], pairs)
+    for _ in range(warmup):
+        plan.segment([dslide], pairs, packed, workspace=ws, outputs=outs)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    records = []
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.segment([dslide], pairs, packed, workspace=ws, outputs=outs)
+        records.extend(plan.read_profile())
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.set_profiling(False)
+    ms = ev0.elapsed_time(ev1) / steps
+    off, _ = plan.region([dslide], pairs, om.REGION_TILE_COUNT)
+    kept = int(ws[off:off + 4].view(torch.int32).item())
+    masks = [m.cpu().numpy().astype(bool) for m in outs[0][0]]
+    return dict(ms=ms, wall_ms=wall * 1e3 / steps, records=records, kept=kept, masks=masks)
+
+
+def cpu_baseline(rgb, flat, pairs, kept, seconds):
+    """The FP64 oracle on a bounded sample of the same workload, extrapolated."""
+    from oracle import omniseg_oracle as O
+
+    try:
+        import threadpoolctl
+        threads = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or 1
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    cfg = O.make_config(**CFG)
+    wts = O.unpack_weights(flat, cfg)
+    fg = O.tissue_map(rgb, 3)
+    tl = O.tile_list([rgb.shape[:2]], cfg, [fg])
+    rng = np.random.default_rng(0)
+    order = rng.permutation(len(tl))
+    done, t_tiles = 0, 0.0
+    t_start = time.perf_counter()
+    for i in order:
+        n, si, jy, jx = tl[i]
+        t0 = time.perf_counter()
+        x = O.tile_input(rgb, cfg["scales"][si], 256, 128, jy, jx)
+        O.tile_logits(x, wts, cfg, si, list(range(6)))
+        t_tiles += time.perf_counter() - t0
+        done += 1
+        if time.perf_counter() - t_start > seconds:
+            break
+    per_tile = t_tiles / done
+    # stitch: one plane at 5x of the sampled kind, timed, scaled by tile pixels
+    ts = [(jy, jx) for (_, si, jy, jx) in tl if si == 3]
+    t0 = time.perf_counter()
+    O.stitch(ts, [np.zeros((256, 256))] * len(ts), 1024, 1024, 256, 128)
+    per_tile_stitch = (time.perf_counter() - t0) / max(1, len(ts))
+    t_slide = per_tile * kept + per_tile_stitch * kept * 6
+    value = rgb.shape[0] * rgb.shape[1] * len(pairs) / (t_slide * 1e6)
+    return dict(value=value, unit=UNIT, cores=int(threads), kind="oracle",
+                sample=f"{done} of {kept} kept tiles through the FP64 oracle backbone, controller and "
+                       f"6-class head ({per_tile:.2f} s/tile) plus one 5x stitch plane, extrapolated "
+                       f"to the whole slide ({t_slide:.0f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=8192, help="slide side in pixels")
+    ap.add_argument("--batch-tiles", type=int, default=0)
+    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
+                                   "part of this build (--gpus must be 1)"}))
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2305_14566_amd import metrics as M
+    from paper_2305_14566_amd import omniseg as om
+
+    om.lib()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    rgb, _ = synth.strip_slide(2, args.size, args.size, fg_frac=0.30, with_gt=False)
+    flat = synth.he_normal_weights(12, CFG["base"], CFG["levels"], CFG["n_classes"], len(CFG["scales"]),
+                                   CFG["head_out"])
+    gen_s = time.perf_counter() - t0
+    dslide = torch.from_numpy(rgb).to(dev)
+    flat_dev = torch.from_numpy(flat).to(dev)
+    pairs = [(c, si) for si in range(4) for c in range(6)]
+    print(f"# slide {args.size}^2 generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+
+    bf = run_leg(om, torch, dslide, flat_dev, pairs, "bf16", args.steps, args.warmup, args.batch_tiles)
+    print(f"# bf16: {bf['ms']:.1f} ms/step, {bf['kept']} kept tiles", file=sys.stderr, flush=True)
+    px = args.size * args.size * len(pairs)
+    result = {
+        "metric": METRIC, "value": px / (bf["ms"] * 1e-3) / 1e6, "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": bf["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"one {args.size}x{args.size} synthetic 40x slide (strip, ~30% tissue), "
+                               "4 scales x 6 classes, 256 tiles at stride 128, foreground tiles only, "
+                               "base-64 5-level residual U-Net + dynamic head, ramp stitch",
+                   "slides": 1, "pairs": len(pairs), "kept_tiles": bf["kept"],
+                   "tflop_per_step": sum(r["flops"] for r in bf["records"]) / args.steps / 1e12},
+        "stages_bf16": stage_summary([dict(r, ms=r["ms"] / args.steps, flops=r["flops"] / args.steps,
+                                           bytes=r["bytes"] / args.steps) for r in bf["records"]]),
+        "roofline": roofline(bf["records"], "bf16"),
+    }
+    st = result["stages_bf16"].get("stitch")
+    if st:
+        result["roofline_stitch"] = dict(bound="hbm", achieved=st["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                                         frac=st["gbs"] / HBM_PEAK_GBS, traffic=None)
+    if not args.no_fp32:
+        fp = run_leg(om, torch, dslide, flat_dev, pairs, "fp32", args.fp32_steps, 1, args.batch_tiles)
+        print(f"# fp32: {fp['ms']:.1f} ms/step", file=sys.stderr, flush=True)
+        dices = [M.dice(a, b) for a, b in zip(bf["masks"], fp["masks"])]
+        dis = [M.disagreement(a, b) for a, b in zip(bf["masks"], fp["masks"])]
+        result["fp32"] = {"value": px / (fp["ms"] * 1e-3) / 1e6, "ms_per_step": fp["ms"],
+                          "steps": args.fp32_steps, "roofline": roofline(fp["records"], "fp32")}
+        result["speedup_bf16_vs_fp32"] = fp["ms"] / bf["ms"]
+        result["bf16_vs_fp32_masks"] = {"dice_min": min(dices), "dice_mean": float(np.mean(dices)),
+                                        "disagreement_max": max(dis)}
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(rgb, flat, pairs, bf["kept"], args.cpu_seconds)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

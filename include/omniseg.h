@@ -1,0 +1,278 @@
+/*
+ * omniseg.h -- C ABI of the MI355X (gfx950) slide-wise Omni-Seg hot path.
+ *
+ * The library segments whole-slide images (WSIs) the way the accelerated
+ * pipeline of arXiv 2305.14566 does on one GPU:
+ *   1. pad the slide with the rounded mean colour of its top-left 2x2 block
+ *      and resample it into a multi-scale pyramid (Section 2.1; Section 2.2:
+ *      several magnifications from the 40x base);
+ *   2. keep only tiles that touch tissue (Section 2.1, blank-region removal);
+ *   3. run a residual U-Net on every kept tile, whose 1x1 dynamic head is
+ *      generated per tile by a controller from a class x scale one-hot code
+ *      (the dynamic multi-class multi-scale network the paper applies,
+ *      Section 2.2);
+ *   4. merge the overlapping tile logits of each class into a whole-slide
+ *      mask by a ramp-weighted average and a threshold (Section 2.2 overlap
+ *      tiling; Section 2.3 slide-wise aggregation; constants in Section 3.2).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int32_t status (OMNISEG_OK = 0 or one of the
+ *     OMNISEG_ERR_* codes).  No C++ exception crosses the ABI.
+ *   - Arguments are validated before any HIP call.  On an error nothing is
+ *     launched and no caller buffer is written; omniseg_last_error() gives a
+ *     thread-local description of the last failure.
+ *   - "device" pointers point to memory on the current HIP device; "host"
+ *     pointers to ordinary host memory.  The caller owns every buffer it
+ *     passes in (slides, weights, outputs, workspace); the library never
+ *     frees caller memory and never allocates device memory.
+ *   - Work is enqueued asynchronously on the given stream (NULL = the null
+ *     stream).  Device buffers must stay valid until that work completes.
+ *   - A plan is not thread-safe; use one plan per stream at a time.
+ */
+#ifndef OMNISEG_H
+#define OMNISEG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OMNISEG_ABI_VERSION 1
+
+/* status codes */
+#define OMNISEG_OK 0
+#define OMNISEG_ERR_ARG 1         /* a NULL pointer, a size out of range, ... */
+#define OMNISEG_ERR_UNSUPPORTED 2 /* a valid but unsupported configuration  */
+#define OMNISEG_ERR_WORKSPACE 3   /* the workspace is smaller than required  */
+#define OMNISEG_ERR_HIP 4         /* a HIP runtime call failed               */
+
+/* backbone arithmetic */
+#define OMNISEG_FP32 0 /* FP32 activations and weights, FP32 MFMA           */
+#define OMNISEG_BF16 1 /* BF16 activations and weights, FP32 accumulation   */
+
+/* flags */
+#define OMNISEG_FLAG_EMIT_LOGITS 1 /* also write the stitched FP32 logit map */
+
+/* limits */
+#define OMNISEG_MAX_SCALES 4
+#define OMNISEG_MAX_CLASSES 16
+#define OMNISEG_MAX_SLIDES 32
+
+typedef struct omniseg_hip_stream_opaque* omniseg_stream; /* a hipStream_t */
+
+/*
+ * Network and tiling configuration.
+ *   base_channels  C_0 >= 1; encoder/decoder level l has C_0 * 2^l channels.
+ *   levels         L >= 1 U-Net levels; tile / 2^(L-1) must be a multiple of 8.
+ *   head_out       1 or 2 outputs of the dynamic head; with 2 the class logit
+ *                  is z_1 - z_0 (two-way softmax), with 1 it is z_0.
+ *   n_classes      C in [1, 16] (the class one-hot length).
+ *   n_scales       S in [1, 4] (the scale one-hot length).
+ *   scale_log2     downsampling exponent of each scale slot: slot i is the
+ *                  magnification 40x / 2^scale_log2[i] (0 = 40x, 1 = 20x,
+ *                  2 = 10x, 3 = 5x); values in [0, 3].
+ *   tile, stride   square tile size T (a multiple of 16, <= 512) and the
+ *                  overlap stride s (1 <= s <= T).
+ *   fg_filter      1: keep only tiles whose footprint touches a foreground
+ *                  pixel of the tissue map; 0: keep every tile.
+ *   fg_threshold   gray threshold of the tissue map (pixels darker than this
+ *                  on the coarsest scale are tissue), in [1, 255].
+ *   mask_and_fg    1: the output mask is also ANDed with the tissue map.
+ *   precision      OMNISEG_FP32 or OMNISEG_BF16.
+ *   flags          OR of OMNISEG_FLAG_*.
+ *   batch_tiles    tiles per backbone batch (0 = library default).
+ */
+typedef struct omniseg_config {
+  int32_t abi_version;
+  int32_t base_channels;
+  int32_t levels;
+  int32_t head_out;
+  int32_t n_classes;
+  int32_t n_scales;
+  int32_t scale_log2[OMNISEG_MAX_SCALES];
+  int32_t tile;
+  int32_t stride;
+  int32_t fg_filter;
+  int32_t fg_threshold;
+  int32_t mask_and_fg;
+  int32_t precision;
+  int32_t flags;
+  int32_t batch_tiles;
+} omniseg_config;
+
+/* One slide: uint8 RGB, interleaved (HWC), rows `row_pitch` bytes apart
+ * (row_pitch >= 3 * width).  rgb points to device memory.  height, width >= 2. */
+typedef struct omniseg_slide {
+  const uint8_t* rgb;
+  int32_t height;
+  int32_t width;
+  int64_t row_pitch;
+} omniseg_slide;
+
+/* One requested output: class index and scale slot. */
+typedef struct omniseg_pair {
+  int32_t cls;
+  int32_t scale;
+} omniseg_pair;
+
+/* Output buffers of one (slide, pair), at the pair's scale:
+ * H_k = ceil(height / 2^k) rows, W_k = ceil(width / 2^k) columns.
+ * mask: device uint8, 1 = the class is present; rows mask_pitch bytes apart.
+ * logit: device float or NULL; written only with OMNISEG_FLAG_EMIT_LOGITS;
+ * rows logit_pitch floats apart; 0 where no kept tile covers the pixel. */
+typedef struct omniseg_output {
+  uint8_t* mask;
+  float* logit;
+  int64_t mask_pitch;
+  int64_t logit_pitch;
+} omniseg_output;
+
+typedef struct omniseg_plan omniseg_plan;
+
+/* Text of a status code (static storage). */
+const char* omniseg_status_string(int32_t status);
+/* Thread-local text of the last error raised on this thread ("" if none). */
+const char* omniseg_last_error(void);
+
+/*
+ * Validate a configuration and build a plan (host memory only; no HIP call).
+ * cfg: host pointer.  *out receives the plan; release it with
+ * omniseg_plan_destroy.  Errors: ERR_ARG for NULL pointers or out-of-range
+ * fields, ERR_UNSUPPORTED for valid but unsupported shapes.
+ */
+int32_t omniseg_plan_create(const omniseg_config* cfg, omniseg_plan** out);
+/* Free a plan (NULL is accepted). */
+int32_t omniseg_plan_destroy(omniseg_plan* plan);
+
+/*
+ * Number of FP32 values of the canonical weight vector.  Canonical order:
+ * encoder levels 0..L-1 (conv_a W[C_l][C_in][3][3], b[C_l], conv_b W, b),
+ * decoder levels L-2..0 (conv_a W[C_l][3 C_l][3][3] whose input channels are
+ * the 2 C_l upsampled channels then the C_l skip channels, b, conv_b W, b),
+ * precls W[8][C_0], b[8] only when C_0 != 8, then the controller
+ * W_c[P][C_{L-1} + C + S] and b_c[P], P = 144 + 9 * head_out.
+ */
+int32_t omniseg_weight_count(const omniseg_plan* plan, int64_t* count);
+/* Bytes of the packed (device-internal) weight buffer for this plan. */
+int32_t omniseg_packed_weight_bytes(const omniseg_plan* plan, int64_t* bytes);
+/*
+ * Convert the canonical FP32 weights (device, omniseg_weight_count floats)
+ * into the packed layout the kernels read (device, omniseg_packed_weight_bytes
+ * bytes, 256-byte aligned).  Channel padding, MFMA-friendly ordering and the
+ * precision conversion happen here, once per weight set.
+ */
+int32_t omniseg_pack_weights(const omniseg_plan* plan, const float* canonical,
+                             void* packed, omniseg_stream stream);
+
+/*
+ * Workspace bytes that omniseg_segment_slide needs for these slides and
+ * pairs (host arrays).  The bound assumes every tile passes the tissue
+ * filter.
+ */
+int32_t omniseg_workspace_bytes(const omniseg_plan* plan, const omniseg_slide* slides,
+                                int32_t n_slides, const omniseg_pair* pairs,
+                                int32_t n_pairs, int64_t* bytes);
+
+/*
+ * Segment n_slides slides for n_pairs (class, scale) pairs.
+ *   packed     device weights from omniseg_pack_weights.
+ *   slides     host array [n_slides] (1 <= n_slides <= 32).
+ *   pairs      host array [n_pairs] (1 <= n_pairs); each pair unique.
+ *   outs       host array [n_slides * n_pairs], slide-major: outs[i * n_pairs + p].
+ *   workspace  device, ws_bytes >= omniseg_workspace_bytes, 256-byte aligned.
+ * All slides share one tile work list: every kept tile of every slide and
+ * scale runs through the backbone in batches of batch_tiles tiles; the head
+ * runs once per (tile, pair at the tile's scale); the stitch writes every
+ * output.  The call waits once for the stream after the tile list is built
+ * (to read the number of kept tiles, so every backbone launch is sized
+ * exactly); all later work is enqueued asynchronously on `stream`.
+ */
+int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
+                              const omniseg_slide* slides, int32_t n_slides,
+                              const omniseg_pair* pairs, int32_t n_pairs,
+                              const omniseg_output* outs, void* workspace,
+                              int64_t ws_bytes, omniseg_stream stream);
+
+/* Regions of the workspace after omniseg_segment_slide, for inspection. */
+#define OMNISEG_REGION_PAD 0        /* int32[4] per slide: pad colour (index = slide) */
+#define OMNISEG_REGION_PYRAMID 1    /* uint16[E_y][E_x][4] box sums of (slide, scale slot);
+                                       index = slide * n_scales + slot; empty for 40x */
+#define OMNISEG_REGION_TISSUE 2     /* uint8[H_c][W_c] tissue map of a slide (index = slide) */
+#define OMNISEG_REGION_TILE_COUNT 3 /* int32: number of kept tiles */
+#define OMNISEG_REGION_TILE_LIST 4  /* int32[max_tiles][4]: (slide, slot, jy, jx) in list order */
+#define OMNISEG_REGION_TILE_INDEX 5 /* int32 per grid tile of (slide, slot): list index or -1,
+                                       row-major (jy, jx); index = slide * n_scales + slot */
+#define OMNISEG_REGION_TILE_LOGITS 6 /* float[max_tiles][max_pairs_per_scale][T][T] */
+/*
+ * Byte offset and size of one region inside the workspace for these slides
+ * and pairs (host arrays); the layout depends only on the arguments.
+ */
+int32_t omniseg_workspace_region(const omniseg_plan* plan, const omniseg_slide* slides,
+                                 int32_t n_slides, const omniseg_pair* pairs,
+                                 int32_t n_pairs, int32_t region, int32_t index,
+                                 int64_t* offset, int64_t* bytes);
+
+/*
+ * Stand-alone overlap-weighted stitch of one (slide, class, scale) plane
+ * (Section 2.2 overlap tiling; Section 2.3 merge).
+ *   tile_logits  device float[n_tiles][tile][tile], tile i at grid position
+ *                tile_yx[2 i], tile_yx[2 i + 1] (rows, columns of tiles).
+ *   tile_yx      device int32[n_tiles][2]: distinct grid positions inside the
+ *                ceil-grid of (height, width).
+ *   mask, logit  outputs as in omniseg_output (logit may be NULL).
+ *   workspace    device, >= omniseg_stitch_workspace_bytes bytes.
+ * For each pixel p: N = sum_t w_t(p) l_t, D = sum_t w_t(p) over the tiles
+ * covering p, w(i, j) = r(i) r(j), r(i) = min(i + 1, T - i); the logit is N / D
+ * (0 where D = 0), the mask is N > 0.  N is accumulated in FP32 with
+ * compensated (Neumaier) summation over the covering tiles in (jy, jx) order;
+ * D is an exact integer.
+ */
+int32_t omniseg_stitch_workspace_bytes(int32_t tile, int32_t stride, int32_t height,
+                                       int32_t width, int64_t* bytes);
+int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32_t width,
+                             const float* tile_logits, const int32_t* tile_yx,
+                             int32_t n_tiles, uint8_t* mask, int64_t mask_pitch,
+                             float* logit, int64_t logit_pitch, void* workspace,
+                             int64_t ws_bytes, omniseg_stream stream);
+
+/*
+ * Per-launch profiling.  With profiling enabled, omniseg_segment_slide
+ * records a pair of HIP events around every kernel launch on the call's
+ * stream, plus the launch's algorithmic work: FLOPs of the arithmetic the
+ * method defines (2 per multiply-add, real channel counts, no padding) and
+ * the HBM bytes the step must move at minimum.  omniseg_read_profile waits
+ * for those events and returns the records of the last profiled call.
+ * Profiling creates HIP events lazily and is off by default.
+ */
+#define OMNISEG_STAGE_PREP 0       /* pad colour, pyramid, tissue map, tile list */
+#define OMNISEG_STAGE_FIRST_CONV 1 /* encoder level 0, first conv (3 -> C_0)     */
+#define OMNISEG_STAGE_ENC_A 2      /* encoder first conv (with fused 2x2 max-pool) */
+#define OMNISEG_STAGE_ENC_B 3      /* encoder second conv (+ residual)          */
+#define OMNISEG_STAGE_DEC_A 4      /* decoder first conv (fused upsample+concat) */
+#define OMNISEG_STAGE_DEC_B 5      /* decoder second conv (+ residual)          */
+#define OMNISEG_STAGE_GAP_CTRL 6   /* bottleneck mean and controller            */
+#define OMNISEG_STAGE_HEAD 7       /* precls and dynamic head                   */
+#define OMNISEG_STAGE_STITCH 8     /* overlap-weighted stitch of one plane      */
+
+typedef struct omniseg_launch_record {
+  int32_t stage;  /* OMNISEG_STAGE_* */
+  int32_t level;  /* U-Net level, or -1 */
+  int32_t tiles;  /* tiles the launch processes (0 if not tile-based) */
+  int32_t precision;
+  double flops;   /* algorithmic FLOPs */
+  double bytes;   /* algorithmic HBM bytes */
+  double ms;      /* elapsed time between the events around the launch */
+} omniseg_launch_record;
+
+int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable);
+/* Waits for the last profiled call's events; copies min(cap, n) records to
+ * recs (host array) and the total number of records to *n. */
+int32_t omniseg_read_profile(omniseg_plan* plan, omniseg_launch_record* recs, int32_t cap,
+                             int32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OMNISEG_H */

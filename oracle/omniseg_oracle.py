@@ -273,12 +273,28 @@ def conv3x3(X, Wt, b):
     Y = np.zeros((Wt.shape[0], H * W))
     for i in range(3):
         for j in range(3):
-            Y += Wt[:, :, i, j] @ Xp[:, i:i + H, j:j + W].reshape(Cin, H * W)
+            # contiguous operands keep numpy on its BLAS path
+            Wij = np.ascontiguousarray(Wt[:, :, i, j])
+            Y += Wij @ Xp[:, i:i + H, j:j + W].reshape(Cin, H * W)
     return Y.reshape(-1, H, W) + b[:, None, None]
 
 
 def relu(x):
     return np.maximum(x, 0.0)
+
+
+def round_bf16(x):
+    """Round to bfloat16 (1 sign, 8 exponent, 7 fraction bits), ties to even.
+
+    bfloat16 keeps the upper 16 bits of an IEEE float32.  Values are first
+    rounded to float32, then the low 16 bits are rounded away: add 0x7FFF
+    plus the lowest kept bit and truncate.  Used only to emulate a path that
+    stores activations and weights in bfloat16.
+    """
+    f = np.asarray(x, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 def maxpool2(X):
@@ -291,7 +307,17 @@ def up2(X):
     return np.repeat(np.repeat(X, 2, axis=1), 2, axis=2)
 
 
-def unet_forward(x, wts, cfg, keep=False):
+def bf16_weights(wts):
+    """Weights as a bfloat16 backbone stores them: every 3x3 conv except the
+    first (3 -> C_0) in bfloat16; first conv, precls and controller in FP32."""
+    out = dict(wts)
+    for k, v in wts.items():
+        if k.endswith(".w") and (k.startswith("enc") or k.startswith("dec")) and k != "enc0.a.w":
+            out[k] = round_bf16(v)
+    return out
+
+
+def unet_forward(x, wts, cfg, keep=False, store=None):
     """Residual U-Net on one tile.
 
     Encoder level l: A = ReLU(conv_a(X_l)); E_l = ReLU(conv_b(A) + A);
@@ -299,18 +325,20 @@ def unet_forward(x, wts, cfg, keep=False):
     Z = concat(up2(D_{l+1}), E_l); A = ReLU(conv_a(Z)); D_l = ReLU(conv_b(A) + A),
     with D_{L-1} = E_{L-1}.  Head input F = ReLU(W_p D_0 + b_p) if C_0 != 8,
     else D_0.  Returns (F, g) with g the pixel mean of E_{L-1}; with keep,
-    also a dict of every intermediate for the reverse pass.
+    also a dict of every intermediate for the reverse pass.  `store`, if
+    given, rounds every conv output as a reduced-precision path stores it.
     """
     L = cfg["levels"]
     C = channels(cfg)
     saved = {}
+    q = store if store is not None else (lambda v: v)
     X = x
     E = []
     for l in range(L):
         if l > 0:
             X = maxpool2(E[l - 1])
-        A = relu(conv3x3(X, wts[f"enc{l}.a.w"], wts[f"enc{l}.a.b"]))
-        El = relu(conv3x3(A, wts[f"enc{l}.b.w"], wts[f"enc{l}.b.b"]) + A)
+        A = q(relu(conv3x3(X, wts[f"enc{l}.a.w"], wts[f"enc{l}.a.b"])))
+        El = q(relu(conv3x3(A, wts[f"enc{l}.b.w"], wts[f"enc{l}.b.b"]) + A))
         if keep:
             saved[f"enc{l}.X"] = X
             saved[f"enc{l}.A"] = A
@@ -318,8 +346,8 @@ def unet_forward(x, wts, cfg, keep=False):
     D = E[L - 1]
     for l in range(L - 2, -1, -1):
         Z = np.concatenate([up2(D), E[l]], axis=0)
-        A = relu(conv3x3(Z, wts[f"dec{l}.a.w"], wts[f"dec{l}.a.b"]))
-        D = relu(conv3x3(A, wts[f"dec{l}.b.w"], wts[f"dec{l}.b.b"]) + A)
+        A = q(relu(conv3x3(Z, wts[f"dec{l}.a.w"], wts[f"dec{l}.a.b"])))
+        D = q(relu(conv3x3(A, wts[f"dec{l}.b.w"], wts[f"dec{l}.b.b"]) + A))
         if keep:
             saved[f"dec{l}.Z"] = Z
             saved[f"dec{l}.A"] = A
@@ -386,9 +414,9 @@ def head(F, theta, o):
     return z[0] if o == 1 else z[1] - z[0]
 
 
-def tile_logits(x, wts, cfg, si, classes):
+def tile_logits(x, wts, cfg, si, classes, store=None):
     """Logits of one tile for the given classes (all at the tile's scale slot)."""
-    F, g = unet_forward(x, wts, cfg)
+    F, g = unet_forward(x, wts, cfg, store=store)
     return np.stack([head(F, controller(g, c, si, wts, cfg), cfg["head_out"]) for c in classes])
 
 
@@ -436,15 +464,21 @@ def fg_at_scale(fg, kc, k, H_k, W_k):
 # --------------------------------------------------------------------------
 
 
-def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False):
+def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False, emulate=None):
     """Masks and stitched logits for every (slide, pair).
 
     slides: list of uint8 HWC arrays; pairs: list of (class, scale slot).
     Returns dict with 'mask'[n][p] (bool H_k x W_k), 'logit'[n][p] (float64),
     'tiles' (the kept tile list), 'pad' per slide, 'fg' per slide, and with
     keep_tiles the per-tile logits {(n, si, jy, jx): {class: TxT}}.
+    emulate="bf16" rounds weights and stored activations as a bfloat16
+    backbone does (round_bf16); the default is exact FP64.
     """
     wts = unpack_weights(flat_weights, cfg)
+    store = None
+    if emulate == "bf16":
+        wts = bf16_weights(wts)
+        store = round_bf16
     T, s = cfg["tile"], cfg["stride"]
     kc = max(cfg["scales"])
     need_fg = cfg["fg_filter"] or cfg["mask_and_fg"]
@@ -459,7 +493,7 @@ def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False
             continue
         k = cfg["scales"][si]
         x = tile_input(slides[n], k, T, s, jy, jx)
-        lg = tile_logits(x, wts, cfg, si, classes)
+        lg = tile_logits(x, wts, cfg, si, classes, store=store)
         per_tile[(n, si, jy, jx)] = {c: lg[i] for i, c in enumerate(classes)}
     masks, logits = [], []
     for n, rgb in enumerate(slides):
@@ -521,7 +555,7 @@ def conv3x3_backward(X, Wt, dY):
         for j in range(3):
             sl = Xp[:, i:i + H, j:j + W].reshape(Cin, H * W)
             dW[:, :, i, j] = dY2 @ sl.T
-            dXp[:, i:i + H, j:j + W] += (Wt[:, :, i, j].T @ dY2).reshape(Cin, H, W)
+            dXp[:, i:i + H, j:j + W] += (np.ascontiguousarray(Wt[:, :, i, j].T) @ dY2).reshape(Cin, H, W)
     return dXp[:, 1:H + 1, 1:W + 1], dW, dY2.sum(axis=1)
 
 

@@ -1,0 +1,800 @@
+// C ABI of the omniseg library: plan, validation, workspace layout and the
+// orchestration of the slide-wise segmentation on one HIP stream.
+//
+// Validation runs entirely on the host before the first HIP call, so an
+// invalid call launches nothing and writes nothing.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace omniseg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(OMNISEG_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+struct ConvDesc {
+  int64_t canon_w, canon_b;
+  int cin, cout, cu;
+  int cin_p, cout_p, cu_p;
+  int64_t pk_w, pk_b;
+};
+
+int elem_size(int precision) { return precision == OMNISEG_BF16 ? 2 : 4; }
+
+}  // namespace
+
+struct omniseg_plan {
+  omniseg_config cfg;
+  int L = 0;
+  int C[8] = {0};
+  int Cp[8] = {0};
+  int P = 0;
+  int G = 0;
+  int64_t n_canon = 0;
+  ConvDesc enc_a[8], enc_b[8], dec_a[8], dec_b[8];
+  int64_t canon_first_w = 0, canon_first_b = 0, pk_first_w = 0, pk_first_b = 0;
+  int64_t canon_pre_w = -1, canon_pre_b = -1, pk_pre_w = 0, pk_pre_b = 0;
+  int64_t canon_ctrl_w = 0, canon_ctrl_b = 0, pk_ctrl_w = 0, pk_ctrl_b = 0;
+  int64_t packed_bytes = 0;
+  mutable std::vector<SlideDev> slide_tab;  // host staging of the device slide table
+  // per-launch profiling (off by default)
+  bool profiling = false;
+  mutable std::vector<hipEvent_t> events;
+  mutable std::vector<omniseg_launch_record> recs;
+  ~omniseg_plan() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+// Records a pair of events around each launch when profiling is on.
+struct Prof {
+  const omniseg_plan* p;
+  hipStream_t st;
+  size_t next = 0;
+  hipError_t begin() {
+    if (!p->profiling) return hipSuccess;
+    while (p->events.size() < 2 * (next + 1)) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      p->events.push_back(e);
+    }
+    return hipEventRecord(p->events[2 * next], st);
+  }
+  hipError_t end(int stage, int level, int tiles, double flops, double bytes) {
+    if (!p->profiling) return hipSuccess;
+    hipError_t r = hipEventRecord(p->events[2 * next + 1], st);
+    omniseg_launch_record rec;
+    rec.stage = stage;
+    rec.level = level;
+    rec.tiles = tiles;
+    rec.precision = p->cfg.precision;
+    rec.flops = flops;
+    rec.bytes = bytes;
+    rec.ms = 0.0;
+    p->recs.push_back(rec);
+    ++next;
+    return r;
+  }
+};
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// workspace layout of one segment call
+// ---------------------------------------------------------------------------
+
+struct Layout {
+  int n_slides = 0;
+  int S = 0;
+  int kmax = 0, kc = 0;
+  bool need_fg = false;
+  ScaleGeom geom[OMNISEG_MAX_SLIDES][OMNISEG_MAX_SCALES];
+  int Hc[OMNISEG_MAX_SLIDES], Wc[OMNISEG_MAX_SLIDES];
+  TileGroups groups;
+  int total_tiles = 0;
+  int batch = 0;
+  SlotTable slots;
+  int max_slots = 0;
+  int pair_slot[256];  // slot index of each pair within its scale
+  int64_t off_tab = 0, off_pad[OMNISEG_MAX_SLIDES], off_pyr[OMNISEG_MAX_SLIDES][OMNISEG_MAX_SCALES],
+          off_fg[OMNISEG_MAX_SLIDES];
+  int64_t sz_pyr[OMNISEG_MAX_SLIDES][OMNISEG_MAX_SCALES], sz_fg[OMNISEG_MAX_SLIDES];
+  int64_t off_index = 0, off_list = 0, off_count = 0;
+  int64_t off_E[8], off_A = 0, off_g = 0, off_theta = 0, off_logits = 0;
+  int64_t sz_E[8], sz_A = 0, sz_logits = 0;
+  int64_t total = 0;
+};
+
+int32_t validate_config(const omniseg_config* c) {
+  if (!c) return fail(OMNISEG_ERR_ARG, "config is NULL");
+  if (c->abi_version != OMNISEG_ABI_VERSION)
+    return fail(OMNISEG_ERR_ARG, "abi_version %d, library has %d", c->abi_version, OMNISEG_ABI_VERSION);
+  if (c->base_channels < 1 || c->base_channels > 128)
+    return fail(OMNISEG_ERR_ARG, "base_channels %d outside [1, 128]", c->base_channels);
+  if (c->levels < 1 || c->levels > 7) return fail(OMNISEG_ERR_ARG, "levels %d outside [1, 7]", c->levels);
+  if (c->head_out != 1 && c->head_out != 2) return fail(OMNISEG_ERR_ARG, "head_out must be 1 or 2");
+  if (c->n_classes < 1 || c->n_classes > OMNISEG_MAX_CLASSES)
+    return fail(OMNISEG_ERR_ARG, "n_classes %d outside [1, %d]", c->n_classes, OMNISEG_MAX_CLASSES);
+  if (c->n_scales < 1 || c->n_scales > OMNISEG_MAX_SCALES)
+    return fail(OMNISEG_ERR_ARG, "n_scales %d outside [1, %d]", c->n_scales, OMNISEG_MAX_SCALES);
+  for (int i = 0; i < c->n_scales; ++i)
+    if (c->scale_log2[i] < 0 || c->scale_log2[i] > 3)
+      return fail(OMNISEG_ERR_ARG, "scale_log2[%d] = %d outside [0, 3]", i, c->scale_log2[i]);
+  if (c->tile < 16 || c->tile > 512 || c->tile % 16)
+    return fail(OMNISEG_ERR_ARG, "tile %d must be a multiple of 16 in [16, 512]", c->tile);
+  if (c->stride < 1 || c->stride > c->tile)
+    return fail(OMNISEG_ERR_ARG, "stride %d outside [1, tile]", c->stride);
+  const int deep = c->tile >> (c->levels - 1);
+  if ((c->tile % (1 << (c->levels - 1))) || deep < 8 || deep % 8)
+    return fail(OMNISEG_ERR_UNSUPPORTED, "tile / 2^(levels-1) = %d must be a multiple of 8", deep);
+  if (c->fg_filter != 0 && c->fg_filter != 1) return fail(OMNISEG_ERR_ARG, "fg_filter must be 0 or 1");
+  if (c->mask_and_fg != 0 && c->mask_and_fg != 1) return fail(OMNISEG_ERR_ARG, "mask_and_fg must be 0 or 1");
+  if (c->fg_threshold < 1 || c->fg_threshold > 255)
+    return fail(OMNISEG_ERR_ARG, "fg_threshold %d outside [1, 255]", c->fg_threshold);
+  if (c->precision != OMNISEG_FP32 && c->precision != OMNISEG_BF16)
+    return fail(OMNISEG_ERR_UNSUPPORTED, "unknown precision %d", c->precision);
+  if (c->flags & ~OMNISEG_FLAG_EMIT_LOGITS) return fail(OMNISEG_ERR_ARG, "unknown flags 0x%x", c->flags);
+  if (c->batch_tiles < 0 || c->batch_tiles > 65536)
+    return fail(OMNISEG_ERR_ARG, "batch_tiles %d outside [0, 65536]", c->batch_tiles);
+  const int64_t G = (int64_t)c->base_channels << (c->levels - 1);
+  if (G > 4096) return fail(OMNISEG_ERR_UNSUPPORTED, "bottleneck width %lld > 4096", (long long)G);
+  return OMNISEG_OK;
+}
+
+int32_t validate_call(const omniseg_plan* plan, const omniseg_slide* slides, int32_t n_slides,
+                      const omniseg_pair* pairs, int32_t n_pairs, Layout& lay) {
+  if (!plan) return fail(OMNISEG_ERR_ARG, "plan is NULL");
+  if (!slides) return fail(OMNISEG_ERR_ARG, "slides is NULL");
+  if (!pairs) return fail(OMNISEG_ERR_ARG, "pairs is NULL");
+  if (n_slides < 1 || n_slides > OMNISEG_MAX_SLIDES)
+    return fail(OMNISEG_ERR_ARG, "n_slides %d outside [1, %d]", n_slides, OMNISEG_MAX_SLIDES);
+  const omniseg_config& c = plan->cfg;
+  if (n_pairs < 1 || n_pairs > c.n_classes * c.n_scales)
+    return fail(OMNISEG_ERR_ARG, "n_pairs %d outside [1, %d]", n_pairs, c.n_classes * c.n_scales);
+  for (int i = 0; i < n_slides; ++i) {
+    const omniseg_slide& s = slides[i];
+    if (!s.rgb) return fail(OMNISEG_ERR_ARG, "slide %d: rgb is NULL", i);
+    if (s.height < 2 || s.width < 2) return fail(OMNISEG_ERR_ARG, "slide %d: size %dx%d below 2x2", i, s.height, s.width);
+    if (s.height > (1 << 20) || s.width > (1 << 20))
+      return fail(OMNISEG_ERR_UNSUPPORTED, "slide %d: side above 2^20", i);
+    if (s.row_pitch < 3LL * s.width) return fail(OMNISEG_ERR_ARG, "slide %d: row_pitch %lld < 3*width", i, (long long)s.row_pitch);
+  }
+  bool seen[OMNISEG_MAX_CLASSES][OMNISEG_MAX_SCALES] = {};
+  lay.S = c.n_scales;
+  for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) lay.slots.n_slots[si] = 0;
+  for (int p = 0; p < n_pairs; ++p) {
+    const int cl = pairs[p].cls, sc = pairs[p].scale;
+    if (cl < 0 || cl >= c.n_classes) return fail(OMNISEG_ERR_ARG, "pair %d: class %d outside [0, %d)", p, cl, c.n_classes);
+    if (sc < 0 || sc >= c.n_scales) return fail(OMNISEG_ERR_ARG, "pair %d: scale %d outside [0, %d)", p, sc, c.n_scales);
+    if (seen[cl][sc]) return fail(OMNISEG_ERR_ARG, "pair %d: (class %d, scale %d) repeated", p, cl, sc);
+    seen[cl][sc] = true;
+    lay.pair_slot[p] = lay.slots.n_slots[sc];
+    lay.slots.cls[sc][lay.slots.n_slots[sc]++] = cl;
+  }
+  lay.max_slots = 0;
+  for (int si = 0; si < c.n_scales; ++si) lay.max_slots = std::max(lay.max_slots, lay.slots.n_slots[si]);
+  return OMNISEG_OK;
+}
+
+void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32_t n_slides,
+                    Layout& lay) {
+  const omniseg_config& c = plan->cfg;
+  const int T = c.tile, s = c.stride;
+  lay.n_slides = n_slides;
+  lay.kmax = 0;
+  for (int si = 0; si < c.n_scales; ++si) lay.kmax = std::max(lay.kmax, c.scale_log2[si]);
+  lay.kc = lay.kmax;
+  lay.need_fg = c.fg_filter || c.mask_and_fg;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t o = off;
+    off += align256(std::max<int64_t>(bytes, 1));
+    return o;
+  };
+  lay.off_tab = take((int64_t)n_slides * sizeof(SlideDev));
+  lay.groups.n = 0;
+  int tiles = 0;
+  for (int i = 0; i < n_slides; ++i) {
+    lay.off_pad[i] = take(16);
+    for (int si = 0; si < c.n_scales; ++si) {
+      const ScaleGeom g = make_geom(slides[i].height, slides[i].width, c.scale_log2[si], T, s);
+      lay.geom[i][si] = g;
+      lay.sz_pyr[i][si] = g.k >= 1 ? (int64_t)g.Ey * g.Ex * 8 : 0;
+      lay.off_pyr[i][si] = g.k >= 1 ? take(lay.sz_pyr[i][si]) : -1;
+      const int gi = lay.groups.n++;
+      lay.groups.base[gi] = tiles;
+      lay.groups.ny[gi] = (short)g.ny;
+      lay.groups.nx[gi] = (short)g.nx;
+      lay.groups.slide[gi] = (char)i;
+      lay.groups.slot[gi] = (char)si;
+      lay.groups.k[gi] = (char)g.k;
+      tiles += g.ny * g.nx;
+    }
+    lay.Hc[i] = ceil_div(slides[i].height, 1 << lay.kc);
+    lay.Wc[i] = ceil_div(slides[i].width, 1 << lay.kc);
+    lay.sz_fg[i] = lay.need_fg ? (int64_t)lay.Hc[i] * lay.Wc[i] : 0;
+    lay.off_fg[i] = lay.need_fg ? take(lay.sz_fg[i]) : -1;
+  }
+  lay.groups.base[lay.groups.n] = tiles;
+  lay.total_tiles = tiles;
+  lay.off_index = take((int64_t)tiles * 4);
+  lay.off_list = take((int64_t)tiles * 16);
+  lay.off_count = take(4);
+  const int bt = c.batch_tiles > 0 ? c.batch_tiles : 256;
+  lay.batch = std::min(bt, tiles);
+  const int es = elem_size(c.precision);
+  for (int l = 0; l < plan->L; ++l) {
+    const int tl = T >> l;
+    lay.sz_E[l] = (int64_t)lay.batch * tl * tl * plan->Cp[l] * es;
+    lay.off_E[l] = take(lay.sz_E[l]);
+  }
+  lay.sz_A = (int64_t)lay.batch * T * T * plan->Cp[0] * es;
+  lay.off_A = take(lay.sz_A);
+  lay.off_g = take((int64_t)lay.batch * plan->Cp[plan->L - 1] * 4);
+  lay.off_theta = take((int64_t)lay.batch * lay.max_slots * plan->P * 4);
+  lay.sz_logits = (int64_t)tiles * lay.max_slots * T * T * 4;
+  lay.off_logits = take(lay.sz_logits);
+  lay.total = off;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* omniseg_status_string(int32_t status) {
+  switch (status) {
+    case OMNISEG_OK: return "ok";
+    case OMNISEG_ERR_ARG: return "invalid argument";
+    case OMNISEG_ERR_UNSUPPORTED: return "unsupported configuration";
+    case OMNISEG_ERR_WORKSPACE: return "workspace too small";
+    case OMNISEG_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* omniseg_last_error(void) { return g_last_error.c_str(); }
+
+int32_t omniseg_plan_create(const omniseg_config* cfg, omniseg_plan** out) {
+  if (!out) return fail(OMNISEG_ERR_ARG, "out is NULL");
+  int32_t st = validate_config(cfg);
+  if (st) return st;
+  omniseg_plan* p = new (std::nothrow) omniseg_plan();
+  if (!p) return fail(OMNISEG_ERR_ARG, "out of host memory");
+  p->cfg = *cfg;
+  p->L = cfg->levels;
+  for (int l = 0; l < p->L; ++l) {
+    p->C[l] = cfg->base_channels << l;
+    p->Cp[l] = pad_ch(p->C[l]);
+  }
+  p->P = 144 + 9 * cfg->head_out;
+  p->G = p->C[p->L - 1];
+  const int es = elem_size(cfg->precision);
+  int64_t canon = 0, pk = 0;
+  auto ptake = [&](int64_t bytes) {
+    int64_t o = pk;
+    pk += align256(std::max<int64_t>(bytes, 1));
+    return o;
+  };
+  auto conv = [&](ConvDesc& d, int cin, int cout, int cu, int cu_p, int cin_p) {
+    d.canon_w = canon;
+    canon += (int64_t)cout * cin * 9;
+    d.canon_b = canon;
+    canon += cout;
+    d.cin = cin;
+    d.cout = cout;
+    d.cu = cu;
+    d.cu_p = cu_p;
+    d.cin_p = cin_p;
+    d.cout_p = pad_ch(cout);
+    d.pk_w = ptake((int64_t)d.cin_p * 9 * d.cout_p * es);
+    d.pk_b = ptake((int64_t)d.cout_p * 4);
+  };
+  for (int l = 0; l < p->L; ++l) {
+    if (l == 0) {
+      p->canon_first_w = canon;
+      canon += (int64_t)p->C[0] * 27;
+      p->canon_first_b = canon;
+      canon += p->C[0];
+      p->pk_first_w = ptake((int64_t)p->C[0] * 27 * 4);
+      p->pk_first_b = ptake((int64_t)p->C[0] * 4);
+    } else {
+      conv(p->enc_a[l], p->C[l - 1], p->C[l], p->C[l - 1], p->Cp[l - 1], p->Cp[l - 1]);
+    }
+    conv(p->enc_b[l], p->C[l], p->C[l], p->C[l], p->Cp[l], p->Cp[l]);
+  }
+  for (int l = p->L - 2; l >= 0; --l) {
+    const int cu = p->C[l + 1], cu_p = p->Cp[l + 1];
+    conv(p->dec_a[l], 3 * p->C[l], p->C[l], cu, cu_p, cu_p + p->Cp[l]);
+    conv(p->dec_b[l], p->C[l], p->C[l], p->C[l], p->Cp[l], p->Cp[l]);
+  }
+  if (p->C[0] != 8) {
+    p->canon_pre_w = canon;
+    canon += 8LL * p->C[0];
+    p->canon_pre_b = canon;
+    canon += 8;
+    p->pk_pre_w = ptake(8LL * p->C[0] * 4);
+    p->pk_pre_b = ptake(8 * 4);
+  }
+  const int row = p->G + cfg->n_classes + cfg->n_scales;
+  p->canon_ctrl_w = canon;
+  canon += (int64_t)p->P * row;
+  p->canon_ctrl_b = canon;
+  canon += p->P;
+  p->pk_ctrl_w = ptake((int64_t)p->P * row * 4);
+  p->pk_ctrl_b = ptake((int64_t)p->P * 4);
+  p->n_canon = canon;
+  p->packed_bytes = pk;
+  *out = p;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_plan_destroy(omniseg_plan* plan) {
+  delete plan;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_weight_count(const omniseg_plan* plan, int64_t* count) {
+  if (!plan || !count) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  *count = plan->n_canon;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_packed_weight_bytes(const omniseg_plan* plan, int64_t* bytes) {
+  if (!plan || !bytes) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  *bytes = plan->packed_bytes;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_pack_weights(const omniseg_plan* plan, const float* canonical, void* packed,
+                             omniseg_stream stream) {
+  if (!plan || !canonical || !packed) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(packed) % 256) return fail(OMNISEG_ERR_ARG, "packed buffer not 256-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int prec = plan->cfg.precision;
+  char* pk = static_cast<char*>(packed);
+  auto pack = [&](const ConvDesc& d) -> hipError_t {
+    PackConv pc;
+    pc.src = d.canon_w;
+    pc.src_b = d.canon_b;
+    pc.cout = d.cout;
+    pc.cin = d.cin;
+    pc.cu = d.cu;
+    pc.cu_p = d.cu_p;
+    pc.cin_p = d.cin_p;
+    pc.cout_p = d.cout_p;
+    pc.dst = d.pk_w;
+    pc.dst_b = d.pk_b;
+    return launch_pack_conv(prec, canonical, packed, pc, st);
+  };
+  HIP_TRY(launch_copy_f32(canonical + plan->canon_first_w, (float*)(pk + plan->pk_first_w), (int64_t)plan->C[0] * 27, st));
+  HIP_TRY(launch_copy_f32(canonical + plan->canon_first_b, (float*)(pk + plan->pk_first_b), plan->C[0], st));
+  for (int l = 0; l < plan->L; ++l) {
+    if (l > 0) HIP_TRY(pack(plan->enc_a[l]));
+    HIP_TRY(pack(plan->enc_b[l]));
+  }
+  for (int l = plan->L - 2; l >= 0; --l) {
+    HIP_TRY(pack(plan->dec_a[l]));
+    HIP_TRY(pack(plan->dec_b[l]));
+  }
+  if (plan->canon_pre_w >= 0) {
+    HIP_TRY(launch_copy_f32(canonical + plan->canon_pre_w, (float*)(pk + plan->pk_pre_w), 8LL * plan->C[0], st));
+    HIP_TRY(launch_copy_f32(canonical + plan->canon_pre_b, (float*)(pk + plan->pk_pre_b), 8, st));
+  }
+  const int row = plan->G + plan->cfg.n_classes + plan->cfg.n_scales;
+  HIP_TRY(launch_copy_f32(canonical + plan->canon_ctrl_w, (float*)(pk + plan->pk_ctrl_w), (int64_t)plan->P * row, st));
+  HIP_TRY(launch_copy_f32(canonical + plan->canon_ctrl_b, (float*)(pk + plan->pk_ctrl_b), plan->P, st));
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_workspace_bytes(const omniseg_plan* plan, const omniseg_slide* slides,
+                                int32_t n_slides, const omniseg_pair* pairs, int32_t n_pairs,
+                                int64_t* bytes) {
+  if (!bytes) return fail(OMNISEG_ERR_ARG, "bytes is NULL");
+  Layout lay;
+  int32_t st = validate_call(plan, slides, n_slides, pairs, n_pairs, lay);
+  if (st) return st;
+  compute_layout(plan, slides, n_slides, lay);
+  *bytes = lay.total;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_workspace_region(const omniseg_plan* plan, const omniseg_slide* slides,
+                                 int32_t n_slides, const omniseg_pair* pairs, int32_t n_pairs,
+                                 int32_t region, int32_t index, int64_t* offset, int64_t* bytes) {
+  if (!offset || !bytes) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  Layout lay;
+  int32_t st = validate_call(plan, slides, n_slides, pairs, n_pairs, lay);
+  if (st) return st;
+  compute_layout(plan, slides, n_slides, lay);
+  const int S = plan->cfg.n_scales;
+  switch (region) {
+    case OMNISEG_REGION_PAD:
+      if (index < 0 || index >= n_slides) break;
+      *offset = lay.off_pad[index];
+      *bytes = 16;
+      return OMNISEG_OK;
+    case OMNISEG_REGION_PYRAMID:
+      if (index < 0 || index >= n_slides * S) break;
+      *offset = lay.off_pyr[index / S][index % S];
+      *bytes = lay.sz_pyr[index / S][index % S];
+      return OMNISEG_OK;
+    case OMNISEG_REGION_TISSUE:
+      if (index < 0 || index >= n_slides) break;
+      *offset = lay.off_fg[index];
+      *bytes = lay.sz_fg[index];
+      return OMNISEG_OK;
+    case OMNISEG_REGION_TILE_COUNT:
+      *offset = lay.off_count;
+      *bytes = 4;
+      return OMNISEG_OK;
+    case OMNISEG_REGION_TILE_LIST:
+      *offset = lay.off_list;
+      *bytes = (int64_t)lay.total_tiles * 16;
+      return OMNISEG_OK;
+    case OMNISEG_REGION_TILE_INDEX: {
+      if (index < 0 || index >= n_slides * S) break;
+      const int gi = index;  // groups are enumerated slide-major, slot-minor
+      *offset = lay.off_index + (int64_t)lay.groups.base[gi] * 4;
+      *bytes = (int64_t)(lay.groups.base[gi + 1] - lay.groups.base[gi]) * 4;
+      return OMNISEG_OK;
+    }
+    case OMNISEG_REGION_TILE_LOGITS:
+      *offset = lay.off_logits;
+      *bytes = lay.sz_logits;
+      return OMNISEG_OK;
+    default:
+      return fail(OMNISEG_ERR_ARG, "unknown region %d", region);
+  }
+  return fail(OMNISEG_ERR_ARG, "region %d: index %d out of range", region, index);
+}
+
+int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
+                              const omniseg_slide* slides, int32_t n_slides,
+                              const omniseg_pair* pairs, int32_t n_pairs,
+                              const omniseg_output* outs, void* workspace, int64_t ws_bytes,
+                              omniseg_stream stream) {
+  Layout lay;
+  int32_t st = validate_call(plan, slides, n_slides, pairs, n_pairs, lay);
+  if (st) return st;
+  if (!packed) return fail(OMNISEG_ERR_ARG, "packed weights are NULL");
+  if (!outs) return fail(OMNISEG_ERR_ARG, "outs is NULL");
+  if (!workspace) return fail(OMNISEG_ERR_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 || reinterpret_cast<uintptr_t>(packed) % 256)
+    return fail(OMNISEG_ERR_ARG, "workspace and packed weights must be 256-byte aligned");
+  const omniseg_config& c = plan->cfg;
+  const bool emit = (c.flags & OMNISEG_FLAG_EMIT_LOGITS) != 0;
+  for (int i = 0; i < n_slides; ++i) {
+    for (int p = 0; p < n_pairs; ++p) {
+      const omniseg_output& o = outs[(int64_t)i * n_pairs + p];
+      const int Wk = ceil_div(slides[i].width, 1 << c.scale_log2[pairs[p].scale]);
+      if (!o.mask) return fail(OMNISEG_ERR_ARG, "output (%d, %d): mask is NULL", i, p);
+      if (o.mask_pitch < Wk) return fail(OMNISEG_ERR_ARG, "output (%d, %d): mask_pitch %lld < %d", i, p, (long long)o.mask_pitch, Wk);
+      if (emit && !o.logit) return fail(OMNISEG_ERR_ARG, "output (%d, %d): logit is NULL with EMIT_LOGITS", i, p);
+      if (emit && o.logit_pitch < Wk) return fail(OMNISEG_ERR_ARG, "output (%d, %d): logit_pitch %lld < %d", i, p, (long long)o.logit_pitch, Wk);
+    }
+  }
+  compute_layout(plan, slides, n_slides, lay);
+  if (ws_bytes < lay.total)
+    return fail(OMNISEG_ERR_WORKSPACE, "workspace has %lld bytes, needs %lld", (long long)ws_bytes, (long long)lay.total);
+
+  // ---- all checks passed: enqueue the work ----
+  hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const char* pk = static_cast<const char*>(packed);
+  const int T = c.tile, s = c.stride, prec = c.precision;
+
+  plan->slide_tab.assign(n_slides, SlideDev());
+  for (int i = 0; i < n_slides; ++i) {
+    SlideDev& d = plan->slide_tab[i];
+    d.rgb = slides[i].rgb;
+    d.pitch = slides[i].row_pitch;
+    d.H = slides[i].height;
+    d.W = slides[i].width;
+    d.pad = reinterpret_cast<const int32_t*>(ws + lay.off_pad[i]);
+    for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) {
+      d.pyr[si] = nullptr;
+      d.pyr_ex[si] = 0;
+      if (si < c.n_scales && lay.off_pyr[i][si] >= 0) {
+        d.pyr[si] = reinterpret_cast<const uint16_t*>(ws + lay.off_pyr[i][si]);
+        d.pyr_ex[si] = lay.geom[i][si].Ex;
+      }
+    }
+    d.fg = lay.need_fg ? reinterpret_cast<const uint8_t*>(ws + lay.off_fg[i]) : nullptr;
+    d.Hc = lay.Hc[i];
+    d.Wc = lay.Wc[i];
+  }
+  SlideDev* tab_dev = reinterpret_cast<SlideDev*>(ws + lay.off_tab);
+  HIP_TRY(hipMemcpyAsync(tab_dev, plan->slide_tab.data(), sizeof(SlideDev) * n_slides,
+                         hipMemcpyHostToDevice, sm));
+
+  Prof prof{plan, sm};
+  plan->recs.clear();
+  double prep_bytes = 0.0;
+  for (int i = 0; i < n_slides; ++i) {
+    prep_bytes += 3.0 * slides[i].height * slides[i].width;
+    for (int si = 0; si < c.n_scales; ++si)
+      if (lay.geom[i][si].k >= 1) prep_bytes += 6.0 * lay.geom[i][si].Ey * lay.geom[i][si].Ex;
+    prep_bytes += (double)lay.sz_fg[i];
+  }
+  HIP_TRY(prof.begin());
+
+  // 1. pad colour, pyramid, tissue map
+  for (int i = 0; i < n_slides; ++i) {
+    int32_t* pad = reinterpret_cast<int32_t*>(ws + lay.off_pad[i]);
+    HIP_TRY(launch_pad_colour(slides[i].rgb, slides[i].row_pitch, pad, sm));
+    uint16_t* lvl[4] = {nullptr, nullptr, nullptr, nullptr};
+    int Ey[4] = {0, 0, 0, 0}, Ex[4] = {0, 0, 0, 0};
+    for (int si = 0; si < c.n_scales; ++si) {
+      const ScaleGeom& g = lay.geom[i][si];
+      if (g.k >= 1) {
+        lvl[g.k] = reinterpret_cast<uint16_t*>(ws + lay.off_pyr[i][si]);
+        Ey[g.k] = g.Ey;
+        Ex[g.k] = g.Ex;
+      }
+    }
+    HIP_TRY(launch_pyramid(slides[i].rgb, slides[i].row_pitch, slides[i].height, slides[i].width, pad,
+                           lay.kmax, lvl, Ey, Ex, sm));
+    if (lay.need_fg) {
+      const uint16_t* sums = lay.kc >= 1 ? lvl[lay.kc] : nullptr;
+      const int ex = lay.kc >= 1 ? Ex[lay.kc] : 0;
+      HIP_TRY(launch_tissue(slides[i].rgb, slides[i].row_pitch, slides[i].height, slides[i].width, pad,
+                            sums, ex, lay.kc, lay.Hc[i], lay.Wc[i], c.fg_threshold,
+                            reinterpret_cast<uint8_t*>(ws + lay.off_fg[i]), sm));
+    }
+  }
+  // 2. tile flags and compaction; the kept-tile count sizes every later launch
+  int32_t* index = reinterpret_cast<int32_t*>(ws + lay.off_index);
+  int32_t* list = reinterpret_cast<int32_t*>(ws + lay.off_list);
+  int32_t* count = reinterpret_cast<int32_t*>(ws + lay.off_count);
+  HIP_TRY(launch_tile_flags(lay.groups, tab_dev, T, s, lay.kc, c.fg_filter, index, sm));
+  HIP_TRY(launch_compact(index, lay.total_tiles, lay.groups, list, count, sm));
+  HIP_TRY(prof.end(OMNISEG_STAGE_PREP, -1, 0, 0.0, prep_bytes));
+  int32_t n_kept = 0;
+  HIP_TRY(hipMemcpyAsync(&n_kept, count, sizeof(int32_t), hipMemcpyDeviceToHost, sm));
+  HIP_TRY(hipStreamSynchronize(sm));
+  if (n_kept < 0 || n_kept > lay.total_tiles)
+    return fail(OMNISEG_ERR_HIP, "kept-tile count %d outside [0, %d]", n_kept, lay.total_tiles);
+
+  // 3. backbone, controller and head, batch by batch
+  void* E[8];
+  for (int l = 0; l < plan->L; ++l) E[l] = ws + lay.off_E[l];
+  void* A = ws + lay.off_A;
+  float* g = reinterpret_cast<float*>(ws + lay.off_g);
+  float* theta = reinterpret_cast<float*>(ws + lay.off_theta);
+  float* logits = reinterpret_cast<float*>(ws + lay.off_logits);
+  auto layer = [&](const ConvDesc& d) {
+    ConvLayer L;
+    L.cin_p = d.cin_p;
+    L.cu_p = d.cu_p;
+    L.cout_p = d.cout_p;
+    L.w = pk + d.pk_w;
+    L.b = reinterpret_cast<const float*>(pk + d.pk_b);
+    return L;
+  };
+  const int es = elem_size(prec);
+  // algorithmic work of one 3x3 conv launch over `nt` tiles at h x h
+  auto conv_flops = [&](const ConvDesc& d, int h, int nt) { return 2.0 * 9 * d.cin * d.cout * (double)h * h * nt; };
+  auto conv_bytes = [&](const ConvDesc& d, int h, int nt, double in_px_factor, bool res) {
+    const double px = (double)h * h * nt;
+    return px * in_px_factor * d.cin * es + px * d.cout * es * (res ? 2 : 1) + 9.0 * d.cin * d.cout * es;
+  };
+  const int B = lay.batch;
+  FirstConvArgs fa;
+  fa.list = list;
+  fa.count = count;
+  fa.T = T;
+  fa.s = s;
+  fa.w = reinterpret_cast<const float*>(pk + plan->pk_first_w);
+  fa.b = reinterpret_cast<const float*>(pk + plan->pk_first_b);
+  fa.c0 = plan->C[0];
+  fa.c0_p = plan->Cp[0];
+  fa.y = A;
+  fa.slides = tab_dev;
+  for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) fa.scale_k[si] = si < c.n_scales ? c.scale_log2[si] : 0;
+  const int L = plan->L;
+  for (int base = 0; base < n_kept; base += B) {
+    const int nb = std::min(B, n_kept - base);
+    fa.chunk_base = base;
+    fa.batch = nb;
+    HIP_TRY(prof.begin());
+    HIP_TRY(launch_first_conv(prec, fa, sm));
+    HIP_TRY(prof.end(OMNISEG_STAGE_FIRST_CONV, 0, nb, 2.0 * 27 * plan->C[0] * (double)T * T * nb,
+                     (double)T * T * nb * (3.0 + plan->C[0] * es)));
+    HIP_TRY(prof.begin());
+    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[0]), T, T, nb, count, base, A, nullptr, E[0], sm));
+    HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, 0, nb, conv_flops(plan->enc_b[0], T, nb), conv_bytes(plan->enc_b[0], T, nb, 1.0, true)));
+    for (int l = 1; l < L; ++l) {
+      const int tl = T >> l;
+      HIP_TRY(prof.begin());
+      HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count, base, E[l - 1], nullptr, A, sm));
+      HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nb, conv_flops(plan->enc_a[l], tl, nb), conv_bytes(plan->enc_a[l], tl, nb, 4.0, false)));
+      HIP_TRY(prof.begin());
+      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm));
+      HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nb, conv_flops(plan->enc_b[l], tl, nb), conv_bytes(plan->enc_b[l], tl, nb, 1.0, true)));
+    }
+    const int tb = T >> (L - 1);
+    HIP_TRY(prof.begin());
+    HIP_TRY(launch_gap(prec, E[L - 1], nb, tb * tb, plan->Cp[L - 1], plan->G, count, base, g, sm));
+    HIP_TRY(launch_controller(g, nb, plan->G, reinterpret_cast<const float*>(pk + plan->pk_ctrl_w),
+                              reinterpret_cast<const float*>(pk + plan->pk_ctrl_b), plan->P, c.n_classes,
+                              c.n_scales, lay.slots, lay.max_slots, list, count, base, theta, sm));
+    HIP_TRY(prof.end(OMNISEG_STAGE_GAP_CTRL, L - 1, nb,
+                     (double)nb * ((double)plan->G * tb * tb + 2.0 * plan->P * plan->G * lay.max_slots),
+                     (double)nb * tb * tb * plan->G * es));
+    for (int l = L - 2; l >= 0; --l) {
+      const int tl = T >> l;
+      // decoder level l: Z = [up2(D_{l+1}) ; E_l]; D_{l+1} lives in E[l+1]'s buffer
+      HIP_TRY(prof.begin());
+      HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1], E[l], A, sm));
+      HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nb, conv_flops(plan->dec_a[l], tl, nb), conv_bytes(plan->dec_a[l], tl, nb, 0.5, false)));
+      HIP_TRY(prof.begin());
+      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm));
+      HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nb, conv_flops(plan->dec_b[l], tl, nb), conv_bytes(plan->dec_b[l], tl, nb, 1.0, true)));
+    }
+    HIP_TRY(prof.begin());
+    HIP_TRY(launch_head(prec, E[0], nb, T, plan->C[0], plan->Cp[0],
+                        plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_w) : nullptr,
+                        plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_b) : nullptr,
+                        theta, plan->P, c.head_out, lay.slots, lay.max_slots, list, count, base, logits, sm));
+    {
+      const double px = (double)T * T * nb;
+      const double pre = plan->canon_pre_w >= 0 ? 2.0 * 8 * plan->C[0] : 0.0;
+      // slots per tile vary with the tile's scale; count the largest
+      const double head = lay.max_slots * (2.0 * 64 + 2.0 * 64 + 2.0 * 8 * c.head_out);
+      HIP_TRY(prof.end(OMNISEG_STAGE_HEAD, 0, nb, px * (pre + head), px * (plan->C[0] * es + 4.0 * lay.max_slots)));
+    }
+  }
+
+  // 4. stitch every (slide, pair)
+  std::vector<int32_t> idx_host;
+  if (plan->profiling) {
+    idx_host.resize(lay.total_tiles);
+    HIP_TRY(hipMemcpyAsync(idx_host.data(), index, sizeof(int32_t) * lay.total_tiles, hipMemcpyDeviceToHost, sm));
+    HIP_TRY(hipStreamSynchronize(sm));
+  }
+  for (int i = 0; i < n_slides; ++i) {
+    for (int p = 0; p < n_pairs; ++p) {
+      const int si = pairs[p].scale;
+      const ScaleGeom& gm = lay.geom[i][si];
+      const omniseg_output& o = outs[(int64_t)i * n_pairs + p];
+      const int gbase = lay.groups.base[i * c.n_scales + si];
+      StitchArgs sa;
+      sa.logits = logits;
+      sa.tile_stride = (int64_t)lay.max_slots * T * T;
+      sa.slot_off = (int64_t)lay.pair_slot[p] * T * T;
+      sa.index = index + gbase;
+      sa.ny = gm.ny;
+      sa.nx = gm.nx;
+      sa.T = T;
+      sa.s = s;
+      sa.Hk = gm.Hk;
+      sa.Wk = gm.Wk;
+      sa.mask = o.mask;
+      sa.mask_pitch = o.mask_pitch;
+      sa.logit = emit ? o.logit : nullptr;
+      sa.logit_pitch = o.logit_pitch;
+      sa.fg = c.mask_and_fg ? reinterpret_cast<const uint8_t*>(ws + lay.off_fg[i]) : nullptr;
+      sa.fg_shift = lay.kc - gm.k;
+      sa.Hc = lay.Hc[i];
+      sa.Wc = lay.Wc[i];
+      double cover = 0.0;
+      if (plan->profiling) {
+        // every in-plane pixel of every kept tile is read exactly once
+        for (int jy = 0; jy < gm.ny; ++jy)
+          for (int jx = 0; jx < gm.nx; ++jx)
+            if (idx_host[gbase + jy * gm.nx + jx] >= 0)
+              cover += (double)std::min(T, gm.Hk - jy * s) * std::min(T, gm.Wk - jx * s);
+      }
+      HIP_TRY(prof.begin());
+      HIP_TRY(launch_stitch(sa, sm));
+      HIP_TRY(prof.end(OMNISEG_STAGE_STITCH, -1, 0, 0.0,
+                       4.0 * cover + (double)gm.Hk * gm.Wk * (1.0 + (emit ? 4.0 : 0.0))));
+    }
+  }
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable) {
+  if (!plan) return fail(OMNISEG_ERR_ARG, "plan is NULL");
+  plan->profiling = enable != 0;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_read_profile(omniseg_plan* plan, omniseg_launch_record* recs, int32_t cap, int32_t* n) {
+  if (!plan || !n || (cap > 0 && !recs)) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  const int32_t total = (int32_t)plan->recs.size();
+  for (int32_t i = 0; i < total; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventSynchronize(plan->events[2 * i + 1]));
+    HIP_TRY(hipEventElapsedTime(&ms, plan->events[2 * i], plan->events[2 * i + 1]));
+    plan->recs[i].ms = ms;
+    if (i < cap) recs[i] = plan->recs[i];
+  }
+  *n = total;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_stitch_workspace_bytes(int32_t tile, int32_t stride, int32_t height, int32_t width,
+                                       int64_t* bytes) {
+  if (!bytes) return fail(OMNISEG_ERR_ARG, "bytes is NULL");
+  if (tile < 1 || tile > 4096 || stride < 1 || stride > tile || height < 1 || width < 1)
+    return fail(OMNISEG_ERR_ARG, "bad stitch geometry");
+  const int64_t ny = grid_count(height, tile, stride), nx = grid_count(width, tile, stride);
+  *bytes = align256(ny * nx * 4);
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32_t width,
+                             const float* tile_logits, const int32_t* tile_yx, int32_t n_tiles,
+                             uint8_t* mask, int64_t mask_pitch, float* logit, int64_t logit_pitch,
+                             void* workspace, int64_t ws_bytes, omniseg_stream stream) {
+  int64_t need = 0;
+  int32_t st = omniseg_stitch_workspace_bytes(tile, stride, height, width, &need);
+  if (st) return st;
+  if (n_tiles < 0) return fail(OMNISEG_ERR_ARG, "n_tiles < 0");
+  if (n_tiles > 0 && (!tile_logits || !tile_yx)) return fail(OMNISEG_ERR_ARG, "tile arrays are NULL");
+  if (!mask || mask_pitch < width) return fail(OMNISEG_ERR_ARG, "bad mask buffer");
+  if (logit && logit_pitch < width) return fail(OMNISEG_ERR_ARG, "bad logit pitch");
+  if (!workspace || ws_bytes < need) return fail(OMNISEG_ERR_WORKSPACE, "stitch workspace needs %lld bytes", (long long)need);
+  const int ny = grid_count(height, tile, stride), nx = grid_count(width, tile, stride);
+  if ((int64_t)n_tiles > (int64_t)ny * nx) return fail(OMNISEG_ERR_ARG, "more tiles than grid positions");
+  hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
+  int32_t* grid = static_cast<int32_t*>(workspace);
+  HIP_TRY(launch_grid_from_list(tile_yx, n_tiles, ny, nx, grid, sm));
+  StitchArgs sa;
+  sa.logits = tile_logits;
+  sa.tile_stride = (int64_t)tile * tile;
+  sa.slot_off = 0;
+  sa.index = grid;
+  sa.ny = ny;
+  sa.nx = nx;
+  sa.T = tile;
+  sa.s = stride;
+  sa.Hk = height;
+  sa.Wk = width;
+  sa.mask = mask;
+  sa.mask_pitch = mask_pitch;
+  sa.logit = logit;
+  sa.logit_pitch = logit_pitch;
+  sa.fg = nullptr;
+  sa.fg_shift = 0;
+  sa.Hc = 0;
+  sa.Wc = 0;
+  HIP_TRY(launch_stitch(sa, sm));
+  return OMNISEG_OK;
+}
+
+}  // extern "C"

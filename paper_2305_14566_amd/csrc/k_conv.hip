@@ -1,0 +1,411 @@
+// 3x3 convolutions of the residual U-Net backbone on gfx950.
+//
+// Each conv is an implicit GEMM: M = output pixels of a batch of tiles,
+// N = output channels, K = 9 taps x input channels.  Activations are NHWC
+// with channels padded to a multiple of 32, so one K-chunk of a pixel is a
+// contiguous 16-byte vector.  A workgroup owns a BY x BX pixel block of one
+// tile and BN output channels; per input-channel chunk it stages the
+// (BY+2) x (BX+2) halo patch once in LDS and reuses it for all nine taps
+// (9x reuse of every activation load), together with the chunk's weights
+// for the nine taps.  Four waves each own a (BM/WM) x (BN/WN) sub-tile of
+// 16x16 MFMA fragments with FP32 accumulators.
+//
+//   BF16: v_mfma_f32_16x16x32_bf16, one 16-byte LDS read per operand and
+//         fragment covers K = 32.
+//   FP32: v_mfma_f32_16x16x4_f32.  A 16-byte LDS read gives a lane four
+//         consecutive K values; MFMA step s (s = 0..3) feeds element s, so
+//         lane group j covers K = 4 j + s.  A and B use the same mapping, so
+//         the four steps together sum over all 16 K values of the fragment.
+//
+// Loaders fuse the layer's input transform: PLAIN (NHWC), POOL (2x2 max of
+// the previous level's output, read at twice the resolution) and UPCAT
+// (nearest 2x upsampling of the coarser decoder output for the first cu_p
+// channels, then the encoder skip).  Zero padding applies at the tile
+// border.  Epilogues: bias + ReLU, or bias + residual (the conv's own input)
+// + ReLU.
+#include "internal.h"
+
+namespace omniseg {
+
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (inputs are finite)
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <typename T>
+struct ConvTraits;
+template <>
+struct ConvTraits<float> {
+  static constexpr int KC = 16;   // channels per LDS chunk
+  static constexpr int VEC = 4;   // elements per 16-byte vector
+  static constexpr int ROW = 20;  // LDS row length (80 bytes: conflict-free 16-byte reads)
+};
+template <>
+struct ConvTraits<uint16_t> {
+  static constexpr int KC = 32;
+  static constexpr int VEC = 8;
+  static constexpr int ROW = 40;
+};
+
+struct ConvArgs {
+  const void* x0;
+  const void* x1;
+  void* y;
+  const void* w;
+  const float* bias;
+  int H, W;
+  int cin_p, cu_p, cout_p;
+  const int32_t* count;
+  int chunk_base;
+  int tiles_y, tiles_x, n_nblk;
+};
+
+__device__ __forceinline__ uint4 vmax(uint4 a, uint4 b, float) {
+  uint4 r;
+  r.x = __float_as_uint(fmaxf(__uint_as_float(a.x), __uint_as_float(b.x)));
+  r.y = __float_as_uint(fmaxf(__uint_as_float(a.y), __uint_as_float(b.y)));
+  r.z = __float_as_uint(fmaxf(__uint_as_float(a.z), __uint_as_float(b.z)));
+  r.w = __float_as_uint(fmaxf(__uint_as_float(a.w), __uint_as_float(b.w)));
+  return r;
+}
+__device__ __forceinline__ uint32_t bmax2(uint32_t a, uint32_t b) {
+  float a0 = bf2f(a & 0xffff), a1 = bf2f(a >> 16), b0 = bf2f(b & 0xffff), b1 = bf2f(b >> 16);
+  return (uint32_t)f2bf(fmaxf(a0, b0)) | ((uint32_t)f2bf(fmaxf(a1, b1)) << 16);
+}
+__device__ __forceinline__ uint4 vmax(uint4 a, uint4 b, uint16_t) {
+  return make_uint4(bmax2(a.x, b.x), bmax2(a.y, b.y), bmax2(a.z, b.z), bmax2(a.w, b.w));
+}
+
+template <typename T, int LOADER>
+__device__ __forceinline__ uint4 load_vec(const ConvArgs& a, int b, int y, int x, int c) {
+  if (LOADER == LOAD_PLAIN) {
+    const T* p = (const T*)a.x0 + (((int64_t)b * a.H + y) * a.W + x) * a.cin_p + c;
+    return *reinterpret_cast<const uint4*>(p);
+  } else if (LOADER == LOAD_POOL) {
+    const int H2 = 2 * a.H, W2 = 2 * a.W;
+    const T* p = (const T*)a.x0 + (((int64_t)b * H2 + 2 * y) * W2 + 2 * x) * a.cin_p + c;
+    uint4 v00 = *reinterpret_cast<const uint4*>(p);
+    uint4 v01 = *reinterpret_cast<const uint4*>(p + a.cin_p);
+    uint4 v10 = *reinterpret_cast<const uint4*>(p + (int64_t)W2 * a.cin_p);
+    uint4 v11 = *reinterpret_cast<const uint4*>(p + (int64_t)W2 * a.cin_p + a.cin_p);
+    return vmax(vmax(v00, v01, T()), vmax(v10, v11, T()), T());
+  } else {
+    if (c < a.cu_p) {
+      const int Hh = a.H >> 1, Wh = a.W >> 1;
+      const T* p = (const T*)a.x0 + (((int64_t)b * Hh + (y >> 1)) * Wh + (x >> 1)) * a.cu_p + c;
+      return *reinterpret_cast<const uint4*>(p);
+    } else {
+      const int ce_p = a.cin_p - a.cu_p;
+      const T* p = (const T*)a.x1 + (((int64_t)b * a.H + y) * a.W + x) * ce_p + (c - a.cu_p);
+      return *reinterpret_cast<const uint4*>(p);
+    }
+  }
+}
+
+__device__ __forceinline__ void mma(f32x4& acc, uint4 av, uint4 bv, float) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.x), __uint_as_float(bv.x), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.y), __uint_as_float(bv.y), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.z), __uint_as_float(bv.z), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.w), __uint_as_float(bv.w), acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mma(f32x4& acc, uint4 av, uint4 bv, uint16_t) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ float load_scalar(const float* p) { return *p; }
+__device__ __forceinline__ float load_scalar(const uint16_t* p) { return bf2f(*p); }
+__device__ __forceinline__ void store_scalar(float* p, float v) { *p = v; }
+__device__ __forceinline__ void store_scalar(uint16_t* p, float v) { *p = f2bf(v); }
+
+template <typename T, int BY, int BX, int BN, int WM, int WN, int LOADER, int EPI>
+__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+  using TR = ConvTraits<T>;
+  constexpr int KC = TR::KC, VEC = TR::VEC, ROW = TR::ROW;
+  constexpr int NV = KC / VEC;  // 16-byte vectors per pixel chunk
+  constexpr int BM = BY * BX;
+  constexpr int PX = BX + 2, NPIX = (BY + 2) * PX;
+  constexpr int MW = BM / WM, NW = BN / WN;  // wave sub-tile
+  constexpr int FM = MW / 16, FN = NW / 16;
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(FM >= 1 && FN >= 1 && MW % 16 == 0 && NW % 16 == 0, "fragment shape");
+  __shared__ __attribute__((aligned(16))) T sX[NPIX * ROW];
+  __shared__ __attribute__((aligned(16))) T sW[9 * BN * ROW];
+
+  int rest = blockIdx.x;
+  const int nb = rest % a.n_nblk;
+  rest /= a.n_nblk;
+  const int sxb = rest % a.tiles_x;
+  rest /= a.tiles_x;
+  const int syb = rest % a.tiles_y;
+  const int b = rest / a.tiles_y;
+  if (a.chunk_base + b >= *a.count) return;
+  const int y0 = syb * BY, x0 = sxb * BX, n0 = nb * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int kg = (lane >> 4) * VEC;  // K offset of this lane inside a fragment
+  const int l16 = lane & 15;
+
+  int a_off[FM];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) {
+    const int m = wm * MW + fm * 16 + l16;
+    a_off[fm] = ((m / BX) * PX + (m % BX)) * ROW + kg;
+  }
+  int b_off[FN];
+#pragma unroll
+  for (int fn = 0; fn < FN; ++fn) b_off[fn] = (wn * NW + fn * 16 + l16) * ROW + kg;
+
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nchunks = a.cin_p / KC;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    for (int i = tid; i < NPIX * NV; i += 256) {
+      const int p = i / NV, v = i % NV;
+      const int y = y0 + p / PX - 1, x = x0 + p % PX - 1;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (y >= 0 && y < a.H && x >= 0 && x < a.W) val = load_vec<T, LOADER>(a, b, y, x, ch * KC + v * VEC);
+      *reinterpret_cast<uint4*>(&sX[p * ROW + v * VEC]) = val;
+    }
+    const T* wsrc = (const T*)a.w + (int64_t)ch * 9 * a.cout_p * KC;
+    for (int i = tid; i < 9 * BN * NV; i += 256) {
+      const int v = i % NV, r = i / NV;
+      const int tap = r / BN, n = r % BN;
+      *reinterpret_cast<uint4*>(&sW[r * ROW + v * VEC]) =
+          *reinterpret_cast<const uint4*>(wsrc + ((int64_t)tap * a.cout_p + n0 + n) * KC + v * VEC);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int sh = ((tap / 3) * PX + (tap % 3)) * ROW;
+#pragma unroll
+      for (int kk = 0; kk < KC / (4 * VEC); ++kk) {
+        uint4 av[FM], bv[FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) av[fm] = *reinterpret_cast<const uint4*>(&sX[a_off[fm] + sh + kk * 4 * VEC]);
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+          bv[fn] = *reinterpret_cast<const uint4*>(&sW[tap * BN * ROW + b_off[fn] + kk * 4 * VEC]);
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < FN; ++fn) mma(acc[fm][fn], av[fm], bv[fn], T());
+      }
+    }
+    __syncthreads();
+  }
+
+  T* out = (T*)a.y;
+  const T* res = (const T*)a.x0;
+#pragma unroll
+  for (int fn = 0; fn < FN; ++fn) {
+    const int n = n0 + wn * NW + fn * 16 + l16;
+    const float bias = a.bias[n];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = wm * MW + fm * 16 + (lane >> 4) * 4 + r;
+        const int y = y0 + m / BX, x = x0 + m % BX;
+        const int64_t o = (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + n;
+        float v = acc[fm][fn][r] + bias;
+        if (EPI == EPI_RES_RELU) v += load_scalar(res + o);
+        store_scalar(out + o, fmaxf(v, 0.f));
+      }
+    }
+  }
+}
+
+template <typename T, int BY, int BX, int BN, int LOADER, int EPI>
+static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
+                                int chunk_base, const void* x0, const void* x1, void* y,
+                                hipStream_t st) {
+  constexpr int WN = (BN >= 64) ? 2 : 1;
+  constexpr int WM = 4 / WN;
+  ConvArgs a;
+  a.x0 = x0;
+  a.x1 = x1;
+  a.y = y;
+  a.w = L.w;
+  a.bias = L.b;
+  a.H = H;
+  a.W = W;
+  a.cin_p = L.cin_p;
+  a.cu_p = L.cu_p;
+  a.cout_p = L.cout_p;
+  a.count = count;
+  a.chunk_base = chunk_base;
+  a.tiles_y = H / BY;
+  a.tiles_x = W / BX;
+  a.n_nblk = L.cout_p / BN;
+  const int64_t blocks = (int64_t)batch * a.tiles_y * a.tiles_x * a.n_nblk;
+  hipLaunchKernelGGL((k_conv3x3<T, BY, BX, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks),
+                     dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int BY, int BX, int LOADER, int EPI>
+static hipError_t launch_conv_bn(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
+                                 int chunk_base, const void* x0, const void* x1, void* y,
+                                 hipStream_t st) {
+  if (L.cout_p % 64 == 0)
+    return launch_conv_t<T, BY, BX, 64, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+  return launch_conv_t<T, BY, BX, 32, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+}
+
+template <typename T, int LOADER, int EPI>
+static hipError_t launch_conv_sp(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
+                                 int chunk_base, const void* x0, const void* x1, void* y,
+                                 hipStream_t st) {
+  if (W % 16 == 0 && H % 8 == 0)
+    return launch_conv_bn<T, 8, 16, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+  return launch_conv_bn<T, 8, 8, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+}
+
+template <typename T>
+static hipError_t launch_conv_mode(int loader, int epi, const ConvLayer& L, int H, int W, int batch,
+                                   const int32_t* count, int chunk_base, const void* x0,
+                                   const void* x1, void* y, hipStream_t st) {
+  if (loader == LOAD_PLAIN && epi == EPI_RES_RELU)
+    return launch_conv_sp<T, LOAD_PLAIN, EPI_RES_RELU>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+  if (loader == LOAD_POOL && epi == EPI_RELU)
+    return launch_conv_sp<T, LOAD_POOL, EPI_RELU>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+  if (loader == LOAD_UPCAT && epi == EPI_RELU)
+    return launch_conv_sp<T, LOAD_UPCAT, EPI_RELU>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+  if (loader == LOAD_PLAIN && epi == EPI_RELU)
+    return launch_conv_sp<T, LOAD_PLAIN, EPI_RELU>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L, int H, int W,
+                          int batch, const int32_t* count, int chunk_base, const void* x0,
+                          const void* x1, void* y, hipStream_t st) {
+  if (precision == OMNISEG_BF16)
+    return launch_conv_mode<uint16_t>(loader, epi, L, H, W, batch, count, chunk_base, x0, x1, y, st);
+  return launch_conv_mode<float>(loader, epi, L, H, W, batch, count, chunk_base, x0, x1, y, st);
+}
+
+// ---------------------------------------------------------------------------
+// First conv, 3 -> C_0, from the slide (40x) or the box-sum pyramid.  One
+// workgroup per 16x16 output block of one tile; the 18x18x3 input patch is
+// normalised to [0, 1] (value / (255 * 4^k)) in FP32 in LDS, with the pad
+// colour outside the slide and zeros outside the tile.  FP32 arithmetic for
+// every precision; the output is stored in the backbone's storage type.
+// ---------------------------------------------------------------------------
+
+constexpr int kFirstMaxC0 = 128;
+
+__device__ __forceinline__ void store_vec(float* p, const float* v) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store_vec(uint16_t* p, const float* v) {
+  uint4 u;
+  u.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+  u.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+  u.z = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
+  u.w = (uint32_t)f2bf(v[6]) | ((uint32_t)f2bf(v[7]) << 16);
+  *reinterpret_cast<uint4*>(p) = u;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
+  constexpr int VEC = 16 / sizeof(T);
+  __shared__ float sIn[3][18][19];
+  __shared__ float sw[kFirstMaxC0 * 28];
+  const int nb = a.T / 16;
+  int rest = blockIdx.x;
+  const int sx = rest % nb;
+  rest /= nb;
+  const int sy = rest % nb;
+  const int b = rest / nb;
+  if (a.chunk_base + b >= *a.count) return;
+  const int4 t = reinterpret_cast<const int4*>(a.list)[a.chunk_base + b];
+  const SlideDev& sd = a.slides[t.x];
+  const int k = a.scale_k[t.y];
+  const int oy = t.z * a.s, ox = t.w * a.s;  // tile origin at scale k
+  const float scale = 1.0f / (255.0f * (float)(1 << (2 * k)));
+  for (int i = threadIdx.x; i < a.c0 * 27; i += 256) sw[(i / 27) * 28 + i % 27] = a.w[i];
+  for (int i = threadIdx.x; i < a.c0; i += 256) sw[i * 28 + 27] = a.b[i];
+  for (int i = threadIdx.x; i < 18 * 18; i += 256) {
+    const int py = i / 18, px = i % 18;
+    const int ty = sy * 16 + py - 1, tx = sx * 16 + px - 1;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+    if (ty >= 0 && ty < a.T && tx >= 0 && tx < a.T) {
+      const int Y = oy + ty, X = ox + tx;
+      if (k == 0) {
+        int r, g, bb;
+        if (Y < sd.H && X < sd.W) {
+          const uint8_t* p = sd.rgb + (int64_t)Y * sd.pitch + 3 * X;
+          r = p[0];
+          g = p[1];
+          bb = p[2];
+        } else {
+          r = sd.pad[0];
+          g = sd.pad[1];
+          bb = sd.pad[2];
+        }
+        v0 = r * scale;
+        v1 = g * scale;
+        v2 = bb * scale;
+      } else {
+        const ushort4 s4 = reinterpret_cast<const ushort4*>(sd.pyr[t.y])[(int64_t)Y * sd.pyr_ex[t.y] + X];
+        v0 = s4.x * scale;
+        v1 = s4.y * scale;
+        v2 = s4.z * scale;
+      }
+    }
+    sIn[0][py][px] = v0;
+    sIn[1][py][px] = v1;
+    sIn[2][py][px] = v2;
+  }
+  __syncthreads();
+  const int py = threadIdx.x / 16, px = threadIdx.x % 16;
+  float in[27];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) in[c * 9 + dy * 3 + dx] = sIn[c][py + dy][px + dx];
+  const int y = sy * 16 + py, x = sx * 16 + px;
+  T* out = (T*)a.y + (((int64_t)b * a.T + y) * a.T + x) * a.c0_p;
+  for (int o0 = 0; o0 < a.c0_p; o0 += VEC) {
+    float v[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+      const int o = o0 + j;
+      float acc = 0.f;
+      if (o < a.c0) {
+        const float* wr = &sw[o * 28];
+        acc = wr[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) acc = fmaf(wr[i], in[i], acc);
+        acc = fmaxf(acc, 0.f);
+      }
+      v[j] = acc;
+    }
+    store_vec(out + o0, v);
+  }
+}
+
+hipError_t launch_first_conv(int precision, const FirstConvArgs& a, hipStream_t st) {
+  if (a.c0 > kFirstMaxC0 || a.T % 16) return hipErrorInvalidValue;
+  const int nb = a.T / 16;
+  const int64_t blocks = (int64_t)a.batch * nb * nb;
+  if (precision == OMNISEG_BF16)
+    hipLaunchKernelGGL(k_first_conv<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_first_conv<float>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace omniseg

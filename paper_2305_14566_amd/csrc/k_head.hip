@@ -1,0 +1,187 @@
+// Global average pool of the bottleneck, the controller and the dynamic head.
+//
+// The controller maps [g; onehot_C(class); onehot_S(scale)] to the P
+// parameters of a per-(tile, class) head, theta = W_c v + b_c, where g is the
+// bottleneck's pixel mean.  With one-hot inputs this is W_c[:, :G] g plus two
+// columns of W_c plus b_c.  The head is three 1x1 convs on the 8-channel
+// feature F: h1 = ReLU(W1 F + b1), h2 = ReLU(W2 h1 + b2), z = W3 h2 + b3, with
+// theta split as W1 (8x8), W2 (8x8), W3 (o x 8), b1, b2, b3.  The class logit
+// is z_0 for one output and z_1 - z_0 for two.  F = ReLU(W_p D_0 + b_p) when
+// the decoder's last level has C_0 != 8 channels, else D_0 itself.  All head
+// arithmetic is FP32; the per-tile parameters live in LDS.
+#include "internal.h"
+
+namespace omniseg {
+
+__device__ __forceinline__ float ld1(const float* p) { return *p; }
+__device__ __forceinline__ float ld1(const uint16_t* p) { return __uint_as_float((uint32_t)(*p) << 16); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gap(const T* __restrict__ e, int hw, int c_p, int c,
+                                             const int32_t* count, int chunk_base, float* g) {
+  const int b = blockIdx.x;
+  if (chunk_base + b >= *count) return;
+  const T* base = e + (int64_t)b * hw * c_p;
+  for (int ch = threadIdx.x; ch < c; ch += blockDim.x) {
+    float s = 0.f;
+    for (int p = 0; p < hw; ++p) s += ld1(base + (int64_t)p * c_p + ch);
+    g[(int64_t)b * c_p + ch] = s / (float)hw;
+  }
+}
+
+hipError_t launch_gap(int precision, const void* e, int batch, int hw, int c_p, int c,
+                      const int32_t* count, int chunk_base, float* g, hipStream_t st) {
+  if (precision == OMNISEG_BF16)
+    hipLaunchKernelGGL(k_gap<uint16_t>, dim3(batch), dim3(256), 0, st, (const uint16_t*)e, hw, c_p, c,
+                       count, chunk_base, g);
+  else
+    hipLaunchKernelGGL(k_gap<float>, dim3(batch), dim3(256), 0, st, (const float*)e, hw, c_p, c, count,
+                       chunk_base, g);
+  return hipGetLastError();
+}
+
+// theta[b][slot][p]; one workgroup per (tile, slot).  W_c rows are row_len =
+// G + n_classes + n_scales long.
+__global__ __launch_bounds__(256) void k_controller(const float* __restrict__ g, int g_stride, int G,
+                                                     const float* __restrict__ wc,
+                                                     const float* __restrict__ bc, int P, int row_len,
+                                                     int n_classes, SlotTable slots, int max_slots,
+                                                     const int32_t* list, const int32_t* count,
+                                                     int chunk_base, float* theta) {
+  const int b = blockIdx.x / max_slots, j = blockIdx.x % max_slots;
+  if (chunk_base + b >= *count) return;
+  const int si = list[4 * (chunk_base + b) + 1];
+  if (j >= slots.n_slots[si]) return;
+  const int cls = slots.cls[si][j];
+  __shared__ float sg[4096];
+  const float* gb = g + (int64_t)b * g_stride;
+  for (int i = threadIdx.x; i < G; i += blockDim.x) sg[i] = gb[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // one wave per output row p: coalesced reads of W_c's row, wave reduction
+  for (int p = wave; p < P; p += 4) {
+    const float* w = wc + (int64_t)p * row_len;
+    float s = 0.f;
+    for (int i = lane; i < G; i += 64) s = fmaf(w[i], sg[i], s);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0)
+      theta[((int64_t)b * max_slots + j) * P + p] = s + w[G + cls] + w[G + n_classes + si] + bc[p];
+  }
+}
+
+hipError_t launch_controller(const float* g, int batch, int G, const float* wc, const float* bc,
+                             int P, int n_classes, int n_scales, const SlotTable& slots,
+                             int max_slots, const int32_t* list, const int32_t* count,
+                             int chunk_base, float* theta, hipStream_t st) {
+  if (G > 4096) return hipErrorInvalidValue;
+  const int g_stride = pad_ch(G);
+  hipLaunchKernelGGL(k_controller, dim3(batch * max_slots), dim3(256), 0, st, g, g_stride, G, wc,
+                     bc, P, G + n_classes + n_scales, n_classes, slots, max_slots, list, count,
+                     chunk_base, theta);
+  return hipGetLastError();
+}
+
+// One thread per pixel of one tile; all the tile's slots in one pass.
+template <typename T, int O>
+__global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, int c0, int c0_p,
+                                              const float* __restrict__ wp,
+                                              const float* __restrict__ bp,
+                                              const float* __restrict__ theta, int P,
+                                              SlotTable slots, int max_slots,
+                                              const int32_t* list, const int32_t* count,
+                                              int chunk_base, float* __restrict__ out) {
+  constexpr int kMaxC0 = 256;
+  __shared__ float sth[OMNISEG_MAX_CLASSES * (144 + 9 * 2)];
+  __shared__ float swp[8 * kMaxC0 + 8];
+  const int per_tile = T2 / 256;
+  const int b = blockIdx.x / per_tile;
+  const int pix = (blockIdx.x % per_tile) * 256 + threadIdx.x;
+  if (chunk_base + b >= *count) return;
+  const int si = list[4 * (chunk_base + b) + 1];
+  const int ns = slots.n_slots[si];
+  for (int i = threadIdx.x; i < ns * P; i += 256) sth[i] = theta[(int64_t)b * max_slots * P + i];
+  const bool pre = (c0 != 8);
+  if (pre) {
+    for (int i = threadIdx.x; i < 8 * c0; i += 256) swp[i] = wp[i];
+    if (threadIdx.x < 8) swp[8 * c0 + threadIdx.x] = bp[threadIdx.x];
+  }
+  __syncthreads();
+  const T* px = d0 + ((int64_t)b * T2 + pix) * c0_p;
+  float F[8];
+  if (pre) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) F[o] = swp[8 * c0 + o];
+    for (int c = 0; c < c0; ++c) {
+      const float v = ld1(px + c);
+#pragma unroll
+      for (int o = 0; o < 8; ++o) F[o] = fmaf(swp[o * c0 + c], v, F[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) F[o] = fmaxf(F[o], 0.f);
+  } else {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) F[o] = ld1(px + o);
+  }
+  for (int j = 0; j < ns; ++j) {
+    const float* th = &sth[j * P];
+    const float* W1 = th;
+    const float* W2 = th + 64;
+    const float* W3 = th + 128;
+    const float* b1 = th + 128 + 8 * O;
+    const float* b2 = b1 + 8;
+    const float* b3 = b2 + 8;
+    float h1[8], h2[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      float s = b1[o];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s = fmaf(W1[o * 8 + i], F[i], s);
+      h1[o] = fmaxf(s, 0.f);
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      float s = b2[o];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s = fmaf(W2[o * 8 + i], h1[i], s);
+      h2[o] = fmaxf(s, 0.f);
+    }
+    float z[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+      float s = b3[o];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s = fmaf(W3[o * 8 + i], h2[i], s);
+      z[o] = s;
+    }
+    const float l = (O == 1) ? z[0] : z[O - 1] - z[0];
+    out[((int64_t)(chunk_base + b) * max_slots + j) * T2 + pix] = l;
+  }
+}
+
+hipError_t launch_head(int precision, const void* d0, int batch, int T, int c0, int c0_p,
+                       const float* wp, const float* bp, const float* theta, int P, int o,
+                       const SlotTable& slots, int max_slots, const int32_t* list,
+                       const int32_t* count, int chunk_base, float* tile_logits, hipStream_t st) {
+  const int T2 = T * T;
+  if (T2 % 256 || c0 > 256 || max_slots > OMNISEG_MAX_CLASSES) return hipErrorInvalidValue;
+  dim3 grid(batch * (T2 / 256));
+  if (precision == OMNISEG_BF16) {
+    if (o == 1)
+      hipLaunchKernelGGL((k_head<uint16_t, 1>), grid, dim3(256), 0, st, (const uint16_t*)d0, T2, c0,
+                         c0_p, wp, bp, theta, P, slots, max_slots, list, count, chunk_base, tile_logits);
+    else
+      hipLaunchKernelGGL((k_head<uint16_t, 2>), grid, dim3(256), 0, st, (const uint16_t*)d0, T2, c0,
+                         c0_p, wp, bp, theta, P, slots, max_slots, list, count, chunk_base, tile_logits);
+  } else {
+    if (o == 1)
+      hipLaunchKernelGGL((k_head<float, 1>), grid, dim3(256), 0, st, (const float*)d0, T2, c0, c0_p,
+                         wp, bp, theta, P, slots, max_slots, list, count, chunk_base, tile_logits);
+    else
+      hipLaunchKernelGGL((k_head<float, 2>), grid, dim3(256), 0, st, (const float*)d0, T2, c0, c0_p,
+                         wp, bp, theta, P, slots, max_slots, list, count, chunk_base, tile_logits);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace omniseg

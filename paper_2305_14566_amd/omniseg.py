@@ -1,0 +1,287 @@
+"""ctypes binding of libomniseg.so (argument marshalling only).
+
+Every step of the segmentation runs in the library's HIP kernels; torch is
+used here only to allocate device memory and to supply the current HIP
+stream.  The functions mirror the C ABI in include/omniseg.h.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libomniseg.so")
+
+FP32, BF16 = 0, 1
+FLAG_EMIT_LOGITS = 1
+(REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
+ REGION_TILE_INDEX, REGION_TILE_LOGITS) = range(7)
+ABI_VERSION = 1
+
+_lib = None
+
+
+class OmnisegError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"omniseg status {status}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("base_channels", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
+        ("head_out", ctypes.c_int32),
+        ("n_classes", ctypes.c_int32),
+        ("n_scales", ctypes.c_int32),
+        ("scale_log2", ctypes.c_int32 * 4),
+        ("tile", ctypes.c_int32),
+        ("stride", ctypes.c_int32),
+        ("fg_filter", ctypes.c_int32),
+        ("fg_threshold", ctypes.c_int32),
+        ("mask_and_fg", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("batch_tiles", ctypes.c_int32),
+    ]
+
+
+class Slide(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_void_p), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("row_pitch", ctypes.c_int64)]
+
+
+class Pair(ctypes.Structure):
+    _fields_ = [("cls", ctypes.c_int32), ("scale", ctypes.c_int32)]
+
+
+class LaunchRecord(ctypes.Structure):
+    _fields_ = [("stage", ctypes.c_int32), ("level", ctypes.c_int32), ("tiles", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+
+STAGE_NAMES = ("prep", "first_conv", "enc_a", "enc_b", "dec_a", "dec_b", "gap_ctrl", "head", "stitch")
+
+
+class Output(ctypes.Structure):
+    _fields_ = [("mask", ctypes.c_void_p), ("logit", ctypes.c_void_p),
+                ("mask_pitch", ctypes.c_int64), ("logit_pitch", ctypes.c_int64)]
+
+
+def _declare(lib):
+    P = ctypes.POINTER
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    sig = {
+        "omniseg_status_string": (ctypes.c_char_p, [i32]),
+        "omniseg_last_error": (ctypes.c_char_p, []),
+        "omniseg_plan_create": (i32, [P(Config), P(vp)]),
+        "omniseg_plan_destroy": (i32, [vp]),
+        "omniseg_weight_count": (i32, [vp, P(i64)]),
+        "omniseg_packed_weight_bytes": (i32, [vp, P(i64)]),
+        "omniseg_pack_weights": (i32, [vp, vp, vp, vp]),
+        "omniseg_workspace_bytes": (i32, [vp, P(Slide), i32, P(Pair), i32, P(i64)]),
+        "omniseg_segment_slide": (i32, [vp, vp, P(Slide), i32, P(Pair), i32, P(Output), vp, i64, vp]),
+        "omniseg_workspace_region": (i32, [vp, P(Slide), i32, P(Pair), i32, i32, i32, P(i64), P(i64)]),
+        "omniseg_stitch_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
+        "omniseg_stitch_tiles": (i32, [i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, i64, vp, i64, vp]),
+        "omniseg_set_profiling": (i32, [vp, i32]),
+        "omniseg_read_profile": (i32, [vp, P(LaunchRecord), i32, P(i32)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def lib():
+    """Load libomniseg.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2305_14566_amd.build`")
+        l = ctypes.CDLL(LIB_PATH)
+        _declare(l)
+        _lib = l
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        l = lib()
+        raise OmnisegError(status, f"{l.omniseg_status_string(status).decode()}: "
+                                   f"{l.omniseg_last_error().decode()}")
+
+
+def _stream(stream=None):
+    if stream is None:
+        if not torch.cuda.is_available():
+            return None
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def level_size(n, k):
+    return -(-n // (1 << k))
+
+
+class Plan:
+    """A validated configuration (host side only)."""
+
+    def __init__(self, base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
+                 stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False,
+                 precision=FP32, emit_logits=False, batch_tiles=0):
+        c = Config()
+        c.abi_version = ABI_VERSION
+        c.base_channels = base
+        c.levels = levels
+        c.head_out = head_out
+        c.n_classes = n_classes
+        c.n_scales = len(scales)
+        for i, k in enumerate(scales):
+            c.scale_log2[i] = k
+        c.tile = tile
+        c.stride = stride
+        c.fg_filter = int(fg_filter)
+        c.fg_threshold = fg_threshold
+        c.mask_and_fg = int(mask_and_fg)
+        c.precision = precision
+        c.flags = FLAG_EMIT_LOGITS if emit_logits else 0
+        c.batch_tiles = batch_tiles
+        self.cfg = c
+        self.scales = tuple(scales)
+        self.emit_logits = emit_logits
+        self._h = ctypes.c_void_p()
+        _check(lib().omniseg_plan_create(ctypes.byref(c), ctypes.byref(self._h)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.omniseg_plan_destroy(h)
+            self._h = None
+
+    @property
+    def weight_count(self):
+        n = ctypes.c_int64()
+        _check(lib().omniseg_weight_count(self._h, ctypes.byref(n)))
+        return n.value
+
+    @property
+    def packed_bytes(self):
+        n = ctypes.c_int64()
+        _check(lib().omniseg_packed_weight_bytes(self._h, ctypes.byref(n)))
+        return n.value
+
+    def set_profiling(self, enable):
+        _check(lib().omniseg_set_profiling(self._h, int(bool(enable))))
+
+    def read_profile(self):
+        """Per-launch records of the last profiled segment call (list of dicts)."""
+        n = ctypes.c_int32()
+        _check(lib().omniseg_read_profile(self._h, None, 0, ctypes.byref(n)))
+        recs = (LaunchRecord * max(1, n.value))()
+        _check(lib().omniseg_read_profile(self._h, recs, n.value, ctypes.byref(n)))
+        return [dict(stage=STAGE_NAMES[r.stage], level=r.level, tiles=r.tiles, flops=r.flops,
+                     bytes=r.bytes, ms=r.ms) for r in recs[:n.value]]
+
+    def pack(self, canonical, stream=None):
+        """Canonical FP32 weights (device tensor) -> packed device buffer (uint8)."""
+        if canonical.dtype != torch.float32 or not canonical.is_cuda or not canonical.is_contiguous():
+            raise ValueError("canonical weights must be a contiguous float32 device tensor")
+        if canonical.numel() != self.weight_count:
+            raise ValueError(f"expected {self.weight_count} weights, got {canonical.numel()}")
+        packed = torch.empty(self.packed_bytes, dtype=torch.uint8, device=canonical.device)
+        _check(lib().omniseg_pack_weights(self._h, _ptr(canonical), _ptr(packed), _stream(stream)))
+        return packed
+
+    def _arrays(self, slides, pairs):
+        sl = (Slide * len(slides))()
+        for i, s in enumerate(slides):
+            if s.dtype != torch.uint8 or s.dim() != 3 or s.shape[2] != 3:
+                raise ValueError("slides must be uint8 [H, W, 3] tensors")
+            if s.stride(2) != 1 or s.stride(1) != 3:
+                raise ValueError("slide rows must be interleaved RGB")
+            sl[i].rgb = s.data_ptr()
+            sl[i].height = s.shape[0]
+            sl[i].width = s.shape[1]
+            sl[i].row_pitch = s.stride(0)
+        pr = (Pair * len(pairs))()
+        for i, (c, k) in enumerate(pairs):
+            pr[i].cls = c
+            pr[i].scale = k
+        return sl, pr
+
+    def workspace_bytes(self, slides, pairs):
+        sl, pr = self._arrays(slides, pairs)
+        n = ctypes.c_int64()
+        _check(lib().omniseg_workspace_bytes(self._h, sl, len(slides), pr, len(pairs), ctypes.byref(n)))
+        return n.value
+
+    def region(self, slides, pairs, region, index=0):
+        sl, pr = self._arrays(slides, pairs)
+        off, nb = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().omniseg_workspace_region(self._h, sl, len(slides), pr, len(pairs), region, index,
+                                              ctypes.byref(off), ctypes.byref(nb)))
+        return off.value, nb.value
+
+    def alloc_outputs(self, slides, pairs):
+        masks, logits = [], []
+        for s in slides:
+            mrow, lrow = [], []
+            for (c, si) in pairs:
+                k = self.scales[si]
+                hk, wk = level_size(s.shape[0], k), level_size(s.shape[1], k)
+                mrow.append(torch.empty((hk, wk), dtype=torch.uint8, device=s.device))
+                lrow.append(torch.empty((hk, wk), dtype=torch.float32, device=s.device)
+                            if self.emit_logits else None)
+            masks.append(mrow)
+            logits.append(lrow)
+        return masks, logits
+
+    def segment(self, slides, pairs, packed, workspace=None, outputs=None, stream=None):
+        """Run the whole path; returns (masks, logits, workspace).
+
+        masks[i][p] is uint8 [H_k, W_k]; logits[i][p] float32 or None.
+        """
+        sl, pr = self._arrays(slides, pairs)
+        need = self.workspace_bytes(slides, pairs)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=slides[0].device)
+        masks, logits = outputs if outputs is not None else self.alloc_outputs(slides, pairs)
+        outs = (Output * (len(slides) * len(pairs)))()
+        for i in range(len(slides)):
+            for p in range(len(pairs)):
+                o = outs[i * len(pairs) + p]
+                m = masks[i][p]
+                o.mask = m.data_ptr()
+                o.mask_pitch = m.stride(0)
+                lg = logits[i][p]
+                o.logit = lg.data_ptr() if lg is not None else 0
+                o.logit_pitch = lg.stride(0) if lg is not None else 0
+        _check(lib().omniseg_segment_slide(self._h, _ptr(packed), sl, len(slides), pr, len(pairs), outs,
+                                           _ptr(workspace), workspace.numel(), _stream(stream)))
+        return masks, logits, workspace
+
+
+def stitch_tiles(tile, stride, height, width, tile_logits, tile_yx, emit_logits=True, stream=None):
+    """Stand-alone stitch of one plane; returns (mask uint8, logit float32 or None)."""
+    l = lib()
+    n = ctypes.c_int64()
+    _check(l.omniseg_stitch_workspace_bytes(tile, stride, height, width, ctypes.byref(n)))
+    dev = tile_logits.device
+    ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+    mask = torch.empty((height, width), dtype=torch.uint8, device=dev)
+    logit = torch.empty((height, width), dtype=torch.float32, device=dev) if emit_logits else None
+    n_tiles = tile_yx.shape[0]
+    _check(l.omniseg_stitch_tiles(tile, stride, height, width, _ptr(tile_logits), _ptr(tile_yx), n_tiles,
+                                  _ptr(mask), mask.stride(0), _ptr(logit),
+                                  logit.stride(0) if logit is not None else 0, _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return mask, logit

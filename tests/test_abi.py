@@ -1,0 +1,226 @@
+"""C-ABI library tests that need no GPU: it loads, exports every declared
+symbol, shares torch's HIP runtime, and rejects bad arguments before any
+HIP call (so no compute happens here)."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2305_14566_amd import omniseg as om
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "omniseg.h")
+FAKE = 1 << 20  # never dereferenced: every call below fails validation first
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    decl = r"^(?:const\s+)?\w+\s*\*?\s*(omniseg_\w+)\s*\("
+    return sorted(set(re.findall(decl, src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 12
+    lib = om.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", om.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (omniseg_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_library_uses_torchs_hip_runtime():
+    """The library's HIP dependency resolves to the runtime torch loads."""
+    import torch
+    tlib = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+    need = subprocess.run(["readelf", "-d", om.LIB_PATH], capture_output=True, text=True).stdout
+    son = subprocess.run(["readelf", "-d", tlib], capture_output=True, text=True).stdout
+    needed = re.findall(r"NEEDED.*\[(libamdhip64[^\]]*)\]", need)
+    soname = re.findall(r"SONAME.*\[([^\]]*)\]", son)
+    assert needed and soname and needed[0] == soname[0]
+
+
+def test_status_strings():
+    lib = om.lib()
+    assert lib.omniseg_status_string(0) == b"ok"
+    assert b"workspace" in lib.omniseg_status_string(3)
+
+
+def _cfg(**kw):
+    c = om.Config()
+    c.abi_version = om.ABI_VERSION
+    c.base_channels = 8
+    c.levels = 3
+    c.head_out = 1
+    c.n_classes = 1
+    c.n_scales = 1
+    c.tile = 128
+    c.stride = 64
+    c.fg_filter = 0
+    c.fg_threshold = 220
+    c.mask_and_fg = 0
+    c.precision = om.FP32
+    c.flags = 0
+    c.batch_tiles = 0
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("abi_version", 99, 1), ("base_channels", 0, 1), ("base_channels", 129, 1),
+    ("levels", 0, 1), ("head_out", 3, 1), ("n_classes", 0, 1), ("n_classes", 17, 1),
+    ("n_scales", 5, 1), ("tile", 100, 1), ("tile", 1024, 1), ("stride", 0, 1), ("stride", 129, 1),
+    ("levels", 6, 2), ("fg_threshold", 0, 1), ("precision", 7, 2), ("flags", 8, 1),
+    ("batch_tiles", -1, 1), ("fg_filter", 2, 1),
+])
+def test_plan_create_rejects(field, value, status):
+    lib = om.lib()
+    h = ctypes.c_void_p()
+    c = _cfg(**{field: value})
+    assert lib.omniseg_plan_create(ctypes.byref(c), ctypes.byref(h)) == status
+    assert lib.omniseg_last_error() != b""
+    assert not h.value
+
+
+@pytest.mark.parametrize("base,L,C,scales,o", [(8, 3, 1, (0,), 1), (64, 5, 6, (0, 1, 2, 3), 2),
+                                                (4, 3, 6, (0, 1), 2), (16, 4, 3, (0, 2, 3), 2)])
+def test_weight_count_matches_canonical_layout(base, L, C, scales, o):
+    p = om.Plan(base=base, levels=L, head_out=o, n_classes=C, scales=scales, tile=256, stride=128)
+    n = sum(int(np.prod(sh)) for _, sh, _ in synth.weight_layout(base, L, C, len(scales), o))
+    assert p.weight_count == n
+    assert p.packed_bytes > 0 and p.packed_bytes % 256 == 0
+
+
+def test_config2_parameter_count():
+    """Base 64, 5 levels, 6 classes, 4 scales, 8-8-8-2 head."""
+    p = om.Plan(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 1, 2, 3), tile=256, stride=128)
+    ctrl = 162 * (1024 + 10) + 162
+    assert p.weight_count - ctrl == 31_378_880 + 8 * 64 + 8
+
+
+def _slides(shapes):
+    arr = (om.Slide * len(shapes))()
+    for i, (h, w) in enumerate(shapes):
+        arr[i].rgb = FAKE
+        arr[i].height = h
+        arr[i].width = w
+        arr[i].row_pitch = 3 * w
+    return arr
+
+
+def _pairs(pairs):
+    arr = (om.Pair * len(pairs))()
+    for i, (c, s) in enumerate(pairs):
+        arr[i].cls = c
+        arr[i].scale = s
+    return arr
+
+
+def test_workspace_layout_and_regions():
+    p = om.Plan(base=8, levels=3, head_out=2, n_classes=2, scales=(0, 1), tile=64, stride=32,
+                fg_filter=True)
+    lib = om.lib()
+    sl = _slides([(300, 517), (129, 64)])
+    pr = _pairs([(0, 0), (1, 1), (1, 0)])
+    n = ctypes.c_int64()
+    assert lib.omniseg_workspace_bytes(p._h, sl, 2, pr, 3, ctypes.byref(n)) == 0
+    total = n.value
+    assert total > 0 and total % 256 == 0
+    seen = []
+    for region, count in [(0, 2), (1, 4), (2, 2), (3, 1), (4, 1), (5, 4), (6, 1)]:
+        for idx in range(count):
+            off, nb = ctypes.c_int64(), ctypes.c_int64()
+            assert lib.omniseg_workspace_region(p._h, sl, 2, pr, 3, region, idx, ctypes.byref(off),
+                                                ctypes.byref(nb)) == 0
+            if nb.value > 0 and off.value >= 0:
+                assert off.value + nb.value <= total
+                seen.append((off.value, nb.value))
+    # tile index regions follow the grid sizes: 300x517 at 40x -> 9 x 16 tiles
+    off, nb = ctypes.c_int64(), ctypes.c_int64()
+    lib.omniseg_workspace_region(p._h, sl, 2, pr, 3, 5, 0, ctypes.byref(off), ctypes.byref(nb))
+    assert nb.value == 9 * 16 * 4
+    assert lib.omniseg_workspace_region(p._h, sl, 2, pr, 3, 9, 0, ctypes.byref(off), ctypes.byref(nb)) == 1
+    assert lib.omniseg_workspace_region(p._h, sl, 2, pr, 3, 1, 4, ctypes.byref(off), ctypes.byref(nb)) == 1
+
+
+def _segment(p, sl, ns, pr, npairs, outs, ws=FAKE, wsb=1 << 40, packed=FAKE):
+    return om.lib().omniseg_segment_slide(p._h, packed, sl, ns, pr, npairs, outs, ws, wsb, None)
+
+
+def _outs(n):
+    o = (om.Output * n)()
+    for i in range(n):
+        o[i].mask = FAKE
+        o[i].mask_pitch = 1 << 20
+    return o
+
+
+@pytest.mark.parametrize("case", ["bad_class", "bad_scale", "dup_pair", "small_slide", "pitch",
+                                  "null_rgb", "null_mask", "mask_pitch", "ws_small", "misaligned",
+                                  "too_many_slides", "null_logit"])
+def test_segment_rejects_before_any_hip_call(case):
+    p = om.Plan(base=8, levels=3, head_out=1, n_classes=2, scales=(0, 1), tile=64, stride=32,
+                emit_logits=(case == "null_logit"))
+    sl = _slides([(100, 80)])
+    pr = _pairs([(0, 0), (1, 1)])
+    outs = _outs(2)
+    if case == "null_logit":
+        for i in range(2):
+            outs[i].logit = 0
+            outs[i].logit_pitch = 1 << 20
+        assert _segment(p, sl, 1, pr, 2, outs) == 1
+        return
+    if case == "bad_class":
+        pr = _pairs([(2, 0)])
+        assert _segment(p, sl, 1, pr, 1, outs) == 1
+    elif case == "bad_scale":
+        pr = _pairs([(0, 2)])
+        assert _segment(p, sl, 1, pr, 1, outs) == 1
+    elif case == "dup_pair":
+        pr = _pairs([(0, 0), (0, 0)])
+        assert _segment(p, sl, 1, pr, 2, outs) == 1
+    elif case == "small_slide":
+        assert _segment(p, _slides([(1, 80)]), 1, pr, 2, outs) == 1
+    elif case == "pitch":
+        s = _slides([(100, 80)])
+        s[0].row_pitch = 100
+        assert _segment(p, s, 1, pr, 2, outs) == 1
+    elif case == "null_rgb":
+        s = _slides([(100, 80)])
+        s[0].rgb = 0
+        assert _segment(p, s, 1, pr, 2, outs) == 1
+    elif case == "null_mask":
+        outs[1].mask = 0
+        assert _segment(p, sl, 1, pr, 2, outs) == 1
+    elif case == "mask_pitch":
+        outs[0].mask_pitch = 79
+        assert _segment(p, sl, 1, pr, 2, outs) == 1
+    elif case == "ws_small":
+        assert _segment(p, sl, 1, pr, 2, outs, wsb=1024) == 3
+    elif case == "misaligned":
+        assert _segment(p, sl, 1, pr, 2, outs, ws=FAKE + 8) == 1
+    elif case == "too_many_slides":
+        assert _segment(p, _slides([(100, 80)] * 33), 33, pr, 2, _outs(66)) == 1
+
+
+def test_stitch_rejects_before_any_hip_call():
+    lib = om.lib()
+    n = ctypes.c_int64()
+    assert lib.omniseg_stitch_workspace_bytes(64, 32, 100, 90, ctypes.byref(n)) == 0
+    assert n.value == 256  # 4 x 3 grid of int32, aligned
+    assert lib.omniseg_stitch_workspace_bytes(64, 65, 100, 90, ctypes.byref(n)) == 1
+    args = dict(tile=64, stride=32, h=100, w=90)
+    # workspace too small
+    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, FAKE, FAKE, 3, FAKE, 90, 0, 0, FAKE, 16, None) == 3
+    # more tiles than grid positions
+    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, FAKE, FAKE, 13, FAKE, 90, 0, 0, FAKE, 256, None) == 1
+    # mask pitch
+    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, FAKE, FAKE, 3, FAKE, 89, 0, 0, FAKE, 256, None) == 1
+    del args

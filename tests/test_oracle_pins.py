@@ -273,6 +273,28 @@ def test_bias_only_network_closed_form():
     assert np.allclose(g, E[-1], atol=0, rtol=1e-15)
 
 
+def test_round_bf16_against_torch():
+    rng = np.random.default_rng(23)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.4e38, -1e-40]])
+    want = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(O.round_bf16(x), want)
+
+
+def test_bf16_emulation_only_rounds():
+    """With rounding that is the identity the emulated path equals FP64."""
+    cfg = O.make_config(base=4, levels=2, head_out=1, n_classes=1, scales=(0,), tile=16, stride=8)
+    flat = synth.he_normal_weights(3, 4, 2, 1, 1, 1, bias_std=0.1)
+    x = np.random.default_rng(1).uniform(size=(3, 16, 16))
+    wts = O.unpack_weights(flat, cfg)
+    F0, g0 = O.unet_forward(x, wts, cfg)
+    F1, g1 = O.unet_forward(x, wts, cfg, store=lambda v: v)
+    assert np.array_equal(F0, F1) and np.array_equal(g0, g1)
+    Fb, gb, sv = O.unet_forward(x, O.bf16_weights(wts), cfg, keep=True, store=O.round_bf16)
+    D0 = sv["D0"]  # stored activations are bfloat16 values; precls after it is FP32
+    assert np.array_equal(D0, O.round_bf16(D0)) and np.abs(Fb - F0).max() > 0
+
+
 # ---------------------------------------------------------------- O7-O8 controller and head
 
 def test_controller_closed_form_without_gap_columns():
