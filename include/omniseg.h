@@ -53,6 +53,7 @@ extern "C" {
 
 /* flags */
 #define OMNISEG_FLAG_EMIT_LOGITS 1 /* also write the stitched FP32 logit map */
+#define OMNISEG_FLAG_TRAINING 2    /* also pack the data-gradient weights (training entry points) */
 
 /* limits */
 #define OMNISEG_MAX_SCALES 4
@@ -235,6 +236,76 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
                              int32_t n_tiles, uint8_t* mask, int64_t mask_pitch,
                              float* logit, int64_t logit_pitch, void* workspace,
                              int64_t ws_bytes, omniseg_stream stream);
+
+/*
+ * ---- training: forward over a tile batch, BCE loss, hand-written backward ----
+ *
+ * A training step takes a batch of tiles of one slide (or region), runs the
+ * backbone, controller and head on them, stitches each requested (class,
+ * scale) plane from the batch tiles only, and compares it with a soft target
+ * by binary cross-entropy over the pixels the batch covers.  The backward
+ * pass returns dLoss/dweights in the canonical FP32 order.  U-Net levels are
+ * checkpointed: the forward keeps each level's output (E_l, D_l), the
+ * backward recomputes each level's first conv from its saved input.
+ *
+ * Planes of all pairs are concatenated in one flat array in pair order;
+ * plane p holds ceil(height / 2^k) x ceil(width / 2^k) values (k = the
+ * pair's scale), rows contiguous, starting at omniseg_plane_offsets()[p].
+ */
+typedef struct omniseg_tile {
+  int32_t scale; /* scale slot */
+  int32_t jy;    /* tile row in the slot's grid */
+  int32_t jx;    /* tile column */
+} omniseg_tile;
+
+#define OMNISEG_MAX_TRAIN_TILES 256
+
+/* offsets[n_pairs + 1] (host): start of each flat plane; offsets[n_pairs] =
+ * total number of values. */
+int32_t omniseg_plane_offsets(const omniseg_plan* plan, const omniseg_slide* slide,
+                              const omniseg_pair* pairs, int32_t n_pairs, int64_t* offsets);
+/* Workspace for omniseg_train_forward + omniseg_backward (the same buffer). */
+int32_t omniseg_train_workspace_bytes(const omniseg_plan* plan, const omniseg_slide* slide,
+                                      const omniseg_tile* tiles, int32_t n_tiles,
+                                      const omniseg_pair* pairs, int32_t n_pairs,
+                                      int64_t* bytes);
+/*
+ * Forward pass of a training batch (plan created with OMNISEG_FLAG_TRAINING).
+ *   slide       host pointer to one slide (device pixels).
+ *   tiles       host array [n_tiles], 1 <= n_tiles <= 256, distinct, inside
+ *               the slot grids; no tissue filter is applied.
+ *   logit       device float[offsets[n_pairs]]: stitched logits of the batch
+ *               (0 where no batch tile covers the pixel).
+ *   covered     device uint8[offsets[n_pairs]]: 1 where a batch tile covers.
+ * The workspace keeps what omniseg_backward needs; do not modify it between
+ * the two calls.
+ */
+int32_t omniseg_train_forward(const omniseg_plan* plan, const void* packed,
+                              const omniseg_slide* slide, const omniseg_tile* tiles,
+                              int32_t n_tiles, const omniseg_pair* pairs, int32_t n_pairs,
+                              float* logit, uint8_t* covered, void* workspace, int64_t ws_bytes,
+                              omniseg_stream stream);
+/*
+ * Backward pass after omniseg_train_forward with the same arguments.
+ *   grad_logit    device float[offsets[n_pairs]]: dLoss/dlogit (0 where uncovered).
+ *   grad_weights  device float[omniseg_weight_count]: overwritten with
+ *                 dLoss/dweights in canonical order.
+ * Deterministic: every reduction sums in a fixed order.
+ */
+int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omniseg_slide* slide,
+                         const omniseg_tile* tiles, int32_t n_tiles, const omniseg_pair* pairs,
+                         int32_t n_pairs, const float* grad_logit, float* grad_weights,
+                         void* workspace, int64_t ws_bytes, omniseg_stream stream);
+/*
+ * Mean binary cross-entropy with logits over the entries where valid != 0:
+ * loss = sum(max(x, 0) - y x + log1p(exp(-|x|))) / count, accumulated in
+ * FP64 with a fixed-order reduction; grad (device float[n], may be NULL) =
+ * (sigmoid(x) - y) / count where valid, else 0.  loss: device double.
+ * workspace: device, >= 16384 bytes.
+ */
+int32_t omniseg_bce_loss(const float* logit, const float* target, const uint8_t* valid, int64_t n,
+                         double* loss, float* grad, void* workspace, int64_t ws_bytes,
+                         omniseg_stream stream);
 
 /*
  * Per-launch profiling.  With profiling enabled, omniseg_segment_slide

@@ -11,13 +11,15 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
+#include "plan.h"
 
 using namespace omniseg;
 
-namespace {
+namespace omniseg {
 
+namespace {
 thread_local std::string g_last_error;
+}
 
 int32_t fail(int32_t code, const char* fmt, ...) {
   char buf[512];
@@ -29,82 +31,9 @@ int32_t fail(int32_t code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(OMNISEG_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
-  } while (0)
+const char* last_error_text() { return g_last_error.c_str(); }
 
-struct ConvDesc {
-  int64_t canon_w, canon_b;
-  int cin, cout, cu;
-  int cin_p, cout_p, cu_p;
-  int64_t pk_w, pk_b;
-};
-
-int elem_size(int precision) { return precision == OMNISEG_BF16 ? 2 : 4; }
-
-}  // namespace
-
-struct omniseg_plan {
-  omniseg_config cfg;
-  int L = 0;
-  int C[8] = {0};
-  int Cp[8] = {0};
-  int P = 0;
-  int G = 0;
-  int64_t n_canon = 0;
-  ConvDesc enc_a[8], enc_b[8], dec_a[8], dec_b[8];
-  int64_t canon_first_w = 0, canon_first_b = 0, pk_first_w = 0, pk_first_b = 0;
-  int64_t canon_pre_w = -1, canon_pre_b = -1, pk_pre_w = 0, pk_pre_b = 0;
-  int64_t canon_ctrl_w = 0, canon_ctrl_b = 0, pk_ctrl_w = 0, pk_ctrl_b = 0;
-  int64_t packed_bytes = 0;
-  mutable std::vector<SlideDev> slide_tab;  // host staging of the device slide table
-  // per-launch profiling (off by default)
-  bool profiling = false;
-  mutable std::vector<hipEvent_t> events;
-  mutable std::vector<omniseg_launch_record> recs;
-  ~omniseg_plan() {
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
-  }
-};
-
-namespace {
-
-// Records a pair of events around each launch when profiling is on.
-struct Prof {
-  const omniseg_plan* p;
-  hipStream_t st;
-  size_t next = 0;
-  hipError_t begin() {
-    if (!p->profiling) return hipSuccess;
-    while (p->events.size() < 2 * (next + 1)) {
-      hipEvent_t e;
-      hipError_t r = hipEventCreate(&e);
-      if (r != hipSuccess) return r;
-      p->events.push_back(e);
-    }
-    return hipEventRecord(p->events[2 * next], st);
-  }
-  hipError_t end(int stage, int level, int tiles, double flops, double bytes) {
-    if (!p->profiling) return hipSuccess;
-    hipError_t r = hipEventRecord(p->events[2 * next + 1], st);
-    omniseg_launch_record rec;
-    rec.stage = stage;
-    rec.level = level;
-    rec.tiles = tiles;
-    rec.precision = p->cfg.precision;
-    rec.flops = flops;
-    rec.bytes = bytes;
-    rec.ms = 0.0;
-    p->recs.push_back(rec);
-    ++next;
-    return r;
-  }
-};
-
-}  // namespace
+}  // namespace omniseg
 
 namespace {
 
@@ -162,7 +91,8 @@ int32_t validate_config(const omniseg_config* c) {
     return fail(OMNISEG_ERR_ARG, "fg_threshold %d outside [1, 255]", c->fg_threshold);
   if (c->precision != OMNISEG_FP32 && c->precision != OMNISEG_BF16)
     return fail(OMNISEG_ERR_UNSUPPORTED, "unknown precision %d", c->precision);
-  if (c->flags & ~OMNISEG_FLAG_EMIT_LOGITS) return fail(OMNISEG_ERR_ARG, "unknown flags 0x%x", c->flags);
+  if (c->flags & ~(OMNISEG_FLAG_EMIT_LOGITS | OMNISEG_FLAG_TRAINING))
+    return fail(OMNISEG_ERR_ARG, "unknown flags 0x%x", c->flags);
   if (c->batch_tiles < 0 || c->batch_tiles > 65536)
     return fail(OMNISEG_ERR_ARG, "batch_tiles %d outside [0, 65536]", c->batch_tiles);
   const int64_t G = (int64_t)c->base_channels << (c->levels - 1);
@@ -285,7 +215,7 @@ const char* omniseg_status_string(int32_t status) {
   }
 }
 
-const char* omniseg_last_error(void) { return g_last_error.c_str(); }
+const char* omniseg_last_error(void) { return omniseg::last_error_text(); }
 
 int32_t omniseg_plan_create(const omniseg_config* cfg, omniseg_plan** out) {
   if (!out) return fail(OMNISEG_ERR_ARG, "out is NULL");
@@ -302,6 +232,7 @@ int32_t omniseg_plan_create(const omniseg_config* cfg, omniseg_plan** out) {
   p->P = 144 + 9 * cfg->head_out;
   p->G = p->C[p->L - 1];
   const int es = elem_size(cfg->precision);
+  const bool training = (cfg->flags & OMNISEG_FLAG_TRAINING) != 0;
   int64_t canon = 0, pk = 0;
   auto ptake = [&](int64_t bytes) {
     int64_t o = pk;
@@ -321,6 +252,7 @@ int32_t omniseg_plan_create(const omniseg_config* cfg, omniseg_plan** out) {
     d.cout_p = pad_ch(cout);
     d.pk_w = ptake((int64_t)d.cin_p * 9 * d.cout_p * es);
     d.pk_b = ptake((int64_t)d.cout_p * 4);
+    d.pk_wt = training ? ptake((int64_t)d.cin_p * 9 * d.cout_p * es) : -1;
   };
   for (int l = 0; l < p->L; ++l) {
     if (l == 0) {
@@ -397,6 +329,12 @@ int32_t omniseg_pack_weights(const omniseg_plan* plan, const float* canonical, v
     pc.cout_p = d.cout_p;
     pc.dst = d.pk_w;
     pc.dst_b = d.pk_b;
+    pc.transpose = 0;
+    hipError_t e = launch_pack_conv(prec, canonical, packed, pc, st);
+    if (e != hipSuccess || d.pk_wt < 0) return e;
+    pc.dst = d.pk_wt;
+    pc.dst_b = -1;
+    pc.transpose = 1;
     return launch_pack_conv(prec, canonical, packed, pc, st);
   };
   HIP_TRY(launch_copy_f32(canonical + plan->canon_first_w, (float*)(pk + plan->pk_first_w), (int64_t)plan->C[0] * 27, st));
@@ -710,6 +648,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
       sa.fg_shift = lay.kc - gm.k;
       sa.Hc = lay.Hc[i];
       sa.Wc = lay.Wc[i];
+      sa.coverage = 0;
       double cover = 0.0;
       if (plan->profiling) {
         // every in-plane pixel of every kept tile is read exactly once
@@ -793,6 +732,7 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
   sa.fg_shift = 0;
   sa.Hc = 0;
   sa.Wc = 0;
+  sa.coverage = 0;
   HIP_TRY(launch_stitch(sa, sm));
   return OMNISEG_OK;
 }

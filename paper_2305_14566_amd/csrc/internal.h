@@ -86,12 +86,15 @@ struct ConvLayer {
 };
 
 enum Loader { LOAD_PLAIN = 0, LOAD_POOL = 1, LOAD_UPCAT = 2 };
-enum Epilogue { EPI_RELU = 0, EPI_RES_RELU = 1 };
+// RELU: ReLU(acc + bias).  RES_RELU: ReLU(acc + bias + x0).  NONE: acc (data
+// gradients).  RES_MASK: (acc + x0) where aux > 0, else 0 (the data gradient
+// of a residual conv block, through the ReLU of its first conv).
+enum Epilogue { EPI_RELU = 0, EPI_RES_RELU = 1, EPI_NONE = 2, EPI_RES_MASK = 3 };
 
 // 3x3 conv on a batch of tiles (NHWC, padded channels), output H x W per tile.
 hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L, int H, int W,
                           int batch, const int32_t* count, int chunk_base, const void* x0,
-                          const void* x1, void* y, hipStream_t st);
+                          const void* x1, void* y, hipStream_t st, const void* aux = nullptr);
 
 // First conv (3 -> C_0) straight from the slide / pyramid.
 struct FirstConvArgs {
@@ -140,10 +143,81 @@ struct StitchArgs {
   int64_t logit_pitch;
   const uint8_t* fg;  // tissue map for mask_and_fg (or null)
   int fg_shift, Hc, Wc;
+  int coverage;       // 1: mask = (D > 0) instead of (N > 0)
 };
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t st);
 hipError_t launch_grid_from_list(const int32_t* tile_yx, int n_tiles, int ny, int nx,
                                  int32_t* grid, hipStream_t st);
+
+// ---- backward ---------------------------------------------------------------
+
+hipError_t launch_input_x(const FirstConvArgs& a, float* x, hipStream_t st);
+
+struct StitchBwdArgs {
+  const float* dlam;  // flat per-pair gradient planes
+  float* dl;          // [n_tiles][max_slots][T][T]
+  const int32_t* list;
+  int n_tiles, T, s, max_slots;
+  int ny[OMNISEG_MAX_SCALES], nx[OMNISEG_MAX_SCALES], Hk[OMNISEG_MAX_SCALES], Wk[OMNISEG_MAX_SCALES];
+  const int32_t* grid[OMNISEG_MAX_SCALES];
+  int n_slots[OMNISEG_MAX_SCALES];
+  int64_t plane_off[OMNISEG_MAX_SCALES][OMNISEG_MAX_CLASSES];
+};
+hipError_t launch_stitch_bwd(const StitchBwdArgs& a, hipStream_t st);
+
+struct HeadBwdArgs {
+  const void* d0;         // decoder output D_0 [tile][T][T][c0_p]
+  const float* theta;     // [tile][max_slots][P]
+  const float* dl;        // [tile][max_slots][T][T]
+  const float* wp;        // precls W [8][c0] (or null)
+  const float* bp;
+  const int32_t* list;
+  int n_slots[OMNISEG_MAX_SCALES];
+  int n_tiles, T, c0, c0_p, o, max_slots;
+  float* dtheta_part;     // [tile][max_slots][T*T/256][P]
+  float* dwp_part;        // [tile][T*T/256][8 c0 + 8]
+  void* dd0;              // dL/dD_0 [tile][T][T][c0_p]
+};
+hipError_t launch_head_bwd(int precision, const HeadBwdArgs& a, hipStream_t st);
+hipError_t launch_sum_mid(const float* in, int R, int K, int I, float* out, hipStream_t st);
+
+struct CtrlBwdArgs {
+  const float* dtheta;  // [tile][max_slots][P]
+  const float* g;       // [tile][g_stride]
+  const float* wc;      // [P][row_len]
+  const int32_t* list;
+  int n_slots[OMNISEG_MAX_SCALES];
+  int cls[OMNISEG_MAX_SCALES][OMNISEG_MAX_CLASSES];
+  int n_tiles, max_slots, P, G, g_stride, n_classes, row_len;
+  float* dwc;  // canonical W_c gradient
+  float* dbc;  // canonical b_c gradient
+  float* dg;   // [tile][g_stride]
+};
+hipError_t launch_ctrl_bwd(const CtrlBwdArgs& a, hipStream_t st);
+
+hipError_t launch_gap_bwd(int precision, const float* dg, int g_stride, int G, int hw, int c_p, int n_tiles,
+                          void* dE, hipStream_t st);
+hipError_t launch_relu_mask(int precision, const void* dy, const void* y, int64_t n, void* out, hipStream_t st);
+hipError_t launch_concat_bwd(int precision, const void* dZ, int n_tiles, int H, int W, int cu_p, int ce_p,
+                             void* dE, void* dD, int accumulate, hipStream_t st);
+hipError_t launch_maxpool_bwd(int precision, const void* E, const void* dX, int n_tiles, int H, int W, int c_p,
+                              void* dE, hipStream_t st);
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+
+struct WgradArgs {
+  const void* x0;  // forward conv input (loader source)
+  const void* x1;  // UPCAT skip source
+  const void* dy;  // gradient at the conv output [tile][H][W][cout_p]
+  float* part;     // [splits][cout_p][9][cin_p]
+  int H, W, cin_p, cu_p, cout_p, n_tiles, splits;
+};
+int wgrad_bo(int cout_p);
+hipError_t launch_wgrad(int precision_x, int precision_g, int loader, const WgradArgs& a, int cout, int cin,
+                        int cu, float* dst, hipStream_t st);
+hipError_t launch_bias_grad(int precision, const void* dy, int64_t npix, int c_p, int cout, float* part,
+                            int splits, float* dst, hipStream_t st);
+hipError_t launch_bce(const float* lg, const float* y, const uint8_t* valid, int64_t n, double* part_sum,
+                      int* part_cnt, int nb, double* loss, int* count, float* grad, hipStream_t st);
 
 // Weight packing
 struct PackConv {
@@ -153,7 +227,8 @@ struct PackConv {
   int cu, cu_p;    // UPCAT split: real / padded channels of the first source
   int cin_p, cout_p;
   int64_t dst;     // byte offset of packed weights
-  int64_t dst_b;   // byte offset of packed bias
+  int64_t dst_b;   // byte offset of packed bias (< 0: none)
+  int transpose;   // 1: pack the data-gradient conv (channels swapped, taps flipped)
 };
 hipError_t launch_pack_conv(int precision, const float* canon, void* packed, const PackConv& p,
                             hipStream_t st);

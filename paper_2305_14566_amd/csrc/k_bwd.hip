@@ -1,0 +1,759 @@
+// Backward pass of the slide-wise path: stitch, dynamic head, controller,
+// bottleneck mean, and the U-Net's weight and data gradients.
+//
+// Every reduction is deterministic: partial sums go to per-block slots and
+// are summed in a fixed order by a second kernel (no floating-point atomics).
+// Weight gradients are written straight into the canonical FP32 order.
+#include "internal.h"
+
+namespace omniseg {
+
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+__device__ __forceinline__ float ldf(const float* p) { return *p; }
+__device__ __forceinline__ float ldf(const uint16_t* p) { return __uint_as_float((uint32_t)(*p) << 16); }
+__device__ __forceinline__ void stf(float* p, float v) { *p = v; }
+__device__ __forceinline__ void stf(uint16_t* p, float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  *p = (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// network input of each batch tile, FP32 NHWC with 32 channels (3 real)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_input_x(FirstConvArgs a, float* __restrict__ x) {
+  const int T2 = a.T * a.T;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)a.batch * T2) return;
+  const int b = (int)(i / T2), q = (int)(i % T2);
+  const int4 t = reinterpret_cast<const int4*>(a.list)[a.chunk_base + b];
+  const SlideDev& sd = a.slides[t.x];
+  const int k = a.scale_k[t.y];
+  const int Y = t.z * a.s + q / a.T, X = t.w * a.s + q % a.T;
+  const float scale = 1.0f / (255.0f * (float)(1 << (2 * k)));
+  float v0, v1, v2;
+  if (k == 0) {
+    int r, g, bb;
+    if (Y < sd.H && X < sd.W) {
+      const uint8_t* p = sd.rgb + (int64_t)Y * sd.pitch + 3 * X;
+      r = p[0];
+      g = p[1];
+      bb = p[2];
+    } else {
+      r = sd.pad[0];
+      g = sd.pad[1];
+      bb = sd.pad[2];
+    }
+    v0 = r * scale;
+    v1 = g * scale;
+    v2 = bb * scale;
+  } else {
+    const ushort4 s4 = reinterpret_cast<const ushort4*>(sd.pyr[t.y])[(int64_t)Y * sd.pyr_ex[t.y] + X];
+    v0 = s4.x * scale;
+    v1 = s4.y * scale;
+    v2 = s4.z * scale;
+  }
+  float4* o = reinterpret_cast<float4*>(x + i * 32);
+  o[0] = make_float4(v0, v1, v2, 0.f);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) o[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+hipError_t launch_input_x(const FirstConvArgs& a, float* x, hipStream_t st) {
+  const int64_t n = (int64_t)a.batch * a.T * a.T;
+  hipLaunchKernelGGL(k_input_x, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, x);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// stitch backward: dl_t(q) = dLambda(o_t + q) w(q) / D(o_t + q)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_stitch_bwd(StitchBwdArgs a) {
+  const int T = a.T, s = a.s, T2 = T * T;
+  const int per = T2 / 256;
+  const int blk = blockIdx.x;
+  const int t = blk / (a.max_slots * per);
+  const int j = (blk / per) % a.max_slots;
+  const int q = (blk % per) * 256 + threadIdx.x;
+  const int4 tl = reinterpret_cast<const int4*>(a.list)[t];
+  const int si = tl.y;
+  if (j >= a.n_slots[si]) return;
+  const int qy = q / T, qx = q % T;
+  const int y = tl.z * s + qy, x = tl.w * s + qx;
+  float out = 0.f;
+  if (y < a.Hk[si] && x < a.Wk[si]) {
+    const int ny = a.ny[si], nx = a.nx[si];
+    const int32_t* grid = a.grid[si];
+    const int jy0 = (y < T) ? 0 : (y - T) / s + 1, jy1 = min(ny - 1, y / s);
+    const int jx0 = (x < T) ? 0 : (x - T) / s + 1, jx1 = min(nx - 1, x / s);
+    int den = 0;
+    for (int jy = jy0; jy <= jy1; ++jy) {
+      const int iy = y - jy * s;
+      const int ry = min(iy + 1, T - iy);
+      for (int jx = jx0; jx <= jx1; ++jx) {
+        if (grid[jy * nx + jx] < 0) continue;
+        const int ix = x - jx * s;
+        den += ry * min(ix + 1, T - ix);
+      }
+    }
+    const int w = min(qy + 1, T - qy) * min(qx + 1, T - qx);
+    const float g = a.dlam[a.plane_off[si][j] + (int64_t)y * a.Wk[si] + x];
+    out = g * (float)w / (float)den;
+  }
+  a.dl[((int64_t)t * a.max_slots + j) * T2 + q] = out;
+}
+
+hipError_t launch_stitch_bwd(const StitchBwdArgs& a, hipStream_t st) {
+  const int per = a.T * a.T / 256;
+  hipLaunchKernelGGL(k_stitch_bwd, dim3(a.n_tiles * a.max_slots * per), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dynamic head + precls backward, one thread per pixel; per-block partial
+// sums of the parameter gradients (theta per slot, W_p and b_p)
+// ---------------------------------------------------------------------------
+template <typename T, int O>
+__global__ __launch_bounds__(256) void k_head_bwd(HeadBwdArgs a) {
+  constexpr int P = 144 + 9 * O;
+  __shared__ float sth[OMNISEG_MAX_CLASSES * P];
+  __shared__ float swp[8 * 128 + 8];
+  __shared__ float red[4][8 * 128 + 8];
+  const int T2 = a.T * a.T;
+  const int per = T2 / 256;
+  const int b = blockIdx.x / per, pblk = blockIdx.x % per;
+  const int pix = pblk * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int si = a.list[4 * b + 1];
+  const int ns = a.n_slots[si];
+  const int c0 = a.c0;
+  for (int i = threadIdx.x; i < ns * P; i += 256) sth[i] = a.theta[(int64_t)b * a.max_slots * P + i];
+  const bool pre = (c0 != 8);
+  if (pre) {
+    for (int i = threadIdx.x; i < 8 * c0; i += 256) swp[i] = a.wp[i];
+    if (threadIdx.x < 8) swp[8 * c0 + threadIdx.x] = a.bp[threadIdx.x];
+  }
+  __syncthreads();
+  const T* px = (const T*)a.d0 + ((int64_t)b * T2 + pix) * a.c0_p;
+  float F[8], Fpre[8];
+  if (pre) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) Fpre[o] = swp[8 * c0 + o];
+    for (int c = 0; c < c0; ++c) {
+      const float v = ldf(px + c);
+#pragma unroll
+      for (int o = 0; o < 8; ++o) Fpre[o] = fmaf(swp[o * c0 + c], v, Fpre[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) F[o] = fmaxf(Fpre[o], 0.f);
+  } else {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) F[o] = Fpre[o] = ldf(px + o);
+  }
+  float dF[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) dF[o] = 0.f;
+  for (int j = 0; j < ns; ++j) {
+    const float* th = &sth[j * P];
+    const float* W1 = th;
+    const float* W2 = th + 64;
+    const float* W3 = th + 128;
+    const float* b1 = th + 128 + 8 * O;
+    const float* b2 = b1 + 8;
+    float h1p[8], h1[8], h2p[8], h2[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      float s = b1[o];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s = fmaf(W1[o * 8 + i], F[i], s);
+      h1p[o] = s;
+      h1[o] = fmaxf(s, 0.f);
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      float s = b2[o];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s = fmaf(W2[o * 8 + i], h1[i], s);
+      h2p[o] = s;
+      h2[o] = fmaxf(s, 0.f);
+    }
+    const float dl = a.dl[((int64_t)b * a.max_slots + j) * T2 + pix];
+    float dz[O];
+    if (O == 1) {
+      dz[0] = dl;
+    } else {
+      dz[0] = -dl;
+      dz[O - 1] = dl;
+    }
+    float dh2[8], dh1[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float s = 0.f;
+#pragma unroll
+      for (int o = 0; o < O; ++o) s = fmaf(W3[o * 8 + i], dz[o], s);
+      dh2[i] = h2p[i] > 0.f ? s : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float s = 0.f;
+#pragma unroll
+      for (int o = 0; o < 8; ++o) s = fmaf(W2[o * 8 + i], dh2[o], s);
+      dh1[i] = h1p[i] > 0.f ? s : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float s = 0.f;
+#pragma unroll
+      for (int o = 0; o < 8; ++o) s = fmaf(W1[o * 8 + i], dh1[o], s);
+      dF[i] += s;
+    }
+    // per-pixel parameter gradient, reduced over the block: W1, W2, W3, b1, b2, b3
+    float* dst = a.dtheta_part + (((int64_t)b * a.max_slots + j) * per + pblk) * P;
+    for (int p = 0; p < P; ++p) {
+      float v;
+      if (p < 64) v = dh1[p / 8] * F[p % 8];
+      else if (p < 128) v = dh2[(p - 64) / 8] * h1[(p - 64) % 8];
+      else if (p < 128 + 8 * O) v = dz[(p - 128) / 8] * h2[(p - 128) % 8];
+      else if (p < 136 + 8 * O) v = dh1[p - 128 - 8 * O];
+      else if (p < 144 + 8 * O) v = dh2[p - 136 - 8 * O];
+      else v = dz[p - 144 - 8 * O];
+      v = wave_sum(v);
+      if (lane == 0) red[wave][p] = v;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < P; p += 256) dst[p] = (red[0][p] + red[1][p]) + (red[2][p] + red[3][p]);
+    __syncthreads();
+  }
+  // precls backward
+  T* dd0 = (T*)a.dd0 + ((int64_t)b * T2 + pix) * a.c0_p;
+  if (pre) {
+    float dpre[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) dpre[o] = Fpre[o] > 0.f ? dF[o] : 0.f;
+    for (int c = 0; c < a.c0_p; ++c) {
+      float s = 0.f;
+      if (c < c0) {
+#pragma unroll
+        for (int o = 0; o < 8; ++o) s = fmaf(swp[o * c0 + c], dpre[o], s);
+      }
+      stf(dd0 + c, s);
+    }
+    const int NP = 8 * c0 + 8;
+    float* dst = a.dwp_part + ((int64_t)b * per + pblk) * NP;
+    for (int p = 0; p < NP; ++p) {
+      float v = (p < 8 * c0) ? dpre[p / c0] * ldf(px + p % c0) : dpre[p - 8 * c0];
+      v = wave_sum(v);
+      if (lane == 0) red[wave][p] = v;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < NP; p += 256) dst[p] = (red[0][p] + red[1][p]) + (red[2][p] + red[3][p]);
+  } else {
+    for (int c = 0; c < a.c0_p; ++c) stf(dd0 + c, c < 8 ? dF[c] : 0.f);
+  }
+}
+
+hipError_t launch_head_bwd(int precision, const HeadBwdArgs& a, hipStream_t st) {
+  const int per = a.T * a.T / 256;
+  dim3 grid(a.n_tiles * per);
+  if (a.c0 > 128) return hipErrorInvalidValue;
+  if (precision == OMNISEG_BF16) {
+    if (a.o == 1) hipLaunchKernelGGL((k_head_bwd<uint16_t, 1>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_head_bwd<uint16_t, 2>), grid, dim3(256), 0, st, a);
+  } else {
+    if (a.o == 1) hipLaunchKernelGGL((k_head_bwd<float, 1>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_head_bwd<float, 2>), grid, dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+// out[r][i] = sum_k in[r][k][i] for k = 0..K-1 (fixed order); optional scatter
+// of each row into the canonical vector at dst[r * dst_stride + i]
+__global__ void k_sum_mid(const float* __restrict__ in, int R, int K, int I, float* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)R * I) return;
+  const int r = (int)(idx / I), i = (int)(idx % I);
+  float s = 0.f;
+  for (int k = 0; k < K; ++k) s += in[((int64_t)r * K + k) * I + i];
+  out[idx] = s;
+}
+
+hipError_t launch_sum_mid(const float* in, int R, int K, int I, float* out, hipStream_t st) {
+  const int64_t n = (int64_t)R * I;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_mid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, R, K, I, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// controller backward
+// ---------------------------------------------------------------------------
+// dW_c[p][i] (row_len columns) and db_c[p], summed over (tile, slot) in order
+__global__ void k_ctrl_wgrad(CtrlBwdArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int cols = a.row_len + 1;
+  if (idx >= (int64_t)a.P * cols) return;
+  const int p = (int)(idx / cols), i = (int)(idx % cols);
+  float s = 0.f;
+  for (int t = 0; t < a.n_tiles; ++t) {
+    const int si = a.list[4 * t + 1];
+    for (int j = 0; j < a.n_slots[si]; ++j) {
+      const float d = a.dtheta[((int64_t)t * a.max_slots + j) * a.P + p];
+      float v;
+      if (i < a.G) v = a.g[(int64_t)t * a.g_stride + i];
+      else if (i < a.G + a.n_classes) v = (a.cls[si][j] == i - a.G) ? 1.f : 0.f;
+      else if (i < a.row_len) v = (si == i - a.G - a.n_classes) ? 1.f : 0.f;
+      else v = 1.f;  // bias
+      s = fmaf(d, v, s);
+    }
+  }
+  if (i < a.row_len) a.dwc[(int64_t)p * a.row_len + i] = s;
+  else a.dbc[p] = s;
+}
+
+// dg[t][i] = sum_j sum_p W_c[p][i] dtheta[t][j][p]
+__global__ void k_ctrl_dg(CtrlBwdArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.n_tiles * a.G) return;
+  const int t = (int)(idx / a.G), i = (int)(idx % a.G);
+  const int si = a.list[4 * t + 1];
+  float s = 0.f;
+  for (int j = 0; j < a.n_slots[si]; ++j)
+    for (int p = 0; p < a.P; ++p)
+      s = fmaf(a.wc[(int64_t)p * a.row_len + i], a.dtheta[((int64_t)t * a.max_slots + j) * a.P + p], s);
+  a.dg[(int64_t)t * a.g_stride + i] = s;
+}
+
+hipError_t launch_ctrl_bwd(const CtrlBwdArgs& a, hipStream_t st) {
+  const int64_t n1 = (int64_t)a.P * (a.row_len + 1);
+  hipLaunchKernelGGL(k_ctrl_wgrad, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, a);
+  const int64_t n2 = (int64_t)a.n_tiles * a.G;
+  hipLaunchKernelGGL(k_ctrl_dg, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise gradient routing
+// ---------------------------------------------------------------------------
+// bottleneck mean backward: dE[t][pix][c] = dg[t][c] / hw (c < G), 0 on padding
+template <typename T>
+__global__ void k_gap_bwd(const float* dg, int g_stride, int G, int hw, int c_p, int64_t n, T* dE) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)(i % c_p);
+  const int64_t t = i / ((int64_t)hw * c_p);
+  stf(dE + i, c < G ? dg[t * g_stride + c] / (float)hw : 0.f);
+}
+
+hipError_t launch_gap_bwd(int precision, const float* dg, int g_stride, int G, int hw, int c_p, int n_tiles,
+                          void* dE, hipStream_t st) {
+  const int64_t n = (int64_t)n_tiles * hw * c_p;
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (precision == OMNISEG_BF16)
+    hipLaunchKernelGGL(k_gap_bwd<uint16_t>, grid, dim3(256), 0, st, dg, g_stride, G, hw, c_p, n, (uint16_t*)dE);
+  else
+    hipLaunchKernelGGL(k_gap_bwd<float>, grid, dim3(256), 0, st, dg, g_stride, G, hw, c_p, n, (float*)dE);
+  return hipGetLastError();
+}
+
+// out = (y > 0) ? dy : 0, elementwise
+template <typename T>
+__global__ void k_relu_mask(const T* dy, const T* y, int64_t n, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) stf(out + i, ldf(y + i) > 0.f ? ldf(dy + i) : 0.f);
+}
+
+hipError_t launch_relu_mask(int precision, const void* dy, const void* y, int64_t n, void* out, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (precision == OMNISEG_BF16)
+    hipLaunchKernelGGL(k_relu_mask<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)dy, (const uint16_t*)y, n,
+                       (uint16_t*)out);
+  else
+    hipLaunchKernelGGL(k_relu_mask<float>, grid, dim3(256), 0, st, (const float*)dy, (const float*)y, n, (float*)out);
+  return hipGetLastError();
+}
+
+// Split the data gradient of the decoder's concat input dZ [pix][cu_p + ce_p]:
+// skip part added into dE [pix][ce_p]; upsampled part summed over each 2x2
+// block into dD [pix/4][cu_p] (set, or added when `accumulate`).
+template <typename T>
+__global__ void k_concat_bwd(const T* dZ, int n_tiles, int H, int W, int cu_p, int ce_p, T* dE, T* dD,
+                             int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int cz = cu_p + ce_p;
+  const int64_t n_skip = (int64_t)n_tiles * H * W * ce_p;
+  const int64_t n_up = (int64_t)n_tiles * (H / 2) * (W / 2) * cu_p;
+  if (i < n_skip) {
+    const int c = (int)(i % ce_p);
+    const int64_t px = i / ce_p;
+    stf(dE + i, ldf(dE + i) + ldf(dZ + px * cz + cu_p + c));
+  } else if (i < n_skip + n_up) {
+    const int64_t k = i - n_skip;
+    const int c = (int)(k % cu_p);
+    int64_t r = k / cu_p;
+    const int X = (int)(r % (W / 2));
+    r /= (W / 2);
+    const int Y = (int)(r % (H / 2));
+    const int64_t t = r / (H / 2);
+    const T* z = dZ + ((t * H + 2 * Y) * W + 2 * X) * cz + c;
+    float s = (ldf(z) + ldf(z + cz)) + (ldf(z + (int64_t)W * cz) + ldf(z + (int64_t)W * cz + cz));
+    if (accumulate) s += ldf(dD + k);
+    stf(dD + k, s);
+  }
+}
+
+hipError_t launch_concat_bwd(int precision, const void* dZ, int n_tiles, int H, int W, int cu_p, int ce_p,
+                             void* dE, void* dD, int accumulate, hipStream_t st) {
+  const int64_t n = (int64_t)n_tiles * H * W * ce_p + (int64_t)n_tiles * (H / 2) * (W / 2) * cu_p;
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (precision == OMNISEG_BF16)
+    hipLaunchKernelGGL(k_concat_bwd<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)dZ, n_tiles, H, W, cu_p,
+                       ce_p, (uint16_t*)dE, (uint16_t*)dD, accumulate);
+  else
+    hipLaunchKernelGGL(k_concat_bwd<float>, grid, dim3(256), 0, st, (const float*)dZ, n_tiles, H, W, cu_p, ce_p,
+                       (float*)dE, (float*)dD, accumulate);
+  return hipGetLastError();
+}
+
+// 2x2 max-pool backward: each window's gradient goes to its first maximum
+// (row-major); added into dE of the finer level.
+template <typename T>
+__global__ void k_maxpool_bwd(const T* E, const T* dX, int n_tiles, int H, int W, int c_p, T* dE) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;  // coarse element
+  const int Hh = H / 2, Wh = W / 2;
+  if (i >= (int64_t)n_tiles * Hh * Wh * c_p) return;
+  const int c = (int)(i % c_p);
+  int64_t r = i / c_p;
+  const int X = (int)(r % Wh);
+  r /= Wh;
+  const int Y = (int)(r % Hh);
+  const int64_t t = r / Hh;
+  int64_t off[4];
+  off[0] = ((t * H + 2 * Y) * W + 2 * X) * c_p + c;
+  off[1] = off[0] + c_p;
+  off[2] = off[0] + (int64_t)W * c_p;
+  off[3] = off[2] + c_p;
+  int best = 0;
+  float bv = ldf(E + off[0]);
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    const float v = ldf(E + off[k]);
+    if (v > bv) {
+      bv = v;
+      best = k;
+    }
+  }
+  const float g = ldf(dX + i);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (k == best) stf(dE + off[k], ldf(dE + off[k]) + g);
+}
+
+hipError_t launch_maxpool_bwd(int precision, const void* E, const void* dX, int n_tiles, int H, int W, int c_p,
+                              void* dE, hipStream_t st) {
+  const int64_t n = (int64_t)n_tiles * (H / 2) * (W / 2) * c_p;
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (precision == OMNISEG_BF16)
+    hipLaunchKernelGGL(k_maxpool_bwd<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)E, (const uint16_t*)dX,
+                       n_tiles, H, W, c_p, (uint16_t*)dE);
+  else
+    hipLaunchKernelGGL(k_maxpool_bwd<float>, grid, dim3(256), 0, st, (const float*)E, (const float*)dX, n_tiles,
+                       H, W, c_p, (float*)dE);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_zero(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st) {
+  const int64_t n = bytes / 4;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient of a 3x3 conv on FP32 MFMA:
+// dW[o][tap][c] = sum over pixels of dY[pix][o] * X[pix + tap offset][c].
+// M = o (64 per block), N = c (32 per block), K = pixels of a BY x BX block;
+// the block's share of the pixel blocks is split-K slot `split`, whose
+// partial goes to part[split][o][tap][c].
+// ---------------------------------------------------------------------------
+template <typename TX, int LOADER>
+__device__ __forceinline__ float4 wg_load_x(const WgradArgs& a, int b, int y, int x, int c) {
+  const TX* X0 = (const TX*)a.x0;
+  if (LOADER == LOAD_PLAIN) {
+    const TX* p = X0 + (((int64_t)b * a.H + y) * a.W + x) * a.cin_p + c;
+    return make_float4(ldf(p), ldf(p + 1), ldf(p + 2), ldf(p + 3));
+  } else if (LOADER == LOAD_POOL) {
+    const int W2 = 2 * a.W;
+    const TX* p = X0 + (((int64_t)b * 2 * a.H + 2 * y) * W2 + 2 * x) * a.cin_p + c;
+    float4 r;
+    float* rr = &r.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float v0 = ldf(p + k), v1 = ldf(p + a.cin_p + k);
+      const float v2 = ldf(p + (int64_t)W2 * a.cin_p + k), v3 = ldf(p + (int64_t)W2 * a.cin_p + a.cin_p + k);
+      rr[k] = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
+    }
+    return r;
+  } else {
+    if (c < a.cu_p) {
+      const TX* p = X0 + (((int64_t)b * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1)) * a.cu_p + c;
+      return make_float4(ldf(p), ldf(p + 1), ldf(p + 2), ldf(p + 3));
+    }
+    const int ce_p = a.cin_p - a.cu_p;
+    const TX* p = (const TX*)a.x1 + (((int64_t)b * a.H + y) * a.W + x) * ce_p + (c - a.cu_p);
+    return make_float4(ldf(p), ldf(p + 1), ldf(p + 2), ldf(p + 3));
+  }
+}
+
+template <typename TX, typename TG, int BX, int BO, int LOADER>
+__global__ __launch_bounds__(256) void k_wgrad3x3(WgradArgs a) {
+  constexpr int BY = 8, BM = BY * BX, PX = BX + 2, NPIX = (BY + 2) * PX;
+  constexpr int BC = 32;
+  constexpr int FO = BO / 32;                  // 16-row fragments per wave along o
+  constexpr int GROW = BO + 1, XROW = BC + 1;  // odd row lengths spread LDS banks
+  __shared__ float sG[BM * GROW];
+  __shared__ float sX[NPIX * XROW];
+  const int n_ob = a.cout_p / BO, n_cb = a.cin_p / BC;
+  int rest = blockIdx.x;
+  const int ob = rest % n_ob;
+  rest /= n_ob;
+  const int cb = rest % n_cb;
+  const int split = rest / n_cb;
+  const int o0 = ob * BO, c0 = cb * BC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // wave tile: BO/2 o x 16 c
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int tiles_y = a.H / BY, tiles_x = a.W / BX;
+  const int n_chunks = a.n_tiles * tiles_y * tiles_x;
+  f32x4 acc[9][FO];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int f = 0; f < FO; ++f) acc[t][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ch = split; ch < n_chunks; ch += a.splits) {
+    const int b = ch / (tiles_y * tiles_x);
+    const int sy = (ch / tiles_x) % tiles_y, sx = ch % tiles_x;
+    const int y0 = sy * BY, x0 = sx * BX;
+    const TG* G = (const TG*)a.dy;
+    for (int i = tid; i < BM * BO; i += 256) {
+      const int m = i / BO, o = i % BO;
+      const int y = y0 + m / BX, x = x0 + m % BX;
+      sG[m * GROW + o] = ldf(G + (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + o0 + o);
+    }
+    for (int i = tid; i < NPIX * (BC / 4); i += 256) {
+      const int p = i / (BC / 4), v = (i % (BC / 4)) * 4;
+      const int y = y0 + p / PX - 1, x = x0 + p % PX - 1;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (y >= 0 && y < a.H && x >= 0 && x < a.W) val = wg_load_x<TX, LOADER>(a, b, y, x, c0 + v);
+      float* d = &sX[p * XROW + v];
+      d[0] = val.x;
+      d[1] = val.y;
+      d[2] = val.z;
+      d[3] = val.w;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < BM; k0 += 4) {
+      const int m = k0 + kq;  // this lane's pixel (MFMA K index)
+      const int py = m / BX, pxx = m % BX;
+      float ga[FO];
+#pragma unroll
+      for (int f = 0; f < FO; ++f) ga[f] = sG[m * GROW + wm * (BO / 2) + f * 16 + l16];
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const float xv = sX[((py + tap / 3) * PX + pxx + tap % 3) * XROW + wn * 16 + l16];
+#pragma unroll
+        for (int f = 0; f < FO; ++f)
+          acc[tap][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[f], xv, acc[tap][f], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  float* part = a.part + (int64_t)split * a.cout_p * 9 * a.cin_p;
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int f = 0; f < FO; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = o0 + wm * (BO / 2) + f * 16 + kq * 4 + r;
+        const int c = c0 + wn * 16 + l16;
+        part[((int64_t)o * 9 + tap) * a.cin_p + c] = acc[tap][f][r];
+      }
+}
+
+// canonical[w_off + (o cin + c) 9 + tap] = sum_s part[s][o][tap][cp(c)]
+__global__ void k_wgrad_reduce(const float* part, int splits, int cout, int cin, int cu, int cu_p, int cout_p,
+                               int cin_p, float* dst) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)cout * cin * 9) return;
+  const int tap = (int)(idx % 9);
+  const int c = (int)((idx / 9) % cin);
+  const int o = (int)(idx / (9LL * cin));
+  const int cp = c < cu ? c : cu_p + (c - cu);
+  const int64_t stride = (int64_t)cout_p * 9 * cin_p;
+  const int64_t src = ((int64_t)o * 9 + tap) * cin_p + cp;
+  float s = 0.f;
+  for (int k = 0; k < splits; ++k) s += part[k * stride + src];
+  dst[idx] = s;
+}
+
+int wgrad_bo(int cout_p) { return cout_p % 64 == 0 ? 64 : 32; }
+
+hipError_t launch_wgrad(int precision_x, int precision_g, int loader, const WgradArgs& a, int cout, int cin,
+                        int cu, float* dst, hipStream_t st) {
+  if (a.cout_p % 32 || a.cin_p % 32) return hipErrorInvalidValue;
+  const int bo = wgrad_bo(a.cout_p);
+  const int blocks = (a.cout_p / bo) * (a.cin_p / 32) * a.splits;
+  const bool bx16 = (a.W % 16 == 0);
+#define OMNISEG_WG(TX, TG, BXV, LD)                                                                   \
+  do {                                                                                              \
+    if (bo == 64) hipLaunchKernelGGL((k_wgrad3x3<TX, TG, BXV, 64, LD>), dim3(blocks), dim3(256), 0, st, a); \
+    else hipLaunchKernelGGL((k_wgrad3x3<TX, TG, BXV, 32, LD>), dim3(blocks), dim3(256), 0, st, a);          \
+  } while (0)
+#define OMNISEG_WG_LD(TX, TG, BXV)                                \
+  do {                                                            \
+    if (loader == LOAD_PLAIN) OMNISEG_WG(TX, TG, BXV, LOAD_PLAIN); \
+    else if (loader == LOAD_POOL) OMNISEG_WG(TX, TG, BXV, LOAD_POOL); \
+    else OMNISEG_WG(TX, TG, BXV, LOAD_UPCAT);                     \
+  } while (0)
+#define OMNISEG_WG_BX(TX, TG)             \
+  do {                                    \
+    if (bx16) OMNISEG_WG_LD(TX, TG, 16);  \
+    else OMNISEG_WG_LD(TX, TG, 8);        \
+  } while (0)
+  const bool xb = precision_x == OMNISEG_BF16, gb = precision_g == OMNISEG_BF16;
+  if (xb && gb) OMNISEG_WG_BX(uint16_t, uint16_t);
+  else if (!xb && gb) OMNISEG_WG_BX(float, uint16_t);
+  else if (xb && !gb) OMNISEG_WG_BX(uint16_t, float);
+  else OMNISEG_WG_BX(float, float);
+#undef OMNISEG_WG_BX
+#undef OMNISEG_WG_LD
+#undef OMNISEG_WG
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)cout * cin * 9;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.part, a.splits, cout,
+                     cin, cu, a.cu_p, a.cout_p, a.cin_p, dst);
+  return hipGetLastError();
+}
+
+// bias gradient: per-channel sum of dY over all pixels; split over pixel
+// ranges into part[split][c], then a fixed-order reduce into dst[c < cout]
+template <typename T>
+__global__ __launch_bounds__(256) void k_colsum(const T* dy, int64_t npix, int c_p, int splits, float* part) {
+  __shared__ float red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int lane4 = threadIdx.x >> 6;
+  const int split = blockIdx.y;
+  const int64_t per = (npix + splits - 1) / splits;
+  const int64_t p0 = split * per, p1 = min(npix, p0 + per);
+  float s = 0.f;
+  if (c < c_p)
+    for (int64_t p = p0 + lane4; p < p1; p += 4) s += ldf(dy + p * c_p + c);
+  red[lane4][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (lane4 == 0 && c < c_p)
+    part[(int64_t)split * c_p + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ void k_colsum_reduce(const float* part, int splits, int c_p, int cout, float* dst) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cout) return;
+  float s = 0.f;
+  for (int k = 0; k < splits; ++k) s += part[(int64_t)k * c_p + c];
+  dst[c] = s;
+}
+
+hipError_t launch_bias_grad(int precision, const void* dy, int64_t npix, int c_p, int cout, float* part,
+                            int splits, float* dst, hipStream_t st) {
+  dim3 grid((c_p + 63) / 64, splits);
+  if (precision == OMNISEG_BF16)
+    hipLaunchKernelGGL(k_colsum<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)dy, npix, c_p, splits, part);
+  else
+    hipLaunchKernelGGL(k_colsum<float>, grid, dim3(256), 0, st, (const float*)dy, npix, c_p, splits, part);
+  hipLaunchKernelGGL(k_colsum_reduce, dim3((cout + 255) / 256), dim3(256), 0, st, part, splits, c_p, cout, dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// BCE-with-logits loss over the valid entries, mean over their count; FP64
+// partial sums with a fixed-order final reduction
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bce_partial(const float* lg, const float* y, const uint8_t* valid,
+                                                     int64_t n, double* part_sum, int* part_cnt) {
+  __shared__ double rs[256];
+  __shared__ int rc[256];
+  double s = 0.0;
+  int c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    if (valid[i]) {
+      const double L = lg[i], t = y[i];
+      s += fmax(L, 0.0) - t * L + log1p(exp(-fabs(L)));
+      ++c;
+    }
+  }
+  rs[threadIdx.x] = s;
+  rc[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rs[threadIdx.x] += rs[threadIdx.x + w];
+      rc[threadIdx.x] += rc[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part_sum[blockIdx.x] = rs[0];
+    part_cnt[blockIdx.x] = rc[0];
+  }
+}
+
+__global__ void k_bce_final(const double* part_sum, const int* part_cnt, int nb, double* loss, int* count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    long long c = 0;
+    for (int i = 0; i < nb; ++i) {
+      s += part_sum[i];
+      c += part_cnt[i];
+    }
+    *loss = c > 0 ? s / (double)c : 0.0;
+    *count = (int)c;
+  }
+}
+
+__global__ void k_bce_grad(const float* lg, const float* y, const uint8_t* valid, int64_t n, const int* count,
+                           float* grad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int c = *count;
+  float g = 0.f;
+  if (valid[i] && c > 0) {
+    const float L = lg[i];
+    const float sig = 1.f / (1.f + expf(-L));
+    g = (sig - y[i]) / (float)c;
+  }
+  grad[i] = g;
+}
+
+hipError_t launch_bce(const float* lg, const float* y, const uint8_t* valid, int64_t n, double* part_sum,
+                      int* part_cnt, int nb, double* loss, int* count, float* grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_bce_partial, dim3(nb), dim3(256), 0, st, lg, y, valid, n, part_sum, part_cnt);
+  hipLaunchKernelGGL(k_bce_final, dim3(1), dim3(64), 0, st, part_sum, part_cnt, nb, loss, count);
+  if (grad)
+    hipLaunchKernelGGL(k_bce_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lg, y, valid, n, count,
+                       grad);
+  return hipGetLastError();
+}
+
+}  // namespace omniseg

@@ -55,6 +55,7 @@ struct ConvTraits<uint16_t> {
 struct ConvArgs {
   const void* x0;
   const void* x1;
+  const void* aux;  // EPI_RES_MASK: the activation whose sign gates the output
   void* y;
   const void* w;
   const float* bias;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 #pragma unroll
   for (int fn = 0; fn < FN; ++fn) {
     const int n = n0 + wn * NW + fn * 16 + l16;
-    const float bias = a.bias[n];
+    const float bias = (EPI == EPI_RELU || EPI == EPI_RES_RELU) ? a.bias[n] : 0.f;
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm) {
 #pragma unroll
@@ -217,9 +218,18 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
         const int m = wm * MW + fm * 16 + (lane >> 4) * 4 + r;
         const int y = y0 + m / BX, x = x0 + m % BX;
         const int64_t o = (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + n;
-        float v = acc[fm][fn][r] + bias;
-        if (EPI == EPI_RES_RELU) v += load_scalar(res + o);
-        store_scalar(out + o, fmaxf(v, 0.f));
+        if (EPI == EPI_NONE) {
+          store_scalar(out + o, acc[fm][fn][r]);
+        } else if (EPI == EPI_RES_MASK) {
+          // gradient through "ReLU(conv(A) + A)" back to A's pre-activation:
+          // (acc + g) where the recomputed A is positive, else 0
+          const float v = acc[fm][fn][r] + load_scalar(res + o);
+          store_scalar(out + o, load_scalar((const T*)a.aux + o) > 0.f ? v : 0.f);
+        } else {
+          float v = acc[fm][fn][r] + bias;
+          if (EPI == EPI_RES_RELU) v += load_scalar(res + o);
+          store_scalar(out + o, fmaxf(v, 0.f));
+        }
       }
     }
   }
@@ -227,13 +237,14 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 
 template <typename T, int BY, int BX, int BN, int LOADER, int EPI>
 static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
-                                int chunk_base, const void* x0, const void* x1, void* y,
-                                hipStream_t st) {
+                                int chunk_base, const void* x0, const void* x1, const void* aux,
+                                void* y, hipStream_t st) {
   constexpr int WN = (BN >= 64) ? 2 : 1;
   constexpr int WM = 4 / WN;
   ConvArgs a;
   a.x0 = x0;
   a.x1 = x1;
+  a.aux = aux;
   a.y = y;
   a.w = L.w;
   a.bias = L.b;
@@ -255,43 +266,45 @@ static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, con
 
 template <typename T, int BY, int BX, int LOADER, int EPI>
 static hipError_t launch_conv_bn(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
-                                 int chunk_base, const void* x0, const void* x1, void* y,
-                                 hipStream_t st) {
+                                 int chunk_base, const void* x0, const void* x1, const void* aux,
+                                 void* y, hipStream_t st) {
   if (L.cout_p % 64 == 0)
-    return launch_conv_t<T, BY, BX, 64, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
-  return launch_conv_t<T, BY, BX, 32, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+    return launch_conv_t<T, BY, BX, 64, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+  return launch_conv_t<T, BY, BX, 32, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
 }
 
 template <typename T, int LOADER, int EPI>
 static hipError_t launch_conv_sp(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
-                                 int chunk_base, const void* x0, const void* x1, void* y,
-                                 hipStream_t st) {
+                                 int chunk_base, const void* x0, const void* x1, const void* aux,
+                                 void* y, hipStream_t st) {
   if (W % 16 == 0 && H % 8 == 0)
-    return launch_conv_bn<T, 8, 16, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
-  return launch_conv_bn<T, 8, 8, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+    return launch_conv_bn<T, 8, 16, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+  return launch_conv_bn<T, 8, 8, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
 }
 
 template <typename T>
 static hipError_t launch_conv_mode(int loader, int epi, const ConvLayer& L, int H, int W, int batch,
                                    const int32_t* count, int chunk_base, const void* x0,
-                                   const void* x1, void* y, hipStream_t st) {
-  if (loader == LOAD_PLAIN && epi == EPI_RES_RELU)
-    return launch_conv_sp<T, LOAD_PLAIN, EPI_RES_RELU>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
-  if (loader == LOAD_POOL && epi == EPI_RELU)
-    return launch_conv_sp<T, LOAD_POOL, EPI_RELU>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
-  if (loader == LOAD_UPCAT && epi == EPI_RELU)
-    return launch_conv_sp<T, LOAD_UPCAT, EPI_RELU>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
-  if (loader == LOAD_PLAIN && epi == EPI_RELU)
-    return launch_conv_sp<T, LOAD_PLAIN, EPI_RELU>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+                                   const void* x1, const void* aux, void* y, hipStream_t st) {
+#define OMNISEG_CONV_CASE(LD, EP)                                                                  \
+  if (loader == LD && epi == EP)                                                                  \
+    return launch_conv_sp<T, LD, EP>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+  OMNISEG_CONV_CASE(LOAD_PLAIN, EPI_RES_RELU)
+  OMNISEG_CONV_CASE(LOAD_POOL, EPI_RELU)
+  OMNISEG_CONV_CASE(LOAD_UPCAT, EPI_RELU)
+  OMNISEG_CONV_CASE(LOAD_PLAIN, EPI_RELU)
+  OMNISEG_CONV_CASE(LOAD_PLAIN, EPI_NONE)
+  OMNISEG_CONV_CASE(LOAD_PLAIN, EPI_RES_MASK)
+#undef OMNISEG_CONV_CASE
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L, int H, int W,
                           int batch, const int32_t* count, int chunk_base, const void* x0,
-                          const void* x1, void* y, hipStream_t st) {
+                          const void* x1, void* y, hipStream_t st, const void* aux) {
   if (precision == OMNISEG_BF16)
-    return launch_conv_mode<uint16_t>(loader, epi, L, H, W, batch, count, chunk_base, x0, x1, y, st);
-  return launch_conv_mode<float>(loader, epi, L, H, W, batch, count, chunk_base, x0, x1, y, st);
+    return launch_conv_mode<uint16_t>(loader, epi, L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+  return launch_conv_mode<float>(loader, epi, L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
 }
 
 // ---------------------------------------------------------------------------

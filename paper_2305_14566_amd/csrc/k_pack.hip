@@ -23,6 +23,34 @@ __device__ __forceinline__ float cvt<float>(float v) { return v; }
 template <>
 __device__ __forceinline__ uint16_t cvt<uint16_t>(float v) { return f2bf_rne(v); }
 
+// The data gradient of Y = conv(X, W) is a 3x3 conv of dY with
+// W'[c][o][i][j] = W[o][c][2 - i][2 - j]; its input channels are the forward
+// outputs (plain padding) and its outputs the forward inputs (concat padding).
+template <typename T, int KC>
+__global__ void k_pack_conv_t(const float* __restrict__ canon, char* packed, PackConv p) {
+  const int64_t total = (int64_t)p.cout_p * 9 * p.cin_p;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  // i enumerates [chunk of o][tap'][c'][kk]
+  const int kk = (int)(i % KC);
+  int64_t r = i / KC;
+  const int cp = (int)(r % p.cin_p);
+  r /= p.cin_p;
+  const int tap = (int)(r % 9);
+  const int chunk = (int)(r / 9);
+  const int o = chunk * KC + kk;
+  int c = -1;
+  if (cp < p.cu_p) {
+    if (cp < p.cu) c = cp;
+  } else {
+    const int ce = p.cin - p.cu;
+    if (cp - p.cu_p < ce) c = p.cu + (cp - p.cu_p);
+  }
+  float v = 0.f;
+  if (o < p.cout && c >= 0) v = canon[p.src + ((int64_t)o * p.cin + c) * 9 + (8 - tap)];
+  reinterpret_cast<T*>(packed + p.dst)[i] = cvt<T>(v);
+}
+
 template <typename T, int KC>
 __global__ void k_pack_conv(const float* __restrict__ canon, char* packed, PackConv p) {
   const int64_t total = (int64_t)p.cin_p * 9 * p.cout_p;
@@ -47,7 +75,7 @@ __global__ void k_pack_conv(const float* __restrict__ canon, char* packed, PackC
     if (n < p.cout && c >= 0) v = canon[p.src + ((int64_t)n * p.cin + c) * 9 + tap];
     reinterpret_cast<T*>(packed + p.dst)[i] = cvt<T>(v);
   }
-  if (i < p.cout_p) {
+  if (i < p.cout_p && p.dst_b >= 0) {
     reinterpret_cast<float*>(packed + p.dst_b)[i] = (i < p.cout) ? canon[p.src_b + i] : 0.f;
   }
 }
@@ -56,6 +84,13 @@ hipError_t launch_pack_conv(int precision, const float* canon, void* packed, con
                             hipStream_t st) {
   const int64_t total = std::max<int64_t>((int64_t)p.cin_p * 9 * p.cout_p, p.cout_p);
   dim3 grid((unsigned)((total + 255) / 256));
+  if (p.transpose) {
+    if (precision == OMNISEG_BF16)
+      hipLaunchKernelGGL((k_pack_conv_t<uint16_t, 32>), grid, dim3(256), 0, st, canon, (char*)packed, p);
+    else
+      hipLaunchKernelGGL((k_pack_conv_t<float, 16>), grid, dim3(256), 0, st, canon, (char*)packed, p);
+    return hipGetLastError();
+  }
   if (precision == OMNISEG_BF16)
     hipLaunchKernelGGL((k_pack_conv<uint16_t, 32>), grid, dim3(256), 0, st, canon, (char*)packed, p);
   else

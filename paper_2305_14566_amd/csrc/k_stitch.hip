@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
     }
   }
   const float n = sum + comp;
-  bool m = (den > 0) && (n > 0.f);
+  bool m = (den > 0) && (a.coverage || n > 0.f);
   if (a.fg) m = m && a.fg[(int64_t)(y >> a.fg_shift) * a.Wc + (x >> a.fg_shift)];
   a.mask[(int64_t)y * a.mask_pitch + x] = m ? 1 : 0;
   if (a.logit) a.logit[(int64_t)y * a.logit_pitch + x] = den > 0 ? n / (float)den : 0.f;

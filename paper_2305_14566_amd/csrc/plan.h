@@ -1,0 +1,91 @@
+// Plan object and host-side helpers shared by the library's C-ABI sources.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace omniseg {
+
+// Records the error text of the calling thread and returns `code`.
+int32_t fail(int32_t code, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::omniseg::fail(OMNISEG_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct ConvDesc {
+  int64_t canon_w, canon_b;
+  int cin, cout, cu;
+  int cin_p, cout_p, cu_p;
+  int64_t pk_w, pk_b;
+  int64_t pk_wt;  // data-gradient (transposed, flipped) weights, or -1
+};
+
+inline int elem_size(int precision) { return precision == OMNISEG_BF16 ? 2 : 4; }
+
+}  // namespace omniseg
+
+struct omniseg_plan {
+  omniseg_config cfg;
+  int L = 0;
+  int C[8] = {0};
+  int Cp[8] = {0};
+  int P = 0;
+  int G = 0;
+  int64_t n_canon = 0;
+  omniseg::ConvDesc enc_a[8], enc_b[8], dec_a[8], dec_b[8];
+  int64_t canon_first_w = 0, canon_first_b = 0, pk_first_w = 0, pk_first_b = 0;
+  int64_t canon_pre_w = -1, canon_pre_b = -1, pk_pre_w = 0, pk_pre_b = 0;
+  int64_t canon_ctrl_w = 0, canon_ctrl_b = 0, pk_ctrl_w = 0, pk_ctrl_b = 0;
+  int64_t packed_bytes = 0;
+  mutable std::vector<omniseg::SlideDev> slide_tab;  // host staging of the device slide table
+  mutable std::vector<int32_t> host_tab;             // host staging of tile lists and grids
+  // per-launch profiling (off by default)
+  bool profiling = false;
+  mutable std::vector<hipEvent_t> events;
+  mutable std::vector<omniseg_launch_record> recs;
+  ~omniseg_plan() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
+};
+
+namespace omniseg {
+
+// Records a pair of events around each launch when profiling is on.
+struct Prof {
+  const omniseg_plan* p;
+  hipStream_t st;
+  size_t next = 0;
+  hipError_t begin() {
+    if (!p->profiling) return hipSuccess;
+    while (p->events.size() < 2 * (next + 1)) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      p->events.push_back(e);
+    }
+    return hipEventRecord(p->events[2 * next], st);
+  }
+  hipError_t end(int stage, int level, int tiles, double flops, double bytes) {
+    if (!p->profiling) return hipSuccess;
+    hipError_t r = hipEventRecord(p->events[2 * next + 1], st);
+    omniseg_launch_record rec;
+    rec.stage = stage;
+    rec.level = level;
+    rec.tiles = tiles;
+    rec.precision = p->cfg.precision;
+    rec.flops = flops;
+    rec.bytes = bytes;
+    rec.ms = 0.0;
+    p->recs.push_back(rec);
+    ++next;
+    return r;
+  }
+};
+
+}  // namespace omniseg

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libomniseg.so")
 
 FP32, BF16 = 0, 1
 FLAG_EMIT_LOGITS = 1
+FLAG_TRAINING = 2
 (REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
  REGION_TILE_INDEX, REGION_TILE_LOGITS) = range(7)
 ABI_VERSION = 1
@@ -66,6 +67,10 @@ class LaunchRecord(ctypes.Structure):
 STAGE_NAMES = ("prep", "first_conv", "enc_a", "enc_b", "dec_a", "dec_b", "gap_ctrl", "head", "stitch")
 
 
+class Tile(ctypes.Structure):
+    _fields_ = [("scale", ctypes.c_int32), ("jy", ctypes.c_int32), ("jx", ctypes.c_int32)]
+
+
 class Output(ctypes.Structure):
     _fields_ = [("mask", ctypes.c_void_p), ("logit", ctypes.c_void_p),
                 ("mask_pitch", ctypes.c_int64), ("logit_pitch", ctypes.c_int64)]
@@ -88,6 +93,11 @@ def _declare(lib):
         "omniseg_stitch_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
         "omniseg_stitch_tiles": (i32, [i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, i64, vp, i64, vp]),
         "omniseg_set_profiling": (i32, [vp, i32]),
+        "omniseg_plane_offsets": (i32, [vp, P(Slide), P(Pair), i32, P(i64)]),
+        "omniseg_train_workspace_bytes": (i32, [vp, P(Slide), P(Tile), i32, P(Pair), i32, P(i64)]),
+        "omniseg_train_forward": (i32, [vp, vp, P(Slide), P(Tile), i32, P(Pair), i32, vp, vp, vp, i64, vp]),
+        "omniseg_backward": (i32, [vp, vp, P(Slide), P(Tile), i32, P(Pair), i32, vp, vp, vp, i64, vp]),
+        "omniseg_bce_loss": (i32, [vp, vp, vp, i64, vp, vp, vp, i64, vp]),
         "omniseg_read_profile": (i32, [vp, P(LaunchRecord), i32, P(i32)]),
     }
     for name, (res, args) in sig.items():
@@ -137,7 +147,7 @@ class Plan:
 
     def __init__(self, base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
                  stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False,
-                 precision=FP32, emit_logits=False, batch_tiles=0):
+                 precision=FP32, emit_logits=False, batch_tiles=0, training=False):
         c = Config()
         c.abi_version = ABI_VERSION
         c.base_channels = base
@@ -153,7 +163,7 @@ class Plan:
         c.fg_threshold = fg_threshold
         c.mask_and_fg = int(mask_and_fg)
         c.precision = precision
-        c.flags = FLAG_EMIT_LOGITS if emit_logits else 0
+        c.flags = (FLAG_EMIT_LOGITS if emit_logits else 0) | (FLAG_TRAINING if training else 0)
         c.batch_tiles = batch_tiles
         self.cfg = c
         self.scales = tuple(scales)
@@ -231,6 +241,49 @@ class Plan:
                                               ctypes.byref(off), ctypes.byref(nb)))
         return off.value, nb.value
 
+    # ---- training -------------------------------------------------------------
+
+    def _train_arrays(self, slide, tiles, pairs):
+        sl, pr = self._arrays([slide], pairs)
+        tl = (Tile * len(tiles))()
+        for i, (si, jy, jx) in enumerate(tiles):
+            tl[i].scale = si
+            tl[i].jy = jy
+            tl[i].jx = jx
+        return sl, tl, pr
+
+    def plane_offsets(self, slide, pairs):
+        sl, pr = self._arrays([slide], pairs)
+        off = (ctypes.c_int64 * (len(pairs) + 1))()
+        _check(lib().omniseg_plane_offsets(self._h, sl, pr, len(pairs), off))
+        return list(off)
+
+    def train_workspace_bytes(self, slide, tiles, pairs):
+        sl, tl, pr = self._train_arrays(slide, tiles, pairs)
+        n = ctypes.c_int64()
+        _check(lib().omniseg_train_workspace_bytes(self._h, sl, tl, len(tiles), pr, len(pairs), ctypes.byref(n)))
+        return n.value
+
+    def train_forward(self, slide, tiles, pairs, packed, workspace, stream=None):
+        """Forward over a tile batch; returns (flat logits, flat coverage)."""
+        sl, tl, pr = self._train_arrays(slide, tiles, pairs)
+        total = self.plane_offsets(slide, pairs)[-1]
+        logit = torch.empty(total, dtype=torch.float32, device=slide.device)
+        covered = torch.empty(total, dtype=torch.uint8, device=slide.device)
+        _check(lib().omniseg_train_forward(self._h, _ptr(packed), sl, tl, len(tiles), pr, len(pairs), _ptr(logit),
+                                           _ptr(covered), _ptr(workspace), workspace.numel(), _stream(stream)))
+        return logit, covered
+
+    def backward(self, slide, tiles, pairs, packed, workspace, grad_logit, stream=None):
+        """dLoss/dweights (canonical FP32 order) after train_forward."""
+        sl, tl, pr = self._train_arrays(slide, tiles, pairs)
+        if grad_logit.dtype != torch.float32 or not grad_logit.is_contiguous():
+            raise ValueError("grad_logit must be contiguous float32")
+        gw = torch.empty(self.weight_count, dtype=torch.float32, device=slide.device)
+        _check(lib().omniseg_backward(self._h, _ptr(packed), sl, tl, len(tiles), pr, len(pairs), _ptr(grad_logit),
+                                      _ptr(gw), _ptr(workspace), workspace.numel(), _stream(stream)))
+        return gw
+
     def alloc_outputs(self, slides, pairs):
         masks, logits = [], []
         for s in slides:
@@ -285,3 +338,52 @@ def stitch_tiles(tile, stride, height, width, tile_logits, tile_yx, emit_logits=
                                   logit.stride(0) if logit is not None else 0, _ptr(ws), ws.numel(),
                                   _stream(stream)))
     return mask, logit
+
+
+def bce_loss(logit, target, valid, with_grad=True, stream=None):
+    """Mean BCE-with-logits over valid entries; returns (loss float64 tensor, grad or None)."""
+    dev = logit.device
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    grad = torch.empty_like(logit) if with_grad else None
+    ws = torch.empty(16384, dtype=torch.uint8, device=dev)
+    _check(lib().omniseg_bce_loss(_ptr(logit), _ptr(target), _ptr(valid), logit.numel(), _ptr(loss), _ptr(grad),
+                                  _ptr(ws), ws.numel(), _stream(stream)))
+    return loss, grad
+
+
+class OmniSegFn(torch.autograd.Function):
+    """Differentiable stitched logits of a tile batch w.r.t. the canonical weights.
+
+    forward(weights, plan, slide, tiles, pairs) -> (flat logits, flat coverage);
+    backward runs the library's hand-written reverse pass.
+    """
+
+    @staticmethod
+    def forward(ctx, weights, plan, slide, tiles, pairs):
+        packed = plan.pack(weights.detach().contiguous())
+        ws = torch.empty(plan.train_workspace_bytes(slide, tiles, pairs), dtype=torch.uint8, device=slide.device)
+        logit, covered = plan.train_forward(slide, tiles, pairs, packed, ws)
+        ctx.state = (plan, slide, tiles, pairs, packed, ws)
+        ctx.mark_non_differentiable(covered)
+        return logit, covered
+
+    @staticmethod
+    def backward(ctx, grad_logit, grad_covered):
+        plan, slide, tiles, pairs, packed, ws = ctx.state
+        gw = plan.backward(slide, tiles, pairs, packed, ws, grad_logit.contiguous().float())
+        return gw, None, None, None, None
+
+
+class BCELossFn(torch.autograd.Function):
+    """Mean BCE-with-logits over covered pixels (library kernel)."""
+
+    @staticmethod
+    def forward(ctx, logit, target, valid):
+        loss, grad = bce_loss(logit.detach().contiguous(), target.contiguous(), valid.contiguous())
+        ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (grad,) = ctx.saved_tensors
+        return grad * grad_out.to(grad.dtype), None, None

@@ -224,3 +224,53 @@ def test_stitch_rejects_before_any_hip_call():
     # mask pitch
     assert lib.omniseg_stitch_tiles(64, 32, 100, 90, FAKE, FAKE, 3, FAKE, 89, 0, 0, FAKE, 256, None) == 1
     del args
+
+
+def _tiles(ts):
+    arr = (om.Tile * len(ts))()
+    for i, (s, y, x) in enumerate(ts):
+        arr[i].scale, arr[i].jy, arr[i].jx = s, y, x
+    return arr
+
+
+@pytest.mark.parametrize("case", ["no_flag", "dup_tile", "tile_out", "too_many", "scale_out", "ws_small",
+                                  "null_grad", "one_level"])
+def test_training_entry_points_reject_before_any_hip_call(case):
+    lib = om.lib()
+    p = om.Plan(base=4, levels=1 if case == "one_level" else 3, head_out=2, n_classes=6, scales=(0, 1), tile=32,
+                stride=16, training=(case != "no_flag"))
+    sl = _slides([(64, 64)])
+    pr = _pairs([(0, 0), (3, 1)])
+    tl = [(0, 0, 0), (1, 0, 0)]
+    if case == "dup_tile":
+        tl = [(0, 1, 1), (0, 1, 1)]
+    elif case == "tile_out":
+        tl = [(0, 3, 0)]
+    elif case == "too_many":
+        tl = [(0, 0, 0)] * 257
+    elif case == "scale_out":
+        tl = [(2, 0, 0)]
+    t = _tiles(tl)
+    n = ctypes.c_int64()
+    st = lib.omniseg_train_workspace_bytes(p._h, sl, t, len(tl), pr, 2, ctypes.byref(n))
+    if case in ("ws_small", "null_grad"):
+        assert st == 0 and n.value > 0
+        if case == "ws_small":
+            assert lib.omniseg_train_forward(p._h, FAKE, sl, t, len(tl), pr, 2, FAKE, FAKE, FAKE, 4096, None) == 3
+        else:
+            assert lib.omniseg_backward(p._h, FAKE, sl, t, len(tl), pr, 2, FAKE, 0, FAKE, n.value, None) == 1
+        return
+    assert st in (1, 2), st
+    assert lib.omniseg_train_forward(p._h, FAKE, sl, t, len(tl), pr, 2, FAKE, FAKE, FAKE, 1 << 40, None) == st
+
+
+def test_plane_offsets_and_bce_validation():
+    lib = om.lib()
+    p = om.Plan(base=4, levels=3, head_out=2, n_classes=6, scales=(0, 1), tile=32, stride=16, training=True)
+    sl = _slides([(65, 40)])
+    pr = _pairs([(0, 0), (3, 1), (5, 0)])
+    off = (ctypes.c_int64 * 4)()
+    assert lib.omniseg_plane_offsets(p._h, sl, pr, 3, off) == 0
+    assert list(off) == [0, 65 * 40, 65 * 40 + 33 * 20, 2 * 65 * 40 + 33 * 20]
+    assert lib.omniseg_bce_loss(FAKE, FAKE, FAKE, 0, FAKE, 0, FAKE, 16384, None) == 1
+    assert lib.omniseg_bce_loss(FAKE, FAKE, FAKE, 10, FAKE, 0, FAKE, 100, None) == 3
