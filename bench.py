@@ -120,6 +120,56 @@ def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles
     return dict(ms=ms, wall_ms=wall * 1e3 / steps, records=records, kept=kept, masks=masks)
 
 
+def train_leg(om, torch, steps, warmup, batch=32):
+    """Training step on the 2048^2 region: 32 random tiles of 40x/20x (256^2,
+    stride 128), 6 classes x 2 scales, BF16 backbone: forward, stitch, BCE,
+    hand-written backward and a plain SGD update of the canonical weights."""
+    import synth
+
+    dev = torch.device("cuda:0")
+    rgb, gt = synth.strip_slide(3, 2048, 2048, fg_frac=0.30)
+    base, L, C, scales = 64, 5, 6, (0, 1)
+    flat = synth.he_normal_weights(13, base, L, C, len(scales), 2)
+    pairs = [(c, si) for si in range(len(scales)) for c in range(C)]
+    plan = om.Plan(base=base, levels=L, head_out=2, n_classes=C, scales=scales, tile=256, stride=128,
+                   precision=om.BF16, training=True)
+    slide = torch.from_numpy(rgb).to(dev)
+    y = torch.from_numpy(synth.soft_targets(gt, scales, pairs)).to(dev)
+    w = torch.from_numpy(flat).to(dev)
+    grid = [(si, jy, jx) for si, k in enumerate(scales)
+            for jy in range(-(-(-(-2048 // (1 << k)) - 256) // 128) + 1)
+            for jx in range(-(-(-(-2048 // (1 << k)) - 256) // 128) + 1)]
+    rng = np.random.default_rng(14)
+
+    def step():
+        idx = rng.choice(len(grid), size=batch, replace=False)
+        tiles = [grid[i] for i in sorted(idx)]
+        wt = w.detach().requires_grad_(True)
+        logit, covered = om.OmniSegFn.apply(wt, plan, slide, tiles, pairs)
+        loss = om.BCELossFn.apply(logit, y, covered)
+        loss.backward()
+        w.sub_(1e-3 * wt.grad)
+        return loss
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    losses = [step() for _ in range(steps)]
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fwd_flops = 18.0 * base * base * 256 * 256 * (3.0 / base + 1 + 5.5 * (L - 1)) * batch
+    return {"ms_per_step": ms, "tiles_per_step": batch, "grid_tiles": len(grid), "steps": steps,
+            "dtype": "bf16", "tiles_per_s": batch / (ms * 1e-3),
+            "algorithmic_tflop_per_step": 3 * fwd_flops / 1e12,
+            "achieved_tflops": 3 * fwd_flops / (ms * 1e-3) / 1e12,
+            "loss_first_last": [float(losses[0]), float(losses[-1])],
+            "workload": "2048x2048 synthetic region, 32 random 256^2 tiles of 40x/20x per step, 6 classes x "
+                        "2 scales, base-64 5-level U-Net, BCE vs soft masks, backward + SGD update"}
+
+
 def cpu_baseline(rgb, flat, pairs, kept, seconds):
     """The FP64 oracle on a bounded sample of the same workload, extrapolated."""
     from oracle import omniseg_oracle as O
@@ -171,6 +221,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--train-steps", type=int, default=3, help="training-step leg (0 = skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -226,6 +277,9 @@ def main():
         result["speedup_bf16_vs_fp32"] = fp["ms"] / bf["ms"]
         result["bf16_vs_fp32_masks"] = {"dice_min": min(dices), "dice_mean": float(np.mean(dices)),
                                         "disagreement_max": max(dis)}
+    if args.train_steps > 0:
+        result["train_step"] = train_leg(om, torch, args.train_steps, 1)
+        print(f"# train: {result['train_step']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(rgb, flat, pairs, bf["kept"], args.cpu_seconds)
     print(json.dumps(result))

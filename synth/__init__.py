@@ -11,6 +11,7 @@ from .slides import (
     strip_slide,
     tiny_slide,
     batch_slide_specs,
+    soft_targets,
     CLASS_NAMES,
 )
 from .weights import weight_layout, he_normal_weights, head_param_count
@@ -20,6 +21,7 @@ __all__ = [
     "strip_slide",
     "tiny_slide",
     "batch_slide_specs",
+    "soft_targets",
     "CLASS_NAMES",
     "weight_layout",
     "he_normal_weights",

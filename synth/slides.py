@@ -223,3 +223,21 @@ def batch_slide_specs(seed=99, n=16, h_range=(2000, 8000), w_range=(4000, 40000)
         fg = float(rng.uniform(*fg_range))
         specs.append(dict(seed=100 + i, H=H, W=W, fg_frac=fg))
     return specs
+
+
+def soft_targets(gt, scale_log2, pairs):
+    """Per-pair training targets, concatenated in pair order (float32).
+
+    Target of pair (class c, scale slot si) at scale k = scale_log2[si]: the
+    mean of the 40x ground-truth mask of class c over each 2^k x 2^k block,
+    blocks reaching past the slide counting as background.
+    """
+    out = []
+    H, W = gt.shape[1:]
+    for (c, si) in pairs:
+        f = 1 << scale_log2[si]
+        Hk, Wk = -(-H // f), -(-W // f)
+        m = np.zeros((Hk * f, Wk * f), np.float64)
+        m[:H, :W] = gt[c]
+        out.append(m.reshape(Hk, f, Wk, f).mean(axis=(1, 3)).ravel())
+    return np.concatenate(out).astype(np.float32)

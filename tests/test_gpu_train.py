@@ -26,7 +26,7 @@ def _fd_case():
 
 
 def _targets(gt, cfg, pairs):
-    return np.concatenate([O.soft_target(gt[c], cfg["scales"][si]).ravel() for (c, si) in pairs]).astype(np.float32)
+    return synth.soft_targets(gt, cfg["scales"], pairs)
 
 
 def _gpu_step(rgb, gt, cfg, flat, pairs, batch, precision):
