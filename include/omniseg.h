@@ -54,6 +54,8 @@ extern "C" {
 /* flags */
 #define OMNISEG_FLAG_EMIT_LOGITS 1 /* also write the stitched FP32 logit map */
 #define OMNISEG_FLAG_TRAINING 2    /* also pack the data-gradient weights (training entry points) */
+#define OMNISEG_FLAG_GRAPH 4       /* omniseg_segment_slide: capture the work after the tile list
+                                      in a HIP graph, replayed on calls with identical arguments */
 
 /* limits */
 #define OMNISEG_MAX_SCALES 4

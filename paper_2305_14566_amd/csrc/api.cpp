@@ -91,7 +91,7 @@ int32_t validate_config(const omniseg_config* c) {
     return fail(OMNISEG_ERR_ARG, "fg_threshold %d outside [1, 255]", c->fg_threshold);
   if (c->precision != OMNISEG_FP32 && c->precision != OMNISEG_BF16)
     return fail(OMNISEG_ERR_UNSUPPORTED, "unknown precision %d", c->precision);
-  if (c->flags & ~(OMNISEG_FLAG_EMIT_LOGITS | OMNISEG_FLAG_TRAINING))
+  if (c->flags & ~(OMNISEG_FLAG_EMIT_LOGITS | OMNISEG_FLAG_TRAINING | OMNISEG_FLAG_GRAPH))
     return fail(OMNISEG_ERR_ARG, "unknown flags 0x%x", c->flags);
   if (c->batch_tiles < 0 || c->batch_tiles > 65536)
     return fail(OMNISEG_ERR_ARG, "batch_tiles %d outside [0, 65536]", c->batch_tiles);
@@ -526,143 +526,188 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   if (n_kept < 0 || n_kept > lay.total_tiles)
     return fail(OMNISEG_ERR_HIP, "kept-tile count %d outside [0, %d]", n_kept, lay.total_tiles);
 
-  // 3. backbone, controller and head, batch by batch
-  void* E[8];
-  for (int l = 0; l < plan->L; ++l) E[l] = ws + lay.off_E[l];
-  void* A = ws + lay.off_A;
-  float* g = reinterpret_cast<float*>(ws + lay.off_g);
-  float* theta = reinterpret_cast<float*>(ws + lay.off_theta);
-  float* logits = reinterpret_cast<float*>(ws + lay.off_logits);
-  auto layer = [&](const ConvDesc& d) {
-    ConvLayer L;
-    L.cin_p = d.cin_p;
-    L.cu_p = d.cu_p;
-    L.cout_p = d.cout_p;
-    L.w = pk + d.pk_w;
-    L.b = reinterpret_cast<const float*>(pk + d.pk_b);
-    return L;
-  };
-  const int es = elem_size(prec);
-  // algorithmic work of one 3x3 conv launch over `nt` tiles at h x h
-  auto conv_flops = [&](const ConvDesc& d, int h, int nt) { return 2.0 * 9 * d.cin * d.cout * (double)h * h * nt; };
-  auto conv_bytes = [&](const ConvDesc& d, int h, int nt, double in_px_factor, bool res) {
-    const double px = (double)h * h * nt;
-    return px * in_px_factor * d.cin * es + px * d.cout * es * (res ? 2 : 1) + 9.0 * d.cin * d.cout * es;
-  };
-  const int B = lay.batch;
-  FirstConvArgs fa;
-  fa.list = list;
-  fa.count = count;
-  fa.T = T;
-  fa.s = s;
-  fa.w = reinterpret_cast<const float*>(pk + plan->pk_first_w);
-  fa.b = reinterpret_cast<const float*>(pk + plan->pk_first_b);
-  fa.c0 = plan->C[0];
-  fa.c0_p = plan->Cp[0];
-  fa.y = A;
-  fa.slides = tab_dev;
-  for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) fa.scale_k[si] = si < c.n_scales ? c.scale_log2[si] : 0;
-  const int L = plan->L;
-  for (int base = 0; base < n_kept; base += B) {
-    const int nb = std::min(B, n_kept - base);
-    fa.chunk_base = base;
-    fa.batch = nb;
-    HIP_TRY(prof.begin());
-    HIP_TRY(launch_first_conv(prec, fa, sm));
-    HIP_TRY(prof.end(OMNISEG_STAGE_FIRST_CONV, 0, nb, 2.0 * 27 * plan->C[0] * (double)T * T * nb,
-                     (double)T * T * nb * (3.0 + plan->C[0] * es)));
-    HIP_TRY(prof.begin());
-    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[0]), T, T, nb, count, base, A, nullptr, E[0], sm));
-    HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, 0, nb, conv_flops(plan->enc_b[0], T, nb), conv_bytes(plan->enc_b[0], T, nb, 1.0, true)));
-    for (int l = 1; l < L; ++l) {
-      const int tl = T >> l;
+  // 3-4. everything after the tile list: backbone batches, head, stitch.  With
+  // OMNISEG_FLAG_GRAPH this sequence is captured once per distinct argument set
+  // and replayed as one HIP graph.
+  auto enqueue = [&]() -> int32_t {
+    // 3. backbone, controller and head, batch by batch
+    void* E[8];
+    for (int l = 0; l < plan->L; ++l) E[l] = ws + lay.off_E[l];
+    void* A = ws + lay.off_A;
+    float* g = reinterpret_cast<float*>(ws + lay.off_g);
+    float* theta = reinterpret_cast<float*>(ws + lay.off_theta);
+    float* logits = reinterpret_cast<float*>(ws + lay.off_logits);
+    auto layer = [&](const ConvDesc& d) {
+      ConvLayer L;
+      L.cin_p = d.cin_p;
+      L.cu_p = d.cu_p;
+      L.cout_p = d.cout_p;
+      L.w = pk + d.pk_w;
+      L.b = reinterpret_cast<const float*>(pk + d.pk_b);
+      return L;
+    };
+    const int es = elem_size(prec);
+    // algorithmic work of one 3x3 conv launch over `nt` tiles at h x h
+    auto conv_flops = [&](const ConvDesc& d, int h, int nt) { return 2.0 * 9 * d.cin * d.cout * (double)h * h * nt; };
+    auto conv_bytes = [&](const ConvDesc& d, int h, int nt, double in_px_factor, bool res) {
+      const double px = (double)h * h * nt;
+      return px * in_px_factor * d.cin * es + px * d.cout * es * (res ? 2 : 1) + 9.0 * d.cin * d.cout * es;
+    };
+    const int B = lay.batch;
+    FirstConvArgs fa;
+    fa.list = list;
+    fa.count = count;
+    fa.T = T;
+    fa.s = s;
+    fa.w = reinterpret_cast<const float*>(pk + plan->pk_first_w);
+    fa.b = reinterpret_cast<const float*>(pk + plan->pk_first_b);
+    fa.c0 = plan->C[0];
+    fa.c0_p = plan->Cp[0];
+    fa.y = A;
+    fa.slides = tab_dev;
+    for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) fa.scale_k[si] = si < c.n_scales ? c.scale_log2[si] : 0;
+    const int L = plan->L;
+    for (int base = 0; base < n_kept; base += B) {
+      const int nb = std::min(B, n_kept - base);
+      fa.chunk_base = base;
+      fa.batch = nb;
       HIP_TRY(prof.begin());
-      HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count, base, E[l - 1], nullptr, A, sm));
-      HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nb, conv_flops(plan->enc_a[l], tl, nb), conv_bytes(plan->enc_a[l], tl, nb, 4.0, false)));
+      HIP_TRY(launch_first_conv(prec, fa, sm));
+      HIP_TRY(prof.end(OMNISEG_STAGE_FIRST_CONV, 0, nb, 2.0 * 27 * plan->C[0] * (double)T * T * nb,
+                       (double)T * T * nb * (3.0 + plan->C[0] * es)));
       HIP_TRY(prof.begin());
-      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm));
-      HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nb, conv_flops(plan->enc_b[l], tl, nb), conv_bytes(plan->enc_b[l], tl, nb, 1.0, true)));
-    }
-    const int tb = T >> (L - 1);
-    HIP_TRY(prof.begin());
-    HIP_TRY(launch_gap(prec, E[L - 1], nb, tb * tb, plan->Cp[L - 1], plan->G, count, base, g, sm));
-    HIP_TRY(launch_controller(g, nb, plan->G, reinterpret_cast<const float*>(pk + plan->pk_ctrl_w),
-                              reinterpret_cast<const float*>(pk + plan->pk_ctrl_b), plan->P, c.n_classes,
-                              c.n_scales, lay.slots, lay.max_slots, list, count, base, theta, sm));
-    HIP_TRY(prof.end(OMNISEG_STAGE_GAP_CTRL, L - 1, nb,
-                     (double)nb * ((double)plan->G * tb * tb + 2.0 * plan->P * plan->G * lay.max_slots),
-                     (double)nb * tb * tb * plan->G * es));
-    for (int l = L - 2; l >= 0; --l) {
-      const int tl = T >> l;
-      // decoder level l: Z = [up2(D_{l+1}) ; E_l]; D_{l+1} lives in E[l+1]'s buffer
+      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[0]), T, T, nb, count, base, A, nullptr, E[0], sm));
+      HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, 0, nb, conv_flops(plan->enc_b[0], T, nb), conv_bytes(plan->enc_b[0], T, nb, 1.0, true)));
+      for (int l = 1; l < L; ++l) {
+        const int tl = T >> l;
+        HIP_TRY(prof.begin());
+        HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count, base, E[l - 1], nullptr, A, sm));
+        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nb, conv_flops(plan->enc_a[l], tl, nb), conv_bytes(plan->enc_a[l], tl, nb, 4.0, false)));
+        HIP_TRY(prof.begin());
+        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm));
+        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nb, conv_flops(plan->enc_b[l], tl, nb), conv_bytes(plan->enc_b[l], tl, nb, 1.0, true)));
+      }
+      const int tb = T >> (L - 1);
       HIP_TRY(prof.begin());
-      HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1], E[l], A, sm));
-      HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nb, conv_flops(plan->dec_a[l], tl, nb), conv_bytes(plan->dec_a[l], tl, nb, 0.5, false)));
-      HIP_TRY(prof.begin());
-      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm));
-      HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nb, conv_flops(plan->dec_b[l], tl, nb), conv_bytes(plan->dec_b[l], tl, nb, 1.0, true)));
-    }
-    HIP_TRY(prof.begin());
-    HIP_TRY(launch_head(prec, E[0], nb, T, plan->C[0], plan->Cp[0],
-                        plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_w) : nullptr,
-                        plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_b) : nullptr,
-                        theta, plan->P, c.head_out, lay.slots, lay.max_slots, list, count, base, logits, sm));
-    {
-      const double px = (double)T * T * nb;
-      const double pre = plan->canon_pre_w >= 0 ? 2.0 * 8 * plan->C[0] : 0.0;
-      // slots per tile vary with the tile's scale; count the largest
-      const double head = lay.max_slots * (2.0 * 64 + 2.0 * 64 + 2.0 * 8 * c.head_out);
-      HIP_TRY(prof.end(OMNISEG_STAGE_HEAD, 0, nb, px * (pre + head), px * (plan->C[0] * es + 4.0 * lay.max_slots)));
-    }
-  }
-
-  // 4. stitch every (slide, pair)
-  std::vector<int32_t> idx_host;
-  if (plan->profiling) {
-    idx_host.resize(lay.total_tiles);
-    HIP_TRY(hipMemcpyAsync(idx_host.data(), index, sizeof(int32_t) * lay.total_tiles, hipMemcpyDeviceToHost, sm));
-    HIP_TRY(hipStreamSynchronize(sm));
-  }
-  for (int i = 0; i < n_slides; ++i) {
-    for (int p = 0; p < n_pairs; ++p) {
-      const int si = pairs[p].scale;
-      const ScaleGeom& gm = lay.geom[i][si];
-      const omniseg_output& o = outs[(int64_t)i * n_pairs + p];
-      const int gbase = lay.groups.base[i * c.n_scales + si];
-      StitchArgs sa;
-      sa.logits = logits;
-      sa.tile_stride = (int64_t)lay.max_slots * T * T;
-      sa.slot_off = (int64_t)lay.pair_slot[p] * T * T;
-      sa.index = index + gbase;
-      sa.ny = gm.ny;
-      sa.nx = gm.nx;
-      sa.T = T;
-      sa.s = s;
-      sa.Hk = gm.Hk;
-      sa.Wk = gm.Wk;
-      sa.mask = o.mask;
-      sa.mask_pitch = o.mask_pitch;
-      sa.logit = emit ? o.logit : nullptr;
-      sa.logit_pitch = o.logit_pitch;
-      sa.fg = c.mask_and_fg ? reinterpret_cast<const uint8_t*>(ws + lay.off_fg[i]) : nullptr;
-      sa.fg_shift = lay.kc - gm.k;
-      sa.Hc = lay.Hc[i];
-      sa.Wc = lay.Wc[i];
-      sa.coverage = 0;
-      double cover = 0.0;
-      if (plan->profiling) {
-        // every in-plane pixel of every kept tile is read exactly once
-        for (int jy = 0; jy < gm.ny; ++jy)
-          for (int jx = 0; jx < gm.nx; ++jx)
-            if (idx_host[gbase + jy * gm.nx + jx] >= 0)
-              cover += (double)std::min(T, gm.Hk - jy * s) * std::min(T, gm.Wk - jx * s);
+      HIP_TRY(launch_gap(prec, E[L - 1], nb, tb * tb, plan->Cp[L - 1], plan->G, count, base, g, sm));
+      HIP_TRY(launch_controller(g, nb, plan->G, reinterpret_cast<const float*>(pk + plan->pk_ctrl_w),
+                                reinterpret_cast<const float*>(pk + plan->pk_ctrl_b), plan->P, c.n_classes,
+                                c.n_scales, lay.slots, lay.max_slots, list, count, base, theta, sm));
+      HIP_TRY(prof.end(OMNISEG_STAGE_GAP_CTRL, L - 1, nb,
+                       (double)nb * ((double)plan->G * tb * tb + 2.0 * plan->P * plan->G * lay.max_slots),
+                       (double)nb * tb * tb * plan->G * es));
+      for (int l = L - 2; l >= 0; --l) {
+        const int tl = T >> l;
+        // decoder level l: Z = [up2(D_{l+1}) ; E_l]; D_{l+1} lives in E[l+1]'s buffer
+        HIP_TRY(prof.begin());
+        HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1], E[l], A, sm));
+        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nb, conv_flops(plan->dec_a[l], tl, nb), conv_bytes(plan->dec_a[l], tl, nb, 0.5, false)));
+        HIP_TRY(prof.begin());
+        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm));
+        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nb, conv_flops(plan->dec_b[l], tl, nb), conv_bytes(plan->dec_b[l], tl, nb, 1.0, true)));
       }
       HIP_TRY(prof.begin());
-      HIP_TRY(launch_stitch(sa, sm));
-      HIP_TRY(prof.end(OMNISEG_STAGE_STITCH, -1, 0, 0.0,
-                       4.0 * cover + (double)gm.Hk * gm.Wk * (1.0 + (emit ? 4.0 : 0.0))));
+      HIP_TRY(launch_head(prec, E[0], nb, T, plan->C[0], plan->Cp[0],
+                          plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_w) : nullptr,
+                          plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_b) : nullptr,
+                          theta, plan->P, c.head_out, lay.slots, lay.max_slots, list, count, base, logits, sm));
+      {
+        const double px = (double)T * T * nb;
+        const double pre = plan->canon_pre_w >= 0 ? 2.0 * 8 * plan->C[0] : 0.0;
+        // slots per tile vary with the tile's scale; count the largest
+        const double head = lay.max_slots * (2.0 * 64 + 2.0 * 64 + 2.0 * 8 * c.head_out);
+        HIP_TRY(prof.end(OMNISEG_STAGE_HEAD, 0, nb, px * (pre + head), px * (plan->C[0] * es + 4.0 * lay.max_slots)));
+      }
+    }
+
+    // 4. stitch every (slide, pair)
+    std::vector<int32_t> idx_host;
+    if (plan->profiling) {
+      idx_host.resize(lay.total_tiles);
+      HIP_TRY(hipMemcpyAsync(idx_host.data(), index, sizeof(int32_t) * lay.total_tiles, hipMemcpyDeviceToHost, sm));
+      HIP_TRY(hipStreamSynchronize(sm));
+    }
+    for (int i = 0; i < n_slides; ++i) {
+      for (int p = 0; p < n_pairs; ++p) {
+        const int si = pairs[p].scale;
+        const ScaleGeom& gm = lay.geom[i][si];
+        const omniseg_output& o = outs[(int64_t)i * n_pairs + p];
+        const int gbase = lay.groups.base[i * c.n_scales + si];
+        StitchArgs sa;
+        sa.logits = logits;
+        sa.tile_stride = (int64_t)lay.max_slots * T * T;
+        sa.slot_off = (int64_t)lay.pair_slot[p] * T * T;
+        sa.index = index + gbase;
+        sa.ny = gm.ny;
+        sa.nx = gm.nx;
+        sa.T = T;
+        sa.s = s;
+        sa.Hk = gm.Hk;
+        sa.Wk = gm.Wk;
+        sa.mask = o.mask;
+        sa.mask_pitch = o.mask_pitch;
+        sa.logit = emit ? o.logit : nullptr;
+        sa.logit_pitch = o.logit_pitch;
+        sa.fg = c.mask_and_fg ? reinterpret_cast<const uint8_t*>(ws + lay.off_fg[i]) : nullptr;
+        sa.fg_shift = lay.kc - gm.k;
+        sa.Hc = lay.Hc[i];
+        sa.Wc = lay.Wc[i];
+        sa.coverage = 0;
+        double cover = 0.0;
+        if (plan->profiling) {
+          // every in-plane pixel of every kept tile is read exactly once
+          for (int jy = 0; jy < gm.ny; ++jy)
+            for (int jx = 0; jx < gm.nx; ++jx)
+              if (idx_host[gbase + jy * gm.nx + jx] >= 0)
+                cover += (double)std::min(T, gm.Hk - jy * s) * std::min(T, gm.Wk - jx * s);
+        }
+        HIP_TRY(prof.begin());
+        HIP_TRY(launch_stitch(sa, sm));
+        HIP_TRY(prof.end(OMNISEG_STAGE_STITCH, -1, 0, 0.0,
+                         4.0 * cover + (double)gm.Hk * gm.Wk * (1.0 + (emit ? 4.0 : 0.0))));
+      }
+    }
+    return OMNISEG_OK;
+  };
+  const bool use_graph = (c.flags & OMNISEG_FLAG_GRAPH) && !plan->profiling;
+  if (!use_graph) return enqueue();
+  uint64_t key = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) key = (key ^ b[i]) * 1099511628211ull;
+  };
+  mix(&packed, sizeof(packed));
+  mix(&workspace, sizeof(workspace));
+  mix(&ws_bytes, sizeof(ws_bytes));
+  mix(&n_kept, sizeof(n_kept));
+  mix(slides, sizeof(omniseg_slide) * n_slides);
+  mix(pairs, sizeof(omniseg_pair) * n_pairs);
+  mix(outs, sizeof(omniseg_output) * (size_t)n_slides * n_pairs);
+  for (const auto& gc : plan->graphs) {
+    if (gc.key == key) {
+      HIP_TRY(hipGraphLaunch(gc.exec, sm));
+      return OMNISEG_OK;
     }
   }
+  HIP_TRY(hipStreamBeginCapture(sm, hipStreamCaptureModeThreadLocal));
+  const int32_t est = enqueue();
+  hipGraph_t graph = nullptr;
+  const hipError_t cap = hipStreamEndCapture(sm, &graph);
+  if (est != OMNISEG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return est;
+  }
+  if (cap != hipSuccess) return fail(OMNISEG_ERR_HIP, "stream capture failed: %s", hipGetErrorString(cap));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ins = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ins != hipSuccess) return fail(OMNISEG_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ins));
+  if (plan->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(plan->graphs.front().exec);
+    plan->graphs.erase(plan->graphs.begin());
+  }
+  plan->graphs.push_back({key, exec});
+  HIP_TRY(hipGraphLaunch(exec, sm));
   return OMNISEG_OK;
 }
 

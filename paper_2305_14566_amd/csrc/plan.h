@@ -49,8 +49,15 @@ struct omniseg_plan {
   bool profiling = false;
   mutable std::vector<hipEvent_t> events;
   mutable std::vector<omniseg_launch_record> recs;
+  // captured graphs of omniseg_segment_slide, keyed by a hash of the arguments
+  struct GraphEntry {
+    uint64_t key;
+    hipGraphExec_t exec;
+  };
+  mutable std::vector<GraphEntry> graphs;
   ~omniseg_plan() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (const GraphEntry& g : graphs) (void)hipGraphExecDestroy(g.exec);
   }
 };
 

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libomniseg.so")
 FP32, BF16 = 0, 1
 FLAG_EMIT_LOGITS = 1
 FLAG_TRAINING = 2
+FLAG_GRAPH = 4
 (REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
  REGION_TILE_INDEX, REGION_TILE_LOGITS) = range(7)
 ABI_VERSION = 1
@@ -147,7 +148,7 @@ class Plan:
 
     def __init__(self, base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
                  stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False,
-                 precision=FP32, emit_logits=False, batch_tiles=0, training=False):
+                 precision=FP32, emit_logits=False, batch_tiles=0, training=False, graph=False):
         c = Config()
         c.abi_version = ABI_VERSION
         c.base_channels = base
@@ -163,7 +164,8 @@ class Plan:
         c.fg_threshold = fg_threshold
         c.mask_and_fg = int(mask_and_fg)
         c.precision = precision
-        c.flags = (FLAG_EMIT_LOGITS if emit_logits else 0) | (FLAG_TRAINING if training else 0)
+        c.flags = ((FLAG_EMIT_LOGITS if emit_logits else 0) | (FLAG_TRAINING if training else 0)
+                   | (FLAG_GRAPH if graph else 0))
         c.batch_tiles = batch_tiles
         self.cfg = c
         self.scales = tuple(scales)

@@ -273,3 +273,31 @@ def test_wide_network_sampled_tiles(precision, tol):
                   f"(exact bf16 arithmetic {emu_vs_ref:.3e})")
             assert err_emu <= 5e-3, (li, err_emu)
             assert err <= max(tol, 1.25 * emu_vs_ref), (li, err)
+
+
+def test_graph_replay_matches_eager():
+    """With OMNISEG_FLAG_GRAPH the work after the tile list is captured once
+    and replayed; every replay must equal the eager result bit for bit."""
+    slides, cfg, flat, pairs = _prep_case()
+    for prec in (om.FP32, om.BF16):
+        _, _, m_eager, l_eager, _ = _run(cfg, slides, flat, pairs, prec, batch_tiles=16)
+        plan = om.Plan(base=cfg["base"], levels=cfg["levels"], head_out=cfg["head_out"],
+                       n_classes=cfg["n_classes"], scales=cfg["scales"], tile=cfg["tile"], stride=cfg["stride"],
+                       fg_filter=cfg["fg_filter"], mask_and_fg=cfg["mask_and_fg"], precision=prec,
+                       emit_logits=True, batch_tiles=16, graph=True)
+        ds = [torch.from_numpy(np.ascontiguousarray(s)).to(DEV) for s in slides]
+        packed = plan.pack(torch.from_numpy(flat).to(DEV))
+        ws = torch.empty(plan.workspace_bytes(ds, pairs), dtype=torch.uint8, device=DEV)
+        outs = plan.alloc_outputs(ds, pairs)
+        for rep in range(4):
+            for row in outs[0] + outs[1]:
+                for t in row:
+                    if t is not None:
+                        t.fill_(7)  # eager work between replays; replay must overwrite it
+            float(torch.ones(1000, device=DEV).sum())
+            masks, logits, _ = plan.segment(ds, pairs, packed, workspace=ws, outputs=outs)
+            torch.cuda.synchronize()
+            for i in range(len(slides)):
+                for p in range(len(pairs)):
+                    assert torch.equal(masks[i][p], m_eager[i][p]), (prec, rep, i, p)
+                    assert torch.equal(logits[i][p], l_eager[i][p]), (prec, rep, i, p)
