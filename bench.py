@@ -148,15 +148,16 @@ def train_leg(om, torch, steps, warmup, batch=32):
         logit, covered = om.OmniSegFn.apply(wt, plan, slide, tiles, pairs)
         loss = om.BCELossFn.apply(logit, y, covered)
         loss.backward()
-        w.sub_(1e-3 * wt.grad)
-        return loss
+        g = wt.grad
+        # SGD step of length lr (the random-weight network's gradients are huge)
+        w.sub_(g * (1e-3 / torch.clamp(g.norm(), min=1.0)))
+        return loss.detach()
 
-    for _ in range(warmup):
-        step()
+    losses = [step() for _ in range(warmup)]
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    losses = [step() for _ in range(steps)]
+    losses += [step() for _ in range(steps)]
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps

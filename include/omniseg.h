@@ -55,7 +55,8 @@ extern "C" {
 #define OMNISEG_FLAG_EMIT_LOGITS 1 /* also write the stitched FP32 logit map */
 #define OMNISEG_FLAG_TRAINING 2    /* also pack the data-gradient weights (training entry points) */
 #define OMNISEG_FLAG_GRAPH 4       /* omniseg_segment_slide: capture the work after the tile list
-                                      in a HIP graph, replayed on calls with identical arguments */
+                                      in a HIP graph, replayed on calls with identical arguments;
+                                      needs a created (non-null) stream */
 
 /* limits */
 #define OMNISEG_MAX_SCALES 4
@@ -238,6 +239,36 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
                              int32_t n_tiles, uint8_t* mask, int64_t mask_pitch,
                              float* logit, int64_t logit_pitch, void* workspace,
                              int64_t ws_bytes, omniseg_stream stream);
+
+/*
+ * Stand-alone 3x3 convolution of the backbone (verification and reuse).
+ * Tensors are NHWC over n images, channels padded to a multiple of 32 with
+ * zeros in the padding; element type FP32 or BF16 (precision).  Zero padding
+ * of 1 at the image border.  H x W is the output size (multiples of 8).
+ *   OMNISEG_CONV_RELU        y = ReLU(conv(x0) + b)
+ *   OMNISEG_CONV_RES_RELU    y = ReLU(conv(x0) + b + x0)          (cin = cout)
+ *   OMNISEG_CONV_POOL_RELU   y = ReLU(conv(maxpool2x2(x0)) + b)   (x0 is 2H x 2W)
+ *   OMNISEG_CONV_UPCAT_RELU  y = ReLU(conv([up2(x0); x1]) + b)    (x0: H/2 x W/2 with cu
+ *                            channels, x1: H x W with cin - cu channels)
+ *   OMNISEG_CONV_DGRAD       y = data gradient of conv: the 3x3 conv of x0 (cout
+ *                            channels) with the weights transposed and flipped;
+ *                            y has cin channels (concat padding when cu < cin)
+ *   OMNISEG_CONV_DGRAD_RES_MASK  y = (DGRAD(x0) + x0) where aux > 0, else 0 (cin = cout)
+ * weights: device FP32 canonical W[cout][cin][3][3]; bias: device FP32 [cout]
+ * (ignored by the DGRAD modes).  workspace: device, >= omniseg_conv3x3_workspace_bytes.
+ */
+#define OMNISEG_CONV_RELU 0
+#define OMNISEG_CONV_RES_RELU 1
+#define OMNISEG_CONV_POOL_RELU 2
+#define OMNISEG_CONV_UPCAT_RELU 3
+#define OMNISEG_CONV_DGRAD 4
+#define OMNISEG_CONV_DGRAD_RES_MASK 5
+int32_t omniseg_conv3x3_workspace_bytes(int32_t precision, int32_t cin, int32_t cu, int32_t cout,
+                                        int64_t* bytes);
+int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t height, int32_t width,
+                        int32_t cin, int32_t cu, int32_t cout, const float* weights,
+                        const float* bias, const void* x0, const void* x1, const void* aux, void* y,
+                        void* workspace, int64_t ws_bytes, omniseg_stream stream);
 
 /*
  * ---- training: forward over a tile batch, BCE loss, hand-written backward ----

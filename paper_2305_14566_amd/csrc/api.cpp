@@ -315,6 +315,7 @@ int32_t omniseg_pack_weights(const omniseg_plan* plan, const float* canonical, v
   if (!plan || !canonical || !packed) return fail(OMNISEG_ERR_ARG, "NULL argument");
   if (reinterpret_cast<uintptr_t>(packed) % 256) return fail(OMNISEG_ERR_ARG, "packed buffer not 256-byte aligned");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
   const int prec = plan->cfg.precision;
   char* pk = static_cast<char*>(packed);
   auto pack = [&](const ConvDesc& d) -> hipError_t {
@@ -447,8 +448,11 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   compute_layout(plan, slides, n_slides, lay);
   if (ws_bytes < lay.total)
     return fail(OMNISEG_ERR_WORKSPACE, "workspace has %lld bytes, needs %lld", (long long)ws_bytes, (long long)lay.total);
+  if ((c.flags & OMNISEG_FLAG_GRAPH) && stream == nullptr)
+    return fail(OMNISEG_ERR_ARG, "OMNISEG_FLAG_GRAPH needs a created stream: the null stream cannot be captured");
 
   // ---- all checks passed: enqueue the work ----
+  (void)hipGetLastError();  // launches below report their own errors, not stale ones
   hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   const char* pk = static_cast<const char*>(packed);
@@ -731,6 +735,82 @@ int32_t omniseg_read_profile(omniseg_plan* plan, omniseg_launch_record* recs, in
   return OMNISEG_OK;
 }
 
+int32_t omniseg_conv3x3_workspace_bytes(int32_t precision, int32_t cin, int32_t cu, int32_t cout,
+                                        int64_t* bytes) {
+  if (!bytes) return fail(OMNISEG_ERR_ARG, "bytes is NULL");
+  if (precision != OMNISEG_FP32 && precision != OMNISEG_BF16) return fail(OMNISEG_ERR_UNSUPPORTED, "unknown precision");
+  if (cin < 1 || cout < 1 || cu < 1 || cu > cin || cin > 8192 || cout > 8192) return fail(OMNISEG_ERR_ARG, "bad channel counts");
+  const int cin_p = cu < cin ? pad_ch(cu) + pad_ch(cin - cu) : pad_ch(cin);
+  *bytes = 256 + align256((int64_t)cin_p * 9 * pad_ch(cout) * elem_size(precision)) + align256((int64_t)pad_ch(cout) * 4);
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t height, int32_t width, int32_t cin,
+                        int32_t cu, int32_t cout, const float* weights, const float* bias, const void* x0,
+                        const void* x1, const void* aux, void* y, void* workspace, int64_t ws_bytes,
+                        omniseg_stream stream) {
+  int64_t need = 0;
+  int32_t st = omniseg_conv3x3_workspace_bytes(precision, cin, cu, cout, &need);
+  if (st) return st;
+  if (mode < OMNISEG_CONV_RELU || mode > OMNISEG_CONV_DGRAD_RES_MASK) return fail(OMNISEG_ERR_ARG, "unknown mode %d", mode);
+  if (n < 1 || height < 8 || width < 8 || height % 8 || width % 8 || height > 4096 || width > 4096)
+    return fail(OMNISEG_ERR_ARG, "n >= 1 and H, W multiples of 8 in [8, 4096] required");
+  if (!weights || !x0 || !y || !workspace) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  const bool dgrad = mode >= OMNISEG_CONV_DGRAD;
+  if (!dgrad && !bias) return fail(OMNISEG_ERR_ARG, "bias is NULL");
+  if (mode == OMNISEG_CONV_UPCAT_RELU) {
+    if (!x1 || cu >= cin || height % 2 || width % 2) return fail(OMNISEG_ERR_ARG, "UPCAT needs x1, cu < cin and even H, W");
+  } else if (cu != cin && mode != OMNISEG_CONV_DGRAD) {
+    return fail(OMNISEG_ERR_ARG, "cu must equal cin outside UPCAT / DGRAD");
+  }
+  if ((mode == OMNISEG_CONV_RES_RELU || mode == OMNISEG_CONV_DGRAD_RES_MASK) && cin != cout)
+    return fail(OMNISEG_ERR_ARG, "residual modes need cin == cout");
+  if (mode == OMNISEG_CONV_DGRAD_RES_MASK && !aux) return fail(OMNISEG_ERR_ARG, "aux is NULL");
+  if (ws_bytes < need) return fail(OMNISEG_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OMNISEG_ERR_ARG, "workspace not 256-byte aligned");
+  hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  char* ws = static_cast<char*>(workspace);
+  int32_t* count = reinterpret_cast<int32_t*>(ws);
+  const int cu_p = pad_ch(cu), cin_p = cu < cin ? cu_p + pad_ch(cin - cu) : pad_ch(cin), cout_p = pad_ch(cout);
+  PackConv pc;
+  pc.src = 0;
+  pc.src_b = 0;
+  pc.cout = cout;
+  pc.cin = cin;
+  pc.cu = cu;
+  pc.cu_p = cu < cin ? cu_p : cin_p;
+  pc.cin_p = cin_p;
+  pc.cout_p = cout_p;
+  pc.dst = 256;
+  pc.dst_b = -1;  // the bias is copied separately below
+  pc.transpose = dgrad ? 1 : 0;
+  const int64_t off_b = 256 + align256((int64_t)cin_p * 9 * cout_p * elem_size(precision));
+  HIP_TRY(launch_set_i32(count, n, sm));
+  HIP_TRY(launch_pack_conv(precision, weights, ws, pc, sm));
+  float* pb = reinterpret_cast<float*>(ws + off_b);
+  if (!dgrad) {
+    HIP_TRY(launch_zero(pb, (int64_t)cout_p * 4, sm));
+    HIP_TRY(launch_copy_f32(bias, pb, cout, sm));
+  }
+  ConvLayer L;
+  L.w = ws + 256;
+  L.b = pb;
+  if (dgrad) {
+    L.cin_p = cout_p;
+    L.cu_p = cout_p;
+    L.cout_p = cin_p;
+  } else {
+    L.cin_p = cin_p;
+    L.cu_p = pc.cu_p;
+    L.cout_p = cout_p;
+  }
+  static const int loader_of[] = {LOAD_PLAIN, LOAD_PLAIN, LOAD_POOL, LOAD_UPCAT, LOAD_PLAIN, LOAD_PLAIN};
+  static const int epi_of[] = {EPI_RELU, EPI_RES_RELU, EPI_RELU, EPI_RELU, EPI_NONE, EPI_RES_MASK};
+  HIP_TRY(launch_conv3x3(precision, loader_of[mode], epi_of[mode], L, height, width, n, count, 0, x0, x1, y, sm, aux));
+  return OMNISEG_OK;
+}
+
 int32_t omniseg_stitch_workspace_bytes(int32_t tile, int32_t stride, int32_t height, int32_t width,
                                        int64_t* bytes) {
   if (!bytes) return fail(OMNISEG_ERR_ARG, "bytes is NULL");
@@ -756,6 +836,7 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
   const int ny = grid_count(height, tile, stride), nx = grid_count(width, tile, stride);
   if ((int64_t)n_tiles > (int64_t)ny * nx) return fail(OMNISEG_ERR_ARG, "more tiles than grid positions");
   hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
   int32_t* grid = static_cast<int32_t*>(workspace);
   HIP_TRY(launch_grid_from_list(tile_yx, n_tiles, ny, nx, grid, sm));
   StitchArgs sa;

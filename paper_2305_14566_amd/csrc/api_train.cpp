@@ -301,6 +301,7 @@ int32_t omniseg_train_forward(const omniseg_plan* plan, const void* packed, cons
   if (st) return st;
 
   const omniseg_config& c = plan->cfg;
+  (void)hipGetLastError();  // launches below report their own errors, not stale ones
   hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   const char* pk = static_cast<const char*>(packed);
@@ -400,6 +401,7 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
   if (st) return st;
 
   const omniseg_config& c = plan->cfg;
+  (void)hipGetLastError();  // launches below report their own errors, not stale ones
   hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   const char* pk = static_cast<const char*>(packed);
@@ -589,6 +591,7 @@ int32_t omniseg_bce_loss(const float* logit, const float* target, const uint8_t*
   if (ws_bytes < 16384) return fail(OMNISEG_ERR_WORKSPACE, "bce workspace needs 16384 bytes");
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OMNISEG_ERR_ARG, "workspace not 256-byte aligned");
   const int nb = 1024;
+  (void)hipGetLastError();
   char* ws = static_cast<char*>(workspace);
   double* psum = reinterpret_cast<double*>(ws);
   int* pcnt = reinterpret_cast<int*>(ws + 8 * nb);

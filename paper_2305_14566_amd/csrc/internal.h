@@ -203,6 +203,7 @@ hipError_t launch_concat_bwd(int precision, const void* dZ, int n_tiles, int H, 
 hipError_t launch_maxpool_bwd(int precision, const void* E, const void* dX, int n_tiles, int H, int W, int c_p,
                               void* dE, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);
 
 struct WgradArgs {
   const void* x0;  // forward conv input (loader source)

@@ -473,6 +473,15 @@ __global__ void k_fill_zero(uint32_t* p, int64_t n) {
   if (i < n) p[i] = 0u;
 }
 
+__global__ void k_set_i32(int32_t* p, int32_t v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, st, p, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st) {
   const int64_t n = bytes / 4;
   if (n <= 0) return hipSuccess;

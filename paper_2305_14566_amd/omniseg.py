@@ -21,6 +21,8 @@ FLAG_GRAPH = 4
  REGION_TILE_INDEX, REGION_TILE_LOGITS) = range(7)
 ABI_VERSION = 1
 
+CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
+
 _lib = None
 
 
@@ -99,6 +101,8 @@ def _declare(lib):
         "omniseg_train_forward": (i32, [vp, vp, P(Slide), P(Tile), i32, P(Pair), i32, vp, vp, vp, i64, vp]),
         "omniseg_backward": (i32, [vp, vp, P(Slide), P(Tile), i32, P(Pair), i32, vp, vp, vp, i64, vp]),
         "omniseg_bce_loss": (i32, [vp, vp, vp, i64, vp, vp, vp, i64, vp]),
+        "omniseg_conv3x3_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
+        "omniseg_conv3x3": (i32, [i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp]),
         "omniseg_read_profile": (i32, [vp, P(LaunchRecord), i32, P(i32)]),
     }
     for name, (res, args) in sig.items():
@@ -389,3 +393,33 @@ class BCELossFn(torch.autograd.Function):
     def backward(ctx, grad_out):
         (grad,) = ctx.saved_tensors
         return grad * grad_out.to(grad.dtype), None, None
+
+
+def conv3x3(precision, mode, x0, weights, bias=None, x1=None, aux=None, cin=None, cu=None, cout=None,
+            height=None, width=None, stream=None):
+    """Stand-alone backbone conv on NHWC tensors with 32-padded channels.
+
+    Returns y (same dtype as x0) of shape [n, H, W, pad32(out channels)].
+    """
+    n = x0.shape[0]
+    cout_, cin_ = weights.shape[0], weights.shape[1]
+    cin = cin_ if cin is None else cin
+    cout = cout_ if cout is None else cout
+    cu = cin if cu is None else cu
+    if height is None:
+        height = x0.shape[1] // 2 if mode == CONV_POOL_RELU else (x0.shape[1] * 2 if mode == CONV_UPCAT_RELU
+                                                                  else x0.shape[1])
+        width = x0.shape[2] // 2 if mode == CONV_POOL_RELU else (x0.shape[2] * 2 if mode == CONV_UPCAT_RELU
+                                                                 else x0.shape[2])
+    p32 = lambda c: -(-c // 32) * 32
+    if mode >= CONV_DGRAD:
+        out_c = p32(cu) + p32(cin - cu) if cu < cin else p32(cin)
+    else:
+        out_c = p32(cout)
+    y = torch.empty((n, height, width, out_c), dtype=x0.dtype, device=x0.device)
+    nb = ctypes.c_int64()
+    _check(lib().omniseg_conv3x3_workspace_bytes(precision, cin, cu, cout, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=x0.device)
+    _check(lib().omniseg_conv3x3(precision, mode, n, height, width, cin, cu, cout, _ptr(weights), _ptr(bias),
+                                 _ptr(x0), _ptr(x1), _ptr(aux), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+    return y
