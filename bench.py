@@ -36,26 +36,21 @@ CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 1, 2, 3), tile
            fg_filter=True)
 
 
-def conv_symbol(prec, stage, cout_p, width):
+def conv_symbol(om, prec, stage, config):
     """Kernel symbol (as rocprofv3 prints it) that a conv launch uses."""
     t = "unsigned short" if prec == "bf16" else "float"
     loader, epi = {"enc_a": (1, 0), "enc_b": (0, 1), "dec_a": (2, 0), "dec_b": (0, 1)}[stage]
-    bn = 64 if cout_p % 64 == 0 else 32
-    wn = 2 if bn >= 64 else 1
-    bx = 16 if width % 16 == 0 else 8
-    return f"omniseg::k_conv3x3<{t}, 8, {bx}, {bn}, {4 // wn}, {wn}, {loader}, {epi}>"
+    by, bx, bn, wm, wn = om.conv_config(config)
+    return f"omniseg::k_conv3x3<{t}, {by}, {bx}, {bn}, {wm}, {wn}, {loader}, {epi}>"
 
 
-def roofline(records, prec):
+def roofline(om, records, prec):
     """Aggregate the profile by kernel symbol; report the dominant conv kernel."""
-    T = CFG["tile"]
     groups = {}
     for r in records:
         if r["stage"] not in ("enc_a", "enc_b", "dec_a", "dec_b"):
             continue
-        l = r["level"]
-        cout = CFG["base"] << l
-        sym = conv_symbol(prec, r["stage"], ((cout + 31) // 32) * 32, T >> l)
+        sym = conv_symbol(om, prec, r["stage"], r["config"])
         g = groups.setdefault(sym, dict(n=0, flops=0.0, ms=0.0, bytes=0.0))
         g["n"] += 1
         g["flops"] += r["flops"]
@@ -96,6 +91,10 @@ def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles
     packed = plan.pack(flat_dev)
     ws = torch.empty(plan.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
     outs = plan.alloc_outputs([dslide], pairs)
+    t_tune = time.perf_counter()
+    plan.autotune([dslide], pairs, packed, ws)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t_tune
     for _ in range(warmup):
         plan.segment([dslide], pairs, packed, workspace=ws, outputs=outs)
     torch.cuda.synchronize()
@@ -117,7 +116,9 @@ def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles
     off, _ = plan.region([dslide], pairs, om.REGION_TILE_COUNT)
     kept = int(ws[off:off + 4].view(torch.int32).item())
     masks = [m.cpu().numpy().astype(bool) for m in outs[0][0]]
-    return dict(ms=ms, wall_ms=wall * 1e3 / steps, records=records, kept=kept, masks=masks)
+    tuned = sorted({(r["stage"], r["level"], r["config"]) for r in records if r["config"] >= 0})
+    return dict(ms=ms, wall_ms=wall * 1e3 / steps, records=records, kept=kept, masks=masks,
+                tuned={f"{st}{l}": list(om.conv_config(c)) for st, l, c in tuned}, tune_s=t_tune)
 
 
 def train_leg(om, torch, steps, warmup, batch=32):
@@ -262,7 +263,8 @@ def main():
                    "tflop_per_step": sum(r["flops"] for r in bf["records"]) / args.steps / 1e12},
         "stages_bf16": stage_summary([dict(r, ms=r["ms"] / args.steps, flops=r["flops"] / args.steps,
                                            bytes=r["bytes"] / args.steps) for r in bf["records"]]),
-        "roofline": roofline(bf["records"], "bf16"),
+        "roofline": roofline(om, bf["records"], "bf16"),
+        "autotuned_conv_tiles_bf16": bf["tuned"],
     }
     st = result["stages_bf16"].get("stitch")
     if st:
@@ -274,7 +276,8 @@ def main():
         dices = [M.dice(a, b) for a, b in zip(bf["masks"], fp["masks"])]
         dis = [M.disagreement(a, b) for a, b in zip(bf["masks"], fp["masks"])]
         result["fp32"] = {"value": px / (fp["ms"] * 1e-3) / 1e6, "ms_per_step": fp["ms"],
-                          "steps": args.fp32_steps, "roofline": roofline(fp["records"], "fp32")}
+                          "steps": args.fp32_steps, "roofline": roofline(om, fp["records"], "fp32"),
+                          "autotuned_conv_tiles": fp["tuned"]}
         result["speedup_bf16_vs_fp32"] = fp["ms"] / bf["ms"]
         result["bf16_vs_fp32_masks"] = {"dice_min": min(dices), "dice_mean": float(np.mean(dices)),
                                         "disagreement_max": max(dis)}

@@ -255,7 +255,10 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
  *                            y has cin channels (concat padding when cu < cin)
  *   OMNISEG_CONV_DGRAD_RES_MASK  y = (DGRAD(x0) + x0) where aux > 0, else 0 (cin = cout)
  * weights: device FP32 canonical W[cout][cin][3][3]; bias: device FP32 [cout]
- * (ignored by the DGRAD modes).  workspace: device, >= omniseg_conv3x3_workspace_bytes.
+ * (ignored by the DGRAD modes).  config: a tile configuration id (see
+ * omniseg_conv_config) valid for the shape, or -1 for the default; ERR_ARG
+ * if it does not fit H, W and the output channels.
+ * workspace: device, >= omniseg_conv3x3_workspace_bytes.
  */
 #define OMNISEG_CONV_RELU 0
 #define OMNISEG_CONV_RES_RELU 1
@@ -268,7 +271,7 @@ int32_t omniseg_conv3x3_workspace_bytes(int32_t precision, int32_t cin, int32_t 
 int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t height, int32_t width,
                         int32_t cin, int32_t cu, int32_t cout, const float* weights,
                         const float* bias, const void* x0, const void* x1, const void* aux, void* y,
-                        void* workspace, int64_t ws_bytes, omniseg_stream stream);
+                        int32_t config, void* workspace, int64_t ws_bytes, omniseg_stream stream);
 
 /*
  * ---- training: forward over a tile batch, BCE loss, hand-written backward ----
@@ -364,12 +367,28 @@ typedef struct omniseg_launch_record {
   int32_t level;  /* U-Net level, or -1 */
   int32_t tiles;  /* tiles the launch processes (0 if not tile-based) */
   int32_t precision;
+  int32_t config; /* conv tile configuration (see omniseg_conv_config), or -1 */
+  int32_t reserved;
   double flops;   /* algorithmic FLOPs */
   double bytes;   /* algorithmic HBM bytes */
   double ms;      /* elapsed time between the events around the launch */
 } omniseg_launch_record;
 
 int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable);
+/* Shape of conv tile configuration `config`: pixel block by x bx, bn output
+ * channels per workgroup, wm x wn waves.  ERR_ARG for an unknown id. */
+int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* bn, int32_t* wm,
+                            int32_t* wn);
+/*
+ * Autotune the conv tile configuration of every backbone layer for these
+ * slides and pairs: each valid configuration runs on the plan's batch shape
+ * in the workspace (whose contents it overwrites) and the fastest by HIP
+ * events is kept in the plan for later omniseg_segment_slide calls.  Waits
+ * for the stream.  Same arguments as omniseg_segment_slide without outputs.
+ */
+int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_slide* slides,
+                         int32_t n_slides, const omniseg_pair* pairs, int32_t n_pairs,
+                         void* workspace, int64_t ws_bytes, omniseg_stream stream);
 /* Waits for the last profiled call's events; copies min(cap, n) records to
  * recs (host array) and the total number of records to *n. */
 int32_t omniseg_read_profile(omniseg_plan* plan, omniseg_launch_record* recs, int32_t cap,

@@ -225,6 +225,8 @@ int32_t omniseg_plan_create(const omniseg_config* cfg, omniseg_plan** out) {
   if (!p) return fail(OMNISEG_ERR_ARG, "out of host memory");
   p->cfg = *cfg;
   p->L = cfg->levels;
+  for (int st = 0; st < 4; ++st)
+    for (int l = 0; l < 8; ++l) p->tune[st][l] = -1;
   for (int l = 0; l < p->L; ++l) {
     p->C[l] = cfg->base_channels << l;
     p->Cp[l] = pad_ch(p->C[l]);
@@ -580,16 +582,19 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
       HIP_TRY(prof.end(OMNISEG_STAGE_FIRST_CONV, 0, nb, 2.0 * 27 * plan->C[0] * (double)T * T * nb,
                        (double)T * T * nb * (3.0 + plan->C[0] * es)));
       HIP_TRY(prof.begin());
-      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[0]), T, T, nb, count, base, A, nullptr, E[0], sm));
-      HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, 0, nb, conv_flops(plan->enc_b[0], T, nb), conv_bytes(plan->enc_b[0], T, nb, 1.0, true)));
+      int cf = layer_config(plan, 1, 0, T, T, plan->enc_b[0].cout_p);
+      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[0]), T, T, nb, count, base, A, nullptr, E[0], sm, nullptr, cf));
+      HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, 0, nb, conv_flops(plan->enc_b[0], T, nb), conv_bytes(plan->enc_b[0], T, nb, 1.0, true), cf));
       for (int l = 1; l < L; ++l) {
         const int tl = T >> l;
         HIP_TRY(prof.begin());
-        HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count, base, E[l - 1], nullptr, A, sm));
-        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nb, conv_flops(plan->enc_a[l], tl, nb), conv_bytes(plan->enc_a[l], tl, nb, 4.0, false)));
+        cf = layer_config(plan, 0, l, tl, tl, plan->enc_a[l].cout_p);
+        HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count, base, E[l - 1], nullptr, A, sm, nullptr, cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nb, conv_flops(plan->enc_a[l], tl, nb), conv_bytes(plan->enc_a[l], tl, nb, 4.0, false), cf));
         HIP_TRY(prof.begin());
-        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm));
-        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nb, conv_flops(plan->enc_b[l], tl, nb), conv_bytes(plan->enc_b[l], tl, nb, 1.0, true)));
+        cf = layer_config(plan, 1, l, tl, tl, plan->enc_b[l].cout_p);
+        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm, nullptr, cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nb, conv_flops(plan->enc_b[l], tl, nb), conv_bytes(plan->enc_b[l], tl, nb, 1.0, true), cf));
       }
       const int tb = T >> (L - 1);
       HIP_TRY(prof.begin());
@@ -604,11 +609,13 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
         const int tl = T >> l;
         // decoder level l: Z = [up2(D_{l+1}) ; E_l]; D_{l+1} lives in E[l+1]'s buffer
         HIP_TRY(prof.begin());
-        HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1], E[l], A, sm));
-        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nb, conv_flops(plan->dec_a[l], tl, nb), conv_bytes(plan->dec_a[l], tl, nb, 0.5, false)));
+        cf = layer_config(plan, 2, l, tl, tl, plan->dec_a[l].cout_p);
+        HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1], E[l], A, sm, nullptr, cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nb, conv_flops(plan->dec_a[l], tl, nb), conv_bytes(plan->dec_a[l], tl, nb, 0.5, false), cf));
         HIP_TRY(prof.begin());
-        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm));
-        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nb, conv_flops(plan->dec_b[l], tl, nb), conv_bytes(plan->dec_b[l], tl, nb, 1.0, true)));
+        cf = layer_config(plan, 3, l, tl, tl, plan->dec_b[l].cout_p);
+        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm, nullptr, cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nb, conv_flops(plan->dec_b[l], tl, nb), conv_bytes(plan->dec_b[l], tl, nb, 1.0, true), cf));
       }
       HIP_TRY(prof.begin());
       HIP_TRY(launch_head(prec, E[0], nb, T, plan->C[0], plan->Cp[0],
@@ -715,6 +722,97 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   return OMNISEG_OK;
 }
 
+int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* bn, int32_t* wm, int32_t* wn) {
+  if (config < 0 || config >= CONV_CFG_COUNT || !by || !bx || !bn || !wm || !wn)
+    return fail(OMNISEG_ERR_ARG, "unknown conv config %d", config);
+  int a, b, c, d, e;
+  conv_config_shape(config, &a, &b, &c, &d, &e);
+  *by = a;
+  *bx = b;
+  *bn = c;
+  *wm = d;
+  *wn = e;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_slide* slides, int32_t n_slides,
+                         const omniseg_pair* pairs, int32_t n_pairs, void* workspace, int64_t ws_bytes,
+                         omniseg_stream stream) {
+  Layout lay;
+  int32_t st = validate_call(plan, slides, n_slides, pairs, n_pairs, lay);
+  if (st) return st;
+  if (!packed || !workspace) return fail(OMNISEG_ERR_ARG, "NULL packed weights or workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 || reinterpret_cast<uintptr_t>(packed) % 256)
+    return fail(OMNISEG_ERR_ARG, "workspace and packed weights must be 256-byte aligned");
+  compute_layout(plan, slides, n_slides, lay);
+  if (ws_bytes < lay.total)
+    return fail(OMNISEG_ERR_WORKSPACE, "workspace has %lld bytes, needs %lld", (long long)ws_bytes, (long long)lay.total);
+  (void)hipGetLastError();
+  hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const char* pk = static_cast<const char*>(packed);
+  const int T = plan->cfg.tile, prec = plan->cfg.precision, L = plan->L, B = lay.batch;
+  void* E[8];
+  for (int l = 0; l < L; ++l) {
+    E[l] = ws + lay.off_E[l];
+    HIP_TRY(launch_zero(E[l], lay.sz_E[l], sm));
+  }
+  void* A = ws + lay.off_A;
+  HIP_TRY(launch_zero(A, lay.sz_A, sm));
+  int32_t* count = reinterpret_cast<int32_t*>(ws + lay.off_count);
+  HIP_TRY(launch_set_i32(count, B, sm));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto layer = [&](const ConvDesc& d) {
+    ConvLayer Ly;
+    Ly.cin_p = d.cin_p;
+    Ly.cu_p = d.cu_p;
+    Ly.cout_p = d.cout_p;
+    Ly.w = pk + d.pk_w;
+    Ly.b = reinterpret_cast<const float*>(pk + d.pk_b);
+    return Ly;
+  };
+  int32_t result = OMNISEG_OK;
+  for (int stg = 0; stg < 4 && result == OMNISEG_OK; ++stg) {
+    for (int l = 0; l < L && result == OMNISEG_OK; ++l) {
+      if ((stg == 0 && l == 0) || (stg >= 2 && l >= L - 1)) continue;
+      const ConvDesc& d = stg == 0 ? plan->enc_a[l] : stg == 1 ? plan->enc_b[l] : stg == 2 ? plan->dec_a[l] : plan->dec_b[l];
+      const int h = T >> l;
+      const int loader = stg == 0 ? LOAD_POOL : stg == 2 ? LOAD_UPCAT : LOAD_PLAIN;
+      const int epi = (stg == 1 || stg == 3) ? EPI_RES_RELU : EPI_RELU;
+      const void* x0 = stg == 0 ? E[l - 1] : stg == 2 ? E[l + 1] : A;
+      const void* x1 = stg == 2 ? E[l] : nullptr;
+      void* y = (stg == 1 || stg == 3) ? E[l] : A;
+      int best = -1;
+      float best_ms = 1e30f;
+      for (int cf = 0; cf < CONV_CFG_COUNT; ++cf) {
+        if (!conv_config_valid(cf, h, h, d.cout_p)) continue;
+        hipError_t e = launch_conv3x3(prec, loader, epi, layer(d), h, h, B, count, 0, x0, x1, y, sm, nullptr, cf);
+        if (e == hipSuccess) e = hipEventRecord(e0, sm);
+        for (int r = 0; r < 2 && e == hipSuccess; ++r)
+          e = launch_conv3x3(prec, loader, epi, layer(d), h, h, B, count, 0, x0, x1, y, sm, nullptr, cf);
+        if (e == hipSuccess) e = hipEventRecord(e1, sm);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          result = fail(OMNISEG_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(e));
+          break;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = cf;
+        }
+      }
+      plan->tune[stg][l] = best;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return result;
+}
+
 int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable) {
   if (!plan) return fail(OMNISEG_ERR_ARG, "plan is NULL");
   plan->profiling = enable != 0;
@@ -747,7 +845,7 @@ int32_t omniseg_conv3x3_workspace_bytes(int32_t precision, int32_t cin, int32_t 
 
 int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t height, int32_t width, int32_t cin,
                         int32_t cu, int32_t cout, const float* weights, const float* bias, const void* x0,
-                        const void* x1, const void* aux, void* y, void* workspace, int64_t ws_bytes,
+                        const void* x1, const void* aux, void* y, int32_t config, void* workspace, int64_t ws_bytes,
                         omniseg_stream stream) {
   int64_t need = 0;
   int32_t st = omniseg_conv3x3_workspace_bytes(precision, cin, cu, cout, &need);
@@ -766,6 +864,11 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
   if ((mode == OMNISEG_CONV_RES_RELU || mode == OMNISEG_CONV_DGRAD_RES_MASK) && cin != cout)
     return fail(OMNISEG_ERR_ARG, "residual modes need cin == cout");
   if (mode == OMNISEG_CONV_DGRAD_RES_MASK && !aux) return fail(OMNISEG_ERR_ARG, "aux is NULL");
+  {
+    const int out_p = dgrad ? (cu < cin ? pad_ch(cu) + pad_ch(cin - cu) : pad_ch(cin)) : pad_ch(cout);
+    if (config != -1 && !conv_config_valid(config, height, width, out_p))
+      return fail(OMNISEG_ERR_ARG, "conv config %d does not fit %dx%d with %d output channels", config, height, width, out_p);
+  }
   if (ws_bytes < need) return fail(OMNISEG_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OMNISEG_ERR_ARG, "workspace not 256-byte aligned");
   hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
@@ -807,7 +910,8 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
   }
   static const int loader_of[] = {LOAD_PLAIN, LOAD_PLAIN, LOAD_POOL, LOAD_UPCAT, LOAD_PLAIN, LOAD_PLAIN};
   static const int epi_of[] = {EPI_RELU, EPI_RES_RELU, EPI_RELU, EPI_RELU, EPI_NONE, EPI_RES_MASK};
-  HIP_TRY(launch_conv3x3(precision, loader_of[mode], epi_of[mode], L, height, width, n, count, 0, x0, x1, y, sm, aux));
+  HIP_TRY(launch_conv3x3(precision, loader_of[mode], epi_of[mode], L, height, width, n, count, 0, x0, x1, y, sm, aux,
+                         config));
   return OMNISEG_OK;
 }
 

@@ -339,11 +339,14 @@ int32_t omniseg_train_forward(const omniseg_plan* plan, const void* packed, cons
   FirstConvArgs fa = first_args(plan, pk, lay, ws, A);
   HIP_TRY(launch_input_x(fa, reinterpret_cast<float*>(ws + lay.off_x), sm));
   HIP_TRY(launch_first_conv(prec, fa, sm));
-  HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, fwd_layer(pk, plan->enc_b[0]), T, T, n, count, 0, A, nullptr, E[0], sm));
+  HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, fwd_layer(pk, plan->enc_b[0]), T, T, n, count, 0, A, nullptr, E[0], sm,
+                         nullptr, layer_config(plan, 1, 0, T, T, plan->enc_b[0].cout_p)));
   for (int l = 1; l < L; ++l) {
     const int tl = T >> l;
-    HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, fwd_layer(pk, plan->enc_a[l]), tl, tl, n, count, 0, E[l - 1], nullptr, A, sm));
-    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, fwd_layer(pk, plan->enc_b[l]), tl, tl, n, count, 0, A, nullptr, E[l], sm));
+    HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, fwd_layer(pk, plan->enc_a[l]), tl, tl, n, count, 0, E[l - 1], nullptr, A, sm,
+                           nullptr, layer_config(plan, 0, l, tl, tl, plan->enc_a[l].cout_p)));
+    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, fwd_layer(pk, plan->enc_b[l]), tl, tl, n, count, 0, A, nullptr, E[l], sm,
+                           nullptr, layer_config(plan, 1, l, tl, tl, plan->enc_b[l].cout_p)));
   }
   const int tb = T >> (L - 1);
   HIP_TRY(launch_gap(prec, E[L - 1], n, tb * tb, plan->Cp[L - 1], plan->G, count, 0, g, sm));
@@ -353,8 +356,10 @@ int32_t omniseg_train_forward(const omniseg_plan* plan, const void* packed, cons
   for (int l = L - 2; l >= 0; --l) {
     const int tl = T >> l;
     const void* below = (l + 1 == L - 1) ? E[L - 1] : D[l + 1];
-    HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, fwd_layer(pk, plan->dec_a[l]), tl, tl, n, count, 0, below, E[l], A, sm));
-    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, fwd_layer(pk, plan->dec_b[l]), tl, tl, n, count, 0, A, nullptr, D[l], sm));
+    HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, fwd_layer(pk, plan->dec_a[l]), tl, tl, n, count, 0, below, E[l], A, sm,
+                           nullptr, layer_config(plan, 2, l, tl, tl, plan->dec_a[l].cout_p)));
+    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, fwd_layer(pk, plan->dec_b[l]), tl, tl, n, count, 0, A, nullptr, D[l], sm,
+                           nullptr, layer_config(plan, 3, l, tl, tl, plan->dec_b[l].cout_p)));
   }
   const void* d0 = L >= 2 ? D[0] : E[0];
   HIP_TRY(launch_head(prec, d0, n, T, plan->C[0], plan->Cp[0],

@@ -92,9 +92,25 @@ enum Loader { LOAD_PLAIN = 0, LOAD_POOL = 1, LOAD_UPCAT = 2 };
 enum Epilogue { EPI_RELU = 0, EPI_RES_RELU = 1, EPI_NONE = 2, EPI_RES_MASK = 3 };
 
 // 3x3 conv on a batch of tiles (NHWC, padded channels), output H x W per tile.
+// Conv tile configurations (pixel block, output channels, wave layout).
+enum ConvConfig {
+  CONV_CFG_8x16_32 = 0,
+  CONV_CFG_8x16_64,
+  CONV_CFG_16x16_64,
+  CONV_CFG_8x16_128,
+  CONV_CFG_8x8_32,
+  CONV_CFG_8x8_64,
+  CONV_CFG_COUNT
+};
+bool conv_config_valid(int cfg, int H, int W, int cout_p);
+void conv_config_shape(int cfg, int* by, int* bx, int* bn, int* wm, int* wn);
+int conv_default_config(int precision, int H, int W, int cout_p);
+
+// cfg < 0 (or not valid for the shape) picks the default configuration.
 hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L, int H, int W,
                           int batch, const int32_t* count, int chunk_base, const void* x0,
-                          const void* x1, void* y, hipStream_t st, const void* aux = nullptr);
+                          const void* x1, void* y, hipStream_t st, const void* aux = nullptr,
+                          int cfg = -1);
 
 // First conv (3 -> C_0) straight from the slide / pyramid.
 struct FirstConvArgs {

@@ -108,6 +108,22 @@ __device__ __forceinline__ uint4 load_vec(const ConvArgs& a, int b, int y, int x
   }
 }
 
+// Issue the global loads of one 16-byte input vector without waiting for
+// them: POOL keeps its four raw vectors (reduced when committed to LDS).
+template <typename T, int LOADER>
+__device__ __forceinline__ void fetch_vec(const ConvArgs& a, int b, int y, int x, int c, uint4* r) {
+  if (LOADER == LOAD_POOL) {
+    const int W2 = 2 * a.W;
+    const T* p = (const T*)a.x0 + (((int64_t)b * 2 * a.H + 2 * y) * W2 + 2 * x) * a.cin_p + c;
+    r[0] = *reinterpret_cast<const uint4*>(p);
+    r[1] = *reinterpret_cast<const uint4*>(p + a.cin_p);
+    r[2] = *reinterpret_cast<const uint4*>(p + (int64_t)W2 * a.cin_p);
+    r[3] = *reinterpret_cast<const uint4*>(p + (int64_t)W2 * a.cin_p + a.cin_p);
+  } else {
+    r[0] = load_vec<T, LOADER>(a, b, y, x, c);
+  }
+}
+
 __device__ __forceinline__ void mma(f32x4& acc, uint4 av, uint4 bv, float) {
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.x), __uint_as_float(bv.x), acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.y), __uint_as_float(bv.y), acc, 0, 0, 0);
@@ -123,6 +139,63 @@ __device__ __forceinline__ float load_scalar(const float* p) { return *p; }
 __device__ __forceinline__ float load_scalar(const uint16_t* p) { return bf2f(*p); }
 __device__ __forceinline__ void store_scalar(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_scalar(uint16_t* p, float v) { *p = f2bf(v); }
+
+// Global -> register -> LDS staging of one input-channel chunk.  Each thread
+// owns HPT halo vectors (LPV raw loads each; HALO_V in total) and WPT weight
+// vectors (W_V in total); fetch issues the loads, commit writes LDS.
+template <typename T, int LOADER, int HALO_V, int W_V, int LPV, int NV, int VEC, int KC, int ROW, int PX, int BN>
+struct Stager {
+  static constexpr int HPT = (HALO_V + 255) / 256;
+  static constexpr int WPT = (W_V + 255) / 256;
+  __device__ __forceinline__ static void fetch(const ConvArgs& a, int b, int tid, int y0, int x0, int n0, int ch,
+                                               uint4 (&hreg)[HPT][LPV], uint4 (&wreg)[WPT]) {
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) {
+      const int idx = tid + i * 256;
+#pragma unroll
+      for (int j = 0; j < LPV; ++j) hreg[i][j] = make_uint4(0, 0, 0, 0);
+      if (idx < HALO_V) {
+        const int p = idx / NV, v = idx % NV;
+        const int y = y0 + p / PX - 1, x = x0 + p % PX - 1;
+        if (y >= 0 && y < a.H && x >= 0 && x < a.W) fetch_vec<T, LOADER>(a, b, y, x, ch * KC + v * VEC, hreg[i]);
+      }
+    }
+    const T* wsrc = (const T*)a.w + (int64_t)ch * 9 * a.cout_p * KC;
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int idx = tid + i * 256;
+      wreg[i] = make_uint4(0, 0, 0, 0);
+      if (idx < W_V) {
+        const int v = idx % NV, r = idx / NV;
+        const int tap = r / BN, n = r % BN;
+        wreg[i] = *reinterpret_cast<const uint4*>(wsrc + ((int64_t)tap * a.cout_p + n0 + n) * KC + v * VEC);
+      }
+    }
+  }
+  __device__ __forceinline__ static void commit(int tid, const uint4 (&hreg)[HPT][LPV], const uint4 (&wreg)[WPT],
+                                                T* sX, T* sW) {
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) {
+      const int idx = tid + i * 256;
+      if (idx < HALO_V) {
+        const int p = idx / NV, v = idx % NV;
+        uint4 val = hreg[i][0];
+        if (LPV == 4)
+          val = vmax(vmax(hreg[i][0], hreg[i][LPV > 1 ? 1 : 0], T()),
+                     vmax(hreg[i][LPV > 2 ? 2 : 0], hreg[i][LPV > 3 ? 3 : 0], T()), T());
+        *reinterpret_cast<uint4*>(&sX[p * ROW + v * VEC]) = val;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int idx = tid + i * 256;
+      if (idx < W_V) {
+        const int v = idx % NV, r = idx / NV;
+        *reinterpret_cast<uint4*>(&sW[r * ROW + v * VEC]) = wreg[i];
+      }
+    }
+  }
+};
 
 template <typename T, int BY, int BX, int BN, int WM, int WN, int LOADER, int EPI>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
@@ -168,23 +241,22 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // Staging: each thread owns HPT halo vectors and WPT weight vectors of a
+  // chunk.  The next chunk's global loads are issued before the current
+  // chunk's MFMAs and committed to LDS after them, so their latency overlaps
+  // the arithmetic.
+  constexpr int HALO_V = NPIX * NV, W_V = 9 * BN * NV;
+  constexpr int HPT = (HALO_V + 255) / 256, WPT = (W_V + 255) / 256;
+  constexpr int LPV = (LOADER == LOAD_POOL) ? 4 : 1;
+  uint4 hreg[HPT][LPV];
+  uint4 wreg[WPT];
   const int nchunks = a.cin_p / KC;
+  using ST = Stager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN>;
+  ST::fetch(a, b, tid, y0, x0, n0, 0, hreg, wreg);
+  ST::commit(tid, hreg, wreg, sX, sW);
+  __syncthreads();
   for (int ch = 0; ch < nchunks; ++ch) {
-    for (int i = tid; i < NPIX * NV; i += 256) {
-      const int p = i / NV, v = i % NV;
-      const int y = y0 + p / PX - 1, x = x0 + p % PX - 1;
-      uint4 val = make_uint4(0, 0, 0, 0);
-      if (y >= 0 && y < a.H && x >= 0 && x < a.W) val = load_vec<T, LOADER>(a, b, y, x, ch * KC + v * VEC);
-      *reinterpret_cast<uint4*>(&sX[p * ROW + v * VEC]) = val;
-    }
-    const T* wsrc = (const T*)a.w + (int64_t)ch * 9 * a.cout_p * KC;
-    for (int i = tid; i < 9 * BN * NV; i += 256) {
-      const int v = i % NV, r = i / NV;
-      const int tap = r / BN, n = r % BN;
-      *reinterpret_cast<uint4*>(&sW[r * ROW + v * VEC]) =
-          *reinterpret_cast<const uint4*>(wsrc + ((int64_t)tap * a.cout_p + n0 + n) * KC + v * VEC);
-    }
-    __syncthreads();
+    if (ch + 1 < nchunks) ST::fetch(a, b, tid, y0, x0, n0, ch + 1, hreg, wreg);
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int sh = ((tap / 3) * PX + (tap % 3)) * ROW;
@@ -203,6 +275,10 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
       }
     }
     __syncthreads();
+    if (ch + 1 < nchunks) {
+      ST::commit(tid, hreg, wreg, sX, sW);
+      __syncthreads();
+    }
   }
 
   T* out = (T*)a.y;
@@ -235,12 +311,10 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
   }
 }
 
-template <typename T, int BY, int BX, int BN, int LOADER, int EPI>
+template <typename T, int BY, int BX, int BN, int WM, int WN, int LOADER, int EPI>
 static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
                                 int chunk_base, const void* x0, const void* x1, const void* aux,
                                 void* y, hipStream_t st) {
-  constexpr int WN = (BN >= 64) ? 2 : 1;
-  constexpr int WM = 4 / WN;
   ConvArgs a;
   a.x0 = x0;
   a.x1 = x1;
@@ -264,31 +338,75 @@ static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, con
   return hipGetLastError();
 }
 
-template <typename T, int BY, int BX, int LOADER, int EPI>
-static hipError_t launch_conv_bn(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
-                                 int chunk_base, const void* x0, const void* x1, const void* aux,
-                                 void* y, hipStream_t st) {
-  if (L.cout_p % 64 == 0)
-    return launch_conv_t<T, BY, BX, 64, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
-  return launch_conv_t<T, BY, BX, 32, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+// Tile configurations: pixel block BY x BX, BN output channels, and the
+// 4-wave layout WM x WN (each wave owns (BY BX / WM) x (BN / WN) outputs).
+#define OMNISEG_CONV_CONFIGS(X)  \
+  X(CONV_CFG_8x16_32, 8, 16, 32, 4, 1)    \
+  X(CONV_CFG_8x16_64, 8, 16, 64, 2, 2)    \
+  X(CONV_CFG_16x16_64, 16, 16, 64, 4, 1)  \
+  X(CONV_CFG_8x16_128, 8, 16, 128, 2, 2)  \
+  X(CONV_CFG_8x8_32, 8, 8, 32, 4, 1)      \
+  X(CONV_CFG_8x8_64, 8, 8, 64, 2, 2)
+
+static const int kCfgShape[][3] = {
+#define OMNISEG_SHAPE(id, by, bx, bn, wm, wn) {by, bx, bn},
+    OMNISEG_CONV_CONFIGS(OMNISEG_SHAPE)
+#undef OMNISEG_SHAPE
+};
+
+void conv_config_shape(int cfg, int* by, int* bx, int* bn, int* wm, int* wn) {
+  static const int t[][5] = {
+#define OMNISEG_T(id, a, b, c, d, e) {a, b, c, d, e},
+      OMNISEG_CONV_CONFIGS(OMNISEG_T)
+#undef OMNISEG_T
+  };
+  *by = t[cfg][0];
+  *bx = t[cfg][1];
+  *bn = t[cfg][2];
+  *wm = t[cfg][3];
+  *wn = t[cfg][4];
+}
+
+bool conv_config_valid(int cfg, int H, int W, int cout_p) {
+  if (cfg < 0 || cfg >= CONV_CFG_COUNT) return false;
+  return H % kCfgShape[cfg][0] == 0 && W % kCfgShape[cfg][1] == 0 && cout_p % kCfgShape[cfg][2] == 0;
+}
+
+int conv_default_config(int precision, int H, int W, int cout_p) {
+  const int order_bf16[] = {CONV_CFG_16x16_64, CONV_CFG_8x16_64, CONV_CFG_8x16_32, CONV_CFG_8x8_64, CONV_CFG_8x8_32};
+  const int order_f32[] = {CONV_CFG_8x16_64, CONV_CFG_8x16_32, CONV_CFG_8x8_64, CONV_CFG_8x8_32};
+  if (precision == OMNISEG_BF16) {
+    for (int c : order_bf16)
+      if (conv_config_valid(c, H, W, cout_p)) return c;
+  } else {
+    for (int c : order_f32)
+      if (conv_config_valid(c, H, W, cout_p)) return c;
+  }
+  return -1;
 }
 
 template <typename T, int LOADER, int EPI>
-static hipError_t launch_conv_sp(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
-                                 int chunk_base, const void* x0, const void* x1, const void* aux,
-                                 void* y, hipStream_t st) {
-  if (W % 16 == 0 && H % 8 == 0)
-    return launch_conv_bn<T, 8, 16, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
-  return launch_conv_bn<T, 8, 8, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+static hipError_t launch_conv_cfg(int cfg, const ConvLayer& L, int H, int W, int batch, const int32_t* count,
+                                  int chunk_base, const void* x0, const void* x1, const void* aux, void* y,
+                                  hipStream_t st) {
+  switch (cfg) {
+#define OMNISEG_CASE(id, by, bx, bn, wm, wn) \
+  case id:                                   \
+    return launch_conv_t<T, by, bx, bn, wm, wn, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+    OMNISEG_CONV_CONFIGS(OMNISEG_CASE)
+#undef OMNISEG_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>
-static hipError_t launch_conv_mode(int loader, int epi, const ConvLayer& L, int H, int W, int batch,
-                                   const int32_t* count, int chunk_base, const void* x0,
-                                   const void* x1, const void* aux, void* y, hipStream_t st) {
-#define OMNISEG_CONV_CASE(LD, EP)                                                                  \
-  if (loader == LD && epi == EP)                                                                  \
-    return launch_conv_sp<T, LD, EP>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+static hipError_t launch_conv_mode(int cfg, int loader, int epi, const ConvLayer& L, int H, int W, int batch,
+                                   const int32_t* count, int chunk_base, const void* x0, const void* x1,
+                                   const void* aux, void* y, hipStream_t st) {
+#define OMNISEG_CONV_CASE(LD, EP)  \
+  if (loader == LD && epi == EP) \
+    return launch_conv_cfg<T, LD, EP>(cfg, L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
   OMNISEG_CONV_CASE(LOAD_PLAIN, EPI_RES_RELU)
   OMNISEG_CONV_CASE(LOAD_POOL, EPI_RELU)
   OMNISEG_CONV_CASE(LOAD_UPCAT, EPI_RELU)
@@ -301,10 +419,12 @@ static hipError_t launch_conv_mode(int loader, int epi, const ConvLayer& L, int 
 
 hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L, int H, int W,
                           int batch, const int32_t* count, int chunk_base, const void* x0,
-                          const void* x1, void* y, hipStream_t st, const void* aux) {
+                          const void* x1, void* y, hipStream_t st, const void* aux, int cfg) {
+  if (cfg < 0 || !conv_config_valid(cfg, H, W, L.cout_p)) cfg = conv_default_config(precision, H, W, L.cout_p);
+  if (cfg < 0) return hipErrorInvalidValue;
   if (precision == OMNISEG_BF16)
-    return launch_conv_mode<uint16_t>(loader, epi, L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
-  return launch_conv_mode<float>(loader, epi, L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+    return launch_conv_mode<uint16_t>(cfg, loader, epi, L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+  return launch_conv_mode<float>(cfg, loader, epi, L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
 }
 
 // ---------------------------------------------------------------------------

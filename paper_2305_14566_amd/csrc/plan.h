@@ -45,6 +45,8 @@ struct omniseg_plan {
   int64_t packed_bytes = 0;
   mutable std::vector<omniseg::SlideDev> slide_tab;  // host staging of the device slide table
   mutable std::vector<int32_t> host_tab;             // host staging of tile lists and grids
+  // conv tile configuration per (stage, level): stage 0 enc_a, 1 enc_b, 2 dec_a, 3 dec_b; -1 = default
+  int tune[4][8];
   // per-launch profiling (off by default)
   bool profiling = false;
   mutable std::vector<hipEvent_t> events;
@@ -63,6 +65,14 @@ struct omniseg_plan {
 
 namespace omniseg {
 
+// Conv tile configuration for a backbone layer: the tuned one when it is
+// valid for the shape, else the default.  stage: 0 enc_a, 1 enc_b, 2 dec_a, 3 dec_b.
+inline int layer_config(const omniseg_plan* p, int stage, int level, int H, int W, int cout_p) {
+  const int t = p->tune[stage][level];
+  if (t >= 0 && conv_config_valid(t, H, W, cout_p)) return t;
+  return conv_default_config(p->cfg.precision, H, W, cout_p);
+}
+
 // Records a pair of events around each launch when profiling is on.
 struct Prof {
   const omniseg_plan* p;
@@ -78,7 +88,7 @@ struct Prof {
     }
     return hipEventRecord(p->events[2 * next], st);
   }
-  hipError_t end(int stage, int level, int tiles, double flops, double bytes) {
+  hipError_t end(int stage, int level, int tiles, double flops, double bytes, int config = -1) {
     if (!p->profiling) return hipSuccess;
     hipError_t r = hipEventRecord(p->events[2 * next + 1], st);
     omniseg_launch_record rec;
@@ -86,6 +96,8 @@ struct Prof {
     rec.level = level;
     rec.tiles = tiles;
     rec.precision = p->cfg.precision;
+    rec.config = config;
+    rec.reserved = 0;
     rec.flops = flops;
     rec.bytes = bytes;
     rec.ms = 0.0;

@@ -22,6 +22,7 @@ FLAG_GRAPH = 4
 ABI_VERSION = 1
 
 CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
+N_CONV_CONFIGS = 6
 
 _lib = None
 
@@ -63,8 +64,8 @@ class Pair(ctypes.Structure):
 
 class LaunchRecord(ctypes.Structure):
     _fields_ = [("stage", ctypes.c_int32), ("level", ctypes.c_int32), ("tiles", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("precision", ctypes.c_int32), ("config", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
 STAGE_NAMES = ("prep", "first_conv", "enc_a", "enc_b", "dec_a", "dec_b", "gap_ctrl", "head", "stitch")
@@ -96,13 +97,15 @@ def _declare(lib):
         "omniseg_stitch_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
         "omniseg_stitch_tiles": (i32, [i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, i64, vp, i64, vp]),
         "omniseg_set_profiling": (i32, [vp, i32]),
+        "omniseg_conv_config": (i32, [i32, P(i32), P(i32), P(i32), P(i32), P(i32)]),
+        "omniseg_autotune": (i32, [vp, vp, P(Slide), i32, P(Pair), i32, vp, i64, vp]),
         "omniseg_plane_offsets": (i32, [vp, P(Slide), P(Pair), i32, P(i64)]),
         "omniseg_train_workspace_bytes": (i32, [vp, P(Slide), P(Tile), i32, P(Pair), i32, P(i64)]),
         "omniseg_train_forward": (i32, [vp, vp, P(Slide), P(Tile), i32, P(Pair), i32, vp, vp, vp, i64, vp]),
         "omniseg_backward": (i32, [vp, vp, P(Slide), P(Tile), i32, P(Pair), i32, vp, vp, vp, i64, vp]),
         "omniseg_bce_loss": (i32, [vp, vp, vp, i64, vp, vp, vp, i64, vp]),
         "omniseg_conv3x3_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
-        "omniseg_conv3x3": (i32, [i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp]),
+        "omniseg_conv3x3": (i32, [i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, i32, vp, i64, vp]),
         "omniseg_read_profile": (i32, [vp, P(LaunchRecord), i32, P(i32)]),
     }
     for name, (res, args) in sig.items():
@@ -205,7 +208,13 @@ class Plan:
         recs = (LaunchRecord * max(1, n.value))()
         _check(lib().omniseg_read_profile(self._h, recs, n.value, ctypes.byref(n)))
         return [dict(stage=STAGE_NAMES[r.stage], level=r.level, tiles=r.tiles, flops=r.flops,
-                     bytes=r.bytes, ms=r.ms) for r in recs[:n.value]]
+                     bytes=r.bytes, ms=r.ms, config=r.config) for r in recs[:n.value]]
+
+    def autotune(self, slides, pairs, packed, workspace, stream=None):
+        """Time every valid conv tile configuration per layer; keep the fastest."""
+        sl, pr = self._arrays(slides, pairs)
+        _check(lib().omniseg_autotune(self._h, _ptr(packed), sl, len(slides), pr, len(pairs), _ptr(workspace),
+                                      workspace.numel(), _stream(stream)))
 
     def pack(self, canonical, stream=None):
         """Canonical FP32 weights (device tensor) -> packed device buffer (uint8)."""
@@ -396,7 +405,7 @@ class BCELossFn(torch.autograd.Function):
 
 
 def conv3x3(precision, mode, x0, weights, bias=None, x1=None, aux=None, cin=None, cu=None, cout=None,
-            height=None, width=None, stream=None):
+            height=None, width=None, config=-1, stream=None):
     """Stand-alone backbone conv on NHWC tensors with 32-padded channels.
 
     Returns y (same dtype as x0) of shape [n, H, W, pad32(out channels)].
@@ -421,5 +430,13 @@ def conv3x3(precision, mode, x0, weights, bias=None, x1=None, aux=None, cin=None
     _check(lib().omniseg_conv3x3_workspace_bytes(precision, cin, cu, cout, ctypes.byref(nb)))
     ws = torch.empty(nb.value, dtype=torch.uint8, device=x0.device)
     _check(lib().omniseg_conv3x3(precision, mode, n, height, width, cin, cu, cout, _ptr(weights), _ptr(bias),
-                                 _ptr(x0), _ptr(x1), _ptr(aux), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+                                 _ptr(x0), _ptr(x1), _ptr(aux), _ptr(y), config, _ptr(ws), ws.numel(),
+                                 _stream(stream)))
     return y
+
+
+def conv_config(config):
+    """(by, bx, bn, wm, wn) of a conv tile configuration id."""
+    v = [ctypes.c_int32() for _ in range(5)]
+    _check(lib().omniseg_conv_config(config, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)

@@ -116,3 +116,41 @@ def test_conv_dgrad_concat_layout(prec):
     ref = [O.conv3x3_backward(np.zeros((cin, H, W)), Wt, g)[0] for g in G]
     check(got, ref, prec)
     assert np.all(yn[..., cu:p32(cu)] == 0) and np.all(yn[..., p32(cu) + ce:] == 0)
+
+
+@pytest.mark.parametrize("prec", [om.FP32, om.BF16])
+@pytest.mark.parametrize("config", list(range(om.N_CONV_CONFIGS)))
+@pytest.mark.parametrize("mode", ["res", "pool", "upcat", "dgrad_res"])
+def test_every_tile_configuration(prec, config, mode):
+    """Each conv tile configuration the autotuner may pick, on a shape it fits."""
+    by, bx, bn, wm, wn = om.conv_config(config)
+    n, H, W = 2, 2 * by, 2 * bx
+    cout = bn if bn > 32 else 32
+    cin = cout if mode in ("res", "dgrad_res") else 48
+    rng = np.random.default_rng(config * 17 + len(mode))
+    Wt = q(rng.standard_normal((cout, cin, 3, 3)) * np.sqrt(2.0 / (9 * cin)), prec)
+    b = rng.standard_normal(cout) * 0.1
+    wdev = torch.from_numpy(Wt.astype(np.float32)).to(DEV)
+    bdev = torch.from_numpy(b.astype(np.float32)).to(DEV)
+    if mode == "res":
+        X = [q(rng.standard_normal((cin, H, W)), prec) for _ in range(n)]
+        y = om.conv3x3(prec, om.CONV_RES_RELU, to_nhwc(X, prec), wdev, bdev, config=config)
+        check(from_nhwc(y, cout), [np.maximum(O.conv3x3(x, Wt, b) + x, 0) for x in X], prec)
+    elif mode == "pool":
+        X = [q(np.abs(rng.standard_normal((cin, 2 * H, 2 * W))), prec) for _ in range(n)]
+        y = om.conv3x3(prec, om.CONV_POOL_RELU, to_nhwc(X, prec), wdev, bdev, config=config)
+        check(from_nhwc(y, cout), [np.maximum(O.conv3x3(O.maxpool2(x), Wt, b), 0) for x in X], prec)
+    elif mode == "upcat":
+        cu = 32
+        D = [q(rng.standard_normal((cu, H // 2, W // 2)), prec) for _ in range(n)]
+        E = [q(rng.standard_normal((cin - cu, H, W)), prec) for _ in range(n)]
+        y = om.conv3x3(prec, om.CONV_UPCAT_RELU, to_nhwc(D, prec), wdev, bdev, x1=to_nhwc(E, prec), cu=cu,
+                       config=config)
+        check(from_nhwc(y, cout), [np.maximum(O.conv3x3(np.concatenate([O.up2(d), e]), Wt, b), 0)
+                                   for d, e in zip(D, E)], prec)
+    else:
+        G = [q(rng.standard_normal((cout, H, W)), prec) for _ in range(n)]
+        A = [q(rng.standard_normal((cin, H, W)), prec) for _ in range(n)]
+        y = om.conv3x3(prec, om.CONV_DGRAD_RES_MASK, to_nhwc(G, prec), wdev, aux=to_nhwc(A, prec), config=config)
+        check(from_nhwc(y, cin), [(O.conv3x3_backward(np.zeros((cin, H, W)), Wt, g)[0] + g) * (a > 0)
+                                  for g, a in zip(G, A)], prec)
