@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define OMNISEG_ABI_VERSION 1
+#define OMNISEG_ABI_VERSION 2
 
 /* status codes */
 #define OMNISEG_OK 0
@@ -86,6 +86,11 @@ typedef struct omniseg_hip_stream_opaque* omniseg_stream; /* a hipStream_t */
  *   precision      OMNISEG_FP32 or OMNISEG_BF16.
  *   flags          OR of OMNISEG_FLAG_*.
  *   batch_tiles    tiles per backbone batch (0 = library default).
+ *   max_kept_tiles capacity of the per-tile logit store in the workspace:
+ *                  0 sizes it for every grid tile; a positive value sizes it
+ *                  for at most that many kept tiles, and a call that keeps
+ *                  more returns OMNISEG_ERR_WORKSPACE once the tile list is
+ *                  built (no output is written then).
  */
 typedef struct omniseg_config {
   int32_t abi_version;
@@ -103,6 +108,7 @@ typedef struct omniseg_config {
   int32_t precision;
   int32_t flags;
   int32_t batch_tiles;
+  int32_t max_kept_tiles;
 } omniseg_config;
 
 /* One slide: uint8 RGB, interleaved (HWC), rows `row_pitch` bytes apart

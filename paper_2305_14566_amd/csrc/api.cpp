@@ -50,6 +50,7 @@ struct Layout {
   int Hc[OMNISEG_MAX_SLIDES], Wc[OMNISEG_MAX_SLIDES];
   TileGroups groups;
   int total_tiles = 0;
+  int logit_cap = 0;  // kept tiles the logit store holds
   int batch = 0;
   SlotTable slots;
   int max_slots = 0;
@@ -95,6 +96,7 @@ int32_t validate_config(const omniseg_config* c) {
     return fail(OMNISEG_ERR_ARG, "unknown flags 0x%x", c->flags);
   if (c->batch_tiles < 0 || c->batch_tiles > 65536)
     return fail(OMNISEG_ERR_ARG, "batch_tiles %d outside [0, 65536]", c->batch_tiles);
+  if (c->max_kept_tiles < 0) return fail(OMNISEG_ERR_ARG, "max_kept_tiles %d < 0", c->max_kept_tiles);
   const int64_t G = (int64_t)c->base_channels << (c->levels - 1);
   if (G > 4096) return fail(OMNISEG_ERR_UNSUPPORTED, "bottleneck width %lld > 4096", (long long)G);
   return OMNISEG_OK;
@@ -191,7 +193,8 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
   lay.off_A = take(lay.sz_A);
   lay.off_g = take((int64_t)lay.batch * plan->Cp[plan->L - 1] * 4);
   lay.off_theta = take((int64_t)lay.batch * lay.max_slots * plan->P * 4);
-  lay.sz_logits = (int64_t)tiles * lay.max_slots * T * T * 4;
+  lay.logit_cap = c.max_kept_tiles > 0 ? std::min(tiles, c.max_kept_tiles) : tiles;
+  lay.sz_logits = (int64_t)lay.logit_cap * lay.max_slots * T * T * 4;
   lay.off_logits = take(lay.sz_logits);
   lay.total = off;
 }
@@ -531,6 +534,8 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   HIP_TRY(hipStreamSynchronize(sm));
   if (n_kept < 0 || n_kept > lay.total_tiles)
     return fail(OMNISEG_ERR_HIP, "kept-tile count %d outside [0, %d]", n_kept, lay.total_tiles);
+  if (n_kept > lay.logit_cap)
+    return fail(OMNISEG_ERR_WORKSPACE, "%d tiles kept, the logit store holds %d (max_kept_tiles)", n_kept, lay.logit_cap);
 
   // 3-4. everything after the tile list: backbone batches, head, stitch.  With
   // OMNISEG_FLAG_GRAPH this sequence is captured once per distinct argument set

@@ -19,7 +19,7 @@ FLAG_TRAINING = 2
 FLAG_GRAPH = 4
 (REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
  REGION_TILE_INDEX, REGION_TILE_LOGITS) = range(7)
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
 N_CONV_CONFIGS = 6
@@ -50,6 +50,7 @@ class Config(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("batch_tiles", ctypes.c_int32),
+        ("max_kept_tiles", ctypes.c_int32),
     ]
 
 
@@ -155,7 +156,8 @@ class Plan:
 
     def __init__(self, base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
                  stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False,
-                 precision=FP32, emit_logits=False, batch_tiles=0, training=False, graph=False):
+                 precision=FP32, emit_logits=False, batch_tiles=0, training=False, graph=False,
+                 max_kept_tiles=0):
         c = Config()
         c.abi_version = ABI_VERSION
         c.base_channels = base
@@ -174,6 +176,7 @@ class Plan:
         c.flags = ((FLAG_EMIT_LOGITS if emit_logits else 0) | (FLAG_TRAINING if training else 0)
                    | (FLAG_GRAPH if graph else 0))
         c.batch_tiles = batch_tiles
+        c.max_kept_tiles = max_kept_tiles
         self.cfg = c
         self.scales = tuple(scales)
         self.emit_logits = emit_logits

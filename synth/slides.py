@@ -22,17 +22,16 @@ _NOISE_ROWS = 512  # rows of noise drawn per block (bounds host memory)
 
 
 def _finish(canvas, rng):
-    """Add N(0, 4^2) noise block by block, round, clip, cast to uint8."""
+    """Add N(0, 4^2) noise block by block, round, clip, cast to uint8 (in place)."""
     H, W, _ = canvas.shape
-    out = np.empty((H, W, 3), np.uint8)
     for y0 in range(0, H, _NOISE_ROWS):
         y1 = min(H, y0 + _NOISE_ROWS)
         noise = rng.standard_normal((y1 - y0, W, 3), dtype=np.float32) * np.float32(_NOISE_SIGMA)
         blk = canvas[y0:y1].astype(np.float32) + noise
         np.rint(blk, out=blk)
         np.clip(blk, 0, 255, out=blk)
-        out[y0:y1] = blk.astype(np.uint8)
-    return out
+        canvas[y0:y1] = blk.astype(np.uint8)
+    return canvas
 
 
 def _bbox(cy, cx, r, H, W):
@@ -67,7 +66,7 @@ def ellipse_slide(seed, H=256, W=256, n_ellipses=6):
     """
     rng = np.random.default_rng(seed)
     bg = int(rng.integers(235, 246))
-    canvas = np.full((H, W, 3), bg, np.float32)
+    canvas = np.full((H, W, 3), bg, np.uint8)
     gt = np.zeros((1, H, W), bool)
     for _ in range(n_ellipses):
         cy, cx = rng.uniform(0, H), rng.uniform(0, W)
@@ -92,7 +91,7 @@ def tiny_slide(seed, H=64, W=64):
     """
     rng = np.random.default_rng(seed)
     bg = int(rng.integers(235, 246))
-    canvas = np.full((H, W, 3), bg, np.float32)
+    canvas = np.full((H, W, 3), bg, np.uint8)
     gt = np.zeros((6, H, W), bool)
     for c in range(6):
         cy, cx = rng.uniform(0, H), rng.uniform(0, W)
@@ -125,7 +124,7 @@ def strip_slide(seed, H, W, fg_frac=0.30, with_gt=True, density=1.0):
     """
     rng = np.random.default_rng(seed)
     bg = int(rng.integers(235, 246))
-    canvas = np.full((H, W, 3), bg, np.float32)
+    canvas = np.full((H, W, 3), bg, np.uint8)
     gt = np.zeros((6, H, W), bool) if with_gt else None
 
     amp = rng.uniform(0.05, 0.15) * H
