@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define OMNISEG_ABI_VERSION 2
+#define OMNISEG_ABI_VERSION 3
 
 /* status codes */
 #define OMNISEG_OK 0
@@ -50,6 +50,9 @@ extern "C" {
 /* backbone arithmetic */
 #define OMNISEG_FP32 0 /* FP32 activations and weights, FP32 MFMA           */
 #define OMNISEG_BF16 1 /* BF16 activations and weights, FP32 accumulation   */
+#define OMNISEG_FP8 2  /* FP8 E4M3 activations and 3x3 weights with per-channel
+                        * power-of-two scales, FP32 accumulation (inference
+                        * only; weights from omniseg_pack_weights_fp8)       */
 
 /* flags */
 #define OMNISEG_FLAG_EMIT_LOGITS 1 /* also write the stitched FP32 logit map */
@@ -83,7 +86,8 @@ typedef struct omniseg_hip_stream_opaque* omniseg_stream; /* a hipStream_t */
  *   fg_threshold   gray threshold of the tissue map (pixels darker than this
  *                  on the coarsest scale are tissue), in [1, 255].
  *   mask_and_fg    1: the output mask is also ANDed with the tissue map.
- *   precision      OMNISEG_FP32 or OMNISEG_BF16.
+ *   precision      OMNISEG_FP32, OMNISEG_BF16 or OMNISEG_FP8 (not with
+ *                  OMNISEG_FLAG_TRAINING).
  *   flags          OR of OMNISEG_FLAG_*.
  *   batch_tiles    tiles per backbone batch (0 = library default).
  *   max_kept_tiles capacity of the per-tile logit store in the workspace:
@@ -174,6 +178,63 @@ int32_t omniseg_packed_weight_bytes(const omniseg_plan* plan, int64_t* bytes);
  */
 int32_t omniseg_pack_weights(const omniseg_plan* plan, const float* canonical,
                              void* packed, omniseg_stream stream);
+
+/*
+ * FP8 backbone (precision OMNISEG_FP8; the paper's pipeline runs its network
+ * in FP32, Section 2.2 -- this is a reduced-precision form of that step).
+ * Every stored backbone activation t keeps one power-of-two scale s_t[c] per
+ * channel and holds E4M3(x_c / s_t[c]) (OCP FP8 E4M3: 4 exponent bits with
+ * bias 7, 3 fraction bits, largest value 448, ties to even, saturating).
+ * Each 3x3 conv except the first folds its input's channel scales into the
+ * weight columns (W'[o][c] = W[o][c] s_in[c]) and stores W'[o] as E4M3 with
+ * its own power-of-two scale w_o; the MFMA sums exact FP8 products in FP32,
+ * and the epilogue forms w_o acc + b_o (+ the residual decoded with its
+ * scales), applies ReLU and encodes the result with the output's scales.
+ * The first conv (from the RGB tile), the controller and the head compute in
+ * FP32.  A scale is 2^ceil(log2(amax / 448)) of the channel's maximum over
+ * calibration tiles (1 if that maximum is 0).
+ *
+ * Activation table: one float per padded channel (pad32(C_l)) of every
+ * stored activation, ordered by kind then level: OMNISEG_ACT_ENC_A (conv_a
+ * outputs of encoder levels 0..L-1; level 0 is the first conv's output),
+ * OMNISEG_ACT_ENC_E (encoder block outputs E_0..E_{L-1}), OMNISEG_ACT_DEC_A
+ * (decoder conv_a outputs of levels 0..L-2), OMNISEG_ACT_DEC_D (decoder block
+ * outputs D_0..D_{L-2}).
+ */
+#define OMNISEG_ACT_ENC_A 0
+#define OMNISEG_ACT_ENC_E 1
+#define OMNISEG_ACT_DEC_A 2
+#define OMNISEG_ACT_DEC_D 3
+/* Length of the activation table of this plan's network (any precision). */
+int32_t omniseg_activation_channels(const omniseg_plan* plan, int64_t* count);
+/* Offset (in floats) of (kind, level) inside the activation table; ERR_ARG
+ * for a kind or level the network does not have. */
+int32_t omniseg_activation_offset(const omniseg_plan* plan, int32_t kind, int32_t level,
+                                  int64_t* offset);
+/*
+ * Calibration pass for the FP8 backbone.  `plan` must be an FP32 plan (no
+ * TRAINING flag) of the same network, `packed` its weights from
+ * omniseg_pack_weights.  Runs the backbone on the first min(n_tiles, kept)
+ * kept tiles of these slides in tile-list order (slide, scale slot, tile row,
+ * tile column) and writes each stored activation's per-channel maximum into
+ * amax (device, omniseg_activation_channels floats; padded channels get 0).
+ * Same slides, pairs and workspace rules as omniseg_segment_slide; no
+ * outputs are written.  Waits for the stream.  n_tiles >= 1.
+ */
+int32_t omniseg_calibrate_fp8(const omniseg_plan* plan, const void* packed,
+                              const omniseg_slide* slides, int32_t n_slides,
+                              const omniseg_pair* pairs, int32_t n_pairs, int32_t n_tiles,
+                              float* amax, void* workspace, int64_t ws_bytes,
+                              omniseg_stream stream);
+/*
+ * Pack canonical weights (device) for an FP8 plan, with the channel scales
+ * derived from `amax` (device activation table, e.g. from
+ * omniseg_calibrate_fp8).  The packed buffer (omniseg_packed_weight_bytes,
+ * 256-byte aligned) then also holds the scale tables the kernels read.
+ * omniseg_pack_weights refuses FP8 plans (ERR_UNSUPPORTED).
+ */
+int32_t omniseg_pack_weights_fp8(const omniseg_plan* plan, const float* canonical,
+                                 const float* amax, void* packed, omniseg_stream stream);
 
 /*
  * Workspace bytes that omniseg_segment_slide needs for these slides and
@@ -278,6 +339,26 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
                         int32_t cin, int32_t cu, int32_t cout, const float* weights,
                         const float* bias, const void* x0, const void* x1, const void* aux, void* y,
                         int32_t config, void* workspace, int64_t ws_bytes, omniseg_stream stream);
+/*
+ * FP8 form of omniseg_conv3x3 (modes RELU, RES_RELU, POOL_RELU, UPCAT_RELU;
+ * the FP8 backbone described at omniseg_pack_weights_fp8).  x0 (and x1 for
+ * UPCAT) hold E4M3 codes (uint8, NHWC, channels padded to 32) of
+ * non-negative activations whose channel c has the power-of-two scale
+ * in_scale[c] (device float[cin], real channel order: for UPCAT the cu
+ * upsampled channels, then the skip channels); y receives the E4M3 codes of
+ * the result with the power-of-two channel scales out_scale (device
+ * float[cout]).  The weights are quantised as omniseg_pack_weights_fp8 does,
+ * with in_scale folded into their columns; RES_RELU (cin == cout) decodes
+ * the residual with in_scale.  config: a configuration whose precisions
+ * include OMNISEG_FP8, or -1.  workspace: device, 256-byte aligned, >=
+ * omniseg_conv3x3_fp8_workspace_bytes.
+ */
+int32_t omniseg_conv3x3_fp8_workspace_bytes(int32_t cin, int32_t cu, int32_t cout, int64_t* bytes);
+int32_t omniseg_conv3x3_fp8(int32_t mode, int32_t n, int32_t height, int32_t width, int32_t cin,
+                            int32_t cu, int32_t cout, const float* weights, const float* bias,
+                            const float* in_scale, const float* out_scale, const void* x0,
+                            const void* x1, void* y, int32_t config, void* workspace,
+                            int64_t ws_bytes, omniseg_stream stream);
 
 /*
  * ---- training: forward over a tile batch, BCE loss, hand-written backward ----
@@ -382,9 +463,13 @@ typedef struct omniseg_launch_record {
 
 int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable);
 /* Shape of conv tile configuration `config`: pixel block by x bx, bn output
- * channels per workgroup, wm x wn waves.  ERR_ARG for an unknown id. */
+ * channels per workgroup, wm x wn waves; *precisions gets bit p set for each
+ * precision p (OMNISEG_FP32, OMNISEG_BF16, OMNISEG_FP8) the configuration
+ * runs at.
+ * Configurations 0..OMNISEG_CONV_CONFIGS-1 exist; ERR_ARG for any other id. */
+#define OMNISEG_CONV_CONFIGS 10
 int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* bn, int32_t* wm,
-                            int32_t* wn);
+                            int32_t* wn, int32_t* precisions);
 /*
  * Autotune the conv tile configuration of every backbone layer for these
  * slides and pairs: each valid configuration runs on the plan's batch shape

@@ -297,6 +297,66 @@ def round_bf16(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+E4M3_MAX = 448.0
+
+
+def round_e4m3(x):
+    """Round to the OCP FP8 E4M3 format (1 sign, 4 exponent bits with bias
+    7, 3 fraction bits, subnormals below 2^-6, largest finite value 448),
+    ties to even, after saturating magnitudes above 448 to 448.
+
+    Inside a binade [2^e, 2^(e+1)) the representable values are spaced
+    2^(e-3); below 2^-6 the spacing stays at 2^-9 (subnormals).  So the
+    value is rounded to a multiple of 2^(max(e, -6) - 3).  Used only to
+    emulate a path that stores activations and weights in FP8.
+    """
+    x = np.asarray(x, np.float64)
+    a = np.minimum(np.abs(x), E4M3_MAX)
+    _, ex = np.frexp(a)  # a = m 2^ex with m in [0.5, 1): binade exponent ex - 1
+    e = np.maximum(ex - 1, -6)
+    step = np.ldexp(1.0, e - 3)
+    q = np.rint(a / step) * step  # rint: ties to even
+    return np.where(x < 0, -q, q)
+
+
+def pow2_scale(amax):
+    """Power-of-two scale 2^ceil(log2(amax / 448)) that maps [0, amax] into
+    the E4M3 range; 1 for amax = 0.  Powers of two keep every rescaling
+    exact."""
+    amax = np.asarray(amax, np.float64)
+    out = np.ones_like(amax)
+    pos = amax > 0
+    r = amax[pos] / E4M3_MAX
+    m, ex = np.frexp(r)  # r = m 2^ex, m in [0.5, 1): ceil(log2 r) = ex - 1 if m == 0.5 else ex
+    out[pos] = np.ldexp(1.0, np.where(m == 0.5, ex - 1, ex))
+    return out
+
+
+def fp8_activation(X, scale):
+    """An activation [C, H, W] as an FP8 path stores it: channel c as
+    E4M3(X_c / s_c), read back as s_c E4M3(X_c / s_c)."""
+    s = np.asarray(scale, np.float64)[:, None, None]
+    return s * round_e4m3(X / s)
+
+
+def fp8_conv_weights(Wt, s_in):
+    """Weights of a 3x3 conv [Cout, Cin, 3, 3] as an FP8 path uses them.
+
+    The input's channel scale s_in[c] folds into column c (W'[o, c] =
+    W[o, c] s_in[c]); each output channel o then gets the power-of-two scale
+    w_o = pow2_scale(max |W'[o]|) and W' is stored as E4M3(W'[o] / w_o).
+    Returns the stored codes' values (q), the output scales w and the
+    effective weights w_o q[o, c] / s_in[c] that act on the real-valued
+    input, so that conv(fp8_activation(X), effective) is what the path
+    computes (up to its FP32 accumulation)."""
+    s_in = np.asarray(s_in, np.float64)
+    Wf = Wt * s_in[None, :, None, None]
+    w = pow2_scale(np.abs(Wf).reshape(Wf.shape[0], -1).max(axis=1))
+    q = round_e4m3(Wf / w[:, None, None, None])
+    eff = q * w[:, None, None, None] / s_in[None, :, None, None]
+    return q, w, eff
+
+
 def maxpool2(X):
     C, H, W = X.shape
     return X.reshape(C, H // 2, 2, W // 2, 2).max(axis=(2, 4))
@@ -317,7 +377,7 @@ def bf16_weights(wts):
     return out
 
 
-def unet_forward(x, wts, cfg, keep=False, store=None):
+def unet_forward(x, wts, cfg, keep=False, store=None, act_scales=None):
     """Residual U-Net on one tile.
 
     Encoder level l: A = ReLU(conv_a(X_l)); E_l = ReLU(conv_b(A) + A);
@@ -326,19 +386,27 @@ def unet_forward(x, wts, cfg, keep=False, store=None):
     with D_{L-1} = E_{L-1}.  Head input F = ReLU(W_p D_0 + b_p) if C_0 != 8,
     else D_0.  Returns (F, g) with g the pixel mean of E_{L-1}; with keep,
     also a dict of every intermediate for the reverse pass.  `store`, if
-    given, rounds every conv output as a reduced-precision path stores it.
+    given, rounds every conv output as a reduced-precision path stores it;
+    `act_scales` (tensor name -> per-channel scale, names as in
+    activation_names) instead stores each conv output as FP8 with its
+    channel scales (fp8_activation).
     """
     L = cfg["levels"]
     C = channels(cfg)
     saved = {}
-    q = store if store is not None else (lambda v: v)
+
+    def q(name, v):
+        if act_scales is not None:
+            return fp8_activation(v, act_scales[name])
+        return store(v) if store is not None else v
+
     X = x
     E = []
     for l in range(L):
         if l > 0:
             X = maxpool2(E[l - 1])
-        A = q(relu(conv3x3(X, wts[f"enc{l}.a.w"], wts[f"enc{l}.a.b"])))
-        El = q(relu(conv3x3(A, wts[f"enc{l}.b.w"], wts[f"enc{l}.b.b"]) + A))
+        A = q(f"enc{l}.A", relu(conv3x3(X, wts[f"enc{l}.a.w"], wts[f"enc{l}.a.b"])))
+        El = q(f"enc{l}.E", relu(conv3x3(A, wts[f"enc{l}.b.w"], wts[f"enc{l}.b.b"]) + A))
         if keep:
             saved[f"enc{l}.X"] = X
             saved[f"enc{l}.A"] = A
@@ -346,8 +414,8 @@ def unet_forward(x, wts, cfg, keep=False, store=None):
     D = E[L - 1]
     for l in range(L - 2, -1, -1):
         Z = np.concatenate([up2(D), E[l]], axis=0)
-        A = q(relu(conv3x3(Z, wts[f"dec{l}.a.w"], wts[f"dec{l}.a.b"])))
-        D = q(relu(conv3x3(A, wts[f"dec{l}.b.w"], wts[f"dec{l}.b.b"]) + A))
+        A = q(f"dec{l}.A", relu(conv3x3(Z, wts[f"dec{l}.a.w"], wts[f"dec{l}.a.b"])))
+        D = q(f"dec{l}.D", relu(conv3x3(A, wts[f"dec{l}.b.w"], wts[f"dec{l}.b.b"]) + A))
         if keep:
             saved[f"dec{l}.Z"] = Z
             saved[f"dec{l}.A"] = A
@@ -414,10 +482,83 @@ def head(F, theta, o):
     return z[0] if o == 1 else z[1] - z[0]
 
 
-def tile_logits(x, wts, cfg, si, classes, store=None):
+def tile_logits(x, wts, cfg, si, classes, store=None, act_scales=None):
     """Logits of one tile for the given classes (all at the tile's scale slot)."""
-    F, g = unet_forward(x, wts, cfg, store=store)
+    F, g = unet_forward(x, wts, cfg, store=store, act_scales=act_scales)
     return np.stack([head(F, controller(g, c, si, wts, cfg), cfg["head_out"]) for c in classes])
+
+
+# --------------------------------------------------------------------------
+# FP8 form of the backbone: per-channel power-of-two scales
+# --------------------------------------------------------------------------
+
+
+def activation_names(cfg):
+    """Names of the stored backbone activations: the output of every conv_a
+    (enc{l}.A, dec{l}.A) and of every residual block (enc{l}.E, dec{l}.D)."""
+    L = cfg["levels"]
+    return ([f"enc{l}.A" for l in range(L)] + [f"enc{l}.E" for l in range(L)] +
+            [f"dec{l}.A" for l in range(L - 1)] + [f"dec{l}.D" for l in range(L - 1)])
+
+
+def conv_input_scale(name, cfg, act_scales):
+    """Per-channel scale of the stored input of backbone conv `name`
+    ("enc{l}.a", "enc{l}.b", "dec{l}.a", "dec{l}.b"); None for the first
+    conv, which reads the RGB tile.  Max-pooling keeps the channel scales
+    (a positive per-channel factor commutes with max); the decoder's concat
+    input takes the upsampled tensor's scales, then the skip's."""
+    L = cfg["levels"]
+    part, l, ab = name[:3], int(name[3:-2]), name[-1]
+    if part == "enc":
+        if ab == "a":
+            return None if l == 0 else act_scales[f"enc{l - 1}.E"]
+        return act_scales[f"enc{l}.A"]
+    if ab == "a":
+        below = act_scales[f"enc{L - 1}.E"] if l + 1 == L - 1 else act_scales[f"dec{l + 1}.D"]
+        return np.concatenate([below, act_scales[f"enc{l}.E"]])
+    return act_scales[f"dec{l}.A"]
+
+
+def fp8_weights(wts, cfg, act_scales):
+    """Weights as the FP8 backbone uses them: every 3x3 conv except the
+    first gets the effective weights of fp8_conv_weights for its input's
+    channel scales; first conv, precls and controller stay as they are."""
+    out = dict(wts)
+    L = cfg["levels"]
+    convs = [f"enc{l}.{ab}" for l in range(L) for ab in "ab"] + [f"dec{l}.{ab}" for l in range(L - 1) for ab in "ab"]
+    for name in convs:
+        s_in = conv_input_scale(name, cfg, act_scales)
+        if s_in is not None:
+            out[name + ".w"] = fp8_conv_weights(wts[name + ".w"], s_in)[2]
+    return out
+
+
+def fp8_calibrate(tiles_x, wts, cfg):
+    """Per-channel activation scales from the exact forward pass over the
+    given tile inputs: pow2_scale of each stored tensor's per-channel
+    maximum (activations are ReLU outputs, so the maximum is the amax)."""
+    return {k: pow2_scale(v) for k, v in activation_amax(tiles_x, wts, cfg).items()}
+
+
+def activation_amax(tiles_x, wts, cfg):
+    """Per-channel maximum of every stored backbone activation (names as in
+    activation_names) over the exact forward passes of the given tiles."""
+    L = cfg["levels"]
+    amax = {}
+
+    def take(name, V):
+        m = V.reshape(V.shape[0], -1).max(axis=1)
+        amax[name] = m if name not in amax else np.maximum(amax[name], m)
+
+    for x in tiles_x:
+        _, _, sv = unet_forward(x, wts, cfg, keep=True)
+        for l in range(L):
+            take(f"enc{l}.A", sv[f"enc{l}.A"])
+            take(f"enc{l}.E", sv["E"][l])
+        for l in range(L - 1):
+            take(f"dec{l}.A", sv[f"dec{l}.A"])
+            take(f"dec{l}.D", sv[f"dec{l}.D"])
+    return amax
 
 
 # --------------------------------------------------------------------------
@@ -464,7 +605,7 @@ def fg_at_scale(fg, kc, k, H_k, W_k):
 # --------------------------------------------------------------------------
 
 
-def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False, emulate=None):
+def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False, emulate=None, fp8_scales=None):
     """Masks and stitched logits for every (slide, pair).
 
     slides: list of uint8 HWC arrays; pairs: list of (class, scale slot).
@@ -472,13 +613,19 @@ def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False
     'tiles' (the kept tile list), 'pad' per slide, 'fg' per slide, and with
     keep_tiles the per-tile logits {(n, si, jy, jx): {class: TxT}}.
     emulate="bf16" rounds weights and stored activations as a bfloat16
-    backbone does (round_bf16); the default is exact FP64.
+    backbone does (round_bf16); emulate="fp8" stores them as the FP8
+    backbone does, with the channel scales `fp8_scales` (from
+    fp8_calibrate); the default is exact FP64.
     """
     wts = unpack_weights(flat_weights, cfg)
     store = None
+    act_scales = None
     if emulate == "bf16":
         wts = bf16_weights(wts)
         store = round_bf16
+    elif emulate == "fp8":
+        act_scales = fp8_scales
+        wts = fp8_weights(wts, cfg, act_scales)
     T, s = cfg["tile"], cfg["stride"]
     kc = max(cfg["scales"])
     need_fg = cfg["fg_filter"] or cfg["mask_and_fg"]
@@ -493,7 +640,7 @@ def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False
             continue
         k = cfg["scales"][si]
         x = tile_input(slides[n], k, T, s, jy, jx)
-        lg = tile_logits(x, wts, cfg, si, classes, store=store)
+        lg = tile_logits(x, wts, cfg, si, classes, store=store, act_scales=act_scales)
         per_tile[(n, si, jy, jx)] = {c: lg[i] for i, c in enumerate(classes)}
     masks, logits = [], []
     for n, rgb in enumerate(slides):

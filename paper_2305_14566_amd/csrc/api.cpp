@@ -90,8 +90,12 @@ int32_t validate_config(const omniseg_config* c) {
   if (c->mask_and_fg != 0 && c->mask_and_fg != 1) return fail(OMNISEG_ERR_ARG, "mask_and_fg must be 0 or 1");
   if (c->fg_threshold < 1 || c->fg_threshold > 255)
     return fail(OMNISEG_ERR_ARG, "fg_threshold %d outside [1, 255]", c->fg_threshold);
-  if (c->precision != OMNISEG_FP32 && c->precision != OMNISEG_BF16)
+  if (c->precision != OMNISEG_FP32 && c->precision != OMNISEG_BF16 && c->precision != OMNISEG_FP8)
     return fail(OMNISEG_ERR_UNSUPPORTED, "unknown precision %d", c->precision);
+  if (c->precision == OMNISEG_FP8) {
+    if (c->flags & OMNISEG_FLAG_TRAINING) return fail(OMNISEG_ERR_UNSUPPORTED, "FP8 plans are inference only");
+    if (deep % 16) return fail(OMNISEG_ERR_UNSUPPORTED, "FP8 needs tile / 2^(levels-1) = %d a multiple of 16", deep);
+  }
   if (c->flags & ~(OMNISEG_FLAG_EMIT_LOGITS | OMNISEG_FLAG_TRAINING | OMNISEG_FLAG_GRAPH))
     return fail(OMNISEG_ERR_ARG, "unknown flags 0x%x", c->flags);
   if (c->batch_tiles < 0 || c->batch_tiles > 65536)
@@ -199,6 +203,110 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
   lay.total = off;
 }
 
+// Conv layer view of a packed weight buffer (with the FP8 scale tables).
+ConvLayer make_layer(const omniseg_plan* plan, const char* pk, const ConvDesc& d) {
+  ConvLayer L;
+  L.cin_p = d.cin_p;
+  L.cu_p = d.cu_p;
+  L.cout_p = d.cout_p;
+  L.w = pk + d.pk_w;
+  L.b = reinterpret_cast<const float*>(pk + d.pk_b);
+  if (plan->cfg.precision == OMNISEG_FP8) {
+    L.wscale = reinterpret_cast<const float*>(pk + d.pk_ws);
+    L.rscale = reinterpret_cast<const float*>(pk + plan->pk_scale) + d.act_in;
+    L.oinv = reinterpret_cast<const float*>(pk + plan->pk_iscale) + d.act_out;
+  }
+  return L;
+}
+
+// FP8 channel scales of the bottleneck E_{L-1} (GAP input) and of D_0 (head
+// input); null for other precisions.
+const float* fp8_scale_of(const omniseg_plan* plan, const char* pk, int kind, int level) {
+  if (plan->cfg.precision != OMNISEG_FP8) return nullptr;
+  return reinterpret_cast<const float*>(pk + plan->pk_scale) + plan->act_off[kind][level];
+}
+
+// Steps 1-2 of a call: slide table, pad colour, pyramid, tissue map, tile
+// flags and the compacted tile list; reads the kept-tile count back (waits
+// for the stream).
+int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, int32_t n_slides, const Layout& lay,
+                        char* ws, hipStream_t sm, Prof& prof, SlideDev** tab_out, int32_t* n_kept_out) {
+  const omniseg_config& c = plan->cfg;
+  const int T = c.tile, s = c.stride;
+  plan->slide_tab.assign(n_slides, SlideDev());
+  for (int i = 0; i < n_slides; ++i) {
+    SlideDev& d = plan->slide_tab[i];
+    d.rgb = slides[i].rgb;
+    d.pitch = slides[i].row_pitch;
+    d.H = slides[i].height;
+    d.W = slides[i].width;
+    d.pad = reinterpret_cast<const int32_t*>(ws + lay.off_pad[i]);
+    for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) {
+      d.pyr[si] = nullptr;
+      d.pyr_ex[si] = 0;
+      if (si < c.n_scales && lay.off_pyr[i][si] >= 0) {
+        d.pyr[si] = reinterpret_cast<const uint16_t*>(ws + lay.off_pyr[i][si]);
+        d.pyr_ex[si] = lay.geom[i][si].Ex;
+      }
+    }
+    d.fg = lay.need_fg ? reinterpret_cast<const uint8_t*>(ws + lay.off_fg[i]) : nullptr;
+    d.Hc = lay.Hc[i];
+    d.Wc = lay.Wc[i];
+  }
+  SlideDev* tab_dev = reinterpret_cast<SlideDev*>(ws + lay.off_tab);
+  *tab_out = tab_dev;
+  HIP_TRY(hipMemcpyAsync(tab_dev, plan->slide_tab.data(), sizeof(SlideDev) * n_slides,
+                         hipMemcpyHostToDevice, sm));
+
+  double prep_bytes = 0.0;
+  for (int i = 0; i < n_slides; ++i) {
+    prep_bytes += 3.0 * slides[i].height * slides[i].width;
+    for (int si = 0; si < c.n_scales; ++si)
+      if (lay.geom[i][si].k >= 1) prep_bytes += 6.0 * lay.geom[i][si].Ey * lay.geom[i][si].Ex;
+    prep_bytes += (double)lay.sz_fg[i];
+  }
+  HIP_TRY(prof.begin());
+
+  // 1. pad colour, pyramid, tissue map
+  for (int i = 0; i < n_slides; ++i) {
+    int32_t* pad = reinterpret_cast<int32_t*>(ws + lay.off_pad[i]);
+    HIP_TRY(launch_pad_colour(slides[i].rgb, slides[i].row_pitch, pad, sm));
+    uint16_t* lvl[4] = {nullptr, nullptr, nullptr, nullptr};
+    int Ey[4] = {0, 0, 0, 0}, Ex[4] = {0, 0, 0, 0};
+    for (int si = 0; si < c.n_scales; ++si) {
+      const ScaleGeom& g = lay.geom[i][si];
+      if (g.k >= 1) {
+        lvl[g.k] = reinterpret_cast<uint16_t*>(ws + lay.off_pyr[i][si]);
+        Ey[g.k] = g.Ey;
+        Ex[g.k] = g.Ex;
+      }
+    }
+    HIP_TRY(launch_pyramid(slides[i].rgb, slides[i].row_pitch, slides[i].height, slides[i].width, pad,
+                           lay.kmax, lvl, Ey, Ex, sm));
+    if (lay.need_fg) {
+      const uint16_t* sums = lay.kc >= 1 ? lvl[lay.kc] : nullptr;
+      const int ex = lay.kc >= 1 ? Ex[lay.kc] : 0;
+      HIP_TRY(launch_tissue(slides[i].rgb, slides[i].row_pitch, slides[i].height, slides[i].width, pad,
+                            sums, ex, lay.kc, lay.Hc[i], lay.Wc[i], c.fg_threshold,
+                            reinterpret_cast<uint8_t*>(ws + lay.off_fg[i]), sm));
+    }
+  }
+  // 2. tile flags and compaction; the kept-tile count sizes every later launch
+  int32_t* index = reinterpret_cast<int32_t*>(ws + lay.off_index);
+  int32_t* list = reinterpret_cast<int32_t*>(ws + lay.off_list);
+  int32_t* count = reinterpret_cast<int32_t*>(ws + lay.off_count);
+  HIP_TRY(launch_tile_flags(lay.groups, tab_dev, T, s, lay.kc, c.fg_filter, index, sm));
+  HIP_TRY(launch_compact(index, lay.total_tiles, lay.groups, list, count, sm));
+  HIP_TRY(prof.end(OMNISEG_STAGE_PREP, -1, 0, 0.0, prep_bytes));
+  int32_t n_kept = 0;
+  HIP_TRY(hipMemcpyAsync(&n_kept, count, sizeof(int32_t), hipMemcpyDeviceToHost, sm));
+  HIP_TRY(hipStreamSynchronize(sm));
+  if (n_kept < 0 || n_kept > lay.total_tiles)
+    return fail(OMNISEG_ERR_HIP, "kept-tile count %d outside [0, %d]", n_kept, lay.total_tiles);
+  *n_kept_out = n_kept;
+  return OMNISEG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -238,6 +346,21 @@ int32_t omniseg_plan_create(const omniseg_config* cfg, omniseg_plan** out) {
   p->G = p->C[p->L - 1];
   const int es = elem_size(cfg->precision);
   const bool training = (cfg->flags & OMNISEG_FLAG_TRAINING) != 0;
+  const bool fp8 = cfg->precision == OMNISEG_FP8;
+  // activation table: kind-major, level ascending
+  for (int k = 0; k < 4; ++k)
+    for (int l = 0; l < 8; ++l) p->act_off[k][l] = -1;
+  {
+    int64_t a = 0;
+    for (int k = 0; k < 4; ++k) {
+      const int nl = k < 2 ? p->L : p->L - 1;
+      for (int l = 0; l < nl; ++l) {
+        p->act_off[k][l] = a;
+        a += p->Cp[l];
+      }
+    }
+    p->n_act = a;
+  }
   int64_t canon = 0, pk = 0;
   auto ptake = [&](int64_t bytes) {
     int64_t o = pk;
@@ -255,9 +378,11 @@ int32_t omniseg_plan_create(const omniseg_config* cfg, omniseg_plan** out) {
     d.cu_p = cu_p;
     d.cin_p = cin_p;
     d.cout_p = pad_ch(cout);
-    d.pk_w = ptake((int64_t)d.cin_p * 9 * d.cout_p * es);
+    const int64_t kin = fp8 ? (int64_t)ceil_div(d.cin_p, kFp8Chunk) * kFp8Chunk : d.cin_p;
+    d.pk_w = ptake(kin * 9 * d.cout_p * es);
     d.pk_b = ptake((int64_t)d.cout_p * 4);
     d.pk_wt = training ? ptake((int64_t)d.cin_p * 9 * d.cout_p * es) : -1;
+    d.pk_ws = fp8 ? ptake((int64_t)d.cout_p * 4) : -1;
   };
   for (int l = 0; l < p->L; ++l) {
     if (l == 0) {
@@ -284,6 +409,27 @@ int32_t omniseg_plan_create(const omniseg_config* cfg, omniseg_plan** out) {
     canon += 8;
     p->pk_pre_w = ptake(8LL * p->C[0] * 4);
     p->pk_pre_b = ptake(8 * 4);
+  }
+  // activation-table offsets of each conv's input and output channel scales
+  for (int l = 0; l < p->L; ++l) {
+    if (l > 0) {
+      p->enc_a[l].act_in = p->act_off[OMNISEG_ACT_ENC_E][l - 1];
+      p->enc_a[l].act_out = p->act_off[OMNISEG_ACT_ENC_A][l];
+    }
+    p->enc_b[l].act_in = p->act_off[OMNISEG_ACT_ENC_A][l];
+    p->enc_b[l].act_out = p->act_off[OMNISEG_ACT_ENC_E][l];
+  }
+  for (int l = p->L - 2; l >= 0; --l) {
+    // D_{L-1} is E_{L-1}
+    p->dec_a[l].act_in = l + 1 == p->L - 1 ? p->act_off[OMNISEG_ACT_ENC_E][l + 1] : p->act_off[OMNISEG_ACT_DEC_D][l + 1];
+    p->dec_a[l].act_in_e = p->act_off[OMNISEG_ACT_ENC_E][l];
+    p->dec_a[l].act_out = p->act_off[OMNISEG_ACT_DEC_A][l];
+    p->dec_b[l].act_in = p->act_off[OMNISEG_ACT_DEC_A][l];
+    p->dec_b[l].act_out = p->act_off[OMNISEG_ACT_DEC_D][l];
+  }
+  if (fp8) {
+    p->pk_scale = ptake(p->n_act * 4);
+    p->pk_iscale = ptake(p->n_act * 4);
   }
   const int row = p->G + cfg->n_classes + cfg->n_scales;
   p->canon_ctrl_w = canon;
@@ -319,6 +465,8 @@ int32_t omniseg_pack_weights(const omniseg_plan* plan, const float* canonical, v
                              omniseg_stream stream) {
   if (!plan || !canonical || !packed) return fail(OMNISEG_ERR_ARG, "NULL argument");
   if (reinterpret_cast<uintptr_t>(packed) % 256) return fail(OMNISEG_ERR_ARG, "packed buffer not 256-byte aligned");
+  if (plan->cfg.precision == OMNISEG_FP8)
+    return fail(OMNISEG_ERR_UNSUPPORTED, "FP8 plans pack with omniseg_pack_weights_fp8 (activation scales needed)");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   (void)hipGetLastError();
   const int prec = plan->cfg.precision;
@@ -360,6 +508,150 @@ int32_t omniseg_pack_weights(const omniseg_plan* plan, const float* canonical, v
   const int row = plan->G + plan->cfg.n_classes + plan->cfg.n_scales;
   HIP_TRY(launch_copy_f32(canonical + plan->canon_ctrl_w, (float*)(pk + plan->pk_ctrl_w), (int64_t)plan->P * row, st));
   HIP_TRY(launch_copy_f32(canonical + plan->canon_ctrl_b, (float*)(pk + plan->pk_ctrl_b), plan->P, st));
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_activation_channels(const omniseg_plan* plan, int64_t* count) {
+  if (!plan || !count) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  *count = plan->n_act;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_activation_offset(const omniseg_plan* plan, int32_t kind, int32_t level, int64_t* offset) {
+  if (!plan || !offset) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  if (kind < 0 || kind > 3 || level < 0 || level > 7 || plan->act_off[kind][level] < 0)
+    return fail(OMNISEG_ERR_ARG, "no activation (kind %d, level %d) in this network", kind, level);
+  *offset = plan->act_off[kind][level];
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_pack_weights_fp8(const omniseg_plan* plan, const float* canonical, const float* amax, void* packed,
+                                 omniseg_stream stream) {
+  if (!plan || !canonical || !amax || !packed) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  if (plan->cfg.precision != OMNISEG_FP8) return fail(OMNISEG_ERR_ARG, "plan precision is not OMNISEG_FP8");
+  if (reinterpret_cast<uintptr_t>(packed) % 256) return fail(OMNISEG_ERR_ARG, "packed buffer not 256-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  char* pk = static_cast<char*>(packed);
+  float* scale = reinterpret_cast<float*>(pk + plan->pk_scale);
+  float* iscale = reinterpret_cast<float*>(pk + plan->pk_iscale);
+  HIP_TRY(launch_fp8_scales(amax, plan->n_act, scale, iscale, st));
+  auto pack = [&](const ConvDesc& d) -> hipError_t {
+    PackConv pc;
+    pc.src = d.canon_w;
+    pc.src_b = d.canon_b;
+    pc.cout = d.cout;
+    pc.cin = d.cin;
+    pc.cu = d.cu;
+    pc.cu_p = d.cu_p;
+    pc.cin_p = d.cin_p;
+    pc.cout_p = d.cout_p;
+    pc.dst = d.pk_w;
+    pc.dst_b = d.pk_b;
+    pc.transpose = 0;
+    return launch_pack_conv_fp8(canonical, packed, pc, scale + d.act_in, d.act_in_e >= 0 ? scale + d.act_in_e : nullptr,
+                                reinterpret_cast<float*>(pk + d.pk_ws), st);
+  };
+  HIP_TRY(launch_copy_f32(canonical + plan->canon_first_w, (float*)(pk + plan->pk_first_w), (int64_t)plan->C[0] * 27, st));
+  HIP_TRY(launch_copy_f32(canonical + plan->canon_first_b, (float*)(pk + plan->pk_first_b), plan->C[0], st));
+  for (int l = 0; l < plan->L; ++l) {
+    if (l > 0) HIP_TRY(pack(plan->enc_a[l]));
+    HIP_TRY(pack(plan->enc_b[l]));
+  }
+  for (int l = plan->L - 2; l >= 0; --l) {
+    HIP_TRY(pack(plan->dec_a[l]));
+    HIP_TRY(pack(plan->dec_b[l]));
+  }
+  if (plan->canon_pre_w >= 0) {
+    HIP_TRY(launch_copy_f32(canonical + plan->canon_pre_w, (float*)(pk + plan->pk_pre_w), 8LL * plan->C[0], st));
+    HIP_TRY(launch_copy_f32(canonical + plan->canon_pre_b, (float*)(pk + plan->pk_pre_b), 8, st));
+  }
+  const int row = plan->G + plan->cfg.n_classes + plan->cfg.n_scales;
+  HIP_TRY(launch_copy_f32(canonical + plan->canon_ctrl_w, (float*)(pk + plan->pk_ctrl_w), (int64_t)plan->P * row, st));
+  HIP_TRY(launch_copy_f32(canonical + plan->canon_ctrl_b, (float*)(pk + plan->pk_ctrl_b), plan->P, st));
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_calibrate_fp8(const omniseg_plan* plan, const void* packed, const omniseg_slide* slides,
+                              int32_t n_slides, const omniseg_pair* pairs, int32_t n_pairs, int32_t n_tiles,
+                              float* amax, void* workspace, int64_t ws_bytes, omniseg_stream stream) {
+  Layout lay;
+  int32_t st = validate_call(plan, slides, n_slides, pairs, n_pairs, lay);
+  if (st) return st;
+  if (plan->cfg.precision != OMNISEG_FP32) return fail(OMNISEG_ERR_ARG, "calibration runs on an FP32 plan");
+  if (n_tiles < 1) return fail(OMNISEG_ERR_ARG, "n_tiles %d < 1", n_tiles);
+  if (!packed || !workspace || !amax) return fail(OMNISEG_ERR_ARG, "NULL packed weights, workspace or amax");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 || reinterpret_cast<uintptr_t>(packed) % 256)
+    return fail(OMNISEG_ERR_ARG, "workspace and packed weights must be 256-byte aligned");
+  compute_layout(plan, slides, n_slides, lay);
+  if (ws_bytes < lay.total)
+    return fail(OMNISEG_ERR_WORKSPACE, "workspace has %lld bytes, needs %lld", (long long)ws_bytes, (long long)lay.total);
+  (void)hipGetLastError();
+  hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const char* pk = static_cast<const char*>(packed);
+  const omniseg_config& c = plan->cfg;
+  Prof prof{plan, sm};
+  plan->recs.clear();
+  SlideDev* tab_dev = nullptr;
+  int32_t n_kept = 0;
+  st = build_tile_list(plan, slides, n_slides, lay, ws, sm, prof, &tab_dev, &n_kept);
+  if (st) return st;
+  const int n = std::min(n_kept, n_tiles);
+  int32_t* list = reinterpret_cast<int32_t*>(ws + lay.off_list);
+  int32_t* count = reinterpret_cast<int32_t*>(ws + lay.off_count);
+  HIP_TRY(launch_zero(amax, plan->n_act * 4, sm));
+  const int T = c.tile, L = plan->L, B = lay.batch;
+  void* E[8];
+  for (int l = 0; l < L; ++l) E[l] = ws + lay.off_E[l];
+  void* A = ws + lay.off_A;
+  auto layer = [&](const ConvDesc& d) { return make_layer(plan, pk, d); };
+  auto stat = [&](const void* x, int nb, int h, int l, int kind) {
+    return launch_amax_channels(static_cast<const float*>(x), (int64_t)nb * h * h, plan->Cp[l],
+                                amax + plan->act_off[kind][l], sm);
+  };
+  FirstConvArgs fa;
+  fa.list = list;
+  fa.count = count;
+  fa.T = T;
+  fa.s = c.stride;
+  fa.w = reinterpret_cast<const float*>(pk + plan->pk_first_w);
+  fa.b = reinterpret_cast<const float*>(pk + plan->pk_first_b);
+  fa.c0 = plan->C[0];
+  fa.c0_p = plan->Cp[0];
+  fa.y = A;
+  fa.slides = tab_dev;
+  for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) fa.scale_k[si] = si < c.n_scales ? c.scale_log2[si] : 0;
+  const int prec = OMNISEG_FP32;
+  for (int base = 0; base < n; base += B) {
+    const int nb = std::min(B, n - base);
+    fa.chunk_base = base;
+    fa.batch = nb;
+    HIP_TRY(launch_first_conv(prec, fa, sm));
+    HIP_TRY(stat(A, nb, T, 0, OMNISEG_ACT_ENC_A));
+    int cf = layer_config(plan, 1, 0, T, T, plan->enc_b[0].cout_p);
+    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[0]), T, T, nb, count, base, A, nullptr, E[0], sm, nullptr, cf));
+    HIP_TRY(stat(E[0], nb, T, 0, OMNISEG_ACT_ENC_E));
+    for (int l = 1; l < L; ++l) {
+      const int tl = T >> l;
+      cf = layer_config(plan, 0, l, tl, tl, plan->enc_a[l].cout_p);
+      HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count, base, E[l - 1], nullptr, A, sm, nullptr, cf));
+      HIP_TRY(stat(A, nb, tl, l, OMNISEG_ACT_ENC_A));
+      cf = layer_config(plan, 1, l, tl, tl, plan->enc_b[l].cout_p);
+      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm, nullptr, cf));
+      HIP_TRY(stat(E[l], nb, tl, l, OMNISEG_ACT_ENC_E));
+    }
+    for (int l = L - 2; l >= 0; --l) {
+      const int tl = T >> l;
+      cf = layer_config(plan, 2, l, tl, tl, plan->dec_a[l].cout_p);
+      HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1], E[l], A, sm, nullptr, cf));
+      HIP_TRY(stat(A, nb, tl, l, OMNISEG_ACT_DEC_A));
+      cf = layer_config(plan, 3, l, tl, tl, plan->dec_b[l].cout_p);
+      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm, nullptr, cf));
+      HIP_TRY(stat(E[l], nb, tl, l, OMNISEG_ACT_DEC_D));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(sm));
   return OMNISEG_OK;
 }
 
@@ -463,77 +755,17 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   const char* pk = static_cast<const char*>(packed);
   const int T = c.tile, s = c.stride, prec = c.precision;
 
-  plan->slide_tab.assign(n_slides, SlideDev());
-  for (int i = 0; i < n_slides; ++i) {
-    SlideDev& d = plan->slide_tab[i];
-    d.rgb = slides[i].rgb;
-    d.pitch = slides[i].row_pitch;
-    d.H = slides[i].height;
-    d.W = slides[i].width;
-    d.pad = reinterpret_cast<const int32_t*>(ws + lay.off_pad[i]);
-    for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) {
-      d.pyr[si] = nullptr;
-      d.pyr_ex[si] = 0;
-      if (si < c.n_scales && lay.off_pyr[i][si] >= 0) {
-        d.pyr[si] = reinterpret_cast<const uint16_t*>(ws + lay.off_pyr[i][si]);
-        d.pyr_ex[si] = lay.geom[i][si].Ex;
-      }
-    }
-    d.fg = lay.need_fg ? reinterpret_cast<const uint8_t*>(ws + lay.off_fg[i]) : nullptr;
-    d.Hc = lay.Hc[i];
-    d.Wc = lay.Wc[i];
-  }
-  SlideDev* tab_dev = reinterpret_cast<SlideDev*>(ws + lay.off_tab);
-  HIP_TRY(hipMemcpyAsync(tab_dev, plan->slide_tab.data(), sizeof(SlideDev) * n_slides,
-                         hipMemcpyHostToDevice, sm));
-
   Prof prof{plan, sm};
   plan->recs.clear();
-  double prep_bytes = 0.0;
-  for (int i = 0; i < n_slides; ++i) {
-    prep_bytes += 3.0 * slides[i].height * slides[i].width;
-    for (int si = 0; si < c.n_scales; ++si)
-      if (lay.geom[i][si].k >= 1) prep_bytes += 6.0 * lay.geom[i][si].Ey * lay.geom[i][si].Ex;
-    prep_bytes += (double)lay.sz_fg[i];
+  SlideDev* tab_dev = nullptr;
+  int32_t n_kept = 0;
+  {
+    const int32_t pst = build_tile_list(plan, slides, n_slides, lay, ws, sm, prof, &tab_dev, &n_kept);
+    if (pst) return pst;
   }
-  HIP_TRY(prof.begin());
-
-  // 1. pad colour, pyramid, tissue map
-  for (int i = 0; i < n_slides; ++i) {
-    int32_t* pad = reinterpret_cast<int32_t*>(ws + lay.off_pad[i]);
-    HIP_TRY(launch_pad_colour(slides[i].rgb, slides[i].row_pitch, pad, sm));
-    uint16_t* lvl[4] = {nullptr, nullptr, nullptr, nullptr};
-    int Ey[4] = {0, 0, 0, 0}, Ex[4] = {0, 0, 0, 0};
-    for (int si = 0; si < c.n_scales; ++si) {
-      const ScaleGeom& g = lay.geom[i][si];
-      if (g.k >= 1) {
-        lvl[g.k] = reinterpret_cast<uint16_t*>(ws + lay.off_pyr[i][si]);
-        Ey[g.k] = g.Ey;
-        Ex[g.k] = g.Ex;
-      }
-    }
-    HIP_TRY(launch_pyramid(slides[i].rgb, slides[i].row_pitch, slides[i].height, slides[i].width, pad,
-                           lay.kmax, lvl, Ey, Ex, sm));
-    if (lay.need_fg) {
-      const uint16_t* sums = lay.kc >= 1 ? lvl[lay.kc] : nullptr;
-      const int ex = lay.kc >= 1 ? Ex[lay.kc] : 0;
-      HIP_TRY(launch_tissue(slides[i].rgb, slides[i].row_pitch, slides[i].height, slides[i].width, pad,
-                            sums, ex, lay.kc, lay.Hc[i], lay.Wc[i], c.fg_threshold,
-                            reinterpret_cast<uint8_t*>(ws + lay.off_fg[i]), sm));
-    }
-  }
-  // 2. tile flags and compaction; the kept-tile count sizes every later launch
   int32_t* index = reinterpret_cast<int32_t*>(ws + lay.off_index);
   int32_t* list = reinterpret_cast<int32_t*>(ws + lay.off_list);
   int32_t* count = reinterpret_cast<int32_t*>(ws + lay.off_count);
-  HIP_TRY(launch_tile_flags(lay.groups, tab_dev, T, s, lay.kc, c.fg_filter, index, sm));
-  HIP_TRY(launch_compact(index, lay.total_tiles, lay.groups, list, count, sm));
-  HIP_TRY(prof.end(OMNISEG_STAGE_PREP, -1, 0, 0.0, prep_bytes));
-  int32_t n_kept = 0;
-  HIP_TRY(hipMemcpyAsync(&n_kept, count, sizeof(int32_t), hipMemcpyDeviceToHost, sm));
-  HIP_TRY(hipStreamSynchronize(sm));
-  if (n_kept < 0 || n_kept > lay.total_tiles)
-    return fail(OMNISEG_ERR_HIP, "kept-tile count %d outside [0, %d]", n_kept, lay.total_tiles);
   if (n_kept > lay.logit_cap)
     return fail(OMNISEG_ERR_WORKSPACE, "%d tiles kept, the logit store holds %d (max_kept_tiles)", n_kept, lay.logit_cap);
 
@@ -548,15 +780,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
     float* g = reinterpret_cast<float*>(ws + lay.off_g);
     float* theta = reinterpret_cast<float*>(ws + lay.off_theta);
     float* logits = reinterpret_cast<float*>(ws + lay.off_logits);
-    auto layer = [&](const ConvDesc& d) {
-      ConvLayer L;
-      L.cin_p = d.cin_p;
-      L.cu_p = d.cu_p;
-      L.cout_p = d.cout_p;
-      L.w = pk + d.pk_w;
-      L.b = reinterpret_cast<const float*>(pk + d.pk_b);
-      return L;
-    };
+    auto layer = [&](const ConvDesc& d) { return make_layer(plan, pk, d); };
     const int es = elem_size(prec);
     // algorithmic work of one 3x3 conv launch over `nt` tiles at h x h
     auto conv_flops = [&](const ConvDesc& d, int h, int nt) { return 2.0 * 9 * d.cin * d.cout * (double)h * h * nt; };
@@ -577,6 +801,8 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
     fa.y = A;
     fa.slides = tab_dev;
     for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) fa.scale_k[si] = si < c.n_scales ? c.scale_log2[si] : 0;
+    if (prec == OMNISEG_FP8)
+      fa.oinv = reinterpret_cast<const float*>(pk + plan->pk_iscale) + plan->act_off[OMNISEG_ACT_ENC_A][0];
     const int L = plan->L;
     for (int base = 0; base < n_kept; base += B) {
       const int nb = std::min(B, n_kept - base);
@@ -603,7 +829,8 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
       }
       const int tb = T >> (L - 1);
       HIP_TRY(prof.begin());
-      HIP_TRY(launch_gap(prec, E[L - 1], nb, tb * tb, plan->Cp[L - 1], plan->G, count, base, g, sm));
+      HIP_TRY(launch_gap(prec, E[L - 1], nb, tb * tb, plan->Cp[L - 1], plan->G, count, base, g, sm,
+                         fp8_scale_of(plan, pk, OMNISEG_ACT_ENC_E, L - 1)));
       HIP_TRY(launch_controller(g, nb, plan->G, reinterpret_cast<const float*>(pk + plan->pk_ctrl_w),
                                 reinterpret_cast<const float*>(pk + plan->pk_ctrl_b), plan->P, c.n_classes,
                                 c.n_scales, lay.slots, lay.max_slots, list, count, base, theta, sm));
@@ -626,7 +853,8 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
       HIP_TRY(launch_head(prec, E[0], nb, T, plan->C[0], plan->Cp[0],
                           plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_w) : nullptr,
                           plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_b) : nullptr,
-                          theta, plan->P, c.head_out, lay.slots, lay.max_slots, list, count, base, logits, sm));
+                          theta, plan->P, c.head_out, lay.slots, lay.max_slots, list, count, base, logits, sm,
+                          L >= 2 ? fp8_scale_of(plan, pk, OMNISEG_ACT_DEC_D, 0) : fp8_scale_of(plan, pk, OMNISEG_ACT_ENC_E, 0)));
       {
         const double px = (double)T * T * nb;
         const double pre = plan->canon_pre_w >= 0 ? 2.0 * 8 * plan->C[0] : 0.0;
@@ -727,9 +955,13 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   return OMNISEG_OK;
 }
 
-int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* bn, int32_t* wm, int32_t* wn) {
-  if (config < 0 || config >= CONV_CFG_COUNT || !by || !bx || !bn || !wm || !wn)
+static_assert(CONV_CFG_COUNT == OMNISEG_CONV_CONFIGS, "configuration count in the header");
+
+int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* bn, int32_t* wm, int32_t* wn,
+                            int32_t* precisions) {
+  if (config < 0 || config >= CONV_CFG_COUNT || !by || !bx || !bn || !wm || !wn || !precisions)
     return fail(OMNISEG_ERR_ARG, "unknown conv config %d", config);
+  *precisions = conv_config_precisions(config);
   int a, b, c, d, e;
   conv_config_shape(config, &a, &b, &c, &d, &e);
   *by = a;
@@ -769,15 +1001,7 @@ int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_s
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  auto layer = [&](const ConvDesc& d) {
-    ConvLayer Ly;
-    Ly.cin_p = d.cin_p;
-    Ly.cu_p = d.cu_p;
-    Ly.cout_p = d.cout_p;
-    Ly.w = pk + d.pk_w;
-    Ly.b = reinterpret_cast<const float*>(pk + d.pk_b);
-    return Ly;
-  };
+  auto layer = [&](const ConvDesc& d) { return make_layer(plan, pk, d); };
   int32_t result = OMNISEG_OK;
   for (int stg = 0; stg < 4 && result == OMNISEG_OK; ++stg) {
     for (int l = 0; l < L && result == OMNISEG_OK; ++l) {
@@ -792,7 +1016,7 @@ int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_s
       int best = -1;
       float best_ms = 1e30f;
       for (int cf = 0; cf < CONV_CFG_COUNT; ++cf) {
-        if (!conv_config_valid(cf, h, h, d.cout_p)) continue;
+        if (!conv_config_valid(cf, prec, h, h, d.cout_p)) continue;
         hipError_t e = launch_conv3x3(prec, loader, epi, layer(d), h, h, B, count, 0, x0, x1, y, sm, nullptr, cf);
         if (e == hipSuccess) e = hipEventRecord(e0, sm);
         for (int r = 0; r < 2 && e == hipSuccess; ++r)
@@ -871,7 +1095,7 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
   if (mode == OMNISEG_CONV_DGRAD_RES_MASK && !aux) return fail(OMNISEG_ERR_ARG, "aux is NULL");
   {
     const int out_p = dgrad ? (cu < cin ? pad_ch(cu) + pad_ch(cin - cu) : pad_ch(cin)) : pad_ch(cout);
-    if (config != -1 && !conv_config_valid(config, height, width, out_p))
+    if (config != -1 && !conv_config_valid(config, precision, height, width, out_p))
       return fail(OMNISEG_ERR_ARG, "conv config %d does not fit %dx%d with %d output channels", config, height, width, out_p);
   }
   if (ws_bytes < need) return fail(OMNISEG_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
@@ -917,6 +1141,101 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
   static const int epi_of[] = {EPI_RELU, EPI_RES_RELU, EPI_RELU, EPI_RELU, EPI_NONE, EPI_RES_MASK};
   HIP_TRY(launch_conv3x3(precision, loader_of[mode], epi_of[mode], L, height, width, n, count, 0, x0, x1, y, sm, aux,
                          config));
+  return OMNISEG_OK;
+}
+
+namespace {
+struct Fp8ConvLayout {
+  int cu_p, cin_p, cout_p, nch;
+  int64_t w, b, ws, sin, oinv, total;
+};
+Fp8ConvLayout fp8_conv_layout(int cin, int cu, int cout) {
+  Fp8ConvLayout f;
+  f.cu_p = pad_ch(cu);
+  f.cin_p = cu < cin ? f.cu_p + pad_ch(cin - cu) : pad_ch(cin);
+  f.cout_p = pad_ch(cout);
+  f.nch = ceil_div(f.cin_p, kFp8Chunk);
+  f.w = 256;
+  f.b = f.w + align256((int64_t)f.nch * kFp8Chunk * 9 * f.cout_p);
+  f.ws = f.b + align256((int64_t)f.cout_p * 4);
+  f.sin = f.ws + align256((int64_t)f.cout_p * 4);
+  f.oinv = f.sin + align256((int64_t)f.cin_p * 4);
+  f.total = f.oinv + align256((int64_t)f.cout_p * 4);
+  return f;
+}
+}  // namespace
+
+int32_t omniseg_conv3x3_fp8_workspace_bytes(int32_t cin, int32_t cu, int32_t cout, int64_t* bytes) {
+  if (!bytes) return fail(OMNISEG_ERR_ARG, "bytes is NULL");
+  if (cin < 1 || cout < 1 || cu < 1 || cu > cin || cin > 8192 || cout > 8192) return fail(OMNISEG_ERR_ARG, "bad channel counts");
+  *bytes = fp8_conv_layout(cin, cu, cout).total;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_conv3x3_fp8(int32_t mode, int32_t n, int32_t height, int32_t width, int32_t cin, int32_t cu,
+                            int32_t cout, const float* weights, const float* bias, const float* in_scale,
+                            const float* out_scale, const void* x0, const void* x1, void* y, int32_t config,
+                            void* workspace, int64_t ws_bytes, omniseg_stream stream) {
+  int64_t need = 0;
+  int32_t st = omniseg_conv3x3_fp8_workspace_bytes(cin, cu, cout, &need);
+  if (st) return st;
+  if (mode < OMNISEG_CONV_RELU || mode > OMNISEG_CONV_UPCAT_RELU)
+    return fail(OMNISEG_ERR_UNSUPPORTED, "FP8 conv modes are RELU, RES_RELU, POOL_RELU and UPCAT_RELU");
+  if (n < 1 || height < 16 || width < 16 || height % 16 || width % 16 || height > 4096 || width > 4096)
+    return fail(OMNISEG_ERR_ARG, "n >= 1 and H, W multiples of 16 in [16, 4096] required");
+  if (!weights || !bias || !in_scale || !out_scale || !x0 || !y || !workspace) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  if (mode == OMNISEG_CONV_UPCAT_RELU) {
+    if (!x1 || cu >= cin) return fail(OMNISEG_ERR_ARG, "UPCAT needs x1 and cu < cin");
+  } else if (cu != cin) {
+    return fail(OMNISEG_ERR_ARG, "cu must equal cin outside UPCAT");
+  }
+  if (mode == OMNISEG_CONV_RES_RELU && cin != cout) return fail(OMNISEG_ERR_ARG, "RES_RELU needs cin == cout");
+  const Fp8ConvLayout f = fp8_conv_layout(cin, cu, cout);
+  if (config != -1 && !conv_config_valid(config, OMNISEG_FP8, height, width, f.cout_p))
+    return fail(OMNISEG_ERR_ARG, "conv config %d does not run FP8 at %dx%d with %d output channels", config, height,
+                width, f.cout_p);
+  if (conv_default_config(OMNISEG_FP8, height, width, f.cout_p) < 0)
+    return fail(OMNISEG_ERR_UNSUPPORTED, "no FP8 configuration fits %dx%d", height, width);
+  if (ws_bytes < need) return fail(OMNISEG_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OMNISEG_ERR_ARG, "workspace not 256-byte aligned");
+  hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  char* ws = static_cast<char*>(workspace);
+  int32_t* count = reinterpret_cast<int32_t*>(ws);
+  float* s_in = reinterpret_cast<float*>(ws + f.sin);
+  float* oinv = reinterpret_cast<float*>(ws + f.oinv);
+  float* wscale = reinterpret_cast<float*>(ws + f.ws);
+  HIP_TRY(launch_set_i32(count, n, sm));
+  HIP_TRY(launch_fp8_conv_scales(in_scale, cin, cu, cu < cin ? f.cu_p : f.cin_p, f.cin_p, out_scale, cout, f.cout_p,
+                                 s_in, oinv, sm));
+  PackConv pc;
+  pc.src = 0;
+  pc.src_b = 0;
+  pc.cout = cout;
+  pc.cin = cin;
+  pc.cu = cu;
+  pc.cu_p = cu < cin ? f.cu_p : f.cin_p;
+  pc.cin_p = f.cin_p;
+  pc.cout_p = f.cout_p;
+  pc.dst = f.w;
+  pc.dst_b = -1;
+  pc.transpose = 0;
+  HIP_TRY(launch_pack_conv_fp8(weights, ws, pc, s_in, s_in + pc.cu_p, wscale, sm));
+  HIP_TRY(launch_copy_f32(bias, reinterpret_cast<float*>(ws + f.b), cout, sm));
+  if (f.cout_p > cout) HIP_TRY(launch_zero(ws + f.b + (int64_t)cout * 4, (int64_t)(f.cout_p - cout) * 4, sm));
+  ConvLayer L;
+  L.cin_p = f.cin_p;
+  L.cu_p = pc.cu_p;
+  L.cout_p = f.cout_p;
+  L.w = ws + f.w;
+  L.b = reinterpret_cast<const float*>(ws + f.b);
+  L.wscale = wscale;
+  L.rscale = s_in;
+  L.oinv = oinv;
+  static const int loader_of[] = {LOAD_PLAIN, LOAD_PLAIN, LOAD_POOL, LOAD_UPCAT};
+  static const int epi_of[] = {EPI_RELU, EPI_RES_RELU, EPI_RELU, EPI_RELU};
+  HIP_TRY(launch_conv3x3(OMNISEG_FP8, loader_of[mode], epi_of[mode], L, height, width, n, count, 0, x0, x1, y, sm,
+                         nullptr, config));
   return OMNISEG_OK;
 }
 

@@ -81,9 +81,19 @@ struct ConvLayer {
   int cin_p;      // padded input channels (concat: cu_p + ce_p)
   int cu_p;       // UPCAT: padded channels of the upsampled source
   int cout_p;     // padded output channels
-  const void* w;  // packed weights [cin_p / KC][9][cout_p][KC]
+  const void* w;  // packed weights [ceil(cin_p / KC)][9][cout_p][KC]
   const float* b; // bias [cout_p]
+  // FP8 only: per-output-channel weight scale, the residual input's channel
+  // scales (residual epilogues) and the output tensor's inverse channel scales
+  const float* wscale = nullptr;
+  const float* rscale = nullptr;
+  const float* oinv = nullptr;
 };
+
+// FP8 E4M3 storage: channels per LDS chunk of the FP8 conv (one K = 64 MFMA
+// step per tap), and the largest finite magnitude.
+constexpr int kFp8Chunk = 64;
+constexpr float kFp8Max = 448.0f;
 
 enum Loader { LOAD_PLAIN = 0, LOAD_POOL = 1, LOAD_UPCAT = 2 };
 // RELU: ReLU(acc + bias).  RES_RELU: ReLU(acc + bias + x0).  NONE: acc (data
@@ -92,7 +102,11 @@ enum Loader { LOAD_PLAIN = 0, LOAD_POOL = 1, LOAD_UPCAT = 2 };
 enum Epilogue { EPI_RELU = 0, EPI_RES_RELU = 1, EPI_NONE = 2, EPI_RES_MASK = 3 };
 
 // 3x3 conv on a batch of tiles (NHWC, padded channels), output H x W per tile.
-// Conv tile configurations (pixel block, output channels, wave layout).
+// Conv tile configurations (pixel block, output channels, wave layout).  The
+// first six run for FP32 and BF16 with 16-pixel M fragments inside the
+// block; the ROWS configurations (BF16 only) give each wave whole 16-pixel
+// rows of the block and reuse every loaded halo row across the three
+// vertical taps.
 enum ConvConfig {
   CONV_CFG_8x16_32 = 0,
   CONV_CFG_8x16_64,
@@ -100,10 +114,16 @@ enum ConvConfig {
   CONV_CFG_8x16_128,
   CONV_CFG_8x8_32,
   CONV_CFG_8x8_64,
+  CONV_CFG_ROWS_16x16_64,
+  CONV_CFG_ROWS_16x16_128,
+  CONV_CFG_ROWS_32x16_32,
+  CONV_CFG_ROWS_16x16_32,
   CONV_CFG_COUNT
 };
-bool conv_config_valid(int cfg, int H, int W, int cout_p);
+bool conv_config_valid(int cfg, int precision, int H, int W, int cout_p);
 void conv_config_shape(int cfg, int* by, int* bx, int* bn, int* wm, int* wn);
+// Bit p set when the configuration runs at precision p.
+int conv_config_precisions(int cfg);
 int conv_default_config(int precision, int H, int W, int cout_p);
 
 // cfg < 0 (or not valid for the shape) picks the default configuration.
@@ -125,11 +145,14 @@ struct FirstConvArgs {
   void* y;  // [batch][T][T][c0_p]
   const SlideDev* slides;  // device array, one per slide
   int scale_k[OMNISEG_MAX_SCALES];
+  const float* oinv = nullptr;  // FP8: inverse channel scales of the output
 };
 hipError_t launch_first_conv(int precision, const FirstConvArgs& a, hipStream_t st);
 
+// scale: FP8 channel scales of e (null otherwise)
 hipError_t launch_gap(int precision, const void* e, int batch, int hw, int c_p, int c,
-                      const int32_t* count, int chunk_base, float* g, hipStream_t st);
+                      const int32_t* count, int chunk_base, float* g, hipStream_t st,
+                      const float* scale = nullptr);
 
 struct SlotTable {
   int n_slots[OMNISEG_MAX_SCALES];
@@ -141,11 +164,26 @@ hipError_t launch_controller(const float* g, int batch, int G, const float* wc, 
                              int max_slots, const int32_t* list, const int32_t* count,
                              int chunk_base, float* theta, hipStream_t st);
 
+// d0_scale: FP8 channel scales of d0 (null otherwise)
 hipError_t launch_head(int precision, const void* d0, int batch, int T, int c0, int c0_p,
                        const float* wp, const float* bp, const float* theta, int P, int o,
                        const SlotTable& slots, int max_slots, const int32_t* list,
                        const int32_t* count, int chunk_base, float* tile_logits,
-                       hipStream_t st);
+                       hipStream_t st, const float* d0_scale = nullptr);
+
+// ---- FP8 calibration and packing --------------------------------------------
+
+// amax[c] = max(amax[c], max over pixels of x[p][c]) for an FP32 tensor of
+// npix pixels x c_p channels whose values are >= 0 (ReLU outputs).
+hipError_t launch_amax_channels(const float* x, int64_t npix, int c_p, float* amax, hipStream_t st);
+// Padded-order scales of one stand-alone FP8 conv: s_in_pad[cp] = the real
+// input channel's scale (1 for padding), oinv[o] = 1 / out_scale[o] (1 for
+// padding).
+hipError_t launch_fp8_conv_scales(const float* in_scale, int cin, int cu, int cu_p, int cin_p,
+                                  const float* out_scale, int cout, int cout_p, float* s_in_pad, float* oinv,
+                                  hipStream_t st);
+// scale[i] = 2^ceil(log2(amax[i] / 448)) (1 for amax <= 0), inv[i] = 1 / scale[i].
+hipError_t launch_fp8_scales(const float* amax, int64_t n, float* scale, float* inv, hipStream_t st);
 
 struct StitchArgs {
   const float* logits;     // tile logits base
@@ -247,6 +285,12 @@ struct PackConv {
   int64_t dst_b;   // byte offset of packed bias (< 0: none)
   int transpose;   // 1: pack the data-gradient conv (channels swapped, taps flipped)
 };
+// FP8 packing of one conv: input channel scales s_in (padded channel order,
+// cin_p entries: the upsampled part's then the skip part's) fold into the
+// columns, each output channel gets a power-of-two scale (wscale[o]) and the
+// codes go to [ceil(cin_p / 64)][9][cout_p][64]; bias copied to dst_b.
+hipError_t launch_pack_conv_fp8(const float* canon, void* packed, const PackConv& p, const float* s_in_u,
+                                const float* s_in_e, float* wscale, hipStream_t st);
 hipError_t launch_pack_conv(int precision, const float* canon, void* packed, const PackConv& p,
                             hipStream_t st);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t st);

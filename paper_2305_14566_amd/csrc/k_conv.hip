@@ -25,6 +25,8 @@
 // + ReLU.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace omniseg {
 
 typedef __attribute__((ext_vector_type(4))) float f32x4;
@@ -51,6 +53,12 @@ struct ConvTraits<uint16_t> {
   static constexpr int VEC = 8;
   static constexpr int ROW = 40;
 };
+template <>
+struct ConvTraits<uint8_t> {
+  static constexpr int KC = kFp8Chunk;  // 64 FP8 channels = 64 bytes per pixel
+  static constexpr int VEC = 16;
+  static constexpr int ROW = 80;
+};
 
 struct ConvArgs {
   const void* x0;
@@ -64,6 +72,9 @@ struct ConvArgs {
   const int32_t* count;
   int chunk_base;
   int tiles_y, tiles_x, n_nblk;
+  const float* wscale;  // FP8 epilogue scales (see ConvLayer)
+  const float* rscale;
+  const float* oinv;
 };
 
 __device__ __forceinline__ uint4 vmax(uint4 a, uint4 b, float) {
@@ -80,6 +91,17 @@ __device__ __forceinline__ uint32_t bmax2(uint32_t a, uint32_t b) {
 }
 __device__ __forceinline__ uint4 vmax(uint4 a, uint4 b, uint16_t) {
   return make_uint4(bmax2(a.x, b.x), bmax2(a.y, b.y), bmax2(a.z, b.z), bmax2(a.w, b.w));
+}
+// FP8 activations are ReLU outputs: non-negative E4M3 codes (sign bit clear)
+// order like their values, so the max of the codes is the code of the max.
+__device__ __forceinline__ uint32_t u8max4(uint32_t a, uint32_t b) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < 32; i += 8) r |= max((a >> i) & 0xffu, (b >> i) & 0xffu) << i;
+  return r;
+}
+__device__ __forceinline__ uint4 vmax(uint4 a, uint4 b, uint8_t) {
+  return make_uint4(u8max4(a.x, b.x), u8max4(a.y, b.y), u8max4(a.z, b.z), u8max4(a.w, b.w));
 }
 
 template <typename T, int LOADER>
@@ -157,7 +179,8 @@ struct Stager {
       if (idx < HALO_V) {
         const int p = idx / NV, v = idx % NV;
         const int y = y0 + p / PX - 1, x = x0 + p % PX - 1;
-        if (y >= 0 && y < a.H && x >= 0 && x < a.W) fetch_vec<T, LOADER>(a, b, y, x, ch * KC + v * VEC, hreg[i]);
+        const int c = ch * KC + v * VEC;  // beyond cin_p only in an FP8 chunk's padding
+        if (y >= 0 && y < a.H && x >= 0 && x < a.W && c < a.cin_p) fetch_vec<T, LOADER>(a, b, y, x, c, hreg[i]);
       }
     }
     const T* wsrc = (const T*)a.w + (int64_t)ch * 9 * a.cout_p * KC;
@@ -311,6 +334,383 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
   }
 }
 
+// BF16 row-reuse form.  The block is BY rows x 16 pixels x BN channels; a
+// wave owns FM = BY / WM whole rows (one 16-pixel MFMA fragment each) and
+// BN / WN channels.  For each horizontal tap offset dx it reads the FM + 2
+// halo rows it needs once and feeds them to the three vertical taps, so an
+// input fragment read serves up to three MFMA groups instead of one.  The
+// weights are the MFMA's A operand (rows = output channels) and the pixels
+// its B operand, so each lane's accumulator holds four consecutive channels
+// of one pixel; the epilogue stages the FP32 results through LDS and writes
+// 16-byte vectors of the output (and reads the residual the same way).
+// Rounding is the same as in k_conv3x3: bias, residual and ReLU in FP32 on
+// the accumulator, then one rounding to BF16.
+template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
+// Two waves per SIMD where the registers allow it without spilling; the
+// 128-channel block and the pooled loads of the larger blocks (four raw
+// vectors staged per halo vector) take one.
+__global__ __launch_bounds__(256, ((BN >= 128 || (LOADER == LOAD_POOL && BY * BN > 512)) ? 1 : 2))
+void k_conv3x3_rows(ConvArgs a) {
+  using T = uint16_t;
+  using TR = ConvTraits<T>;
+  constexpr int KC = TR::KC, VEC = TR::VEC, ROW = TR::ROW;
+  constexpr int NV = KC / VEC;
+  constexpr int BX = 16, PX = BX + 2, NPIX = (BY + 2) * PX;
+  constexpr int FM = BY / WM;
+  constexpr int NW = BN / WN, FN = NW / 16;
+  static_assert(WM * WN == 4 && BY % WM == 0 && NW % 16 == 0, "wave layout");
+  constexpr int MAIN_B = (NPIX + 9 * BN) * ROW * (int)sizeof(T);
+  constexpr int OROW = BN + 4;  // FP32 values per pixel in the epilogue staging
+  constexpr int EPI_B = BY * BX * OROW * 4;
+  constexpr int SMEM_B = MAIN_B > EPI_B ? MAIN_B : EPI_B;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM_B];
+  T* sX = reinterpret_cast<T*>(smem);
+  T* sW = sX + NPIX * ROW;
+
+  int rest = blockIdx.x;
+  const int nb = rest % a.n_nblk;
+  rest /= a.n_nblk;
+  const int sxb = rest % a.tiles_x;
+  rest /= a.tiles_x;
+  const int syb = rest % a.tiles_y;
+  const int b = rest / a.tiles_y;
+  if (a.chunk_base + b >= *a.count) return;
+  const int y0 = syb * BY, x0 = sxb * BX, n0 = nb * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int kg = (lane >> 4) * VEC;
+  const int l16 = lane & 15;
+  const int xoff = (wm * FM * PX + l16) * ROW + kg;  // halo row wm*FM, column l16 (dx = 0)
+  const int woff = (wn * NW + l16) * ROW + kg;
+
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int HALO_V = NPIX * NV, W_V = 9 * BN * NV;
+  constexpr int HPT = (HALO_V + 255) / 256, WPT = (W_V + 255) / 256;
+  constexpr int LPV = (LOADER == LOAD_POOL) ? 4 : 1;
+  uint4 hreg[HPT][LPV];
+  uint4 wreg[WPT];
+  const int nchunks = a.cin_p / KC;
+  using ST = Stager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN>;
+  ST::fetch(a, b, tid, y0, x0, n0, 0, hreg, wreg);
+  ST::commit(tid, hreg, wreg, sX, sW);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ++ch) {
+    if (ch + 1 < nchunks) ST::fetch(a, b, tid, y0, x0, n0, ch + 1, hreg, wreg);
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      uint4 xv[FM + 2];
+#pragma unroll
+      for (int r = 0; r < FM + 2; ++r) xv[r] = *reinterpret_cast<const uint4*>(&sX[xoff + (r * PX + dx) * ROW]);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int tap = dy * 3 + dx;
+        uint4 wv[FN];
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+          wv[fn] = *reinterpret_cast<const uint4*>(&sW[tap * BN * ROW + woff + fn * 16 * ROW]);
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < FN; ++fn) mma(acc[fm][fn], wv[fn], xv[fm + dy], T());
+      }
+    }
+    __syncthreads();
+    if (ch + 1 < nchunks) {
+      ST::commit(tid, hreg, wreg, sX, sW);
+      __syncthreads();
+    }
+  }
+
+  // Epilogue: accumulators -> LDS [pixel][channel] (FP32) -> 16-byte rows.
+  float* sO = reinterpret_cast<float*>(smem);
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) {
+      const int p = (wm * FM + fm) * BX + l16;
+      const int c = wn * NW + fn * 16 + (lane >> 4) * 4;
+      *reinterpret_cast<f32x4*>(&sO[p * OROW + c]) = acc[fm][fn];
+    }
+  __syncthreads();
+  constexpr int NVO = BN / 8;
+  T* out = (T*)a.y;
+  const T* res = (const T*)a.x0;
+  for (int i = tid; i < BY * BX * NVO; i += 256) {
+    const int p = i / NVO, c = (i % NVO) * 8;
+    const int y = y0 + p / BX, x = x0 + p % BX, n = n0 + c;
+    const int64_t o = (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + n;
+    const f32x4 lo = *reinterpret_cast<const f32x4*>(&sO[p * OROW + c]);
+    const f32x4 hi = *reinterpret_cast<const f32x4*>(&sO[p * OROW + c + 4]);
+    float v[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    if (EPI == EPI_RELU || EPI == EPI_RES_RELU) {
+      const float4 b0 = *reinterpret_cast<const float4*>(a.bias + n);
+      const float4 b1 = *reinterpret_cast<const float4*>(a.bias + n + 4);
+      v[0] += b0.x; v[1] += b0.y; v[2] += b0.z; v[3] += b0.w;
+      v[4] += b1.x; v[5] += b1.y; v[6] += b1.z; v[7] += b1.w;
+    }
+    if (EPI == EPI_RES_RELU || EPI == EPI_RES_MASK) {
+      const uint4 r = *reinterpret_cast<const uint4*>(res + o);
+      const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[2 * j] += bf2f(rw[j] & 0xffff);
+        v[2 * j + 1] += bf2f(rw[j] >> 16);
+      }
+    }
+    if (EPI == EPI_RES_MASK) {
+      const uint4 g = *reinterpret_cast<const uint4*>((const T*)a.aux + o);
+      const uint32_t gw[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!(bf2f(gw[j] & 0xffff) > 0.f)) v[2 * j] = 0.f;
+        if (!(bf2f(gw[j] >> 16) > 0.f)) v[2 * j + 1] = 0.f;
+      }
+    }
+    if (EPI == EPI_RELU || EPI == EPI_RES_RELU) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = fmaxf(v[j], 0.f);
+    }
+    uint4 u;
+    u.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+    u.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+    u.z = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
+    u.w = (uint32_t)f2bf(v[6]) | ((uint32_t)f2bf(v[7]) << 16);
+    *reinterpret_cast<uint4*>(out + o) = u;
+  }
+}
+
+// FP8 (E4M3) row-reuse form on v_mfma_scale_f32_32x32x64_f8f6f4 (unit block
+// scales): one MFMA is one tap of a 64-channel chunk for 32 output channels
+// (A, weights) x 32 pixels (B).  A pixel fragment is two 16-pixel rows; lane
+// l holds pixel column l & 15 of row (l >> 4) & 1 and K half l >> 5 (32
+// channels, two 16-byte LDS reads).  Per horizontal offset dx a wave reads
+// the 2 FM + 1 halo rows its FM fragments need once and feeds them to the
+// three vertical taps.  The accumulator of lane l holds channels
+// 8 (r / 4) + 4 (l >> 5) + r % 4 (r = 0..15) of pixel l & 31.  Epilogue:
+// v = wscale[o] acc + bias[o] (+ residual code * rscale[o]), ReLU, then
+// E4M3(min(v * oinv[o], 448)).
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+__device__ __forceinline__ float fp8_decode(uint32_t word, int byte) {
+  switch (byte) {
+    case 0: return __builtin_amdgcn_cvt_f32_fp8(word, 0);
+    case 1: return __builtin_amdgcn_cvt_f32_fp8(word, 1);
+    case 2: return __builtin_amdgcn_cvt_f32_fp8(word, 2);
+    default: return __builtin_amdgcn_cvt_f32_fp8(word, 3);
+  }
+}
+// four non-negative values -> four E4M3 codes (saturated at 448)
+__device__ __forceinline__ uint32_t fp8_encode4(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(a, kFp8Max), fminf(b, kFp8Max), 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(c, kFp8Max), fminf(d, kFp8Max), w, true);
+  return (uint32_t)w;
+}
+
+template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
+__global__ __launch_bounds__(256, ((BN >= 128 || LOADER == LOAD_POOL) ? 1 : 2))
+void k_conv3x3_fp8(ConvArgs a) {
+  using T = uint8_t;
+  using TR = ConvTraits<T>;
+  constexpr int KC = TR::KC, VEC = TR::VEC, ROW = TR::ROW;
+  constexpr int NV = KC / VEC;
+  constexpr int BX = 16, PX = BX + 2, NPIX = (BY + 2) * PX;
+  constexpr int RPW = BY / WM;       // pixel rows per wave
+  constexpr int FM = RPW / 2;        // two-row pixel fragments per wave
+  constexpr int NW = BN / WN, FN = NW / 32;
+  static_assert(WM * WN == 4 && BY % WM == 0 && RPW % 2 == 0 && NW % 32 == 0, "wave layout");
+  constexpr int MAIN_B = (NPIX + 9 * BN) * ROW;
+  constexpr int OROW = BN + 4;
+  constexpr int EPI_B = BY * BX * OROW * 4;
+  constexpr int SMEM_B = MAIN_B > EPI_B ? MAIN_B : EPI_B;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SMEM_B];
+  T* sX = reinterpret_cast<T*>(smem);
+  T* sW = sX + NPIX * ROW;
+
+  int rest = blockIdx.x;
+  const int nb = rest % a.n_nblk;
+  rest /= a.n_nblk;
+  const int sxb = rest % a.tiles_x;
+  rest /= a.tiles_x;
+  const int syb = rest % a.tiles_y;
+  const int b = rest / a.tiles_y;
+  if (a.chunk_base + b >= *a.count) return;
+  const int y0 = syb * BY, x0 = sxb * BX, n0 = nb * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int kh = (lane >> 5) * 32;       // K half of this lane, in bytes
+  const int ro = (lane >> 4) & 1;        // row of this lane inside a pixel fragment
+  const int l16 = lane & 15;
+  const int xoff = ((wm * RPW + ro) * PX + l16) * ROW + kh;
+  const int woff = (wn * NW + (lane & 31)) * ROW + kh;
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  constexpr int HALO_V = NPIX * NV, W_V = 9 * BN * NV;
+  constexpr int HPT = (HALO_V + 255) / 256, WPT = (W_V + 255) / 256;
+  constexpr int LPV = (LOADER == LOAD_POOL) ? 4 : 1;
+  uint4 hreg[HPT][LPV];
+  uint4 wreg[WPT];
+  const int nchunks = (a.cin_p + KC - 1) / KC;
+  using ST = Stager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN>;
+  ST::fetch(a, b, tid, y0, x0, n0, 0, hreg, wreg);
+  ST::commit(tid, hreg, wreg, sX, sW);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ++ch) {
+    if (ch + 1 < nchunks) ST::fetch(a, b, tid, y0, x0, n0, ch + 1, hreg, wreg);
+#pragma unroll 1  // one dx at a time: the halo rows of all three would not fit in registers
+    for (int dx = 0; dx < 3; ++dx) {
+      i32x8 xv[2 * FM + 1];
+#pragma unroll
+      for (int r = 0; r < 2 * FM + 1; ++r) {
+        const uint4 lo = *reinterpret_cast<const uint4*>(&sX[xoff + (r * PX + dx) * ROW]);
+        const uint4 hi = *reinterpret_cast<const uint4*>(&sX[xoff + (r * PX + dx) * ROW + 16]);
+        xv[r] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      }
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int tap = dy * 3 + dx;
+        i32x8 wv[FN];
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+          const T* src = &sW[tap * BN * ROW + woff + fn * 32 * ROW];
+          const uint4 lo = *reinterpret_cast<const uint4*>(src);
+          const uint4 hi = *reinterpret_cast<const uint4*>(src + 16);
+          wv[fn] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        }
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < FN; ++fn)
+            acc[fm][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(wv[fn], xv[2 * fm + dy], acc[fm][fn],
+                                                                          0, 0, 0, 127, 0, 127);
+      }
+    }
+    __syncthreads();
+    if (ch + 1 < nchunks) {
+      ST::commit(tid, hreg, wreg, sX, sW);
+      __syncthreads();
+    }
+  }
+
+  // Epilogue: accumulators -> LDS [pixel][channel] (FP32) -> 16-byte rows of codes.
+  float* sO = reinterpret_cast<float*>(smem);
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int p = (wm * RPW + 2 * fm + ro) * BX + l16;
+        const int c = wn * NW + fn * 32 + 8 * q + 4 * (lane >> 5);
+        *reinterpret_cast<f32x4*>(&sO[p * OROW + c]) =
+            f32x4{acc[fm][fn][4 * q], acc[fm][fn][4 * q + 1], acc[fm][fn][4 * q + 2], acc[fm][fn][4 * q + 3]};
+      }
+  __syncthreads();
+  constexpr int NVO = BN / 16;
+  T* out = (T*)a.y;
+  const T* res = (const T*)a.x0;
+  for (int i = tid; i < BY * BX * NVO; i += 256) {
+    const int p = i / NVO, c = (i % NVO) * 16;
+    const int y = y0 + p / BX, x = x0 + p % BX, n = n0 + c;
+    const int64_t o = (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + n;
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 16; j += 4) {
+      const f32x4 t = *reinterpret_cast<const f32x4*>(&sO[p * OROW + c + j]);
+      const float4 ws = *reinterpret_cast<const float4*>(a.wscale + n + j);
+      const float4 bs = *reinterpret_cast<const float4*>(a.bias + n + j);
+      v[j] = fmaf(t[0], ws.x, bs.x);
+      v[j + 1] = fmaf(t[1], ws.y, bs.y);
+      v[j + 2] = fmaf(t[2], ws.z, bs.z);
+      v[j + 3] = fmaf(t[3], ws.w, bs.w);
+    }
+    if (EPI == EPI_RES_RELU) {
+      const uint4 r = *reinterpret_cast<const uint4*>(res + o);
+      const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] += fp8_decode(rw[j / 4], j % 4) * a.rscale[n + j];
+    }
+    uint32_t ow[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float e[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float t = v[4 * j + k];
+        e[k] = (t > 0.f ? t : 0.f) * a.oinv[n + 4 * j + k];  // ReLU; +0 for the rest
+      }
+      ow[j] = fp8_encode4(e[0], e[1], e[2], e[3]);
+    }
+    *reinterpret_cast<uint4*>(out + o) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+  }
+}
+
+template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
+static hipError_t launch_conv_fp8_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
+                                    int chunk_base, const void* x0, const void* x1, void* y, hipStream_t st) {
+  ConvArgs a;
+  a.x0 = x0;
+  a.x1 = x1;
+  a.aux = nullptr;
+  a.y = y;
+  a.w = L.w;
+  a.bias = L.b;
+  a.H = H;
+  a.W = W;
+  a.cin_p = L.cin_p;
+  a.cu_p = L.cu_p;
+  a.cout_p = L.cout_p;
+  a.count = count;
+  a.chunk_base = chunk_base;
+  a.tiles_y = H / BY;
+  a.tiles_x = W / 16;
+  a.n_nblk = L.cout_p / BN;
+  a.wscale = L.wscale;
+  a.rscale = L.rscale;
+  a.oinv = L.oinv;
+  const int64_t blocks = (int64_t)batch * a.tiles_y * a.tiles_x * a.n_nblk;
+  hipLaunchKernelGGL((k_conv3x3_fp8<BY, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
+static hipError_t launch_conv_rows_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
+                                     int chunk_base, const void* x0, const void* x1, const void* aux,
+                                     void* y, hipStream_t st) {
+  ConvArgs a;
+  a.x0 = x0;
+  a.x1 = x1;
+  a.aux = aux;
+  a.y = y;
+  a.w = L.w;
+  a.bias = L.b;
+  a.H = H;
+  a.W = W;
+  a.cin_p = L.cin_p;
+  a.cu_p = L.cu_p;
+  a.cout_p = L.cout_p;
+  a.count = count;
+  a.chunk_base = chunk_base;
+  a.tiles_y = H / BY;
+  a.tiles_x = W / 16;
+  a.n_nblk = L.cout_p / BN;
+  const int64_t blocks = (int64_t)batch * a.tiles_y * a.tiles_x * a.n_nblk;
+  hipLaunchKernelGGL((k_conv3x3_rows<BY, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 template <typename T, int BY, int BX, int BN, int WM, int WN, int LOADER, int EPI>
 static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
                                 int chunk_base, const void* x0, const void* x1, const void* aux,
@@ -347,40 +747,53 @@ static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, con
   X(CONV_CFG_8x16_128, 8, 16, 128, 2, 2)  \
   X(CONV_CFG_8x8_32, 8, 8, 32, 4, 1)      \
   X(CONV_CFG_8x8_64, 8, 8, 64, 2, 2)
+// Row-reuse configurations (BF16): BY rows of 16 pixels, BN channels, waves.
+#define OMNISEG_CONV_ROW_CONFIGS(X)             \
+  X(CONV_CFG_ROWS_16x16_64, 16, 16, 64, 2, 2)   \
+  X(CONV_CFG_ROWS_16x16_128, 16, 16, 128, 2, 2) \
+  X(CONV_CFG_ROWS_32x16_32, 32, 16, 32, 4, 1)   \
+  X(CONV_CFG_ROWS_16x16_32, 16, 16, 32, 4, 1)
 
-static const int kCfgShape[][3] = {
-#define OMNISEG_SHAPE(id, by, bx, bn, wm, wn) {by, bx, bn},
-    OMNISEG_CONV_CONFIGS(OMNISEG_SHAPE)
+static const int kCfgShape[][5] = {
+#define OMNISEG_SHAPE(id, by, bx, bn, wm, wn) {by, bx, bn, wm, wn},
+    OMNISEG_CONV_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW_CONFIGS(OMNISEG_SHAPE)
 #undef OMNISEG_SHAPE
 };
+static_assert(sizeof(kCfgShape) / sizeof(kCfgShape[0]) == CONV_CFG_COUNT, "one shape per configuration");
 
 void conv_config_shape(int cfg, int* by, int* bx, int* bn, int* wm, int* wn) {
-  static const int t[][5] = {
-#define OMNISEG_T(id, a, b, c, d, e) {a, b, c, d, e},
-      OMNISEG_CONV_CONFIGS(OMNISEG_T)
-#undef OMNISEG_T
-  };
-  *by = t[cfg][0];
-  *bx = t[cfg][1];
-  *bn = t[cfg][2];
-  *wm = t[cfg][3];
-  *wn = t[cfg][4];
+  *by = kCfgShape[cfg][0];
+  *bx = kCfgShape[cfg][1];
+  *bn = kCfgShape[cfg][2];
+  *wm = kCfgShape[cfg][3];
+  *wn = kCfgShape[cfg][4];
 }
 
-bool conv_config_valid(int cfg, int H, int W, int cout_p) {
-  if (cfg < 0 || cfg >= CONV_CFG_COUNT) return false;
+int conv_config_precisions(int cfg) {
+  if (cfg < 0 || cfg >= CONV_CFG_COUNT) return 0;
+  return cfg >= CONV_CFG_ROWS_16x16_64 ? (1 << OMNISEG_BF16) | (1 << OMNISEG_FP8)
+                                       : (1 << OMNISEG_FP32) | (1 << OMNISEG_BF16);
+}
+
+bool conv_config_valid(int cfg, int precision, int H, int W, int cout_p) {
+  if (cfg < 0 || cfg >= CONV_CFG_COUNT || precision < 0 || precision > 30) return false;
+  if (!(conv_config_precisions(cfg) & (1 << precision))) return false;
   return H % kCfgShape[cfg][0] == 0 && W % kCfgShape[cfg][1] == 0 && cout_p % kCfgShape[cfg][2] == 0;
 }
 
 int conv_default_config(int precision, int H, int W, int cout_p) {
   const int order_bf16[] = {CONV_CFG_16x16_64, CONV_CFG_8x16_64, CONV_CFG_8x16_32, CONV_CFG_8x8_64, CONV_CFG_8x8_32};
   const int order_f32[] = {CONV_CFG_8x16_64, CONV_CFG_8x16_32, CONV_CFG_8x8_64, CONV_CFG_8x8_32};
-  if (precision == OMNISEG_BF16) {
+  const int order_fp8[] = {CONV_CFG_ROWS_16x16_64, CONV_CFG_ROWS_16x16_32};
+  if (precision == OMNISEG_FP8) {
+    for (int c : order_fp8)
+      if (conv_config_valid(c, precision, H, W, cout_p)) return c;
+  } else if (precision == OMNISEG_BF16) {
     for (int c : order_bf16)
-      if (conv_config_valid(c, H, W, cout_p)) return c;
+      if (conv_config_valid(c, precision, H, W, cout_p)) return c;
   } else {
     for (int c : order_f32)
-      if (conv_config_valid(c, H, W, cout_p)) return c;
+      if (conv_config_valid(c, precision, H, W, cout_p)) return c;
   }
   return -1;
 }
@@ -396,8 +809,20 @@ static hipError_t launch_conv_cfg(int cfg, const ConvLayer& L, int H, int W, int
     OMNISEG_CONV_CONFIGS(OMNISEG_CASE)
 #undef OMNISEG_CASE
     default:
-      return hipErrorInvalidValue;
+      break;
   }
+  if constexpr (std::is_same<T, uint16_t>::value) {
+    switch (cfg) {
+#define OMNISEG_CASE(id, by, bx, bn, wm, wn) \
+  case id:                                   \
+    return launch_conv_rows_t<by, bn, wm, wn, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+      OMNISEG_CONV_ROW_CONFIGS(OMNISEG_CASE)
+#undef OMNISEG_CASE
+      default:
+        break;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -417,11 +842,40 @@ static hipError_t launch_conv_mode(int cfg, int loader, int epi, const ConvLayer
   return hipErrorInvalidValue;
 }
 
+template <int LOADER, int EPI>
+static hipError_t launch_fp8_cfg(int cfg, const ConvLayer& L, int H, int W, int batch, const int32_t* count,
+                                 int chunk_base, const void* x0, const void* x1, void* y, hipStream_t st) {
+  switch (cfg) {
+#define OMNISEG_CASE(id, by, bx, bn, wm, wn) \
+  case id:                                   \
+    return launch_conv_fp8_t<by, bn, wm, wn, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, y, st);
+    OMNISEG_CONV_ROW_CONFIGS(OMNISEG_CASE)
+#undef OMNISEG_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t launch_fp8_mode(int cfg, int loader, int epi, const ConvLayer& L, int H, int W, int batch,
+                                  const int32_t* count, int chunk_base, const void* x0, const void* x1, void* y,
+                                  hipStream_t st) {
+  if (!L.wscale || !L.oinv || (epi == EPI_RES_RELU && !L.rscale)) return hipErrorInvalidValue;
+#define OMNISEG_FP8_CASE(LD, EP) \
+  if (loader == LD && epi == EP) return launch_fp8_cfg<LD, EP>(cfg, L, H, W, batch, count, chunk_base, x0, x1, y, st);
+  OMNISEG_FP8_CASE(LOAD_PLAIN, EPI_RES_RELU)
+  OMNISEG_FP8_CASE(LOAD_POOL, EPI_RELU)
+  OMNISEG_FP8_CASE(LOAD_UPCAT, EPI_RELU)
+  OMNISEG_FP8_CASE(LOAD_PLAIN, EPI_RELU)
+#undef OMNISEG_FP8_CASE
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L, int H, int W,
                           int batch, const int32_t* count, int chunk_base, const void* x0,
                           const void* x1, void* y, hipStream_t st, const void* aux, int cfg) {
-  if (cfg < 0 || !conv_config_valid(cfg, H, W, L.cout_p)) cfg = conv_default_config(precision, H, W, L.cout_p);
+  if (cfg < 0 || !conv_config_valid(cfg, precision, H, W, L.cout_p)) cfg = conv_default_config(precision, H, W, L.cout_p);
   if (cfg < 0) return hipErrorInvalidValue;
+  if (precision == OMNISEG_FP8) return launch_fp8_mode(cfg, loader, epi, L, H, W, batch, count, chunk_base, x0, x1, y, st);
   if (precision == OMNISEG_BF16)
     return launch_conv_mode<uint16_t>(cfg, loader, epi, L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
   return launch_conv_mode<float>(cfg, loader, epi, L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
@@ -439,6 +893,13 @@ constexpr int kFirstMaxC0 = 128;
 
 __device__ __forceinline__ void store_vec(float* p, const float* v) {
   *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+// FP8: 16 channels per vector, each multiplied by its inverse channel scale
+// before encoding (values are ReLU outputs, >= 0).
+__device__ __forceinline__ void store_vec(uint8_t* p, const float* v) {
+  *reinterpret_cast<uint4*>(p) = make_uint4(fp8_encode4(v[0], v[1], v[2], v[3]), fp8_encode4(v[4], v[5], v[6], v[7]),
+                                            fp8_encode4(v[8], v[9], v[10], v[11]),
+                                            fp8_encode4(v[12], v[13], v[14], v[15]));
 }
 __device__ __forceinline__ void store_vec(uint16_t* p, const float* v) {
   uint4 u;
@@ -522,7 +983,8 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
         acc = wr[27];
 #pragma unroll
         for (int i = 0; i < 27; ++i) acc = fmaf(wr[i], in[i], acc);
-        acc = fmaxf(acc, 0.f);
+        acc = acc > 0.f ? acc : 0.f;
+        if (std::is_same<T, uint8_t>::value) acc *= a.oinv[o];
       }
       v[j] = acc;
     }
@@ -534,7 +996,10 @@ hipError_t launch_first_conv(int precision, const FirstConvArgs& a, hipStream_t 
   if (a.c0 > kFirstMaxC0 || a.T % 16) return hipErrorInvalidValue;
   const int nb = a.T / 16;
   const int64_t blocks = (int64_t)a.batch * nb * nb;
-  if (precision == OMNISEG_BF16)
+  if (precision == OMNISEG_FP8) {
+    if (!a.oinv) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_first_conv<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  } else if (precision == OMNISEG_BF16)
     hipLaunchKernelGGL(k_first_conv<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(k_first_conv<float>, dim3((unsigned)blocks), dim3(256), 0, st, a);

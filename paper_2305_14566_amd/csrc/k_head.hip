@@ -15,28 +15,37 @@ namespace omniseg {
 
 __device__ __forceinline__ float ld1(const float* p) { return *p; }
 __device__ __forceinline__ float ld1(const uint16_t* p) { return __uint_as_float((uint32_t)(*p) << 16); }
+// FP8: the E4M3 code's value (the caller applies the channel scale)
+__device__ __forceinline__ float ld1(const uint8_t* p) { return __builtin_amdgcn_cvt_f32_fp8((int)*p, 0); }
 
+// scale: FP8 channel scales (null for FP32 / BF16)
 template <typename T>
 __global__ __launch_bounds__(256) void k_gap(const T* __restrict__ e, int hw, int c_p, int c,
-                                             const int32_t* count, int chunk_base, float* g) {
+                                             const int32_t* count, int chunk_base, float* g,
+                                             const float* __restrict__ scale) {
   const int b = blockIdx.x;
   if (chunk_base + b >= *count) return;
   const T* base = e + (int64_t)b * hw * c_p;
   for (int ch = threadIdx.x; ch < c; ch += blockDim.x) {
     float s = 0.f;
     for (int p = 0; p < hw; ++p) s += ld1(base + (int64_t)p * c_p + ch);
+    if (scale) s *= scale[ch];
     g[(int64_t)b * c_p + ch] = s / (float)hw;
   }
 }
 
 hipError_t launch_gap(int precision, const void* e, int batch, int hw, int c_p, int c,
-                      const int32_t* count, int chunk_base, float* g, hipStream_t st) {
-  if (precision == OMNISEG_BF16)
+                      const int32_t* count, int chunk_base, float* g, hipStream_t st, const float* scale) {
+  if (precision == OMNISEG_FP8) {
+    if (!scale) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gap<uint8_t>, dim3(batch), dim3(256), 0, st, (const uint8_t*)e, hw, c_p, c, count,
+                       chunk_base, g, scale);
+  } else if (precision == OMNISEG_BF16)
     hipLaunchKernelGGL(k_gap<uint16_t>, dim3(batch), dim3(256), 0, st, (const uint16_t*)e, hw, c_p, c,
-                       count, chunk_base, g);
+                       count, chunk_base, g, nullptr);
   else
     hipLaunchKernelGGL(k_gap<float>, dim3(batch), dim3(256), 0, st, (const float*)e, hw, c_p, c, count,
-                       chunk_base, g);
+                       chunk_base, g, nullptr);
   return hipGetLastError();
 }
 
@@ -90,7 +99,8 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
                                               const float* __restrict__ theta, int P,
                                               SlotTable slots, int max_slots,
                                               const int32_t* list, const int32_t* count,
-                                              int chunk_base, float* __restrict__ out) {
+                                              int chunk_base, float* __restrict__ out,
+                                              const float* __restrict__ dscale) {
   constexpr int kMaxC0 = 256;
   __shared__ float sth[OMNISEG_MAX_CLASSES * (144 + 9 * 2)];
   __shared__ float swp[8 * kMaxC0 + 8];
@@ -113,7 +123,7 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
 #pragma unroll
     for (int o = 0; o < 8; ++o) F[o] = swp[8 * c0 + o];
     for (int c = 0; c < c0; ++c) {
-      const float v = ld1(px + c);
+      const float v = dscale ? ld1(px + c) * dscale[c] : ld1(px + c);
 #pragma unroll
       for (int o = 0; o < 8; ++o) F[o] = fmaf(swp[o * c0 + c], v, F[o]);
     }
@@ -121,7 +131,7 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
     for (int o = 0; o < 8; ++o) F[o] = fmaxf(F[o], 0.f);
   } else {
 #pragma unroll
-    for (int o = 0; o < 8; ++o) F[o] = ld1(px + o);
+    for (int o = 0; o < 8; ++o) F[o] = dscale ? ld1(px + o) * dscale[o] : ld1(px + o);
   }
   for (int j = 0; j < ns; ++j) {
     const float* th = &sth[j * P];
@@ -162,25 +172,23 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
 hipError_t launch_head(int precision, const void* d0, int batch, int T, int c0, int c0_p,
                        const float* wp, const float* bp, const float* theta, int P, int o,
                        const SlotTable& slots, int max_slots, const int32_t* list,
-                       const int32_t* count, int chunk_base, float* tile_logits, hipStream_t st) {
+                       const int32_t* count, int chunk_base, float* tile_logits, hipStream_t st,
+                       const float* d0_scale) {
   const int T2 = T * T;
   if (T2 % 256 || c0 > 256 || max_slots > OMNISEG_MAX_CLASSES) return hipErrorInvalidValue;
+  if ((precision == OMNISEG_FP8) != (d0_scale != nullptr)) return hipErrorInvalidValue;
   dim3 grid(batch * (T2 / 256));
-  if (precision == OMNISEG_BF16) {
-    if (o == 1)
-      hipLaunchKernelGGL((k_head<uint16_t, 1>), grid, dim3(256), 0, st, (const uint16_t*)d0, T2, c0,
-                         c0_p, wp, bp, theta, P, slots, max_slots, list, count, chunk_base, tile_logits);
-    else
-      hipLaunchKernelGGL((k_head<uint16_t, 2>), grid, dim3(256), 0, st, (const uint16_t*)d0, T2, c0,
-                         c0_p, wp, bp, theta, P, slots, max_slots, list, count, chunk_base, tile_logits);
+#define OMNISEG_HEAD(TY, O)                                                                                      \
+  hipLaunchKernelGGL((k_head<TY, O>), grid, dim3(256), 0, st, (const TY*)d0, T2, c0, c0_p, wp, bp, theta, P, \
+                     slots, max_slots, list, count, chunk_base, tile_logits, d0_scale)
+  if (precision == OMNISEG_FP8) {
+    if (o == 1) OMNISEG_HEAD(uint8_t, 1); else OMNISEG_HEAD(uint8_t, 2);
+  } else if (precision == OMNISEG_BF16) {
+    if (o == 1) OMNISEG_HEAD(uint16_t, 1); else OMNISEG_HEAD(uint16_t, 2);
   } else {
-    if (o == 1)
-      hipLaunchKernelGGL((k_head<float, 1>), grid, dim3(256), 0, st, (const float*)d0, T2, c0, c0_p,
-                         wp, bp, theta, P, slots, max_slots, list, count, chunk_base, tile_logits);
-    else
-      hipLaunchKernelGGL((k_head<float, 2>), grid, dim3(256), 0, st, (const float*)d0, T2, c0, c0_p,
-                         wp, bp, theta, P, slots, max_slots, list, count, chunk_base, tile_logits);
+    if (o == 1) OMNISEG_HEAD(float, 1); else OMNISEG_HEAD(float, 2);
   }
+#undef OMNISEG_HEAD
   return hipGetLastError();
 }
 

@@ -24,9 +24,16 @@ struct ConvDesc {
   int cin_p, cout_p, cu_p;
   int64_t pk_w, pk_b;
   int64_t pk_wt;  // data-gradient (transposed, flipped) weights, or -1
+  // FP8: packed per-output-channel weight scales (or -1), and the activation
+  // table offsets of the input's channel scales (upsampled / plain part, skip
+  // part or -1) and of the output's
+  int64_t pk_ws = -1;
+  int64_t act_in = -1, act_in_e = -1, act_out = -1;
 };
 
-inline int elem_size(int precision) { return precision == OMNISEG_BF16 ? 2 : 4; }
+inline int elem_size(int precision) {
+  return precision == OMNISEG_BF16 ? 2 : precision == OMNISEG_FP8 ? 1 : 4;
+}
 
 }  // namespace omniseg
 
@@ -43,6 +50,12 @@ struct omniseg_plan {
   int64_t canon_pre_w = -1, canon_pre_b = -1, pk_pre_w = 0, pk_pre_b = 0;
   int64_t canon_ctrl_w = 0, canon_ctrl_b = 0, pk_ctrl_w = 0, pk_ctrl_b = 0;
   int64_t packed_bytes = 0;
+  // activation table (per padded channel of every stored activation):
+  // offset of (kind, level), kinds OMNISEG_ACT_*; -1 where absent
+  int64_t act_off[4][8];
+  int64_t n_act = 0;
+  // FP8: packed channel scales and their inverses, one per table entry
+  int64_t pk_scale = -1, pk_iscale = -1;
   mutable std::vector<omniseg::SlideDev> slide_tab;  // host staging of the device slide table
   mutable std::vector<int32_t> host_tab;             // host staging of tile lists and grids
   // conv tile configuration per (stage, level): stage 0 enc_a, 1 enc_b, 2 dec_a, 3 dec_b; -1 = default
@@ -69,7 +82,7 @@ namespace omniseg {
 // valid for the shape, else the default.  stage: 0 enc_a, 1 enc_b, 2 dec_a, 3 dec_b.
 inline int layer_config(const omniseg_plan* p, int stage, int level, int H, int W, int cout_p) {
   const int t = p->tune[stage][level];
-  if (t >= 0 && conv_config_valid(t, H, W, cout_p)) return t;
+  if (t >= 0 && conv_config_valid(t, p->cfg.precision, H, W, cout_p)) return t;
   return conv_default_config(p->cfg.precision, H, W, cout_p);
 }
 

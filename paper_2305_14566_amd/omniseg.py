@@ -13,16 +13,17 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libomniseg.so")
 
-FP32, BF16 = 0, 1
+FP32, BF16, FP8 = 0, 1, 2
+ACT_ENC_A, ACT_ENC_E, ACT_DEC_A, ACT_DEC_D = range(4)
 FLAG_EMIT_LOGITS = 1
 FLAG_TRAINING = 2
 FLAG_GRAPH = 4
 (REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
  REGION_TILE_INDEX, REGION_TILE_LOGITS) = range(7)
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
-N_CONV_CONFIGS = 6
+N_CONV_CONFIGS = 10
 
 _lib = None
 
@@ -98,7 +99,7 @@ def _declare(lib):
         "omniseg_stitch_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
         "omniseg_stitch_tiles": (i32, [i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, i64, vp, i64, vp]),
         "omniseg_set_profiling": (i32, [vp, i32]),
-        "omniseg_conv_config": (i32, [i32, P(i32), P(i32), P(i32), P(i32), P(i32)]),
+        "omniseg_conv_config": (i32, [i32, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]),
         "omniseg_autotune": (i32, [vp, vp, P(Slide), i32, P(Pair), i32, vp, i64, vp]),
         "omniseg_plane_offsets": (i32, [vp, P(Slide), P(Pair), i32, P(i64)]),
         "omniseg_train_workspace_bytes": (i32, [vp, P(Slide), P(Tile), i32, P(Pair), i32, P(i64)]),
@@ -108,6 +109,13 @@ def _declare(lib):
         "omniseg_conv3x3_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
         "omniseg_conv3x3": (i32, [i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, i32, vp, i64, vp]),
         "omniseg_read_profile": (i32, [vp, P(LaunchRecord), i32, P(i32)]),
+        "omniseg_conv3x3_fp8_workspace_bytes": (i32, [i32, i32, i32, P(i64)]),
+        "omniseg_conv3x3_fp8": (i32, [i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, i64,
+                                      vp]),
+        "omniseg_activation_channels": (i32, [vp, P(i64)]),
+        "omniseg_activation_offset": (i32, [vp, i32, i32, P(i64)]),
+        "omniseg_calibrate_fp8": (i32, [vp, vp, P(Slide), i32, P(Pair), i32, i32, vp, vp, i64, vp]),
+        "omniseg_pack_weights_fp8": (i32, [vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -227,6 +235,41 @@ class Plan:
             raise ValueError(f"expected {self.weight_count} weights, got {canonical.numel()}")
         packed = torch.empty(self.packed_bytes, dtype=torch.uint8, device=canonical.device)
         _check(lib().omniseg_pack_weights(self._h, _ptr(canonical), _ptr(packed), _stream(stream)))
+        return packed
+
+    # ---- FP8 -------------------------------------------------------------------
+
+    @property
+    def activation_channels(self):
+        n = ctypes.c_int64()
+        _check(lib().omniseg_activation_channels(self._h, ctypes.byref(n)))
+        return n.value
+
+    def activation_offset(self, kind, level):
+        n = ctypes.c_int64()
+        _check(lib().omniseg_activation_offset(self._h, kind, level, ctypes.byref(n)))
+        return n.value
+
+    def calibrate_fp8(self, slides, pairs, packed, workspace, n_tiles=64, stream=None):
+        """Per-channel activation maxima (device float32 activation table) of
+        this FP32 plan's backbone over the first n_tiles kept tiles."""
+        sl, pr = self._arrays(slides, pairs)
+        amax = torch.empty(self.activation_channels, dtype=torch.float32, device=slides[0].device)
+        _check(lib().omniseg_calibrate_fp8(self._h, _ptr(packed), sl, len(slides), pr, len(pairs), n_tiles,
+                                           _ptr(amax), _ptr(workspace), workspace.numel(), _stream(stream)))
+        return amax
+
+    def pack_fp8(self, canonical, amax, stream=None):
+        """Canonical FP32 weights + activation maxima (device) -> packed FP8 buffer."""
+        if canonical.dtype != torch.float32 or not canonical.is_cuda or not canonical.is_contiguous():
+            raise ValueError("canonical weights must be a contiguous float32 device tensor")
+        if canonical.numel() != self.weight_count:
+            raise ValueError(f"expected {self.weight_count} weights, got {canonical.numel()}")
+        if amax.dtype != torch.float32 or amax.numel() != self.activation_channels:
+            raise ValueError("amax must be the float32 activation table of this network")
+        packed = torch.empty(self.packed_bytes, dtype=torch.uint8, device=canonical.device)
+        _check(lib().omniseg_pack_weights_fp8(self._h, _ptr(canonical), _ptr(amax.contiguous()), _ptr(packed),
+                                              _stream(stream)))
         return packed
 
     def _arrays(self, slides, pairs):
@@ -438,8 +481,38 @@ def conv3x3(precision, mode, x0, weights, bias=None, x1=None, aux=None, cin=None
     return y
 
 
+def conv3x3_fp8(mode, x0, weights, bias, in_scale, out_scale, x1=None, cu=None, height=None, width=None,
+                config=-1, stream=None):
+    """Stand-alone FP8 backbone conv: x0 (x1) uint8 E4M3 codes, NHWC with
+    32-padded channels, channel scales in_scale (real channel order) and
+    out_scale.  Returns the uint8 output codes [n, H, W, pad32(cout)]."""
+    n = x0.shape[0]
+    cout, cin = weights.shape[0], weights.shape[1]
+    cu = cin if cu is None else cu
+    if height is None:
+        height = x0.shape[1] // 2 if mode == CONV_POOL_RELU else (x0.shape[1] * 2 if mode == CONV_UPCAT_RELU
+                                                                  else x0.shape[1])
+        width = x0.shape[2] // 2 if mode == CONV_POOL_RELU else (x0.shape[2] * 2 if mode == CONV_UPCAT_RELU
+                                                                 else x0.shape[2])
+    y = torch.empty((n, height, width, -(-cout // 32) * 32), dtype=torch.uint8, device=x0.device)
+    nb = ctypes.c_int64()
+    _check(lib().omniseg_conv3x3_fp8_workspace_bytes(cin, cu, cout, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=x0.device)
+    _check(lib().omniseg_conv3x3_fp8(mode, n, height, width, cin, cu, cout, _ptr(weights), _ptr(bias),
+                                     _ptr(in_scale), _ptr(out_scale), _ptr(x0), _ptr(x1), _ptr(y), config, _ptr(ws),
+                                     ws.numel(), _stream(stream)))
+    return y
+
+
 def conv_config(config):
     """(by, bx, bn, wm, wn) of a conv tile configuration id."""
-    v = [ctypes.c_int32() for _ in range(5)]
+    return conv_config_info(config)[:5]
+
+
+def conv_config_info(config):
+    """(by, bx, bn, wm, wn, precisions) of a conv tile configuration id;
+    precisions is the set of precisions (FP32, BF16, FP8) it runs at."""
+    v = [ctypes.c_int32() for _ in range(6)]
     _check(lib().omniseg_conv_config(config, *[ctypes.byref(x) for x in v]))
-    return tuple(x.value for x in v)
+    vals = [x.value for x in v]
+    return tuple(vals[:5]) + (frozenset(p for p in (FP32, BF16, FP8) if vals[5] >> p & 1),)

@@ -275,3 +275,60 @@ def test_plane_offsets_and_bce_validation():
     assert list(off) == [0, 65 * 40, 65 * 40 + 33 * 20, 2 * 65 * 40 + 33 * 20]
     assert lib.omniseg_bce_loss(FAKE, FAKE, FAKE, 0, FAKE, 0, FAKE, 16384, None) == 1
     assert lib.omniseg_bce_loss(FAKE, FAKE, FAKE, 10, FAKE, 0, FAKE, 100, None) == 3
+
+
+def test_conv_config_query_and_precision_gate():
+    """Every configuration has a shape and a precision set; the row-reuse
+    configurations are BF16 only, and the stand-alone conv refuses a
+    configuration at a precision it does not run at, or one that does not
+    fit the shape, before any HIP call."""
+    assert om.N_CONV_CONFIGS == 10
+    for c in range(om.N_CONV_CONFIGS):
+        by, bx, bn, wm, wn, precs = om.conv_config_info(c)
+        assert wm * wn == 4 and by % 8 == 0 and bx in (8, 16) and bn % 32 == 0
+        assert om.BF16 in precs
+        assert (om.FP32 in precs) == (c < 6) and (om.FP8 in precs) == (c >= 6)
+    with pytest.raises(om.OmnisegError):
+        om.conv_config_info(om.N_CONV_CONFIGS)
+    lib = om.lib()
+    ws = ctypes.c_int64()
+    assert lib.omniseg_conv3x3_workspace_bytes(om.FP32, 64, 64, 64, ctypes.byref(ws)) == 0
+    call = lambda prec, cfg, h=32, w=32: lib.omniseg_conv3x3(prec, om.CONV_RELU, 1, h, w, 64, 64, 64, FAKE, FAKE,
+                                                             FAKE, None, None, FAKE, cfg, FAKE, ws.value, None)
+    assert call(om.FP32, 6) == 1           # row-reuse configuration at FP32
+    assert call(om.BF16, 8, h=16) == 1     # 32-row block on a 16-row image
+    assert call(om.BF16, 3, w=24) == 1     # 16-pixel block on a 24-pixel-wide image
+
+
+def test_fp8_plan_validation_and_activation_table():
+    """FP8 plans: inference only, deepest level a multiple of 16; the
+    activation table has one entry per padded channel of every stored
+    activation, kind-major then level; the packing and calibration entry
+    points refuse the wrong precision before any HIP call."""
+    lib = om.lib()
+    h = ctypes.c_void_p()
+    c = _cfg(precision=om.FP8, flags=om.FLAG_TRAINING)
+    assert lib.omniseg_plan_create(ctypes.byref(c), ctypes.byref(h)) == 2 and not h.value
+    c = _cfg(precision=om.FP8, tile=32, stride=16)  # 32 / 2^2 = 8 rows at the bottleneck
+    assert lib.omniseg_plan_create(ctypes.byref(c), ctypes.byref(h)) == 2 and not h.value
+    p8 = om.Plan(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 1, 2, 3), tile=256, stride=128,
+                 precision=om.FP8)
+    p32 = om.Plan(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 1, 2, 3), tile=256, stride=128)
+    C = [64 * 2 ** l for l in range(5)]
+    assert p8.activation_channels == p32.activation_channels == 2 * sum(C) + 2 * sum(C[:4])
+    off = 0
+    for kind, nl in ((om.ACT_ENC_A, 5), (om.ACT_ENC_E, 5), (om.ACT_DEC_A, 4), (om.ACT_DEC_D, 4)):
+        for l in range(nl):
+            assert p8.activation_offset(kind, l) == off
+            off += C[l]
+    with pytest.raises(om.OmnisegError):
+        p8.activation_offset(om.ACT_DEC_D, 4)  # D_{L-1} is E_{L-1}: no own entry
+    # FP8 packed weights: 64-channel chunks, one byte per weight, plus scale tables
+    assert 0 < p8.packed_bytes < p32.packed_bytes / 3
+    assert lib.omniseg_pack_weights(p8._h, FAKE, FAKE, None) == 2
+    assert lib.omniseg_pack_weights_fp8(p32._h, FAKE, FAKE, FAKE, None) == 1
+    sl = (om.Slide * 1)()
+    sl[0].rgb, sl[0].height, sl[0].width, sl[0].row_pitch = FAKE, 512, 512, 1536
+    pr = (om.Pair * 1)()
+    assert lib.omniseg_calibrate_fp8(p8._h, FAKE, sl, 1, pr, 1, 64, FAKE, FAKE, 1 << 40, None) == 1
+    assert lib.omniseg_calibrate_fp8(p32._h, FAKE, sl, 1, pr, 1, 0, FAKE, FAKE, 1 << 40, None) == 1

@@ -122,10 +122,18 @@ def test_conv_dgrad_concat_layout(prec):
 @pytest.mark.parametrize("config", list(range(om.N_CONV_CONFIGS)))
 @pytest.mark.parametrize("mode", ["res", "pool", "upcat", "dgrad_res"])
 def test_every_tile_configuration(prec, config, mode):
-    """Each conv tile configuration the autotuner may pick, on a shape it fits."""
-    by, bx, bn, wm, wn = om.conv_config(config)
+    """Each conv tile configuration the autotuner may pick, on a shape it
+    fits (two blocks per axis and per channel block), at every precision it
+    declares; at any other precision the entry point must refuse it."""
+    by, bx, bn, wm, wn, precs = om.conv_config_info(config)
     n, H, W = 2, 2 * by, 2 * bx
-    cout = bn if bn > 32 else 32
+    if prec not in precs:
+        x = torch.zeros((n, H, W, 32), dtype=torch.float32, device=DEV)
+        w = torch.zeros((32, 32, 3, 3), dtype=torch.float32, device=DEV)
+        with pytest.raises(om.OmnisegError):
+            om.conv3x3(prec, om.CONV_RELU, x, w, torch.zeros(32, device=DEV), config=config)
+        return
+    cout = 2 * bn
     cin = cout if mode in ("res", "dgrad_res") else 48
     rng = np.random.default_rng(config * 17 + len(mode))
     Wt = q(rng.standard_normal((cout, cin, 3, 3)) * np.sqrt(2.0 / (9 * cin)), prec)
@@ -154,3 +162,118 @@ def test_every_tile_configuration(prec, config, mode):
         y = om.conv3x3(prec, om.CONV_DGRAD_RES_MASK, to_nhwc(G, prec), wdev, aux=to_nhwc(A, prec), config=config)
         check(from_nhwc(y, cin), [(O.conv3x3_backward(np.zeros((cin, H, W)), Wt, g)[0] + g) * (a > 0)
                                   for g, a in zip(G, A)], prec)
+
+
+# ------------------------------------------------------------------ FP8 (E4M3)
+
+def _e4m3_values():
+    """Non-negative E4M3 values by code (bit-level decode), code 0x7F (NaN) excluded."""
+    v = np.zeros(127)
+    for code in range(127):
+        e, m = code >> 3, code & 7
+        v[code] = (m / 8.0) * 2.0 ** -6 if e == 0 else (1 + m / 8.0) * 2.0 ** (e - 7)
+    return v
+
+
+E4M3 = _e4m3_values()
+
+
+def fp8_codes(X, scale):
+    """[C, H, W] non-negative values -> (codes uint8 of E4M3(X / s), the values those codes stand for)."""
+    q = O.round_e4m3(X / scale[:, None, None])
+    codes = np.searchsorted(E4M3, q).astype(np.uint8)
+    assert np.array_equal(E4M3[codes], q)
+    return codes, q * scale[:, None, None]
+
+
+def to_nhwc_u8(codes_list):
+    C, H, W = codes_list[0].shape
+    out = np.zeros((len(codes_list), H, W, p32(C)), np.uint8)
+    for i, c in enumerate(codes_list):
+        out[i, :, :, :C] = np.transpose(c, (1, 2, 0))
+    return torch.from_numpy(out).to(DEV)
+
+
+def check_fp8(got_codes, Yref, Yabs, s_out):
+    """GPU codes against the E4M3 encoding of the FP64 result Yref / s_out.
+    The GPU sums in FP32, so its pre-rounding value may differ from Yref by
+    up to the summation error, bounded here by 3e-5 * Yabs (Yabs: the same
+    conv on |inputs| and |weights|, i.e. the sum of the magnitudes of the
+    terms).  Each code must be the encoding of some value in
+    [Yref - err, Yref + err]; mismatches must be rare."""
+    got = np.stack([np.transpose(g, (2, 0, 1))[:len(s_out)] for g in got_codes.cpu().numpy()]).astype(np.int64)
+    sc = s_out[None, :, None, None]
+    v = np.stack(Yref) / sc
+    e = 3e-5 * np.stack(Yabs) / sc
+    code = lambda x: np.searchsorted(E4M3, O.round_e4m3(np.clip(x, 0.0, 448.0)))
+    want, lo, hi = code(v), code(v - e), code(v + e)
+    assert np.all((got >= lo) & (got <= hi)), np.argwhere((got < lo) | (got > hi))[:5]
+    assert (got != want).mean() < 1e-2, (got != want).mean()
+    assert np.all(np.transpose(got_codes.cpu().numpy(), (0, 3, 1, 2))[:, len(s_out):] == 0)  # padded channels
+
+
+def pow2(rng, n, lo=-3, hi=3):
+    return 2.0 ** rng.integers(lo, hi + 1, n).astype(np.float64)
+
+
+def _fp8_case(rng, mode, n, H, W, cin, cout, cu=None):
+    """Inputs (codes and the values they stand for), weights, the FP64
+    reference and output scales calibrated on it (pow2_scale of each output
+    channel's maximum, as the FP8 path derives them)."""
+    Wt = (rng.standard_normal((cout, cin, 3, 3)) * np.sqrt(2.0 / (9 * cin))).astype(np.float32).astype(np.float64)
+    b = (rng.standard_normal(cout) * 0.1).astype(np.float32).astype(np.float64)
+    s_in = pow2(rng, cin)
+    eff = O.fp8_conv_weights(Wt, s_in)[2]
+    act = lambda shape, s: fp8_codes(np.abs(rng.standard_normal(shape)) * 50 * s[:, None, None], s)
+    kw = {}
+    if mode in ("relu", "res"):
+        codes, X = zip(*[act((cin, H, W), s_in) for _ in range(n)])
+        x0 = to_nhwc_u8(codes)
+        Z = X
+    elif mode == "pool":
+        codes, X = zip(*[act((cin, 2 * H, 2 * W), s_in) for _ in range(n)])
+        x0 = to_nhwc_u8(codes)
+        Z = [O.maxpool2(x) for x in X]
+    else:
+        dc, D = zip(*[act((cu, H // 2, W // 2), s_in[:cu]) for _ in range(n)])
+        ec, E = zip(*[act((cin - cu, H, W), s_in[cu:]) for _ in range(n)])
+        x0 = to_nhwc_u8(dc)
+        kw = dict(x1=to_nhwc_u8(ec), cu=cu)
+        Z = [np.concatenate([O.up2(d), e]) for d, e in zip(D, E)]
+    res = mode == "res"
+    ref = [np.maximum(O.conv3x3(z, eff, b) + (z if res else 0), 0) for z in Z]
+    mag = [O.conv3x3(z, np.abs(eff), np.abs(b)) + (z if res else 0) for z in Z]
+    s_out = O.pow2_scale(np.stack(ref).max(axis=(0, 2, 3)))
+    args = [torch.from_numpy(a.astype(np.float32)).to(DEV) for a in (Wt, b, s_in, s_out)]
+    m = {"relu": om.CONV_RELU, "res": om.CONV_RES_RELU, "pool": om.CONV_POOL_RELU, "upcat": om.CONV_UPCAT_RELU}[mode]
+    return m, x0, args, kw, ref, mag, s_out
+
+
+FP8_CASES = [(2, 32, 48, 40, 64), (1, 16, 32, 64, 96), (2, 32, 16, 8, 32), (1, 16, 16, 200, 64)]
+
+
+@pytest.mark.parametrize("n,H,W,cin,cout", FP8_CASES)
+@pytest.mark.parametrize("mode", ["relu", "res", "pool", "upcat"])
+def test_conv_layer_fp8(n, H, W, cin, cout, mode):
+    """One FP8 conv: the oracle's effective weights (fp8_conv_weights) on the
+    decoded input codes in FP64, encoded with the output scales, against the
+    GPU's output codes."""
+    rng = np.random.default_rng(hash((n, H, W, cin, cout, mode, "fp8")) % 2 ** 32)
+    if mode == "res":
+        cin = cout
+    m, x0, args, kw, ref, mag, s_out = _fp8_case(rng, mode, n, H, W, cin, cout, cu=max(1, (2 * cin) // 3))
+    check_fp8(om.conv3x3_fp8(m, x0, *args, **kw), ref, mag, s_out)
+
+
+@pytest.mark.parametrize("config", [c for c in range(om.N_CONV_CONFIGS) if om.FP8 in om.conv_config_info(c)[5]])
+@pytest.mark.parametrize("mode", ["res", "pool", "upcat"])
+def test_every_fp8_tile_configuration(config, mode):
+    """Each FP8 tile configuration on a shape with two blocks per axis and
+    per channel block."""
+    by, bx, bn, wm, wn, _ = om.conv_config_info(config)
+    n, H, W = 2, 2 * by, 2 * bx
+    cout = 2 * bn
+    cin = cout if mode == "res" else 96
+    rng = np.random.default_rng(config * 31 + len(mode))
+    m, x0, args, kw, ref, mag, s_out = _fp8_case(rng, mode, n, H, W, cin, cout, cu=64)
+    check_fp8(om.conv3x3_fp8(m, x0, *args, config=config, **kw), ref, mag, s_out)

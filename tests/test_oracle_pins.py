@@ -560,3 +560,109 @@ def test_gradient_central_differences():
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * np.abs(grad).max()), (trial, fd, an)
         checked += 1
     assert checked >= 6, (checked, skipped)
+
+
+# --------------------------------------------------------------------------
+# FP8 (OCP E4M3) emulation: pinned to a bit-level decode of all 256 codes
+# --------------------------------------------------------------------------
+
+
+def _e4m3_table():
+    """Every finite E4M3 value from its bit fields: sign s, exponent e (bias
+    7), fraction m; e = 0 is subnormal (m/8) 2^-6; e = 15, m = 7 is NaN."""
+    vals, codes = [], []
+    for code in range(256):
+        s, e, m = code >> 7, (code >> 3) & 15, code & 7
+        if e == 15 and m == 7:
+            continue
+        v = (m / 8.0) * 2.0 ** -6 if e == 0 else (1 + m / 8.0) * 2.0 ** (e - 7)
+        vals.append(-v if s else v)
+        codes.append(code)
+    return np.array(vals), np.array(codes)
+
+
+def test_e4m3_fixed_points_and_range():
+    vals, _ = _e4m3_table()
+    assert np.array_equal(O.round_e4m3(vals), vals)
+    assert vals.max() == 448.0 and np.min(np.abs(vals[vals != 0])) == 2.0 ** -9
+    assert len(np.unique(vals)) == 253  # 254 finite codes, +0 and -0 equal
+
+
+def test_e4m3_rounding_is_nearest_ties_to_even_code():
+    vals, codes = _e4m3_table()
+    pos = vals >= 0
+    pv, pc = vals[pos], codes[pos]
+    order = np.argsort(pv)
+    pv, pc = pv[order], pc[order]
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.uniform(0, 450, 3000), 2.0 ** rng.uniform(-12, 9, 3000),
+                        (pv[:-1] + pv[1:]) / 2])  # every midpoint between neighbours
+    got = O.round_e4m3(x)
+    for xi, gi in zip(x, got):
+        xc = min(xi, 448.0)
+        d = np.abs(pv - xc)
+        best = np.flatnonzero(d == d.min())
+        if len(best) == 2:  # a tie: the code with the even fraction field
+            best = [b for b in best if pc[b] % 2 == 0]
+        assert gi == pv[best[0]], (xi, gi)
+    assert np.array_equal(O.round_e4m3(-x), -got)
+
+
+def test_pow2_scale_and_fp8_weight_folding():
+    amax = np.array([0.0, 448.0, 448.0001, 1e-3, 3e4])
+    s = O.pow2_scale(amax)
+    assert np.all(np.log2(s) == np.round(np.log2(s)))  # powers of two
+    assert np.all(amax / s <= 448.0) and np.all((amax[1:] / s[1:]) > 224.0)
+    assert s[0] == 1.0 and s[1] == 1.0 and s[2] == 2.0
+    rng = np.random.default_rng(6)
+    Wt = rng.standard_normal((8, 5, 3, 3))
+    s_in = 2.0 ** rng.integers(-4, 4, 5).astype(np.float64)
+    q, w, eff = O.fp8_conv_weights(Wt, s_in)
+    vals, _ = _e4m3_table()
+    assert np.all(np.isin(q, vals))  # stored codes are E4M3 values
+    assert np.all(np.abs(q).reshape(8, -1).max(axis=1) >= 224.0)  # each output channel reaches the top binade
+    # effective weights are within half an E4M3 step (relative 2^-4) of the originals, or tiny
+    rel = np.abs(eff - Wt) / np.maximum(np.abs(Wt), (w[:, None, None, None] / s_in[None, :, None, None]) * 2.0 ** -6)
+    assert rel.max() <= 2.0 ** -4 + 1e-12
+    X = rng.uniform(0, 50, (5, 6, 6))
+    Xq = O.fp8_activation(X, s_in)
+    assert np.all(np.isin(Xq / s_in[:, None, None], vals))
+
+
+def test_fp8_forward_scale_wiring():
+    """In the FP8 forward every conv's stored input, divided by the channel
+    scales its weights were folded with, lies on E4M3 values, and on the
+    calibration tiles each channel's largest code reaches the top binade
+    [224, 448] (a scale vector taken from another tensor or in another
+    concat order misses that range).  The result stays near the exact
+    forward."""
+    vals, _ = _e4m3_table()
+    cfg = O.make_config(base=4, levels=3, head_out=2, n_classes=2, scales=(0,), tile=32, stride=16)
+    flat = synth.he_normal_weights(21, 4, 3, 2, 1, 2, bias_std=0.05)
+    wts = O.unpack_weights(flat.astype(np.float64), cfg)
+    rgb, _ = synth.tiny_slide(8, 64, 64)
+    xs = [O.tile_input(rgb, 0, 32, 16, jy, jx) for jy, jx in ((0, 0), (1, 2))]
+    S = O.fp8_calibrate(xs, wts, cfg)
+    assert sorted(S) == sorted(O.activation_names(cfg))
+    w8 = O.fp8_weights(wts, cfg, S)
+    L = cfg["levels"]
+    top = {}
+    for x in xs:
+        _, _, sv = O.unet_forward(x, w8, cfg, keep=True, act_scales=S)
+        inputs = {f"enc{l}.b": sv[f"enc{l}.A"] for l in range(L)}
+        inputs.update({f"enc{l}.a": sv[f"enc{l}.X"] for l in range(1, L)})
+        inputs.update({f"dec{l}.a": sv[f"dec{l}.Z"] for l in range(L - 1)})
+        inputs.update({f"dec{l}.b": sv[f"dec{l}.A"] for l in range(L - 1)})
+        for name, X in inputs.items():
+            s_in = O.conv_input_scale(name, cfg, S)
+            assert len(s_in) == X.shape[0]
+            code = X / s_in[:, None, None]
+            assert np.all(np.isin(code, vals)), name
+            m = code.reshape(code.shape[0], -1).max(axis=1)
+            top[name] = m if name not in top else np.maximum(top[name], m)
+    for name, m in top.items():
+        live = m > 0  # channels that are never positive keep scale 1
+        assert np.all((m[live] >= 224.0) & (m[live] <= 448.0)), (name, m)
+    F8, _ = O.unet_forward(xs[1], w8, cfg, act_scales=S)
+    F, _ = O.unet_forward(xs[1], wts, cfg)
+    assert np.abs(F8 - F).max() <= 0.25 * np.abs(F).max()
