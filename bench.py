@@ -29,18 +29,48 @@ sys.path.insert(0, ROOT)
 
 METRIC = "WSI Mpixel/s per class-scale (BF16 batched vs FP32 plain) at ≥0.999 Dice; %MFMA peak"
 UNIT = "Mpixel/s per class-scale"
-PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0}
 HBM_PEAK_GBS = 8000.0
 
 CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 1, 2, 3), tile=256, stride=128,
            fg_filter=True)
 
+# HBM bytes per launch of the dominant BF16 conv kernel on this workload, from
+# two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
+#   bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu --train-steps 0 --fp8-steps 0 --copy-gib 1
+# over the launches of the timed step, each counter scaled by its reading for
+# the 1 GiB device copy that command makes first (FETCH_SIZE read 0.5 GiB,
+# WRITE_SIZE 1 GiB).  It describes the conv source whose SHA-256 is stored
+# here and is reported as null for any other.
+MEASURED_TRAFFIC = {
+    "kernel": "omniseg::k_conv3x3_rows<16, 64, 2, 2, 0, 1>",
+    "bytes_per_launch": 3326979393.0,
+    "fetch_bytes_per_launch": 2494570248.0,
+    "write_bytes_per_launch": 832409145.0,
+    "conv_source_sha256": "9f6cc069222b62f09002b4ff5f8910417a6f76bcafb07e88f1dd8dd141a451eb",
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2305_14566_amd", "csrc", "k_conv.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if kernel != MEASURED_TRAFFIC["kernel"] or sha != MEASURED_TRAFFIC["conv_source_sha256"]:
+        return None
+    return MEASURED_TRAFFIC["bytes_per_launch"]
+
 
 def conv_symbol(om, prec, stage, config):
     """Kernel symbol (as rocprofv3 prints it) that a conv launch uses."""
-    t = "unsigned short" if prec == "bf16" else "float"
     loader, epi = {"enc_a": (1, 0), "enc_b": (0, 1), "dec_a": (2, 0), "dec_b": (0, 1)}[stage]
     by, bx, bn, wm, wn = om.conv_config(config)
+    if prec == "fp8":
+        return f"omniseg::k_conv3x3_fp8<{by}, {bn}, {wm}, {wn}, {loader}, {epi}>"
+    if prec == "bf16" and config >= 6:  # row-reuse configurations
+        return f"omniseg::k_conv3x3_rows<{by}, {bn}, {wm}, {wn}, {loader}, {epi}>"
+    t = "unsigned short" if prec == "bf16" else "float"
     return f"omniseg::k_conv3x3<{t}, {by}, {bx}, {bn}, {wm}, {wn}, {loader}, {epi}>"
 
 
@@ -63,7 +93,8 @@ def roofline(om, records, prec):
     return dict(bound="mfma", kernel=sym, launches=g["n"],
                 flops_per_launch=g["flops"] / g["n"], avg_launch_ms=g["ms"] / g["n"],
                 achieved=achieved, peak=PEAK_TFLOPS[prec], unit="TFLOP/s",
-                frac=achieved / PEAK_TFLOPS[prec], traffic=None,
+                frac=achieved / PEAK_TFLOPS[prec], traffic=measured_traffic(sym),
+                algorithmic_bytes_per_launch=g["bytes"] / g["n"],
                 all_convs_tflops=conv_flops / (conv_ms * 1e-3) / 1e12,
                 all_convs_frac=conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec])
 
@@ -82,14 +113,31 @@ def stage_summary(records):
     return out
 
 
-def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles):
-    plan = om.Plan(base=CFG["base"], levels=CFG["levels"], head_out=CFG["head_out"],
+def _plan(om, prec, batch_tiles):
+    return om.Plan(base=CFG["base"], levels=CFG["levels"], head_out=CFG["head_out"],
                    n_classes=CFG["n_classes"], scales=CFG["scales"], tile=CFG["tile"],
                    stride=CFG["stride"], fg_filter=CFG["fg_filter"],
-                   precision=om.BF16 if prec == "bf16" else om.FP32, emit_logits=False,
+                   precision={"bf16": om.BF16, "fp32": om.FP32, "fp8": om.FP8}[prec], emit_logits=False,
                    batch_tiles=batch_tiles)
-    packed = plan.pack(flat_dev)
+
+
+def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles, calib_tiles=64):
+    plan = _plan(om, prec, batch_tiles)
     ws = torch.empty(plan.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
+    extra = {}
+    if prec == "fp8":
+        # per-channel activation scales from the FP32 path on the first kept tiles
+        p32 = _plan(om, "fp32", batch_tiles)
+        ws32 = torch.empty(p32.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
+        t_cal = time.perf_counter()
+        amax = p32.calibrate_fp8([dslide], pairs, p32.pack(flat_dev), ws32, n_tiles=calib_tiles)
+        torch.cuda.synchronize()
+        extra["calibration_s"] = time.perf_counter() - t_cal
+        extra["calibration_tiles"] = calib_tiles
+        del ws32, p32
+        packed = plan.pack_fp8(flat_dev, amax)
+    else:
+        packed = plan.pack(flat_dev)
     outs = plan.alloc_outputs([dslide], pairs)
     t_tune = time.perf_counter()
     plan.autotune([dslide], pairs, packed, ws)
@@ -118,7 +166,7 @@ def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles
     masks = [m.cpu().numpy().astype(bool) for m in outs[0][0]]
     tuned = sorted({(r["stage"], r["level"], r["config"]) for r in records if r["config"] >= 0})
     return dict(ms=ms, wall_ms=wall * 1e3 / steps, records=records, kept=kept, masks=masks,
-                tuned={f"{st}{l}": list(om.conv_config(c)) for st, l, c in tuned}, tune_s=t_tune)
+                tuned={f"{st}{l}": list(om.conv_config(c)) for st, l, c in tuned}, tune_s=t_tune, **extra)
 
 
 def train_leg(om, torch, steps, warmup, batch=32):
@@ -294,6 +342,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--train-steps", type=int, default=3, help="training-step leg (0 = skip)")
+    ap.add_argument("--fp8-steps", type=int, default=3, help="FP8 backbone leg (0 = skip)")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="first copy this many GiB device to device (a plain copy of known size for "
+                         "scaling profiler byte counters)")
     ap.add_argument("--workload", choices=["slide", "batch16"], default="slide",
                     help="slide: the 8192^2 slide (default); batch16: 16 uneven slides, batched vs per slide")
     args = ap.parse_args()
@@ -326,6 +378,14 @@ def main():
     dslide = torch.from_numpy(rgb).to(dev)
     flat_dev = torch.from_numpy(flat).to(dev)
     pairs = [(c, si) for si in range(4) for c in range(6)]
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * 2 ** 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copied {n * 4} bytes device to device", file=sys.stderr, flush=True)
+        del src, dst
     print(f"# slide {args.size}^2 generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
     bf = run_leg(om, torch, dslide, flat_dev, pairs, "bf16", args.steps, args.warmup, args.batch_tiles)
@@ -360,6 +420,23 @@ def main():
         result["speedup_bf16_vs_fp32"] = fp["ms"] / bf["ms"]
         result["bf16_vs_fp32_masks"] = {"dice_min": min(dices), "dice_mean": float(np.mean(dices)),
                                         "disagreement_max": max(dis)}
+    if args.fp8_steps > 0:
+        f8 = run_leg(om, torch, dslide, flat_dev, pairs, "fp8", args.fp8_steps, 1, args.batch_tiles)
+        print(f"# fp8: {f8['ms']:.1f} ms/step", file=sys.stderr, flush=True)
+        r8 = {"value": px / (f8["ms"] * 1e-3) / 1e6, "ms_per_step": f8["ms"], "steps": args.fp8_steps,
+              "dtype": "fp8 e4m3 (per-channel power-of-two scales), FP32 accumulation",
+              "calibration": f"{f8['calibration_tiles']} first kept tiles on the FP32 path "
+                             f"({f8['calibration_s']:.1f} s)",
+              "roofline": roofline(om, f8["records"], "fp8"), "autotuned_conv_tiles": f8["tuned"],
+              "speedup_vs_bf16": bf["ms"] / f8["ms"],
+              "stages": stage_summary([dict(r, ms=r["ms"] / args.fp8_steps, flops=r["flops"] / args.fp8_steps,
+                                            bytes=r["bytes"] / args.fp8_steps) for r in f8["records"]])}
+        if "fp32" in result:
+            d8 = [M.dice(a, b) for a, b in zip(f8["masks"], fp["masks"])]
+            r8["fp8_vs_fp32_masks"] = {"dice_min": min(d8), "dice_mean": float(np.mean(d8)),
+                                       "disagreement_max": max(M.disagreement(a, b)
+                                                               for a, b in zip(f8["masks"], fp["masks"]))}
+        result["fp8"] = r8
     if args.train_steps > 0:
         result["train_step"] = train_leg(om, torch, args.train_steps, 1)
         print(f"# train: {result['train_step']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)

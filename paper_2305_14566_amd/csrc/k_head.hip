@@ -11,6 +11,8 @@
 // arithmetic is FP32; the per-tile parameters live in LDS.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace omniseg {
 
 __device__ __forceinline__ float ld1(const float* p) { return *p; }
@@ -29,7 +31,7 @@ __global__ __launch_bounds__(256) void k_gap(const T* __restrict__ e, int hw, in
   for (int ch = threadIdx.x; ch < c; ch += blockDim.x) {
     float s = 0.f;
     for (int p = 0; p < hw; ++p) s += ld1(base + (int64_t)p * c_p + ch);
-    if (scale) s *= scale[ch];
+    if constexpr (std::is_same<T, uint8_t>::value) s *= scale[ch];
     g[(int64_t)b * c_p + ch] = s / (float)hw;
   }
 }
@@ -123,7 +125,8 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
 #pragma unroll
     for (int o = 0; o < 8; ++o) F[o] = swp[8 * c0 + o];
     for (int c = 0; c < c0; ++c) {
-      const float v = dscale ? ld1(px + c) * dscale[c] : ld1(px + c);
+      float v = ld1(px + c);
+      if constexpr (std::is_same<T, uint8_t>::value) v *= dscale[c];
 #pragma unroll
       for (int o = 0; o < 8; ++o) F[o] = fmaf(swp[o * c0 + c], v, F[o]);
     }
@@ -131,7 +134,10 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
     for (int o = 0; o < 8; ++o) F[o] = fmaxf(F[o], 0.f);
   } else {
 #pragma unroll
-    for (int o = 0; o < 8; ++o) F[o] = dscale ? ld1(px + o) * dscale[o] : ld1(px + o);
+    for (int o = 0; o < 8; ++o) {
+      F[o] = ld1(px + o);
+      if constexpr (std::is_same<T, uint8_t>::value) F[o] *= dscale[o];
+    }
   }
   for (int j = 0; j < ns; ++j) {
     const float* th = &sth[j * P];
