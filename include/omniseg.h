@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define OMNISEG_ABI_VERSION 3
+#define OMNISEG_ABI_VERSION 4
 
 /* status codes */
 #define OMNISEG_OK 0
@@ -325,6 +325,11 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
  * (ignored by the DGRAD modes).  config: a tile configuration id (see
  * omniseg_conv_config) valid for the shape, or -1 for the default; ERR_ARG
  * if it does not fit H, W and the output channels.
+ * y_pool: NULL, or (mode OMNISEG_CONV_RES_RELU, BF16, with a row-reuse
+ * configuration or -1) device [n][H/2][W/2][pad32(cout)] that receives the
+ * 2x2 max-pool of y as well -- the encoder's next input, written by the same
+ * kernel (ERR_UNSUPPORTED for FP32, ERR_ARG for other modes or
+ * configurations).
  * workspace: device, >= omniseg_conv3x3_workspace_bytes.
  */
 #define OMNISEG_CONV_RELU 0
@@ -338,7 +343,8 @@ int32_t omniseg_conv3x3_workspace_bytes(int32_t precision, int32_t cin, int32_t 
 int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t height, int32_t width,
                         int32_t cin, int32_t cu, int32_t cout, const float* weights,
                         const float* bias, const void* x0, const void* x1, const void* aux, void* y,
-                        int32_t config, void* workspace, int64_t ws_bytes, omniseg_stream stream);
+                        void* y_pool, int32_t config, void* workspace, int64_t ws_bytes,
+                        omniseg_stream stream);
 /*
  * FP8 form of omniseg_conv3x3 (modes RELU, RES_RELU, POOL_RELU, UPCAT_RELU;
  * the FP8 backbone described at omniseg_pack_weights_fp8).  x0 (and x1 for
@@ -349,16 +355,17 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
  * the result with the power-of-two channel scales out_scale (device
  * float[cout]).  The weights are quantised as omniseg_pack_weights_fp8 does,
  * with in_scale folded into their columns; RES_RELU (cin == cout) decodes
- * the residual with in_scale.  config: a configuration whose precisions
- * include OMNISEG_FP8, or -1.  workspace: device, 256-byte aligned, >=
- * omniseg_conv3x3_fp8_workspace_bytes.
+ * the residual with in_scale.  y_pool: NULL, or (RES_RELU) the codes of the
+ * 2x2 max-pool of y, [n][H/2][W/2][pad32(cout)], same scales.  config: a
+ * configuration whose precisions include OMNISEG_FP8, or -1.  workspace:
+ * device, 256-byte aligned, >= omniseg_conv3x3_fp8_workspace_bytes.
  */
 int32_t omniseg_conv3x3_fp8_workspace_bytes(int32_t cin, int32_t cu, int32_t cout, int64_t* bytes);
 int32_t omniseg_conv3x3_fp8(int32_t mode, int32_t n, int32_t height, int32_t width, int32_t cin,
                             int32_t cu, int32_t cout, const float* weights, const float* bias,
                             const float* in_scale, const float* out_scale, const void* x0,
-                            const void* x1, void* y, int32_t config, void* workspace,
-                            int64_t ws_bytes, omniseg_stream stream);
+                            const void* x1, void* y, void* y_pool, int32_t config,
+                            void* workspace, int64_t ws_bytes, omniseg_stream stream);
 
 /*
  * ---- training: forward over a tile batch, BCE loss, hand-written backward ----

@@ -61,6 +61,7 @@ struct Layout {
   int64_t off_index = 0, off_list = 0, off_count = 0;
   int64_t off_E[8], off_A = 0, off_g = 0, off_theta = 0, off_logits = 0;
   int64_t sz_E[8], sz_A = 0, sz_logits = 0;
+  int64_t off_P = 0, sz_P = 0;  // pooled encoder output (row-reuse precisions)
   int64_t total = 0;
 };
 
@@ -141,6 +142,23 @@ int32_t validate_call(const omniseg_plan* plan, const omniseg_slide* slides, int
   return OMNISEG_OK;
 }
 
+// BF16 and FP8 inference fuse the encoder's 2x2 max-pool into the residual
+// conv that produces E_l (its row-reuse epilogue also writes the pooled
+// tensor), so the next level's conv_a reads it with the plain loader.
+bool fuse_pool(const omniseg_plan* plan) { return plan->cfg.precision != OMNISEG_FP32 && plan->L >= 2; }
+
+// Conv configuration of an encoder residual conv that writes the pooled copy:
+// the tuned one if it is a valid row-reuse configuration, else the first
+// valid row-reuse configuration.
+int pool_config(const omniseg_plan* plan, int level, int H, int W, int cout_p) {
+  const int prec = plan->cfg.precision;
+  const int t = plan->tune[1][level];
+  if (t >= CONV_CFG_ROWS_16x16_64 && conv_config_valid(t, prec, H, W, cout_p)) return t;
+  for (int c : {CONV_CFG_ROWS_16x16_64, CONV_CFG_ROWS_16x16_32, CONV_CFG_ROWS_32x16_32, CONV_CFG_ROWS_16x16_128})
+    if (conv_config_valid(c, prec, H, W, cout_p)) return c;
+  return -1;
+}
+
 void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32_t n_slides,
                     Layout& lay) {
   const omniseg_config& c = plan->cfg;
@@ -195,6 +213,11 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
   }
   lay.sz_A = (int64_t)lay.batch * T * T * plan->Cp[0] * es;
   lay.off_A = take(lay.sz_A);
+  if (fuse_pool(plan)) {
+    // the largest pooled encoder output is level 0's: (T/2)^2 pixels x C_0
+    lay.sz_P = (int64_t)lay.batch * (T / 2) * (T / 2) * plan->Cp[0] * es;
+    lay.off_P = take(lay.sz_P);
+  }
   lay.off_g = take((int64_t)lay.batch * plan->Cp[plan->L - 1] * 4);
   lay.off_theta = take((int64_t)lay.batch * lay.max_slots * plan->P * 4);
   lay.logit_cap = c.max_kept_tiles > 0 ? std::min(tiles, c.max_kept_tiles) : tiles;
@@ -812,20 +835,35 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
       HIP_TRY(launch_first_conv(prec, fa, sm));
       HIP_TRY(prof.end(OMNISEG_STAGE_FIRST_CONV, 0, nb, 2.0 * 27 * plan->C[0] * (double)T * T * nb,
                        (double)T * T * nb * (3.0 + plan->C[0] * es)));
-      HIP_TRY(prof.begin());
-      int cf = layer_config(plan, 1, 0, T, T, plan->enc_b[0].cout_p);
-      HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[0]), T, T, nb, count, base, A, nullptr, E[0], sm, nullptr, cf));
-      HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, 0, nb, conv_flops(plan->enc_b[0], T, nb), conv_bytes(plan->enc_b[0], T, nb, 1.0, true), cf));
-      for (int l = 1; l < L; ++l) {
+      // encoder; with the fused pool, enc_b writes E_l and its pooled copy P
+      // and the next conv_a reads P with the plain loader
+      const bool fp = fuse_pool(plan);
+      void* P = ws + lay.off_P;
+      for (int l = 0; l < L; ++l) {
         const int tl = T >> l;
+        int cf;
+        if (l > 0) {
+          HIP_TRY(prof.begin());
+          cf = layer_config(plan, 0, l, tl, tl, plan->enc_a[l].cout_p);
+          HIP_TRY(launch_conv3x3(prec, fp ? LOAD_PLAIN : LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count,
+                                 base, fp ? P : E[l - 1], nullptr, A, sm, nullptr, cf));
+          HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nb, conv_flops(plan->enc_a[l], tl, nb),
+                           conv_bytes(plan->enc_a[l], tl, nb, fp ? 1.0 : 4.0, false), cf));
+        }
         HIP_TRY(prof.begin());
-        cf = layer_config(plan, 0, l, tl, tl, plan->enc_a[l].cout_p);
-        HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count, base, E[l - 1], nullptr, A, sm, nullptr, cf));
-        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nb, conv_flops(plan->enc_a[l], tl, nb), conv_bytes(plan->enc_a[l], tl, nb, 4.0, false), cf));
-        HIP_TRY(prof.begin());
-        cf = layer_config(plan, 1, l, tl, tl, plan->enc_b[l].cout_p);
-        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->enc_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm, nullptr, cf));
-        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nb, conv_flops(plan->enc_b[l], tl, nb), conv_bytes(plan->enc_b[l], tl, nb, 1.0, true), cf));
+        ConvLayer lb = layer(plan->enc_b[l]);
+        double pooled_bytes = 0.0;
+        if (fp && l + 1 < L) {
+          lb.pool_out = P;
+          cf = pool_config(plan, l, tl, tl, plan->enc_b[l].cout_p);
+          pooled_bytes = (double)nb * (tl / 2) * (tl / 2) * plan->enc_b[l].cout * es;
+        } else {
+          cf = layer_config(plan, 1, l, tl, tl, plan->enc_b[l].cout_p);
+        }
+        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, lb, tl, tl, nb, count, base, A, nullptr, E[l], sm,
+                               nullptr, cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nb, conv_flops(plan->enc_b[l], tl, nb),
+                         conv_bytes(plan->enc_b[l], tl, nb, 1.0, true) + pooled_bytes, cf));
       }
       const int tb = T >> (L - 1);
       HIP_TRY(prof.begin());
@@ -841,7 +879,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
         const int tl = T >> l;
         // decoder level l: Z = [up2(D_{l+1}) ; E_l]; D_{l+1} lives in E[l+1]'s buffer
         HIP_TRY(prof.begin());
-        cf = layer_config(plan, 2, l, tl, tl, plan->dec_a[l].cout_p);
+        int cf = layer_config(plan, 2, l, tl, tl, plan->dec_a[l].cout_p);
         HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1], E[l], A, sm, nullptr, cf));
         HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nb, conv_flops(plan->dec_a[l], tl, nb), conv_bytes(plan->dec_a[l], tl, nb, 0.5, false), cf));
         HIP_TRY(prof.begin());
@@ -996,6 +1034,9 @@ int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_s
   }
   void* A = ws + lay.off_A;
   HIP_TRY(launch_zero(A, lay.sz_A, sm));
+  const bool fp = fuse_pool(plan);
+  void* P = ws + lay.off_P;
+  if (fp) HIP_TRY(launch_zero(P, lay.sz_P, sm));
   int32_t* count = reinterpret_cast<int32_t*>(ws + lay.off_count);
   HIP_TRY(launch_set_i32(count, B, sm));
   hipEvent_t e0, e1;
@@ -1008,19 +1049,25 @@ int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_s
       if ((stg == 0 && l == 0) || (stg >= 2 && l >= L - 1)) continue;
       const ConvDesc& d = stg == 0 ? plan->enc_a[l] : stg == 1 ? plan->enc_b[l] : stg == 2 ? plan->dec_a[l] : plan->dec_b[l];
       const int h = T >> l;
-      const int loader = stg == 0 ? LOAD_POOL : stg == 2 ? LOAD_UPCAT : LOAD_PLAIN;
+      // the launches segment_slide makes: with the fused pool, conv_a reads the
+      // pooled tensor plainly and the residual conv also writes it
+      const int loader = stg == 0 ? (fp ? LOAD_PLAIN : LOAD_POOL) : stg == 2 ? LOAD_UPCAT : LOAD_PLAIN;
       const int epi = (stg == 1 || stg == 3) ? EPI_RES_RELU : EPI_RELU;
-      const void* x0 = stg == 0 ? E[l - 1] : stg == 2 ? E[l + 1] : A;
+      const void* x0 = stg == 0 ? (fp ? P : E[l - 1]) : stg == 2 ? E[l + 1] : A;
       const void* x1 = stg == 2 ? E[l] : nullptr;
       void* y = (stg == 1 || stg == 3) ? E[l] : A;
+      const bool pooled = fp && stg == 1 && l + 1 < L;
+      ConvLayer Ly = layer(d);
+      if (pooled) Ly.pool_out = P;
       int best = -1;
       float best_ms = 1e30f;
       for (int cf = 0; cf < CONV_CFG_COUNT; ++cf) {
         if (!conv_config_valid(cf, prec, h, h, d.cout_p)) continue;
-        hipError_t e = launch_conv3x3(prec, loader, epi, layer(d), h, h, B, count, 0, x0, x1, y, sm, nullptr, cf);
+        if (pooled && cf < CONV_CFG_ROWS_16x16_64) continue;
+        hipError_t e = launch_conv3x3(prec, loader, epi, Ly, h, h, B, count, 0, x0, x1, y, sm, nullptr, cf);
         if (e == hipSuccess) e = hipEventRecord(e0, sm);
         for (int r = 0; r < 2 && e == hipSuccess; ++r)
-          e = launch_conv3x3(prec, loader, epi, layer(d), h, h, B, count, 0, x0, x1, y, sm, nullptr, cf);
+          e = launch_conv3x3(prec, loader, epi, Ly, h, h, B, count, 0, x0, x1, y, sm, nullptr, cf);
         if (e == hipSuccess) e = hipEventRecord(e1, sm);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -1072,10 +1119,26 @@ int32_t omniseg_conv3x3_workspace_bytes(int32_t precision, int32_t cin, int32_t 
   return OMNISEG_OK;
 }
 
+// Row-reuse configuration for a stand-alone conv with a pooled output: the
+// requested one (which must be row-reuse), or the first that fits.
+static int32_t pooled_conv_config(int precision, int config, int H, int W, int cout_p, int* out) {
+  if (config != -1) {
+    if (config < CONV_CFG_ROWS_16x16_64) return fail(OMNISEG_ERR_ARG, "a pooled output needs a row-reuse configuration");
+    *out = config;
+    return OMNISEG_OK;
+  }
+  for (int c : {CONV_CFG_ROWS_16x16_64, CONV_CFG_ROWS_16x16_32, CONV_CFG_ROWS_32x16_32, CONV_CFG_ROWS_16x16_128})
+    if (conv_config_valid(c, precision, H, W, cout_p)) {
+      *out = c;
+      return OMNISEG_OK;
+    }
+  return fail(OMNISEG_ERR_UNSUPPORTED, "no row-reuse configuration fits %dx%d", H, W);
+}
+
 int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t height, int32_t width, int32_t cin,
                         int32_t cu, int32_t cout, const float* weights, const float* bias, const void* x0,
-                        const void* x1, const void* aux, void* y, int32_t config, void* workspace, int64_t ws_bytes,
-                        omniseg_stream stream) {
+                        const void* x1, const void* aux, void* y, void* y_pool, int32_t config, void* workspace,
+                        int64_t ws_bytes, omniseg_stream stream) {
   int64_t need = 0;
   int32_t st = omniseg_conv3x3_workspace_bytes(precision, cin, cu, cout, &need);
   if (st) return st;
@@ -1097,6 +1160,12 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
     const int out_p = dgrad ? (cu < cin ? pad_ch(cu) + pad_ch(cin - cu) : pad_ch(cin)) : pad_ch(cout);
     if (config != -1 && !conv_config_valid(config, precision, height, width, out_p))
       return fail(OMNISEG_ERR_ARG, "conv config %d does not fit %dx%d with %d output channels", config, height, width, out_p);
+    if (y_pool) {
+      if (precision == OMNISEG_FP32) return fail(OMNISEG_ERR_UNSUPPORTED, "a pooled output needs BF16 or FP8");
+      if (mode != OMNISEG_CONV_RES_RELU) return fail(OMNISEG_ERR_ARG, "a pooled output needs mode RES_RELU");
+      const int32_t pst = pooled_conv_config(precision, config, height, width, out_p, &config);
+      if (pst) return pst;
+    }
   }
   if (ws_bytes < need) return fail(OMNISEG_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OMNISEG_ERR_ARG, "workspace not 256-byte aligned");
@@ -1137,6 +1206,7 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
     L.cu_p = pc.cu_p;
     L.cout_p = cout_p;
   }
+  L.pool_out = y_pool;
   static const int loader_of[] = {LOAD_PLAIN, LOAD_PLAIN, LOAD_POOL, LOAD_UPCAT, LOAD_PLAIN, LOAD_PLAIN};
   static const int epi_of[] = {EPI_RELU, EPI_RES_RELU, EPI_RELU, EPI_RELU, EPI_NONE, EPI_RES_MASK};
   HIP_TRY(launch_conv3x3(precision, loader_of[mode], epi_of[mode], L, height, width, n, count, 0, x0, x1, y, sm, aux,
@@ -1174,8 +1244,8 @@ int32_t omniseg_conv3x3_fp8_workspace_bytes(int32_t cin, int32_t cu, int32_t cou
 
 int32_t omniseg_conv3x3_fp8(int32_t mode, int32_t n, int32_t height, int32_t width, int32_t cin, int32_t cu,
                             int32_t cout, const float* weights, const float* bias, const float* in_scale,
-                            const float* out_scale, const void* x0, const void* x1, void* y, int32_t config,
-                            void* workspace, int64_t ws_bytes, omniseg_stream stream) {
+                            const float* out_scale, const void* x0, const void* x1, void* y, void* y_pool,
+                            int32_t config, void* workspace, int64_t ws_bytes, omniseg_stream stream) {
   int64_t need = 0;
   int32_t st = omniseg_conv3x3_fp8_workspace_bytes(cin, cu, cout, &need);
   if (st) return st;
@@ -1196,6 +1266,7 @@ int32_t omniseg_conv3x3_fp8(int32_t mode, int32_t n, int32_t height, int32_t wid
                 width, f.cout_p);
   if (conv_default_config(OMNISEG_FP8, height, width, f.cout_p) < 0)
     return fail(OMNISEG_ERR_UNSUPPORTED, "no FP8 configuration fits %dx%d", height, width);
+  if (y_pool && mode != OMNISEG_CONV_RES_RELU) return fail(OMNISEG_ERR_ARG, "a pooled output needs mode RES_RELU");
   if (ws_bytes < need) return fail(OMNISEG_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OMNISEG_ERR_ARG, "workspace not 256-byte aligned");
   hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
@@ -1232,6 +1303,7 @@ int32_t omniseg_conv3x3_fp8(int32_t mode, int32_t n, int32_t height, int32_t wid
   L.wscale = wscale;
   L.rscale = s_in;
   L.oinv = oinv;
+  L.pool_out = y_pool;
   static const int loader_of[] = {LOAD_PLAIN, LOAD_PLAIN, LOAD_POOL, LOAD_UPCAT};
   static const int epi_of[] = {EPI_RELU, EPI_RES_RELU, EPI_RELU, EPI_RELU};
   HIP_TRY(launch_conv3x3(OMNISEG_FP8, loader_of[mode], epi_of[mode], L, height, width, n, count, 0, x0, x1, y, sm,

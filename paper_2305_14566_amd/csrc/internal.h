@@ -88,6 +88,9 @@ struct ConvLayer {
   const float* wscale = nullptr;
   const float* rscale = nullptr;
   const float* oinv = nullptr;
+  // BF16 / FP8 row-reuse configurations, RES_RELU: also write the 2x2
+  // max-pool of the output here ([batch][H/2][W/2][cout_p]); null = no pool
+  void* pool_out = nullptr;
 };
 
 // FP8 E4M3 storage: channels per LDS chunk of the FP8 conv (one K = 64 MFMA

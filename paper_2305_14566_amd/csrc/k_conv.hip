@@ -75,6 +75,7 @@ struct ConvArgs {
   const float* wscale;  // FP8 epilogue scales (see ConvLayer)
   const float* rscale;
   const float* oinv;
+  void* pool_out;  // row-reuse epilogues: also write the 2x2 max-pool of y here (or null)
 };
 
 __device__ __forceinline__ uint4 vmax(uint4 a, uint4 b, float) {
@@ -481,6 +482,40 @@ void k_conv3x3_rows(ConvArgs a) {
     u.z = (uint32_t)f2bf(v[4]) | ((uint32_t)f2bf(v[5]) << 16);
     u.w = (uint32_t)f2bf(v[6]) | ((uint32_t)f2bf(v[7]) << 16);
     *reinterpret_cast<uint4*>(out + o) = u;
+    if (a.pool_out) {  // keep the final values for the pooled copy
+      *reinterpret_cast<f32x4*>(&sO[p * OROW + c]) = f32x4{v[0], v[1], v[2], v[3]};
+      *reinterpret_cast<f32x4*>(&sO[p * OROW + c + 4]) = f32x4{v[4], v[5], v[6], v[7]};
+    }
+  }
+  if (a.pool_out) {
+    // 2x2 max-pool of the block's output (BY and 16 are even, blocks start at
+    // even coordinates): max commutes with the monotonic BF16 rounding, so
+    // this is the pool of the stored output.
+    __syncthreads();
+    T* pout = (T*)a.pool_out;
+    const int Hh = a.H >> 1, Wh = a.W >> 1;
+    for (int i = tid; i < (BY / 2) * (BX / 2) * NVO; i += 256) {
+      const int q = i / NVO, c = (i % NVO) * 8;
+      const int py = q / (BX / 2), px = q % (BX / 2);
+      const int p00 = (2 * py) * BX + 2 * px;
+      float m[8];
+#pragma unroll
+      for (int j = 0; j < 8; j += 4) {
+        const f32x4 a0 = *reinterpret_cast<const f32x4*>(&sO[p00 * OROW + c + j]);
+        const f32x4 a1 = *reinterpret_cast<const f32x4*>(&sO[(p00 + 1) * OROW + c + j]);
+        const f32x4 a2 = *reinterpret_cast<const f32x4*>(&sO[(p00 + BX) * OROW + c + j]);
+        const f32x4 a3 = *reinterpret_cast<const f32x4*>(&sO[(p00 + BX + 1) * OROW + c + j]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m[j + k] = fmaxf(fmaxf(a0[k], a1[k]), fmaxf(a2[k], a3[k]));
+      }
+      const int64_t o = (((int64_t)b * Hh + (y0 >> 1) + py) * Wh + (x0 >> 1) + px) * a.cout_p + n0 + c;
+      uint4 u;
+      u.x = (uint32_t)f2bf(m[0]) | ((uint32_t)f2bf(m[1]) << 16);
+      u.y = (uint32_t)f2bf(m[2]) | ((uint32_t)f2bf(m[3]) << 16);
+      u.z = (uint32_t)f2bf(m[4]) | ((uint32_t)f2bf(m[5]) << 16);
+      u.w = (uint32_t)f2bf(m[6]) | ((uint32_t)f2bf(m[7]) << 16);
+      *reinterpret_cast<uint4*>(pout + o) = u;
+    }
   }
 }
 
@@ -652,8 +687,35 @@ void k_conv3x3_fp8(ConvArgs a) {
         e[k] = (t > 0.f ? t : 0.f) * a.oinv[n + 4 * j + k];  // ReLU; +0 for the rest
       }
       ow[j] = fp8_encode4(e[0], e[1], e[2], e[3]);
+      if (a.pool_out) *reinterpret_cast<f32x4*>(&sO[p * OROW + c + 4 * j]) = f32x4{e[0], e[1], e[2], e[3]};
     }
     *reinterpret_cast<uint4*>(out + o) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+  }
+  if (a.pool_out) {
+    // 2x2 max-pool of the scaled outputs; encoding is monotonic, so the pooled
+    // code is the max of the four stored codes (the scales carry over).
+    __syncthreads();
+    T* pout = (T*)a.pool_out;
+    const int Hh = a.H >> 1, Wh = a.W >> 1;
+    for (int i = tid; i < (BY / 2) * (BX / 2) * NVO; i += 256) {
+      const int q = i / NVO, c = (i % NVO) * 16;
+      const int py = q / (BX / 2), px = q % (BX / 2);
+      const int p00 = (2 * py) * BX + 2 * px;
+      uint32_t ow[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const f32x4 a0 = *reinterpret_cast<const f32x4*>(&sO[p00 * OROW + c + 4 * j]);
+        const f32x4 a1 = *reinterpret_cast<const f32x4*>(&sO[(p00 + 1) * OROW + c + 4 * j]);
+        const f32x4 a2 = *reinterpret_cast<const f32x4*>(&sO[(p00 + BX) * OROW + c + 4 * j]);
+        const f32x4 a3 = *reinterpret_cast<const f32x4*>(&sO[(p00 + BX + 1) * OROW + c + 4 * j]);
+        float m[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m[k] = fmaxf(fmaxf(a0[k], a1[k]), fmaxf(a2[k], a3[k]));
+        ow[j] = fp8_encode4(m[0], m[1], m[2], m[3]);
+      }
+      const int64_t o = (((int64_t)b * Hh + (y0 >> 1) + py) * Wh + (x0 >> 1) + px) * a.cout_p + n0 + c;
+      *reinterpret_cast<uint4*>(pout + o) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+    }
   }
 }
 
@@ -680,6 +742,8 @@ static hipError_t launch_conv_fp8_t(const ConvLayer& L, int H, int W, int batch,
   a.wscale = L.wscale;
   a.rscale = L.rscale;
   a.oinv = L.oinv;
+  a.pool_out = L.pool_out;
+  if (L.pool_out && EPI != EPI_RES_RELU) return hipErrorInvalidValue;
   const int64_t blocks = (int64_t)batch * a.tiles_y * a.tiles_x * a.n_nblk;
   hipLaunchKernelGGL((k_conv3x3_fp8<BY, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();
@@ -706,6 +770,8 @@ static hipError_t launch_conv_rows_t(const ConvLayer& L, int H, int W, int batch
   a.tiles_y = H / BY;
   a.tiles_x = W / 16;
   a.n_nblk = L.cout_p / BN;
+  a.pool_out = L.pool_out;
+  if (L.pool_out && EPI != EPI_RES_RELU) return hipErrorInvalidValue;
   const int64_t blocks = (int64_t)batch * a.tiles_y * a.tiles_x * a.n_nblk;
   hipLaunchKernelGGL((k_conv3x3_rows<BY, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();
@@ -732,6 +798,8 @@ static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, con
   a.tiles_y = H / BY;
   a.tiles_x = W / BX;
   a.n_nblk = L.cout_p / BN;
+  a.pool_out = nullptr;
+  if (L.pool_out) return hipErrorInvalidValue;  // the pooled copy needs a row-reuse configuration
   const int64_t blocks = (int64_t)batch * a.tiles_y * a.tiles_x * a.n_nblk;
   hipLaunchKernelGGL((k_conv3x3<T, BY, BX, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks),
                      dim3(256), 0, st, a);

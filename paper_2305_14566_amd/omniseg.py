@@ -20,7 +20,7 @@ FLAG_TRAINING = 2
 FLAG_GRAPH = 4
 (REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
  REGION_TILE_INDEX, REGION_TILE_LOGITS) = range(7)
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
 N_CONV_CONFIGS = 10
@@ -107,11 +107,12 @@ def _declare(lib):
         "omniseg_backward": (i32, [vp, vp, P(Slide), P(Tile), i32, P(Pair), i32, vp, vp, vp, i64, vp]),
         "omniseg_bce_loss": (i32, [vp, vp, vp, i64, vp, vp, vp, i64, vp]),
         "omniseg_conv3x3_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
-        "omniseg_conv3x3": (i32, [i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, i32, vp, i64, vp]),
+        "omniseg_conv3x3": (i32, [i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, i64,
+                                  vp]),
         "omniseg_read_profile": (i32, [vp, P(LaunchRecord), i32, P(i32)]),
         "omniseg_conv3x3_fp8_workspace_bytes": (i32, [i32, i32, i32, P(i64)]),
-        "omniseg_conv3x3_fp8": (i32, [i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, i64,
-                                      vp]),
+        "omniseg_conv3x3_fp8": (i32, [i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp,
+                                      i64, vp]),
         "omniseg_activation_channels": (i32, [vp, P(i64)]),
         "omniseg_activation_offset": (i32, [vp, i32, i32, P(i64)]),
         "omniseg_calibrate_fp8": (i32, [vp, vp, P(Slide), i32, P(Pair), i32, i32, vp, vp, i64, vp]),
@@ -451,10 +452,12 @@ class BCELossFn(torch.autograd.Function):
 
 
 def conv3x3(precision, mode, x0, weights, bias=None, x1=None, aux=None, cin=None, cu=None, cout=None,
-            height=None, width=None, config=-1, stream=None):
+            height=None, width=None, config=-1, stream=None, pool=False):
     """Stand-alone backbone conv on NHWC tensors with 32-padded channels.
 
-    Returns y (same dtype as x0) of shape [n, H, W, pad32(out channels)].
+    Returns y (same dtype as x0) of shape [n, H, W, pad32(out channels)];
+    with pool=True also its 2x2 max-pool [n, H/2, W/2, ...] from the same
+    kernel, as (y, y_pool).
     """
     n = x0.shape[0]
     cout_, cin_ = weights.shape[0], weights.shape[1]
@@ -472,17 +475,18 @@ def conv3x3(precision, mode, x0, weights, bias=None, x1=None, aux=None, cin=None
     else:
         out_c = p32(cout)
     y = torch.empty((n, height, width, out_c), dtype=x0.dtype, device=x0.device)
+    yp = torch.empty((n, height // 2, width // 2, out_c), dtype=x0.dtype, device=x0.device) if pool else None
     nb = ctypes.c_int64()
     _check(lib().omniseg_conv3x3_workspace_bytes(precision, cin, cu, cout, ctypes.byref(nb)))
     ws = torch.empty(nb.value, dtype=torch.uint8, device=x0.device)
     _check(lib().omniseg_conv3x3(precision, mode, n, height, width, cin, cu, cout, _ptr(weights), _ptr(bias),
-                                 _ptr(x0), _ptr(x1), _ptr(aux), _ptr(y), config, _ptr(ws), ws.numel(),
+                                 _ptr(x0), _ptr(x1), _ptr(aux), _ptr(y), _ptr(yp), config, _ptr(ws), ws.numel(),
                                  _stream(stream)))
-    return y
+    return (y, yp) if pool else y
 
 
 def conv3x3_fp8(mode, x0, weights, bias, in_scale, out_scale, x1=None, cu=None, height=None, width=None,
-                config=-1, stream=None):
+                config=-1, stream=None, pool=False):
     """Stand-alone FP8 backbone conv: x0 (x1) uint8 E4M3 codes, NHWC with
     32-padded channels, channel scales in_scale (real channel order) and
     out_scale.  Returns the uint8 output codes [n, H, W, pad32(cout)]."""
@@ -495,13 +499,14 @@ def conv3x3_fp8(mode, x0, weights, bias, in_scale, out_scale, x1=None, cu=None, 
         width = x0.shape[2] // 2 if mode == CONV_POOL_RELU else (x0.shape[2] * 2 if mode == CONV_UPCAT_RELU
                                                                  else x0.shape[2])
     y = torch.empty((n, height, width, -(-cout // 32) * 32), dtype=torch.uint8, device=x0.device)
+    yp = torch.empty((n, height // 2, width // 2, y.shape[3]), dtype=torch.uint8, device=x0.device) if pool else None
     nb = ctypes.c_int64()
     _check(lib().omniseg_conv3x3_fp8_workspace_bytes(cin, cu, cout, ctypes.byref(nb)))
     ws = torch.empty(nb.value, dtype=torch.uint8, device=x0.device)
     _check(lib().omniseg_conv3x3_fp8(mode, n, height, width, cin, cu, cout, _ptr(weights), _ptr(bias),
-                                     _ptr(in_scale), _ptr(out_scale), _ptr(x0), _ptr(x1), _ptr(y), config, _ptr(ws),
-                                     ws.numel(), _stream(stream)))
-    return y
+                                     _ptr(in_scale), _ptr(out_scale), _ptr(x0), _ptr(x1), _ptr(y), _ptr(yp), config,
+                                     _ptr(ws), ws.numel(), _stream(stream)))
+    return (y, yp) if pool else y
 
 
 def conv_config(config):

@@ -293,11 +293,16 @@ def test_conv_config_query_and_precision_gate():
     lib = om.lib()
     ws = ctypes.c_int64()
     assert lib.omniseg_conv3x3_workspace_bytes(om.FP32, 64, 64, 64, ctypes.byref(ws)) == 0
-    call = lambda prec, cfg, h=32, w=32: lib.omniseg_conv3x3(prec, om.CONV_RELU, 1, h, w, 64, 64, 64, FAKE, FAKE,
-                                                             FAKE, None, None, FAKE, cfg, FAKE, ws.value, None)
+    def call(prec, cfg, h=32, w=32, mode=om.CONV_RELU, pool=None):
+        return lib.omniseg_conv3x3(prec, mode, 1, h, w, 64, 64, 64, FAKE, FAKE, FAKE, None, None, FAKE, pool, cfg,
+                                   FAKE, ws.value, None)
     assert call(om.FP32, 6) == 1           # row-reuse configuration at FP32
     assert call(om.BF16, 8, h=16) == 1     # 32-row block on a 16-row image
     assert call(om.BF16, 3, w=24) == 1     # 16-pixel block on a 24-pixel-wide image
+    # the pooled copy: BF16 / FP8 only, RES_RELU only, row-reuse configurations only
+    assert call(om.FP32, -1, mode=om.CONV_RES_RELU, pool=FAKE) == 2
+    assert call(om.BF16, -1, mode=om.CONV_RELU, pool=FAKE) == 1
+    assert call(om.BF16, 1, mode=om.CONV_RES_RELU, pool=FAKE) == 1
 
 
 def test_fp8_plan_validation_and_activation_table():
