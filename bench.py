@@ -99,6 +99,21 @@ def roofline(om, records, prec):
                 all_convs_frac=conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec])
 
 
+def layer_summary(records, steps):
+    """Per (stage, level) conv time and rate, per step."""
+    out = {}
+    for r in records:
+        if r["stage"] not in ("enc_a", "enc_b", "dec_a", "dec_b"):
+            continue
+        s = out.setdefault(f"{r['stage']}{r['level']}", dict(ms=0.0, flops=0.0, launches=0, config=r["config"]))
+        s["ms"] += r["ms"] / steps
+        s["flops"] += r["flops"] / steps
+        s["launches"] += 1
+    for s in out.values():
+        s["tflops"] = s["flops"] / max(s["ms"], 1e-9) / 1e9
+    return out
+
+
 def stage_summary(records):
     out = {}
     for r in records:
@@ -403,6 +418,7 @@ def main():
         "stages_bf16": stage_summary([dict(r, ms=r["ms"] / args.steps, flops=r["flops"] / args.steps,
                                            bytes=r["bytes"] / args.steps) for r in bf["records"]]),
         "roofline": roofline(om, bf["records"], "bf16"),
+        "layers_bf16": layer_summary(bf["records"], args.steps),
         "autotuned_conv_tiles_bf16": bf["tuned"],
     }
     st = result["stages_bf16"].get("stitch")
@@ -428,6 +444,7 @@ def main():
               "calibration": f"{f8['calibration_tiles']} first kept tiles on the FP32 path "
                              f"({f8['calibration_s']:.1f} s)",
               "roofline": roofline(om, f8["records"], "fp8"), "autotuned_conv_tiles": f8["tuned"],
+              "layers": layer_summary(f8["records"], args.fp8_steps),
               "speedup_vs_bf16": bf["ms"] / f8["ms"],
               "stages": stage_summary([dict(r, ms=r["ms"] / args.fp8_steps, flops=r["flops"] / args.fp8_steps,
                                             bytes=r["bytes"] / args.fp8_steps) for r in f8["records"]])}

@@ -982,7 +982,6 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
   constexpr int VEC = 16 / sizeof(T);
   __shared__ float sIn[3][18][19];
-  __shared__ float sw[kFirstMaxC0 * 28];
   const int nb = a.T / 16;
   int rest = blockIdx.x;
   const int sx = rest % nb;
@@ -995,8 +994,6 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
   const int k = a.scale_k[t.y];
   const int oy = t.z * a.s, ox = t.w * a.s;  // tile origin at scale k
   const float scale = 1.0f / (255.0f * (float)(1 << (2 * k)));
-  for (int i = threadIdx.x; i < a.c0 * 27; i += 256) sw[(i / 27) * 28 + i % 27] = a.w[i];
-  for (int i = threadIdx.x; i < a.c0; i += 256) sw[i * 28 + 27] = a.b[i];
   for (int i = threadIdx.x; i < 18 * 18; i += 256) {
     const int py = i / 18, px = i % 18;
     const int ty = sy * 16 + py - 1, tx = sx * 16 + px - 1;
@@ -1040,6 +1037,11 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
       for (int dx = 0; dx < 3; ++dx) in[c * 9 + dy * 3 + dx] = sIn[c][py + dy][px + dx];
   const int y = sy * 16 + py, x = sx * 16 + px;
   T* out = (T*)a.y + (((int64_t)b * a.T + y) * a.T + x) * a.c0_p;
+  // The weights are the same for every thread and read-only here: read them
+  // as constant memory with uniform indices (scalar loads into SGPRs).
+  typedef const __attribute__((address_space(4))) float cfloat;
+  cfloat* wg = (cfloat*)a.w;
+  cfloat* bg = (cfloat*)a.b;
   for (int o0 = 0; o0 < a.c0_p; o0 += VEC) {
     float v[VEC];
 #pragma unroll
@@ -1047,10 +1049,9 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
       const int o = o0 + j;
       float acc = 0.f;
       if (o < a.c0) {
-        const float* wr = &sw[o * 28];
-        acc = wr[27];
+        acc = bg[o];
 #pragma unroll
-        for (int i = 0; i < 27; ++i) acc = fmaf(wr[i], in[i], acc);
+        for (int i = 0; i < 27; ++i) acc = fmaf(wg[o * 27 + i], in[i], acc);
         acc = acc > 0.f ? acc : 0.f;
         if (std::is_same<T, uint8_t>::value) acc *= a.oinv[o];
       }

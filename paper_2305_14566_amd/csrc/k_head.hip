@@ -20,50 +20,95 @@ __device__ __forceinline__ float ld1(const uint16_t* p) { return __uint_as_float
 // FP8: the E4M3 code's value (the caller applies the channel scale)
 __device__ __forceinline__ float ld1(const uint8_t* p) { return __builtin_amdgcn_cvt_f32_fp8((int)*p, 0); }
 
-// scale: FP8 channel scales (null for FP32 / BF16)
+// 16 bytes of a pixel row -> floats (4 FP32, 8 BF16 or 16 E4M3 code values)
+__device__ __forceinline__ void decode16(uint4 u, float* v /*[4]*/, float) {
+  v[0] = __uint_as_float(u.x);
+  v[1] = __uint_as_float(u.y);
+  v[2] = __uint_as_float(u.z);
+  v[3] = __uint_as_float(u.w);
+}
+__device__ __forceinline__ void decode16(uint4 u, float* v /*[8]*/, uint16_t) {
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[2 * i] = __uint_as_float(w[i] << 16);
+    v[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+__device__ __forceinline__ void decode16(uint4 u, float* v /*[16]*/, uint8_t) {
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[4 * i] = __builtin_amdgcn_cvt_f32_fp8((int)w[i], 0);
+    v[4 * i + 1] = __builtin_amdgcn_cvt_f32_fp8((int)w[i], 1);
+    v[4 * i + 2] = __builtin_amdgcn_cvt_f32_fp8((int)w[i], 2);
+    v[4 * i + 3] = __builtin_amdgcn_cvt_f32_fp8((int)w[i], 3);
+  }
+}
+template <typename T, int N>
+__device__ __forceinline__ void decode16(uint4 u, float (&v)[N]) {
+  decode16(u, &v[0], T());
+}
+
+// Bottleneck mean per channel.  One workgroup per (tile, 64-channel block):
+// lane l of wave w sums channel l over pixels w, w + 4, ... and the four
+// partial sums are added in LDS.  scale: FP8 channel scales (null for FP32 /
+// BF16).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gap(const T* __restrict__ e, int hw, int c_p, int c,
                                              const int32_t* count, int chunk_base, float* g,
                                              const float* __restrict__ scale) {
-  const int b = blockIdx.x;
+  const int nblk = (c + 63) / 64;
+  const int b = blockIdx.x / nblk, cb = blockIdx.x % nblk;
   if (chunk_base + b >= *count) return;
-  const T* base = e + (int64_t)b * hw * c_p;
-  for (int ch = threadIdx.x; ch < c; ch += blockDim.x) {
-    float s = 0.f;
-    for (int p = 0; p < hw; ++p) s += ld1(base + (int64_t)p * c_p + ch);
-    if constexpr (std::is_same<T, uint8_t>::value) s *= scale[ch];
-    g[(int64_t)b * c_p + ch] = s / (float)hw;
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ch = cb * 64 + lane;
+  float s = 0.f;
+  if (ch < c) {
+    const T* base = e + (int64_t)b * hw * c_p + ch;
+    for (int p = wave; p < hw; p += 4) s += ld1(base + (int64_t)p * c_p);
+  }
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && ch < c) {
+    float t = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    if constexpr (std::is_same<T, uint8_t>::value) t *= scale[ch];
+    g[(int64_t)b * c_p + ch] = t / (float)hw;
   }
 }
 
 hipError_t launch_gap(int precision, const void* e, int batch, int hw, int c_p, int c,
                       const int32_t* count, int chunk_base, float* g, hipStream_t st, const float* scale) {
+  const dim3 grid(batch * ((c + 63) / 64));
   if (precision == OMNISEG_FP8) {
     if (!scale) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gap<uint8_t>, dim3(batch), dim3(256), 0, st, (const uint8_t*)e, hw, c_p, c, count,
-                       chunk_base, g, scale);
-  } else if (precision == OMNISEG_BF16)
-    hipLaunchKernelGGL(k_gap<uint16_t>, dim3(batch), dim3(256), 0, st, (const uint16_t*)e, hw, c_p, c,
-                       count, chunk_base, g, nullptr);
-  else
-    hipLaunchKernelGGL(k_gap<float>, dim3(batch), dim3(256), 0, st, (const float*)e, hw, c_p, c, count,
-                       chunk_base, g, nullptr);
+    hipLaunchKernelGGL(k_gap<uint8_t>, grid, dim3(256), 0, st, (const uint8_t*)e, hw, c_p, c, count, chunk_base, g,
+                       scale);
+  } else if (precision == OMNISEG_BF16) {
+    hipLaunchKernelGGL(k_gap<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)e, hw, c_p, c, count, chunk_base,
+                       g, nullptr);
+  } else {
+    hipLaunchKernelGGL(k_gap<float>, grid, dim3(256), 0, st, (const float*)e, hw, c_p, c, count, chunk_base, g,
+                       nullptr);
+  }
   return hipGetLastError();
 }
 
-// theta[b][slot][p]; one workgroup per (tile, slot).  W_c rows are row_len =
-// G + n_classes + n_scales long.
+// theta[b][slot][p]; one workgroup per tile.  W_c rows are row_len =
+// G + n_classes + n_scales long.  The GAP part u[p] = W_c[p, :G] g is the same
+// for every class at the tile's scale, so it is formed once per tile and
+// shared by the tile's slots (same addition order as per slot).
 __global__ __launch_bounds__(256) void k_controller(const float* __restrict__ g, int g_stride, int G,
                                                      const float* __restrict__ wc,
                                                      const float* __restrict__ bc, int P, int row_len,
                                                      int n_classes, SlotTable slots, int max_slots,
                                                      const int32_t* list, const int32_t* count,
                                                      int chunk_base, float* theta) {
-  const int b = blockIdx.x / max_slots, j = blockIdx.x % max_slots;
+  const int b = blockIdx.x;
   if (chunk_base + b >= *count) return;
   const int si = list[4 * (chunk_base + b) + 1];
-  if (j >= slots.n_slots[si]) return;
-  const int cls = slots.cls[si][j];
+  const int ns = slots.n_slots[si];
   __shared__ float sg[4096];
   const float* gb = g + (int64_t)b * g_stride;
   for (int i = threadIdx.x; i < G; i += blockDim.x) sg[i] = gb[i];
@@ -76,8 +121,10 @@ __global__ __launch_bounds__(256) void k_controller(const float* __restrict__ g,
     for (int i = lane; i < G; i += 64) s = fmaf(w[i], sg[i], s);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0)
-      theta[((int64_t)b * max_slots + j) * P + p] = s + w[G + cls] + w[G + n_classes + si] + bc[p];
+    if (lane < ns) {
+      const int cls = slots.cls[si][lane];
+      theta[((int64_t)b * max_slots + lane) * P + p] = s + w[G + cls] + w[G + n_classes + si] + bc[p];
+    }
   }
 }
 
@@ -87,7 +134,7 @@ hipError_t launch_controller(const float* g, int batch, int G, const float* wc, 
                              int chunk_base, float* theta, hipStream_t st) {
   if (G > 4096) return hipErrorInvalidValue;
   const int g_stride = pad_ch(G);
-  hipLaunchKernelGGL(k_controller, dim3(batch * max_slots), dim3(256), 0, st, g, g_stride, G, wc,
+  hipLaunchKernelGGL(k_controller, dim3(batch), dim3(256), 0, st, g, g_stride, G, wc,
                      bc, P, G + n_classes + n_scales, n_classes, slots, max_slots, list, count,
                      chunk_base, theta);
   return hipGetLastError();
@@ -119,24 +166,40 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
     if (threadIdx.x < 8) swp[8 * c0 + threadIdx.x] = bp[threadIdx.x];
   }
   __syncthreads();
+  // D_0 of this pixel in 16-byte vectors (channels padded to 32, so whole
+  // vectors stay inside the pixel's row)
   const T* px = d0 + ((int64_t)b * T2 + pix) * c0_p;
+  constexpr int V = 16 / sizeof(T);
   float F[8];
   if (pre) {
 #pragma unroll
     for (int o = 0; o < 8; ++o) F[o] = swp[8 * c0 + o];
-    for (int c = 0; c < c0; ++c) {
-      float v = ld1(px + c);
-      if constexpr (std::is_same<T, uint8_t>::value) v *= dscale[c];
+    for (int c0v = 0; c0v < c0; c0v += V) {
+      float v[V];
+      decode16<T>(*reinterpret_cast<const uint4*>(px + c0v), v);
 #pragma unroll
-      for (int o = 0; o < 8; ++o) F[o] = fmaf(swp[o * c0 + c], v, F[o]);
+      for (int k = 0; k < V; ++k) {
+        const int c = c0v + k;
+        if (c < c0) {
+          float x = v[k];
+          if constexpr (std::is_same<T, uint8_t>::value) x *= dscale[c];
+#pragma unroll
+          for (int o = 0; o < 8; ++o) F[o] = fmaf(swp[o * c0 + c], x, F[o]);
+        }
+      }
     }
 #pragma unroll
     for (int o = 0; o < 8; ++o) F[o] = fmaxf(F[o], 0.f);
   } else {
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      F[o] = ld1(px + o);
-      if constexpr (std::is_same<T, uint8_t>::value) F[o] *= dscale[o];
+    for (int o0 = 0; o0 < 8; o0 += V) {
+      float v[V];
+      decode16<T>(*reinterpret_cast<const uint4*>(px + o0), v);
+#pragma unroll
+      for (int k = 0; k < V && o0 + k < 8; ++k) {
+        F[o0 + k] = v[k];
+        if constexpr (std::is_same<T, uint8_t>::value) F[o0 + k] *= dscale[o0 + k];
+      }
     }
   }
   for (int j = 0; j < ns; ++j) {
