@@ -474,7 +474,7 @@ int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable);
  * precision p (OMNISEG_FP32, OMNISEG_BF16, OMNISEG_FP8) the configuration
  * runs at.
  * Configurations 0..OMNISEG_CONV_CONFIGS-1 exist; ERR_ARG for any other id. */
-#define OMNISEG_CONV_CONFIGS 10
+#define OMNISEG_CONV_CONFIGS 11
 int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* bn, int32_t* wm,
                             int32_t* wn, int32_t* precisions);
 /*

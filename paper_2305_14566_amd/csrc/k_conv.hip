@@ -45,7 +45,7 @@ template <>
 struct ConvTraits<float> {
   static constexpr int KC = 16;   // channels per LDS chunk
   static constexpr int VEC = 4;   // elements per 16-byte vector
-  static constexpr int ROW = 20;  // LDS row length (80 bytes: conflict-free 16-byte reads)
+  static constexpr int ROW = 20;  // LDS row length (80 bytes)
 };
 template <>
 struct ConvTraits<uint16_t> {
@@ -166,15 +166,29 @@ __device__ __forceinline__ void store_scalar(uint16_t* p, float v) { *p = f2bf(v
 // Global -> register -> LDS staging of one input-channel chunk.  Each thread
 // owns HPT halo vectors (LPV raw loads each; HALO_V in total) and WPT weight
 // vectors (W_V in total); fetch issues the loads, commit writes LDS.
-template <typename T, int LOADER, int HALO_V, int W_V, int LPV, int NV, int VEC, int KC, int ROW, int PX, int BN>
+// LDS slot of 16-byte vector v of row p.  SWZ: rows of exactly NV = 4
+// vectors (64 bytes, no padding) with the vectors of row p rotated by
+// (p >> 1) & 3.  With gfx950's ds_read_b128 lane grouping (16 lanes per
+// cycle over 64 four-byte banks; a cycle takes lanes 0-31 or 32-63 and the
+// quads (lane / 4) of equal bit-0..2 parity) that makes the MFMA operand
+// reads -- 16 consecutive rows, vector g = lane / 16 -- conflict-free for
+// every starting row, where an 80-byte pitch costs 4 extra cycles each.
+template <bool SWZ>
+__device__ __forceinline__ int vslot(int p, int v) {
+  return SWZ ? ((v + (p >> 1)) & 3) : v;
+}
+
+template <typename T, int LOADER, int HALO_V, int W_V, int LPV, int NV, int VEC, int KC, int ROW, int PX, int BN,
+          bool SWZ = false, int NT = 256>
 struct Stager {
-  static constexpr int HPT = (HALO_V + 255) / 256;
-  static constexpr int WPT = (W_V + 255) / 256;
+  static_assert(!SWZ || (NV == 4 && ROW == NV * VEC), "swizzled rows hold exactly four vectors");
+  static constexpr int HPT = (HALO_V + NT - 1) / NT;
+  static constexpr int WPT = (W_V + NT - 1) / NT;
   __device__ __forceinline__ static void fetch(const ConvArgs& a, int b, int tid, int y0, int x0, int n0, int ch,
                                                uint4 (&hreg)[HPT][LPV], uint4 (&wreg)[WPT]) {
 #pragma unroll
     for (int i = 0; i < HPT; ++i) {
-      const int idx = tid + i * 256;
+      const int idx = tid + i * NT;
 #pragma unroll
       for (int j = 0; j < LPV; ++j) hreg[i][j] = make_uint4(0, 0, 0, 0);
       if (idx < HALO_V) {
@@ -187,7 +201,7 @@ struct Stager {
     const T* wsrc = (const T*)a.w + (int64_t)ch * 9 * a.cout_p * KC;
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
-      const int idx = tid + i * 256;
+      const int idx = tid + i * NT;
       wreg[i] = make_uint4(0, 0, 0, 0);
       if (idx < W_V) {
         const int v = idx % NV, r = idx / NV;
@@ -200,22 +214,22 @@ struct Stager {
                                                 T* sX, T* sW) {
 #pragma unroll
     for (int i = 0; i < HPT; ++i) {
-      const int idx = tid + i * 256;
+      const int idx = tid + i * NT;
       if (idx < HALO_V) {
         const int p = idx / NV, v = idx % NV;
         uint4 val = hreg[i][0];
         if (LPV == 4)
           val = vmax(vmax(hreg[i][0], hreg[i][LPV > 1 ? 1 : 0], T()),
                      vmax(hreg[i][LPV > 2 ? 2 : 0], hreg[i][LPV > 3 ? 3 : 0], T()), T());
-        *reinterpret_cast<uint4*>(&sX[p * ROW + v * VEC]) = val;
+        *reinterpret_cast<uint4*>(&sX[p * ROW + vslot<SWZ>(p, v) * VEC]) = val;
       }
     }
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
-      const int idx = tid + i * 256;
+      const int idx = tid + i * NT;
       if (idx < W_V) {
         const int v = idx % NV, r = idx / NV;
-        *reinterpret_cast<uint4*>(&sW[r * ROW + v * VEC]) = wreg[i];
+        *reinterpret_cast<uint4*>(&sW[r * ROW + vslot<SWZ>(r, v) * VEC]) = wreg[i];
       }
     }
   }
@@ -349,17 +363,21 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
 // Two waves per SIMD where the registers allow it without spilling; the
 // 128-channel block and the pooled loads of the larger blocks (four raw
-// vectors staged per halo vector) take one.
-__global__ __launch_bounds__(256, ((BN >= 128 || (LOADER == LOAD_POOL && BY * BN > 512)) ? 1 : 2))
+// vectors staged per halo vector) take one; eight-wave blocks aim at four
+// waves per SIMD.
+__global__ __launch_bounds__(64 * WM * WN,
+                             (WM * WN == 8 ? 4 : ((BN >= 128 || (LOADER == LOAD_POOL && BY * BN > 512)) ? 1 : 2)))
 void k_conv3x3_rows(ConvArgs a) {
   using T = uint16_t;
   using TR = ConvTraits<T>;
-  constexpr int KC = TR::KC, VEC = TR::VEC, ROW = TR::ROW;
+  constexpr int KC = TR::KC, VEC = TR::VEC;
   constexpr int NV = KC / VEC;
+  constexpr int ROW = KC;  // 64-byte rows, vectors rotated per row (vslot<true>)
   constexpr int BX = 16, PX = BX + 2, NPIX = (BY + 2) * PX;
   constexpr int FM = BY / WM;
   constexpr int NW = BN / WN, FN = NW / 16;
-  static_assert(WM * WN == 4 && BY % WM == 0 && NW % 16 == 0, "wave layout");
+  constexpr int NT = 64 * WM * WN;  // four or eight waves
+  static_assert((WM * WN == 4 || WM * WN == 8) && BY % WM == 0 && NW % 16 == 0, "wave layout");
   constexpr int MAIN_B = (NPIX + 9 * BN) * ROW * (int)sizeof(T);
   constexpr int OROW = BN + 4;  // FP32 values per pixel in the epilogue staging
   constexpr int EPI_B = BY * BX * OROW * 4;
@@ -379,10 +397,10 @@ void k_conv3x3_rows(ConvArgs a) {
   const int y0 = syb * BY, x0 = sxb * BX, n0 = nb * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int kg = (lane >> 4) * VEC;
+  const int g = lane >> 4;  // K vector of this lane
   const int l16 = lane & 15;
-  const int xoff = (wm * FM * PX + l16) * ROW + kg;  // halo row wm*FM, column l16 (dx = 0)
-  const int woff = (wn * NW + l16) * ROW + kg;
+  const int xrow = wm * FM * PX + l16;  // halo pixel of row wm*FM, column l16 (dx = 0)
+  const int wrow = wn * NW + l16;
 
   f32x4 acc[FM][FN];
 #pragma unroll
@@ -391,12 +409,12 @@ void k_conv3x3_rows(ConvArgs a) {
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   constexpr int HALO_V = NPIX * NV, W_V = 9 * BN * NV;
-  constexpr int HPT = (HALO_V + 255) / 256, WPT = (W_V + 255) / 256;
+  constexpr int HPT = (HALO_V + NT - 1) / NT, WPT = (W_V + NT - 1) / NT;
   constexpr int LPV = (LOADER == LOAD_POOL) ? 4 : 1;
   uint4 hreg[HPT][LPV];
   uint4 wreg[WPT];
   const int nchunks = a.cin_p / KC;
-  using ST = Stager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN>;
+  using ST = Stager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN, true, NT>;
   ST::fetch(a, b, tid, y0, x0, n0, 0, hreg, wreg);
   ST::commit(tid, hreg, wreg, sX, sW);
   __syncthreads();
@@ -406,14 +424,19 @@ void k_conv3x3_rows(ConvArgs a) {
     for (int dx = 0; dx < 3; ++dx) {
       uint4 xv[FM + 2];
 #pragma unroll
-      for (int r = 0; r < FM + 2; ++r) xv[r] = *reinterpret_cast<const uint4*>(&sX[xoff + (r * PX + dx) * ROW]);
+      for (int r = 0; r < FM + 2; ++r) {
+        const int px = xrow + r * PX + dx;
+        xv[r] = *reinterpret_cast<const uint4*>(&sX[px * ROW + vslot<true>(px, g) * VEC]);
+      }
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
         const int tap = dy * 3 + dx;
         uint4 wv[FN];
 #pragma unroll
-        for (int fn = 0; fn < FN; ++fn)
-          wv[fn] = *reinterpret_cast<const uint4*>(&sW[tap * BN * ROW + woff + fn * 16 * ROW]);
+        for (int fn = 0; fn < FN; ++fn) {
+          const int wr = tap * BN + wrow + fn * 16;
+          wv[fn] = *reinterpret_cast<const uint4*>(&sW[wr * ROW + vslot<true>(wr, g) * VEC]);
+        }
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
@@ -441,7 +464,7 @@ void k_conv3x3_rows(ConvArgs a) {
   constexpr int NVO = BN / 8;
   T* out = (T*)a.y;
   const T* res = (const T*)a.x0;
-  for (int i = tid; i < BY * BX * NVO; i += 256) {
+  for (int i = tid; i < BY * BX * NVO; i += NT) {
     const int p = i / NVO, c = (i % NVO) * 8;
     const int y = y0 + p / BX, x = x0 + p % BX, n = n0 + c;
     const int64_t o = (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + n;
@@ -494,7 +517,7 @@ void k_conv3x3_rows(ConvArgs a) {
     __syncthreads();
     T* pout = (T*)a.pool_out;
     const int Hh = a.H >> 1, Wh = a.W >> 1;
-    for (int i = tid; i < (BY / 2) * (BX / 2) * NVO; i += 256) {
+    for (int i = tid; i < (BY / 2) * (BX / 2) * NVO; i += NT) {
       const int q = i / NVO, c = (i % NVO) * 8;
       const int py = q / (BX / 2), px = q % (BX / 2);
       const int p00 = (2 * py) * BX + 2 * px;
@@ -558,6 +581,7 @@ void k_conv3x3_fp8(ConvArgs a) {
   constexpr int RPW = BY / WM;       // pixel rows per wave
   constexpr int FM = RPW / 2;        // two-row pixel fragments per wave
   constexpr int NW = BN / WN, FN = NW / 32;
+  constexpr int NT = 256;
   static_assert(WM * WN == 4 && BY % WM == 0 && RPW % 2 == 0 && NW % 32 == 0, "wave layout");
   constexpr int MAIN_B = (NPIX + 9 * BN) * ROW;
   constexpr int OROW = BN + 4;
@@ -593,7 +617,7 @@ void k_conv3x3_fp8(ConvArgs a) {
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
   constexpr int HALO_V = NPIX * NV, W_V = 9 * BN * NV;
-  constexpr int HPT = (HALO_V + 255) / 256, WPT = (W_V + 255) / 256;
+  constexpr int HPT = (HALO_V + NT - 1) / NT, WPT = (W_V + NT - 1) / NT;
   constexpr int LPV = (LOADER == LOAD_POOL) ? 4 : 1;
   uint4 hreg[HPT][LPV];
   uint4 wreg[WPT];
@@ -656,7 +680,7 @@ void k_conv3x3_fp8(ConvArgs a) {
   constexpr int NVO = BN / 16;
   T* out = (T*)a.y;
   const T* res = (const T*)a.x0;
-  for (int i = tid; i < BY * BX * NVO; i += 256) {
+  for (int i = tid; i < BY * BX * NVO; i += NT) {
     const int p = i / NVO, c = (i % NVO) * 16;
     const int y = y0 + p / BX, x = x0 + p % BX, n = n0 + c;
     const int64_t o = (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + n;
@@ -697,7 +721,7 @@ void k_conv3x3_fp8(ConvArgs a) {
     __syncthreads();
     T* pout = (T*)a.pool_out;
     const int Hh = a.H >> 1, Wh = a.W >> 1;
-    for (int i = tid; i < (BY / 2) * (BX / 2) * NVO; i += 256) {
+    for (int i = tid; i < (BY / 2) * (BX / 2) * NVO; i += NT) {
       const int q = i / NVO, c = (i % NVO) * 16;
       const int py = q / (BX / 2), px = q % (BX / 2);
       const int p00 = (2 * py) * BX + 2 * px;
@@ -773,7 +797,8 @@ static hipError_t launch_conv_rows_t(const ConvLayer& L, int H, int W, int batch
   a.pool_out = L.pool_out;
   if (L.pool_out && EPI != EPI_RES_RELU) return hipErrorInvalidValue;
   const int64_t blocks = (int64_t)batch * a.tiles_y * a.tiles_x * a.n_nblk;
-  hipLaunchKernelGGL((k_conv3x3_rows<BY, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_conv3x3_rows<BY, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks), dim3(64 * WM * WN), 0, st,
+                     a);
   return hipGetLastError();
 }
 
@@ -821,10 +846,12 @@ static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, con
   X(CONV_CFG_ROWS_16x16_128, 16, 16, 128, 2, 2) \
   X(CONV_CFG_ROWS_32x16_32, 32, 16, 32, 4, 1)   \
   X(CONV_CFG_ROWS_16x16_32, 16, 16, 32, 4, 1)
+// Eight-wave row-reuse configuration (BF16 only)
+#define OMNISEG_CONV_ROW8_CONFIGS(X) X(CONV_CFG_ROWS8_16x16_64, 16, 16, 64, 4, 2)
 
 static const int kCfgShape[][5] = {
 #define OMNISEG_SHAPE(id, by, bx, bn, wm, wn) {by, bx, bn, wm, wn},
-    OMNISEG_CONV_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW_CONFIGS(OMNISEG_SHAPE)
+    OMNISEG_CONV_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW8_CONFIGS(OMNISEG_SHAPE)
 #undef OMNISEG_SHAPE
 };
 static_assert(sizeof(kCfgShape) / sizeof(kCfgShape[0]) == CONV_CFG_COUNT, "one shape per configuration");
@@ -839,6 +866,7 @@ void conv_config_shape(int cfg, int* by, int* bx, int* bn, int* wm, int* wn) {
 
 int conv_config_precisions(int cfg) {
   if (cfg < 0 || cfg >= CONV_CFG_COUNT) return 0;
+  if (cfg >= CONV_CFG_ROWS8_16x16_64) return 1 << OMNISEG_BF16;
   return cfg >= CONV_CFG_ROWS_16x16_64 ? (1 << OMNISEG_BF16) | (1 << OMNISEG_FP8)
                                        : (1 << OMNISEG_FP32) | (1 << OMNISEG_BF16);
 }
@@ -885,6 +913,7 @@ static hipError_t launch_conv_cfg(int cfg, const ConvLayer& L, int H, int W, int
   case id:                                   \
     return launch_conv_rows_t<by, bn, wm, wn, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
       OMNISEG_CONV_ROW_CONFIGS(OMNISEG_CASE)
+      OMNISEG_CONV_ROW8_CONFIGS(OMNISEG_CASE)
 #undef OMNISEG_CASE
       default:
         break;

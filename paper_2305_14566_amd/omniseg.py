@@ -23,7 +23,7 @@ FLAG_GRAPH = 4
 ABI_VERSION = 4
 
 CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
-N_CONV_CONFIGS = 10
+N_CONV_CONFIGS = 11
 
 _lib = None
 

@@ -296,9 +296,8 @@ def test_every_fp8_tile_configuration(config, mode):
 
 # ------------------------------------------------------------------ fused 2x2 max-pool output
 
-@pytest.mark.parametrize("config", [c for c in range(om.N_CONV_CONFIGS) if om.BF16 in om.conv_config_info(c)[5]
-                                    and c >= 6])
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec,config", [(p, c) for c in range(6, om.N_CONV_CONFIGS) for p in ("bf16", "fp8")
+                                         if (om.BF16 if p == "bf16" else om.FP8) in om.conv_config_info(c)[5]])
 def test_fused_pool_output(prec, config):
     """The residual conv's pooled copy (the encoder's next input, written by
     the same kernel) equals the 2x2 max of its stored output bit for bit, and
