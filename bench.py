@@ -34,6 +34,10 @@ HBM_PEAK_GBS = 8000.0
 
 CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 1, 2, 3), tile=256, stride=128,
            fg_filter=True)
+# The tiling of the paper's experiments (Section 3.2): 512^2 tiles at 40x with
+# stride 256 and vote threshold 1, at 10x and 5x with stride 64 and threshold 4.
+PAPER_CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 2, 3), tile=512, stride=256,
+                 fg_filter=True, scale_strides=(256, 64, 64), vote_thresholds=(1, 4, 4))
 
 # HBM bytes per launch of the dominant BF16 conv kernel on this workload, from
 # two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
@@ -128,21 +132,23 @@ def stage_summary(records):
     return out
 
 
-def _plan(om, prec, batch_tiles):
-    return om.Plan(base=CFG["base"], levels=CFG["levels"], head_out=CFG["head_out"],
-                   n_classes=CFG["n_classes"], scales=CFG["scales"], tile=CFG["tile"],
-                   stride=CFG["stride"], fg_filter=CFG["fg_filter"],
+def _plan(om, prec, batch_tiles, cfg=CFG):
+    vote = "vote_thresholds" in cfg
+    return om.Plan(base=cfg["base"], levels=cfg["levels"], head_out=cfg["head_out"],
+                   n_classes=cfg["n_classes"], scales=cfg["scales"], tile=cfg["tile"],
+                   stride=cfg["stride"], fg_filter=cfg["fg_filter"],
                    precision={"bf16": om.BF16, "fp32": om.FP32, "fp8": om.FP8}[prec], emit_logits=False,
-                   batch_tiles=batch_tiles)
+                   batch_tiles=batch_tiles, scale_strides=cfg.get("scale_strides"),
+                   merge=om.MERGE_VOTE if vote else om.MERGE_RAMP, vote_thresholds=cfg.get("vote_thresholds"))
 
 
-def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles, calib_tiles=64):
-    plan = _plan(om, prec, batch_tiles)
+def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles, calib_tiles=64, cfg=CFG):
+    plan = _plan(om, prec, batch_tiles, cfg)
     ws = torch.empty(plan.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
     extra = {}
     if prec == "fp8":
         # per-channel activation scales from the FP32 path on the first kept tiles
-        p32 = _plan(om, "fp32", batch_tiles)
+        p32 = _plan(om, "fp32", batch_tiles, cfg)
         ws32 = torch.empty(p32.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
         t_cal = time.perf_counter()
         amax = p32.calibrate_fp8([dslide], pairs, p32.pack(flat_dev), ws32, n_tiles=calib_tiles)
@@ -182,6 +188,33 @@ def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles
     tuned = sorted({(r["stage"], r["level"], r["config"]) for r in records if r["config"] >= 0})
     return dict(ms=ms, wall_ms=wall * 1e3 / steps, records=records, kept=kept, masks=masks,
                 tuned={f"{st}{l}": list(om.conv_config(c)) for st, l, c in tuned}, tune_s=t_tune, **extra)
+
+
+def paper_leg(om, torch, M, dslide, size, steps, batch_tiles):
+    """The paper's tiling on the same slide: 512^2 tiles, 40x/10x/5x with
+    strides 256/64/64, majority-vote merge with thresholds 1/4/4, 6 classes;
+    BF16 throughput, and its masks against one FP32 step of the same plan."""
+    import synth
+
+    C = PAPER_CFG["n_classes"]
+    flat = synth.he_normal_weights(12, PAPER_CFG["base"], PAPER_CFG["levels"], C, len(PAPER_CFG["scales"]),
+                                   PAPER_CFG["head_out"])
+    flat_dev = torch.from_numpy(flat).to(dslide.device)
+    pairs = [(c, si) for si in range(len(PAPER_CFG["scales"])) for c in range(C)]
+    bf = run_leg(om, torch, dslide, flat_dev, pairs, "bf16", steps, 1, batch_tiles, cfg=PAPER_CFG)
+    fp = run_leg(om, torch, dslide, flat_dev, pairs, "fp32", 1, 0, batch_tiles, cfg=PAPER_CFG)
+    px = size * size * len(pairs)
+    dices = [M.dice(a, b) for a, b in zip(bf["masks"], fp["masks"])]
+    stages = stage_summary([dict(r, ms=r["ms"] / steps, flops=r["flops"] / steps, bytes=r["bytes"] / steps)
+                            for r in bf["records"]])
+    return {"value": px / (bf["ms"] * 1e-3) / 1e6, "unit": UNIT, "ms_per_step": bf["ms"], "steps": steps,
+            "dtype": "bf16", "kept_tiles": bf["kept"], "pairs": len(pairs),
+            "workload": f"the {size}x{size} slide, 512 tiles, scales 40x/10x/5x at strides 256/64/64, "
+                        "majority vote with thresholds 1/4/4, 6 classes",
+            "fp32_ms_per_step": fp["ms"], "speedup_bf16_vs_fp32": fp["ms"] / bf["ms"],
+            "bf16_vs_fp32_vote_masks": {"dice_min": min(dices), "dice_mean": float(np.mean(dices))},
+            "stitch_ms": stages.get("stitch", {}).get("ms"),
+            "roofline": dict(roofline(om, bf["records"], "bf16"), traffic=None)}
 
 
 def train_leg(om, torch, steps, warmup, batch=32):
@@ -233,6 +266,71 @@ def train_leg(om, torch, steps, warmup, batch=32):
             "loss_first_last": [float(losses[0]), float(losses[-1])],
             "workload": "2048x2048 synthetic region, 32 random 256^2 tiles of 40x/20x per step, 6 classes x "
                         "2 scales, base-64 5-level U-Net, BCE vs soft masks, backward + SGD update"}
+
+
+def trained_dice_leg(om, torch, M, steps, lr=3e-4):
+    """Masks from trained weights: the training-step network (2048^2 region,
+    6 classes x 2 scales) trained in FP32 with the library's forward and
+    hand-written backward for `steps` Adam steps of 32 tiles, then the whole
+    region segmented at FP32, BF16 and FP8 and their masks and logits
+    compared.  The classes cover 0.2-1 % of the pixels, so the training loss
+    weights positive pixels by (1 - p) / p (p: the batch's positive share),
+    computed by torch on the stitched logits; plain BCE would learn empty
+    masks."""
+    import synth
+
+    dev = torch.device("cuda:0")
+    rgb, gt = synth.strip_slide(3, 2048, 2048, fg_frac=0.30)
+    base, L, C, scales = 64, 5, 6, (0, 1)
+    flat = synth.he_normal_weights(13, base, L, C, len(scales), 2)
+    pairs = [(c, si) for si in range(len(scales)) for c in range(C)]
+    mk = lambda prec, **kw: om.Plan(base=base, levels=L, head_out=2, n_classes=C, scales=scales, tile=256, stride=128,
+                                    precision=prec, **kw)
+    plan = mk(om.FP32, training=True)
+    slide = torch.from_numpy(rgb).to(dev)
+    y = torch.from_numpy(synth.soft_targets(gt, scales, pairs)).to(dev)
+    w = torch.from_numpy(flat).to(dev).requires_grad_(True)
+    opt = torch.optim.Adam([w], lr=lr)
+    grid = [(si, jy, jx) for si, k in enumerate(scales)
+            for jy in range(-(-(-(-2048 // (1 << k)) - 256) // 128) + 1)
+            for jx in range(-(-(-(-2048 // (1 << k)) - 256) // 128) + 1)]
+    rng = np.random.default_rng(14)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tiles = [grid[i] for i in sorted(rng.choice(len(grid), size=32, replace=False))]
+        opt.zero_grad()
+        logit, covered = om.OmniSegFn.apply(w, plan, slide, tiles, pairs)
+        v = covered.bool()
+        pos = (y * v).sum() / v.sum()
+        pw = ((1 - pos) / pos.clamp(min=1e-4)).detach()
+        torch.nn.functional.binary_cross_entropy_with_logits(logit[v], y[v], pos_weight=pw).backward()
+        opt.step()
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    wt = w.detach().contiguous()
+    out = {}
+    for name, prec in (("fp32", om.FP32), ("bf16", om.BF16), ("fp8", om.FP8)):
+        p = mk(prec, emit_logits=True)
+        if prec == om.FP8:
+            p32 = mk(om.FP32)
+            ws = torch.empty(p32.workspace_bytes([slide], pairs), dtype=torch.uint8, device=dev)
+            packed = p.pack_fp8(wt, p32.calibrate_fp8([slide], pairs, p32.pack(wt), ws, n_tiles=64))
+        else:
+            packed = p.pack(wt)
+        masks, logits, _ = p.segment([slide], pairs, packed)
+        out[name] = ([m.cpu().numpy().astype(bool) for m in masks[0]],
+                     [lg.cpu().numpy().astype(np.float64) for lg in logits[0]])
+    res = {"steps": steps, "train_s": train_s, "lr": lr,
+           "fp32_positive_fraction_mean": float(np.mean([m.mean() for m in out["fp32"][0]])),
+           "fp32_abs_logit_below_1": float(np.mean([np.mean(np.abs(lg) < 1) for lg in out["fp32"][1]]))}
+    for name in ("bf16", "fp8"):
+        d = [M.dice(a, b) for a, b in zip(out[name][0], out["fp32"][0])]
+        e = [M.normwise_error(a, b) for a, b in zip(out[name][1], out["fp32"][1])]
+        res[f"{name}_vs_fp32"] = {"dice_min": min(d), "dice_mean": float(np.mean(d)),
+                                  "disagreement_max": max(M.disagreement(a, b) for a, b in
+                                                          zip(out[name][0], out["fp32"][0])),
+                                  "logit_error_max": max(e)}
+    return res
 
 
 def _gen_batch_slide(spec):
@@ -358,6 +456,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--train-steps", type=int, default=3, help="training-step leg (0 = skip)")
     ap.add_argument("--fp8-steps", type=int, default=3, help="FP8 backbone leg (0 = skip)")
+    ap.add_argument("--paper-steps", type=int, default=2,
+                    help="leg with the paper's tiling (512 tiles, 40x/10x/5x, strides 256/64/64, "
+                         "majority vote 1/4/4), BF16 and one FP32 step for the masks (0 = skip)")
+    ap.add_argument("--trained-dice-steps", type=int, default=0,
+                    help="train the training-step network this many FP32 steps and compare BF16/FP8 masks "
+                         "with FP32 on it (0 = skip)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device to device (a plain copy of known size for "
                          "scaling profiler byte counters)")
@@ -454,6 +558,12 @@ def main():
                                        "disagreement_max": max(M.disagreement(a, b)
                                                                for a, b in zip(f8["masks"], fp["masks"]))}
         result["fp8"] = r8
+    if args.paper_steps > 0:
+        result["paper_tiling"] = paper_leg(om, torch, M, dslide, args.size, args.paper_steps, args.batch_tiles)
+        print(f"# paper tiling: {result['paper_tiling']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    if args.trained_dice_steps > 0:
+        result["trained_weights_masks"] = trained_dice_leg(om, torch, M, args.trained_dice_steps)
+        print(f"# trained-weights masks: {result['trained_weights_masks']}", file=sys.stderr, flush=True)
     if args.train_steps > 0:
         result["train_step"] = train_leg(om, torch, args.train_steps, 1)
         print(f"# train: {result['train_step']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)

@@ -12,8 +12,10 @@
  *      (the dynamic multi-class multi-scale network the paper applies,
  *      Section 2.2);
  *   4. merge the overlapping tile logits of each class into a whole-slide
- *      mask by a ramp-weighted average and a threshold (Section 2.2 overlap
- *      tiling; Section 2.3 slide-wise aggregation; constants in Section 3.2).
+ *      mask, by the majority vote of overlapping tile predictions (Section
+ *      2.2 overlap tiling; thresholds and strides in Section 3.2) or by a
+ *      ramp-weighted average and a threshold (Section 2.3 slide-wise
+ *      aggregation).
  *
  * Conventions shared by every entry point:
  *   - Every function returns an int32_t status (OMNISEG_OK = 0 or one of the
@@ -38,7 +40,7 @@
 extern "C" {
 #endif
 
-#define OMNISEG_ABI_VERSION 4
+#define OMNISEG_ABI_VERSION 5
 
 /* status codes */
 #define OMNISEG_OK 0
@@ -61,6 +63,11 @@ extern "C" {
                                       in a HIP graph, replayed on calls with identical arguments;
                                       needs a created (non-null) stream */
 
+/* merge of overlapping tile predictions (omniseg_config.merge) */
+#define OMNISEG_MERGE_RAMP 0 /* ramp-weighted mean of the tile logits, mask = mean > 0 */
+#define OMNISEG_MERGE_VOTE 1 /* majority vote: mask = (number of covering tiles whose
+                                logit is > 0) >= vote_threshold of the pair's scale */
+
 /* limits */
 #define OMNISEG_MAX_SCALES 4
 #define OMNISEG_MAX_CLASSES 16
@@ -81,11 +88,22 @@ typedef struct omniseg_hip_stream_opaque* omniseg_stream; /* a hipStream_t */
  *                  2 = 10x, 3 = 5x); values in [0, 3].
  *   tile, stride   square tile size T (a multiple of 16, <= 512) and the
  *                  overlap stride s (1 <= s <= T).
+ *   scale_stride   per scale slot: the tile stride of that slot's grid in
+ *                  [1, T], or 0 for `stride` (Section 3.2 tiles 40x with
+ *                  stride 256 and 10x, 5x with stride 64).  Training plans
+ *                  need every slot at `stride`.
+ *   merge          OMNISEG_MERGE_RAMP or OMNISEG_MERGE_VOTE (Section 2.2
+ *                  majority vote; training plans need RAMP).
+ *   vote_threshold per scale slot, with MERGE_VOTE: the least number of
+ *                  covering kept tiles that must predict the class, in
+ *                  [1, ceil(T / s_slot)^2] (Section 3.2: 1 at 40x, 4 at
+ *                  10x and 5x); ignored with MERGE_RAMP.
  *   fg_filter      1: keep only tiles whose footprint touches a foreground
  *                  pixel of the tissue map; 0: keep every tile.
  *   fg_threshold   gray threshold of the tissue map (pixels darker than this
  *                  on the coarsest scale are tissue), in [1, 255].
  *   mask_and_fg    1: the output mask is also ANDed with the tissue map.
+ *   scale_log2 must not repeat a value across the n_scales slots.
  *   precision      OMNISEG_FP32, OMNISEG_BF16 or OMNISEG_FP8 (not with
  *                  OMNISEG_FLAG_TRAINING).
  *   flags          OR of OMNISEG_FLAG_*.
@@ -113,6 +131,9 @@ typedef struct omniseg_config {
   int32_t flags;
   int32_t batch_tiles;
   int32_t max_kept_tiles;
+  int32_t scale_stride[OMNISEG_MAX_SCALES];
+  int32_t merge;
+  int32_t vote_threshold[OMNISEG_MAX_SCALES];
 } omniseg_config;
 
 /* One slide: uint8 RGB, interleaved (HWC), rows `row_pitch` bytes apart
@@ -134,7 +155,9 @@ typedef struct omniseg_pair {
  * H_k = ceil(height / 2^k) rows, W_k = ceil(width / 2^k) columns.
  * mask: device uint8, 1 = the class is present; rows mask_pitch bytes apart.
  * logit: device float or NULL; written only with OMNISEG_FLAG_EMIT_LOGITS;
- * rows logit_pitch floats apart; 0 where no kept tile covers the pixel. */
+ * rows logit_pitch floats apart; 0 where no kept tile covers the pixel.
+ * With OMNISEG_MERGE_VOTE the logit plane holds the vote count instead (the
+ * number of covering kept tiles whose logit is > 0, as a float). */
 typedef struct omniseg_output {
   uint8_t* mask;
   float* logit;
@@ -239,7 +262,9 @@ int32_t omniseg_pack_weights_fp8(const omniseg_plan* plan, const float* canonica
 /*
  * Workspace bytes that omniseg_segment_slide needs for these slides and
  * pairs (host arrays).  The bound assumes every tile passes the tissue
- * filter.
+ * filter.  A tile grid (one slide at one scale) of more than 32767 tiles per
+ * side, or more than 2^26 grid tiles over all slides and scales, is
+ * ERR_UNSUPPORTED (here and in every call that takes slides).
  */
 int32_t omniseg_workspace_bytes(const omniseg_plan* plan, const omniseg_slide* slides,
                                 int32_t n_slides, const omniseg_pair* pairs,
@@ -298,11 +323,15 @@ int32_t omniseg_workspace_region(const omniseg_plan* plan, const omniseg_slide* 
  * (0 where D = 0), the mask is N > 0.  N is accumulated in FP32 with
  * compensated (Neumaier) summation over the covering tiles in (jy, jx) order;
  * D is an exact integer.
+ * vote_threshold > 0 selects the majority vote of Section 2.2 instead: the
+ * mask is (number of covering tiles whose logit is > 0) >= vote_threshold,
+ * and the logit plane receives that count.  0 = the weighted mean.
+ * Grids above 2^30 tile positions are ERR_UNSUPPORTED.
  */
 int32_t omniseg_stitch_workspace_bytes(int32_t tile, int32_t stride, int32_t height,
                                        int32_t width, int64_t* bytes);
 int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32_t width,
-                             const float* tile_logits, const int32_t* tile_yx,
+                             int32_t vote_threshold, const float* tile_logits, const int32_t* tile_yx,
                              int32_t n_tiles, uint8_t* mask, int64_t mask_pitch,
                              float* logit, int64_t logit_pitch, void* workspace,
                              int64_t ws_bytes, omniseg_stream stream);

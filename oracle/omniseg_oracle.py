@@ -34,16 +34,31 @@ import numpy as np
 
 
 def make_config(base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
-                stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False):
+                stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False,
+                scale_strides=None, merge="ramp", vote_thresholds=None):
     """Oracle configuration.
 
     scales: log2 downsampling factor of each scale slot (0 = 40x, 1 = 20x,
     2 = 10x, 3 = 5x); the scale one-hot indexes this list.
+    scale_strides: tile stride of each slot's grid (0 or None = stride);
+    Section 3.2 uses 256 at 40x and 64 at 10x and 5x.
+    merge: "ramp" (weighted mean of logits) or "vote" (majority vote of the
+    binary tile predictions, Section 2.2) with vote_thresholds per slot.
     """
+    n = len(scales)
+    ss = tuple(int(v) if v else int(stride) for v in (scale_strides or (0,) * n))
+    vt = tuple(int(v) for v in (vote_thresholds or (0,) * n))
     return dict(base=int(base), levels=int(levels), head_out=int(head_out),
                 n_classes=int(n_classes), scales=tuple(int(s) for s in scales),
                 tile=int(tile), stride=int(stride), fg_filter=bool(fg_filter),
-                fg_threshold=int(fg_threshold), mask_and_fg=bool(mask_and_fg))
+                fg_threshold=int(fg_threshold), mask_and_fg=bool(mask_and_fg),
+                scale_strides=ss, merge=str(merge), vote_thresholds=vt)
+
+
+def stride_of(cfg, si):
+    """Tile stride of scale slot si."""
+    ss = cfg.get("scale_strides")
+    return ss[si] if ss else cfg["stride"]
 
 
 def channels(cfg):
@@ -232,11 +247,12 @@ def tile_list(slides_hw, cfg, fg_maps=None):
 
     Order: slide, scale slot ascending, tile row, tile column.
     """
-    T, s = cfg["tile"], cfg["stride"]
+    T = cfg["tile"]
     kc = max(cfg["scales"])
     out = []
     for n, (H, W) in enumerate(slides_hw):
         for si, k in enumerate(cfg["scales"]):
+            s = stride_of(cfg, si)
             ny = grid_count(level_size(H, k), T, s)
             nx = grid_count(level_size(W, k), T, s)
             for jy in range(ny):
@@ -592,6 +608,28 @@ def stitch(tiles, logits, H_k, W_k, T, s):
     return Lam, N, D
 
 
+# --------------------------------------------------------------------------
+# O10b  majority vote (Section 2.2 overlap testing; thresholds in Section 3.2)
+# --------------------------------------------------------------------------
+
+
+def vote(tiles, logits, H_k, W_k, T, s):
+    """Votes of overlapping binary tile predictions.
+
+    Each kept tile predicts the class at a pixel where its logit is positive
+    (probability above one half).  V(p) counts the covering tiles that
+    predict the class, C(p) counts all covering tiles.  The mask of a slot
+    with threshold v is V >= v.  Returns (V, C) over [0, H_k) x [0, W_k).
+    """
+    ey, ex = grid_extent(H_k, T, s), grid_extent(W_k, T, s)
+    V = np.zeros((ey, ex), dtype=np.int64)
+    C = np.zeros((ey, ex), dtype=np.int64)
+    for (jy, jx), l in zip(tiles, logits):
+        V[jy * s:jy * s + T, jx * s:jx * s + T] += (np.asarray(l) > 0)
+        C[jy * s:jy * s + T, jx * s:jx * s + T] += 1
+    return V[:H_k, :W_k], C[:H_k, :W_k]
+
+
 def fg_at_scale(fg, kc, k, H_k, W_k):
     """Nearest lookup of the coarse map at scale k: fg(y >> (kc-k), x >> (kc-k))."""
     sh = kc - k
@@ -611,7 +649,8 @@ def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False
     slides: list of uint8 HWC arrays; pairs: list of (class, scale slot).
     Returns dict with 'mask'[n][p] (bool H_k x W_k), 'logit'[n][p] (float64),
     'tiles' (the kept tile list), 'pad' per slide, 'fg' per slide, and with
-    keep_tiles the per-tile logits {(n, si, jy, jx): {class: TxT}}.
+    keep_tiles the per-tile logits {(n, si, jy, jx): {class: TxT}}.  With
+    merge "vote" the 'logit' planes hold the vote counts V.
     emulate="bf16" rounds weights and stored activations as a bfloat16
     backbone does (round_bf16); emulate="fp8" stores them as the FP8
     backbone does, with the channel scales `fp8_scales` (from
@@ -626,7 +665,7 @@ def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False
     elif emulate == "fp8":
         act_scales = fp8_scales
         wts = fp8_weights(wts, cfg, act_scales)
-    T, s = cfg["tile"], cfg["stride"]
+    T = cfg["tile"]
     kc = max(cfg["scales"])
     need_fg = cfg["fg_filter"] or cfg["mask_and_fg"]
     fgs = [tissue_map(r, kc, cfg["fg_threshold"]) if need_fg else None for r in slides]
@@ -639,7 +678,7 @@ def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False
         if not classes:
             continue
         k = cfg["scales"][si]
-        x = tile_input(slides[n], k, T, s, jy, jx)
+        x = tile_input(slides[n], k, T, stride_of(cfg, si), jy, jx)
         lg = tile_logits(x, wts, cfg, si, classes, store=store, act_scales=act_scales)
         per_tile[(n, si, jy, jx)] = {c: lg[i] for i, c in enumerate(classes)}
     masks, logits = [], []
@@ -651,8 +690,13 @@ def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False
             Hk, Wk = level_size(H, k), level_size(W, k)
             ts = [(jy, jx) for (m, sj, jy, jx) in tl if m == n and sj == si]
             ls = [per_tile[(n, si, jy, jx)][c] for (jy, jx) in ts]
-            Lam, N, D = stitch(ts, ls, Hk, Wk, T, s)
-            M = (N > 0) & (D > 0)
+            if cfg.get("merge", "ramp") == "vote":
+                V, _ = vote(ts, ls, Hk, Wk, T, stride_of(cfg, si))
+                M = V >= cfg["vote_thresholds"][si]
+                Lam = V.astype(np.float64)
+            else:
+                Lam, N, D = stitch(ts, ls, Hk, Wk, T, stride_of(cfg, si))
+                M = (N > 0) & (D > 0)
             if cfg["mask_and_fg"]:
                 M &= fg_at_scale(fgs[n], kc, k, Hk, Wk)
             mrow.append(M)

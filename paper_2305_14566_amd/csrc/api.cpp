@@ -65,6 +65,9 @@ struct Layout {
   int64_t total = 0;
 };
 
+// Tile stride of scale slot si (scale_stride[si], 0 = the common stride).
+int stride_of(const omniseg_config& c, int si) { return c.scale_stride[si] > 0 ? c.scale_stride[si] : c.stride; }
+
 int32_t validate_config(const omniseg_config* c) {
   if (!c) return fail(OMNISEG_ERR_ARG, "config is NULL");
   if (c->abi_version != OMNISEG_ABI_VERSION)
@@ -84,6 +87,29 @@ int32_t validate_config(const omniseg_config* c) {
     return fail(OMNISEG_ERR_ARG, "tile %d must be a multiple of 16 in [16, 512]", c->tile);
   if (c->stride < 1 || c->stride > c->tile)
     return fail(OMNISEG_ERR_ARG, "stride %d outside [1, tile]", c->stride);
+  for (int i = 0; i < c->n_scales; ++i) {
+    for (int j = 0; j < i; ++j)
+      if (c->scale_log2[j] == c->scale_log2[i])
+        return fail(OMNISEG_ERR_ARG, "scale_log2[%d] repeats scale_log2[%d]", i, j);
+    if (c->scale_stride[i] < 0 || c->scale_stride[i] > c->tile)
+      return fail(OMNISEG_ERR_ARG, "scale_stride[%d] = %d outside [0, tile]", i, c->scale_stride[i]);
+  }
+  if (c->merge != OMNISEG_MERGE_RAMP && c->merge != OMNISEG_MERGE_VOTE)
+    return fail(OMNISEG_ERR_ARG, "unknown merge %d", c->merge);
+  if (c->merge == OMNISEG_MERGE_VOTE)
+    for (int i = 0; i < c->n_scales; ++i) {
+      const int per = ceil_div(c->tile, stride_of(*c, i));
+      if (c->vote_threshold[i] < 1 || c->vote_threshold[i] > per * per)
+        return fail(OMNISEG_ERR_ARG, "vote_threshold[%d] = %d outside [1, %d] (most tiles covering a pixel)", i,
+                    c->vote_threshold[i], per * per);
+    }
+  if (c->flags & OMNISEG_FLAG_TRAINING) {
+    if (c->merge != OMNISEG_MERGE_RAMP)
+      return fail(OMNISEG_ERR_UNSUPPORTED, "training plans merge with the ramp average only");
+    for (int i = 0; i < c->n_scales; ++i)
+      if (stride_of(*c, i) != c->stride)
+        return fail(OMNISEG_ERR_UNSUPPORTED, "training plans use one stride for every scale");
+  }
   const int deep = c->tile >> (c->levels - 1);
   if ((c->tile % (1 << (c->levels - 1))) || deep < 8 || deep % 8)
     return fail(OMNISEG_ERR_UNSUPPORTED, "tile / 2^(levels-1) = %d must be a multiple of 8", deep);
@@ -125,6 +151,20 @@ int32_t validate_call(const omniseg_plan* plan, const omniseg_slide* slides, int
       return fail(OMNISEG_ERR_UNSUPPORTED, "slide %d: side above 2^20", i);
     if (s.row_pitch < 3LL * s.width) return fail(OMNISEG_ERR_ARG, "slide %d: row_pitch %lld < 3*width", i, (long long)s.row_pitch);
   }
+  // tile grids: the group table keeps 16-bit grid sides, the tile list int32 indices
+  int64_t grid_tiles = 0;
+  for (int i = 0; i < n_slides; ++i)
+    for (int si = 0; si < c.n_scales; ++si) {
+      const int k = c.scale_log2[si];
+      const int64_t ny = grid_count(ceil_div(slides[i].height, 1 << k), c.tile, stride_of(c, si));
+      const int64_t nx = grid_count(ceil_div(slides[i].width, 1 << k), c.tile, stride_of(c, si));
+      if (ny > 32767 || nx > 32767)
+        return fail(OMNISEG_ERR_UNSUPPORTED, "slide %d, scale %d: tile grid %lldx%lld above 32767 per side", i, si,
+                    (long long)ny, (long long)nx);
+      grid_tiles += ny * nx;
+    }
+  if (grid_tiles > (1LL << 26))
+    return fail(OMNISEG_ERR_UNSUPPORTED, "%lld grid tiles above 2^26", (long long)grid_tiles);
   bool seen[OMNISEG_MAX_CLASSES][OMNISEG_MAX_SCALES] = {};
   lay.S = c.n_scales;
   for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) lay.slots.n_slots[si] = 0;
@@ -162,7 +202,7 @@ int pool_config(const omniseg_plan* plan, int level, int H, int W, int cout_p) {
 void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32_t n_slides,
                     Layout& lay) {
   const omniseg_config& c = plan->cfg;
-  const int T = c.tile, s = c.stride;
+  const int T = c.tile;
   lay.n_slides = n_slides;
   lay.kmax = 0;
   for (int si = 0; si < c.n_scales; ++si) lay.kmax = std::max(lay.kmax, c.scale_log2[si]);
@@ -180,7 +220,7 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
   for (int i = 0; i < n_slides; ++i) {
     lay.off_pad[i] = take(16);
     for (int si = 0; si < c.n_scales; ++si) {
-      const ScaleGeom g = make_geom(slides[i].height, slides[i].width, c.scale_log2[si], T, s);
+      const ScaleGeom g = make_geom(slides[i].height, slides[i].width, c.scale_log2[si], T, stride_of(c, si));
       lay.geom[i][si] = g;
       lay.sz_pyr[i][si] = g.k >= 1 ? (int64_t)g.Ey * g.Ex * 8 : 0;
       lay.off_pyr[i][si] = g.k >= 1 ? take(lay.sz_pyr[i][si]) : -1;
@@ -188,6 +228,7 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
       lay.groups.base[gi] = tiles;
       lay.groups.ny[gi] = (short)g.ny;
       lay.groups.nx[gi] = (short)g.nx;
+      lay.groups.s[gi] = (short)stride_of(c, si);
       lay.groups.slide[gi] = (char)i;
       lay.groups.slot[gi] = (char)si;
       lay.groups.k[gi] = (char)g.k;
@@ -255,7 +296,7 @@ const float* fp8_scale_of(const omniseg_plan* plan, const char* pk, int kind, in
 int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, int32_t n_slides, const Layout& lay,
                         char* ws, hipStream_t sm, Prof& prof, SlideDev** tab_out, int32_t* n_kept_out) {
   const omniseg_config& c = plan->cfg;
-  const int T = c.tile, s = c.stride;
+  const int T = c.tile;
   plan->slide_tab.assign(n_slides, SlideDev());
   for (int i = 0; i < n_slides; ++i) {
     SlideDev& d = plan->slide_tab[i];
@@ -318,7 +359,7 @@ int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, i
   int32_t* index = reinterpret_cast<int32_t*>(ws + lay.off_index);
   int32_t* list = reinterpret_cast<int32_t*>(ws + lay.off_list);
   int32_t* count = reinterpret_cast<int32_t*>(ws + lay.off_count);
-  HIP_TRY(launch_tile_flags(lay.groups, tab_dev, T, s, lay.kc, c.fg_filter, index, sm));
+  HIP_TRY(launch_tile_flags(lay.groups, tab_dev, T, lay.kc, c.fg_filter, index, sm));
   HIP_TRY(launch_compact(index, lay.total_tiles, lay.groups, list, count, sm));
   HIP_TRY(prof.end(OMNISEG_STAGE_PREP, -1, 0, 0.0, prep_bytes));
   int32_t n_kept = 0;
@@ -637,7 +678,7 @@ int32_t omniseg_calibrate_fp8(const omniseg_plan* plan, const void* packed, cons
   fa.list = list;
   fa.count = count;
   fa.T = T;
-  fa.s = c.stride;
+  for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) fa.scale_s[si] = si < c.n_scales ? stride_of(c, si) : c.stride;
   fa.w = reinterpret_cast<const float*>(pk + plan->pk_first_w);
   fa.b = reinterpret_cast<const float*>(pk + plan->pk_first_b);
   fa.c0 = plan->C[0];
@@ -816,7 +857,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
     fa.list = list;
     fa.count = count;
     fa.T = T;
-    fa.s = s;
+    for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) fa.scale_s[si] = si < c.n_scales ? stride_of(c, si) : s;
     fa.w = reinterpret_cast<const float*>(pk + plan->pk_first_w);
     fa.b = reinterpret_cast<const float*>(pk + plan->pk_first_b);
     fa.c0 = plan->C[0];
@@ -922,8 +963,9 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
         sa.index = index + gbase;
         sa.ny = gm.ny;
         sa.nx = gm.nx;
+        const int ss = stride_of(c, si);
         sa.T = T;
-        sa.s = s;
+        sa.s = ss;
         sa.Hk = gm.Hk;
         sa.Wk = gm.Wk;
         sa.mask = o.mask;
@@ -935,13 +977,14 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
         sa.Hc = lay.Hc[i];
         sa.Wc = lay.Wc[i];
         sa.coverage = 0;
+        sa.vote = c.merge == OMNISEG_MERGE_VOTE ? c.vote_threshold[si] : 0;
         double cover = 0.0;
         if (plan->profiling) {
           // every in-plane pixel of every kept tile is read exactly once
           for (int jy = 0; jy < gm.ny; ++jy)
             for (int jx = 0; jx < gm.nx; ++jx)
               if (idx_host[gbase + jy * gm.nx + jx] >= 0)
-                cover += (double)std::min(T, gm.Hk - jy * s) * std::min(T, gm.Wk - jx * s);
+                cover += (double)std::min(T, gm.Hk - jy * ss) * std::min(T, gm.Wk - jx * ss);
         }
         HIP_TRY(prof.begin());
         HIP_TRY(launch_stitch(sa, sm));
@@ -1317,18 +1360,20 @@ int32_t omniseg_stitch_workspace_bytes(int32_t tile, int32_t stride, int32_t hei
   if (tile < 1 || tile > 4096 || stride < 1 || stride > tile || height < 1 || width < 1)
     return fail(OMNISEG_ERR_ARG, "bad stitch geometry");
   const int64_t ny = grid_count(height, tile, stride), nx = grid_count(width, tile, stride);
+  if (ny * nx > (1LL << 30)) return fail(OMNISEG_ERR_UNSUPPORTED, "stitch grid of %lld tiles above 2^30", (long long)(ny * nx));
   *bytes = align256(ny * nx * 4);
   return OMNISEG_OK;
 }
 
 int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32_t width,
-                             const float* tile_logits, const int32_t* tile_yx, int32_t n_tiles,
+                             int32_t vote_threshold, const float* tile_logits, const int32_t* tile_yx, int32_t n_tiles,
                              uint8_t* mask, int64_t mask_pitch, float* logit, int64_t logit_pitch,
                              void* workspace, int64_t ws_bytes, omniseg_stream stream) {
   int64_t need = 0;
   int32_t st = omniseg_stitch_workspace_bytes(tile, stride, height, width, &need);
   if (st) return st;
   if (n_tiles < 0) return fail(OMNISEG_ERR_ARG, "n_tiles < 0");
+  if (vote_threshold < 0) return fail(OMNISEG_ERR_ARG, "vote_threshold %d < 0", vote_threshold);
   if (n_tiles > 0 && (!tile_logits || !tile_yx)) return fail(OMNISEG_ERR_ARG, "tile arrays are NULL");
   if (!mask || mask_pitch < width) return fail(OMNISEG_ERR_ARG, "bad mask buffer");
   if (logit && logit_pitch < width) return fail(OMNISEG_ERR_ARG, "bad logit pitch");
@@ -1359,6 +1404,7 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
   sa.Hc = 0;
   sa.Wc = 0;
   sa.coverage = 0;
+  sa.vote = vote_threshold;
   HIP_TRY(launch_stitch(sa, sm));
   return OMNISEG_OK;
 }

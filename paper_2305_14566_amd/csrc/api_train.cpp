@@ -235,7 +235,7 @@ FirstConvArgs first_args(const omniseg_plan* plan, const char* pk, const TrainLa
   fa.chunk_base = 0;
   fa.batch = lay.n;
   fa.T = c.tile;
-  fa.s = c.stride;
+  for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) fa.scale_s[si] = c.stride;  // training plans: one stride
   fa.w = reinterpret_cast<const float*>(pk + plan->pk_first_w);
   fa.b = reinterpret_cast<const float*>(pk + plan->pk_first_b);
   fa.c0 = plan->C[0];

@@ -26,6 +26,9 @@ struct ScaleGeom {
 };
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+// Largest grid extent the kernels launch in y (row loops stride over the rest).
+constexpr int kMaxGridY = 65535;
+
 inline int grid_count(int n, int T, int s) { return n <= T ? 1 : ceil_div(n - T, s) + 1; }
 
 inline ScaleGeom make_geom(int H, int W, int k, int T, int s) {
@@ -48,6 +51,7 @@ struct TileGroups {
   int n;                       // number of groups
   int base[kMaxGroups + 1];    // first canonical tile index of each group
   short ny[kMaxGroups], nx[kMaxGroups];
+  short s[kMaxGroups];         // tile stride of the group's scale slot
   char slide[kMaxGroups], slot[kMaxGroups], k[kMaxGroups];
 };
 
@@ -72,8 +76,8 @@ hipError_t launch_pyramid(const uint8_t* rgb, int64_t pitch, int H, int W, const
 hipError_t launch_tissue(const uint8_t* rgb, int64_t pitch, int H, int W, const int32_t* pad,
                          const uint16_t* sums_kc, int ex_kc, int kc, int Hc, int Wc, int thr,
                          uint8_t* fg, hipStream_t st);
-hipError_t launch_tile_flags(const TileGroups& g, const SlideDev* slides_dev, int T, int s,
-                             int kc, int fg_filter, int32_t* flags, hipStream_t st);
+hipError_t launch_tile_flags(const TileGroups& g, const SlideDev* slides_dev, int T, int kc,
+                             int fg_filter, int32_t* flags, hipStream_t st);
 hipError_t launch_compact(int32_t* flags_to_index, int total, const TileGroups& g,
                           int32_t* list, int32_t* count, hipStream_t st);
 
@@ -142,7 +146,8 @@ struct FirstConvArgs {
   const int32_t* count;
   int chunk_base;
   int batch;
-  int T, s;
+  int T;
+  int scale_s[OMNISEG_MAX_SCALES];  // tile stride per scale slot
   const float* w;  // [C_0][27] (c, dy, dx order: w[o][c*9 + dy*3 + dx])
   const float* b;  // [C_0]
   int c0, c0_p;
@@ -202,6 +207,7 @@ struct StitchArgs {
   const uint8_t* fg;  // tissue map for mask_and_fg (or null)
   int fg_shift, Hc, Wc;
   int coverage;       // 1: mask = (D > 0) instead of (N > 0)
+  int vote;           // > 0: majority vote -- mask = (number of covering tiles with logit > 0) >= vote
 };
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t st);
 hipError_t launch_grid_from_list(const int32_t* tile_yx, int n_tiles, int ny, int nx,

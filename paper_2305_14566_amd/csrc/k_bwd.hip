@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_input_x(FirstConvArgs a, float* __restr
   const int4 t = reinterpret_cast<const int4*>(a.list)[a.chunk_base + b];
   const SlideDev& sd = a.slides[t.x];
   const int k = a.scale_k[t.y];
-  const int Y = t.z * a.s + q / a.T, X = t.w * a.s + q % a.T;
+  const int Y = t.z * a.scale_s[t.y] + q / a.T, X = t.w * a.scale_s[t.y] + q % a.T;
   const float scale = 1.0f / (255.0f * (float)(1 << (2 * k)));
   float v0, v1, v2;
   if (k == 0) {

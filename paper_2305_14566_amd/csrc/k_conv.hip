@@ -1021,7 +1021,7 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
   const int4 t = reinterpret_cast<const int4*>(a.list)[a.chunk_base + b];
   const SlideDev& sd = a.slides[t.x];
   const int k = a.scale_k[t.y];
-  const int oy = t.z * a.s, ox = t.w * a.s;  // tile origin at scale k
+  const int oy = t.z * a.scale_s[t.y], ox = t.w * a.scale_s[t.y];  // tile origin at scale k
   const float scale = 1.0f / (255.0f * (float)(1 << (2 * k)));
   for (int i = threadIdx.x; i < 18 * 18; i += 256) {
     const int py = i / 18, px = i % 18;

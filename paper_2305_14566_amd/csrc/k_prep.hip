@@ -43,11 +43,8 @@ struct PyrArgs {
 };
 
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
+__device__ __forceinline__ void pyramid_block(const PyrArgs& a, int bx, int by) {
   constexpr int F = 1 << KMAX;
-  int bx = blockIdx.x * blockDim.x + threadIdx.x;
-  int by = blockIdx.y;
-  if (bx >= a.nbx || by >= a.nby) return;
   const int p0 = a.pad[0], p1 = a.pad[1], p2 = a.pad[2];
   // level-1 sums of this block: (F/2) x (F/2) x 3
   int s1[F / 2][F / 2][3];
@@ -112,6 +109,14 @@ __global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
   }
 }
 
+// Block rows beyond the grid's y extent (65535 at most) are taken in strides.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_pyramid(PyrArgs a) {
+  const int bx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bx >= a.nbx) return;
+  for (int by = blockIdx.y; by < a.nby; by += gridDim.y) pyramid_block<KMAX>(a, bx, by);
+}
+
 hipError_t launch_pyramid(const uint8_t* rgb, int64_t pitch, int H, int W, const int32_t* pad,
                           int kmax, uint16_t* const* lvl, const int* Ey, const int* Ex,
                           hipStream_t st) {
@@ -138,7 +143,7 @@ hipError_t launch_pyramid(const uint8_t* rgb, int64_t pitch, int H, int W, const
   a.nby = ny;
   a.nbx = nx;
   if (ny == 0) return hipSuccess;
-  dim3 grid(ceil_div(nx, 256), ny);
+  dim3 grid(ceil_div(nx, 256), std::min(ny, kMaxGridY));
   switch (kmax) {
     case 1: hipLaunchKernelGGL(k_pyramid<1>, grid, dim3(256), 0, st, a); break;
     case 2: hipLaunchKernelGGL(k_pyramid<2>, grid, dim3(256), 0, st, a); break;
@@ -151,23 +156,24 @@ hipError_t launch_pyramid(const uint8_t* rgb, int64_t pitch, int H, int W, const
 __global__ void k_tissue(const uint8_t* __restrict__ rgb, int64_t pitch,
                          const uint16_t* __restrict__ sums, int ex, int kc, int Hc, int Wc,
                          int64_t limit, uint8_t* __restrict__ fg) {
-  int x = blockIdx.x * blockDim.x + threadIdx.x;
-  int y = blockIdx.y;
-  if (x >= Wc || y >= Hc) return;
-  int64_t r, g, b;
-  if (kc == 0) {
-    const uint8_t* p = rgb + (int64_t)y * pitch + 3 * x;
-    r = p[0];
-    g = p[1];
-    b = p[2];
-  } else {
-    ushort4 v = reinterpret_cast<const ushort4*>(sums)[(int64_t)y * ex + x];
-    r = v.x;
-    g = v.y;
-    b = v.z;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= Wc) return;
+  for (int y = blockIdx.y; y < Hc; y += gridDim.y) {
+    int64_t r, g, b;
+    if (kc == 0) {
+      const uint8_t* p = rgb + (int64_t)y * pitch + 3 * x;
+      r = p[0];
+      g = p[1];
+      b = p[2];
+    } else {
+      ushort4 v = reinterpret_cast<const ushort4*>(sums)[(int64_t)y * ex + x];
+      r = v.x;
+      g = v.y;
+      b = v.z;
+    }
+    int64_t gray = 299 * r + 587 * g + 114 * b;
+    fg[(int64_t)y * Wc + x] = gray < limit ? 1 : 0;
   }
-  int64_t gray = 299 * r + 587 * g + 114 * b;
-  fg[(int64_t)y * Wc + x] = gray < limit ? 1 : 0;
 }
 
 hipError_t launch_tissue(const uint8_t* rgb, int64_t pitch, int H, int W, const int32_t* pad,
@@ -177,7 +183,7 @@ hipError_t launch_tissue(const uint8_t* rgb, int64_t pitch, int H, int W, const 
   (void)W;
   (void)pad;
   int64_t limit = (int64_t)thr * 1000 * ((int64_t)1 << (2 * kc));
-  dim3 grid(ceil_div(Wc, 256), Hc);
+  dim3 grid(ceil_div(Wc, 256), std::min(Hc, kMaxGridY));
   hipLaunchKernelGGL(k_tissue, grid, dim3(256), 0, st, rgb, pitch, sums_kc, ex_kc, kc, Hc, Wc,
                      limit, fg);
   return hipGetLastError();
@@ -187,8 +193,7 @@ hipError_t launch_tissue(const uint8_t* rgb, int64_t pitch, int H, int W, const 
 // 40x footprint (coarse row r covers 40x rows [r 2^kc, (r+1) 2^kc), the tile
 // covers [jy s 2^k, (jy s + T) 2^k)).
 __global__ __launch_bounds__(256) void k_tile_flags(TileGroups g, const SlideDev* slides, int T,
-                                                    int s, int kc, int fg_filter,
-                                                    int32_t* flags) {
+                                                    int kc, int fg_filter, int32_t* flags) {
   const int t = blockIdx.x;
   int gi = 0;
   while (gi + 1 < g.n && g.base[gi + 1] <= t) ++gi;
@@ -198,6 +203,7 @@ __global__ __launch_bounds__(256) void k_tile_flags(TileGroups g, const SlideDev
   }
   const int local = t - g.base[gi];
   const int nx = g.nx[gi];
+  const int s = g.s[gi];
   const int jy = local / nx, jx = local % nx;
   const int k = g.k[gi];
   const SlideDev& sd = slides[(int)g.slide[gi]];
@@ -220,12 +226,11 @@ __global__ __launch_bounds__(256) void k_tile_flags(TileGroups g, const SlideDev
   if (threadIdx.x == 0) flags[t] = found ? 1 : 0;
 }
 
-hipError_t launch_tile_flags(const TileGroups& g, const SlideDev* slides_dev, int T, int s, int kc,
+hipError_t launch_tile_flags(const TileGroups& g, const SlideDev* slides_dev, int T, int kc,
                              int fg_filter, int32_t* flags, hipStream_t st) {
   int total = g.base[g.n];
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_flags, dim3(total), dim3(256), 0, st, g, slides_dev, T, s, kc,
-                     fg_filter, flags);
+  hipLaunchKernelGGL(k_tile_flags, dim3(total), dim3(256), 0, st, g, slides_dev, T, kc, fg_filter, flags);
   return hipGetLastError();
 }
 

@@ -18,9 +18,10 @@ ACT_ENC_A, ACT_ENC_E, ACT_DEC_A, ACT_DEC_D = range(4)
 FLAG_EMIT_LOGITS = 1
 FLAG_TRAINING = 2
 FLAG_GRAPH = 4
+MERGE_RAMP, MERGE_VOTE = 0, 1
 (REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
  REGION_TILE_INDEX, REGION_TILE_LOGITS) = range(7)
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
 N_CONV_CONFIGS = 11
@@ -52,6 +53,9 @@ class Config(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("batch_tiles", ctypes.c_int32),
         ("max_kept_tiles", ctypes.c_int32),
+        ("scale_stride", ctypes.c_int32 * 4),
+        ("merge", ctypes.c_int32),
+        ("vote_threshold", ctypes.c_int32 * 4),
     ]
 
 
@@ -97,7 +101,7 @@ def _declare(lib):
         "omniseg_segment_slide": (i32, [vp, vp, P(Slide), i32, P(Pair), i32, P(Output), vp, i64, vp]),
         "omniseg_workspace_region": (i32, [vp, P(Slide), i32, P(Pair), i32, i32, i32, P(i64), P(i64)]),
         "omniseg_stitch_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
-        "omniseg_stitch_tiles": (i32, [i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, i64, vp, i64, vp]),
+        "omniseg_stitch_tiles": (i32, [i32, i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, i64, vp, i64, vp]),
         "omniseg_set_profiling": (i32, [vp, i32]),
         "omniseg_conv_config": (i32, [i32, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]),
         "omniseg_autotune": (i32, [vp, vp, P(Slide), i32, P(Pair), i32, vp, i64, vp]),
@@ -166,7 +170,7 @@ class Plan:
     def __init__(self, base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
                  stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False,
                  precision=FP32, emit_logits=False, batch_tiles=0, training=False, graph=False,
-                 max_kept_tiles=0):
+                 max_kept_tiles=0, scale_strides=None, merge=MERGE_RAMP, vote_thresholds=None):
         c = Config()
         c.abi_version = ABI_VERSION
         c.base_channels = base
@@ -186,6 +190,11 @@ class Plan:
                    | (FLAG_GRAPH if graph else 0))
         c.batch_tiles = batch_tiles
         c.max_kept_tiles = max_kept_tiles
+        for i, v in enumerate(scale_strides or ()):
+            c.scale_stride[i] = v
+        c.merge = merge
+        for i, v in enumerate(vote_thresholds or ()):
+            c.vote_threshold[i] = v
         self.cfg = c
         self.scales = tuple(scales)
         self.emit_logits = emit_logits
@@ -385,8 +394,10 @@ class Plan:
         return masks, logits, workspace
 
 
-def stitch_tiles(tile, stride, height, width, tile_logits, tile_yx, emit_logits=True, stream=None):
-    """Stand-alone stitch of one plane; returns (mask uint8, logit float32 or None)."""
+def stitch_tiles(tile, stride, height, width, tile_logits, tile_yx, emit_logits=True, stream=None,
+                 vote_threshold=0):
+    """Stand-alone stitch of one plane; returns (mask uint8, logit float32 or None).
+    vote_threshold > 0: majority vote (the logit plane then holds vote counts)."""
     l = lib()
     n = ctypes.c_int64()
     _check(l.omniseg_stitch_workspace_bytes(tile, stride, height, width, ctypes.byref(n)))
@@ -395,7 +406,7 @@ def stitch_tiles(tile, stride, height, width, tile_logits, tile_yx, emit_logits=
     mask = torch.empty((height, width), dtype=torch.uint8, device=dev)
     logit = torch.empty((height, width), dtype=torch.float32, device=dev) if emit_logits else None
     n_tiles = tile_yx.shape[0]
-    _check(l.omniseg_stitch_tiles(tile, stride, height, width, _ptr(tile_logits), _ptr(tile_yx), n_tiles,
+    _check(l.omniseg_stitch_tiles(tile, stride, height, width, vote_threshold, _ptr(tile_logits), _ptr(tile_yx), n_tiles,
                                   _ptr(mask), mask.stride(0), _ptr(logit),
                                   logit.stride(0) if logit is not None else 0, _ptr(ws), ws.numel(),
                                   _stream(stream)))

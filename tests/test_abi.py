@@ -217,14 +217,45 @@ def test_stitch_rejects_before_any_hip_call():
     assert lib.omniseg_stitch_workspace_bytes(64, 32, 100, 90, ctypes.byref(n)) == 0
     assert n.value == 256  # 4 x 3 grid of int32, aligned
     assert lib.omniseg_stitch_workspace_bytes(64, 65, 100, 90, ctypes.byref(n)) == 1
-    args = dict(tile=64, stride=32, h=100, w=90)
     # workspace too small
-    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, FAKE, FAKE, 3, FAKE, 90, 0, 0, FAKE, 16, None) == 3
+    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, 0, FAKE, FAKE, 3, FAKE, 90, 0, 0, FAKE, 16, None) == 3
     # more tiles than grid positions
-    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, FAKE, FAKE, 13, FAKE, 90, 0, 0, FAKE, 256, None) == 1
+    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, 0, FAKE, FAKE, 13, FAKE, 90, 0, 0, FAKE, 256, None) == 1
     # mask pitch
-    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, FAKE, FAKE, 3, FAKE, 89, 0, 0, FAKE, 256, None) == 1
-    del args
+    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, 0, FAKE, FAKE, 3, FAKE, 89, 0, 0, FAKE, 256, None) == 1
+    # negative vote threshold
+    assert lib.omniseg_stitch_tiles(64, 32, 100, 90, -1, FAKE, FAKE, 3, FAKE, 90, 0, 0, FAKE, 256, None) == 1
+    # a grid above 2^30 positions
+    assert lib.omniseg_stitch_workspace_bytes(16, 1, 1 << 20, 1 << 20, ctypes.byref(n)) == 2
+
+
+@pytest.mark.parametrize("case", ["repeat_scale", "stride_range", "merge", "vote_low", "vote_high",
+                                  "train_vote", "train_strides"])
+def test_merge_and_stride_validation(case):
+    """Per-scale strides and the vote merge are validated at plan creation."""
+    base = dict(base=4, levels=2, head_out=1, n_classes=2, scales=(0, 2), tile=64, stride=32)
+    ok = dict(scale_strides=(32, 16), merge=om.MERGE_VOTE, vote_thresholds=(1, 16))
+    om.Plan(**base, **ok)  # valid: ceil(64/16)^2 = 16 tiles cover a 10x pixel at most
+    bad = {
+        "repeat_scale": dict(scales=(1, 1)),
+        "stride_range": dict(scale_strides=(32, 65)),
+        "merge": dict(merge=2),
+        "vote_low": dict(vote_thresholds=(0, 4)),
+        "vote_high": dict(vote_thresholds=(1, 17)),
+        "train_vote": dict(scale_strides=None, vote_thresholds=(1, 4), training=True),
+        "train_strides": dict(merge=om.MERGE_RAMP, vote_thresholds=None, training=True),
+    }[case]
+    kw = {**base, **ok, **bad}
+    with pytest.raises(om.OmnisegError) as e:
+        om.Plan(**kw)
+    assert e.value.status == (2 if case.startswith("train") else 1)
+
+
+def test_tile_grid_size_guard():
+    """A tile grid of more than 32767 tiles per side is refused before any HIP call."""
+    p = om.Plan(base=4, levels=2, head_out=1, n_classes=1, scales=(0,), tile=16, stride=1)
+    sl = _slides([(40000, 64)])
+    assert _segment(p, sl, 1, _pairs([(0, 0)]), 1, _outs(1)) == 2
 
 
 def _tiles(ts):

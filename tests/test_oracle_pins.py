@@ -399,6 +399,132 @@ def test_stitch_single_tile_identity_and_ramp():
     assert np.array_equal(D, np.outer(r, r))
 
 
+# ---------------------------------------------------------------- O10b majority vote
+
+
+def _axis_cover(n, T, s):
+    """Closed form: tiles at origins j s (0 <= j < grid_count) containing y."""
+    m = O.grid_count(n, T, s)
+    y = np.arange(n)
+    lo = np.maximum(0, -(-(y - T + 1) // s))
+    hi = np.minimum(m - 1, y // s)
+    return hi - lo + 1
+
+
+@pytest.mark.parametrize("H,W,T,s", [(1100, 1300, 512, 256), (1100, 1200, 512, 64), (90, 77, 32, 16),
+                                     (100, 100, 48, 20), (40, 33, 16, 16), (5, 3, 16, 8)])
+def test_vote_full_grid_coverage_closed_form(H, W, T, s):
+    ny, nx = O.grid_count(H, T, s), O.grid_count(W, T, s)
+    tiles = [(jy, jx) for jy in range(ny) for jx in range(nx)]
+    V, C = O.vote(tiles, [np.ones((T, T))] * len(tiles), H, W, T, s)
+    want = np.outer(_axis_cover(H, T, s), _axis_cover(W, T, s))
+    assert np.array_equal(C, want) and np.array_equal(V, want)
+    if (T, s) in [(512, 256), (512, 64)]:
+        # the paper's interior counts: (T/s)^2 = 4 and 64 covering tiles
+        assert C[T:H - T, T:W - T].min() == C[T:H - T, T:W - T].max() == (T // s) ** 2
+
+
+def test_vote_brute_force_with_missing_tiles_and_zero_logits():
+    rng = np.random.default_rng(21)
+    T, s, H, W = 12, 5, 31, 26
+    ny, nx = O.grid_count(H, T, s), O.grid_count(W, T, s)
+    tiles = [(jy, jx) for jy in range(ny) for jx in range(nx) if rng.uniform() < 0.6]
+    logits = [rng.integers(-2, 3, size=(T, T)).astype(np.float64) for _ in tiles]  # a fifth exact zeros
+    V, C = O.vote(tiles, logits, H, W, T, s)
+    for y in range(H):
+        for x in range(W):
+            v = c = 0
+            for (jy, jx), l in zip(tiles, logits):
+                if jy * s <= y < jy * s + T and jx * s <= x < jx * s + T:
+                    c += 1
+                    v += l[y - jy * s, x - jx * s] > 0  # zero is no vote
+            assert V[y, x] == v and C[y, x] == c
+
+
+def test_vote_without_overlap_is_the_tile_sign():
+    rng = np.random.default_rng(22)
+    T, H, W = 16, 48, 40
+    tiles = [(jy, jx) for jy in range(3) for jx in range(3)]
+    logits = [rng.standard_normal((T, T)) for _ in tiles]
+    V, C = O.vote(tiles, logits, H, W, T, T)
+    assert np.all(C == 1)
+    for (jy, jx), l in zip(tiles, logits):
+        blk = V[jy * T:jy * T + T, jx * T:jx * T + T]
+        assert np.array_equal(blk, (l > 0)[:blk.shape[0], :blk.shape[1]])
+
+
+def test_vote_threshold_extremes_and_symmetry():
+    rng = np.random.default_rng(23)
+    T, s, H, W = 32, 8, 70, 60
+    ny, nx = O.grid_count(H, T, s), O.grid_count(W, T, s)
+    tiles = [(jy, jx) for jy in range(ny) for jx in range(nx) if rng.uniform() < 0.8]
+    logits = [rng.standard_normal((T, T)) + 0.3 for _ in tiles]
+    V, C = O.vote(tiles, logits, H, W, T, s)
+    Vn, Cn = O.vote(tiles, [-l for l in logits], H, W, T, s)
+    assert np.array_equal(C, Cn) and np.array_equal(V + Vn, C)  # no exact zeros here
+    # threshold 1: some covering tile predicts the class (union of tile masks)
+    union = np.zeros((H, W), bool)
+    inter = np.ones((H, W), bool)
+    for (jy, jx), l in zip(tiles, logits):
+        sl = (slice(jy * s, min(jy * s + T, H)), slice(jx * s, min(jx * s + T, W)))
+        pos = (l > 0)[:sl[0].stop - sl[0].start, :sl[1].stop - sl[1].start]
+        union[sl] |= pos
+        inter[sl] &= pos
+    assert np.array_equal(V >= 1, union)
+    # threshold C(p): every covering tile agrees (unanimity), where covered
+    cov = C > 0
+    assert np.array_equal((V >= C)[cov], inter[cov])
+    # masks shrink as the threshold grows
+    for v in range(1, (T // s) ** 2):
+        assert np.all((V >= v + 1) <= (V >= v))
+
+
+def test_vote_and_ramp_agree_where_tiles_are_unanimous():
+    rng = np.random.default_rng(24)
+    T, s, H, W = 24, 8, 50, 45
+    ny, nx = O.grid_count(H, T, s), O.grid_count(W, T, s)
+    tiles = [(jy, jx) for jy in range(ny) for jx in range(nx)]
+    # a smooth sign field shared by the tiles plus per-tile noise
+    yy, xx = np.mgrid[0:ny * s + T, 0:nx * s + T]
+    field = np.sin(yy / 9.0) + np.cos(xx / 7.0)
+    logits = [field[jy * s:jy * s + T, jx * s:jx * s + T] + 0.4 * rng.standard_normal((T, T))
+              for (jy, jx) in tiles]
+    V, C = O.vote(tiles, logits, H, W, T, s)
+    _, N, D = O.stitch(tiles, logits, H, W, T, s)
+    unanimous = (V == C) | (V == 0)
+    assert unanimous.mean() > 0.5
+    assert np.array_equal((V >= 1)[unanimous], (N > 0)[unanimous])
+
+
+def test_per_scale_strides_route_each_slot_to_its_grid():
+    """A two-slot plan with strides (32, 16) gives slot 0 the outputs of a
+    stride-32 plan and slot 1 those of a stride-16 plan (same network)."""
+    rgb, _ = synth.strip_slide(25, 70, 90, fg_frac=0.4)
+    flat = synth.he_normal_weights(26, 4, 2, 2, 2, 2)
+    kw = dict(base=4, levels=2, head_out=2, n_classes=2, scales=(0, 1), tile=32, fg_filter=True)
+    pairs = [(1, 0), (0, 1)]
+    mixed = O.make_config(stride=32, scale_strides=(32, 16), **kw)
+    a = O.segment([rgb], flat, mixed, pairs)
+    b0 = O.segment([rgb], flat, O.make_config(stride=32, **kw), pairs)
+    b1 = O.segment([rgb], flat, O.make_config(stride=16, **kw), pairs)
+    assert np.array_equal(a["logit"][0][0], b0["logit"][0][0])
+    assert np.array_equal(a["logit"][0][1], b1["logit"][0][1])
+    assert not np.array_equal(b0["logit"][0][1], b1["logit"][0][1])  # the strides do matter here
+    assert [t for t in a["tiles"] if t[1] == 0] == [t for t in b0["tiles"] if t[1] == 0]
+    assert [t for t in a["tiles"] if t[1] == 1] == [t for t in b1["tiles"] if t[1] == 1]
+    # the 20x grid of the 35 x 45 level at stride 16 has 2 x 2 tiles, the 40x grid at 32 has 3 x 3
+    assert len([t for t in a["tiles"] if t[1] == 1]) <= 4 and len([t for t in a["tiles"] if t[1] == 0]) <= 9
+    assert O.grid_count(O.level_size(70, 1), 32, 16) == 2 and O.grid_count(O.level_size(90, 1), 32, 16) == 2
+    # the vote merge with the paper's thresholds reuses the same tile logits
+    v = O.segment([rgb], flat, O.make_config(stride=32, scale_strides=(32, 16), merge="vote",
+                                            vote_thresholds=(1, 4), **kw), pairs, keep_tiles=True)
+    assert v["tiles"] == a["tiles"]
+    for p, (c, si) in enumerate(pairs):
+        V = v["logit"][0][p]
+        assert np.array_equal(v["mask"][0][p], V >= (1, 4)[si])
+        assert V.dtype == np.float64 and np.all(V == np.round(V)) and V.max() <= 4
+
+
 # ---------------------------------------------------------------- whole path on the tiny instance
 
 def test_segment_tiny_instance_runs():
