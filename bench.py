@@ -41,17 +41,17 @@ PAPER_CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 2, 3), t
 
 # HBM bytes per launch of the dominant BF16 conv kernel on this workload, from
 # two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
-#   bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu --train-steps 0 --fp8-steps 0 --copy-gib 1
-# over the launches of the timed step, each counter scaled by its reading for
-# the 1 GiB device copy that command makes first (FETCH_SIZE read 0.5 GiB,
+#   bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu --train-steps 0 --fp8-steps 0 --paper-steps 0 --copy-gib 1
+# over the 32 launches of the timed step, each counter scaled by its reading
+# for the 1 GiB device copy that command makes first (FETCH_SIZE read 0.5 GiB,
 # WRITE_SIZE 1 GiB).  It describes the conv source whose SHA-256 is stored
 # here and is reported as null for any other.
 MEASURED_TRAFFIC = {
-    "kernel": "omniseg::k_conv3x3_rows<16, 64, 2, 2, 0, 1>",
-    "bytes_per_launch": 3326979393.0,
-    "fetch_bytes_per_launch": 2494570248.0,
-    "write_bytes_per_launch": 832409145.0,
-    "conv_source_sha256": "9f6cc069222b62f09002b4ff5f8910417a6f76bcafb07e88f1dd8dd141a451eb",
+    "kernel": "omniseg::k_conv3x3_rows<16, 64, 2, 2, 2, 0>",
+    "bytes_per_launch": 4492918214.9,
+    "fetch_bytes_per_launch": 3514698658.9,
+    "write_bytes_per_launch": 978219556.0,
+    "conv_source_sha256": "60df7bccfdd9bd7863952107e4d7b17196aac1b129575661b1d3dbe508611403",
 }
 
 

@@ -468,9 +468,10 @@ hipError_t launch_maxpool_bwd(int precision, const void* E, const void* dX, int 
   return hipGetLastError();
 }
 
+// grid-stride: buffers of more than 2^32 words take fewer blocks than words / 256
 __global__ void k_fill_zero(uint32_t* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = 0u;
+  const int64_t step = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += step) p[i] = 0u;
 }
 
 __global__ void k_set_i32(int32_t* p, int32_t v) {
@@ -485,7 +486,8 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st) {
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st) {
   const int64_t n = bytes / 4;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t*)p, n);
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, n);
   return hipGetLastError();
 }
 
