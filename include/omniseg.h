@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define OMNISEG_ABI_VERSION 5
+#define OMNISEG_ABI_VERSION 6
 
 /* status codes */
 #define OMNISEG_OK 0
@@ -67,6 +67,12 @@ extern "C" {
 #define OMNISEG_MERGE_RAMP 0 /* ramp-weighted mean of the tile logits, mask = mean > 0 */
 #define OMNISEG_MERGE_VOTE 1 /* majority vote: mask = (number of covering tiles whose
                                 logit is > 0) >= vote_threshold of the pair's scale */
+
+/* tissue detection (omniseg_config.tissue_method) */
+#define OMNISEG_TISSUE_GRAY 0 /* fixed gray threshold fg_threshold on the coarsest scale */
+#define OMNISEG_TISSUE_OTSU 1 /* Otsu threshold of the median-blurred coarsest-scale gray map,
+                                 then 8-connected tissue components smaller than
+                                 min_tissue_area removed (Sections 2.1 and 3.2) */
 
 /* limits */
 #define OMNISEG_MAX_SCALES 4
@@ -101,7 +107,23 @@ typedef struct omniseg_hip_stream_opaque* omniseg_stream; /* a hipStream_t */
  *   fg_filter      1: keep only tiles whose footprint touches a foreground
  *                  pixel of the tissue map; 0: keep every tile.
  *   fg_threshold   gray threshold of the tissue map (pixels darker than this
- *                  on the coarsest scale are tissue), in [1, 255].
+ *                  on the coarsest scale are tissue), in [1, 255]; used by
+ *                  OMNISEG_TISSUE_GRAY.
+ *   tissue_method  OMNISEG_TISSUE_GRAY or OMNISEG_TISSUE_OTSU.  The tissue
+ *                  map decides which tiles are kept (fg_filter) and, with
+ *                  mask_and_fg, where masks may be on.  OTSU, on the
+ *                  coarsest scale kc: gray g = round((299 R + 587 G + 114 B)
+ *                  / (1000 4^kc)) of the block sums (an integer in [0, 255]);
+ *                  median_kernel x median_kernel median with replicated
+ *                  borders; Otsu's threshold t of the blurred map (the first
+ *                  t maximising n0 n1 (mu0 - mu1)^2 over the splits {<= t},
+ *                  {> t}, in FP64; a one-valued map has no tissue); tissue =
+ *                  blurred gray <= t; then 8-connected tissue components of
+ *                  fewer than min_tissue_area pixels are removed.  The
+ *                  coarse map must have fewer than 2^31 pixels.
+ *   median_kernel  odd, in [1, 255] (1 = no blur); OTSU only.
+ *   min_tissue_area  >= 0, in coarse pixels (0 or 1 keep every component);
+ *                  OTSU only.
  *   mask_and_fg    1: the output mask is also ANDed with the tissue map.
  *   scale_log2 must not repeat a value across the n_scales slots.
  *   precision      OMNISEG_FP32, OMNISEG_BF16 or OMNISEG_FP8 (not with
@@ -134,6 +156,9 @@ typedef struct omniseg_config {
   int32_t scale_stride[OMNISEG_MAX_SCALES];
   int32_t merge;
   int32_t vote_threshold[OMNISEG_MAX_SCALES];
+  int32_t tissue_method;
+  int32_t median_kernel;
+  int32_t min_tissue_area;
 } omniseg_config;
 
 /* One slide: uint8 RGB, interleaved (HWC), rows `row_pitch` bytes apart
@@ -300,6 +325,11 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
 #define OMNISEG_REGION_TILE_INDEX 5 /* int32 per grid tile of (slide, slot): list index or -1,
                                        row-major (jy, jx); index = slide * n_scales + slot */
 #define OMNISEG_REGION_TILE_LOGITS 6 /* float[max_tiles][max_pairs_per_scale][T][T] */
+#define OMNISEG_REGION_TISSUE_GRAY 7  /* uint8[H_c][W_c]: the median-blurred gray map of a slide
+                                         (OMNISEG_TISSUE_OTSU; empty otherwise); index = slide */
+#define OMNISEG_REGION_TISSUE_STATS 8 /* int32[4] of a slide (OMNISEG_TISSUE_OTSU; empty otherwise):
+                                         Otsu threshold (-1: one-valued map), tissue components,
+                                         components kept, 0; index = slide */
 /*
  * Byte offset and size of one region inside the workspace for these slides
  * and pairs (host arrays); the layout depends only on the arguments.

@@ -35,7 +35,8 @@ import numpy as np
 
 def make_config(base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
                 stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False,
-                scale_strides=None, merge="ramp", vote_thresholds=None):
+                scale_strides=None, merge="ramp", vote_thresholds=None, tissue_method="gray",
+                median_kernel=1, min_tissue_area=0):
     """Oracle configuration.
 
     scales: log2 downsampling factor of each scale slot (0 = 40x, 1 = 20x,
@@ -44,6 +45,8 @@ def make_config(base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128
     Section 3.2 uses 256 at 40x and 64 at 10x and 5x.
     merge: "ramp" (weighted mean of logits) or "vote" (majority vote of the
     binary tile predictions, Section 2.2) with vote_thresholds per slot.
+    tissue_method: "gray" (fixed threshold fg_threshold) or "otsu" (with
+    median_kernel and min_tissue_area; tissue_map_otsu).
     """
     n = len(scales)
     ss = tuple(int(v) if v else int(stride) for v in (scale_strides or (0,) * n))
@@ -52,7 +55,8 @@ def make_config(base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128
                 n_classes=int(n_classes), scales=tuple(int(s) for s in scales),
                 tile=int(tile), stride=int(stride), fg_filter=bool(fg_filter),
                 fg_threshold=int(fg_threshold), mask_and_fg=bool(mask_and_fg),
-                scale_strides=ss, merge=str(merge), vote_thresholds=vt)
+                scale_strides=ss, merge=str(merge), vote_thresholds=vt, tissue_method=str(tissue_method),
+                median_kernel=int(median_kernel), min_tissue_area=int(min_tissue_area))
 
 
 def stride_of(cfg, si):
@@ -210,6 +214,111 @@ def tissue_map(rgb, kc, threshold=220):
     S = scale_sums(rgb, kc, Hc, Wc)
     g = 299 * S[..., 0] + 587 * S[..., 1] + 114 * S[..., 2]
     return g < threshold * 1000 * 4 ** kc
+
+
+# --------------------------------------------------------------------------
+# O3b  Otsu tissue detection (Section 2.1; Section 3.2: Otsu, median blur,
+#      removal of tiny noise from the foreground contour)
+# --------------------------------------------------------------------------
+
+
+def gray8(rgb, kc):
+    """Coarse gray map: round((299 S_R + 587 S_G + 114 S_B) / (1000 4^kc)), in [0, 255]."""
+    H, W, _ = rgb.shape
+    Hc, Wc = level_size(H, kc), level_size(W, kc)
+    S = scale_sums(rgb, kc, Hc, Wc).astype(np.int64)
+    den = 1000 * 4 ** kc
+    return ((299 * S[..., 0] + 587 * S[..., 1] + 114 * S[..., 2] + den // 2) // den).astype(np.int64)
+
+
+def median_blur(g, m):
+    """m x m median (m odd) with replicated borders: the middle element of the
+    sorted window."""
+    if m == 1:
+        return g.copy()
+    r = m // 2
+    P = np.pad(g, r, mode="edge")
+    out = np.empty_like(g)
+    for y in range(g.shape[0]):  # one output row at a time keeps the windows small
+        win = np.lib.stride_tricks.sliding_window_view(P[y:y + m], (m, m))[0]
+        out[y] = np.sort(win.reshape(g.shape[1], m * m), axis=-1)[:, (m * m - 1) // 2]
+    return out
+
+
+def otsu_threshold(g):
+    """Otsu's threshold of an integer image in [0, 255].
+
+    For each split {<= t} / {> t} with both classes non-empty the score is
+    the between-class variance up to the constant 1/N^2, n0 n1 (mu0 - mu1)^2,
+    evaluated in FP64 as ((n0 n1) d) d with d = s0/n0 - s1/n1 (one rounding
+    per operation); the first t of the largest score wins.  -1 when the image
+    has a single value.
+    """
+    h = np.bincount(np.asarray(g).ravel(), minlength=256).astype(np.int64)
+    N, S = int(h.sum()), int((h * np.arange(256)).sum())
+    best, best_t = -1.0, -1
+    n0 = s0 = 0
+    for t in range(256):
+        n0 += int(h[t])
+        s0 += t * int(h[t])
+        n1 = N - n0
+        if n0 == 0 or n1 == 0:
+            continue
+        mu0 = float(s0) / float(n0)
+        mu1 = float(S - s0) / float(n1)
+        d = mu0 - mu1
+        score = (float(n0) * float(n1) * d) * d
+        if score > best:
+            best, best_t = score, t
+    return best_t
+
+
+def components8(mask):
+    """8-connected components by breadth-first flood fill.  Returns labels
+    (-1 off the mask; each component labelled by its smallest row-major
+    index) and the component sizes {label: pixels}."""
+    H, W = mask.shape
+    lab = -np.ones((H, W), dtype=np.int64)
+    sizes = {}
+    for y0 in range(H):
+        for x0 in range(W):
+            if not mask[y0, x0] or lab[y0, x0] >= 0:
+                continue
+            root = y0 * W + x0  # the first pixel met in row-major order is the smallest
+            lab[y0, x0] = root
+            queue, n = [(y0, x0)], 0
+            while queue:
+                y, x = queue.pop()
+                n += 1
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        yy, xx = y + dy, x + dx
+                        if 0 <= yy < H and 0 <= xx < W and mask[yy, xx] and lab[yy, xx] < 0:
+                            lab[yy, xx] = root
+                            queue.append((yy, xx))
+            sizes[root] = n
+    return lab, sizes
+
+
+def tissue_map_otsu(rgb, kc, median=1, min_area=0):
+    """Tissue map by Otsu: gray -> median blur -> threshold t (tissue =
+    blurred <= t, the darker class) -> drop 8-connected components below
+    min_area pixels.  Returns (map, blurred gray, (t, components, kept))."""
+    b = median_blur(gray8(rgb, kc), median)
+    t = otsu_threshold(b)
+    fg0 = b <= t
+    lab, sizes = components8(fg0)
+    keep = {r for r, n in sizes.items() if n >= min_area}
+    fg = np.isin(lab, list(keep)) & fg0 if keep else np.zeros_like(fg0)
+    return fg, b, (t, len(sizes), len(keep))
+
+
+def tissue_of(rgb, cfg):
+    """The tissue map a configuration asks for, at the coarsest scale."""
+    kc = max(cfg["scales"])
+    if cfg.get("tissue_method", "gray") == "otsu":
+        return tissue_map_otsu(rgb, kc, cfg["median_kernel"], cfg["min_tissue_area"])[0]
+    return tissue_map(rgb, kc, cfg["fg_threshold"])
 
 
 # --------------------------------------------------------------------------
@@ -668,7 +777,7 @@ def segment(slides, flat_weights, cfg, pairs, tile_subset=None, keep_tiles=False
     T = cfg["tile"]
     kc = max(cfg["scales"])
     need_fg = cfg["fg_filter"] or cfg["mask_and_fg"]
-    fgs = [tissue_map(r, kc, cfg["fg_threshold"]) if need_fg else None for r in slides]
+    fgs = [tissue_of(r, cfg) if need_fg else None for r in slides]
     tl = tile_list([r.shape[:2] for r in slides], cfg, fgs)
     if tile_subset is not None:
         tl = [t for t in tl if t in set(tile_subset)]

@@ -58,6 +58,11 @@ struct Layout {
   int64_t off_tab = 0, off_pad[OMNISEG_MAX_SLIDES], off_pyr[OMNISEG_MAX_SLIDES][OMNISEG_MAX_SCALES],
           off_fg[OMNISEG_MAX_SLIDES];
   int64_t sz_pyr[OMNISEG_MAX_SLIDES][OMNISEG_MAX_SCALES], sz_fg[OMNISEG_MAX_SLIDES];
+  // Otsu tissue detection: per slide the blurred gray map and four stats;
+  // shared scratch for the unblurred map, histogram, labels and areas
+  bool otsu = false;
+  int64_t off_tgray[OMNISEG_MAX_SLIDES], off_tstats[OMNISEG_MAX_SLIDES];
+  int64_t off_ttmp = -1, off_thist = -1, off_tlabel = -1, off_tarea = -1;
   int64_t off_index = 0, off_list = 0, off_count = 0;
   int64_t off_E[8], off_A = 0, off_g = 0, off_theta = 0, off_logits = 0;
   int64_t sz_E[8], sz_A = 0, sz_logits = 0;
@@ -128,6 +133,13 @@ int32_t validate_config(const omniseg_config* c) {
   if (c->batch_tiles < 0 || c->batch_tiles > 65536)
     return fail(OMNISEG_ERR_ARG, "batch_tiles %d outside [0, 65536]", c->batch_tiles);
   if (c->max_kept_tiles < 0) return fail(OMNISEG_ERR_ARG, "max_kept_tiles %d < 0", c->max_kept_tiles);
+  if (c->tissue_method != OMNISEG_TISSUE_GRAY && c->tissue_method != OMNISEG_TISSUE_OTSU)
+    return fail(OMNISEG_ERR_ARG, "unknown tissue_method %d", c->tissue_method);
+  if (c->tissue_method == OMNISEG_TISSUE_OTSU) {
+    if (c->median_kernel < 1 || c->median_kernel > 255 || c->median_kernel % 2 == 0)
+      return fail(OMNISEG_ERR_ARG, "median_kernel %d must be odd in [1, 255]", c->median_kernel);
+    if (c->min_tissue_area < 0) return fail(OMNISEG_ERR_ARG, "min_tissue_area %d < 0", c->min_tissue_area);
+  }
   const int64_t G = (int64_t)c->base_channels << (c->levels - 1);
   if (G > 4096) return fail(OMNISEG_ERR_UNSUPPORTED, "bottleneck width %lld > 4096", (long long)G);
   return OMNISEG_OK;
@@ -165,6 +177,16 @@ int32_t validate_call(const omniseg_plan* plan, const omniseg_slide* slides, int
     }
   if (grid_tiles > (1LL << 26))
     return fail(OMNISEG_ERR_UNSUPPORTED, "%lld grid tiles above 2^26", (long long)grid_tiles);
+  if (c.tissue_method == OMNISEG_TISSUE_OTSU && (c.fg_filter || c.mask_and_fg)) {
+    int kc = 0;
+    for (int si = 0; si < c.n_scales; ++si) kc = std::max(kc, c.scale_log2[si]);
+    for (int i = 0; i < n_slides; ++i) {
+      const int64_t hc = ceil_div(slides[i].height, 1 << kc), wc = ceil_div(slides[i].width, 1 << kc);
+      if (hc * wc >= (1LL << 31))
+        return fail(OMNISEG_ERR_UNSUPPORTED, "slide %d: coarse map of %lld pixels above 2^31 - 1", i,
+                    (long long)(hc * wc));
+    }
+  }
   bool seen[OMNISEG_MAX_CLASSES][OMNISEG_MAX_SCALES] = {};
   lay.S = c.n_scales;
   for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) lay.slots.n_slots[si] = 0;
@@ -208,6 +230,7 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
   for (int si = 0; si < c.n_scales; ++si) lay.kmax = std::max(lay.kmax, c.scale_log2[si]);
   lay.kc = lay.kmax;
   lay.need_fg = c.fg_filter || c.mask_and_fg;
+  lay.otsu = lay.need_fg && c.tissue_method == OMNISEG_TISSUE_OTSU;
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
     int64_t o = off;
@@ -238,6 +261,16 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
     lay.Wc[i] = ceil_div(slides[i].width, 1 << lay.kc);
     lay.sz_fg[i] = lay.need_fg ? (int64_t)lay.Hc[i] * lay.Wc[i] : 0;
     lay.off_fg[i] = lay.need_fg ? take(lay.sz_fg[i]) : -1;
+    lay.off_tgray[i] = lay.otsu ? take(lay.sz_fg[i]) : -1;
+    lay.off_tstats[i] = lay.otsu ? take(16) : -1;
+  }
+  if (lay.otsu) {
+    int64_t most = 0;
+    for (int i = 0; i < n_slides; ++i) most = std::max(most, lay.sz_fg[i]);
+    lay.off_ttmp = take(most);
+    lay.off_thist = take(256 * 4);
+    lay.off_tlabel = take(most * 4);
+    lay.off_tarea = take(most * 4);
   }
   lay.groups.base[lay.groups.n] = tiles;
   lay.total_tiles = tiles;
@@ -347,7 +380,26 @@ int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, i
     }
     HIP_TRY(launch_pyramid(slides[i].rgb, slides[i].row_pitch, slides[i].height, slides[i].width, pad,
                            lay.kmax, lvl, Ey, Ex, sm));
-    if (lay.need_fg) {
+    if (lay.otsu) {
+      TissueOtsuArgs ta;
+      ta.rgb = slides[i].rgb;
+      ta.pitch = slides[i].row_pitch;
+      ta.sums = lay.kc >= 1 ? lvl[lay.kc] : nullptr;
+      ta.ex = lay.kc >= 1 ? Ex[lay.kc] : 0;
+      ta.kc = lay.kc;
+      ta.Hc = lay.Hc[i];
+      ta.Wc = lay.Wc[i];
+      ta.median = c.median_kernel;
+      ta.min_area = c.min_tissue_area;
+      ta.tmp = reinterpret_cast<uint8_t*>(ws + lay.off_ttmp);
+      ta.gray = reinterpret_cast<uint8_t*>(ws + lay.off_tgray[i]);
+      ta.hist = reinterpret_cast<uint32_t*>(ws + lay.off_thist);
+      ta.stats = reinterpret_cast<int32_t*>(ws + lay.off_tstats[i]);
+      ta.label = reinterpret_cast<int32_t*>(ws + lay.off_tlabel);
+      ta.area = reinterpret_cast<int32_t*>(ws + lay.off_tarea);
+      ta.fg = reinterpret_cast<uint8_t*>(ws + lay.off_fg[i]);
+      HIP_TRY(launch_tissue_otsu(ta, sm));
+    } else if (lay.need_fg) {
       const uint16_t* sums = lay.kc >= 1 ? lvl[lay.kc] : nullptr;
       const int ex = lay.kc >= 1 ? Ex[lay.kc] : 0;
       HIP_TRY(launch_tissue(slides[i].rgb, slides[i].row_pitch, slides[i].height, slides[i].width, pad,
@@ -364,7 +416,13 @@ int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, i
   HIP_TRY(prof.end(OMNISEG_STAGE_PREP, -1, 0, 0.0, prep_bytes));
   int32_t n_kept = 0;
   HIP_TRY(hipMemcpyAsync(&n_kept, count, sizeof(int32_t), hipMemcpyDeviceToHost, sm));
+  int32_t tstats[OMNISEG_MAX_SLIDES][4] = {};
+  if (lay.otsu)
+    for (int i = 0; i < n_slides; ++i)
+      HIP_TRY(hipMemcpyAsync(tstats[i], ws + lay.off_tstats[i], 16, hipMemcpyDeviceToHost, sm));
   HIP_TRY(hipStreamSynchronize(sm));
+  for (int i = 0; i < n_slides; ++i)
+    if (tstats[i][3]) return fail(OMNISEG_ERR_HIP, "slide %d: tissue component labelling did not converge", i);
   if (n_kept < 0 || n_kept > lay.total_tiles)
     return fail(OMNISEG_ERR_HIP, "kept-tile count %d outside [0, %d]", n_kept, lay.total_tiles);
   *n_kept_out = n_kept;
@@ -774,6 +832,16 @@ int32_t omniseg_workspace_region(const omniseg_plan* plan, const omniseg_slide* 
     case OMNISEG_REGION_TILE_LOGITS:
       *offset = lay.off_logits;
       *bytes = lay.sz_logits;
+      return OMNISEG_OK;
+    case OMNISEG_REGION_TISSUE_GRAY:
+      if (index < 0 || index >= n_slides) break;
+      *offset = lay.otsu ? lay.off_tgray[index] : 0;
+      *bytes = lay.otsu ? lay.sz_fg[index] : 0;
+      return OMNISEG_OK;
+    case OMNISEG_REGION_TISSUE_STATS:
+      if (index < 0 || index >= n_slides) break;
+      *offset = lay.otsu ? lay.off_tstats[index] : 0;
+      *bytes = lay.otsu ? 16 : 0;
       return OMNISEG_OK;
     default:
       return fail(OMNISEG_ERR_ARG, "unknown region %d", region);

@@ -78,6 +78,24 @@ hipError_t launch_tissue(const uint8_t* rgb, int64_t pitch, int H, int W, const 
                          uint8_t* fg, hipStream_t st);
 hipError_t launch_tile_flags(const TileGroups& g, const SlideDev* slides_dev, int T, int kc,
                              int fg_filter, int32_t* flags, hipStream_t st);
+// Otsu tissue detection of one slide on the coarse scale kc (k_tissue.hip).
+struct TissueOtsuArgs {
+  const uint8_t* rgb;     // the 40x slide (read when kc == 0)
+  int64_t pitch;
+  const uint16_t* sums;   // box sums of scale kc (kc >= 1), row pitch ex pixels
+  int ex;
+  int kc, Hc, Wc;
+  int median;             // odd median kernel size; 1 = no blur
+  int min_area;           // smallest kept 8-connected component, in coarse pixels
+  uint8_t* tmp;           // Hc*Wc: the gray map before the blur (median > 1)
+  uint8_t* gray;          // Hc*Wc: the blurred gray map
+  uint32_t* hist;         // 256 counts
+  int32_t* stats;         // threshold, components, kept components, error flag
+  int32_t* label;         // Hc*Wc
+  int32_t* area;          // Hc*Wc
+  uint8_t* fg;            // Hc*Wc: the tissue map
+};
+hipError_t launch_tissue_otsu(const TissueOtsuArgs& a, hipStream_t st);
 hipError_t launch_compact(int32_t* flags_to_index, int total, const TileGroups& g,
                           int32_t* list, int32_t* count, hipStream_t st);
 

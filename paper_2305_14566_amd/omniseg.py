@@ -19,9 +19,10 @@ FLAG_EMIT_LOGITS = 1
 FLAG_TRAINING = 2
 FLAG_GRAPH = 4
 MERGE_RAMP, MERGE_VOTE = 0, 1
+TISSUE_GRAY, TISSUE_OTSU = 0, 1
 (REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
- REGION_TILE_INDEX, REGION_TILE_LOGITS) = range(7)
-ABI_VERSION = 5
+ REGION_TILE_INDEX, REGION_TILE_LOGITS, REGION_TISSUE_GRAY, REGION_TISSUE_STATS) = range(9)
+ABI_VERSION = 6
 
 CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
 N_CONV_CONFIGS = 11
@@ -56,6 +57,9 @@ class Config(ctypes.Structure):
         ("scale_stride", ctypes.c_int32 * 4),
         ("merge", ctypes.c_int32),
         ("vote_threshold", ctypes.c_int32 * 4),
+        ("tissue_method", ctypes.c_int32),
+        ("median_kernel", ctypes.c_int32),
+        ("min_tissue_area", ctypes.c_int32),
     ]
 
 
@@ -170,7 +174,8 @@ class Plan:
     def __init__(self, base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
                  stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False,
                  precision=FP32, emit_logits=False, batch_tiles=0, training=False, graph=False,
-                 max_kept_tiles=0, scale_strides=None, merge=MERGE_RAMP, vote_thresholds=None):
+                 max_kept_tiles=0, scale_strides=None, merge=MERGE_RAMP, vote_thresholds=None,
+                 tissue_method=TISSUE_GRAY, median_kernel=1, min_tissue_area=0):
         c = Config()
         c.abi_version = ABI_VERSION
         c.base_channels = base
@@ -193,6 +198,9 @@ class Plan:
         for i, v in enumerate(scale_strides or ()):
             c.scale_stride[i] = v
         c.merge = merge
+        c.tissue_method = tissue_method
+        c.median_kernel = median_kernel
+        c.min_tissue_area = min_tissue_area
         for i, v in enumerate(vote_thresholds or ()):
             c.vote_threshold[i] = v
         self.cfg = c

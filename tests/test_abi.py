@@ -251,6 +251,34 @@ def test_merge_and_stride_validation(case):
     assert e.value.status == (2 if case.startswith("train") else 1)
 
 
+@pytest.mark.parametrize("case", ["method", "even_median", "big_median", "area"])
+def test_tissue_validation(case):
+    kw = dict(base=4, levels=2, head_out=1, n_classes=1, scales=(0, 2), tile=64, stride=32, fg_filter=True,
+              tissue_method=om.TISSUE_OTSU, median_kernel=9, min_tissue_area=10)
+    om.Plan(**kw)
+    kw.update({"method": dict(tissue_method=2), "even_median": dict(median_kernel=8),
+               "big_median": dict(median_kernel=257), "area": dict(min_tissue_area=-1)}[case])
+    with pytest.raises(om.OmnisegError) as e:
+        om.Plan(**kw)
+    assert e.value.status == 1
+
+
+def test_tissue_regions_follow_the_method():
+    lib = om.lib()
+    sl = _slides([(300, 517), (129, 64)])
+    pr = _pairs([(0, 0)])
+    for method, want in [(om.TISSUE_GRAY, 0), (om.TISSUE_OTSU, 1)]:
+        p = om.Plan(base=4, levels=2, head_out=1, n_classes=1, scales=(0, 2), tile=64, stride=32, fg_filter=True,
+                    tissue_method=method, median_kernel=5)
+        off, nb = ctypes.c_int64(), ctypes.c_int64()
+        assert lib.omniseg_workspace_region(p._h, sl, 2, pr, 1, om.REGION_TISSUE_GRAY, 1, ctypes.byref(off),
+                                            ctypes.byref(nb)) == 0
+        assert nb.value == want * 33 * 16  # the 10x map of the 129 x 64 slide
+        assert lib.omniseg_workspace_region(p._h, sl, 2, pr, 1, om.REGION_TISSUE_STATS, 0, ctypes.byref(off),
+                                            ctypes.byref(nb)) == 0
+        assert nb.value == want * 16
+
+
 def test_tile_grid_size_guard():
     """A tile grid of more than 32767 tiles per side is refused before any HIP call."""
     p = om.Plan(base=4, levels=2, head_out=1, n_classes=1, scales=(0,), tile=16, stride=1)

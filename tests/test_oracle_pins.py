@@ -342,6 +342,100 @@ def test_head_against_torch_1x1_convs():
     assert np.allclose(O.head(F, theta1, 1), z[0], rtol=0, atol=1e-12)
 
 
+# ---------------------------------------------------------------- O3b Otsu tissue detection
+
+def test_gray8_is_rounded_gray_of_the_block_mean():
+    from fractions import Fraction
+    rng = np.random.default_rng(31)
+    for kc in (0, 1, 2):
+        img = rng.integers(0, 256, size=(9, 7, 3)).astype(np.uint8)
+        g = O.gray8(img, kc)
+        f = 2 ** kc
+        P = O.padded_slide(img, O.level_size(9, kc) * f, O.level_size(7, kc) * f)
+        for y in range(g.shape[0]):
+            for x in range(g.shape[1]):
+                blk = P[y * f:(y + 1) * f, x * f:(x + 1) * f].astype(int)
+                v = Fraction(299 * int(blk[..., 0].sum()) + 587 * int(blk[..., 1].sum()) +
+                             114 * int(blk[..., 2].sum()), 1000 * f * f)
+                assert g[y, x] == math.floor(v + Fraction(1, 2))  # half rounds up
+                assert 0 <= g[y, x] <= 255
+
+
+@pytest.mark.parametrize("m", [1, 3, 5, 9, 15])
+def test_median_blur_against_scipy(m):
+    import scipy.ndimage as nd
+    rng = np.random.default_rng(32 + m)
+    g = rng.integers(0, 256, size=(23, 31)).astype(np.int64)
+    assert np.array_equal(O.median_blur(g, m), nd.median_filter(g, size=m, mode="nearest"))
+    assert np.array_equal(O.median_blur(np.full((5, 6), 77), m), np.full((5, 6), 77))
+
+
+def test_otsu_minimises_within_class_variance_exactly():
+    """Otsu's split maximises the between-class variance, so it minimises the
+    within-class variance; checked with exact rationals on small images."""
+    from fractions import Fraction
+    rng = np.random.default_rng(33)
+    for trial in range(12):
+        n = int(rng.integers(20, 60))
+        g = np.concatenate([rng.integers(40, 120, size=n), rng.integers(100, 230, size=2 * n)])
+        t = O.otsu_threshold(g)
+        vals = [int(v) for v in g]
+
+        def within(tt):
+            a = [v for v in vals if v <= tt]
+            b = [v for v in vals if v > tt]
+            ma, mb = Fraction(sum(a), len(a)), Fraction(sum(b), len(b))
+            return sum((v - ma) ** 2 for v in a) + sum((v - mb) ** 2 for v in b)
+        cands = [tt for tt in range(min(vals), max(vals))]
+        best = min(within(tt) for tt in cands)
+        assert within(t) == best, trial
+        # the first minimiser among splits that change the classes
+        assert t == min(tt for tt in cands if within(tt) == best and (tt in vals))
+
+
+def test_otsu_closed_forms_and_shift():
+    assert O.otsu_threshold(np.array([17] * 10 + [201] * 4)) == 17  # every t in [17, 200] ties: first wins
+    assert O.otsu_threshold(np.full((4, 4), 99)) == -1  # a single value: no split
+    rng = np.random.default_rng(34)
+    g = np.concatenate([rng.integers(30, 90, 300), rng.integers(150, 200, 500)])
+    assert O.otsu_threshold(g + 25) == O.otsu_threshold(g) + 25
+    # every split between the two separated clusters ties; the first is the lower cluster's top
+    assert O.otsu_threshold(g) == g[g < 120].max()
+
+
+def test_components8_against_scipy_label():
+    import scipy.ndimage as nd
+    rng = np.random.default_rng(35)
+    for p in (0.3, 0.45, 0.6):
+        mask = rng.uniform(size=(40, 53)) < p
+        lab, sizes = O.components8(mask)
+        ref, n = nd.label(mask, structure=np.ones((3, 3), int))
+        assert len(sizes) == n
+        for k in range(1, n + 1):
+            ys, xs = np.nonzero(ref == k)
+            root = int((ys * 53 + xs).min())
+            assert np.all(lab[ref == k] == root) and sizes[root] == len(ys)
+        assert np.all(lab[~mask] == -1)
+
+
+def test_tissue_map_otsu_area_filter_and_agreement():
+    # two blobs of 12 and 3 coarse pixels and a diagonal pair (8-connected)
+    img = np.full((10, 12, 3), 240, np.uint8)
+    img[1:4, 1:5] = 90
+    img[6, 6:9] = 90
+    img[8, 1] = img[9, 2] = 90
+    fg, b, (t, comps, kept) = O.tissue_map_otsu(img, 0, 1, 3)
+    assert 90 <= t < 240 and comps == 3 and kept == 2
+    assert fg.sum() == 15 and not fg[8, 1] and not fg[9, 2]
+    fg, _, (_, _, kept) = O.tissue_map_otsu(img, 0, 1, 0)
+    assert kept == 3 and fg.sum() == 17
+    # on the synthetic strip the Otsu map agrees with the fixed gray threshold almost everywhere
+    rgb, _ = synth.strip_slide(2, 1024, 1024, fg_frac=0.3)
+    fg, _, (t, comps, kept) = O.tissue_map_otsu(rgb, 3, 9, 20)
+    assert 150 < t < 235 and kept >= 1
+    assert (fg == O.tissue_map(rgb, 3)).mean() > 0.99
+
+
 # ---------------------------------------------------------------- O10 stitch
 
 def _full_grid(H, T, s):
