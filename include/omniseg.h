@@ -367,6 +367,60 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
                              int64_t ws_bytes, omniseg_stream stream);
 
 /*
+ * Merge of each class's result to the 40x base (Section 2.3: one merged 40x
+ * prediction per tissue type; Section 1: each tissue type has its own best
+ * magnification, e.g. 5x glomeruli, 10x tubules, 40x capillaries).
+ * height, width: the 40x slide, in [1, 2^20].  Plane i has scale k =
+ * scale_log2 in [0, 3] and size ceil(height / 2^k) x ceil(width / 2^k):
+ *   OMNISEG_UPSAMPLE_NEAREST   out(y, x) = mask(y >> k, x >> k) != 0
+ *   OMNISEG_UPSAMPLE_BILINEAR  out(y, x) = bilinear(logit)(y, x) > 0, sampling
+ *                              at max(0, (y + 0.5) / 2^k - 0.5) (the same on
+ *                              x) with the upper neighbour clamped to the
+ *                              plane; weights are exact, the sum is FP32
+ * mask: device uint8, logit: device float (the one the mode reads; the other
+ * may be NULL), rows `pitch` elements apart; out: device uint8 [height]
+ * [width], rows out_pitch bytes apart.  1 <= n_planes <= 16.
+ */
+#define OMNISEG_UPSAMPLE_NEAREST 0
+#define OMNISEG_UPSAMPLE_BILINEAR 1
+typedef struct omniseg_base_plane {
+  const uint8_t* mask;
+  const float* logit;
+  int64_t pitch;
+  int32_t scale_log2;
+  int32_t mode;
+  uint8_t* out;
+  int64_t out_pitch;
+} omniseg_base_plane;
+int32_t omniseg_merge_to_base(int32_t height, int32_t width, const omniseg_base_plane* planes,
+                              int32_t n_planes, omniseg_stream stream);
+
+/*
+ * Colour mapping of the merged results on the 40x slide (Section 2.3: the
+ * tissue types are stained in different colours on the WSI, and the 10x
+ * result is a resize of the 40x one).  For each pixel, every class whose
+ * mask is on blends its colour in class order:
+ *   out = (out * (256 - alpha) + rgb * alpha + 128) >> 8  per channel,
+ * starting from the slide's pixel (exact integers).  The mask of class i is
+ * read at its scale: mask(y >> k, x >> k), k = scale_log2 in [0, 3] (k = 0
+ * for a merged 40x mask).  out: device uint8 HWC [height][width][3], rows
+ * out_pitch bytes apart (it may be the slide itself).  out10: NULL, or
+ * device uint8 HWC [ceil(height / 4)][ceil(width / 4)][3] receiving the
+ * rounded (half up) mean of each 4 x 4 block of `out` inside the slide.
+ * 0 <= n_classes <= 16; alpha in [0, 256].
+ */
+typedef struct omniseg_overlay_class {
+  const uint8_t* mask;
+  int64_t pitch;
+  int32_t scale_log2;
+  int32_t alpha;
+  uint8_t rgb[4]; /* R, G, B, unused */
+} omniseg_overlay_class;
+int32_t omniseg_overlay(const omniseg_slide* slide, const omniseg_overlay_class* classes,
+                        int32_t n_classes, uint8_t* out, int64_t out_pitch, uint8_t* out10,
+                        int64_t out10_pitch, omniseg_stream stream);
+
+/*
  * Stand-alone 3x3 convolution of the backbone (verification and reuse).
  * Tensors are NHWC over n images, channels padded to a multiple of 32 with
  * zeros in the padding; element type FP32 or BF16 (precision).  Zero padding

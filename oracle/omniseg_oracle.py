@@ -748,6 +748,66 @@ def fg_at_scale(fg, kc, k, H_k, W_k):
 
 
 # --------------------------------------------------------------------------
+# O12  merge to the 40x base and colour mapping (Section 2.3; per-class
+#      magnifications in Section 1)
+# --------------------------------------------------------------------------
+
+
+def upsample_nearest(mask_k, k, H, W):
+    """40x mask from a scale-k mask: each value covers its 2^k x 2^k block."""
+    f = 2 ** k
+    return np.repeat(np.repeat(np.asarray(mask_k) != 0, f, axis=0), f, axis=1)[:H, :W]
+
+
+def upsample_bilinear(lam_k, k, H, W):
+    """Bilinear sample of a scale-k plane at the 40x pixel centres: source
+    coordinate max(0, (y + 0.5) / 2^k - 0.5), the upper neighbour clamped to
+    the plane; FP64."""
+    f = 2.0 ** k
+    L = np.asarray(lam_k, dtype=np.float64)
+    Hk, Wk = L.shape
+
+    def axis(n, nk):
+        src = np.maximum(0.0, (np.arange(n) + 0.5) / f - 0.5)
+        i0 = np.floor(src).astype(np.int64)
+        i1 = np.minimum(i0 + 1, nk - 1)
+        return i0, i1, src - i0
+
+    y0, y1, ly = axis(H, Hk)
+    x0, x1, lx = axis(W, Wk)
+    ly, lx = ly[:, None], lx[None, :]
+    top = (1 - lx) * L[np.ix_(y0, x0)] + lx * L[np.ix_(y0, x1)]
+    bot = (1 - lx) * L[np.ix_(y1, x0)] + lx * L[np.ix_(y1, x1)]
+    return (1 - ly) * top + ly * bot
+
+
+def overlay(rgb, classes):
+    """Colour mapping: for every class (mask at scale k, colour, alpha in
+    [0, 256]) whose mask is on, in order: out = (out (256 - a) + c a + 128) >> 8."""
+    H, W, _ = rgb.shape
+    out = rgb.astype(np.int64)
+    for (mask_k, k, col, a) in classes:
+        on = upsample_nearest(mask_k, k, H, W)
+        blended = (out * (256 - a) + np.asarray(col, np.int64) * a + 128) >> 8
+        out = np.where(on[..., None], blended, out)
+    return out.astype(np.uint8)
+
+
+def map_10x(img):
+    """The 10x map from the 40x one: the rounded (half up) mean of each 4 x 4
+    block, over the block's pixels that lie inside the image."""
+    H, W, C = img.shape
+    Hb, Wb = -(-H // 4), -(-W // 4)
+    out = np.zeros((Hb, Wb, C), np.uint8)
+    for by in range(Hb):
+        for bx in range(Wb):
+            blk = img[4 * by:4 * by + 4, 4 * bx:4 * bx + 4].astype(np.int64).reshape(-1, C)
+            n = blk.shape[0]
+            out[by, bx] = (blk.sum(axis=0) + n // 2) // n
+    return out
+
+
+# --------------------------------------------------------------------------
 # whole path
 # --------------------------------------------------------------------------
 

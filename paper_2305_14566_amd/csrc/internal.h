@@ -78,6 +78,41 @@ hipError_t launch_tissue(const uint8_t* rgb, int64_t pitch, int H, int W, const 
                          uint8_t* fg, hipStream_t st);
 hipError_t launch_tile_flags(const TileGroups& g, const SlideDev* slides_dev, int T, int kc,
                              int fg_filter, int32_t* flags, hipStream_t st);
+// Merge of per-class planes to the 40x base, and the colour overlay (k_map.hip).
+struct MergePlane {
+  const uint8_t* mask;   // nearest: the scale-k mask
+  const float* logit;    // bilinear: the scale-k logit plane
+  int64_t pitch;         // source row pitch in elements
+  int k, Hk, Wk;
+  int bilinear;
+  uint8_t* out;          // the 40x mask
+  int64_t out_pitch;
+};
+struct MergeArgs {
+  int H, W;
+  MergePlane plane[OMNISEG_MAX_CLASSES];
+};
+hipError_t launch_merge_base(const MergeArgs& a, int n_planes, hipStream_t st);
+struct OverlayClass {
+  const uint8_t* mask;   // mask at scale k
+  int64_t pitch;
+  int k;
+  int alpha;             // [0, 256]
+  int rgb[3];
+};
+struct OverlayArgs {
+  const uint8_t* rgb;
+  int64_t pitch;
+  int H, W;
+  int n;
+  OverlayClass cls[OMNISEG_MAX_CLASSES];
+  uint8_t* out;
+  int64_t out_pitch;
+  uint8_t* out10;        // optional 4x4 box-mean map
+  int64_t out10_pitch;
+};
+hipError_t launch_overlay(const OverlayArgs& a, hipStream_t st);
+
 // Otsu tissue detection of one slide on the coarse scale kc (k_tissue.hip).
 struct TissueOtsuArgs {
   const uint8_t* rgb;     // the 40x slide (read when kc == 0)

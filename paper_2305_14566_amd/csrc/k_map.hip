@@ -1,0 +1,98 @@
+// Slide-wise aggregation and mapping (Section 2.3; the per-class optimal
+// magnifications are named in Section 1).
+//
+// Merge to 40x: each class's stitched result at its own scale k becomes one
+// 40x mask.  NEAREST repeats the scale-k mask over 2^k x 2^k blocks.
+// BILINEAR samples the scale-k logit plane at the 40x pixel centres
+// (source coordinate max(0, (y + 0.5) / 2^k - 0.5), neighbours clamped to
+// the plane) and thresholds the value at 0.  The interpolation weights are
+// dyadic fractions, exact in FP32.
+//
+// Overlay: every class whose mask is on at a pixel blends its colour into
+// the 40x RGB, in class order, out = (out (256 - a) + colour a + 128) >> 8
+// per channel (a in [0, 256]; exact integers).  The optional 10x map is the
+// rounded mean of each 4 x 4 block of the overlay that lies inside the
+// slide, from the same thread that wrote the block.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace omniseg {
+
+__global__ __launch_bounds__(256) void k_merge_base(MergeArgs a) {
+  const MergePlane& p = a.plane[blockIdx.z];
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= a.W) return;
+  const int k = p.k;
+  for (int y = blockIdx.y; y < a.H; y += gridDim.y) {
+    uint8_t m;
+    if (p.bilinear) {
+      const float inv = 1.0f / (float)(2 << k);  // 1 / 2^(k+1), exact
+      const float sy = fmaxf(0.f, (float)(2 * y + 1 - (1 << k)) * inv);
+      const float sx = fmaxf(0.f, (float)(2 * x + 1 - (1 << k)) * inv);
+      const int y0 = (int)sy, x0 = (int)sx;
+      const int y1 = min(y0 + 1, p.Hk - 1), x1 = min(x0 + 1, p.Wk - 1);
+      const float ly = sy - (float)y0, lx = sx - (float)x0;
+      const float* r0 = p.logit + (int64_t)y0 * p.pitch;
+      const float* r1 = p.logit + (int64_t)y1 * p.pitch;
+      const float top = (1.f - lx) * r0[x0] + lx * r0[x1];
+      const float bot = (1.f - lx) * r1[x0] + lx * r1[x1];
+      m = ((1.f - ly) * top + ly * bot) > 0.f ? 1 : 0;
+    } else {
+      m = p.mask[(int64_t)(y >> k) * p.pitch + (x >> k)] ? 1 : 0;
+    }
+    p.out[(int64_t)y * p.out_pitch + x] = m;
+  }
+}
+
+hipError_t launch_merge_base(const MergeArgs& a, int n_planes, hipStream_t st) {
+  if (n_planes <= 0 || a.H <= 0 || a.W <= 0) return hipSuccess;
+  const dim3 grid(ceil_div(a.W, 256), std::min(a.H, kMaxGridY), n_planes);
+  hipLaunchKernelGGL(k_merge_base, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// One thread per 4 x 4 block of the 40x slide.
+__global__ __launch_bounds__(256) void k_overlay(OverlayArgs a) {
+  const int bx = blockIdx.x * 256 + threadIdx.x;
+  const int Wb = (a.W + 3) >> 2, Hb = (a.H + 3) >> 2;
+  if (bx >= Wb) return;
+  for (int by = blockIdx.y; by < Hb; by += gridDim.y) {
+    int sum[3] = {0, 0, 0}, cnt = 0;
+    for (int i = 0; i < 4; ++i) {
+      const int y = 4 * by + i;
+      if (y >= a.H) break;
+      const uint8_t* src = a.rgb + (int64_t)y * a.pitch;
+      uint8_t* dst = a.out + (int64_t)y * a.out_pitch;
+      for (int j = 0; j < 4; ++j) {
+        const int x = 4 * bx + j;
+        if (x >= a.W) break;
+        int px[3] = {src[3 * x], src[3 * x + 1], src[3 * x + 2]};
+        for (int c = 0; c < a.n; ++c) {
+          const OverlayClass& oc = a.cls[c];
+          if (!oc.mask[(int64_t)(y >> oc.k) * oc.pitch + (x >> oc.k)]) continue;
+          for (int ch = 0; ch < 3; ++ch) px[ch] = (px[ch] * (256 - oc.alpha) + oc.rgb[ch] * oc.alpha + 128) >> 8;
+        }
+        for (int ch = 0; ch < 3; ++ch) {
+          dst[3 * x + ch] = (uint8_t)px[ch];
+          sum[ch] += px[ch];
+        }
+        ++cnt;
+      }
+    }
+    if (a.out10) {
+      uint8_t* d = a.out10 + (int64_t)by * a.out10_pitch + 3 * bx;
+      for (int ch = 0; ch < 3; ++ch) d[ch] = (uint8_t)((sum[ch] + cnt / 2) / cnt);
+    }
+  }
+}
+
+hipError_t launch_overlay(const OverlayArgs& a, hipStream_t st) {
+  if (a.H <= 0 || a.W <= 0) return hipSuccess;
+  const int Wb = (a.W + 3) >> 2, Hb = (a.H + 3) >> 2;
+  const dim3 grid(ceil_div(Wb, 256), std::min(Hb, kMaxGridY));
+  hipLaunchKernelGGL(k_overlay, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace omniseg

@@ -19,6 +19,7 @@ FLAG_EMIT_LOGITS = 1
 FLAG_TRAINING = 2
 FLAG_GRAPH = 4
 MERGE_RAMP, MERGE_VOTE = 0, 1
+UPSAMPLE_NEAREST, UPSAMPLE_BILINEAR = 0, 1
 TISSUE_GRAY, TISSUE_OTSU = 0, 1
 (REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
  REGION_TILE_INDEX, REGION_TILE_LOGITS, REGION_TISSUE_GRAY, REGION_TISSUE_STATS) = range(9)
@@ -85,6 +86,17 @@ class Tile(ctypes.Structure):
     _fields_ = [("scale", ctypes.c_int32), ("jy", ctypes.c_int32), ("jx", ctypes.c_int32)]
 
 
+class BasePlane(ctypes.Structure):
+    _fields_ = [("mask", ctypes.c_void_p), ("logit", ctypes.c_void_p), ("pitch", ctypes.c_int64),
+                ("scale_log2", ctypes.c_int32), ("mode", ctypes.c_int32), ("out", ctypes.c_void_p),
+                ("out_pitch", ctypes.c_int64)]
+
+
+class OverlayClass(ctypes.Structure):
+    _fields_ = [("mask", ctypes.c_void_p), ("pitch", ctypes.c_int64), ("scale_log2", ctypes.c_int32),
+                ("alpha", ctypes.c_int32), ("rgb", ctypes.c_uint8 * 4)]
+
+
 class Output(ctypes.Structure):
     _fields_ = [("mask", ctypes.c_void_p), ("logit", ctypes.c_void_p),
                 ("mask_pitch", ctypes.c_int64), ("logit_pitch", ctypes.c_int64)]
@@ -125,6 +137,8 @@ def _declare(lib):
         "omniseg_activation_offset": (i32, [vp, i32, i32, P(i64)]),
         "omniseg_calibrate_fp8": (i32, [vp, vp, P(Slide), i32, P(Pair), i32, i32, vp, vp, i64, vp]),
         "omniseg_pack_weights_fp8": (i32, [vp, vp, vp, vp, vp]),
+        "omniseg_merge_to_base": (i32, [i32, i32, P(BasePlane), i32, vp]),
+        "omniseg_overlay": (i32, [P(Slide), P(OverlayClass), i32, vp, i64, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -419,6 +433,51 @@ def stitch_tiles(tile, stride, height, width, tile_logits, tile_yx, emit_logits=
                                   logit.stride(0) if logit is not None else 0, _ptr(ws), ws.numel(),
                                   _stream(stream)))
     return mask, logit
+
+
+def merge_to_base(height, width, planes, stream=None):
+    """Merge per-class planes to 40x masks.  planes: list of (k, mode, src)
+    with src the scale-k uint8 mask (NEAREST) or float32 logit plane
+    (BILINEAR), 2-D device tensors.  Returns the 40x uint8 masks."""
+    n = len(planes)
+    arr = (BasePlane * n)()
+    outs = []
+    for i, (k, mode, src) in enumerate(planes):
+        out = torch.empty((height, width), dtype=torch.uint8, device=src.device)
+        if mode == UPSAMPLE_BILINEAR:
+            arr[i].logit = src.data_ptr()
+        else:
+            arr[i].mask = src.data_ptr()
+        arr[i].pitch = src.stride(0)
+        arr[i].scale_log2 = k
+        arr[i].mode = mode
+        arr[i].out = out.data_ptr()
+        arr[i].out_pitch = out.stride(0)
+        outs.append(out)
+    _check(lib().omniseg_merge_to_base(height, width, arr, n, _stream(stream)))
+    return outs
+
+
+def overlay(slide, classes, with_10x=True, out=None, stream=None):
+    """Colour overlay of class masks on a 40x slide (uint8 HWC device tensor).
+    classes: list of (mask, k, (r, g, b), alpha).  Returns (out, out10 or None)."""
+    H, W, _ = slide.shape
+    sl = Slide(slide.data_ptr(), H, W, slide.stride(0))
+    arr = (OverlayClass * max(len(classes), 1))()
+    for i, (m, k, rgb, alpha) in enumerate(classes):
+        arr[i].mask = m.data_ptr()
+        arr[i].pitch = m.stride(0)
+        arr[i].scale_log2 = k
+        arr[i].alpha = alpha
+        for ch in range(3):
+            arr[i].rgb[ch] = rgb[ch]
+    if out is None:
+        out = torch.empty((H, W, 3), dtype=torch.uint8, device=slide.device)
+    o10 = torch.empty(((H + 3) // 4, (W + 3) // 4, 3), dtype=torch.uint8, device=slide.device) if with_10x else None
+    _check(lib().omniseg_overlay(ctypes.byref(sl), arr, len(classes), out.data_ptr(), out.stride(0),
+                                 o10.data_ptr() if o10 is not None else None,
+                                 o10.stride(0) if o10 is not None else 0, _stream(stream)))
+    return out, o10
 
 
 def bce_loss(logit, target, valid, with_grad=True, stream=None):

@@ -279,6 +279,31 @@ def test_tissue_regions_follow_the_method():
         assert nb.value == want * 16
 
 
+def test_merge_and_overlay_reject_before_any_hip_call():
+    lib = om.lib()
+    pl = (om.BasePlane * 1)()
+    pl[0].mask, pl[0].pitch, pl[0].scale_log2, pl[0].mode, pl[0].out, pl[0].out_pitch = FAKE, 13, 3, 0, FAKE, 100
+    for field, value in [("scale_log2", 4), ("mode", 2), ("pitch", 12), ("out_pitch", 99)]:
+        bad = (om.BasePlane * 1)()
+        ctypes.memmove(bad, pl, ctypes.sizeof(pl))
+        setattr(bad[0], field, value)
+        assert lib.omniseg_merge_to_base(100, 100, bad, 1, None) == 1, field
+    assert lib.omniseg_merge_to_base(100, 100, pl, 17, None) == 1
+    assert lib.omniseg_merge_to_base(0, 100, pl, 1, None) == 1
+    bl = (om.BasePlane * 1)()
+    ctypes.memmove(bl, pl, ctypes.sizeof(pl))
+    bl[0].mode = 1  # bilinear needs the logit plane
+    assert lib.omniseg_merge_to_base(100, 100, bl, 1, None) == 1
+    sl = om.Slide(FAKE, 100, 80, 240)
+    oc = (om.OverlayClass * 1)()
+    oc[0].mask, oc[0].pitch, oc[0].scale_log2, oc[0].alpha = FAKE, 80, 0, 300
+    assert lib.omniseg_overlay(ctypes.byref(sl), oc, 1, FAKE, 240, None, 0, None) == 1  # alpha > 256
+    oc[0].alpha = 128
+    assert lib.omniseg_overlay(ctypes.byref(sl), oc, 1, FAKE, 239, None, 0, None) == 1  # out pitch
+    assert lib.omniseg_overlay(ctypes.byref(sl), oc, 1, FAKE, 240, FAKE, 59, None) == 1  # 10x pitch
+    assert lib.omniseg_overlay(ctypes.byref(sl), oc, 17, FAKE, 240, None, 0, None) == 1
+
+
 def test_tile_grid_size_guard():
     """A tile grid of more than 32767 tiles per side is refused before any HIP call."""
     p = om.Plan(base=4, levels=2, head_out=1, n_classes=1, scales=(0,), tile=16, stride=1)

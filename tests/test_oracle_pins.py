@@ -619,6 +619,60 @@ def test_per_scale_strides_route_each_slot_to_its_grid():
         assert V.dtype == np.float64 and np.all(V == np.round(V)) and V.max() <= 4
 
 
+# ---------------------------------------------------------------- O12 merge to 40x and mapping
+
+@pytest.mark.parametrize("k,H,W", [(1, 14, 17), (2, 28, 36), (3, 61, 70), (2, 3, 5)])
+def test_upsample_bilinear_against_torch(k, H, W):
+    rng = np.random.default_rng(40 + k)
+    Hk, Wk = O.level_size(H, k), O.level_size(W, k)
+    L = rng.standard_normal((Hk, Wk))
+    ref = tF.interpolate(torch.from_numpy(L)[None, None], scale_factor=2 ** k, mode="bilinear",
+                         align_corners=False)[0, 0].numpy()[:H, :W]
+    assert np.abs(O.upsample_bilinear(L, k, H, W) - ref).max() <= 1e-12
+    assert np.array_equal(O.upsample_bilinear(L, 0, Hk, Wk), L)
+    assert np.allclose(O.upsample_bilinear(np.full((Hk, Wk), -2.5), k, H, W), -2.5, rtol=0, atol=1e-15)
+
+
+def test_upsample_nearest_blocks():
+    rng = np.random.default_rng(44)
+    m = rng.uniform(size=(6, 5)) < 0.5
+    up = O.upsample_nearest(m, 2, 24, 20)
+    # every 4 x 4 block is constant and equal to its source pixel
+    blocks = up.reshape(6, 4, 5, 4)
+    assert np.array_equal(blocks.min(axis=(1, 3)), m) and np.array_equal(blocks.max(axis=(1, 3)), m)
+    assert O.upsample_nearest(m, 2, 22, 19).shape == (22, 19)
+
+
+def test_overlay_closed_forms():
+    rng = np.random.default_rng(45)
+    rgb = rng.integers(0, 256, size=(9, 11, 3)).astype(np.uint8)
+    m1 = rng.uniform(size=(9, 11)) < 0.5
+    m2 = rng.uniform(size=(5, 6)) < 0.5  # at scale 1
+    assert np.array_equal(O.overlay(rgb, []), rgb)
+    assert np.array_equal(O.overlay(rgb, [(m1, 0, (255, 0, 0), 0)]), rgb)  # alpha 0: unchanged
+    full = O.overlay(rgb, [(m1, 0, (10, 200, 30), 256)])  # alpha 256: the colour
+    assert np.all(full[m1] == (10, 200, 30)) and np.array_equal(full[~m1], rgb[~m1])
+    # brute force per pixel, two classes in order (the later one paints over)
+    got = O.overlay(rgb, [(m1, 0, (255, 0, 0), 100), (m2, 1, (0, 0, 255), 180)])
+    for y in range(9):
+        for x in range(11):
+            px = [int(v) for v in rgb[y, x]]
+            for on, col, a in [(m1[y, x], (255, 0, 0), 100), (m2[y // 2, x // 2], (0, 0, 255), 180)]:
+                if on:
+                    px = [(p * (256 - a) + c * a + 128) // 256 for p, c in zip(px, col)]
+            assert list(got[y, x]) == px
+
+
+def test_map_10x_is_the_rounded_block_mean():
+    rng = np.random.default_rng(46)
+    img = rng.integers(0, 256, size=(16, 12, 3)).astype(np.uint8)
+    want = np.floor(img.reshape(4, 4, 3, 4, 3).astype(np.float64).mean(axis=(1, 3)) + 0.5)
+    assert np.array_equal(O.map_10x(img), want.astype(np.uint8))
+    ragged = O.map_10x(img[:14, :9])
+    assert ragged.shape == (4, 3, 3)
+    assert list(ragged[3, 2]) == [int((img[12:14, 8, c].astype(int).sum() + 1) // 2) for c in range(3)]
+
+
 # ---------------------------------------------------------------- whole path on the tiny instance
 
 def test_segment_tiny_instance_runs():
