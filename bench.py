@@ -37,7 +37,13 @@ CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 1, 2, 3), tile
 # The tiling of the paper's experiments (Section 3.2): 512^2 tiles at 40x with
 # stride 256 and vote threshold 1, at 10x and 5x with stride 64 and threshold 4.
 PAPER_CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 2, 3), tile=512, stride=256,
-                 fg_filter=True, scale_strides=(256, 64, 64), vote_thresholds=(1, 4, 4))
+                 fg_filter=True, scale_strides=(256, 64, 64), vote_thresholds=(1, 4, 4),
+                 tissue_method="otsu", median_kernel=59, min_tissue_area=64)
+# Best magnification per class (Section 1: glomeruli 5x, tubules 10x,
+# capillaries 40x; arteries taken at 10x), as scale slots of CFG's 40/20/10/5x:
+# TUFT, CAP, PT, DT, PTC, VES.
+CLASS_SLOT = (3, 3, 2, 2, 0, 2)
+CLASS_COLOURS = ((230, 25, 75), (60, 180, 75), (255, 225, 25), (0, 130, 200), (245, 130, 48), (145, 30, 180))
 
 # HBM bytes per launch of the dominant BF16 conv kernel on this workload, from
 # two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
@@ -132,14 +138,17 @@ def stage_summary(records):
     return out
 
 
-def _plan(om, prec, batch_tiles, cfg=CFG):
+def _plan(om, prec, batch_tiles, cfg=CFG, emit_logits=False):
     vote = "vote_thresholds" in cfg
+    otsu = cfg.get("tissue_method") == "otsu"
     return om.Plan(base=cfg["base"], levels=cfg["levels"], head_out=cfg["head_out"],
                    n_classes=cfg["n_classes"], scales=cfg["scales"], tile=cfg["tile"],
                    stride=cfg["stride"], fg_filter=cfg["fg_filter"],
-                   precision={"bf16": om.BF16, "fp32": om.FP32, "fp8": om.FP8}[prec], emit_logits=False,
+                   precision={"bf16": om.BF16, "fp32": om.FP32, "fp8": om.FP8}[prec], emit_logits=emit_logits,
                    batch_tiles=batch_tiles, scale_strides=cfg.get("scale_strides"),
-                   merge=om.MERGE_VOTE if vote else om.MERGE_RAMP, vote_thresholds=cfg.get("vote_thresholds"))
+                   merge=om.MERGE_VOTE if vote else om.MERGE_RAMP, vote_thresholds=cfg.get("vote_thresholds"),
+                   tissue_method=om.TISSUE_OTSU if otsu else om.TISSUE_GRAY,
+                   median_kernel=cfg.get("median_kernel", 1), min_tissue_area=cfg.get("min_tissue_area", 0))
 
 
 def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles, calib_tiles=64, cfg=CFG):
@@ -186,6 +195,9 @@ def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles
     kept = int(ws[off:off + 4].view(torch.int32).item())
     masks = [m.cpu().numpy().astype(bool) for m in outs[0][0]]
     tuned = sorted({(r["stage"], r["level"], r["config"]) for r in records if r["config"] >= 0})
+    if cfg.get("tissue_method") == "otsu":
+        off, nb = plan.region([dslide], pairs, om.REGION_TISSUE_STATS)
+        extra["tissue_stats"] = [int(v) for v in ws[off:off + nb].view(torch.int32).cpu()]
     return dict(ms=ms, wall_ms=wall * 1e3 / steps, records=records, kept=kept, masks=masks,
                 tuned={f"{st}{l}": list(om.conv_config(c)) for st, l, c in tuned}, tune_s=t_tune, **extra)
 
@@ -210,11 +222,61 @@ def paper_leg(om, torch, M, dslide, size, steps, batch_tiles):
     return {"value": px / (bf["ms"] * 1e-3) / 1e6, "unit": UNIT, "ms_per_step": bf["ms"], "steps": steps,
             "dtype": "bf16", "kept_tiles": bf["kept"], "pairs": len(pairs),
             "workload": f"the {size}x{size} slide, 512 tiles, scales 40x/10x/5x at strides 256/64/64, "
-                        "majority vote with thresholds 1/4/4, 6 classes",
+                        "majority vote with thresholds 1/4/4, 6 classes, Otsu tissue map (5x, median 59, "
+                        "components of < 64 coarse pixels removed)",
+            "tissue_stats": dict(zip(("otsu_threshold", "components", "kept_components"), bf["tissue_stats"][:3])),
+            "prep_ms": stages.get("prep", {}).get("ms"),
             "fp32_ms_per_step": fp["ms"], "speedup_bf16_vs_fp32": fp["ms"] / bf["ms"],
             "bf16_vs_fp32_vote_masks": {"dice_min": min(dices), "dice_mean": float(np.mean(dices))},
             "stitch_ms": stages.get("stitch", {}).get("ms"),
             "roofline": dict(roofline(om, bf["records"], "bf16"), traffic=None)}
+
+
+def mapping_leg(om, torch, dslide, flat_dev, size, reps, batch_tiles):
+    """Slide-wise aggregation and mapping on the bench slide: each class's
+    stitched logits at its best scale merged to a 40x mask (bilinear), then
+    the six-colour overlay on the 40x slide and its 10x map.  Timed with HIP
+    events on the launch stream over `reps` repetitions."""
+    pairs = [(c, si) for si in range(4) for c in range(6)]
+    plan = _plan(om, "bf16", batch_tiles, emit_logits=True)
+    packed = plan.pack(flat_dev)
+    masks, logits, _ = plan.segment([dslide], pairs, packed)
+    torch.cuda.synchronize()
+    H = W = size
+    planes = []
+    for c, si in enumerate(CLASS_SLOT):
+        p = pairs.index((c, si))
+        planes.append((CFG["scales"][si], om.UPSAMPLE_BILINEAR, logits[0][p]))
+    out = torch.empty((H, W, 3), dtype=torch.uint8, device=dslide.device)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    m40 = om.merge_to_base(H, W, planes)
+    om.overlay(dslide, [(m, 0, col, 128) for m, col in zip(m40, CLASS_COLOURS)], out=out)
+    torch.cuda.synchronize()
+    t_merge = t_over = 0.0
+    for _ in range(reps):
+        ev[0].record(stream)
+        m40 = om.merge_to_base(H, W, planes)
+        ev[1].record(stream)
+        _, o10 = om.overlay(dslide, [(m, 0, col, 128) for m, col in zip(m40, CLASS_COLOURS)], out=out)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        t_merge += ev[0].elapsed_time(ev[1]) / reps
+        t_over += ev[1].elapsed_time(ev[2]) / reps
+    px = H * W
+    merge_bytes = sum(4 * ((H + (1 << k) - 1) >> k) * ((W + (1 << k) - 1) >> k) + px for k, _, _ in planes)
+    over_bytes = 3 * px + len(m40) * px + 3 * px + 3 * ((H + 3) // 4) * ((W + 3) // 4)
+    return {"workload": f"the {size}x{size} slide: 6 classes merged to 40x from their best scales "
+                        "(TUFT, CAP 5x; PT, DT, VES 10x; PTC 40x; bilinear on the stitched logits), then the "
+                        "6-colour overlay (alpha 128/256) and its 10x map",
+            "merge_ms": t_merge, "overlay_ms": t_over, "reps": reps,
+            "merge_roofline": dict(bound="hbm", achieved=merge_bytes / (t_merge * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                                   unit="GB/s", frac=merge_bytes / (t_merge * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                   traffic=None, algorithmic_bytes=merge_bytes),
+            "overlay_roofline": dict(bound="hbm", achieved=over_bytes / (t_over * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                                     unit="GB/s", frac=over_bytes / (t_over * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                     traffic=None, algorithmic_bytes=over_bytes),
+            "class_pixels_40x": [int(m.sum().item()) for m in m40]}
 
 
 def train_leg(om, torch, steps, warmup, batch=32):
@@ -459,6 +521,8 @@ def main():
     ap.add_argument("--paper-steps", type=int, default=2,
                     help="leg with the paper's tiling (512 tiles, 40x/10x/5x, strides 256/64/64, "
                          "majority vote 1/4/4), BF16 and one FP32 step for the masks (0 = skip)")
+    ap.add_argument("--map-reps", type=int, default=5,
+                    help="aggregation and mapping leg (merge to 40x + overlay) repetitions (0 = skip)")
     ap.add_argument("--trained-dice-steps", type=int, default=0,
                     help="train the training-step network this many FP32 steps and compare BF16/FP8 masks "
                          "with FP32 on it (0 = skip)")
@@ -558,6 +622,10 @@ def main():
                                        "disagreement_max": max(M.disagreement(a, b)
                                                                for a, b in zip(f8["masks"], fp["masks"]))}
         result["fp8"] = r8
+    if args.map_reps > 0:
+        result["mapping"] = mapping_leg(om, torch, dslide, flat_dev, args.size, args.map_reps, args.batch_tiles)
+        print(f"# mapping: merge {result['mapping']['merge_ms']:.2f} ms, overlay {result['mapping']['overlay_ms']:.2f} ms",
+              file=sys.stderr, flush=True)
     if args.paper_steps > 0:
         result["paper_tiling"] = paper_leg(om, torch, M, dslide, args.size, args.paper_steps, args.batch_tiles)
         print(f"# paper tiling: {result['paper_tiling']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)

@@ -66,8 +66,15 @@ __global__ __launch_bounds__(256) void k_gap(const T* __restrict__ e, int hw, in
   const int ch = cb * 64 + lane;
   float s = 0.f;
   if (ch < c) {
+    // four independent partial sums per lane keep four loads in flight
     const T* base = e + (int64_t)b * hw * c_p + ch;
-    for (int p = wave; p < hw; p += 4) s += ld1(base + (int64_t)p * c_p);
+    float s4[4] = {0.f, 0.f, 0.f, 0.f};
+    int p = wave;
+    for (; p + 12 < hw; p += 16)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s4[u] += ld1(base + (int64_t)(p + 4 * u) * c_p);
+    for (; p < hw; p += 4) s4[0] += ld1(base + (int64_t)p * c_p);
+    s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   }
   part[wave][lane] = s;
   __syncthreads();

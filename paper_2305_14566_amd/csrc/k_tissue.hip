@@ -180,6 +180,21 @@ __device__ __forceinline__ int find_root(const int32_t* parent, int x) {
   return x;
 }
 
+// The same walk with path halving: each visited node is relinked to its
+// grandparent.  A non-root never becomes a root again and the stored value
+// is an ancestor of the node (smaller than it), so concurrent walks, links
+// and relinks keep every parent pointer valid.
+__device__ __forceinline__ int find_root_halving(int32_t* parent, int x) {
+  while (true) {
+    const int p = ld_parent(parent, x);
+    if (p == x) return x;
+    const int gp = ld_parent(parent, p);
+    if (gp == p) return p;
+    __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = gp;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_tissue_label(const uint8_t* __restrict__ g, const int32_t* stats,
                                                       int64_t n, int32_t* __restrict__ label) {
   const int t = stats[0];
@@ -209,8 +224,8 @@ __global__ __launch_bounds__(256) void k_tissue_union(int32_t* label, int Hc, in
       int a = p, b = q;
       bool done = false;
       for (int it = 0; it < (1 << 24) && !done; ++it) {
-        a = find_root(label, a);
-        b = find_root(label, b);
+        a = find_root_halving(label, a);
+        b = find_root_halving(label, b);
         if (a == b) {
           done = true;
         } else {
@@ -233,12 +248,24 @@ __global__ __launch_bounds__(256) void k_tissue_union(int32_t* label, int Hc, in
 __global__ __launch_bounds__(256) void k_tissue_flatten(int32_t* label, int64_t n, int32_t* area,
                                                         int32_t* stats) {
   const int64_t step = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += step) {
-    if (ld_parent(label, (int)i) < 0) continue;
-    const int root = find_root(label, (int)i);
-    __hip_atomic_store(label + i, root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicAdd(area + root, 1);
-    if (root == (int)i) atomicAdd(stats + 1, 1);
+  const int64_t span = (n + step - 1) / step * step;  // whole waves iterate together
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < span; i += step) {
+    int root = -1;
+    if (i < n && ld_parent(label, (int)i) >= 0) {
+      root = find_root_halving(label, (int)i);
+      __hip_atomic_store(label + i, root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (root == (int)i) atomicAdd(stats + 1, 1);
+    }
+    // One atomic for the lanes that share the first tissue lane's root (a
+    // run of one component, the common case); the other lanes add alone.
+    // Every lane of the wave reaches the ballots.
+    const uint64_t tissue = __ballot(root >= 0);
+    if (tissue == 0) continue;
+    const int leader = __ffsll((unsigned long long)tissue) - 1;
+    const int lroot = __shfl(root, leader);
+    const uint64_t same = __ballot(root >= 0 && root == lroot);
+    if (root >= 0 && root != lroot) atomicAdd(area + root, 1);
+    if ((int)(threadIdx.x & 63) == leader) atomicAdd(area + lroot, (int)__popcll(same));
   }
 }
 
