@@ -70,6 +70,13 @@ struct Layout {
   int64_t total = 0;
 };
 
+// The conv kernels address one image's input with 32-bit byte offsets.
+bool per_image_bytes_too_big(int mode, int H, int W, int cin, int precision) {
+  const int64_t es = precision == OMNISEG_FP32 ? 4 : precision == OMNISEG_BF16 ? 2 : 1;
+  const int64_t px = (int64_t)H * W * (mode == OMNISEG_CONV_POOL_RELU ? 4 : 1);
+  return px * ((cin + 31) / 32 * 32) * es >= (1LL << 31);
+}
+
 // Tile stride of scale slot si (scale_stride[si], 0 = the common stride).
 int stride_of(const omniseg_config& c, int si) { return c.scale_stride[si] > 0 ? c.scale_stride[si] : c.stride; }
 
@@ -381,7 +388,7 @@ int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, i
     HIP_TRY(launch_pyramid(slides[i].rgb, slides[i].row_pitch, slides[i].height, slides[i].width, pad,
                            lay.kmax, lvl, Ey, Ex, sm));
     if (lay.otsu) {
-      TissueOtsuArgs ta;
+      TissueOtsuArgs ta{};
       ta.rgb = slides[i].rgb;
       ta.pitch = slides[i].row_pitch;
       ta.sums = lay.kc >= 1 ? lvl[lay.kc] : nullptr;
@@ -732,7 +739,7 @@ int32_t omniseg_calibrate_fp8(const omniseg_plan* plan, const void* packed, cons
     return launch_amax_channels(static_cast<const float*>(x), (int64_t)nb * h * h, plan->Cp[l],
                                 amax + plan->act_off[kind][l], sm);
   };
-  FirstConvArgs fa;
+  FirstConvArgs fa{};
   fa.list = list;
   fa.count = count;
   fa.T = T;
@@ -921,7 +928,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
       return px * in_px_factor * d.cin * es + px * d.cout * es * (res ? 2 : 1) + 9.0 * d.cin * d.cout * es;
     };
     const int B = lay.batch;
-    FirstConvArgs fa;
+    FirstConvArgs fa{};
     fa.list = list;
     fa.count = count;
     fa.T = T;
@@ -1024,7 +1031,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
         const ScaleGeom& gm = lay.geom[i][si];
         const omniseg_output& o = outs[(int64_t)i * n_pairs + p];
         const int gbase = lay.groups.base[i * c.n_scales + si];
-        StitchArgs sa;
+        StitchArgs sa{};
         sa.logits = logits;
         sa.tile_stride = (int64_t)lay.max_slots * T * T;
         sa.slot_off = (int64_t)lay.pair_slot[p] * T * T;
@@ -1278,6 +1285,8 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
       if (pst) return pst;
     }
   }
+  if (per_image_bytes_too_big(mode, height, width, cin, precision))
+    return fail(OMNISEG_ERR_UNSUPPORTED, "one image's input exceeds 2^31 bytes");
   if (ws_bytes < need) return fail(OMNISEG_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OMNISEG_ERR_ARG, "workspace not 256-byte aligned");
   hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
@@ -1378,6 +1387,8 @@ int32_t omniseg_conv3x3_fp8(int32_t mode, int32_t n, int32_t height, int32_t wid
   if (conv_default_config(OMNISEG_FP8, height, width, f.cout_p) < 0)
     return fail(OMNISEG_ERR_UNSUPPORTED, "no FP8 configuration fits %dx%d", height, width);
   if (y_pool && mode != OMNISEG_CONV_RES_RELU) return fail(OMNISEG_ERR_ARG, "a pooled output needs mode RES_RELU");
+  if (per_image_bytes_too_big(mode, height, width, cin, OMNISEG_FP8))
+    return fail(OMNISEG_ERR_UNSUPPORTED, "one image's input exceeds 2^31 bytes");
   if (ws_bytes < need) return fail(OMNISEG_ERR_WORKSPACE, "workspace needs %lld bytes", (long long)need);
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(OMNISEG_ERR_ARG, "workspace not 256-byte aligned");
   hipStream_t sm = reinterpret_cast<hipStream_t>(stream);
@@ -1452,7 +1463,7 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
   (void)hipGetLastError();
   int32_t* grid = static_cast<int32_t*>(workspace);
   HIP_TRY(launch_grid_from_list(tile_yx, n_tiles, ny, nx, grid, sm));
-  StitchArgs sa;
+  StitchArgs sa{};
   sa.logits = tile_logits;
   sa.tile_stride = (int64_t)tile * tile;
   sa.slot_off = 0;

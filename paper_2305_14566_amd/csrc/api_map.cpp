@@ -16,7 +16,7 @@ int32_t omniseg_merge_to_base(int32_t height, int32_t width, const omniseg_base_
     return fail(OMNISEG_ERR_ARG, "size %dx%d outside [1, 2^20]", height, width);
   if (n_planes < 1 || n_planes > OMNISEG_MAX_CLASSES)
     return fail(OMNISEG_ERR_ARG, "n_planes %d outside [1, %d]", n_planes, OMNISEG_MAX_CLASSES);
-  MergeArgs a;
+  MergeArgs a{};
   a.H = height;
   a.W = width;
   for (int i = 0; i < n_planes; ++i) {
@@ -59,7 +59,7 @@ int32_t omniseg_overlay(const omniseg_slide* slide, const omniseg_overlay_class*
   if (n_classes > 0 && !classes) return fail(OMNISEG_ERR_ARG, "classes is NULL");
   if (!out || out_pitch < 3LL * W) return fail(OMNISEG_ERR_ARG, "bad output buffer");
   if (out10 && out10_pitch < 3LL * ceil_div(W, 4)) return fail(OMNISEG_ERR_ARG, "bad 10x output pitch");
-  OverlayArgs a;
+  OverlayArgs a{};
   a.rgb = slide->rgb;
   a.pitch = slide->row_pitch;
   a.H = H;

@@ -229,7 +229,7 @@ int32_t upload_tables(const omniseg_plan* plan, const omniseg_slide* slide, cons
 
 FirstConvArgs first_args(const omniseg_plan* plan, const char* pk, const TrainLayout& lay, char* ws, void* y) {
   const omniseg_config& c = plan->cfg;
-  FirstConvArgs fa;
+  FirstConvArgs fa{};
   fa.list = reinterpret_cast<const int32_t*>(ws + lay.off_list);
   fa.count = reinterpret_cast<const int32_t*>(ws + lay.off_count);
   fa.chunk_base = 0;
@@ -369,7 +369,7 @@ int32_t omniseg_train_forward(const omniseg_plan* plan, const void* packed, cons
   for (int p = 0; p < n_pairs; ++p) {
     const int si = pairs[p].scale;
     const ScaleGeom& gm = lay.geom[si];
-    StitchArgs sa;
+    StitchArgs sa{};
     sa.logits = tlog;
     sa.tile_stride = (int64_t)lay.max_slots * T * T;
     sa.slot_off = (int64_t)lay.pair_slot[p] * T * T;
@@ -433,7 +433,7 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
   float* gw = grad_weights;
 
   // 1. stitch backward
-  StitchBwdArgs sb;
+  StitchBwdArgs sb{};
   sb.dlam = grad_logit;
   sb.dl = reinterpret_cast<float*>(ws + lay.off_dl);
   sb.list = list;
@@ -455,7 +455,7 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
   HIP_TRY(launch_stitch_bwd(sb, sm));
 
   // 2. head and precls backward
-  HeadBwdArgs hb;
+  HeadBwdArgs hb{};
   hb.d0 = L >= 2 ? D[0] : E[0];
   hb.theta = reinterpret_cast<const float*>(ws + lay.off_theta);
   hb.dl = sb.dl;
@@ -479,7 +479,7 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
     HIP_TRY(launch_sum_mid(hb.dwp_part, 1, n * per, 8 * plan->C[0] + 8, gw + plan->canon_pre_w, sm));
 
   // 3. controller backward
-  CtrlBwdArgs cb;
+  CtrlBwdArgs cb{};
   cb.dtheta = dtheta;
   cb.g = reinterpret_cast<const float*>(ws + lay.off_g);
   cb.wc = reinterpret_cast<const float*>(pk + plan->pk_ctrl_w);
@@ -508,7 +508,7 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
 
   auto wgrad = [&](const ConvDesc& d, int loader, int px, const void* x0, const void* x1, const void* dy, int h,
                    int cin_real, int cin_p, int cu, int cu_p, float* dst) -> int32_t {
-    WgradArgs wa;
+    WgradArgs wa{};
     wa.x0 = x0;
     wa.x1 = x1;
     wa.dy = dy;

@@ -235,6 +235,157 @@ struct Stager {
   }
 };
 
+// Buffer resource (gfx9 layout: 48-bit base, stride 0, byte range, default
+// format word) over `bytes` bytes at p.  A buffer load whose offset lies at
+// or beyond the range returns zeros and touches no memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ uint4 buffer_load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+constexpr uint32_t kOutside = 0x80000000u;  // a byte offset beyond every range used here
+
+// Staging for the row-reuse kernels (BF16 and FP8) with the address
+// arithmetic hoisted out of the chunk loop.  A thread's halo vectors sit at
+// fixed pixels and always at vector v = tid % NV of a pixel's chunk, so
+// their byte offsets inside the tile (one per source tensor; kOutside for
+// pixels outside the image, which then load zeros) and its weight vectors'
+// offsets inside a chunk are computed once.  Each chunk builds buffer
+// resources that start at its channel offset and end at the end of the tile
+// (or of the chunk's weights), so a load is one instruction with no branch.
+// Two uniform cases need more: an FP8 chunk (64 channels) that runs past
+// cin_p (multiples of 32) zeroes the vectors beyond it, and an FP8 UPCAT
+// chunk that straddles the end of the upsampled channels issues both loads,
+// one of them outside its range.  A tile holds at most 512^2 pixels x 4096
+// channels x 2 bytes = 2^31 bytes.
+template <typename T, int LOADER, int HALO_V, int W_V, int LPV, int NV, int VEC, int KC, int ROW, int PX, int BN,
+          bool SWZ, int NT>
+struct RowStager {
+  static constexpr int HPT = (HALO_V + NT - 1) / NT;
+  static constexpr int WPT = (W_V + NT - 1) / NT;
+  static_assert(NT % NV == 0, "a thread's halo vectors share one vector slot");
+  const T* x0b;  // this tile's first element in x0
+  const T* x1b;  // and in x1 (UPCAT)
+  uint32_t bytes0, bytes1;
+  uint32_t o0[HPT], o1[HPT], wo[WPT];
+  int vc;  // channel offset of this thread's halo vectors inside a chunk
+  int cu_p, cin_p, chunk_w;
+  uint32_t pool_dx, pool_dy;
+
+  __device__ __forceinline__ RowStager(const ConvArgs& a, int b, int tid, int y0, int x0, int n0) {
+    const int H = a.H, W = a.W;
+    cu_p = a.cu_p;
+    cin_p = a.cin_p;
+    chunk_w = 9 * a.cout_p * KC;
+    pool_dx = (uint32_t)a.cin_p * sizeof(T);
+    pool_dy = (uint32_t)(2 * W) * a.cin_p * sizeof(T);
+    vc = (tid % NV) * VEC;
+    int64_t tile0;
+    if (LOADER == LOAD_POOL) tile0 = (int64_t)4 * H * W * a.cin_p;
+    else if (LOADER == LOAD_UPCAT) tile0 = (int64_t)(H >> 1) * (W >> 1) * a.cu_p;
+    else tile0 = (int64_t)H * W * a.cin_p;
+    x0b = (const T*)a.x0 + (int64_t)b * tile0;
+    bytes0 = (uint32_t)(tile0 * sizeof(T));
+    const int64_t tile1 = (int64_t)H * W * (a.cin_p - a.cu_p);
+    x1b = LOADER == LOAD_UPCAT ? (const T*)a.x1 + (int64_t)b * tile1 : nullptr;
+    bytes1 = (uint32_t)(tile1 * sizeof(T));
+    const uint32_t vb = (uint32_t)(vc * sizeof(T));
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) {
+      const int idx = tid + i * NT;
+      const int p = idx / NV;
+      const int y = y0 + p / PX - 1, x = x0 + p % PX - 1;
+      const bool in = idx < HALO_V && y >= 0 && y < H && x >= 0 && x < W;
+      if (LOADER == LOAD_POOL) {
+        o0[i] = in ? (uint32_t)(((2 * y) * (2 * W) + 2 * x) * a.cin_p) * sizeof(T) + vb : kOutside;
+      } else if (LOADER == LOAD_UPCAT) {
+        o0[i] = in ? (uint32_t)(((y >> 1) * (W >> 1) + (x >> 1)) * a.cu_p) * sizeof(T) + vb : kOutside;
+        o1[i] = in ? (uint32_t)((y * W + x) * (a.cin_p - a.cu_p)) * sizeof(T) + vb : kOutside;
+      } else {
+        o0[i] = in ? (uint32_t)((y * W + x) * a.cin_p) * sizeof(T) + vb : kOutside;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int idx = tid + i * NT;
+      const int v = idx % NV, r = idx / NV;
+      const int tap = r / BN, n = r % BN;
+      wo[i] = idx < W_V ? (uint32_t)(((tap * a.cout_p + n0 + n) * KC + v * VEC) * sizeof(T)) : kOutside;
+    }
+  }
+
+  // Loads of one source over the chunk starting at channel c of it: every
+  // vector at or beyond channel `lim` of the source reads zeros.
+  __device__ __forceinline__ void load_src(const T* base, uint32_t bytes, const uint32_t (&off)[HPT], int c, int lim,
+                                           uint4 (&hreg)[HPT][LPV]) const {
+    const __amdgpu_buffer_rsrc_t r = buffer_rsrc(base + c, bytes - (uint32_t)(c * sizeof(T)));
+    const bool keep = c + vc < lim;
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) {
+      const uint32_t o = keep ? off[i] : kOutside;
+      hreg[i][0] = buffer_load16(r, o);
+      if (LOADER == LOAD_POOL) {
+        hreg[i][LPV > 1 ? 1 : 0] = buffer_load16(r, o + pool_dx);
+        hreg[i][LPV > 2 ? 2 : 0] = buffer_load16(r, o + pool_dy);
+        hreg[i][LPV > 3 ? 3 : 0] = buffer_load16(r, o + pool_dy + pool_dx);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void fetch(const ConvArgs& a, int ch, uint4 (&hreg)[HPT][LPV], uint4 (&wreg)[WPT]) const {
+    const int c = ch * KC;
+    if (LOADER == LOAD_UPCAT) {
+      if (c + KC <= cu_p) {
+        load_src(x0b, bytes0, o0, c, cu_p, hreg);
+      } else if (c >= cu_p) {
+        load_src(x1b, bytes1, o1, c - cu_p, cin_p - cu_p, hreg);
+      } else {  // the chunk straddles the end of the upsampled channels (FP8 only)
+        uint4 h1[HPT][LPV];
+        load_src(x0b, bytes0, o0, c, cu_p, hreg);
+        const __amdgpu_buffer_rsrc_t r1 = buffer_rsrc(x1b, bytes1);
+        const bool second = c + vc >= cu_p && c + vc < cin_p;
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+          const bool use = second && o1[i] != kOutside;
+          h1[i][0] = buffer_load16(r1, use ? o1[i] + (uint32_t)((c - cu_p) * (int)sizeof(T)) : kOutside);
+          hreg[i][0] = make_uint4(hreg[i][0].x | h1[i][0].x, hreg[i][0].y | h1[i][0].y, hreg[i][0].z | h1[i][0].z,
+                                  hreg[i][0].w | h1[i][0].w);
+        }
+      }
+    } else {
+      load_src(x0b, bytes0, o0, c, cin_p, hreg);
+    }
+    const __amdgpu_buffer_rsrc_t rw = buffer_rsrc((const T*)a.w + (int64_t)ch * chunk_w, (uint32_t)(chunk_w * sizeof(T)));
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) wreg[i] = buffer_load16(rw, wo[i]);
+  }
+
+  __device__ __forceinline__ static void commit(int tid, const uint4 (&hreg)[HPT][LPV], const uint4 (&wreg)[WPT],
+                                                T* sX, T* sW) {
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) {
+      const int idx = tid + i * NT;
+      if (idx < HALO_V) {
+        const int p = idx / NV, v = idx % NV;
+        uint4 val = hreg[i][0];
+        if (LPV == 4)
+          val = vmax(vmax(hreg[i][0], hreg[i][LPV > 1 ? 1 : 0], T()),
+                     vmax(hreg[i][LPV > 2 ? 2 : 0], hreg[i][LPV > 3 ? 3 : 0], T()), T());
+        *reinterpret_cast<uint4*>(&sX[p * ROW + vslot<SWZ>(p, v) * VEC]) = val;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int idx = tid + i * NT;
+      if (idx < W_V) {
+        const int v = idx % NV, r = idx / NV;
+        *reinterpret_cast<uint4*>(&sW[r * ROW + vslot<SWZ>(r, v) * VEC]) = wreg[i];
+      }
+    }
+  }
+};
+
 template <typename T, int BY, int BX, int BN, int WM, int WN, int LOADER, int EPI>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
   using TR = ConvTraits<T>;
@@ -414,12 +565,16 @@ void k_conv3x3_rows(ConvArgs a) {
   uint4 hreg[HPT][LPV];
   uint4 wreg[WPT];
   const int nchunks = a.cin_p / KC;
-  using ST = Stager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN, true, NT>;
-  ST::fetch(a, b, tid, y0, x0, n0, 0, hreg, wreg);
+  using ST = RowStager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN, true, NT>;
+  const ST st(a, b, tid, y0, x0, n0);
+  st.fetch(a, 0, hreg, wreg);
   ST::commit(tid, hreg, wreg, sX, sW);
   __syncthreads();
+  // The loop body has no branch (the last pass fetches and commits its own
+  // chunk again, unused), so the scheduler can interleave the next chunk's
+  // loads and the LDS address arithmetic with the MFMAs.
   for (int ch = 0; ch < nchunks; ++ch) {
-    if (ch + 1 < nchunks) ST::fetch(a, b, tid, y0, x0, n0, ch + 1, hreg, wreg);
+    st.fetch(a, min(ch + 1, nchunks - 1), hreg, wreg);
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
       uint4 xv[FM + 2];
@@ -444,10 +599,8 @@ void k_conv3x3_rows(ConvArgs a) {
       }
     }
     __syncthreads();
-    if (ch + 1 < nchunks) {
-      ST::commit(tid, hreg, wreg, sX, sW);
-      __syncthreads();
-    }
+    ST::commit(tid, hreg, wreg, sX, sW);
+    __syncthreads();
   }
 
   // Epilogue: accumulators -> LDS [pixel][channel] (FP32) -> 16-byte rows.
@@ -622,12 +775,14 @@ void k_conv3x3_fp8(ConvArgs a) {
   uint4 hreg[HPT][LPV];
   uint4 wreg[WPT];
   const int nchunks = (a.cin_p + KC - 1) / KC;
-  using ST = Stager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN>;
-  ST::fetch(a, b, tid, y0, x0, n0, 0, hreg, wreg);
+  using ST = RowStager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN, false, NT>;
+  const ST st(a, b, tid, y0, x0, n0);
+  st.fetch(a, 0, hreg, wreg);
   ST::commit(tid, hreg, wreg, sX, sW);
   __syncthreads();
+  // branch-free loop body, as in the BF16 row-reuse kernel
   for (int ch = 0; ch < nchunks; ++ch) {
-    if (ch + 1 < nchunks) ST::fetch(a, b, tid, y0, x0, n0, ch + 1, hreg, wreg);
+    st.fetch(a, min(ch + 1, nchunks - 1), hreg, wreg);
 #pragma unroll 1  // one dx at a time: the halo rows of all three would not fit in registers
     for (int dx = 0; dx < 3; ++dx) {
       i32x8 xv[2 * FM + 1];
@@ -657,10 +812,8 @@ void k_conv3x3_fp8(ConvArgs a) {
       }
     }
     __syncthreads();
-    if (ch + 1 < nchunks) {
-      ST::commit(tid, hreg, wreg, sX, sW);
-      __syncthreads();
-    }
+    ST::commit(tid, hreg, wreg, sX, sW);
+    __syncthreads();
   }
 
   // Epilogue: accumulators -> LDS [pixel][channel] (FP32) -> 16-byte rows of codes.
@@ -746,7 +899,7 @@ void k_conv3x3_fp8(ConvArgs a) {
 template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
 static hipError_t launch_conv_fp8_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
                                     int chunk_base, const void* x0, const void* x1, void* y, hipStream_t st) {
-  ConvArgs a;
+  ConvArgs a{};
   a.x0 = x0;
   a.x1 = x1;
   a.aux = nullptr;
@@ -777,7 +930,7 @@ template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
 static hipError_t launch_conv_rows_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
                                      int chunk_base, const void* x0, const void* x1, const void* aux,
                                      void* y, hipStream_t st) {
-  ConvArgs a;
+  ConvArgs a{};
   a.x0 = x0;
   a.x1 = x1;
   a.aux = aux;
@@ -806,7 +959,7 @@ template <typename T, int BY, int BX, int BN, int WM, int WN, int LOADER, int EP
 static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
                                 int chunk_base, const void* x0, const void* x1, const void* aux,
                                 void* y, hipStream_t st) {
-  ConvArgs a;
+  ConvArgs a{};
   a.x0 = x0;
   a.x1 = x1;
   a.aux = aux;

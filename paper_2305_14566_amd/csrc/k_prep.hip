@@ -121,7 +121,7 @@ hipError_t launch_pyramid(const uint8_t* rgb, int64_t pitch, int H, int W, const
                           int kmax, uint16_t* const* lvl, const int* Ey, const int* Ex,
                           hipStream_t st) {
   if (kmax < 1) return hipSuccess;
-  PyrArgs a;
+  PyrArgs a{};
   a.rgb = rgb;
   a.pitch = pitch;
   a.H = H;
