@@ -157,22 +157,20 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
                                               const int32_t* list, const int32_t* count,
                                               int chunk_base, float* __restrict__ out,
                                               const float* __restrict__ dscale) {
-  constexpr int kMaxC0 = 256;
-  __shared__ float sth[OMNISEG_MAX_CLASSES * (144 + 9 * 2)];
-  __shared__ float swp[8 * kMaxC0 + 8];
   const int per_tile = T2 / 256;
   const int b = blockIdx.x / per_tile;
   const int pix = (blockIdx.x % per_tile) * 256 + threadIdx.x;
   if (chunk_base + b >= *count) return;
   const int si = list[4 * (chunk_base + b) + 1];
   const int ns = slots.n_slots[si];
-  for (int i = threadIdx.x; i < ns * P; i += 256) sth[i] = theta[(int64_t)b * max_slots * P + i];
   const bool pre = (c0 != 8);
-  if (pre) {
-    for (int i = threadIdx.x; i < 8 * c0; i += 256) swp[i] = wp[i];
-    if (threadIdx.x < 8) swp[8 * c0 + threadIdx.x] = bp[threadIdx.x];
-  }
-  __syncthreads();
+  // The precls weights and the tile's generated head parameters are the
+  // same for every thread of the block: they are read as constant memory
+  // with uniform indices (scalar loads into SGPRs, used directly as FMA
+  // operands), not staged through LDS.
+  typedef const __attribute__((address_space(4))) float cfloat;
+  cfloat* wpc = (cfloat*)wp;
+  cfloat* bpc = (cfloat*)bp;
   // D_0 of this pixel in 16-byte vectors (channels padded to 32, so whole
   // vectors stay inside the pixel's row)
   const T* px = d0 + ((int64_t)b * T2 + pix) * c0_p;
@@ -180,7 +178,7 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
   float F[8];
   if (pre) {
 #pragma unroll
-    for (int o = 0; o < 8; ++o) F[o] = swp[8 * c0 + o];
+    for (int o = 0; o < 8; ++o) F[o] = bpc[o];
     for (int c0v = 0; c0v < c0; c0v += V) {
       float v[V];
       decode16<T>(*reinterpret_cast<const uint4*>(px + c0v), v);
@@ -191,7 +189,7 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
           float x = v[k];
           if constexpr (std::is_same<T, uint8_t>::value) x *= dscale[c];
 #pragma unroll
-          for (int o = 0; o < 8; ++o) F[o] = fmaf(swp[o * c0 + c], x, F[o]);
+          for (int o = 0; o < 8; ++o) F[o] = fmaf(wpc[o * c0 + c], x, F[o]);
         }
       }
     }
@@ -210,13 +208,13 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
     }
   }
   for (int j = 0; j < ns; ++j) {
-    const float* th = &sth[j * P];
-    const float* W1 = th;
-    const float* W2 = th + 64;
-    const float* W3 = th + 128;
-    const float* b1 = th + 128 + 8 * O;
-    const float* b2 = b1 + 8;
-    const float* b3 = b2 + 8;
+    cfloat* th = (cfloat*)(theta + ((int64_t)b * max_slots + j) * P);
+    cfloat* W1 = th;
+    cfloat* W2 = th + 64;
+    cfloat* W3 = th + 128;
+    cfloat* b1 = th + 128 + 8 * O;
+    cfloat* b2 = b1 + 8;
+    cfloat* b3 = b2 + 8;
     float h1[8], h2[8];
 #pragma unroll
     for (int o = 0; o < 8; ++o) {
