@@ -318,8 +318,8 @@ struct RowStager {
   // Loads of one source over the chunk starting at channel c of it: every
   // vector at or beyond channel `lim` of the source reads zeros.
   __device__ __forceinline__ void load_src(const T* base, uint32_t bytes, const uint32_t (&off)[HPT], int c, int lim,
-                                           uint4 (&hreg)[HPT][LPV]) const {
-    const __amdgpu_buffer_rsrc_t r = buffer_rsrc(base + c, bytes - (uint32_t)(c * sizeof(T)));
+                                           uint4 (&hreg)[HPT][LPV], bool live) const {
+    const __amdgpu_buffer_rsrc_t r = buffer_rsrc(base + c, live ? bytes - (uint32_t)(c * sizeof(T)) : 0u);
     const bool keep = c + vc < lim;
 #pragma unroll
     for (int i = 0; i < HPT; ++i) {
@@ -333,17 +333,20 @@ struct RowStager {
     }
   }
 
-  __device__ __forceinline__ void fetch(const ConvArgs& a, int ch, uint4 (&hreg)[HPT][LPV], uint4 (&wreg)[WPT]) const {
+  // live = false issues the same loads over empty ranges: they return zeros
+  // without touching memory (the unused fetch of a branch-free loop's last pass).
+  __device__ __forceinline__ void fetch(const ConvArgs& a, int ch, uint4 (&hreg)[HPT][LPV], uint4 (&wreg)[WPT],
+                                        bool live = true) const {
     const int c = ch * KC;
     if (LOADER == LOAD_UPCAT) {
       if (c + KC <= cu_p) {
-        load_src(x0b, bytes0, o0, c, cu_p, hreg);
+        load_src(x0b, bytes0, o0, c, cu_p, hreg, live);
       } else if (c >= cu_p) {
-        load_src(x1b, bytes1, o1, c - cu_p, cin_p - cu_p, hreg);
+        load_src(x1b, bytes1, o1, c - cu_p, cin_p - cu_p, hreg, live);
       } else {  // the chunk straddles the end of the upsampled channels (FP8 only)
         uint4 h1[HPT][LPV];
-        load_src(x0b, bytes0, o0, c, cu_p, hreg);
-        const __amdgpu_buffer_rsrc_t r1 = buffer_rsrc(x1b, bytes1);
+        load_src(x0b, bytes0, o0, c, cu_p, hreg, live);
+        const __amdgpu_buffer_rsrc_t r1 = buffer_rsrc(x1b, live ? bytes1 : 0u);
         const bool second = c + vc >= cu_p && c + vc < cin_p;
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
@@ -354,9 +357,10 @@ struct RowStager {
         }
       }
     } else {
-      load_src(x0b, bytes0, o0, c, cin_p, hreg);
+      load_src(x0b, bytes0, o0, c, cin_p, hreg, live);
     }
-    const __amdgpu_buffer_rsrc_t rw = buffer_rsrc((const T*)a.w + (int64_t)ch * chunk_w, (uint32_t)(chunk_w * sizeof(T)));
+    const __amdgpu_buffer_rsrc_t rw =
+        buffer_rsrc((const T*)a.w + (int64_t)ch * chunk_w, live ? (uint32_t)(chunk_w * sizeof(T)) : 0u);
 #pragma unroll
     for (int i = 0; i < WPT; ++i) wreg[i] = buffer_load16(rw, wo[i]);
   }
@@ -570,11 +574,11 @@ void k_conv3x3_rows(ConvArgs a) {
   st.fetch(a, 0, hreg, wreg);
   ST::commit(tid, hreg, wreg, sX, sW);
   __syncthreads();
-  // The loop body has no branch (the last pass fetches and commits its own
-  // chunk again, unused), so the scheduler can interleave the next chunk's
+  // The loop body has no branch (the last pass issues an empty fetch and
+  // commits zeros, unused), so the scheduler can interleave the next chunk's
   // loads and the LDS address arithmetic with the MFMAs.
   for (int ch = 0; ch < nchunks; ++ch) {
-    st.fetch(a, min(ch + 1, nchunks - 1), hreg, wreg);
+    st.fetch(a, min(ch + 1, nchunks - 1), hreg, wreg, ch + 1 < nchunks);
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
       uint4 xv[FM + 2];
@@ -782,7 +786,7 @@ void k_conv3x3_fp8(ConvArgs a) {
   __syncthreads();
   // branch-free loop body, as in the BF16 row-reuse kernel
   for (int ch = 0; ch < nchunks; ++ch) {
-    st.fetch(a, min(ch + 1, nchunks - 1), hreg, wreg);
+    st.fetch(a, min(ch + 1, nchunks - 1), hreg, wreg, ch + 1 < nchunks);
 #pragma unroll 1  // one dx at a time: the halo rows of all three would not fit in registers
     for (int dx = 0; dx < 3; ++dx) {
       i32x8 xv[2 * FM + 1];
@@ -1141,6 +1145,17 @@ hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L
 
 constexpr int kFirstMaxC0 = 128;
 
+// Four consecutive channels of one pixel.
+__device__ __forceinline__ void store4(float* p, const float* v) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store4(uint16_t* p, const float* v) {
+  *reinterpret_cast<uint2*>(p) = make_uint2((uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                                            (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16));
+}
+__device__ __forceinline__ void store4(uint8_t* p, const float* v) {
+  *reinterpret_cast<uint32_t*>(p) = fp8_encode4(v[0], v[1], v[2], v[3]);
+}
 __device__ __forceinline__ void store_vec(float* p, const float* v) {
   *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
 }
@@ -1209,37 +1224,57 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
     sIn[2][py][px] = v2;
   }
   __syncthreads();
-  const int py = threadIdx.x / 16, px = threadIdx.x % 16;
-  float in[27];
+  // The 3 -> C_0 conv as a GEMM on FP32 MFMA (v_mfma_f32_16x16x4f32): A =
+  // weights [16 output channels x 4 K], B = the im2col rows of 16 pixels
+  // [4 K x 16 pixels], K = 27 taps x channels padded to 28 (seven steps).
+  // Lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; the accumulator
+  // holds channels 4 (l / 16) .. + 3 of pixel l % 16.  A wave computes four
+  // output rows of the block.
+  constexpr int KS = 7, MAXM = 8;  // C_0 <= 128: at most eight 16-channel fragments
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nm = a.c0_p / 16;
+  float wa[MAXM][KS];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int m = 0; m < MAXM; ++m)
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) in[c * 9 + dy * 3 + dx] = sIn[c][py + dy][px + dx];
-  const int y = sy * 16 + py, x = sx * 16 + px;
-  T* out = (T*)a.y + (((int64_t)b * a.T + y) * a.T + x) * a.c0_p;
-  // The weights are the same for every thread and read-only here: read them
-  // as constant memory with uniform indices (scalar loads into SGPRs).
-  typedef const __attribute__((address_space(4))) float cfloat;
-  cfloat* wg = (cfloat*)a.w;
-  cfloat* bg = (cfloat*)a.b;
-  for (int o0 = 0; o0 < a.c0_p; o0 += VEC) {
-    float v[VEC];
-#pragma unroll
-    for (int j = 0; j < VEC; ++j) {
-      const int o = o0 + j;
-      float acc = 0.f;
-      if (o < a.c0) {
-        acc = bg[o];
-#pragma unroll
-        for (int i = 0; i < 27; ++i) acc = fmaf(wg[o * 27 + i], in[i], acc);
-        acc = acc > 0.f ? acc : 0.f;
-        if (std::is_same<T, uint8_t>::value) acc *= a.oinv[o];
-      }
-      v[j] = acc;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int o = m * 16 + l16, k = 4 * ks + g;
+      wa[m][ks] = (m < nm && o < a.c0 && k < 27) ? a.w[o * 27 + k] : 0.f;
     }
-    store_vec(out + o0, v);
+  // im2col offsets inside sIn of this lane's K entries (k = c*9 + dy*3 + dx)
+  int koff[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = 4 * ks + g;
+    const int c = k / 9, dy = (k % 9) / 3, dx = k % 3;
+    koff[ks] = k < 27 ? (c * 18 + dy) * 19 + dx : -1;
+  }
+  const float* sflat = &sIn[0][0][0];
+  for (int r = 0; r < 4; ++r) {
+    const int py = wave * 4 + r;
+    float xb[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) xb[ks] = koff[ks] >= 0 ? sflat[koff[ks] + py * 19 + l16] : 0.f;
+    const int y = sy * 16 + py, x = sx * 16 + l16;
+    T* out = (T*)a.y + (((int64_t)b * a.T + y) * a.T + x) * a.c0_p;
+#pragma unroll
+    for (int m = 0; m < MAXM; ++m) {
+      if (m >= nm) break;
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[m][ks], xb[ks], acc, 0, 0, 0);
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = m * 16 + 4 * g + q;
+        float t = o < a.c0 ? acc[q] + a.b[o] : 0.f;
+        t = t > 0.f ? t : 0.f;
+        if (std::is_same<T, uint8_t>::value && o < a.c0) t *= a.oinv[o];
+        v[q] = t;
+      }
+      store4(out + m * 16 + 4 * g, v);
+    }
   }
 }
 
