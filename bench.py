@@ -45,19 +45,24 @@ PAPER_CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 2, 3), t
 CLASS_SLOT = (3, 3, 2, 2, 0, 2)
 CLASS_COLOURS = ((230, 25, 75), (60, 180, 75), (255, 225, 25), (0, 130, 200), (245, 130, 48), (145, 30, 180))
 
-# HBM bytes per launch of the dominant BF16 conv kernel on this workload, from
-# two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
-#   bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu --train-steps 0 --fp8-steps 0 --paper-steps 0 --copy-gib 1
-# over the 32 launches of the timed step, each counter scaled by its reading
-# for the 1 GiB device copy that command makes first (FETCH_SIZE read 0.5 GiB,
-# WRITE_SIZE 1 GiB).  It describes the conv source whose SHA-256 is stored
-# here and is reported as null for any other.
+# HBM bytes per launch of the BF16 conv kernels that can dominate this
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
+#   bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu --train-steps 0 --fp8-steps 0 --paper-steps 0
+#            --map-reps 0 --copy-gib 1
+# over each kernel's launches in the timed step, each counter scaled by its
+# reading for the 1 GiB device copy that command makes first (FETCH_SIZE read
+# 0.5 GiB, WRITE_SIZE 1 GiB).  They describe the conv source whose SHA-256 is
+# stored here; any other source, or another kernel, reports null.
 MEASURED_TRAFFIC = {
-    "kernel": "omniseg::k_conv3x3_rows<16, 64, 2, 2, 2, 0>",
-    "bytes_per_launch": 4492918214.9,
-    "fetch_bytes_per_launch": 3514698658.9,
-    "write_bytes_per_launch": 978219556.0,
-    "conv_source_sha256": "60df7bccfdd9bd7863952107e4d7b17196aac1b129575661b1d3dbe508611403",
+    "conv_source_sha256": "b92d367975bae9296d1be64e2650657f7d28d1b3368710373c286273ddc2da96",
+    "kernels": {
+        # decoder upsample-and-concat conv_a, 4 levels x 8 tile batches
+        "omniseg::k_conv3x3_rows<16, 64, 4, 2, 2, 0>": dict(launches=32, fetch_bytes_per_launch=3501391280.2,
+                                                             write_bytes_per_launch=921108480.0),
+        # residual convs (encoder and decoder conv_b), 9 layers x 8 tile batches
+        "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 1>": dict(launches=72, fetch_bytes_per_launch=2432466569.0,
+                                                             write_bytes_per_launch=934754531.6),
+    },
 }
 
 
@@ -67,9 +72,10 @@ def measured_traffic(kernel):
     src = os.path.join(ROOT, "paper_2305_14566_amd", "csrc", "k_conv.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if kernel != MEASURED_TRAFFIC["kernel"] or sha != MEASURED_TRAFFIC["conv_source_sha256"]:
+    k = MEASURED_TRAFFIC["kernels"].get(kernel)
+    if k is None or sha != MEASURED_TRAFFIC["conv_source_sha256"]:
         return None
-    return MEASURED_TRAFFIC["bytes_per_launch"]
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
 def conv_symbol(om, prec, stage, config):
