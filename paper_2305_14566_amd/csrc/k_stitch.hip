@@ -63,6 +63,80 @@ __device__ __forceinline__ void stitch_pixel(const StitchArgs& a, int x, int y) 
   if (a.logit) a.logit[(int64_t)y * a.logit_pitch + x] = den > 0 ? n / (float)den : 0.f;
 }
 
+// Four consecutive pixels x0 .. x0 + 3 (x0 a multiple of 4, all inside the
+// row) when the stride and the tile size are multiples of 4: the four share
+// their covering tiles, and each tile's four logits are one aligned 16-byte
+// load.  Per pixel the arithmetic and its order are those of stitch_pixel.
+__device__ __forceinline__ void stitch_span4(const StitchArgs& a, int x0, int y) {
+  const int T = a.T, s = a.s;
+  const int jy0 = (y < T) ? 0 : (y - T) / s + 1, jy1 = min(a.ny - 1, y / s);
+  const int jx0 = (x0 < T) ? 0 : (x0 - T) / s + 1, jx1 = min(a.nx - 1, x0 / s);
+  float out[4];
+  bool m[4];
+  if (a.vote > 0) {
+    int votes[4] = {0, 0, 0, 0}, cover = 0;
+    for (int jy = jy0; jy <= jy1; ++jy) {
+      const int iy = y - jy * s;
+      for (int jx = jx0; jx <= jx1; ++jx) {
+        const int t = a.index[jy * a.nx + jx];
+        if (t < 0) continue;
+        const int ix = x0 - jx * s;
+        const float4 l =
+            *reinterpret_cast<const float4*>(a.logits + (int64_t)t * a.tile_stride + a.slot_off + (int64_t)iy * T + ix);
+        votes[0] += l.x > 0.f ? 1 : 0;
+        votes[1] += l.y > 0.f ? 1 : 0;
+        votes[2] += l.z > 0.f ? 1 : 0;
+        votes[3] += l.w > 0.f ? 1 : 0;
+        ++cover;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      m[q] = cover > 0 && votes[q] >= a.vote;
+      out[q] = (float)votes[q];
+    }
+  } else {
+    float sum[4] = {0.f, 0.f, 0.f, 0.f}, comp[4] = {0.f, 0.f, 0.f, 0.f};
+    int den[4] = {0, 0, 0, 0};
+    for (int jy = jy0; jy <= jy1; ++jy) {
+      const int iy = y - jy * s;
+      const int ry = min(iy + 1, T - iy);
+      for (int jx = jx0; jx <= jx1; ++jx) {
+        const int t = a.index[jy * a.nx + jx];
+        if (t < 0) continue;
+        const int ix = x0 - jx * s;
+        const float4 l4 =
+            *reinterpret_cast<const float4*>(a.logits + (int64_t)t * a.tile_stride + a.slot_off + (int64_t)iy * T + ix);
+        const float l[4] = {l4.x, l4.y, l4.z, l4.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int w = ry * min(ix + q + 1, T - ix - q);
+          const float v = (float)w * l[q];
+          const float t2 = sum[q] + v;
+          comp[q] += (fabsf(sum[q]) >= fabsf(v)) ? ((sum[q] - t2) + v) : ((v - t2) + sum[q]);
+          sum[q] = t2;
+          den[q] += w;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float n = sum[q] + comp[q];
+      m[q] = (den[q] > 0) && (a.coverage || n > 0.f);
+      out[q] = den[q] > 0 ? n / (float)den[q] : 0.f;
+    }
+  }
+  if (a.fg) {
+    const uint8_t* fr = a.fg + (int64_t)(y >> a.fg_shift) * a.Wc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = m[q] && fr[(x0 + q) >> a.fg_shift];
+  }
+  *reinterpret_cast<uint32_t*>(a.mask + (int64_t)y * a.mask_pitch + x0) =
+      (m[0] ? 1u : 0u) | (m[1] ? 1u << 8 : 0u) | (m[2] ? 1u << 16 : 0u) | (m[3] ? 1u << 24 : 0u);
+  if (a.logit)
+    *reinterpret_cast<float4*>(a.logit + (int64_t)y * a.logit_pitch + x0) = make_float4(out[0], out[1], out[2], out[3]);
+}
+
 // One thread per pixel; rows beyond the grid's y extent are taken in strides.
 __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
   const int x = blockIdx.x * 256 + threadIdx.x;
@@ -70,10 +144,35 @@ __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
   for (int y = blockIdx.y; y < a.Hk; y += gridDim.y) stitch_pixel(a, x, y);
 }
 
+// One thread per four pixels (see stitch_span4); the row's ragged end goes
+// pixel by pixel.
+__global__ __launch_bounds__(256) void k_stitch4(StitchArgs a) {
+  const int x0 = (blockIdx.x * 256 + threadIdx.x) * 4;
+  if (x0 >= a.Wk) return;
+  for (int y = blockIdx.y; y < a.Hk; y += gridDim.y) {
+    if (x0 + 3 < a.Wk) {
+      stitch_span4(a, x0, y);
+    } else {
+      for (int x = x0; x < a.Wk; ++x) stitch_pixel(a, x, y);
+    }
+  }
+}
+
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t st) {
   if (a.Hk <= 0 || a.Wk <= 0) return hipSuccess;
-  dim3 grid(ceil_div(a.Wk, 256), std::min(a.Hk, kMaxGridY));
-  hipLaunchKernelGGL(k_stitch, grid, dim3(256), 0, st, a);
+  // the four-pixel form needs shared covering tiles (s, T multiples of 4) and
+  // aligned vector accesses (tile logits, mask rows, logit rows)
+  const bool span4 = a.s % 4 == 0 && a.T % 4 == 0 && a.tile_stride % 4 == 0 && a.slot_off % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(a.logits) % 16 == 0 && a.mask_pitch % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(a.mask) % 4 == 0 &&
+                     (!a.logit || (a.logit_pitch % 4 == 0 && reinterpret_cast<uintptr_t>(a.logit) % 16 == 0));
+  if (span4) {
+    dim3 grid(ceil_div(a.Wk, 1024), std::min(a.Hk, kMaxGridY));
+    hipLaunchKernelGGL(k_stitch4, grid, dim3(256), 0, st, a);
+  } else {
+    dim3 grid(ceil_div(a.Wk, 256), std::min(a.Hk, kMaxGridY));
+    hipLaunchKernelGGL(k_stitch, grid, dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 

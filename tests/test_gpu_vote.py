@@ -32,7 +32,7 @@ def _tiles(H, W, T, s, keep, rng):
 @pytest.mark.parametrize("H,W,T,s,keep,thr", [(300, 217, 64, 32, 0.7, 1), (300, 217, 64, 32, 0.7, 3),
                                               (97, 250, 32, 8, 0.9, 4), (128, 128, 128, 64, 1.0, 2),
                                               (200, 130, 64, 64, 0.8, 1), (5, 3, 16, 8, 1.0, 1),
-                                              (1100, 600, 512, 64, 1.0, 4)])
+                                              (1100, 600, 512, 64, 1.0, 4), (150, 133, 32, 7, 0.8, 3)])
 def test_stitch_vote_bit_exact(H, W, T, s, keep, thr):
     print(f"vote stitch H={H} W={W} T={T} s={s} thr={thr}", flush=True)
     rng = np.random.default_rng(H * 7 + W + thr)
