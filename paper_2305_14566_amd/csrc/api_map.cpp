@@ -40,6 +40,7 @@ int32_t omniseg_merge_to_base(int32_t height, int32_t width, const omniseg_base_
     m.bilinear = bil ? 1 : 0;
     m.out = p.out;
     m.out_pitch = p.out_pitch;
+    m.vec4 = (reinterpret_cast<uintptr_t>(p.out) % 4 == 0 && p.out_pitch % 4 == 0) ? 1 : 0;
   }
   (void)hipGetLastError();
   HIP_TRY(launch_merge_base(a, n_planes, reinterpret_cast<hipStream_t>(stream)));
@@ -78,11 +79,16 @@ int32_t omniseg_overlay(const omniseg_slide* slide, const omniseg_overlay_class*
     o.k = c.scale_log2;
     o.alpha = c.alpha;
     for (int ch = 0; ch < 3; ++ch) o.rgb[ch] = c.rgb[ch];
+    o.vec4 = (reinterpret_cast<uintptr_t>(c.mask) % 4 == 0 && c.pitch % 4 == 0) ? 1 : 0;
   }
   a.out = out;
   a.out_pitch = out_pitch;
   a.out10 = out10;
   a.out10_pitch = out10_pitch;
+  a.vec = (reinterpret_cast<uintptr_t>(slide->rgb) % 4 == 0 && slide->row_pitch % 4 == 0 &&
+           reinterpret_cast<uintptr_t>(out) % 4 == 0 && out_pitch % 4 == 0)
+              ? 1
+              : 0;
   (void)hipGetLastError();
   HIP_TRY(launch_overlay(a, reinterpret_cast<hipStream_t>(stream)));
   return OMNISEG_OK;

@@ -87,6 +87,7 @@ struct MergePlane {
   int bilinear;
   uint8_t* out;          // the 40x mask
   int64_t out_pitch;
+  int vec4;              // out and out_pitch are multiples of 4: 4-byte stores
 };
 struct MergeArgs {
   int H, W;
@@ -99,6 +100,7 @@ struct OverlayClass {
   int k;
   int alpha;             // [0, 256]
   int rgb[3];
+  int vec4;              // mask and pitch are multiples of 4: 4-byte mask loads at k = 0
 };
 struct OverlayArgs {
   const uint8_t* rgb;
@@ -110,6 +112,7 @@ struct OverlayArgs {
   int64_t out_pitch;
   uint8_t* out10;        // optional 4x4 box-mean map
   int64_t out10_pitch;
+  int vec;               // rgb, out and their pitches are multiples of 4: word loads and stores
 };
 hipError_t launch_overlay(const OverlayArgs& a, hipStream_t st);
 

@@ -19,35 +19,45 @@
 
 namespace omniseg {
 
+__device__ __forceinline__ uint8_t merge_pixel(const MergePlane& p, int y, int x) {
+  const int k = p.k;
+  if (p.bilinear) {
+    const float inv = 1.0f / (float)(2 << k);  // 1 / 2^(k+1), exact
+    const float sy = fmaxf(0.f, (float)(2 * y + 1 - (1 << k)) * inv);
+    const float sx = fmaxf(0.f, (float)(2 * x + 1 - (1 << k)) * inv);
+    const int y0 = (int)sy, x0 = (int)sx;
+    const int y1 = min(y0 + 1, p.Hk - 1), x1 = min(x0 + 1, p.Wk - 1);
+    const float ly = sy - (float)y0, lx = sx - (float)x0;
+    const float* r0 = p.logit + (int64_t)y0 * p.pitch;
+    const float* r1 = p.logit + (int64_t)y1 * p.pitch;
+    const float top = (1.f - lx) * r0[x0] + lx * r0[x1];
+    const float bot = (1.f - lx) * r1[x0] + lx * r1[x1];
+    return ((1.f - ly) * top + ly * bot) > 0.f ? 1 : 0;
+  }
+  return p.mask[(int64_t)(y >> k) * p.pitch + (x >> k)] ? 1 : 0;
+}
+
+// One thread per four consecutive 40x pixels: one 4-byte store when the
+// plane's output rows allow it (vec4), else four byte stores.
 __global__ __launch_bounds__(256) void k_merge_base(MergeArgs a) {
   const MergePlane& p = a.plane[blockIdx.z];
-  const int x = blockIdx.x * 256 + threadIdx.x;
-  if (x >= a.W) return;
-  const int k = p.k;
+  const int x0 = (blockIdx.x * 256 + threadIdx.x) * 4;
+  if (x0 >= a.W) return;
   for (int y = blockIdx.y; y < a.H; y += gridDim.y) {
-    uint8_t m;
-    if (p.bilinear) {
-      const float inv = 1.0f / (float)(2 << k);  // 1 / 2^(k+1), exact
-      const float sy = fmaxf(0.f, (float)(2 * y + 1 - (1 << k)) * inv);
-      const float sx = fmaxf(0.f, (float)(2 * x + 1 - (1 << k)) * inv);
-      const int y0 = (int)sy, x0 = (int)sx;
-      const int y1 = min(y0 + 1, p.Hk - 1), x1 = min(x0 + 1, p.Wk - 1);
-      const float ly = sy - (float)y0, lx = sx - (float)x0;
-      const float* r0 = p.logit + (int64_t)y0 * p.pitch;
-      const float* r1 = p.logit + (int64_t)y1 * p.pitch;
-      const float top = (1.f - lx) * r0[x0] + lx * r0[x1];
-      const float bot = (1.f - lx) * r1[x0] + lx * r1[x1];
-      m = ((1.f - ly) * top + ly * bot) > 0.f ? 1 : 0;
+    uint8_t* o = p.out + (int64_t)y * p.out_pitch + x0;
+    if (p.vec4 && x0 + 3 < a.W) {
+      const uint32_t v = (uint32_t)merge_pixel(p, y, x0) | ((uint32_t)merge_pixel(p, y, x0 + 1) << 8) |
+                         ((uint32_t)merge_pixel(p, y, x0 + 2) << 16) | ((uint32_t)merge_pixel(p, y, x0 + 3) << 24);
+      *reinterpret_cast<uint32_t*>(o) = v;
     } else {
-      m = p.mask[(int64_t)(y >> k) * p.pitch + (x >> k)] ? 1 : 0;
+      for (int q = 0; q < 4 && x0 + q < a.W; ++q) o[q] = merge_pixel(p, y, x0 + q);
     }
-    p.out[(int64_t)y * p.out_pitch + x] = m;
   }
 }
 
 hipError_t launch_merge_base(const MergeArgs& a, int n_planes, hipStream_t st) {
   if (n_planes <= 0 || a.H <= 0 || a.W <= 0) return hipSuccess;
-  const dim3 grid(ceil_div(a.W, 256), std::min(a.H, kMaxGridY), n_planes);
+  const dim3 grid(ceil_div(a.W, 1024), std::min(a.H, kMaxGridY), n_planes);
   hipLaunchKernelGGL(k_merge_base, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
@@ -59,11 +69,51 @@ __global__ __launch_bounds__(256) void k_overlay(OverlayArgs a) {
   if (bx >= Wb) return;
   for (int by = blockIdx.y; by < Hb; by += gridDim.y) {
     int sum[3] = {0, 0, 0}, cnt = 0;
+    const bool full = a.vec && 4 * bx + 3 < a.W;
     for (int i = 0; i < 4; ++i) {
       const int y = 4 * by + i;
       if (y >= a.H) break;
       const uint8_t* src = a.rgb + (int64_t)y * a.pitch;
       uint8_t* dst = a.out + (int64_t)y * a.out_pitch;
+      if (full) {
+        // the block's 4 pixels of this row: 12 bytes, three aligned words
+        const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src + 12 * bx);
+        const uint32_t w3[3] = {s4[0], s4[1], s4[2]};
+        int px[4][3];
+#pragma unroll
+        for (int b = 0; b < 12; ++b) px[b / 3][b % 3] = (int)((w3[b / 4] >> (8 * (b % 4))) & 0xFFu);
+        for (int c = 0; c < a.n; ++c) {
+          const OverlayClass& oc = a.cls[c];
+          const uint8_t* mrow = oc.mask + (int64_t)(y >> oc.k) * oc.pitch;
+          uint32_t on;
+          if (oc.k == 0 && oc.vec4) {
+            on = *reinterpret_cast<const uint32_t*>(mrow + 4 * bx);
+          } else {
+            on = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) on |= (uint32_t)mrow[(4 * bx + q) >> oc.k] << (8 * q);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (!((on >> (8 * q)) & 0xFFu)) continue;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+              px[q][ch] = (px[q][ch] * (256 - oc.alpha) + oc.rgb[ch] * oc.alpha + 128) >> 8;
+          }
+        }
+        uint32_t o3[3] = {0u, 0u, 0u};
+#pragma unroll
+        for (int b = 0; b < 12; ++b) {
+          o3[b / 4] |= (uint32_t)px[b / 3][b % 3] << (8 * (b % 4));
+          sum[b % 3] += px[b / 3][b % 3];
+        }
+        uint32_t* d4 = reinterpret_cast<uint32_t*>(dst + 12 * bx);
+        d4[0] = o3[0];
+        d4[1] = o3[1];
+        d4[2] = o3[2];
+        cnt += 4;
+        continue;
+      }
       for (int j = 0; j < 4; ++j) {
         const int x = 4 * bx + j;
         if (x >= a.W) break;

@@ -45,7 +45,8 @@ def test_merge_to_base(H, W):
             assert np.array_equal(g[~risky], want[~risky])
 
 
-@pytest.mark.parametrize("H,W,in_place", [(64, 64, False), (203, 131, False), (5, 3, False), (130, 97, True)])
+@pytest.mark.parametrize("H,W,in_place", [(64, 64, False), (203, 131, False), (5, 3, False), (130, 97, True),
+                                           (130, 100, True), (37, 256, False)])
 def test_overlay_bit_exact(H, W, in_place):
     print(f"overlay H={H} W={W} in_place={in_place}", flush=True)
     rng = np.random.default_rng(7 * H + W)
@@ -106,3 +107,27 @@ def test_segment_merge_overlay_chain():
     assert sure.mean() > 0.8  # the comparison covers most of the slide
     want_rgb = O.overlay(rgb, ref_classes)
     assert np.array_equal(out.cpu().numpy()[sure], want_rgb[sure])
+
+
+def test_overlay_word_path_with_ragged_block():
+    """Rows whose pitch is a multiple of 4 take the word-wide path; a width of
+    4k + 2 leaves a partial last block that goes pixel by pixel."""
+    H, W = 45, 98
+    rng = np.random.default_rng(77)
+    big = rng.integers(0, 256, size=(H, W + 2, 3)).astype(np.uint8)  # row pitch 300 bytes
+    rgb = np.ascontiguousarray(big[:, :W])
+    classes = []
+    for c in range(3):
+        k = c
+        m = (rng.uniform(size=(O.level_size(H, k), O.level_size(W, k) + 4)) < 0.4).astype(np.uint8)
+        classes.append((m, k, (int(rng.integers(256)), 40 * c, 255 - 30 * c), int(rng.integers(0, 257))))
+    dslide = torch.from_numpy(big).to(DEV)[:, :W]
+    out_big = torch.zeros((H, W + 2, 3), dtype=torch.uint8, device=DEV)
+    dev = [(torch.from_numpy(m).to(DEV)[:, :O.level_size(W, k)], k, col, a) for (m, k, col, a) in classes]
+    out, o10 = om.overlay(dslide, dev, out=out_big[:, :W])
+    torch.cuda.synchronize()
+    ref_classes = [(m[:, :O.level_size(W, k)], k, col, a) for (m, k, col, a) in classes]
+    want = O.overlay(rgb, ref_classes)
+    assert np.array_equal(out_big[:, :W].cpu().numpy(), want)
+    assert np.array_equal(o10.cpu().numpy(), O.map_10x(want))
+    assert not out_big[:, W:].any()  # nothing written past the width
