@@ -148,6 +148,8 @@ hipError_t launch_controller(const float* g, int batch, int G, const float* wc, 
 }
 
 // One thread per pixel of one tile; all the tile's slots in one pass.
+constexpr int kHeadChunk = 128;  // bytes of D_0 per pixel staged at a time
+
 template <typename T, int O>
 __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, int c0, int c0_p,
                                               const float* __restrict__ wp,
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
   const T* px = d0 + ((int64_t)b * T2 + pix) * c0_p;
   constexpr int V = 16 / sizeof(T);
   float F[8];
-  if (pre) {
+  if (pre && sizeof(T) < 4) {
 #pragma unroll
     for (int o = 0; o < 8; ++o) F[o] = bpc[o];
     for (int c0v = 0; c0v < c0; c0v += V) {
@@ -190,6 +192,45 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
           if constexpr (std::is_same<T, uint8_t>::value) x *= dscale[c];
 #pragma unroll
           for (int o = 0; o < 8; ++o) F[o] = fmaf(wpc[o * c0 + c], x, F[o]);
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) F[o] = fmaxf(F[o], 0.f);
+  } else if (pre) {
+    // FP32: the block's 256 pixels are contiguous in D_0.  Their channels
+    // are staged through LDS in chunks of kHeadChunk bytes per pixel with
+    // coalesced 16-byte loads (consecutive lanes, consecutive vectors), one
+    // LDS row per pixel padded by 16 bytes; each thread then reads its own
+    // row.  Read straight from memory, a pixel's 256 bytes per thread cost a
+    // new cache line per lane and load; the 64- and 128-byte rows of FP8 and
+    // BF16 are read directly.
+    constexpr int RV = kHeadChunk / 16;  // 16-byte vectors per pixel and chunk
+    __shared__ uint4 sD[256 * (RV + 1)];
+    const T* blk = d0 + ((int64_t)b * T2 + (blockIdx.x % per_tile) * 256) * c0_p;
+    const int pv = c0_p * (int)sizeof(T) / 16;  // vectors per pixel
+#pragma unroll
+    for (int o = 0; o < 8; ++o) F[o] = bpc[o];
+    for (int v0 = 0; v0 < pv; v0 += RV) {
+      const int nv = min(RV, pv - v0);
+      __syncthreads();  // the previous chunk's rows have been read
+      for (int i = threadIdx.x; i < 256 * nv; i += 256) {
+        const int p = i / nv, v = i % nv;
+        sD[p * (RV + 1) + v] = reinterpret_cast<const uint4*>(blk + (int64_t)p * c0_p)[v0 + v];
+      }
+      __syncthreads();
+      for (int v = 0; v < nv; ++v) {
+        float x16[V];
+        decode16<T>(sD[threadIdx.x * (RV + 1) + v], x16);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const int c = (v0 + v) * V + k;
+          if (c < c0) {
+            float x = x16[k];
+            if constexpr (std::is_same<T, uint8_t>::value) x *= dscale[c];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) F[o] = fmaf(wpc[o * c0 + c], x, F[o]);
+          }
         }
       }
     }
