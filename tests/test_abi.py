@@ -304,6 +304,20 @@ def test_merge_and_overlay_reject_before_any_hip_call():
     assert lib.omniseg_overlay(ctypes.byref(sl), oc, 17, FAKE, 240, None, 0, None) == 1
 
 
+def test_conv_refuses_images_above_2gib_before_any_hip_call():
+    """The conv kernels address one image's input with 32-bit offsets."""
+    lib = om.lib()
+    big = 1 << 40
+    # 4096 x 4096 x 64 BF16 channels = 2^31 bytes: refused; 32 channels fit
+    assert lib.omniseg_conv3x3(om.BF16, om.CONV_RELU, 1, 4096, 4096, 64, 64, 64, FAKE, FAKE, FAKE, None, None, FAKE,
+                               None, -1, FAKE, big, None) == 2
+    # POOL reads a 2H x 2W input: 2048^2 output x 4 x 64 x 2 bytes is refused too
+    assert lib.omniseg_conv3x3(om.BF16, om.CONV_POOL_RELU, 1, 2048, 2048, 64, 64, 64, FAKE, FAKE, FAKE, None, None,
+                               FAKE, None, -1, FAKE, big, None) == 2
+    assert lib.omniseg_conv3x3_fp8(om.CONV_RELU, 1, 4096, 4096, 128, 128, 64, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                                   FAKE, None, -1, FAKE, big, None) == 2
+
+
 def test_tile_grid_size_guard():
     """A tile grid of more than 32767 tiles per side is refused before any HIP call."""
     p = om.Plan(base=4, levels=2, head_out=1, n_classes=1, scales=(0,), tile=16, stride=1)
