@@ -191,3 +191,83 @@ def test_tall_slide_integer_steps():
     got = _region(plan, ds, pairs, ws, om.REGION_TILE_LIST).view(np.int32).reshape(-1, 4)[:cnt]
     assert [tuple(t) for t in got] == ref_list
     assert masks[0][0].shape == (H, W) and masks[0][1].shape == (Hk, Wk)
+
+
+def _paper_like_case():
+    """The paper's settings at a small size: 40x/10x/5x at strides 32/8/8
+    (T/s = 2 and 8, as 512 at 256 and 64), vote thresholds 1/4/4, the Otsu
+    tissue map (median 5, components of < 10 coarse pixels removed), masks
+    gated by the tissue map."""
+    a, _ = synth.strip_slide(71, 300, 517, fg_frac=0.25)
+    cfg = O.make_config(base=8, levels=3, head_out=2, n_classes=3, scales=(0, 2, 3), tile=64, stride=32,
+                        fg_filter=True, mask_and_fg=True, scale_strides=(32, 8, 8), merge="vote",
+                        vote_thresholds=(1, 4, 4), tissue_method="otsu", median_kernel=5, min_tissue_area=10)
+    flat = synth.he_normal_weights(72, 8, 3, 3, 3, 2, bias_std=0.05)
+    pairs = [(0, 0), (2, 1), (1, 2)]
+    return [a], cfg, flat, pairs
+
+
+def _paper_plan(cfg, precision=om.FP32, graph=False):
+    return om.Plan(base=cfg["base"], levels=cfg["levels"], head_out=cfg["head_out"], n_classes=cfg["n_classes"],
+                   scales=cfg["scales"], tile=cfg["tile"], stride=cfg["stride"], fg_filter=True, mask_and_fg=True,
+                   emit_logits=True, scale_strides=cfg["scale_strides"], merge=om.MERGE_VOTE,
+                   vote_thresholds=cfg["vote_thresholds"], tissue_method=om.TISSUE_OTSU,
+                   median_kernel=cfg["median_kernel"], min_tissue_area=cfg["min_tissue_area"], precision=precision,
+                   batch_tiles=16, graph=graph)
+
+
+def test_paper_settings_end_to_end():
+    """Per-scale strides, Otsu tissue map, majority vote and tissue-gated masks together."""
+    slides, cfg, flat, pairs = _paper_like_case()
+    plan = _paper_plan(cfg)
+    ds = [torch.from_numpy(np.ascontiguousarray(s)).to(DEV) for s in slides]
+    masks, logits, ws = plan.segment(ds, pairs, plan.pack(torch.from_numpy(flat).to(DEV)))
+    torch.cuda.synchronize()
+    ref = O.segment(slides, flat, cfg, pairs, keep_tiles=True)
+    fg, _, (t, comps, kept) = O.tissue_map_otsu(slides[0], 3, 5, 10)
+    st = _region(plan, ds, pairs, ws, om.REGION_TISSUE_STATS).view(np.int32)
+    assert list(st) == [t, comps, kept, 0]
+    cnt = int(_region(plan, ds, pairs, ws, om.REGION_TILE_COUNT).view(np.int32)[0])
+    got = _region(plan, ds, pairs, ws, om.REGION_TILE_LIST).view(np.int32).reshape(-1, 4)[:cnt]
+    assert [tuple(x) for x in got] == ref["tiles"]
+    err, amax = _tile_logit_error(plan, ds, pairs, ws, ref, cfg["tile"])
+    assert err <= FP32_TOL, err
+    for p, (c, si) in enumerate(pairs):
+        k, s = cfg["scales"][si], cfg["scale_strides"][si]
+        Hk, Wk = O.level_size(slides[0].shape[0], k), O.level_size(slides[0].shape[1], k)
+        ts = [(jy, jx) for (n, sj, jy, jx) in ref["tiles"] if sj == si]
+        near = [(np.abs(ref["tile_logits"][(0, si, jy, jx)][c]) <= 2 * amax).astype(float) for (jy, jx) in ts]
+        A, _ = O.vote(ts, near, Hk, Wk, cfg["tile"], s)
+        lg = logits[0][p].cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(lg - ref["logit"][0][p]) <= A), p
+        m = masks[0][p].cpu().numpy().astype(bool)
+        sure = A == 0
+        assert np.array_equal(m[sure], ref["mask"][0][p][sure]), p
+        gate = O.fg_at_scale(fg, 3, k, Hk, Wk)
+        assert not (m & ~gate).any()  # masks stay inside the tissue map
+
+
+def test_paper_settings_graph_replay():
+    """The captured work after the tile list (backbone, head, vote stitch)
+    replays bit for bit, with eager work between replays."""
+    slides, cfg, flat, pairs = _paper_like_case()
+    ds = [torch.from_numpy(np.ascontiguousarray(s)).to(DEV) for s in slides]
+    eager = _paper_plan(cfg, om.BF16)
+    m_e, l_e, _ = eager.segment(ds, pairs, eager.pack(torch.from_numpy(flat).to(DEV)))
+    plan = _paper_plan(cfg, om.BF16, graph=True)
+    packed = plan.pack(torch.from_numpy(flat).to(DEV))
+    ws = torch.empty(plan.workspace_bytes(ds, pairs), dtype=torch.uint8, device=DEV)
+    outs = plan.alloc_outputs(ds, pairs)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in outs[0][0] + outs[1][0]:
+            if t is not None:
+                t.fill_(3)
+        float(torch.ones(1000, device=DEV).sum())
+        torch.cuda.synchronize()
+        masks, logits, _ = plan.segment(ds, pairs, packed, workspace=ws, outputs=outs, stream=side)
+        side.synchronize()
+        for p in range(len(pairs)):
+            assert torch.equal(masks[0][p], m_e[0][p]), (rep, p)
+            assert torch.equal(logits[0][p], l_e[0][p]), (rep, p)
