@@ -26,6 +26,18 @@ struct ScaleGeom {
 };
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+// The hardware deals the workgroups of a launch to the eight XCDs round
+// robin (workgroup x to XCD x % 8), and each XCD has its own L2.  The conv
+// kernels read their block index through this bijection, under which XCD j
+// runs one contiguous range of logical indices: the output-channel blocks of
+// a pixel block and neighbouring pixel blocks, which read the same input
+// rows, then share an L2 instead of each XCD fetching them.
+__device__ __forceinline__ int xcd_remap(int x, int n) {
+  constexpr int X = 8;
+  const int q = n / X, r = n % X, j = x % X, i = x / X;
+  return (j < r ? j * (q + 1) : r * (q + 1) + (j - r) * q) + i;
+}
+
 // Largest grid extent the kernels launch in y (row loops stride over the rest).
 constexpr int kMaxGridY = 65535;
 

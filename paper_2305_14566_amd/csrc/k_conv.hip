@@ -541,7 +541,7 @@ void k_conv3x3_rows(ConvArgs a) {
   T* sX = reinterpret_cast<T*>(smem);
   T* sW = sX + NPIX * ROW;
 
-  int rest = blockIdx.x;
+  int rest = xcd_remap(blockIdx.x, gridDim.x);
   const int nb = rest % a.n_nblk;
   rest /= a.n_nblk;
   const int sxb = rest % a.tiles_x;
@@ -748,7 +748,7 @@ void k_conv3x3_fp8(ConvArgs a) {
   T* sX = reinterpret_cast<T*>(smem);
   T* sW = sX + NPIX * ROW;
 
-  int rest = blockIdx.x;
+  int rest = xcd_remap(blockIdx.x, gridDim.x);
   const int nb = rest % a.n_nblk;
   rest /= a.n_nblk;
   const int sxb = rest % a.tiles_x;
