@@ -1137,8 +1137,9 @@ hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L
 
 // ---------------------------------------------------------------------------
 // First conv, 3 -> C_0, from the slide (40x) or the box-sum pyramid.  One
-// workgroup per 16x16 output block of one tile; the 18x18x3 input patch is
-// normalised to [0, 1] (value / (255 * 4^k)) in FP32 in LDS, with the pad
+// workgroup per 16-pixel-wide column of BH rows of one tile; the
+// (BH + 2) x 18 x 3 input patch is normalised to [0, 1] (value / (255 * 4^k))
+// in FP32 in LDS, with the pad
 // colour outside the slide and zeros outside the tile.  FP32 arithmetic for
 // every precision; the output is stored in the backbone's storage type.
 // ---------------------------------------------------------------------------
@@ -1175,25 +1176,30 @@ __device__ __forceinline__ void store_vec(uint16_t* p, const float* v) {
   *reinterpret_cast<uint4*>(p) = u;
 }
 
-template <typename T>
+// BH output rows (64 when the tile allows, else 16) of a 16-pixel-wide column
+// per workgroup; a wave owns BH / 4 rows and loads its weight fragments once.
+template <typename T, int BH>
 __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
-  constexpr int VEC = 16 / sizeof(T);
-  __shared__ float sIn[3][18][19];
-  const int nb = a.T / 16;
+  constexpr int RPW = BH / 4;                           // output rows per wave
+  constexpr int OPAD = 16 / (int)sizeof(T);             // one 16-byte slot per staged pixel row
+  constexpr int OPITCH = kFirstMaxC0 + OPAD;            // staged values per pixel (at most)
+  __shared__ float sIn[3][BH + 2][19];
+  __shared__ __attribute__((aligned(16))) T sOut[4][16 * OPITCH];
+  const int nbx = a.T / 16, nby = a.T / BH;
   int rest = blockIdx.x;
-  const int sx = rest % nb;
-  rest /= nb;
-  const int sy = rest % nb;
-  const int b = rest / nb;
+  const int sx = rest % nbx;
+  rest /= nbx;
+  const int sy = rest % nby;
+  const int b = rest / nby;
   if (a.chunk_base + b >= *a.count) return;
   const int4 t = reinterpret_cast<const int4*>(a.list)[a.chunk_base + b];
   const SlideDev& sd = a.slides[t.x];
   const int k = a.scale_k[t.y];
   const int oy = t.z * a.scale_s[t.y], ox = t.w * a.scale_s[t.y];  // tile origin at scale k
   const float scale = 1.0f / (255.0f * (float)(1 << (2 * k)));
-  for (int i = threadIdx.x; i < 18 * 18; i += 256) {
+  for (int i = threadIdx.x; i < (BH + 2) * 18; i += 256) {
     const int py = i / 18, px = i % 18;
-    const int ty = sy * 16 + py - 1, tx = sx * 16 + px - 1;
+    const int ty = sy * BH + py - 1, tx = sx * 16 + px - 1;
     float v0 = 0.f, v1 = 0.f, v2 = 0.f;
     if (ty >= 0 && ty < a.T && tx >= 0 && tx < a.T) {
       const int Y = oy + ty, X = ox + tx;
@@ -1228,8 +1234,7 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
   // weights [16 output channels x 4 K], B = the im2col rows of 16 pixels
   // [4 K x 16 pixels], K = 27 taps x channels padded to 28 (seven steps).
   // Lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; the accumulator
-  // holds channels 4 (l / 16) .. + 3 of pixel l % 16.  A wave computes four
-  // output rows of the block.
+  // holds channels 4 (l / 16) .. + 3 of pixel l % 16.
   constexpr int KS = 7, MAXM = 8;  // C_0 <= 128: at most eight 16-channel fragments
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
@@ -1248,16 +1253,20 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
   for (int ks = 0; ks < KS; ++ks) {
     const int k = 4 * ks + g;
     const int c = k / 9, dy = (k % 9) / 3, dx = k % 3;
-    koff[ks] = k < 27 ? (c * 18 + dy) * 19 + dx : -1;
+    koff[ks] = k < 27 ? (c * (BH + 2) + dy) * 19 + dx : -1;
   }
   const float* sflat = &sIn[0][0][0];
-  for (int r = 0; r < 4; ++r) {
-    const int py = wave * 4 + r;
+  // A wave's 16 output pixels of one row are contiguous in the output (16 x
+  // c0_p values): they are staged in LDS and written as 16-byte vectors.
+  T* srow = sOut[wave];
+  const int pitch = a.c0_p + OPAD;  // staged row pitch, padded against bank conflicts
+  const int vpp = a.c0_p * (int)sizeof(T) / 16;  // 16-byte vectors per pixel
+  constexpr int VE = 16 / (int)sizeof(T);
+  for (int r = 0; r < RPW; ++r) {
+    const int py = wave * RPW + r;
     float xb[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) xb[ks] = koff[ks] >= 0 ? sflat[koff[ks] + py * 19 + l16] : 0.f;
-    const int y = sy * 16 + py, x = sx * 16 + l16;
-    T* out = (T*)a.y + (((int64_t)b * a.T + y) * a.T + x) * a.c0_p;
 #pragma unroll
     for (int m = 0; m < MAXM; ++m) {
       if (m >= nm) break;
@@ -1273,22 +1282,41 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
         if (std::is_same<T, uint8_t>::value && o < a.c0) t *= a.oinv[o];
         v[q] = t;
       }
-      store4(out + m * 16 + 4 * g, v);
+      store4(srow + l16 * pitch + m * 16 + 4 * g, v);
     }
+    // the wave reads back what its own lanes wrote (LDS keeps a wave's
+    // accesses in order; the fence keeps the compiler from moving them)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int y = sy * BH + py;
+    T* out = (T*)a.y + (((int64_t)b * a.T + y) * a.T + sx * 16) * a.c0_p;
+    for (int v = lane; v < 16 * vpp; v += 64) {
+      const int px = v / vpp, j = v % vpp;
+      *reinterpret_cast<uint4*>(out + v * VE) = *reinterpret_cast<const uint4*>(srow + px * pitch + j * VE);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
 hipError_t launch_first_conv(int precision, const FirstConvArgs& a, hipStream_t st) {
-  if (a.c0 > kFirstMaxC0 || a.T % 16) return hipErrorInvalidValue;
-  const int nb = a.T / 16;
-  const int64_t blocks = (int64_t)a.batch * nb * nb;
+  if (a.c0 > kFirstMaxC0 || a.T % 16 || a.c0_p % 16) return hipErrorInvalidValue;
+  const bool tall = a.T % 64 == 0;
+  const int64_t blocks = (int64_t)a.batch * (a.T / 16) * (a.T / (tall ? 64 : 16));
+  const dim3 grid((unsigned)blocks);
   if (precision == OMNISEG_FP8) {
     if (!a.oinv) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_first_conv<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, st, a);
-  } else if (precision == OMNISEG_BF16)
-    hipLaunchKernelGGL(k_first_conv<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_first_conv<float>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    if (tall) hipLaunchKernelGGL((k_first_conv<uint8_t, 64>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_first_conv<uint8_t, 16>), grid, dim3(256), 0, st, a);
+  } else if (precision == OMNISEG_BF16) {
+    if (tall) hipLaunchKernelGGL((k_first_conv<uint16_t, 64>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_first_conv<uint16_t, 16>), grid, dim3(256), 0, st, a);
+  } else {
+    if (tall) hipLaunchKernelGGL((k_first_conv<float, 64>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_first_conv<float, 16>), grid, dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 
