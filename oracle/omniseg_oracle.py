@@ -217,8 +217,8 @@ def tissue_map(rgb, kc, threshold=220):
 
 
 # --------------------------------------------------------------------------
-# O3b  Otsu tissue detection (Section 2.1; Section 3.2: Otsu, median blur,
-#      removal of tiny noise from the foreground contour)
+# O3b  Otsu tissue detection (Section 2.1; Section 3.2: Otsu threshold,
+#      median blur, small noise components dropped from the foreground)
 # --------------------------------------------------------------------------
 
 
