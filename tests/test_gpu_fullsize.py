@@ -159,3 +159,122 @@ def test_sampled_stitch_pixels(run):
     print(f"stitched pixels checked {checked} ({covered} covered by kept tiles), inside the rounding band "
           f"{skipped}", flush=True)
     assert skipped <= checked // 100 and covered >= 100 * len(run["pairs"])
+
+
+# ------------------------------------------------------------------ the paper's tiling at full size
+
+@pytest.fixture(scope="module")
+def paper_run():
+    """The benchmark's paper-tiling leg: 512^2 tiles at 40x/10x/5x with strides
+    256/64/64, majority vote 1/4/4, Otsu tissue map (median 59, components of
+    fewer than 64 coarse pixels removed), BF16."""
+    print(f"full-size run: {SIZE}^2 strip slide, the paper's tiling, BF16", flush=True)
+    rgb, _ = synth.strip_slide(2, SIZE, SIZE, fg_frac=0.30, with_gt=False)
+    C = bench.PAPER_CFG
+    flat = synth.he_normal_weights(12, C["base"], C["levels"], C["n_classes"], len(C["scales"]), C["head_out"])
+    pairs = [(c, si) for si in range(len(C["scales"])) for c in range(C["n_classes"])]
+    dslide = torch.from_numpy(rgb).to(DEV)
+    plan = bench._plan(om, "bf16", 0, cfg=C)
+    ws = torch.empty(plan.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=DEV)
+    packed = plan.pack(torch.from_numpy(flat).to(DEV))
+    outs = plan.alloc_outputs([dslide], pairs)
+    plan.autotune([dslide], pairs, packed, ws)
+    plan.segment([dslide], pairs, packed, workspace=ws, outputs=outs)
+    torch.cuda.synchronize()
+    yield dict(rgb=rgb, flat=flat, pairs=pairs, dslide=dslide, plan=plan, ws=ws, masks=outs[0][0],
+               cfg=O.make_config(**C))
+    del ws, outs, dslide
+    torch.cuda.empty_cache()
+
+
+def test_paper_tiling_tissue_and_tile_list(paper_run):
+    """Median-blurred gray map at sampled pixels (the oracle's median on a
+    window-sized crop), Otsu threshold of the GPU's blurred map, component
+    filter and tile list bit for bit."""
+    r, cfg = paper_run, paper_run["cfg"]
+    kc, m = max(cfg["scales"]), cfg["median_kernel"]
+    g = O.gray8(r["rgb"], kc)
+    Hc, Wc = g.shape
+    blurred = _region(r, om.REGION_TISSUE_GRAY).cpu().numpy().reshape(Hc, Wc).astype(np.int64)
+    h = m // 2
+    rng = np.random.default_rng(13)
+    pts = [(0, 0), (0, Wc - 1), (Hc - 1, 0), (Hc - 1, Wc - 1)] + [tuple(p) for p in rng.integers(0, Hc, (6, 2))]
+    for y, x in pts:
+        y0, x0 = max(0, y - h), max(0, x - h)
+        crop = g[y0:min(Hc, y + h + 1), x0:min(Wc, x + h + 1)]  # the whole window, with the slide's own edges
+        assert blurred[y, x] == O.median_blur(crop, m)[y - y0, x - x0], (y, x)
+    stats = _region(r, om.REGION_TISSUE_STATS).view(torch.int32).cpu().numpy()
+    t = O.otsu_threshold(blurred)
+    assert stats[0] == t
+    lab, sizes = O.components8(blurred <= t)
+    keep = {k for k, n in sizes.items() if n >= cfg["min_tissue_area"]}
+    ref_fg = np.isin(lab, list(keep)) & (blurred <= t)
+    assert (stats[1], stats[2]) == (len(sizes), len(keep))
+    fg = _region(r, om.REGION_TISSUE).cpu().numpy().reshape(Hc, Wc).astype(bool)
+    assert np.array_equal(fg, ref_fg)
+    ref_list = O.tile_list([r["rgb"].shape[:2]], cfg, [ref_fg])
+    cnt = int(_region(r, om.REGION_TILE_COUNT).view(torch.int32)[0].item())
+    assert cnt == len(ref_list)
+    got = _region(r, om.REGION_TILE_LIST).view(torch.int32).view(-1, 4)[:cnt].cpu().numpy()
+    assert [tuple(v) for v in got] == ref_list
+    r["ref_list"] = ref_list
+    print(f"Otsu threshold {t}, components {len(sizes)} (kept {len(keep)}), {cnt} kept tiles", flush=True)
+
+
+def test_paper_tiling_sampled_tile(paper_run):
+    r, cfg = paper_run, paper_run["cfg"]
+    if "ref_list" not in r:
+        pytest.skip("needs the tile list of test_paper_tiling_tissue_and_tile_list")
+    T = cfg["tile"]
+    tl = _region(r, om.REGION_TILE_LOGITS).view(torch.float32).view(-1, cfg["n_classes"], T, T)
+    wts = O.unpack_weights(r["flat"], cfg)
+    li = len(r["ref_list"]) // 2
+    _, si, jy, jx = r["ref_list"][li]
+    x = O.tile_input(r["rgb"], cfg["scales"][si], T, O.stride_of(cfg, si), jy, jx)
+    classes = list(range(cfg["n_classes"]))
+    ref = O.tile_logits(x, wts, cfg, si, classes)
+    emu = O.tile_logits(x, O.bf16_weights(wts), cfg, si, classes, store=O.round_bf16)
+    err = M.normwise_error(tl[li].double().cpu().numpy(), ref)
+    emu_vs_ref = M.normwise_error(emu, ref)
+    print(f"tile {r['ref_list'][li]}: bf16 vs fp64 {err:.3e} (exact bf16 arithmetic {emu_vs_ref:.3e})", flush=True)
+    assert err <= max(BF16_TOL, 2.0 * emu_vs_ref)
+
+
+def test_paper_tiling_sampled_vote_pixels(paper_run):
+    """Mask = (at least vote_threshold of the covering kept tiles predict the
+    class), counted from the GPU's own FP32 tile logits: exact integers."""
+    r, cfg = paper_run, paper_run["cfg"]
+    T, C = cfg["tile"], cfg["n_classes"]
+    tl = _region(r, om.REGION_TILE_LOGITS).view(torch.float32).view(-1, C, T, T)
+    rng = np.random.default_rng(17)
+    on = covered = 0
+    for p, (c, si) in enumerate(r["pairs"]):
+        k, s, vt = cfg["scales"][si], O.stride_of(cfg, si), cfg["vote_thresholds"][si]
+        Hk = O.level_size(SIZE, k)
+        n = O.grid_count(Hk, T, s)
+        idx = _region(r, om.REGION_TILE_INDEX, si).view(torch.int32).cpu().numpy().reshape(n, n)
+        kept = np.argwhere(idx >= 0)
+        pick = kept[rng.integers(0, len(kept), 150)]
+        ys = np.concatenate([[0, Hk - 1], rng.integers(0, Hk, 30), np.minimum(pick[:, 0] * s + rng.integers(0, T, 150), Hk - 1)])
+        xs = np.concatenate([[0, Hk - 1], rng.integers(0, Hk, 30), np.minimum(pick[:, 1] * s + rng.integers(0, T, 150), Hk - 1)])
+        rows = []
+        for q, (y, x) in enumerate(zip(ys, xs)):
+            for jy in range(0 if y < T else (y - T) // s + 1, min(n - 1, y // s) + 1):
+                for jx in range(0 if x < T else (x - T) // s + 1, min(n - 1, x // s) + 1):
+                    if idx[jy, jx] >= 0:
+                        rows.append((q, idx[jy, jx], y - jy * s, x - jx * s))
+        votes = np.zeros(len(ys), np.int64)
+        cover = np.zeros(len(ys), np.int64)
+        if rows:
+            a = np.array(rows, dtype=np.int64)
+            vals = tl[torch.from_numpy(a[:, 1]).to(DEV), c, torch.from_numpy(a[:, 2]).to(DEV),
+                      torch.from_numpy(a[:, 3]).to(DEV)].cpu().numpy()
+            np.add.at(votes, a[:, 0], (vals > 0).astype(np.int64))
+            np.add.at(cover, a[:, 0], 1)
+        want = (cover > 0) & (votes >= vt)
+        mask = r["masks"][p][torch.from_numpy(ys).to(DEV), torch.from_numpy(xs).to(DEV)].cpu().numpy().astype(bool)
+        assert np.array_equal(mask, want), (c, si)
+        on += int(want.sum())
+        covered += int((cover > 0).sum())
+    print(f"vote pixels checked {covered} covered, {on} on", flush=True)
+    assert covered >= 100 * len(r["pairs"]) and on > 0
