@@ -541,7 +541,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
-                                   "part of this build (--gpus must be 1)"}))
+                                   "supported: the path runs on one GPU (--gpus must be 1)"}))
         sys.exit(2)
 
     import torch
