@@ -579,6 +579,9 @@ void k_conv3x3_rows(ConvArgs a) {
   // loads and the LDS address arithmetic with the MFMAs.
   for (int ch = 0; ch < nchunks; ++ch) {
     st.fetch(a, min(ch + 1, nchunks - 1), hreg, wreg, ch + 1 < nchunks);
+    // Waves in their MFMA phase issue first.  Measured per layer: 1.5-2.3 %
+    // faster for the upsample-and-concat convs, 4 % slower for residual ones.
+    if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
       uint4 xv[FM + 2];
@@ -602,6 +605,7 @@ void k_conv3x3_rows(ConvArgs a) {
           for (int fn = 0; fn < FN; ++fn) mma(acc[fm][fn], wv[fn], xv[fm + dy], T());
       }
     }
+    if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     ST::commit(tid, hreg, wreg, sX, sW);
     __syncthreads();
