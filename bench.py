@@ -54,33 +54,61 @@ CLASS_COLOURS = ((230, 25, 75), (60, 180, 75), (255, 225, 25), (0, 130, 200), (2
 # 0.5 GiB, WRITE_SIZE 1 GiB).  They describe the conv source whose SHA-256 is
 # stored here; any other source, or another kernel, reports null.
 MEASURED_TRAFFIC = {
-    "conv_source_sha256": "5be2350eda8c6ae3025bc3bb0e32e0bb48a2ca8048d9a29474325add2b3be543",
+    "conv_source_sha256": "df60ca2832996292f2767ffc04b2e5af132a81caefe64f15780ffcd0d48dff57",
+    # bytes per launch of each layer (stage + level) for the kernels that can
+    # dominate the BF16 step: FETCH_SIZE x 2 and WRITE_SIZE x 1 (scales from a
+    # 1 GiB device copy), over the 8 tile batches of one step
     "kernels": {
-        # decoder upsample-and-concat conv_a, 4 levels x 8 tile batches
-        "omniseg::k_conv3x3_rows<16, 64, 4, 2, 2, 0>": dict(launches=32, fetch_bytes_per_launch=2631464550.9,
-                                                             write_bytes_per_launch=921108480.0),
-        # residual convs (encoder and decoder conv_b), 9 layers x 8 tile batches
-        "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 1>": dict(launches=72, fetch_bytes_per_launch=1454147688.1,
-                                                             write_bytes_per_launch=934754531.6),
+        "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 0>": {
+            "enc_a1": (492553843, 982515712),
+            "enc_a2": (250478718, 491257856),
+            "enc_a3": (216427240, 245628928),
+            "enc_a4": (1151374692, 122814464),
+        },
+        "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 1>": {
+            "dec_b0": (1986845367, 1965031424),
+            "dec_b1": (1027714927, 982515712),
+            "dec_b2": (762472929, 491257856),
+            "dec_b3": (1485421311, 245628928),
+            "enc_b0": (2000175206, 2456289280),
+            "enc_b1": (1070010838, 1228144640),
+            "enc_b2": (876072293, 614072320),
+            "enc_b3": (1484981362, 307036160),
+            "enc_b4": (2428677081, 122814464),
+        },
+        "omniseg::k_conv3x3_rows<16, 64, 4, 2, 2, 0>": {
+            "dec_a0": (2951200999, 1965031424),
+            "dec_a1": (1497275472, 982515712),
+            "dec_a2": (2388590543, 491257856),
+            "dec_a3": (3659710151, 245628928),
+        },
     },
 }
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, records):
+    """HBM bytes per launch of `kernel` averaged over its launches in
+    `records`, from the per-layer counter measurements; None when the conv
+    source changed since, or a layer it ran for was not measured."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_2305_14566_amd", "csrc", "k_conv.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     k = MEASURED_TRAFFIC["kernels"].get(kernel)
-    if k is None or sha != MEASURED_TRAFFIC["conv_source_sha256"]:
+    if k is None or sha != MEASURED_TRAFFIC["conv_source_sha256"] or not records:
         return None
-    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+    per = [k.get(f"{r['stage']}{r['level']}") for r in records]
+    if any(v is None for v in per):
+        return None
+    return sum(f + w for f, w in per) / len(per)
 
 
 def conv_symbol(om, prec, stage, config):
     """Kernel symbol (as rocprofv3 prints it) that a conv launch uses."""
-    loader, epi = {"enc_a": (1, 0), "enc_b": (0, 1), "dec_a": (2, 0), "dec_b": (0, 1)}[stage]
+    # BF16 and FP8 fuse the max-pool into the encoder's residual conv, so
+    # conv_a then reads the pooled tensor with the plain loader
+    loader, epi = {"enc_a": (1 if prec == "fp32" else 0, 0), "enc_b": (0, 1), "dec_a": (2, 0), "dec_b": (0, 1)}[stage]
     by, bx, bn, wm, wn = om.conv_config(config)
     if prec == "fp8":
         return f"omniseg::k_conv3x3_fp8<{by}, {bn}, {wm}, {wn}, {loader}, {epi}>"
@@ -97,7 +125,8 @@ def roofline(om, records, prec):
         if r["stage"] not in ("enc_a", "enc_b", "dec_a", "dec_b"):
             continue
         sym = conv_symbol(om, prec, r["stage"], r["config"])
-        g = groups.setdefault(sym, dict(n=0, flops=0.0, ms=0.0, bytes=0.0))
+        g = groups.setdefault(sym, dict(n=0, flops=0.0, ms=0.0, bytes=0.0, recs=[]))
+        g["recs"].append(r)
         g["n"] += 1
         g["flops"] += r["flops"]
         g["ms"] += r["ms"]
@@ -109,7 +138,7 @@ def roofline(om, records, prec):
     return dict(bound="mfma", kernel=sym, launches=g["n"],
                 flops_per_launch=g["flops"] / g["n"], avg_launch_ms=g["ms"] / g["n"],
                 achieved=achieved, peak=PEAK_TFLOPS[prec], unit="TFLOP/s",
-                frac=achieved / PEAK_TFLOPS[prec], traffic=measured_traffic(sym),
+                frac=achieved / PEAK_TFLOPS[prec], traffic=measured_traffic(sym, g["recs"]),
                 algorithmic_bytes_per_launch=g["bytes"] / g["n"],
                 all_convs_tflops=conv_flops / (conv_ms * 1e-3) / 1e12,
                 all_convs_frac=conv_flops / (conv_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec])
@@ -121,9 +150,11 @@ def layer_summary(records, steps):
     for r in records:
         if r["stage"] not in ("enc_a", "enc_b", "dec_a", "dec_b"):
             continue
-        s = out.setdefault(f"{r['stage']}{r['level']}", dict(ms=0.0, flops=0.0, launches=0, config=r["config"]))
+        s = out.setdefault(f"{r['stage']}{r['level']}", dict(ms=0.0, flops=0.0, bytes=0.0, launches=0,
+                                                             config=r["config"]))
         s["ms"] += r["ms"] / steps
         s["flops"] += r["flops"] / steps
+        s["bytes"] += r["bytes"] / steps
         s["launches"] += 1
     for s in out.values():
         s["tflops"] = s["flops"] / max(s["ms"], 1e-9) / 1e9
@@ -157,7 +188,7 @@ def _plan(om, prec, batch_tiles, cfg=CFG, emit_logits=False):
                    median_kernel=cfg.get("median_kernel", 1), min_tissue_area=cfg.get("min_tissue_area", 0))
 
 
-def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles, calib_tiles=64, cfg=CFG):
+def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles, calib_tiles=64, cfg=CFG, pin=None):
     plan = _plan(om, prec, batch_tiles, cfg)
     ws = torch.empty(plan.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
     extra = {}
@@ -179,6 +210,10 @@ def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles
     plan.autotune([dslide], pairs, packed, ws)
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t_tune
+    if pin is not None:  # one configuration for every conv layer (where it is valid)
+        for stage in range(4):
+            for level in range(cfg["levels"]):
+                plan.set_conv_tuning(stage, level, pin)
     for _ in range(warmup):
         plan.segment([dslide], pairs, packed, workspace=ws, outputs=outs)
     torch.cuda.synchronize()
@@ -535,6 +570,11 @@ def main():
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device to device (a plain copy of known size for "
                          "scaling profiler byte counters)")
+    ap.add_argument("--pin-config", type=int, default=None,
+                    help="after autotuning, run every conv layer of the BF16 leg with this tile configuration "
+                         "where it is valid (repeatable launch sets for counter runs)")
+    ap.add_argument("--dump-launches", action="store_true",
+                    help="add the (stage, level, config) of every timed BF16 conv launch to the JSON line")
     ap.add_argument("--workload", choices=["slide", "batch16"], default="slide",
                     help="slide: the 8192^2 slide (default); batch16: 16 uneven slides, batched vs per slide")
     args = ap.parse_args()
@@ -577,7 +617,8 @@ def main():
         del src, dst
     print(f"# slide {args.size}^2 generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
-    bf = run_leg(om, torch, dslide, flat_dev, pairs, "bf16", args.steps, args.warmup, args.batch_tiles)
+    bf = run_leg(om, torch, dslide, flat_dev, pairs, "bf16", args.steps, args.warmup, args.batch_tiles,
+                 pin=args.pin_config)
     print(f"# bf16: {bf['ms']:.1f} ms/step, {bf['kept']} kept tiles", file=sys.stderr, flush=True)
     px = args.size * args.size * len(pairs)
     result = {
@@ -595,6 +636,11 @@ def main():
         "layers_bf16": layer_summary(bf["records"], args.steps),
         "autotuned_conv_tiles_bf16": bf["tuned"],
     }
+    if args.pin_config is not None:
+        result["pinned_conv_config_bf16"] = args.pin_config
+    if args.dump_launches:
+        result["launches_bf16"] = [[r["stage"], r["level"], r["config"]] for r in bf["records"]
+                                   if r["stage"] in ("enc_a", "enc_b", "dec_a", "dec_b")]
     st = result["stages_bf16"].get("stitch")
     if st:
         result["roofline_stitch"] = dict(bound="hbm", achieved=st["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",

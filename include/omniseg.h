@@ -600,6 +600,20 @@ int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* b
 int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_slide* slides,
                          int32_t n_slides, const omniseg_pair* pairs, int32_t n_pairs,
                          void* workspace, int64_t ws_bytes, omniseg_stream stream);
+/*
+ * The conv tile configuration of one backbone layer.  stage: 0 = encoder
+ * conv_a, 1 = encoder residual conv, 2 = decoder conv_a (upsample + concat),
+ * 3 = decoder residual conv; level 0 .. levels - 1.  omniseg_autotune sets
+ * them; omniseg_set_conv_tuning pins one (config -1 = the default), for
+ * instance to repeat a tuned table in another process.  A configuration that
+ * is not valid for the layer's shape and precision is ignored when the layer
+ * runs (the default runs instead; an encoder residual conv that also writes
+ * the pooled copy takes the first valid row-reuse configuration).  Host-only,
+ * no GPU work.  ERR_ARG for a NULL plan or output, or a stage, level or
+ * config out of range.
+ */
+int32_t omniseg_set_conv_tuning(omniseg_plan* plan, int32_t stage, int32_t level, int32_t config);
+int32_t omniseg_get_conv_tuning(const omniseg_plan* plan, int32_t stage, int32_t level, int32_t* config);
 /* Waits for the last profiled call's events; copies min(cap, n) records to
  * recs (host array) and the total number of records to *n. */
 int32_t omniseg_read_profile(omniseg_plan* plan, omniseg_launch_record* recs, int32_t cap,

@@ -921,11 +921,13 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
     float* logits = reinterpret_cast<float*>(ws + lay.off_logits);
     auto layer = [&](const ConvDesc& d) { return make_layer(plan, pk, d); };
     const int es = elem_size(prec);
-    // algorithmic work of one 3x3 conv launch over `nt` tiles at h x h
+    // algorithmic work of one 3x3 conv launch over `nt` tiles at h x h: input,
+    // output and weights once (a residual conv adds its own input, so the
+    // residual costs no bytes of its own)
     auto conv_flops = [&](const ConvDesc& d, int h, int nt) { return 2.0 * 9 * d.cin * d.cout * (double)h * h * nt; };
-    auto conv_bytes = [&](const ConvDesc& d, int h, int nt, double in_px_factor, bool res) {
+    auto conv_bytes = [&](const ConvDesc& d, int h, int nt, double in_px_factor) {
       const double px = (double)h * h * nt;
-      return px * in_px_factor * d.cin * es + px * d.cout * es * (res ? 2 : 1) + 9.0 * d.cin * d.cout * es;
+      return px * in_px_factor * d.cin * es + px * d.cout * es + 9.0 * d.cin * d.cout * es;
     };
     const int B = lay.batch;
     FirstConvArgs fa{};
@@ -964,7 +966,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
           HIP_TRY(launch_conv3x3(prec, fp ? LOAD_PLAIN : LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count,
                                  base, fp ? P : E[l - 1], nullptr, A, sm, nullptr, cf));
           HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nb, conv_flops(plan->enc_a[l], tl, nb),
-                           conv_bytes(plan->enc_a[l], tl, nb, fp ? 1.0 : 4.0, false), cf));
+                           conv_bytes(plan->enc_a[l], tl, nb, fp ? 1.0 : 4.0), cf));
         }
         HIP_TRY(prof.begin());
         ConvLayer lb = layer(plan->enc_b[l]);
@@ -979,7 +981,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
         HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, lb, tl, tl, nb, count, base, A, nullptr, E[l], sm,
                                nullptr, cf));
         HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nb, conv_flops(plan->enc_b[l], tl, nb),
-                         conv_bytes(plan->enc_b[l], tl, nb, 1.0, true) + pooled_bytes, cf));
+                         conv_bytes(plan->enc_b[l], tl, nb, 1.0) + pooled_bytes, cf));
       }
       const int tb = T >> (L - 1);
       HIP_TRY(prof.begin());
@@ -997,11 +999,11 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
         HIP_TRY(prof.begin());
         int cf = layer_config(plan, 2, l, tl, tl, plan->dec_a[l].cout_p);
         HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1], E[l], A, sm, nullptr, cf));
-        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nb, conv_flops(plan->dec_a[l], tl, nb), conv_bytes(plan->dec_a[l], tl, nb, 0.5, false), cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nb, conv_flops(plan->dec_a[l], tl, nb), conv_bytes(plan->dec_a[l], tl, nb, 0.5), cf));
         HIP_TRY(prof.begin());
         cf = layer_config(plan, 3, l, tl, tl, plan->dec_b[l].cout_p);
         HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm, nullptr, cf));
-        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nb, conv_flops(plan->dec_b[l], tl, nb), conv_bytes(plan->dec_b[l], tl, nb, 1.0, true), cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nb, conv_flops(plan->dec_b[l], tl, nb), conv_bytes(plan->dec_b[l], tl, nb, 1.0), cf));
       }
       HIP_TRY(prof.begin());
       HIP_TRY(launch_head(prec, E[0], nb, T, plan->C[0], plan->Cp[0],
@@ -1205,6 +1207,23 @@ int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_s
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return result;
+}
+
+int32_t omniseg_set_conv_tuning(omniseg_plan* plan, int32_t stage, int32_t level, int32_t config) {
+  if (!plan) return fail(OMNISEG_ERR_ARG, "plan is NULL");
+  if (stage < 0 || stage > 3 || level < 0 || level >= plan->L)
+    return fail(OMNISEG_ERR_ARG, "no conv layer at stage %d, level %d", stage, level);
+  if (config < -1 || config >= CONV_CFG_COUNT) return fail(OMNISEG_ERR_ARG, "unknown conv config %d", config);
+  plan->tune[stage][level] = config;
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_get_conv_tuning(const omniseg_plan* plan, int32_t stage, int32_t level, int32_t* config) {
+  if (!plan || !config) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  if (stage < 0 || stage > 3 || level < 0 || level >= plan->L)
+    return fail(OMNISEG_ERR_ARG, "no conv layer at stage %d, level %d", stage, level);
+  *config = plan->tune[stage][level];
+  return OMNISEG_OK;
 }
 
 int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable) {

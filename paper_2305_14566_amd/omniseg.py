@@ -119,6 +119,8 @@ def _declare(lib):
         "omniseg_stitch_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
         "omniseg_stitch_tiles": (i32, [i32, i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, i64, vp, i64, vp]),
         "omniseg_set_profiling": (i32, [vp, i32]),
+        "omniseg_set_conv_tuning": (i32, [vp, i32, i32, i32]),
+        "omniseg_get_conv_tuning": (i32, [vp, i32, i32, P(i32)]),
         "omniseg_conv_config": (i32, [i32, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]),
         "omniseg_autotune": (i32, [vp, vp, P(Slide), i32, P(Pair), i32, vp, i64, vp]),
         "omniseg_plane_offsets": (i32, [vp, P(Slide), P(Pair), i32, P(i64)]),
@@ -258,6 +260,16 @@ class Plan:
         sl, pr = self._arrays(slides, pairs)
         _check(lib().omniseg_autotune(self._h, _ptr(packed), sl, len(slides), pr, len(pairs), _ptr(workspace),
                                       workspace.numel(), _stream(stream)))
+
+    def set_conv_tuning(self, stage, level, config):
+        """Pin the tile configuration of one conv layer (stage 0 enc_a, 1 enc_b,
+        2 dec_a, 3 dec_b; config -1 = the default)."""
+        _check(lib().omniseg_set_conv_tuning(self._h, stage, level, config))
+
+    def get_conv_tuning(self, stage, level):
+        v = ctypes.c_int32()
+        _check(lib().omniseg_get_conv_tuning(self._h, stage, level, ctypes.byref(v)))
+        return v.value
 
     def pack(self, canonical, stream=None):
         """Canonical FP32 weights (device tensor) -> packed device buffer (uint8)."""

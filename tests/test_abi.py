@@ -435,3 +435,21 @@ def test_fp8_plan_validation_and_activation_table():
     pr = (om.Pair * 1)()
     assert lib.omniseg_calibrate_fp8(p8._h, FAKE, sl, 1, pr, 1, 64, FAKE, FAKE, 1 << 40, None) == 1
     assert lib.omniseg_calibrate_fp8(p32._h, FAKE, sl, 1, pr, 1, 0, FAKE, FAKE, 1 << 40, None) == 1
+
+
+def test_conv_tuning_get_set():
+    """Tuning entries start at -1 (default), can be pinned per layer and read
+    back, and out-of-range stages, levels and configurations are refused."""
+    p = om.Plan(base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=64, stride=32)
+    assert all(p.get_conv_tuning(st, l) == -1 for st in range(4) for l in range(3))
+    p.set_conv_tuning(2, 1, 10)
+    p.set_conv_tuning(1, 0, 0)
+    assert p.get_conv_tuning(2, 1) == 10 and p.get_conv_tuning(1, 0) == 0 and p.get_conv_tuning(2, 0) == -1
+    p.set_conv_tuning(2, 1, -1)
+    assert p.get_conv_tuning(2, 1) == -1
+    for st, l, c in [(4, 0, 0), (-1, 0, 0), (0, 3, 0), (0, -1, 0), (0, 0, om.N_CONV_CONFIGS), (0, 0, -2)]:
+        with pytest.raises(om.OmnisegError) as e:
+            p.set_conv_tuning(st, l, c)
+        assert e.value.status == 1  # OMNISEG_ERR_ARG
+    with pytest.raises(om.OmnisegError):
+        p.get_conv_tuning(0, 3)
