@@ -1188,6 +1188,7 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
   constexpr int OPAD = 16 / (int)sizeof(T);             // one 16-byte slot per staged pixel row
   constexpr int OPITCH = kFirstMaxC0 + OPAD;            // staged values per pixel (at most)
   __shared__ float sIn[3][BH + 2][19];
+  __shared__ float sBias[kFirstMaxC0], sOinv[kFirstMaxC0];  // zero / one beyond c0
   __shared__ __attribute__((aligned(16))) T sOut[4][16 * OPITCH];
   const int nbx = a.T / 16, nby = a.T / BH;
   int rest = blockIdx.x;
@@ -1233,6 +1234,11 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
     sIn[1][py][px] = v1;
     sIn[2][py][px] = v2;
   }
+  if (threadIdx.x < kFirstMaxC0) {
+    const int o = threadIdx.x;
+    sBias[o] = o < a.c0 ? a.b[o] : 0.f;
+    sOinv[o] = (std::is_same<T, uint8_t>::value && o < a.c0) ? a.oinv[o] : 1.f;
+  }
   __syncthreads();
   // The 3 -> C_0 conv as a GEMM on FP32 MFMA (v_mfma_f32_16x16x4f32): A =
   // weights [16 output channels x 4 K], B = the im2col rows of 16 pixels
@@ -1244,12 +1250,16 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
   const int g = lane >> 4, l16 = lane & 15;
   const int nm = a.c0_p / 16;
   float wa[MAXM][KS];
+  // Branch-free (an out-of-range entry loads element 0 and is replaced by
+  // zero), so the 56 loads are in flight together instead of one by one.
 #pragma unroll
   for (int m = 0; m < MAXM; ++m)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int o = m * 16 + l16, k = 4 * ks + g;
-      wa[m][ks] = (m < nm && o < a.c0 && k < 27) ? a.w[o * 27 + k] : 0.f;
+      const bool ok = m < nm && o < a.c0 && k < 27;
+      const float v = a.w[ok ? o * 27 + k : 0];
+      wa[m][ks] = ok ? v : 0.f;
     }
   // im2col offsets inside sIn of this lane's K entries (k = c*9 + dy*3 + dx)
   int koff[KS];
@@ -1280,10 +1290,11 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
       float v[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        // channels at or beyond c0 have zero weights and bias: t = 0 there
         const int o = m * 16 + 4 * g + q;
-        float t = o < a.c0 ? acc[q] + a.b[o] : 0.f;
+        float t = acc[q] + sBias[o];
         t = t > 0.f ? t : 0.f;
-        if (std::is_same<T, uint8_t>::value && o < a.c0) t *= a.oinv[o];
+        if (std::is_same<T, uint8_t>::value) t *= sOinv[o];
         v[q] = t;
       }
       store4(srow + l16 * pitch + m * 16 + 4 * g, v);
