@@ -181,12 +181,31 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
   if (pre && sizeof(T) < 4) {
 #pragma unroll
     for (int o = 0; o < 8; ++o) F[o] = bpc[o];
-    for (int c0v = 0; c0v < c0; c0v += V) {
+    // Whole 16-byte vectors first, the next one loaded while this one's FMAs
+    // run (an unguarded body keeps the loop one basic block), then the
+    // c0 % V channels of a partial vector; channels are summed in order.
+    const int c0f = c0 - c0 % V;
+    uint4 cur = *reinterpret_cast<const uint4*>(px);
+    for (int c0v = 0; c0v < c0f; c0v += V) {
+      const uint4 nxt = *reinterpret_cast<const uint4*>(px + min(c0v + V, c0_p - V));
       float v[V];
-      decode16<T>(*reinterpret_cast<const uint4*>(px + c0v), v);
+      decode16<T>(cur, v);
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const int c = c0v + k;
+        float x = v[k];
+        if constexpr (std::is_same<T, uint8_t>::value) x *= dscale[c];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) F[o] = fmaf(wpc[o * c0 + c], x, F[o]);
+      }
+      cur = nxt;
+    }
+    if (c0f < c0) {
+      float v[V];
+      decode16<T>(cur, v);
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int c = c0f + k;
         if (c < c0) {
           float x = v[k];
           if constexpr (std::is_same<T, uint8_t>::value) x *= dscale[c];
