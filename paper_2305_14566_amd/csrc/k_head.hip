@@ -102,7 +102,9 @@ hipError_t launch_gap(int precision, const void* e, int batch, int hw, int c_p, 
   return hipGetLastError();
 }
 
-// theta[b][slot][p]; one workgroup per tile.  W_c rows are row_len =
+constexpr int kCtrlRows = 16;  // output rows of one controller workgroup (four per wave)
+
+// theta[b][slot][p]; one workgroup per tile and group of kCtrlRows rows.  W_c rows are row_len =
 // G + n_classes + n_scales long.  The GAP part u[p] = W_c[p, :G] g is the same
 // for every class at the tile's scale, so it is formed once per tile and
 // shared by the tile's slots (same addition order as per slot).
@@ -121,11 +123,22 @@ __global__ __launch_bounds__(256) void k_controller(const float* __restrict__ g,
   for (int i = threadIdx.x; i < G; i += blockDim.x) sg[i] = gb[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // one wave per output row p: coalesced reads of W_c's row, wave reduction
-  for (int p = wave; p < P; p += 4) {
+  // one wave per output row p (blockIdx.y selects a group of kCtrlRows rows):
+  // coalesced reads of W_c's row, wave reduction
+  const int p_end = min(P, (int)(blockIdx.y + 1) * kCtrlRows);
+  for (int p = blockIdx.y * kCtrlRows + wave; p < p_end; p += 4) {
     const float* w = wc + (int64_t)p * row_len;
     float s = 0.f;
-    for (int i = lane; i < G; i += 64) s = fmaf(w[i], sg[i], s);
+    // sixteen loads in flight, then the FMAs in the same order as one at a time
+    int i = lane;
+    for (; i + 15 * 64 < G; i += 16 * 64) {
+      float wv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) wv[u] = w[i + u * 64];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s = fmaf(wv[u], sg[i + u * 64], s);
+    }
+    for (; i < G; i += 64) s = fmaf(w[i], sg[i], s);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane < ns) {
@@ -141,7 +154,7 @@ hipError_t launch_controller(const float* g, int batch, int G, const float* wc, 
                              int chunk_base, float* theta, hipStream_t st) {
   if (G > 4096) return hipErrorInvalidValue;
   const int g_stride = pad_ch(G);
-  hipLaunchKernelGGL(k_controller, dim3(batch), dim3(256), 0, st, g, g_stride, G, wc,
+  hipLaunchKernelGGL(k_controller, dim3(batch, ceil_div(P, kCtrlRows)), dim3(256), 0, st, g, g_stride, G, wc,
                      bc, P, G + n_classes + n_scales, n_classes, slots, max_slots, list, count,
                      chunk_base, theta);
   return hipGetLastError();
