@@ -593,8 +593,9 @@ int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* b
 /*
  * Autotune the conv tile configuration of every backbone layer for these
  * slides and pairs: each valid configuration runs on the plan's batch shape
- * in the workspace (whose contents it overwrites) and the fastest by HIP
- * events is kept in the plan for later omniseg_segment_slide calls.  Waits
+ * in the workspace (whose contents it overwrites), once untimed and five
+ * times timed by HIP events, and the fastest is kept in the plan for later
+ * omniseg_segment_slide calls.  Waits
  * for the stream.  Same arguments as omniseg_segment_slide without outputs.
  */
 int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_slide* slides,

@@ -1184,9 +1184,11 @@ int32_t omniseg_autotune(omniseg_plan* plan, const void* packed, const omniseg_s
       for (int cf = 0; cf < CONV_CFG_COUNT; ++cf) {
         if (!conv_config_valid(cf, prec, h, h, d.cout_p)) continue;
         if (pooled && cf < CONV_CFG_ROWS_16x16_64) continue;
+        // one untimed launch, then five timed ones (near-equal configurations
+        // otherwise swap places from run to run on timing noise)
         hipError_t e = launch_conv3x3(prec, loader, epi, Ly, h, h, B, count, 0, x0, x1, y, sm, nullptr, cf);
         if (e == hipSuccess) e = hipEventRecord(e0, sm);
-        for (int r = 0; r < 2 && e == hipSuccess; ++r)
+        for (int r = 0; r < 5 && e == hipSuccess; ++r)
           e = launch_conv3x3(prec, loader, epi, Ly, h, h, B, count, 0, x0, x1, y, sm, nullptr, cf);
         if (e == hipSuccess) e = hipEventRecord(e1, sm);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
