@@ -555,8 +555,10 @@ int32_t omniseg_bce_loss(const float* logit, const float* target, const uint8_t*
  * records a pair of HIP events around every kernel launch on the call's
  * stream, plus the launch's algorithmic work: FLOPs of the arithmetic the
  * method defines (2 per multiply-add, real channel counts, no padding) and
- * the HBM bytes the step must move at minimum.  omniseg_read_profile waits
- * for those events and returns the records of the last profiled call.
+ * the HBM bytes the step must move at minimum.  Records accumulate over
+ * profiled calls; omniseg_read_profile waits for their events and returns all
+ * of them (again on a repeated read), and the next profiled call after a read
+ * starts a new list, so several calls can run back to back and be read once.
  * Profiling creates HIP events lazily and is off by default.
  */
 #define OMNISEG_STAGE_PREP 0       /* pad colour, pyramid, tissue map, tile list */

@@ -720,8 +720,7 @@ int32_t omniseg_calibrate_fp8(const omniseg_plan* plan, const void* packed, cons
   char* ws = static_cast<char*>(workspace);
   const char* pk = static_cast<const char*>(packed);
   const omniseg_config& c = plan->cfg;
-  Prof prof{plan, sm};
-  plan->recs.clear();
+  Prof prof = profile_start(plan, sm);
   SlideDev* tab_dev = nullptr;
   int32_t n_kept = 0;
   st = build_tile_list(plan, slides, n_slides, lay, ws, sm, prof, &tab_dev, &n_kept);
@@ -894,8 +893,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   const char* pk = static_cast<const char*>(packed);
   const int T = c.tile, s = c.stride, prec = c.precision;
 
-  Prof prof{plan, sm};
-  plan->recs.clear();
+  Prof prof = profile_start(plan, sm);
   SlideDev* tab_dev = nullptr;
   int32_t n_kept = 0;
   {
@@ -1236,6 +1234,7 @@ int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable) {
 
 int32_t omniseg_read_profile(omniseg_plan* plan, omniseg_launch_record* recs, int32_t cap, int32_t* n) {
   if (!plan || !n || (cap > 0 && !recs)) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  plan->profile_read = true;  // the next profiled call starts a new list
   const int32_t total = (int32_t)plan->recs.size();
   for (int32_t i = 0; i < total; ++i) {
     float ms = 0.f;

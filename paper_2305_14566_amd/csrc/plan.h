@@ -60,8 +60,10 @@ struct omniseg_plan {
   mutable std::vector<int32_t> host_tab;             // host staging of tile lists and grids
   // conv tile configuration per (stage, level): stage 0 enc_a, 1 enc_b, 2 dec_a, 3 dec_b; -1 = default
   int tune[4][8];
-  // per-launch profiling (off by default)
+  // per-launch profiling (off by default); records accumulate over calls
+  // until omniseg_read_profile has returned them
   bool profiling = false;
+  mutable bool profile_read = false;
   mutable std::vector<hipEvent_t> events;
   mutable std::vector<omniseg_launch_record> recs;
   // captured graphs of omniseg_segment_slide, keyed by a hash of the arguments
@@ -119,5 +121,17 @@ struct Prof {
     return r;
   }
 };
+
+// The profiler of one call: continues the record list of earlier profiled
+// calls, or starts a new one once the list has been read.
+inline Prof profile_start(const omniseg_plan* p, hipStream_t st) {
+  if (p->profiling && p->profile_read) {
+    p->recs.clear();
+    p->profile_read = false;
+  }
+  Prof prof{p, st};
+  prof.next = p->recs.size();
+  return prof;
+}
 
 }  // namespace omniseg

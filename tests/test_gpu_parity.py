@@ -306,3 +306,27 @@ def test_graph_replay_matches_eager():
                 for p in range(len(pairs)):
                     assert torch.equal(masks[i][p], m_eager[i][p]), (prec, rep, i, p)
                     assert torch.equal(logits[i][p], l_eager[i][p]), (prec, rep, i, p)
+
+
+def test_profile_records_accumulate_until_read():
+    """Profiled calls append to one record list; a read returns all of them
+    (again on a repeated read) and the next profiled call starts a new list."""
+    slides, cfg, flat, pairs = _prep_case()
+    plan = _plan(cfg, om.FP32)
+    ds = [torch.from_numpy(np.ascontiguousarray(s)).to(DEV) for s in slides]
+    packed = plan.pack(torch.from_numpy(flat).to(DEV))
+    ws = torch.empty(plan.workspace_bytes(ds, pairs), dtype=torch.uint8, device=DEV)
+    outs = plan.alloc_outputs(ds, pairs)
+    plan.set_profiling(True)
+    plan.segment(ds, pairs, packed, workspace=ws, outputs=outs)
+    one = plan.read_profile()
+    assert one and plan.read_profile() == one
+    key = lambda recs: [(r["stage"], r["level"], r["tiles"], r["config"]) for r in recs]
+    plan.segment(ds, pairs, packed, workspace=ws, outputs=outs)
+    plan.segment(ds, pairs, packed, workspace=ws, outputs=outs)
+    two = plan.read_profile()
+    assert key(two) == key(one) * 2 and all(r["ms"] > 0 for r in two)
+    plan.set_profiling(False)
+    plan.segment(ds, pairs, packed, workspace=ws, outputs=outs)  # unprofiled: the list stays
+    assert plan.read_profile() == two
+    torch.cuda.synchronize()
