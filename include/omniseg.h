@@ -559,7 +559,9 @@ int32_t omniseg_bce_loss(const float* logit, const float* target, const uint8_t*
  * profiled calls; omniseg_read_profile waits for their events and returns all
  * of them (again on a repeated read), and the next profiled call after a read
  * starts a new list, so several calls can run back to back and be read once.
- * Profiling creates HIP events lazily and is off by default.
+ * Profiling creates HIP events lazily (two per launch, kept by the plan until
+ * it is destroyed, so read the records before the list grows without bound)
+ * and is off by default.
  */
 #define OMNISEG_STAGE_PREP 0       /* pad colour, pyramid, tissue map, tile list */
 #define OMNISEG_STAGE_FIRST_CONV 1 /* encoder level 0, first conv (3 -> C_0)     */
