@@ -137,6 +137,102 @@ __device__ __forceinline__ void stitch_span4(const StitchArgs& a, int x0, int y)
     *reinterpret_cast<float4*>(a.logit + (int64_t)y * a.logit_pitch + x0) = make_float4(out[0], out[1], out[2], out[3]);
 }
 
+// stitch_span4 when T <= 2 s, so at most 2 x 2 tiles cover a pixel: the four
+// index reads, then the four logit-vector reads, are issued together, and
+// the covering tiles are then taken in the same (jy, jx) order with the same
+// arithmetic.  A missing tile's read goes through a buffer resource with an
+// empty range, which returns zeros without touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const float* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ void stitch_span4_2x2(const StitchArgs& a, int x0, int y) {
+  const int T = a.T, s = a.s;
+  const int jy0 = (y < T) ? 0 : (y - T) / s + 1, jy1 = min(a.ny - 1, y / s);
+  const int jx0 = (x0 < T) ? 0 : (x0 - T) / s + 1, jx1 = min(a.nx - 1, x0 / s);
+  int t[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const bool in = jy0 + u <= jy1 && jx0 + v <= jx1;
+      const int ti = a.index[min(jy0 + u, jy1) * a.nx + min(jx0 + v, jx1)];
+      t[u][v] = in ? ti : -1;
+    }
+  float4 L[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int tt = t[u][v];
+      const int iy = y - (jy0 + u) * s, ix = x0 - (jx0 + v) * s;
+      const __amdgpu_buffer_rsrc_t r =
+          tile_rsrc(a.logits + (int64_t)max(tt, 0) * a.tile_stride, tt >= 0 ? (uint32_t)(a.tile_stride * 4) : 0u);
+      const uint32_t off = (uint32_t)(a.slot_off + (int64_t)iy * T + ix) * 4u;
+      L[u][v] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, tt >= 0 ? off : 0u, 0, 0));
+    }
+  float out[4];
+  bool m[4];
+  if (a.vote > 0) {
+    int votes[4] = {0, 0, 0, 0}, cover = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        if (t[u][v] < 0) continue;
+        const float4 l = L[u][v];
+        votes[0] += l.x > 0.f ? 1 : 0;
+        votes[1] += l.y > 0.f ? 1 : 0;
+        votes[2] += l.z > 0.f ? 1 : 0;
+        votes[3] += l.w > 0.f ? 1 : 0;
+        ++cover;
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      m[q] = cover > 0 && votes[q] >= a.vote;
+      out[q] = (float)votes[q];
+    }
+  } else {
+    float sum[4] = {0.f, 0.f, 0.f, 0.f}, comp[4] = {0.f, 0.f, 0.f, 0.f};
+    int den[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int iy = y - (jy0 + u) * s;
+      const int ry = min(iy + 1, T - iy);
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        if (t[u][v] < 0) continue;
+        const int ix = x0 - (jx0 + v) * s;
+        const float l[4] = {L[u][v].x, L[u][v].y, L[u][v].z, L[u][v].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int w = ry * min(ix + q + 1, T - ix - q);
+          const float vv = (float)w * l[q];
+          const float t2 = sum[q] + vv;
+          comp[q] += (fabsf(sum[q]) >= fabsf(vv)) ? ((sum[q] - t2) + vv) : ((vv - t2) + sum[q]);
+          sum[q] = t2;
+          den[q] += w;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float n = sum[q] + comp[q];
+      m[q] = (den[q] > 0) && (a.coverage || n > 0.f);
+      out[q] = den[q] > 0 ? n / (float)den[q] : 0.f;
+    }
+  }
+  if (a.fg) {
+    const uint8_t* fr = a.fg + (int64_t)(y >> a.fg_shift) * a.Wc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = m[q] && fr[(x0 + q) >> a.fg_shift];
+  }
+  *reinterpret_cast<uint32_t*>(a.mask + (int64_t)y * a.mask_pitch + x0) =
+      (m[0] ? 1u : 0u) | (m[1] ? 1u << 8 : 0u) | (m[2] ? 1u << 16 : 0u) | (m[3] ? 1u << 24 : 0u);
+  if (a.logit)
+    *reinterpret_cast<float4*>(a.logit + (int64_t)y * a.logit_pitch + x0) = make_float4(out[0], out[1], out[2], out[3]);
+}
+
 // One thread per pixel; rows beyond the grid's y extent are taken in strides.
 __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
   const int x = blockIdx.x * 256 + threadIdx.x;
@@ -145,13 +241,15 @@ __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
 }
 
 // One thread per four pixels (see stitch_span4); the row's ragged end goes
-// pixel by pixel.
+// pixel by pixel.  TWO: at most 2 x 2 covering tiles (T <= 2 s).
+template <bool TWO>
 __global__ __launch_bounds__(256) void k_stitch4(StitchArgs a) {
   const int x0 = (blockIdx.x * 256 + threadIdx.x) * 4;
   if (x0 >= a.Wk) return;
   for (int y = blockIdx.y; y < a.Hk; y += gridDim.y) {
     if (x0 + 3 < a.Wk) {
-      stitch_span4(a, x0, y);
+      if (TWO) stitch_span4_2x2(a, x0, y);
+      else stitch_span4(a, x0, y);
     } else {
       for (int x = x0; x < a.Wk; ++x) stitch_pixel(a, x, y);
     }
@@ -168,7 +266,12 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t st) {
                      (!a.logit || (a.logit_pitch % 4 == 0 && reinterpret_cast<uintptr_t>(a.logit) % 16 == 0));
   if (span4) {
     dim3 grid(ceil_div(a.Wk, 1024), std::min(a.Hk, kMaxGridY));
-    hipLaunchKernelGGL(k_stitch4, grid, dim3(256), 0, st, a);
+    // a logit plane's float offsets inside a tile must fit the 32-bit byte
+    // offsets of the buffer loads
+    if (a.T <= 2 * a.s && a.tile_stride * 4 <= INT32_MAX)
+      hipLaunchKernelGGL(k_stitch4<true>, grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_stitch4<false>, grid, dim3(256), 0, st, a);
   } else {
     dim3 grid(ceil_div(a.Wk, 256), std::min(a.Hk, kMaxGridY));
     hipLaunchKernelGGL(k_stitch, grid, dim3(256), 0, st, a);
