@@ -37,6 +37,43 @@ __device__ __forceinline__ uint8_t merge_pixel(const MergePlane& p, int y, int x
   return p.mask[(int64_t)(y >> k) * p.pitch + (x >> k)] ? 1 : 0;
 }
 
+// Four consecutive pixels of one row, bilinear: the sixteen logit reads are
+// issued before any is used (same arithmetic per pixel as merge_pixel).
+__device__ __forceinline__ uint32_t merge4_bilinear(const MergePlane& p, int y, int x0) {
+  const int k = p.k;
+  const float inv = 1.0f / (float)(2 << k);
+  const float sy = fmaxf(0.f, (float)(2 * y + 1 - (1 << k)) * inv);
+  const int y0 = (int)sy;
+  const int y1 = min(y0 + 1, p.Hk - 1);
+  const float ly = sy - (float)y0;
+  const float* r0 = p.logit + (int64_t)y0 * p.pitch;
+  const float* r1 = p.logit + (int64_t)y1 * p.pitch;
+  int c0[4], c1[4];
+  float lx[4], v[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float sx = fmaxf(0.f, (float)(2 * (x0 + q) + 1 - (1 << k)) * inv);
+    c0[q] = (int)sx;
+    c1[q] = min(c0[q] + 1, p.Wk - 1);
+    lx[q] = sx - (float)c0[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q][0] = r0[c0[q]];
+    v[q][1] = r0[c1[q]];
+    v[q][2] = r1[c0[q]];
+    v[q][3] = r1[c1[q]];
+  }
+  uint32_t out = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float top = (1.f - lx[q]) * v[q][0] + lx[q] * v[q][1];
+    const float bot = (1.f - lx[q]) * v[q][2] + lx[q] * v[q][3];
+    out |= (((1.f - ly) * top + ly * bot) > 0.f ? 1u : 0u) << (8 * q);
+  }
+  return out;
+}
+
 // One thread per four consecutive 40x pixels: one 4-byte store when the
 // plane's output rows allow it (vec4), else four byte stores.
 __global__ __launch_bounds__(256) void k_merge_base(MergeArgs a) {
@@ -46,8 +83,13 @@ __global__ __launch_bounds__(256) void k_merge_base(MergeArgs a) {
   for (int y = blockIdx.y; y < a.H; y += gridDim.y) {
     uint8_t* o = p.out + (int64_t)y * p.out_pitch + x0;
     if (p.vec4 && x0 + 3 < a.W) {
-      const uint32_t v = (uint32_t)merge_pixel(p, y, x0) | ((uint32_t)merge_pixel(p, y, x0 + 1) << 8) |
-                         ((uint32_t)merge_pixel(p, y, x0 + 2) << 16) | ((uint32_t)merge_pixel(p, y, x0 + 3) << 24);
+      uint32_t v;
+      if (p.bilinear) {
+        v = merge4_bilinear(p, y, x0);
+      } else {
+        v = (uint32_t)merge_pixel(p, y, x0) | ((uint32_t)merge_pixel(p, y, x0 + 1) << 8) |
+            ((uint32_t)merge_pixel(p, y, x0 + 2) << 16) | ((uint32_t)merge_pixel(p, y, x0 + 3) << 24);
+      }
       *reinterpret_cast<uint32_t*>(o) = v;
     } else {
       for (int q = 0; q < 4 && x0 + q < a.W; ++q) o[q] = merge_pixel(p, y, x0 + q);
