@@ -8,7 +8,9 @@
 // theta split as W1 (8x8), W2 (8x8), W3 (o x 8), b1, b2, b3.  The class logit
 // is z_0 for one output and z_1 - z_0 for two.  F = ReLU(W_p D_0 + b_p) when
 // the decoder's last level has C_0 != 8 channels, else D_0 itself.  All head
-// arithmetic is FP32; the per-tile parameters live in LDS.
+// arithmetic is FP32.  The precls weights and a tile's generated head
+// parameters are the same for every thread of a workgroup, so the head reads
+// them as scalar (constant-cache) loads and uses them as FMA operands.
 #include "internal.h"
 
 #include <type_traits>

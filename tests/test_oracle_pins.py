@@ -86,6 +86,81 @@ def test_tile_input_normalisation():
         assert np.allclose(x, 1.0, atol=0, rtol=0)
 
 
+
+def _position_slide(H, W):
+    """R = row, G = column, B = 100: every pixel states its own (y, x)."""
+    assert H <= 256 and W <= 256
+    img = np.empty((H, W, 3), np.uint8)
+    img[:, :, 0] = np.arange(H)[:, None]
+    img[:, :, 1] = np.arange(W)[None, :]
+    img[:, :, 2] = 100
+    return img
+
+
+def test_tile_input_window_origin_closed_form():
+    """The tile (jy, jx) at scale k reads the 40x rows f (jy s + i) .. + f - 1.
+
+    On a slide whose red channel is the row index, the input's red value is
+    the mean row of the block, (f Y + (f - 1) / 2) / 255 with Y = jy s + i
+    (green likewise with columns), wherever the block lies inside the slide;
+    blocks wholly in the pad read the pad colour (1, 1, 100): the rounded
+    mean of the corner rows 0, 0, 1, 1 is 1.  A shifted, scaled or
+    transposed window, or a pad at the top/left, fails this.
+    """
+    H, W = 200, 176
+    img = _position_slide(H, W)
+    pad = O.pad_colour(img)
+    assert list(pad) == [1, 1, 100]
+    T, s = 32, 16
+    checked = 0
+    for k in range(3):
+        f = 2 ** k
+        ny = O.grid_count(O.level_size(H, k), T, s)
+        nx = O.grid_count(O.level_size(W, k), T, s)
+        for jy, jx in {(0, 0), (min(1, ny - 1), min(2, nx - 1)), (ny - 1, nx - 1), (ny - 1, 0), (0, nx - 1),
+                       (ny // 2, nx // 3)}:
+            x = O.tile_input(img, k, T, s, jy, jx)
+            assert x.shape == (3, T, T)
+            for i in range(T):
+                for j in range(T):
+                    Y, X = jy * s + i, jx * s + j
+                    r, g, b = x[:, i, j] * 255.0
+                    if (Y + 1) * f <= H and (X + 1) * f <= W:
+                        assert r == pytest.approx(f * Y + (f - 1) / 2.0, abs=1e-9)
+                        assert g == pytest.approx(f * X + (f - 1) / 2.0, abs=1e-9)
+                        assert b == pytest.approx(100.0, abs=1e-9)
+                        checked += 1
+                    elif Y * f >= H or X * f >= W:
+                        # wholly in the pad (right of or below the slide)
+                        assert (r, g, b) == pytest.approx((1.0, 1.0, 100.0), abs=1e-9)
+                        checked += 1
+    assert checked > 10000
+
+
+def test_tile_input_brute_force_block_sums_on_ragged_slide():
+    """Every input value is the brute-force mean of its 2^k x 2^k block of the
+    padded 40x slide, including blocks that straddle the slide's edge."""
+    rng = np.random.default_rng(31)
+    img = rng.integers(0, 256, size=(37, 29, 3)).astype(np.uint8)
+    pad = O.pad_colour(img)
+    T, s = 16, 8
+    for k in range(3):
+        f = 2 ** k
+        ny = O.grid_count(O.level_size(37, k), T, s)
+        nx = O.grid_count(O.level_size(29, k), T, s)
+        for jy in range(ny):
+            for jx in range(nx):
+                x = O.tile_input(img, k, T, s, jy, jx)
+                for i in range(0, T, 3):
+                    for j in range(0, T, 5):
+                        tot = np.zeros(3)
+                        for a in range(f):
+                            for b in range(f):
+                                yy = (jy * s + i) * f + a
+                                xx = (jx * s + j) * f + b
+                                tot += img[yy, xx] if (yy < 37 and xx < 29) else pad
+                        assert np.allclose(x[:, i, j], tot / (255.0 * f * f), rtol=0, atol=1e-12)
+
 # ---------------------------------------------------------------- O4 tile grid
 
 @pytest.mark.parametrize("n,T,s,want", [
@@ -153,6 +228,37 @@ def test_tile_keep_rule_brute_force():
                     x0, x1 = jx * s * f, (jx * s + T) * f
                     want = bool(big[y0:min(y1, big.shape[0]), x0:min(x1, big.shape[1])].any())
                     assert O.tile_keeps(fg, kc, k, T, s, jy, jx) == want
+
+
+def test_fg_at_scale_against_rasterised_coarse_map():
+    """fg_k(y, x) is the coarse pixel under the 40x footprint of (y, x).
+
+    Brute force: paint every coarse pixel onto its 2^kc x 2^kc block of the
+    40x grid, then read each scale-k pixel's footprint there; the footprint
+    of a scale-k pixel lies inside one coarse pixel, so all its 40x pixels
+    must agree.  Non-square maps with ragged sizes catch swapped axes and
+    wrong shifts.
+    """
+    rng = np.random.default_rng(12)
+    for H, W in ((83, 61), (40, 97), (64, 64)):
+        for kc in range(4):
+            Hc, Wc = O.level_size(H, kc), O.level_size(W, kc)
+            fg = rng.uniform(size=(Hc, Wc)) < 0.4
+            F = 2 ** kc
+            big = np.zeros((Hc * F, Wc * F), bool)
+            for r in range(Hc):
+                for c in range(Wc):
+                    big[r * F:(r + 1) * F, c * F:(c + 1) * F] = fg[r, c]
+            for k in range(kc + 1):
+                f = 2 ** k
+                Hk, Wk = O.level_size(H, k), O.level_size(W, k)
+                got = O.fg_at_scale(fg, kc, k, Hk, Wk)
+                assert got.shape == (Hk, Wk)
+                for y in range(Hk):
+                    for x in range(Wk):
+                        foot = big[y * f:(y + 1) * f, x * f:(x + 1) * f]
+                        assert foot.all() or not foot.any()
+                        assert bool(got[y, x]) == bool(foot[0, 0])
 
 
 def test_tissue_map_against_float_gray():
@@ -699,6 +805,33 @@ def _fd_instance():
     pairs = [(c, si) for si in range(2) for c in range(6)]
     batch = [(si, jy, jx) for (_, si, jy, jx) in O.tile_list([(64, 64)], cfg)]
     return rgb, gt, cfg, flat, pairs, batch
+
+
+def test_soft_target_brute_force_block_mean_with_zero_pad():
+    """y_k(p) = (number of ground-truth pixels in the 2^k x 2^k block) / 4^k,
+    pixels beyond the slide counting as 0 (so a ragged edge block of an
+    all-ones mask holds the fraction of the block inside the slide)."""
+    rng = np.random.default_rng(13)
+    for H, W in ((21, 34), (16, 16), (9, 30)):
+        gt = rng.uniform(size=(H, W)) < 0.3
+        for k in range(4):
+            f = 2 ** k
+            Hk, Wk = O.level_size(H, k), O.level_size(W, k)
+            y = O.soft_target(gt, k)
+            assert y.shape == (Hk, Wk)
+            for yy in range(Hk):
+                for xx in range(Wk):
+                    cnt = 0
+                    for a in range(f):
+                        for b in range(f):
+                            Y, X = yy * f + a, xx * f + b
+                            if Y < H and X < W and gt[Y, X]:
+                                cnt += 1
+                    assert y[yy, xx] == cnt / (f * f)
+        ones = O.soft_target(np.ones((H, W), bool), 3)
+        inside_y = [min(8, H - 8 * r) for r in range(O.level_size(H, 3))]
+        inside_x = [min(8, W - 8 * c) for c in range(O.level_size(W, 3))]
+        assert np.array_equal(ones, np.outer(inside_y, inside_x) / 64.0)
 
 
 def test_gradient_against_torch_autograd():
