@@ -494,7 +494,7 @@ def batch_workload(om, torch, steps, warmup, max_kept):
 
     def sequential():
         for i, sl in enumerate(slides):
-            plan.segment([sl], pairs, packed, workspace=ws, outputs=([outs[i]], [[None] * len(pairs)]))
+            plan.segment([sl], pairs, packed, workspace=ws, outputs=([outs[0][i]], [outs[1][i]]))
 
     ms_s = timed(sequential, 1)
     px = sum(sp["H"] * sp["W"] for sp in specs) * len(pairs)

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define OMNISEG_ABI_VERSION 6
+#define OMNISEG_ABI_VERSION 7
 
 /* status codes */
 #define OMNISEG_OK 0
@@ -59,8 +59,9 @@ extern "C" {
 /* flags */
 #define OMNISEG_FLAG_EMIT_LOGITS 1 /* also write the stitched FP32 logit map */
 #define OMNISEG_FLAG_TRAINING 2    /* also pack the data-gradient weights (training entry points) */
-#define OMNISEG_FLAG_GRAPH 4       /* omniseg_segment_slide: capture the work after the tile list
-                                      in a HIP graph, replayed on calls with identical arguments;
+#define OMNISEG_FLAG_GRAPH 4       /* omniseg_segment_slide: capture the whole call in a HIP graph,
+                                      replayed on later calls with identical arguments and conv
+                                      tile configurations (whatever the slides' pixels hold);
                                       needs a created (non-null) stream */
 
 /* merge of overlapping tile predictions (omniseg_config.merge) */
@@ -129,12 +130,18 @@ typedef struct omniseg_hip_stream_opaque* omniseg_stream; /* a hipStream_t */
  *   precision      OMNISEG_FP32, OMNISEG_BF16 or OMNISEG_FP8 (not with
  *                  OMNISEG_FLAG_TRAINING).
  *   flags          OR of OMNISEG_FLAG_*.
- *   batch_tiles    tiles per backbone batch (0 = library default).
- *   max_kept_tiles capacity of the per-tile logit store in the workspace:
- *                  0 sizes it for every grid tile; a positive value sizes it
- *                  for at most that many kept tiles, and a call that keeps
- *                  more returns OMNISEG_ERR_WORKSPACE once the tile list is
- *                  built (no output is written then).
+ *   batch_tiles    list positions per backbone batch B (0 = library
+ *                  default, 256).
+ *   logit_ring_tiles  slots of the per-tile logit store in the workspace:
+ *                  0 gives every grid tile a slot, so every kept tile's
+ *                  logits stay readable after the call; n > 0 makes it a
+ *                  ring of max(n, the least ring the streamed stitch needs)
+ *                  slots rounded up to a multiple of B (at most one per grid
+ *                  tile), which bounds the workspace for many or large
+ *                  slides.  The least ring is (max over tile rows j of
+ *                  (j + 1 - jlo) nx) + B - 1 slots, where jlo is the first
+ *                  tile row reaching row j's first output row.  Outputs do
+ *                  not depend on the ring size.
  */
 typedef struct omniseg_config {
   int32_t abi_version;
@@ -152,7 +159,7 @@ typedef struct omniseg_config {
   int32_t precision;
   int32_t flags;
   int32_t batch_tiles;
-  int32_t max_kept_tiles;
+  int32_t logit_ring_tiles;
   int32_t scale_stride[OMNISEG_MAX_SCALES];
   int32_t merge;
   int32_t vote_threshold[OMNISEG_MAX_SCALES];
@@ -303,11 +310,16 @@ int32_t omniseg_workspace_bytes(const omniseg_plan* plan, const omniseg_slide* s
  *   outs       host array [n_slides * n_pairs], slide-major: outs[i * n_pairs + p].
  *   workspace  device, ws_bytes >= omniseg_workspace_bytes, 256-byte aligned.
  * All slides share one tile work list: every kept tile of every slide and
- * scale runs through the backbone in batches of batch_tiles tiles; the head
- * runs once per (tile, pair at the tile's scale); the stitch writes every
- * output.  The call waits once for the stream after the tile list is built
- * (to read the number of kept tiles, so every backbone launch is sized
- * exactly); all later work is enqueued asynchronously on `stream`.
+ * scale runs through the backbone in batches of B = batch_tiles list
+ * positions; the head runs once per (tile, pair at the tile's scale).  The
+ * output rows of each tile row of each (slide, scale) grid are stitched
+ * right after the batch that holds the last kept tile covering them, so
+ * the logit store may be a ring (logit_ring_tiles).  The number of kept
+ * tiles stays on the device: the backbone batches are launched for every
+ * grid tile and those past the kept-tile count return at once.  Everything
+ * is enqueued on `stream` and the call returns without waiting for it
+ * (unless profiling is on, see omniseg_set_profiling); outputs are valid
+ * once the stream has completed the work.
  */
 int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
                               const omniseg_slide* slides, int32_t n_slides,
@@ -324,12 +336,17 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
 #define OMNISEG_REGION_TILE_LIST 4  /* int32[max_tiles][4]: (slide, slot, jy, jx) in list order */
 #define OMNISEG_REGION_TILE_INDEX 5 /* int32 per grid tile of (slide, slot): list index or -1,
                                        row-major (jy, jx); index = slide * n_scales + slot */
-#define OMNISEG_REGION_TILE_LOGITS 6 /* float[max_tiles][max_pairs_per_scale][T][T] */
+#define OMNISEG_REGION_TILE_LOGITS 6 /* float[slots][max_pairs_per_scale][T][T]: the logit
+                                         store; the kept tile at list position p is in slot
+                                         p % slots (slots = bytes / (max_pairs_per_scale T^2 4));
+                                         with logit_ring_tiles = 0 every kept tile's slot is p */
 #define OMNISEG_REGION_TISSUE_GRAY 7  /* uint8[H_c][W_c]: the median-blurred gray map of a slide
                                          (OMNISEG_TISSUE_OTSU; empty otherwise); index = slide */
 #define OMNISEG_REGION_TISSUE_STATS 8 /* int32[4] of a slide (OMNISEG_TISSUE_OTSU; empty otherwise):
                                          Otsu threshold (-1: one-valued map), tissue components,
-                                         components kept, 0; index = slide */
+                                         components kept, error flag (1: the component labelling
+                                         stopped at its iteration bound; a bound no input reaches,
+                                         kept so every kernel ends); index = slide */
 /*
  * Byte offset and size of one region inside the workspace for these slides
  * and pairs (host arrays); the layout depends only on the arguments.
@@ -561,7 +578,11 @@ int32_t omniseg_bce_loss(const float* logit, const float* target, const uint8_t*
  * starts a new list, so several calls can run back to back and be read once.
  * Profiling creates HIP events lazily (two per launch, kept by the plan until
  * it is destroyed, so read the records before the list grows without bound)
- * and is off by default.
+ * and is off by default.  A profiled omniseg_segment_slide makes the same
+ * launches as an unprofiled one, but waits for the stream once after the
+ * tile list to read the kept-tile count and index grid, which make each
+ * record's `tiles`, FLOPs and bytes exact (a batch past the count records 0
+ * tiles and no work); profiled calls are never captured in a graph.
  */
 #define OMNISEG_STAGE_PREP 0       /* pad colour, pyramid, tissue map, tile list */
 #define OMNISEG_STAGE_FIRST_CONV 1 /* encoder level 0, first conv (3 -> C_0)     */
@@ -571,7 +592,8 @@ int32_t omniseg_bce_loss(const float* logit, const float* target, const uint8_t*
 #define OMNISEG_STAGE_DEC_B 5      /* decoder second conv (+ residual)          */
 #define OMNISEG_STAGE_GAP_CTRL 6   /* bottleneck mean and controller            */
 #define OMNISEG_STAGE_HEAD 7       /* precls and dynamic head                   */
-#define OMNISEG_STAGE_STITCH 8     /* overlap-weighted stitch of one plane      */
+#define OMNISEG_STAGE_STITCH 8     /* stitch: of one plane (omniseg_stitch_tiles), or of the
+                                      tile rows one backbone batch completed (segment_slide) */
 
 typedef struct omniseg_launch_record {
   int32_t stage;  /* OMNISEG_STAGE_* */

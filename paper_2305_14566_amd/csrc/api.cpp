@@ -4,6 +4,7 @@
 // Validation runs entirely on the host before the first HIP call, so an
 // invalid call launches nothing and writes nothing.
 #include <algorithm>
+#include <climits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -50,8 +51,13 @@ struct Layout {
   int Hc[OMNISEG_MAX_SLIDES], Wc[OMNISEG_MAX_SLIDES];
   TileGroups groups;
   int total_tiles = 0;
-  int logit_cap = 0;  // kept tiles the logit store holds
+  int ring = 0;       // slots of the tile-logit store (kept tile p in slot p % ring)
+  bool resident = false;  // one slot per grid tile: no slot is ever reused
   int batch = 0;
+  int n_batches = 0;  // batches of `batch` list positions covering every grid tile
+  int n_units = 0;    // streamed stitch units (one per tile row of each group)
+  int64_t n_items = 0;
+  std::vector<StreamGroup> sgroups;  // host copy of the group table (pointers filled per call)
   SlotTable slots;
   int max_slots = 0;
   int pair_slot[256];  // slot index of each pair within its scale
@@ -63,7 +69,9 @@ struct Layout {
   bool otsu = false;
   int64_t off_tgray[OMNISEG_MAX_SLIDES], off_tstats[OMNISEG_MAX_SLIDES];
   int64_t off_ttmp = -1, off_thist = -1, off_tlabel = -1, off_tarea = -1;
-  int64_t off_index = 0, off_list = 0, off_count = 0;
+  int64_t off_index = 0, off_list = 0, off_count = 0, off_pre = 0;
+  int64_t off_sgroups = 0, off_splanes = 0, off_units = 0;
+  int n_planes = 0;
   int64_t off_E[8], off_A = 0, off_g = 0, off_theta = 0, off_logits = 0;
   int64_t sz_E[8], sz_A = 0, sz_logits = 0;
   int64_t off_P = 0, sz_P = 0;  // pooled encoder output (row-reuse precisions)
@@ -139,7 +147,7 @@ int32_t validate_config(const omniseg_config* c) {
     return fail(OMNISEG_ERR_ARG, "unknown flags 0x%x", c->flags);
   if (c->batch_tiles < 0 || c->batch_tiles > 65536)
     return fail(OMNISEG_ERR_ARG, "batch_tiles %d outside [0, 65536]", c->batch_tiles);
-  if (c->max_kept_tiles < 0) return fail(OMNISEG_ERR_ARG, "max_kept_tiles %d < 0", c->max_kept_tiles);
+  if (c->logit_ring_tiles < 0) return fail(OMNISEG_ERR_ARG, "logit_ring_tiles %d < 0", c->logit_ring_tiles);
   if (c->tissue_method != OMNISEG_TISSUE_GRAY && c->tissue_method != OMNISEG_TISSUE_OTSU)
     return fail(OMNISEG_ERR_ARG, "unknown tissue_method %d", c->tissue_method);
   if (c->tissue_method == OMNISEG_TISSUE_OTSU) {
@@ -284,8 +292,10 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
   lay.off_index = take((int64_t)tiles * 4);
   lay.off_list = take((int64_t)tiles * 16);
   lay.off_count = take(4);
+  lay.off_pre = take((int64_t)(tiles + 1) * 4);
   const int bt = c.batch_tiles > 0 ? c.batch_tiles : 256;
   lay.batch = std::min(bt, tiles);
+  lay.n_batches = ceil_div(tiles, lay.batch);
   const int es = elem_size(c.precision);
   for (int l = 0; l < plan->L; ++l) {
     const int tl = T >> l;
@@ -301,8 +311,64 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
   }
   lay.off_g = take((int64_t)lay.batch * plan->Cp[plan->L - 1] * 4);
   lay.off_theta = take((int64_t)lay.batch * lay.max_slots * plan->P * 4);
-  lay.logit_cap = c.max_kept_tiles > 0 ? std::min(tiles, c.max_kept_tiles) : tiles;
-  lay.sz_logits = (int64_t)lay.logit_cap * lay.max_slots * T * T * 4;
+  // Streamed stitch: one unit per tile row of each group.  A unit's covering
+  // tiles start at tile row jlo (the first row reaching its first output
+  // row) and end with its own row, at most (j + 1 - jlo) nx list positions;
+  // it is stitched right after the batch that holds its last one, when at
+  // most B - 1 later positions have been written.  A ring of at least
+  // max (j + 1 - jlo) nx + B - 1 slots therefore still holds every tile
+  // logit a unit reads.
+  lay.sgroups.assign(lay.groups.n, StreamGroup());
+  lay.n_units = 0;
+  lay.n_items = 0;
+  lay.n_planes = 0;
+  int64_t need = 0;
+  for (int gi = 0; gi < lay.groups.n; ++gi) {
+    const int i = lay.groups.slide[gi], si = lay.groups.slot[gi];
+    const ScaleGeom& g = lay.geom[i][si];
+    const int ss = stride_of(c, si);
+    StreamGroup& sg = lay.sgroups[gi];
+    sg.grid_base = lay.groups.base[gi];
+    sg.item_base = lay.n_items;
+    sg.ny = g.ny;
+    sg.nx = g.nx;
+    sg.s = ss;
+    sg.Hk = g.Hk;
+    sg.Wk = g.Wk;
+    sg.unit_base = lay.n_units;
+    sg.plane_first = lay.n_planes;
+    sg.n_planes = lay.slots.n_slots[si];
+    sg.fg = nullptr;
+    sg.fg_shift = lay.kc - g.k;
+    sg.Hc = lay.Hc[i];
+    sg.Wc = lay.Wc[i];
+    sg.vote = c.merge == OMNISEG_MERGE_VOTE ? c.vote_threshold[si] : 0;
+    lay.n_units += g.ny;
+    lay.n_planes += sg.n_planes;
+    const int64_t last_rows = g.Hk - (int64_t)(g.ny - 1) * ss;
+    lay.n_items += (int64_t)sg.n_planes * ((int64_t)(g.ny - 1) * ceil_div(ss, kStitchRows) +
+                                           (last_rows + kStitchRows - 1) / kStitchRows);
+    for (int j = 0; j < g.ny; ++j) {
+      const int y0 = j * ss;
+      const int jlo = y0 < T ? 0 : (y0 - T) / ss + 1;
+      need = std::max<int64_t>(need, (int64_t)(j + 1 - jlo) * g.nx);
+    }
+  }
+  lay.off_sgroups = take((int64_t)lay.groups.n * sizeof(StreamGroup));
+  lay.off_splanes = take((int64_t)std::max(1, lay.n_planes) * sizeof(StreamPlane));
+  lay.off_units = take((int64_t)(lay.n_units + 1) * sizeof(StreamUnit));
+  const int64_t B = lay.batch;
+  const int64_t ring_min = (need + B - 1 + B - 1) / B * B;
+  if (c.logit_ring_tiles == 0 || ring_min >= tiles) {
+    lay.resident = true;
+    lay.ring = tiles;
+  } else {
+    lay.resident = false;
+    lay.ring = (int)std::min<int64_t>(std::max<int64_t>(ring_min, ((int64_t)c.logit_ring_tiles + B - 1) / B * B),
+                                      (int64_t)tiles);
+    if (lay.ring >= tiles) lay.resident = true;
+  }
+  lay.sz_logits = (int64_t)lay.ring * lay.max_slots * T * T * 4;
   lay.off_logits = take(lay.sz_logits);
   lay.total = off;
 }
@@ -331,10 +397,10 @@ const float* fp8_scale_of(const omniseg_plan* plan, const char* pk, int kind, in
 }
 
 // Steps 1-2 of a call: slide table, pad colour, pyramid, tissue map, tile
-// flags and the compacted tile list; reads the kept-tile count back (waits
-// for the stream).
-int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, int32_t n_slides, const Layout& lay,
-                        char* ws, hipStream_t sm, Prof& prof, SlideDev** tab_out, int32_t* n_kept_out) {
+// flags, the compacted tile list and its prefix counts.  Enqueues only: the
+// kept-tile count stays on the device.
+int32_t enqueue_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, int32_t n_slides, const Layout& lay,
+                          char* ws, hipStream_t sm, Prof& prof, SlideDev** tab_out) {
   const omniseg_config& c = plan->cfg;
   const int T = c.tile;
   plan->slide_tab.assign(n_slides, SlideDev());
@@ -359,8 +425,7 @@ int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, i
   }
   SlideDev* tab_dev = reinterpret_cast<SlideDev*>(ws + lay.off_tab);
   *tab_out = tab_dev;
-  HIP_TRY(hipMemcpyAsync(tab_dev, plan->slide_tab.data(), sizeof(SlideDev) * n_slides,
-                         hipMemcpyHostToDevice, sm));
+  HIP_TRY(launch_put(tab_dev, plan->slide_tab.data(), (int64_t)sizeof(SlideDev) * n_slides, sm));
 
   double prep_bytes = 0.0;
   for (int i = 0; i < n_slides; ++i) {
@@ -414,15 +479,24 @@ int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, i
                             reinterpret_cast<uint8_t*>(ws + lay.off_fg[i]), sm));
     }
   }
-  // 2. tile flags and compaction; the kept-tile count sizes every later launch
+  // 2. tile flags, compaction and prefix counts; the later launches are
+  // sized for every grid tile and skip list positions at or past the count
   int32_t* index = reinterpret_cast<int32_t*>(ws + lay.off_index);
   int32_t* list = reinterpret_cast<int32_t*>(ws + lay.off_list);
   int32_t* count = reinterpret_cast<int32_t*>(ws + lay.off_count);
+  int32_t* pre = reinterpret_cast<int32_t*>(ws + lay.off_pre);
   HIP_TRY(launch_tile_flags(lay.groups, tab_dev, T, lay.kc, c.fg_filter, index, sm));
-  HIP_TRY(launch_compact(index, lay.total_tiles, lay.groups, list, count, sm));
+  HIP_TRY(launch_compact(index, lay.total_tiles, lay.groups, list, count, pre, sm));
   HIP_TRY(prof.end(OMNISEG_STAGE_PREP, -1, 0, 0.0, prep_bytes));
+  return OMNISEG_OK;
+}
+
+// Waits for the stream and reads the kept-tile count back (calls that are
+// synchronous by contract, and profiled calls); also reports a tissue
+// labelling that did not converge.
+int32_t read_kept(const Layout& lay, int32_t n_slides, const char* ws, hipStream_t sm, int32_t* n_kept_out) {
   int32_t n_kept = 0;
-  HIP_TRY(hipMemcpyAsync(&n_kept, count, sizeof(int32_t), hipMemcpyDeviceToHost, sm));
+  HIP_TRY(hipMemcpyAsync(&n_kept, ws + lay.off_count, sizeof(int32_t), hipMemcpyDeviceToHost, sm));
   int32_t tstats[OMNISEG_MAX_SLIDES][4] = {};
   if (lay.otsu)
     for (int i = 0; i < n_slides; ++i)
@@ -434,6 +508,50 @@ int32_t build_tile_list(const omniseg_plan* plan, const omniseg_slide* slides, i
     return fail(OMNISEG_ERR_HIP, "kept-tile count %d outside [0, %d]", n_kept, lay.total_tiles);
   *n_kept_out = n_kept;
   return OMNISEG_OK;
+}
+
+// Stitch form of a plane (as launch_stitch chooses it): four pixels per
+// thread needs shared covering tiles (s, T multiples of 4) and aligned
+// vector accesses; the 2 x 2 form also needs T <= 2 s and 32-bit byte
+// offsets inside a logit slot.
+int stitch_mode(int T, int s, int64_t tile_stride, int64_t slot_off, const float* logits, const uint8_t* mask,
+                int64_t mask_pitch, const float* logit, int64_t logit_pitch) {
+  const bool span4 = s % 4 == 0 && T % 4 == 0 && tile_stride % 4 == 0 && slot_off % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(logits) % 16 == 0 && mask_pitch % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(mask) % 4 == 0 &&
+                     (!logit || (logit_pitch % 4 == 0 && reinterpret_cast<uintptr_t>(logit) % 16 == 0));
+  if (!span4) return 0;
+  return (T <= 2 * s && tile_stride * 4 <= INT32_MAX) ? 2 : 1;
+}
+
+// Algorithmic bytes of each batch's streamed stitch: every in-plane pixel of
+// every kept covering tile read once (4 B) and every output pixel written
+// (1 B mask, + 4 B logit), attributed to the batch after which its unit is
+// stitched.  idx: the index grid (list index or -1 per grid tile).
+std::vector<double> stream_stitch_bytes(const Layout& lay, const std::vector<int32_t>& idx, int T, bool emit) {
+  std::vector<double> out(lay.n_batches, 0.0);
+  std::vector<int32_t> pre(lay.total_tiles + 1, 0);
+  for (int t = 0; t < lay.total_tiles; ++t) pre[t + 1] = pre[t] + (idx[t] >= 0 ? 1 : 0);
+  for (int gi = 0; gi < lay.groups.n; ++gi) {
+    const StreamGroup& g = lay.sgroups[gi];
+    if (g.n_planes == 0) continue;
+    for (int j = 0; j < g.ny; ++j) {
+      const int pos_end = pre[g.grid_base + (int64_t)(j + 1) * g.nx];
+      const int b = pos_end > 0 ? (pos_end - 1) / lay.batch : 0;
+      const int y0 = j * g.s, y1 = j == g.ny - 1 ? g.Hk : (j + 1) * g.s;
+      double bytes = (double)(y1 - y0) * g.Wk * (emit ? 5.0 : 1.0);
+      const int jlo = y0 < T ? 0 : (y0 - T) / g.s + 1;
+      for (int jt = jlo; jt <= j; ++jt) {
+        const int r0 = std::max(y0, jt * g.s), r1 = std::min(std::min(y1, jt * g.s + T), g.Hk);
+        if (r1 <= r0) continue;
+        for (int jx = 0; jx < g.nx; ++jx)
+          if (idx[g.grid_base + (int64_t)jt * g.nx + jx] >= 0)
+            bytes += 4.0 * (r1 - r0) * std::min(T, g.Wk - jx * g.s);
+      }
+      out[b] += bytes * g.n_planes;
+    }
+  }
+  return out;
 }
 
 }  // namespace
@@ -723,7 +841,9 @@ int32_t omniseg_calibrate_fp8(const omniseg_plan* plan, const void* packed, cons
   Prof prof = profile_start(plan, sm);
   SlideDev* tab_dev = nullptr;
   int32_t n_kept = 0;
-  st = build_tile_list(plan, slides, n_slides, lay, ws, sm, prof, &tab_dev, &n_kept);
+  st = enqueue_tile_list(plan, slides, n_slides, lay, ws, sm, prof, &tab_dev);
+  if (st) return st;
+  st = read_kept(lay, n_slides, ws, sm, &n_kept);
   if (st) return st;
   const int n = std::min(n_kept, n_tiles);
   int32_t* list = reinterpret_cast<int32_t*>(ws + lay.off_list);
@@ -894,40 +1014,82 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   const int T = c.tile, s = c.stride, prec = c.precision;
 
   Prof prof = profile_start(plan, sm);
-  SlideDev* tab_dev = nullptr;
-  int32_t n_kept = 0;
-  {
-    const int32_t pst = build_tile_list(plan, slides, n_slides, lay, ws, sm, prof, &tab_dev, &n_kept);
-    if (pst) return pst;
-  }
+  const int B = lay.batch, L = plan->L;
   int32_t* index = reinterpret_cast<int32_t*>(ws + lay.off_index);
   int32_t* list = reinterpret_cast<int32_t*>(ws + lay.off_list);
   int32_t* count = reinterpret_cast<int32_t*>(ws + lay.off_count);
-  if (n_kept > lay.logit_cap)
-    return fail(OMNISEG_ERR_WORKSPACE, "%d tiles kept, the logit store holds %d (max_kept_tiles)", n_kept, lay.logit_cap);
+  float* logits = reinterpret_cast<float*>(ws + lay.off_logits);
+  const int64_t tile_stride = (int64_t)lay.max_slots * T * T;
 
-  // 3-4. everything after the tile list: backbone batches, head, stitch.  With
-  // OMNISEG_FLAG_GRAPH this sequence is captured once per distinct argument set
-  // and replayed as one HIP graph.
+  // host tables of the streamed stitch: per group its tissue map, per
+  // (slide, pair) its output planes, in the pairs' slot order within a scale
+  std::vector<StreamGroup> groups = lay.sgroups;
+  std::vector<StreamPlane> planes(std::max(1, lay.n_planes));
+  for (int gi = 0; gi < lay.groups.n; ++gi) {
+    const int i = lay.groups.slide[gi], si = lay.groups.slot[gi];
+    StreamGroup& sg = groups[gi];
+    sg.fg = c.mask_and_fg ? reinterpret_cast<const uint8_t*>(ws + lay.off_fg[i]) : nullptr;
+    for (int p = 0; p < n_pairs; ++p) {
+      if (pairs[p].scale != si) continue;
+      const omniseg_output& o = outs[(int64_t)i * n_pairs + p];
+      StreamPlane& pl = planes[sg.plane_first + lay.pair_slot[p]];
+      pl.mask = o.mask;
+      pl.mask_pitch = o.mask_pitch;
+      pl.logit = emit ? o.logit : nullptr;
+      pl.logit_pitch = emit ? o.logit_pitch : 0;
+      pl.slot_off = (int64_t)lay.pair_slot[p] * T * T;
+      pl.mode = stitch_mode(T, sg.s, tile_stride, pl.slot_off, logits, pl.mask, pl.mask_pitch, pl.logit,
+                            pl.logit_pitch);
+      pl.pad_ = 0;
+    }
+  }
+  StreamStitchArgs sargs{};
+  sargs.groups = reinterpret_cast<const StreamGroup*>(ws + lay.off_sgroups);
+  sargs.planes = reinterpret_cast<const StreamPlane*>(ws + lay.off_splanes);
+  sargs.units = reinterpret_cast<StreamUnit*>(ws + lay.off_units);
+  sargs.n_groups = lay.groups.n;
+  sargs.n_units = lay.n_units;
+  sargs.pre = reinterpret_cast<const int32_t*>(ws + lay.off_pre);
+  sargs.index = index;
+  sargs.logits = logits;
+  sargs.tile_stride = tile_stride;
+  sargs.ring = lay.resident ? 0 : lay.ring;
+  sargs.T = T;
+  sargs.B = B;
+  sargs.n_items = lay.n_items;
+
+  // The whole call: tile list, then the backbone over batches of B list
+  // positions, launched for every grid tile (a batch past the kept-tile
+  // count exits at once), each batch followed by the stitch of the tile rows
+  // it completed.  Nothing waits for the device unless profiling is on.
+  // With OMNISEG_FLAG_GRAPH the sequence is captured once per distinct
+  // argument set and replayed as one HIP graph.
   auto enqueue = [&]() -> int32_t {
-    // 3. backbone, controller and head, batch by batch
+    SlideDev* tab_dev = nullptr;
+    int32_t est = enqueue_tile_list(plan, slides, n_slides, lay, ws, sm, prof, &tab_dev);
+    if (est) return est;
+    HIP_TRY(launch_put(ws + lay.off_sgroups, groups.data(), (int64_t)groups.size() * sizeof(StreamGroup), sm));
+    HIP_TRY(launch_put(ws + lay.off_splanes, planes.data(), (int64_t)planes.size() * sizeof(StreamPlane), sm));
+    HIP_TRY(launch_stream_units(sargs, sm));
+    // profiling: the kept-tile count and the index grid make the per-launch
+    // algorithmic work exact (the launches are the same as without profiling)
+    int32_t n_kept = -1;
+    std::vector<double> stitch_bytes;
+    if (plan->profiling) {
+      est = read_kept(lay, n_slides, ws, sm, &n_kept);
+      if (est) return est;
+      std::vector<int32_t> idx_host(lay.total_tiles);
+      HIP_TRY(hipMemcpyAsync(idx_host.data(), index, sizeof(int32_t) * lay.total_tiles, hipMemcpyDeviceToHost, sm));
+      HIP_TRY(hipStreamSynchronize(sm));
+      stitch_bytes = stream_stitch_bytes(lay, idx_host, T, emit);
+    }
     void* E[8];
-    for (int l = 0; l < plan->L; ++l) E[l] = ws + lay.off_E[l];
+    for (int l = 0; l < L; ++l) E[l] = ws + lay.off_E[l];
     void* A = ws + lay.off_A;
     float* g = reinterpret_cast<float*>(ws + lay.off_g);
     float* theta = reinterpret_cast<float*>(ws + lay.off_theta);
-    float* logits = reinterpret_cast<float*>(ws + lay.off_logits);
     auto layer = [&](const ConvDesc& d) { return make_layer(plan, pk, d); };
     const int es = elem_size(prec);
-    // algorithmic work of one 3x3 conv launch over `nt` tiles at h x h: input,
-    // output and weights once (a residual conv adds its own input, so the
-    // residual costs no bytes of its own)
-    auto conv_flops = [&](const ConvDesc& d, int h, int nt) { return 2.0 * 9 * d.cin * d.cout * (double)h * h * nt; };
-    auto conv_bytes = [&](const ConvDesc& d, int h, int nt, double in_px_factor) {
-      const double px = (double)h * h * nt;
-      return px * in_px_factor * d.cin * es + px * d.cout * es + 9.0 * d.cin * d.cout * es;
-    };
-    const int B = lay.batch;
     FirstConvArgs fa{};
     fa.list = list;
     fa.count = count;
@@ -942,15 +1104,25 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
     for (int si = 0; si < OMNISEG_MAX_SCALES; ++si) fa.scale_k[si] = si < c.n_scales ? c.scale_log2[si] : 0;
     if (prec == OMNISEG_FP8)
       fa.oinv = reinterpret_cast<const float*>(pk + plan->pk_iscale) + plan->act_off[OMNISEG_ACT_ENC_A][0];
-    const int L = plan->L;
-    for (int base = 0; base < n_kept; base += B) {
-      const int nb = std::min(B, n_kept - base);
+    for (int bi = 0; bi < lay.n_batches; ++bi) {
+      const int base = bi * B;
+      const int nb = std::min(B, lay.total_tiles - base);
+      // tiles of this batch that are kept (known when profiling; records only)
+      const int nk = n_kept >= 0 ? std::max(0, std::min(nb, n_kept - base)) : nb;
+      // algorithmic work of one 3x3 conv launch over the batch's kept tiles at
+      // h x h: input, output and weights once (a residual conv adds its own
+      // input, so the residual costs no bytes of its own)
+      auto conv_flops = [&](const ConvDesc& d, int h) { return 2.0 * 9 * d.cin * d.cout * (double)h * h * nk; };
+      auto conv_bytes = [&](const ConvDesc& d, int h, double in_px_factor) {
+        const double px = (double)h * h * nk;
+        return nk == 0 ? 0.0 : px * in_px_factor * d.cin * es + px * d.cout * es + 9.0 * d.cin * d.cout * es;
+      };
       fa.chunk_base = base;
       fa.batch = nb;
       HIP_TRY(prof.begin());
       HIP_TRY(launch_first_conv(prec, fa, sm));
-      HIP_TRY(prof.end(OMNISEG_STAGE_FIRST_CONV, 0, nb, 2.0 * 27 * plan->C[0] * (double)T * T * nb,
-                       (double)T * T * nb * (3.0 + plan->C[0] * es)));
+      HIP_TRY(prof.end(OMNISEG_STAGE_FIRST_CONV, 0, nk, 2.0 * 27 * plan->C[0] * (double)T * T * nk,
+                       (double)T * T * nk * (3.0 + plan->C[0] * es)));
       // encoder; with the fused pool, enc_b writes E_l and its pooled copy P
       // and the next conv_a reads P with the plain loader
       const bool fp = fuse_pool(plan);
@@ -963,8 +1135,8 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
           cf = layer_config(plan, 0, l, tl, tl, plan->enc_a[l].cout_p);
           HIP_TRY(launch_conv3x3(prec, fp ? LOAD_PLAIN : LOAD_POOL, EPI_RELU, layer(plan->enc_a[l]), tl, tl, nb, count,
                                  base, fp ? P : E[l - 1], nullptr, A, sm, nullptr, cf));
-          HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nb, conv_flops(plan->enc_a[l], tl, nb),
-                           conv_bytes(plan->enc_a[l], tl, nb, fp ? 1.0 : 4.0), cf));
+          HIP_TRY(prof.end(OMNISEG_STAGE_ENC_A, l, nk, conv_flops(plan->enc_a[l], tl),
+                           conv_bytes(plan->enc_a[l], tl, fp ? 1.0 : 4.0), cf));
         }
         HIP_TRY(prof.begin());
         ConvLayer lb = layer(plan->enc_b[l]);
@@ -972,14 +1144,14 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
         if (fp && l + 1 < L) {
           lb.pool_out = P;
           cf = pool_config(plan, l, tl, tl, plan->enc_b[l].cout_p);
-          pooled_bytes = (double)nb * (tl / 2) * (tl / 2) * plan->enc_b[l].cout * es;
+          pooled_bytes = (double)nk * (tl / 2) * (tl / 2) * plan->enc_b[l].cout * es;
         } else {
           cf = layer_config(plan, 1, l, tl, tl, plan->enc_b[l].cout_p);
         }
         HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, lb, tl, tl, nb, count, base, A, nullptr, E[l], sm,
                                nullptr, cf));
-        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nb, conv_flops(plan->enc_b[l], tl, nb),
-                         conv_bytes(plan->enc_b[l], tl, nb, 1.0) + pooled_bytes, cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_ENC_B, l, nk, conv_flops(plan->enc_b[l], tl),
+                         conv_bytes(plan->enc_b[l], tl, 1.0) + pooled_bytes, cf));
       }
       const int tb = T >> (L - 1);
       HIP_TRY(prof.begin());
@@ -988,84 +1160,44 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
       HIP_TRY(launch_controller(g, nb, plan->G, reinterpret_cast<const float*>(pk + plan->pk_ctrl_w),
                                 reinterpret_cast<const float*>(pk + plan->pk_ctrl_b), plan->P, c.n_classes,
                                 c.n_scales, lay.slots, lay.max_slots, list, count, base, theta, sm));
-      HIP_TRY(prof.end(OMNISEG_STAGE_GAP_CTRL, L - 1, nb,
-                       (double)nb * ((double)plan->G * tb * tb + 2.0 * plan->P * plan->G * lay.max_slots),
-                       (double)nb * tb * tb * plan->G * es));
+      HIP_TRY(prof.end(OMNISEG_STAGE_GAP_CTRL, L - 1, nk,
+                       (double)nk * ((double)plan->G * tb * tb + 2.0 * plan->P * plan->G * lay.max_slots),
+                       (double)nk * tb * tb * plan->G * es));
       for (int l = L - 2; l >= 0; --l) {
         const int tl = T >> l;
         // decoder level l: Z = [up2(D_{l+1}) ; E_l]; D_{l+1} lives in E[l+1]'s buffer
         HIP_TRY(prof.begin());
         int cf = layer_config(plan, 2, l, tl, tl, plan->dec_a[l].cout_p);
-        HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1], E[l], A, sm, nullptr, cf));
-        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nb, conv_flops(plan->dec_a[l], tl, nb), conv_bytes(plan->dec_a[l], tl, nb, 0.5), cf));
+        HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, layer(plan->dec_a[l]), tl, tl, nb, count, base, E[l + 1],
+                               E[l], A, sm, nullptr, cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_A, l, nk, conv_flops(plan->dec_a[l], tl), conv_bytes(plan->dec_a[l], tl, 0.5),
+                         cf));
         HIP_TRY(prof.begin());
         cf = layer_config(plan, 3, l, tl, tl, plan->dec_b[l].cout_p);
-        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A, nullptr, E[l], sm, nullptr, cf));
-        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nb, conv_flops(plan->dec_b[l], tl, nb), conv_bytes(plan->dec_b[l], tl, nb, 1.0), cf));
+        HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A,
+                               nullptr, E[l], sm, nullptr, cf));
+        HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nk, conv_flops(plan->dec_b[l], tl), conv_bytes(plan->dec_b[l], tl, 1.0),
+                         cf));
       }
       HIP_TRY(prof.begin());
       HIP_TRY(launch_head(prec, E[0], nb, T, plan->C[0], plan->Cp[0],
                           plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_w) : nullptr,
                           plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_b) : nullptr,
-                          theta, plan->P, c.head_out, lay.slots, lay.max_slots, list, count, base, logits, sm,
+                          theta, plan->P, c.head_out, lay.slots, lay.max_slots, list, count, base,
+                          lay.resident ? base : base % lay.ring, logits, sm,
                           L >= 2 ? fp8_scale_of(plan, pk, OMNISEG_ACT_DEC_D, 0) : fp8_scale_of(plan, pk, OMNISEG_ACT_ENC_E, 0)));
       {
-        const double px = (double)T * T * nb;
+        const double px = (double)T * T * nk;
         const double pre = plan->canon_pre_w >= 0 ? 2.0 * 8 * plan->C[0] : 0.0;
         // slots per tile vary with the tile's scale; count the largest
         const double head = lay.max_slots * (2.0 * 64 + 2.0 * 64 + 2.0 * 8 * c.head_out);
-        HIP_TRY(prof.end(OMNISEG_STAGE_HEAD, 0, nb, px * (pre + head), px * (plan->C[0] * es + 4.0 * lay.max_slots)));
+        HIP_TRY(prof.end(OMNISEG_STAGE_HEAD, 0, nk, px * (pre + head), px * (plan->C[0] * es + 4.0 * lay.max_slots)));
       }
-    }
-
-    // 4. stitch every (slide, pair)
-    std::vector<int32_t> idx_host;
-    if (plan->profiling) {
-      idx_host.resize(lay.total_tiles);
-      HIP_TRY(hipMemcpyAsync(idx_host.data(), index, sizeof(int32_t) * lay.total_tiles, hipMemcpyDeviceToHost, sm));
-      HIP_TRY(hipStreamSynchronize(sm));
-    }
-    for (int i = 0; i < n_slides; ++i) {
-      for (int p = 0; p < n_pairs; ++p) {
-        const int si = pairs[p].scale;
-        const ScaleGeom& gm = lay.geom[i][si];
-        const omniseg_output& o = outs[(int64_t)i * n_pairs + p];
-        const int gbase = lay.groups.base[i * c.n_scales + si];
-        StitchArgs sa{};
-        sa.logits = logits;
-        sa.tile_stride = (int64_t)lay.max_slots * T * T;
-        sa.slot_off = (int64_t)lay.pair_slot[p] * T * T;
-        sa.index = index + gbase;
-        sa.ny = gm.ny;
-        sa.nx = gm.nx;
-        const int ss = stride_of(c, si);
-        sa.T = T;
-        sa.s = ss;
-        sa.Hk = gm.Hk;
-        sa.Wk = gm.Wk;
-        sa.mask = o.mask;
-        sa.mask_pitch = o.mask_pitch;
-        sa.logit = emit ? o.logit : nullptr;
-        sa.logit_pitch = o.logit_pitch;
-        sa.fg = c.mask_and_fg ? reinterpret_cast<const uint8_t*>(ws + lay.off_fg[i]) : nullptr;
-        sa.fg_shift = lay.kc - gm.k;
-        sa.Hc = lay.Hc[i];
-        sa.Wc = lay.Wc[i];
-        sa.coverage = 0;
-        sa.vote = c.merge == OMNISEG_MERGE_VOTE ? c.vote_threshold[si] : 0;
-        double cover = 0.0;
-        if (plan->profiling) {
-          // every in-plane pixel of every kept tile is read exactly once
-          for (int jy = 0; jy < gm.ny; ++jy)
-            for (int jx = 0; jx < gm.nx; ++jx)
-              if (idx_host[gbase + jy * gm.nx + jx] >= 0)
-                cover += (double)std::min(T, gm.Hk - jy * ss) * std::min(T, gm.Wk - jx * ss);
-        }
-        HIP_TRY(prof.begin());
-        HIP_TRY(launch_stitch(sa, sm));
-        HIP_TRY(prof.end(OMNISEG_STAGE_STITCH, -1, 0, 0.0,
-                         4.0 * cover + (double)gm.Hk * gm.Wk * (1.0 + (emit ? 4.0 : 0.0))));
-      }
+      // 4. stitch the tile rows this batch completed
+      sargs.batch = bi;
+      HIP_TRY(prof.begin());
+      HIP_TRY(launch_stitch_stream(sargs, sm));
+      HIP_TRY(prof.end(OMNISEG_STAGE_STITCH, -1, 0, 0.0, plan->profiling ? stitch_bytes[bi] : 0.0));
     }
     return OMNISEG_OK;
   };
@@ -1079,10 +1211,10 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   mix(&packed, sizeof(packed));
   mix(&workspace, sizeof(workspace));
   mix(&ws_bytes, sizeof(ws_bytes));
-  mix(&n_kept, sizeof(n_kept));
   mix(slides, sizeof(omniseg_slide) * n_slides);
   mix(pairs, sizeof(omniseg_pair) * n_pairs);
   mix(outs, sizeof(omniseg_output) * (size_t)n_slides * n_pairs);
+  mix(plan->tune, sizeof(plan->tune));  // the conv tile configurations are baked into the graph
   for (const auto& gc : plan->graphs) {
     if (gc.key == key) {
       HIP_TRY(hipGraphLaunch(gc.exec, sm));

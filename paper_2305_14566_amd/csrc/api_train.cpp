@@ -365,7 +365,7 @@ int32_t omniseg_train_forward(const omniseg_plan* plan, const void* packed, cons
   HIP_TRY(launch_head(prec, d0, n, T, plan->C[0], plan->Cp[0],
                       plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_w) : nullptr,
                       plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_b) : nullptr, theta,
-                      plan->P, c.head_out, lay.slots, lay.max_slots, list, count, 0, tlog, sm));
+                      plan->P, c.head_out, lay.slots, lay.max_slots, list, count, 0, 0, tlog, sm));
   for (int p = 0; p < n_pairs; ++p) {
     const int si = pairs[p].scale;
     const ScaleGeom& gm = lay.geom[si];

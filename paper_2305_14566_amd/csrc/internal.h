@@ -147,7 +147,7 @@ struct TissueOtsuArgs {
 };
 hipError_t launch_tissue_otsu(const TissueOtsuArgs& a, hipStream_t st);
 hipError_t launch_compact(int32_t* flags_to_index, int total, const TileGroups& g,
-                          int32_t* list, int32_t* count, hipStream_t st);
+                          int32_t* list, int32_t* count, int32_t* pre, hipStream_t st);
 
 struct ConvLayer {
   int cin_p;      // padded input channels (concat: cu_p + ce_p)
@@ -241,11 +241,12 @@ hipError_t launch_controller(const float* g, int batch, int G, const float* wc, 
                              int max_slots, const int32_t* list, const int32_t* count,
                              int chunk_base, float* theta, hipStream_t st);
 
-// d0_scale: FP8 channel scales of d0 (null otherwise)
+// Tile chunk_base + b of the list writes its logits to slot out_base + b of
+// tile_logits.  d0_scale: FP8 channel scales of d0 (null otherwise).
 hipError_t launch_head(int precision, const void* d0, int batch, int T, int c0, int c0_p,
                        const float* wp, const float* bp, const float* theta, int P, int o,
                        const SlotTable& slots, int max_slots, const int32_t* list,
-                       const int32_t* count, int chunk_base, float* tile_logits,
+                       const int32_t* count, int chunk_base, int out_base, float* tile_logits,
                        hipStream_t st, const float* d0_scale = nullptr);
 
 // ---- FP8 calibration and packing --------------------------------------------
@@ -276,8 +277,70 @@ struct StitchArgs {
   int fg_shift, Hc, Wc;
   int coverage;       // 1: mask = (D > 0) instead of (N > 0)
   int vote;           // > 0: majority vote -- mask = (number of covering tiles with logit > 0) >= vote
+  int ring = 0;       // > 0: list index t lives in logit slot t % ring (a ring store)
 };
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t st);
+
+// ---- streamed stitch of omniseg_segment_slide ---------------------------------
+//
+// The backbone runs over the kept-tile list in batches of B list positions
+// (batch b holds positions [b B, (b + 1) B)), and the tile logits go to a
+// ring of slots (position p in slot p % ring).  The output planes are
+// stitched in units of one tile row: unit (group g, row j) owns the output
+// rows whose last covering tile row is j, [j s, (j + 1) s) (the last row of
+// the grid also owns the rows below it, down to H_k).  Its covering tiles are
+// list positions before pre[grid index of (j + 1, 0)], so the unit is stitched
+// right after the batch that holds the last of them (batch 0 when there is
+// none).  Units are enumerated group by group, rows in order, so their
+// batches do not decrease.  Each unit is cut into items: one plane (pair)
+// and kStitchRows output rows each.
+constexpr int kStitchRows = 8;
+
+struct StreamGroup {
+  int64_t grid_base;   // canonical index of the group's first grid tile
+  int64_t item_base;   // first item of the group
+  int ny, nx, s, Hk, Wk;
+  int unit_base;       // first unit of the group
+  int plane_first, n_planes;
+  const uint8_t* fg;   // tissue map for mask_and_fg (or null)
+  int fg_shift, Hc, Wc;
+  int vote;            // > 0: majority vote threshold of the group's scale slot
+};
+struct StreamPlane {
+  uint8_t* mask;
+  float* logit;        // or null
+  int64_t mask_pitch, logit_pitch;
+  int64_t slot_off;    // float offset of the pair's plane inside a tile slot
+  int mode;            // 0: one pixel per thread; 1: four; 2: four, at most 2 x 2 covering tiles
+  int pad_;
+};
+struct StreamUnit {
+  int batch;           // the batch after which the unit is stitched
+  int g, y0, y1;
+  int64_t item_base;   // first item of the unit (the entry after the last unit: the item count)
+};
+struct StreamStitchArgs {
+  const StreamGroup* groups;
+  const StreamPlane* planes;
+  StreamUnit* units;   // n_units + 1 entries
+  int n_groups, n_units;
+  const int32_t* pre;  // kept tiles before each grid tile (grid tiles + 1 entries)
+  const int32_t* index;  // list index per grid tile, or -1
+  const float* logits;
+  int64_t tile_stride; // floats per logit slot
+  int ring;            // logit slots
+  int T, B;            // tile size, list positions per batch
+  int batch;           // k_stitch_stream: the batch just computed
+  int64_t n_items;     // items of all units
+};
+// Unit table from the compacted list (one thread per unit).
+hipError_t launch_stream_units(const StreamStitchArgs& a, hipStream_t st);
+// Stitches every unit of batch a.batch.
+hipError_t launch_stitch_stream(const StreamStitchArgs& a, hipStream_t st);
+// Writes `bytes` (a multiple of 4) from host memory to device memory with
+// kernels whose arguments carry the data, so the write is captured by value
+// in a HIP graph (no host pointer is kept).
+hipError_t launch_put(void* dst, const void* src, int64_t bytes, hipStream_t st);
 hipError_t launch_grid_from_list(const int32_t* tile_yx, int n_tiles, int ny, int nx,
                                  int32_t* grid, hipStream_t st);
 

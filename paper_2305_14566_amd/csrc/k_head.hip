@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
                                               const float* __restrict__ theta, int P,
                                               SlotTable slots, int max_slots,
                                               const int32_t* list, const int32_t* count,
-                                              int chunk_base, float* __restrict__ out,
+                                              int chunk_base, int out_base, float* __restrict__ out,
                                               const float* __restrict__ dscale) {
   const int per_tile = T2 / 256;
   const int b = blockIdx.x / per_tile;
@@ -314,22 +314,22 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
       z[o] = s;
     }
     const float l = (O == 1) ? z[0] : z[O - 1] - z[0];
-    out[((int64_t)(chunk_base + b) * max_slots + j) * T2 + pix] = l;
+    out[((int64_t)(out_base + b) * max_slots + j) * T2 + pix] = l;
   }
 }
 
 hipError_t launch_head(int precision, const void* d0, int batch, int T, int c0, int c0_p,
                        const float* wp, const float* bp, const float* theta, int P, int o,
                        const SlotTable& slots, int max_slots, const int32_t* list,
-                       const int32_t* count, int chunk_base, float* tile_logits, hipStream_t st,
-                       const float* d0_scale) {
+                       const int32_t* count, int chunk_base, int out_base, float* tile_logits,
+                       hipStream_t st, const float* d0_scale) {
   const int T2 = T * T;
   if (T2 % 256 || c0 > 256 || max_slots > OMNISEG_MAX_CLASSES) return hipErrorInvalidValue;
   if ((precision == OMNISEG_FP8) != (d0_scale != nullptr)) return hipErrorInvalidValue;
   dim3 grid(batch * (T2 / 256));
 #define OMNISEG_HEAD(TY, O)                                                                                      \
   hipLaunchKernelGGL((k_head<TY, O>), grid, dim3(256), 0, st, (const TY*)d0, T2, c0, c0_p, wp, bp, theta, P, \
-                     slots, max_slots, list, count, chunk_base, tile_logits, d0_scale)
+                     slots, max_slots, list, count, chunk_base, out_base, tile_logits, d0_scale)
   if (precision == OMNISEG_FP8) {
     if (o == 1) OMNISEG_HEAD(uint8_t, 1); else OMNISEG_HEAD(uint8_t, 2);
   } else if (precision == OMNISEG_BF16) {

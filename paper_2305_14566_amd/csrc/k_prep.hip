@@ -9,6 +9,7 @@
 // when its gray value 0.299 R + 0.587 G + 0.114 B is below a threshold,
 // tested exactly in integers (blank-region removal, Section 2.1).
 #include <algorithm>
+#include <cstring>
 
 #include "internal.h"
 
@@ -236,9 +237,11 @@ hipError_t launch_tile_flags(const TileGroups& g, const SlideDev* slides_dev, in
 
 // Single-workgroup ordered compaction: flags (0/1 per grid tile, canonical
 // order) become list indices (-1 for dropped tiles); kept tiles are appended
-// to the list as (slide, slot, jy, jx) in canonical order.
+// to the list as (slide, slot, jy, jx) in canonical order.  pre[t] (total + 1
+// entries) is the number of kept tiles before grid tile t, so the kept tiles
+// of grid tiles [a, b) are the list positions [pre[a], pre[b]).
 __global__ __launch_bounds__(1024) void k_compact(int32_t* idx, int total, TileGroups g,
-                                                  int4* list, int32_t* count) {
+                                                  int4* list, int32_t* count, int32_t* pre) {
   __shared__ int wave_tot[16];
   __shared__ int run;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -255,6 +258,7 @@ __global__ __launch_bounds__(1024) void k_compact(int32_t* idx, int total, TileG
     int off = run;
     for (int w = 0; w < wave; ++w) off += wave_tot[w];
     if (t < total) {
+      pre[t] = off + before;
       if (f) {
         const int pos = off + before;
         while (gi + 1 < g.n && g.base[gi + 1] <= t) ++gi;
@@ -273,13 +277,37 @@ __global__ __launch_bounds__(1024) void k_compact(int32_t* idx, int total, TileG
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *count = run;
+  if (threadIdx.x == 0) {
+    *count = run;
+    pre[total] = run;
+  }
+}
+
+// launch_put: one workgroup per payload of kPutWords words.
+constexpr int kPutWords = 896;
+struct PutPayload {
+  uint32_t w[kPutWords];
+};
+__global__ __launch_bounds__(256) void k_put(uint32_t* dst, int n, PutPayload p) {
+  for (int i = threadIdx.x; i < n; i += 256) dst[i] = p.w[i];
+}
+
+hipError_t launch_put(void* dst, const void* src, int64_t bytes, hipStream_t st) {
+  if (bytes % 4) return hipErrorInvalidValue;
+  const int64_t n = bytes / 4;
+  for (int64_t o = 0; o < n; o += kPutWords) {
+    PutPayload p;
+    const int m = (int)std::min<int64_t>(kPutWords, n - o);
+    memcpy(p.w, static_cast<const uint32_t*>(src) + o, (size_t)m * 4);
+    hipLaunchKernelGGL(k_put, dim3(1), dim3(256), 0, st, static_cast<uint32_t*>(dst) + o, m, p);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_compact(int32_t* flags_to_index, int total, const TileGroups& g, int32_t* list,
-                          int32_t* count, hipStream_t st) {
+                          int32_t* count, int32_t* pre, hipStream_t st) {
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, flags_to_index, total, g,
-                     reinterpret_cast<int4*>(list), count);
+                     reinterpret_cast<int4*>(list), count, pre);
   return hipGetLastError();
 }
 

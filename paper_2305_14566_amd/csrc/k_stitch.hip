@@ -16,6 +16,11 @@
 
 namespace omniseg {
 
+// Logit slot of list index t: t itself, or t % ring in a ring store.
+__device__ __forceinline__ int64_t tile_slot(const StitchArgs& a, int t) {
+  return a.ring > 0 ? (int64_t)(t % a.ring) : (int64_t)t;
+}
+
 __device__ __forceinline__ void stitch_pixel(const StitchArgs& a, int x, int y) {
   const int T = a.T, s = a.s;
   const int jy0 = (y < T) ? 0 : (y - T) / s + 1, jy1 = min(a.ny - 1, y / s);
@@ -29,7 +34,7 @@ __device__ __forceinline__ void stitch_pixel(const StitchArgs& a, int x, int y) 
         const int t = a.index[jy * a.nx + jx];
         if (t < 0) continue;
         const int ix = x - jx * s;
-        votes += a.logits[(int64_t)t * a.tile_stride + a.slot_off + (int64_t)iy * T + ix] > 0.f ? 1 : 0;
+        votes += a.logits[tile_slot(a, t) * a.tile_stride + a.slot_off + (int64_t)iy * T + ix] > 0.f ? 1 : 0;
         ++cover;
       }
     }
@@ -49,7 +54,7 @@ __device__ __forceinline__ void stitch_pixel(const StitchArgs& a, int x, int y) 
       if (t < 0) continue;
       const int ix = x - jx * s;
       const int w = ry * min(ix + 1, T - ix);
-      const float v = (float)w * a.logits[(int64_t)t * a.tile_stride + a.slot_off + (int64_t)iy * T + ix];
+      const float v = (float)w * a.logits[tile_slot(a, t) * a.tile_stride + a.slot_off + (int64_t)iy * T + ix];
       const float t2 = sum + v;
       comp += (fabsf(sum) >= fabsf(v)) ? ((sum - t2) + v) : ((v - t2) + sum);
       sum = t2;
@@ -82,7 +87,7 @@ __device__ __forceinline__ void stitch_span4(const StitchArgs& a, int x0, int y)
         if (t < 0) continue;
         const int ix = x0 - jx * s;
         const float4 l =
-            *reinterpret_cast<const float4*>(a.logits + (int64_t)t * a.tile_stride + a.slot_off + (int64_t)iy * T + ix);
+            *reinterpret_cast<const float4*>(a.logits + tile_slot(a, t) * a.tile_stride + a.slot_off + (int64_t)iy * T + ix);
         votes[0] += l.x > 0.f ? 1 : 0;
         votes[1] += l.y > 0.f ? 1 : 0;
         votes[2] += l.z > 0.f ? 1 : 0;
@@ -106,7 +111,7 @@ __device__ __forceinline__ void stitch_span4(const StitchArgs& a, int x0, int y)
         if (t < 0) continue;
         const int ix = x0 - jx * s;
         const float4 l4 =
-            *reinterpret_cast<const float4*>(a.logits + (int64_t)t * a.tile_stride + a.slot_off + (int64_t)iy * T + ix);
+            *reinterpret_cast<const float4*>(a.logits + tile_slot(a, t) * a.tile_stride + a.slot_off + (int64_t)iy * T + ix);
         const float l[4] = {l4.x, l4.y, l4.z, l4.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -167,7 +172,7 @@ __device__ __forceinline__ void stitch_span4_2x2(const StitchArgs& a, int x0, in
       const int tt = t[u][v];
       const int iy = y - (jy0 + u) * s, ix = x0 - (jx0 + v) * s;
       const __amdgpu_buffer_rsrc_t r =
-          tile_rsrc(a.logits + (int64_t)max(tt, 0) * a.tile_stride, tt >= 0 ? (uint32_t)(a.tile_stride * 4) : 0u);
+          tile_rsrc(a.logits + tile_slot(a, max(tt, 0)) * a.tile_stride, tt >= 0 ? (uint32_t)(a.tile_stride * 4) : 0u);
       const uint32_t off = (uint32_t)(a.slot_off + (int64_t)iy * T + ix) * 4u;
       L[u][v] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, tt >= 0 ? off : 0u, 0, 0));
     }
@@ -276,6 +281,134 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t st) {
     dim3 grid(ceil_div(a.Wk, 256), std::min(a.Hk, kMaxGridY));
     hipLaunchKernelGGL(k_stitch, grid, dim3(256), 0, st, a);
   }
+  return hipGetLastError();
+}
+
+// ---- streamed stitch --------------------------------------------------------
+
+// First unit in [0, n) whose batch is >= b (the units' batches do not decrease).
+__device__ int first_unit_of_batch(const StreamUnit* u, int n, int b) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (u[m].batch < b) lo = m + 1;
+    else hi = m;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_stream_units(StreamStitchArgs a) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u > a.n_units) return;
+  StreamUnit out;
+  if (u == a.n_units) {  // sentinel after the last unit: the item count
+    out.batch = INT32_MAX;
+    out.g = a.n_groups;
+    out.y0 = out.y1 = 0;
+    out.item_base = a.n_items;
+    a.units[u] = out;
+    return;
+  }
+  // the group of the unit: the last one whose first unit is <= u (every group
+  // has at least one tile row, so the first units increase)
+  int lo = 0, hi = a.n_groups - 1;
+  while (lo < hi) {
+    const int m = (lo + hi + 1) >> 1;
+    if (a.groups[m].unit_base <= u) lo = m;
+    else hi = m - 1;
+  }
+  const StreamGroup& G = a.groups[lo];
+  const int j = u - G.unit_base;
+  const int pos_end = a.pre[G.grid_base + (int64_t)(j + 1) * G.nx];
+  out.batch = pos_end > 0 ? (pos_end - 1) / a.B : 0;
+  out.g = lo;
+  out.y0 = j * G.s;
+  out.y1 = j == G.ny - 1 ? G.Hk : (j + 1) * G.s;
+  // every row of the group before this unit's is a full row of s rows
+  out.item_base = G.item_base + (int64_t)G.n_planes * j * ((G.s + kStitchRows - 1) / kStitchRows);
+  a.units[u] = out;
+}
+
+hipError_t launch_stream_units(const StreamStitchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_stream_units, dim3(ceil_div(a.n_units + 1, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Every unit of batch a.batch: a persistent grid takes the units' items
+// (one plane, kStitchRows rows) in turn; per pixel the arithmetic and its
+// order are those of the plane-wise stitch.
+__global__ __launch_bounds__(256) void k_stitch_stream(StreamStitchArgs a) {
+  __shared__ int s_u[3];
+  if (threadIdx.x == 0) {
+    s_u[0] = first_unit_of_batch(a.units, a.n_units, a.batch);
+    s_u[1] = first_unit_of_batch(a.units, a.n_units, a.batch + 1);
+  }
+  __syncthreads();
+  const int u_lo = s_u[0], u_hi = s_u[1];
+  if (u_lo >= u_hi) return;
+  const int64_t i_hi = a.units[u_hi].item_base;
+  int cur = u_lo;
+  for (int64_t it = a.units[u_lo].item_base + blockIdx.x; it < i_hi; it += gridDim.x) {
+    __syncthreads();  // every thread has read s_u[2] of the previous item
+    if (threadIdx.x == 0) {
+      // the item's unit: the last one in [cur, u_hi) whose first item is <= it
+      int lo = cur, hi = u_hi - 1;
+      while (lo < hi) {
+        const int m = (lo + hi + 1) >> 1;
+        if (a.units[m].item_base <= it) lo = m;
+        else hi = m - 1;
+      }
+      s_u[2] = lo;
+    }
+    __syncthreads();
+    cur = s_u[2];
+    const StreamUnit un = a.units[cur];
+    const StreamGroup& G = a.groups[un.g];
+    const int nblk = (un.y1 - un.y0 + kStitchRows - 1) / kStitchRows;
+    const int local = (int)(it - un.item_base);
+    const StreamPlane& P = a.planes[G.plane_first + local / nblk];
+    StitchArgs sa;
+    sa.logits = a.logits;
+    sa.tile_stride = a.tile_stride;
+    sa.slot_off = P.slot_off;
+    sa.index = a.index + G.grid_base;
+    sa.ny = G.ny;
+    sa.nx = G.nx;
+    sa.T = a.T;
+    sa.s = G.s;
+    sa.Hk = G.Hk;
+    sa.Wk = G.Wk;
+    sa.mask = P.mask;
+    sa.mask_pitch = P.mask_pitch;
+    sa.logit = P.logit;
+    sa.logit_pitch = P.logit_pitch;
+    sa.fg = G.fg;
+    sa.fg_shift = G.fg_shift;
+    sa.Hc = G.Hc;
+    sa.Wc = G.Wc;
+    sa.coverage = 0;
+    sa.vote = G.vote;
+    sa.ring = a.ring;
+    const int r0 = un.y0 + (local % nblk) * kStitchRows, r1 = min(un.y1, r0 + kStitchRows);
+    for (int y = r0; y < r1; ++y) {
+      if (P.mode == 0) {
+        for (int x = threadIdx.x; x < sa.Wk; x += 256) stitch_pixel(sa, x, y);
+        continue;
+      }
+      for (int x0 = threadIdx.x * 4; x0 < sa.Wk; x0 += 1024) {
+        if (x0 + 3 < sa.Wk) {
+          if (P.mode == 2) stitch_span4_2x2(sa, x0, y);
+          else stitch_span4(sa, x0, y);
+        } else {
+          for (int x = x0; x < sa.Wk; ++x) stitch_pixel(sa, x, y);
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_stitch_stream(const StreamStitchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_stitch_stream, dim3(2048), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ UPSAMPLE_NEAREST, UPSAMPLE_BILINEAR = 0, 1
 TISSUE_GRAY, TISSUE_OTSU = 0, 1
 (REGION_PAD, REGION_PYRAMID, REGION_TISSUE, REGION_TILE_COUNT, REGION_TILE_LIST,
  REGION_TILE_INDEX, REGION_TILE_LOGITS, REGION_TISSUE_GRAY, REGION_TISSUE_STATS) = range(9)
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
 N_CONV_CONFIGS = 11
@@ -54,7 +54,7 @@ class Config(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("batch_tiles", ctypes.c_int32),
-        ("max_kept_tiles", ctypes.c_int32),
+        ("logit_ring_tiles", ctypes.c_int32),
         ("scale_stride", ctypes.c_int32 * 4),
         ("merge", ctypes.c_int32),
         ("vote_threshold", ctypes.c_int32 * 4),
@@ -190,7 +190,7 @@ class Plan:
     def __init__(self, base=8, levels=3, head_out=1, n_classes=1, scales=(0,), tile=128,
                  stride=64, fg_filter=False, fg_threshold=220, mask_and_fg=False,
                  precision=FP32, emit_logits=False, batch_tiles=0, training=False, graph=False,
-                 max_kept_tiles=0, scale_strides=None, merge=MERGE_RAMP, vote_thresholds=None,
+                 logit_ring_tiles=0, scale_strides=None, merge=MERGE_RAMP, vote_thresholds=None,
                  tissue_method=TISSUE_GRAY, median_kernel=1, min_tissue_area=0):
         c = Config()
         c.abi_version = ABI_VERSION
@@ -210,7 +210,7 @@ class Plan:
         c.flags = ((FLAG_EMIT_LOGITS if emit_logits else 0) | (FLAG_TRAINING if training else 0)
                    | (FLAG_GRAPH if graph else 0))
         c.batch_tiles = batch_tiles
-        c.max_kept_tiles = max_kept_tiles
+        c.logit_ring_tiles = logit_ring_tiles
         for i, v in enumerate(scale_strides or ()):
             c.scale_stride[i] = v
         c.merge = merge

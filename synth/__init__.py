@@ -14,7 +14,7 @@ from .slides import (
     soft_targets,
     CLASS_NAMES,
 )
-from .weights import weight_layout, he_normal_weights, head_param_count
+from .weights import weight_layout, he_normal_weights, head_param_count, training_init_weights
 
 __all__ = [
     "ellipse_slide",
@@ -26,4 +26,5 @@ __all__ = [
     "weight_layout",
     "he_normal_weights",
     "head_param_count",
+    "training_init_weights",
 ]

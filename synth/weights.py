@@ -68,3 +68,20 @@ def he_normal_weights(seed, base, levels, n_classes, n_scales, head_out, bias_st
         else:
             parts.append(np.zeros(n))
     return np.concatenate(parts).astype(np.float32)
+
+
+def training_init_weights(seed, base, levels, n_classes, n_scales, head_out):
+    """Start point for training: the he_normal_weights draw with the second
+    (residual) conv of every block set to zero, so each block starts as its
+    first conv and activations keep their scale through the depth (the
+    He-normal network's logits grow to ~1e5, where BCE gradients are
+    useless).  Biases are zero."""
+    flat = he_normal_weights(seed, base, levels, n_classes, n_scales, head_out).copy()
+    off = 0
+    for name, shape, _ in weight_layout(base, levels, n_classes, n_scales, head_out):
+        n = int(np.prod(shape))
+        if name.endswith(".b.w"):
+            flat[off:off + n] = 0.0
+        off += n
+    return flat
+

@@ -68,7 +68,7 @@ def _cfg(**kw):
     c.precision = om.FP32
     c.flags = 0
     c.batch_tiles = 0
-    c.max_kept_tiles = 0
+    c.logit_ring_tiles = 0
     for k, v in kw.items():
         setattr(c, k, v)
     return c
@@ -79,7 +79,7 @@ def _cfg(**kw):
     ("levels", 0, 1), ("head_out", 3, 1), ("n_classes", 0, 1), ("n_classes", 17, 1),
     ("n_scales", 5, 1), ("tile", 100, 1), ("tile", 1024, 1), ("stride", 0, 1), ("stride", 129, 1),
     ("levels", 6, 2), ("fg_threshold", 0, 1), ("precision", 7, 2), ("flags", 8, 1),
-    ("batch_tiles", -1, 1), ("fg_filter", 2, 1), ("max_kept_tiles", -1, 1),
+    ("batch_tiles", -1, 1), ("fg_filter", 2, 1), ("logit_ring_tiles", -1, 1),
 ])
 def test_plan_create_rejects(field, value, status):
     lib = om.lib()
