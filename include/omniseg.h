@@ -382,6 +382,24 @@ int32_t omniseg_stitch_tiles(int32_t tile, int32_t stride, int32_t height, int32
                              int32_t n_tiles, uint8_t* mask, int64_t mask_pitch,
                              float* logit, int64_t logit_pitch, void* workspace,
                              int64_t ws_bytes, omniseg_stream stream);
+/*
+ * omniseg_stitch_tiles for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, outputs and arithmetic, without the
+ * workspace.  The tile-index grid lives in a library-owned device array of
+ * 2^20 int32 positions (4 MiB per device, held until the process ends), so
+ * grids of more than 2^20 tile positions are ERR_UNSUPPORTED.  Allocates
+ * nothing: the first call on a device looks the array up
+ * (hipGetSymbolAddress).  Every call on one device shares that device's
+ * array: calls that overlap on a device (other streams, other threads) race
+ * and must be serialised by the caller.  Each call rewrites the whole grid
+ * it uses before reading it.
+ */
+int32_t omniseg_stitch_tiles_noalloc(int32_t tile, int32_t stride, int32_t height, int32_t width,
+                                     int32_t vote_threshold, const float* tile_logits,
+                                     const int32_t* tile_yx, int32_t n_tiles, uint8_t* mask,
+                                     int64_t mask_pitch, float* logit, int64_t logit_pitch,
+                                     omniseg_stream stream);
 
 /*
  * Merge of each class's result to the 40x base (Section 2.3: one merged 40x

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libomniseg.so")
-SOURCES = ["k_prep.hip", "k_tissue.hip", "k_map.hip", "k_conv.hip", "k_head.hip", "k_stitch.hip", "k_pack.hip", "k_bwd.hip", "api.cpp", "api_train.cpp", "api_map.cpp"]
+SOURCES = ["k_prep.hip", "k_tissue.hip", "k_map.hip", "k_conv.hip", "k_head.hip", "k_stitch.hip", "k_pack.hip", "k_bwd.hip", "api.cpp", "api_train.cpp", "api_map.cpp", "api_noalloc.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -118,6 +118,7 @@ def _declare(lib):
         "omniseg_workspace_region": (i32, [vp, P(Slide), i32, P(Pair), i32, i32, i32, P(i64), P(i64)]),
         "omniseg_stitch_workspace_bytes": (i32, [i32, i32, i32, i32, P(i64)]),
         "omniseg_stitch_tiles": (i32, [i32, i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, i64, vp, i64, vp]),
+        "omniseg_stitch_tiles_noalloc": (i32, [i32, i32, i32, i32, i32, vp, vp, i32, vp, i64, vp, i64, vp]),
         "omniseg_set_profiling": (i32, [vp, i32]),
         "omniseg_set_conv_tuning": (i32, [vp, i32, i32, i32]),
         "omniseg_get_conv_tuning": (i32, [vp, i32, i32, P(i32)]),
@@ -444,6 +445,17 @@ def stitch_tiles(tile, stride, height, width, tile_logits, tile_yx, emit_logits=
                                   _ptr(mask), mask.stride(0), _ptr(logit),
                                   logit.stride(0) if logit is not None else 0, _ptr(ws), ws.numel(),
                                   _stream(stream)))
+    return mask, logit
+
+
+def stitch_tiles_noalloc(tile, stride, height, width, tile_logits, tile_yx, mask, logit=None, stream=None,
+                         vote_threshold=0):
+    """stitch_tiles into caller-provided outputs with the library's own index
+    grid (no workspace, nothing allocated by the library)."""
+    n_tiles = tile_yx.shape[0]
+    _check(lib().omniseg_stitch_tiles_noalloc(tile, stride, height, width, vote_threshold, _ptr(tile_logits),
+                                              _ptr(tile_yx), n_tiles, _ptr(mask), mask.stride(0), _ptr(logit),
+                                              logit.stride(0) if logit is not None else 0, _stream(stream)))
     return mask, logit
 
 
