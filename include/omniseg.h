@@ -494,6 +494,27 @@ int32_t omniseg_conv3x3(int32_t precision, int32_t mode, int32_t n, int32_t heig
                         void* y_pool, int32_t config, void* workspace, int64_t ws_bytes,
                         omniseg_stream stream);
 /*
+ * Weight gradient of one stand-alone 3x3 convolution (verification of the
+ * backward's kernels): dW[o][c][i][j] = sum over images and output pixels of
+ * dY[o][y][x] * Xin[c][y + i - 1][x + j - 1], Xin taken as 0 outside the
+ * image, where Xin is the conv's input as omniseg_conv3x3 forms it for
+ * `mode`: OMNISEG_CONV_RELU (x0), OMNISEG_CONV_POOL_RELU (maxpool2x2 of the
+ * 2H x 2W x0) or OMNISEG_CONV_UPCAT_RELU ([up2(x0); x1], cu < cin).
+ *   precision  OMNISEG_FP32 or OMNISEG_BF16: the element type of x0, x1
+ *              and dy (BF16 runs on BF16 MFMA with FP32 accumulation).
+ *   dy         device NHWC [n][H][W][pad32(cout)] (zeros in the padding).
+ *   dw         device FP32, canonical [cout][cin][3][3].
+ * The pixel sum is split over fixed slots and reduced in a fixed order
+ * (deterministic).  H, W multiples of 8 in [8, 4096]; n >= 1.
+ * workspace: device, >= omniseg_conv3x3_wgrad_workspace_bytes.
+ */
+int32_t omniseg_conv3x3_wgrad_workspace_bytes(int32_t n, int32_t height, int32_t width, int32_t cin,
+                                              int32_t cu, int32_t cout, int64_t* bytes);
+int32_t omniseg_conv3x3_wgrad(int32_t precision, int32_t mode, int32_t n, int32_t height, int32_t width,
+                              int32_t cin, int32_t cu, int32_t cout, const void* x0, const void* x1,
+                              const void* dy, float* dw, void* workspace, int64_t ws_bytes,
+                              omniseg_stream stream);
+/*
  * FP8 form of omniseg_conv3x3 (modes RELU, RES_RELU, POOL_RELU, UPCAT_RELU;
  * the FP8 backbone described at omniseg_pack_weights_fp8).  x0 (and x1 for
  * UPCAT) hold E4M3 codes (uint8, NHWC, channels padded to 32) of

@@ -15,6 +15,8 @@
 #include <cstring>
 #include <vector>
 
+#include <climits>
+
 #include "plan.h"
 
 using namespace omniseg;
@@ -586,6 +588,72 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
     }
   }
 #undef OMNISEG_CALL
+  return OMNISEG_OK;
+}
+
+namespace {
+struct WgradGeom {
+  int cin_p, cu_p, cout_p, chunks, splits;
+};
+int32_t wgrad_geom(int32_t n, int32_t height, int32_t width, int32_t cin, int32_t cu, int32_t cout, WgradGeom* g) {
+  if (n < 1 || height < 8 || width < 8 || height % 8 || width % 8 || height > 4096 || width > 4096)
+    return fail(OMNISEG_ERR_ARG, "n >= 1 and H, W multiples of 8 in [8, 4096] required");
+  if (cin < 1 || cout < 1 || cu < 1 || cu > cin || cin > 8192 || cout > 8192) return fail(OMNISEG_ERR_ARG, "bad channel counts");
+  g->cu_p = pad_ch(cu);
+  g->cin_p = cu < cin ? g->cu_p + pad_ch(cin - cu) : pad_ch(cin);
+  g->cout_p = pad_ch(cout);
+  const int64_t chunks = (int64_t)n * (height / 8) * (width / (width % 16 == 0 ? 16 : 8));
+  if (chunks > INT32_MAX) return fail(OMNISEG_ERR_UNSUPPORTED, "too many pixel blocks");
+  g->chunks = (int)chunks;
+  g->splits = wgrad_splits(g->cout_p, g->cin_p, g->chunks);
+  return OMNISEG_OK;
+}
+}  // namespace
+
+int32_t omniseg_conv3x3_wgrad_workspace_bytes(int32_t n, int32_t height, int32_t width, int32_t cin, int32_t cu,
+                                              int32_t cout, int64_t* bytes) {
+  if (!bytes) return fail(OMNISEG_ERR_ARG, "bytes is NULL");
+  WgradGeom g;
+  const int32_t st = wgrad_geom(n, height, width, cin, cu, cout, &g);
+  if (st) return st;
+  *bytes = align256((int64_t)g.splits * g.cout_p * 9 * g.cin_p * 4);
+  return OMNISEG_OK;
+}
+
+int32_t omniseg_conv3x3_wgrad(int32_t precision, int32_t mode, int32_t n, int32_t height, int32_t width, int32_t cin,
+                              int32_t cu, int32_t cout, const void* x0, const void* x1, const void* dy, float* dw,
+                              void* workspace, int64_t ws_bytes, omniseg_stream stream) {
+  if (precision != OMNISEG_FP32 && precision != OMNISEG_BF16) return fail(OMNISEG_ERR_UNSUPPORTED, "precision %d", precision);
+  int loader;
+  if (mode == OMNISEG_CONV_RELU) loader = LOAD_PLAIN;
+  else if (mode == OMNISEG_CONV_POOL_RELU) loader = LOAD_POOL;
+  else if (mode == OMNISEG_CONV_UPCAT_RELU) loader = LOAD_UPCAT;
+  else return fail(OMNISEG_ERR_ARG, "mode %d: RELU, POOL_RELU or UPCAT_RELU", mode);
+  WgradGeom g;
+  int32_t st = wgrad_geom(n, height, width, cin, cu, cout, &g);
+  if (st) return st;
+  if (loader == LOAD_UPCAT) {
+    if (!x1 || cu >= cin || height % 2 || width % 2) return fail(OMNISEG_ERR_ARG, "UPCAT needs x1, cu < cin and even H, W");
+  } else if (cu != cin) {
+    return fail(OMNISEG_ERR_ARG, "cu must equal cin outside UPCAT");
+  }
+  if (!x0 || !dy || !dw || !workspace) return fail(OMNISEG_ERR_ARG, "NULL argument");
+  if (ws_bytes < (int64_t)g.splits * g.cout_p * 9 * g.cin_p * 4) return fail(OMNISEG_ERR_WORKSPACE, "workspace too small");
+  (void)hipGetLastError();
+  WgradArgs wa{};
+  wa.x0 = x0;
+  wa.x1 = x1;
+  wa.dy = dy;
+  wa.part = static_cast<float*>(workspace);
+  wa.H = height;
+  wa.W = width;
+  wa.cin_p = g.cin_p;
+  wa.cu_p = loader == LOAD_UPCAT ? g.cu_p : g.cin_p;
+  wa.cout_p = g.cout_p;
+  wa.n_tiles = n;
+  wa.splits = g.splits;
+  HIP_TRY(launch_wgrad(precision, precision, loader, wa, cout, cin, loader == LOAD_UPCAT ? cu : cin, dw,
+                       reinterpret_cast<hipStream_t>(stream)));
   return OMNISEG_OK;
 }
 

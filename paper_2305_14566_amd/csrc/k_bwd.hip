@@ -603,6 +603,145 @@ __global__ __launch_bounds__(256) void k_wgrad3x3(WgradArgs a) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// The same weight gradient for BF16 inputs and output gradients on BF16 MFMA
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation): the products are exact in
+// FP32 and the pixel sums run in FP32, as in the FP32-MFMA kernel.  K (the
+// MFMA reduction) is the pixel, so both operands are staged transposed in
+// LDS: dY as [o][pixel], and the input halo as [dx][c][halo row][x], one
+// copy per horizontal tap offset dx, so that every operand read is one
+// aligned 16-byte vector of 8 consecutive pixels.  A block owns BO output
+// and 32 input channels; its four waves split them 2 x 2; one chunk is an
+// 8-row x BX-column pixel block (K steps of 32 pixels).
+// ---------------------------------------------------------------------------
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+template <int LOADER>
+__device__ __forceinline__ uint4 wg_load_x_bf16(const WgradArgs& a, int b, int y, int x, int c) {
+  const uint16_t* X0 = (const uint16_t*)a.x0;
+  if (LOADER == LOAD_PLAIN) {
+    return *reinterpret_cast<const uint4*>(X0 + (((int64_t)b * a.H + y) * a.W + x) * a.cin_p + c);
+  } else if (LOADER == LOAD_POOL) {
+    const int W2 = 2 * a.W;
+    const uint16_t* p = X0 + (((int64_t)b * 2 * a.H + 2 * y) * W2 + 2 * x) * a.cin_p + c;
+    uint4 q[4];
+    q[0] = *reinterpret_cast<const uint4*>(p);
+    q[1] = *reinterpret_cast<const uint4*>(p + a.cin_p);
+    q[2] = *reinterpret_cast<const uint4*>(p + (int64_t)W2 * a.cin_p);
+    q[3] = *reinterpret_cast<const uint4*>(p + (int64_t)W2 * a.cin_p + a.cin_p);
+    uint4 r;
+    uint16_t* rr = reinterpret_cast<uint16_t*>(&r);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      float m = ldf(reinterpret_cast<const uint16_t*>(&q[0]) + k);
+#pragma unroll
+      for (int j = 1; j < 4; ++j) m = fmaxf(m, ldf(reinterpret_cast<const uint16_t*>(&q[j]) + k));
+      rr[k] = (uint16_t)(__float_as_uint(m) >> 16);  // the maximum is one of the BF16 inputs: exact
+    }
+    return r;
+  } else {
+    if (c < a.cu_p) {
+      const uint16_t* p = X0 + (((int64_t)b * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1)) * a.cu_p + c;
+      return *reinterpret_cast<const uint4*>(p);
+    }
+    const int ce_p = a.cin_p - a.cu_p;
+    const uint16_t* p = (const uint16_t*)a.x1 + (((int64_t)b * a.H + y) * a.W + x) * ce_p + (c - a.cu_p);
+    return *reinterpret_cast<const uint4*>(p);
+  }
+}
+
+template <int BX, int BO, int LOADER>
+__global__ __launch_bounds__(256) void k_wgrad3x3_bf16(WgradArgs a) {
+  constexpr int BY = 8, BM = BY * BX;  // pixels per chunk
+  constexpr int BC = 32;
+  constexpr int FO = BO / 32;          // 16-row fragments per wave along o
+  constexpr int GP = BM + 8;           // sGt row (elements): 16 more bytes rotate the banks by 4 per row
+  constexpr int HR = BY + 2, HX = BX + 2;
+  constexpr int XP = BX + 8;           // sXt row (elements), 16-byte rows
+  constexpr int CP = HR * XP + 8;      // sXt channel plane (elements): rotates the banks between channels
+  __shared__ __align__(16) uint16_t sGt[BO * GP];
+  __shared__ __align__(16) uint16_t sXt[3 * BC * CP];
+  const int n_ob = a.cout_p / BO, n_cb = a.cin_p / BC;
+  int rest = blockIdx.x;
+  const int ob = rest % n_ob;
+  rest /= n_ob;
+  const int cb = rest % n_cb;
+  const int split = rest / n_cb;
+  const int o0 = ob * BO, c0 = cb * BC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // wave tile: BO/2 o x 16 c
+  const int l16 = lane & 15, kg = lane >> 4;
+  const int tiles_y = a.H / BY, tiles_x = a.W / BX;
+  const int n_chunks = a.n_tiles * tiles_y * tiles_x;
+  f32x4 acc[9][FO];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int f = 0; f < FO; ++f) acc[t][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* G = (const uint16_t*)a.dy;
+  for (int ch = split; ch < n_chunks; ch += a.splits) {
+    const int b = ch / (tiles_y * tiles_x);
+    const int sy = (ch / tiles_x) % tiles_y, sx = ch % tiles_x;
+    const int y0 = sy * BY, x0 = sx * BX;
+    // dY of the chunk, transposed: sGt[o][pixel]
+    for (int i = tid; i < BM * (BO / 8); i += 256) {
+      const int m = i / (BO / 8), og = (i % (BO / 8)) * 8;
+      const int y = y0 + m / BX, x = x0 + m % BX;
+      const uint4 v = *reinterpret_cast<const uint4*>(G + (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + o0 + og);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sGt[(og + j) * GP + m] = e[j];
+    }
+    // the input halo, transposed, one copy per dx: sXt[dx][c][row][x] = X(row - 1, x + dx - 1)
+    for (int i = tid; i < HR * HX * (BC / 8); i += 256) {
+      const int p = i / (BC / 8), cv = (i % (BC / 8)) * 8;
+      const int hr = p / HX, hx = p % HX;
+      const int y = y0 + hr - 1, x = x0 + hx - 1;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (y >= 0 && y < a.H && x >= 0 && x < a.W) v = wg_load_x_bf16<LOADER>(a, b, y, x, c0 + cv);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int xq = hx - d;
+        if (xq < 0 || xq >= BX) continue;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sXt[(d * BC + cv + j) * CP + hr * XP + xq] = e[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BM / 32; ++ks) {
+      const int pix0 = ks * 32 + kg * 8;  // this lane's 8 pixels (MFMA K index)
+      const int row = pix0 / BX, xo = pix0 % BX;
+      uint4 ga[FO];
+#pragma unroll
+      for (int f = 0; f < FO; ++f)
+        ga[f] = *reinterpret_cast<const uint4*>(&sGt[(wm * (BO / 2) + f * 16 + l16) * GP + pix0]);
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;
+        const uint4 xb = *reinterpret_cast<const uint4*>(&sXt[(dx * BC + wn * 16 + l16) * CP + (row + dy) * XP + xo]);
+#pragma unroll
+        for (int f = 0; f < FO; ++f)
+          acc[tap][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ga[f]),
+                                                                __builtin_bit_cast(bf16x8, xb), acc[tap][f], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  float* part = a.part + (int64_t)split * a.cout_p * 9 * a.cin_p;
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int f = 0; f < FO; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = o0 + wm * (BO / 2) + f * 16 + kg * 4 + r;
+        const int c = c0 + wn * 16 + l16;
+        part[((int64_t)o * 9 + tap) * a.cin_p + c] = acc[tap][f][r];
+      }
+}
+
 // canonical[w_off + (o cin + c) 9 + tap] = sum_s part[s][o][tap][cp(c)]
 __global__ void k_wgrad_reduce(const float* part, int splits, int cout, int cin, int cu, int cu_p, int cout_p,
                                int cin_p, float* dst) {
@@ -644,7 +783,23 @@ hipError_t launch_wgrad(int precision_x, int precision_g, int loader, const Wgra
     else OMNISEG_WG_LD(TX, TG, 8);        \
   } while (0)
   const bool xb = precision_x == OMNISEG_BF16, gb = precision_g == OMNISEG_BF16;
-  if (xb && gb) OMNISEG_WG_BX(uint16_t, uint16_t);
+#define OMNISEG_WGB(BXV, LD)                                                                                     \
+  do {                                                                                                         \
+    if (bo == 64) hipLaunchKernelGGL((k_wgrad3x3_bf16<BXV, 64, LD>), dim3(blocks), dim3(256), 0, st, a);        \
+    else hipLaunchKernelGGL((k_wgrad3x3_bf16<BXV, 32, LD>), dim3(blocks), dim3(256), 0, st, a);                 \
+  } while (0)
+#define OMNISEG_WGB_LD(BXV)                                 \
+  do {                                                      \
+    if (loader == LOAD_PLAIN) OMNISEG_WGB(BXV, LOAD_PLAIN); \
+    else if (loader == LOAD_POOL) OMNISEG_WGB(BXV, LOAD_POOL); \
+    else OMNISEG_WGB(BXV, LOAD_UPCAT);                      \
+  } while (0)
+  if (xb && gb) {
+    if (bx16) OMNISEG_WGB_LD(16);
+    else OMNISEG_WGB_LD(8);
+  }
+#undef OMNISEG_WGB_LD
+#undef OMNISEG_WGB
   else if (!xb && gb) OMNISEG_WG_BX(float, uint16_t);
   else if (xb && !gb) OMNISEG_WG_BX(uint16_t, float);
   else OMNISEG_WG_BX(float, float);

@@ -133,6 +133,8 @@ def _declare(lib):
         "omniseg_conv3x3": (i32, [i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, i64,
                                   vp]),
         "omniseg_read_profile": (i32, [vp, P(LaunchRecord), i32, P(i32)]),
+        "omniseg_conv3x3_wgrad_workspace_bytes": (i32, [i32, i32, i32, i32, i32, i32, P(i64)]),
+        "omniseg_conv3x3_wgrad": (i32, [i32, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp]),
         "omniseg_conv3x3_fp8_workspace_bytes": (i32, [i32, i32, i32, P(i64)]),
         "omniseg_conv3x3_fp8": (i32, [i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp,
                                       i64, vp]),
@@ -585,6 +587,21 @@ def conv3x3(precision, mode, x0, weights, bias=None, x1=None, aux=None, cin=None
                                  _ptr(x0), _ptr(x1), _ptr(aux), _ptr(y), _ptr(yp), config, _ptr(ws), ws.numel(),
                                  _stream(stream)))
     return (y, yp) if pool else y
+
+
+def conv3x3_wgrad(precision, mode, x0, dy, cin, cout, x1=None, cu=None, stream=None):
+    """Weight gradient (canonical FP32 [cout][cin][3][3]) of the stand-alone
+    conv `mode` (CONV_RELU, CONV_POOL_RELU or CONV_UPCAT_RELU) with input x0
+    (x1) and output gradient dy [n, H, W, pad32(cout)]."""
+    n, height, width = dy.shape[0], dy.shape[1], dy.shape[2]
+    cu = cin if cu is None else cu
+    nb = ctypes.c_int64()
+    _check(lib().omniseg_conv3x3_wgrad_workspace_bytes(n, height, width, cin, cu, cout, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dy.device)
+    dw = torch.empty((cout, cin, 3, 3), dtype=torch.float32, device=dy.device)
+    _check(lib().omniseg_conv3x3_wgrad(precision, mode, n, height, width, cin, cu, cout, _ptr(x0), _ptr(x1), _ptr(dy),
+                                       _ptr(dw), _ptr(ws), ws.numel(), _stream(stream)))
+    return dw
 
 
 def conv3x3_fp8(mode, x0, weights, bias, in_scale, out_scale, x1=None, cu=None, height=None, width=None,
