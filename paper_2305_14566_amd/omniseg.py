@@ -11,7 +11,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libomniseg.so")
+# OMNISEG_LIBRARY selects another build of the same library (the host
+# sanitizer build of build.build_sanitized, for the ABI tests).
+LIB_PATH = os.environ.get("OMNISEG_LIBRARY") or os.path.join(_HERE, "libomniseg.so")
 
 FP32, BF16, FP8 = 0, 1, 2
 ACT_ENC_A, ACT_ENC_E, ACT_DEC_A, ACT_DEC_D = range(4)
