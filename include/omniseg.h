@@ -118,10 +118,10 @@ typedef struct omniseg_hip_stream_opaque* omniseg_stream; /* a hipStream_t */
  *                  median_kernel x median_kernel median with replicated
  *                  borders; Otsu's threshold t of the blurred map (the first
  *                  t maximising n0 n1 (mu0 - mu1)^2 over the splits {<= t},
- *                  {> t}, in FP64; a one-valued map has no tissue); tissue =
- *                  blurred gray <= t; then 8-connected tissue components of
- *                  fewer than min_tissue_area pixels are removed.  The
- *                  coarse map must have fewer than 2^31 pixels.
+ *                  {> t}, compared exactly in integers; a one-valued map has
+ *                  no tissue); tissue = blurred gray <= t; then 8-connected
+ *                  tissue components of fewer than min_tissue_area pixels are
+ *                  removed.  The coarse map must have fewer than 2^28 pixels.
  *   median_kernel  odd, in [1, 255] (1 = no blur); OTSU only.
  *   min_tissue_area  >= 0, in coarse pixels (0 or 1 keep every component);
  *                  OTSU only.

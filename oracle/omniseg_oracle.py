@@ -249,14 +249,15 @@ def otsu_threshold(g):
     """Otsu's threshold of an integer image in [0, 255].
 
     For each split {<= t} / {> t} with both classes non-empty the score is
-    the between-class variance up to the constant 1/N^2, n0 n1 (mu0 - mu1)^2,
-    evaluated in FP64 as ((n0 n1) d) d with d = s0/n0 - s1/n1 (one rounding
-    per operation); the first t of the largest score wins.  -1 when the image
-    has a single value.
+    the between-class variance up to the constant 1/N^2, n0 n1 (mu0 - mu1)^2
+    = (N s0 - n0 S)^2 / (n0 n1) with s0 the sum of the class {<= t} and S
+    the sum of all pixels; scores are compared exactly (integers,
+    cross-multiplied) and the first t of the largest score wins.  -1 when the
+    image has a single value.
     """
     h = np.bincount(np.asarray(g).ravel(), minlength=256).astype(np.int64)
     N, S = int(h.sum()), int((h * np.arange(256)).sum())
-    best, best_t = -1.0, -1
+    best_t, best_a2, best_d = -1, 0, 1
     n0 = s0 = 0
     for t in range(256):
         n0 += int(h[t])
@@ -264,12 +265,10 @@ def otsu_threshold(g):
         n1 = N - n0
         if n0 == 0 or n1 == 0:
             continue
-        mu0 = float(s0) / float(n0)
-        mu1 = float(S - s0) / float(n1)
-        d = mu0 - mu1
-        score = (float(n0) * float(n1) * d) * d
-        if score > best:
-            best, best_t = score, t
+        a2 = (N * s0 - n0 * S) ** 2
+        d = n0 * n1
+        if best_t < 0 or a2 * best_d > best_a2 * d:
+            best_t, best_a2, best_d = t, a2, d
     return best_t
 
 

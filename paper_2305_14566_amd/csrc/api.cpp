@@ -70,7 +70,7 @@ struct Layout {
   int64_t off_tgray[OMNISEG_MAX_SLIDES], off_tstats[OMNISEG_MAX_SLIDES];
   int64_t off_ttmp = -1, off_thist = -1, off_tlabel = -1, off_tarea = -1;
   int64_t off_index = 0, off_list = 0, off_count = 0, off_pre = 0;
-  int64_t off_sgroups = 0, off_splanes = 0, off_units = 0;
+  int64_t off_sgroups = 0, off_splanes = 0, off_units = 0, off_bfirst = 0;
   int n_planes = 0;
   int64_t off_E[8], off_A = 0, off_g = 0, off_theta = 0, off_logits = 0;
   int64_t sz_E[8], sz_A = 0, sz_logits = 0;
@@ -197,8 +197,8 @@ int32_t validate_call(const omniseg_plan* plan, const omniseg_slide* slides, int
     for (int si = 0; si < c.n_scales; ++si) kc = std::max(kc, c.scale_log2[si]);
     for (int i = 0; i < n_slides; ++i) {
       const int64_t hc = ceil_div(slides[i].height, 1 << kc), wc = ceil_div(slides[i].width, 1 << kc);
-      if (hc * wc >= (1LL << 31))
-        return fail(OMNISEG_ERR_UNSUPPORTED, "slide %d: coarse map of %lld pixels above 2^31 - 1", i,
+      if (hc * wc >= (1LL << 28))
+        return fail(OMNISEG_ERR_UNSUPPORTED, "slide %d: coarse map of %lld pixels above 2^28 - 1", i,
                     (long long)(hc * wc));
     }
   }
@@ -336,6 +336,7 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
     sg.Hk = g.Hk;
     sg.Wk = g.Wk;
     sg.unit_base = lay.n_units;
+    sg.nxc = ceil_div(g.Wk, kStitchCols);
     sg.plane_first = lay.n_planes;
     sg.n_planes = lay.slots.n_slots[si];
     sg.fg = nullptr;
@@ -346,8 +347,8 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
     lay.n_units += g.ny;
     lay.n_planes += sg.n_planes;
     const int64_t last_rows = g.Hk - (int64_t)(g.ny - 1) * ss;
-    lay.n_items += (int64_t)sg.n_planes * ((int64_t)(g.ny - 1) * ceil_div(ss, kStitchRows) +
-                                           (last_rows + kStitchRows - 1) / kStitchRows);
+    lay.n_items += (int64_t)sg.n_planes * sg.nxc *
+                   ((int64_t)(g.ny - 1) * ceil_div(ss, kStitchRows) + (last_rows + kStitchRows - 1) / kStitchRows);
     for (int j = 0; j < g.ny; ++j) {
       const int y0 = j * ss;
       const int jlo = y0 < T ? 0 : (y0 - T) / ss + 1;
@@ -357,6 +358,7 @@ void compute_layout(const omniseg_plan* plan, const omniseg_slide* slides, int32
   lay.off_sgroups = take((int64_t)lay.groups.n * sizeof(StreamGroup));
   lay.off_splanes = take((int64_t)std::max(1, lay.n_planes) * sizeof(StreamPlane));
   lay.off_units = take((int64_t)(lay.n_units + 1) * sizeof(StreamUnit));
+  lay.off_bfirst = take((int64_t)(lay.n_batches + 1) * 4);
   const int64_t B = lay.batch;
   const int64_t ring_min = (need + B - 1 + B - 1) / B * B;
   if (c.logit_ring_tiles == 0 || ring_min >= tiles) {
@@ -1047,6 +1049,8 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
   sargs.groups = reinterpret_cast<const StreamGroup*>(ws + lay.off_sgroups);
   sargs.planes = reinterpret_cast<const StreamPlane*>(ws + lay.off_splanes);
   sargs.units = reinterpret_cast<StreamUnit*>(ws + lay.off_units);
+  sargs.batch_first = reinterpret_cast<int32_t*>(ws + lay.off_bfirst);
+  sargs.n_batches = lay.n_batches;
   sargs.n_groups = lay.groups.n;
   sargs.n_units = lay.n_units;
   sargs.pre = reinterpret_cast<const int32_t*>(ws + lay.off_pre);

@@ -292,15 +292,17 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t st);
 // list positions before pre[grid index of (j + 1, 0)], so the unit is stitched
 // right after the batch that holds the last of them (batch 0 when there is
 // none).  Units are enumerated group by group, rows in order, so their
-// batches do not decrease.  Each unit is cut into items: one plane (pair)
-// and kStitchRows output rows each.
-constexpr int kStitchRows = 8;
+// batches do not decrease.  Each unit is cut into items: one plane (pair),
+// kStitchRows output rows and kStitchCols columns each.
+constexpr int kStitchRows = 16;
+constexpr int kStitchCols = 1024;
 
 struct StreamGroup {
   int64_t grid_base;   // canonical index of the group's first grid tile
   int64_t item_base;   // first item of the group
   int ny, nx, s, Hk, Wk;
   int unit_base;       // first unit of the group
+  int nxc;             // column chunks per row: ceil(Wk / kStitchCols)
   int plane_first, n_planes;
   const uint8_t* fg;   // tissue map for mask_and_fg (or null)
   int fg_shift, Hc, Wc;
@@ -323,6 +325,8 @@ struct StreamStitchArgs {
   const StreamGroup* groups;
   const StreamPlane* planes;
   StreamUnit* units;   // n_units + 1 entries
+  int32_t* batch_first;  // n_batches + 1 entries: the first unit of each batch (n_units past the last)
+  int n_batches;
   int n_groups, n_units;
   const int32_t* pre;  // kept tiles before each grid tile (grid tiles + 1 entries)
   const int32_t* index;  // list index per grid tile, or -1
@@ -410,6 +414,9 @@ struct WgradArgs {
 int wgrad_bo(int cout_p);
 hipError_t launch_wgrad(int precision_x, int precision_g, int loader, const WgradArgs& a, int cout, int cin,
                         int cu, float* dst, hipStream_t st);
+// Split count of the bias gradient over npix pixels (at most kBiasGradSplits).
+constexpr int kBiasGradSplits = 512;
+int bias_grad_splits(int64_t npix);
 hipError_t launch_bias_grad(int precision, const void* dy, int64_t npix, int c_p, int cout, float* part,
                             int splits, float* dst, hipStream_t st);
 hipError_t launch_bce(const float* lg, const float* y, const uint8_t* valid, int64_t n, double* part_sum,

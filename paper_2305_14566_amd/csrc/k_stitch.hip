@@ -142,40 +142,70 @@ __device__ __forceinline__ void stitch_span4(const StitchArgs& a, int x0, int y)
     *reinterpret_cast<float4*>(a.logit + (int64_t)y * a.logit_pitch + x0) = make_float4(out[0], out[1], out[2], out[3]);
 }
 
-// stitch_span4 when T <= 2 s, so at most 2 x 2 tiles cover a pixel: the four
-// index reads, then the four logit-vector reads, are issued together, and
-// the covering tiles are then taken in the same (jy, jx) order with the same
-// arithmetic.  A missing tile's read goes through a buffer resource with an
-// empty range, which returns zeros without touching memory.
+// Buffer resource of `bytes` bytes at p (raw buffer loads, 32-bit offsets).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const float* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-__device__ __forceinline__ void stitch_span4_2x2(const StitchArgs& a, int x0, int y) {
+// The covering tiles of four pixels x0 .. x0 + 3 in the rows of one tile-row
+// band (at most 2 x 2 tiles): their slots' buffer resources and in-tile
+// column.  A missing tile's resource has an empty range, so its reads
+// return zeros without touching memory.
+struct Cover2x2 {
+  int jy0, jx0;
+  bool have[2][2];
+  __amdgpu_buffer_rsrc_t r[2][2];
+  int ix[2];
+};
+
+__device__ __forceinline__ Cover2x2 cover_2x2(const StitchArgs& a, int x0, int y) {
   const int T = a.T, s = a.s;
-  const int jy0 = (y < T) ? 0 : (y - T) / s + 1, jy1 = min(a.ny - 1, y / s);
-  const int jx0 = (x0 < T) ? 0 : (x0 - T) / s + 1, jx1 = min(a.nx - 1, x0 / s);
+  Cover2x2 c;
+  c.jy0 = (y < T) ? 0 : (y - T) / s + 1;
+  const int jy1 = min(a.ny - 1, y / s);
+  c.jx0 = (x0 < T) ? 0 : (x0 - T) / s + 1;
+  const int jx1 = min(a.nx - 1, x0 / s);
   int t[2][2];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
-      const bool in = jy0 + u <= jy1 && jx0 + v <= jx1;
-      const int ti = a.index[min(jy0 + u, jy1) * a.nx + min(jx0 + v, jx1)];
+      const bool in = c.jy0 + u <= jy1 && c.jx0 + v <= jx1;
+      const int ti = a.index[min(c.jy0 + u, jy1) * a.nx + min(c.jx0 + v, jx1)];
       t[u][v] = in ? ti : -1;
     }
-  float4 L[2][2];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
       const int tt = t[u][v];
-      const int iy = y - (jy0 + u) * s, ix = x0 - (jx0 + v) * s;
-      const __amdgpu_buffer_rsrc_t r =
-          tile_rsrc(a.logits + tile_slot(a, max(tt, 0)) * a.tile_stride, tt >= 0 ? (uint32_t)(a.tile_stride * 4) : 0u);
-      const uint32_t off = (uint32_t)(a.slot_off + (int64_t)iy * T + ix) * 4u;
-      L[u][v] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, tt >= 0 ? off : 0u, 0, 0));
+      c.have[u][v] = tt >= 0;
+      c.r[u][v] = tile_rsrc(a.logits + tile_slot(a, max(tt, 0)) * a.tile_stride,
+                            tt >= 0 ? (uint32_t)(a.tile_stride * 4) : 0u);
     }
+#pragma unroll
+  for (int v = 0; v < 2; ++v) c.ix[v] = x0 - (c.jx0 + v) * s;
+  return c;
+}
+
+__device__ __forceinline__ void load_2x2(const StitchArgs& a, const Cover2x2& c, int y, float4 (&L)[2][2]) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int iy = y - (c.jy0 + u) * a.s;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const uint32_t off = (uint32_t)(a.slot_off + (int64_t)iy * a.T + c.ix[v]) * 4u;
+      L[u][v] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(c.r[u][v], c.have[u][v] ? off : 0u,
+                                                                                 0, 0));
+    }
+  }
+}
+
+// Mask (and logit or vote count) of pixels x0 .. x0 + 3 of row y from the
+// logits of their covering tiles, in (jy, jx) order.
+__device__ __forceinline__ void finish_2x2(const StitchArgs& a, const Cover2x2& c, int x0, int y,
+                                           const float4 (&L)[2][2]) {
+  const int T = a.T;
   float out[4];
   bool m[4];
   if (a.vote > 0) {
@@ -184,7 +214,7 @@ __device__ __forceinline__ void stitch_span4_2x2(const StitchArgs& a, int x0, in
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
-        if (t[u][v] < 0) continue;
+        if (!c.have[u][v]) continue;
         const float4 l = L[u][v];
         votes[0] += l.x > 0.f ? 1 : 0;
         votes[1] += l.y > 0.f ? 1 : 0;
@@ -202,12 +232,12 @@ __device__ __forceinline__ void stitch_span4_2x2(const StitchArgs& a, int x0, in
     int den[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int iy = y - (jy0 + u) * s;
+      const int iy = y - (c.jy0 + u) * a.s;
       const int ry = min(iy + 1, T - iy);
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
-        if (t[u][v] < 0) continue;
-        const int ix = x0 - (jx0 + v) * s;
+        if (!c.have[u][v]) continue;
+        const int ix = c.ix[v];
         const float l[4] = {L[u][v].x, L[u][v].y, L[u][v].z, L[u][v].w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -236,6 +266,37 @@ __device__ __forceinline__ void stitch_span4_2x2(const StitchArgs& a, int x0, in
       (m[0] ? 1u : 0u) | (m[1] ? 1u << 8 : 0u) | (m[2] ? 1u << 16 : 0u) | (m[3] ? 1u << 24 : 0u);
   if (a.logit)
     *reinterpret_cast<float4*>(a.logit + (int64_t)y * a.logit_pitch + x0) = make_float4(out[0], out[1], out[2], out[3]);
+}
+
+// stitch_span4 when T <= 2 s, so at most 2 x 2 tiles cover a pixel: the four
+// index reads, then the four logit-vector reads, are issued together, and
+// the covering tiles are then taken in the same (jy, jx) order with the same
+// arithmetic.
+__device__ __forceinline__ void stitch_span4_2x2(const StitchArgs& a, int x0, int y) {
+  const Cover2x2 c = cover_2x2(a, x0, y);
+  float4 L[2][2];
+  load_2x2(a, c, y, L);
+  finish_2x2(a, c, x0, y, L);
+}
+
+// Rows y0 .. y1 - 1 at columns x0 .. x0 + 3, rows that share their covering
+// tiles (one tile-row band): the index reads are done once, and two rows'
+// logit reads are in flight together.  Per pixel as stitch_span4_2x2.
+__device__ __forceinline__ void stitch_rows4_2x2(const StitchArgs& a, int x0, int y0, int y1) {
+  const Cover2x2 c = cover_2x2(a, x0, y0);
+  int y = y0;
+  for (; y + 1 < y1; y += 2) {
+    float4 L0[2][2], L1[2][2];
+    load_2x2(a, c, y, L0);
+    load_2x2(a, c, y + 1, L1);
+    finish_2x2(a, c, x0, y, L0);
+    finish_2x2(a, c, x0, y + 1, L1);
+  }
+  if (y < y1) {
+    float4 L0[2][2];
+    load_2x2(a, c, y, L0);
+    finish_2x2(a, c, x0, y, L0);
+  }
 }
 
 // One thread per pixel; rows beyond the grid's y extent are taken in strides.
@@ -286,17 +347,6 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t st) {
 
 // ---- streamed stitch --------------------------------------------------------
 
-// First unit in [0, n) whose batch is >= b (the units' batches do not decrease).
-__device__ int first_unit_of_batch(const StreamUnit* u, int n, int b) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int m = (lo + hi) >> 1;
-    if (u[m].batch < b) lo = m + 1;
-    else hi = m;
-  }
-  return lo;
-}
-
 __global__ __launch_bounds__(256) void k_stream_units(StreamStitchArgs a) {
   const int u = blockIdx.x * 256 + threadIdx.x;
   if (u > a.n_units) return;
@@ -325,31 +375,40 @@ __global__ __launch_bounds__(256) void k_stream_units(StreamStitchArgs a) {
   out.y0 = j * G.s;
   out.y1 = j == G.ny - 1 ? G.Hk : (j + 1) * G.s;
   // every row of the group before this unit's is a full row of s rows
-  out.item_base = G.item_base + (int64_t)G.n_planes * j * ((G.s + kStitchRows - 1) / kStitchRows);
+  out.item_base = G.item_base + (int64_t)G.n_planes * G.nxc * j * ((G.s + kStitchRows - 1) / kStitchRows);
   a.units[u] = out;
+}
+
+// batch_first[b] = the first unit stitched after batch b or later: for each
+// unit u, the batches after its predecessor's up to its own (the sentinel
+// closes the table at n_units).
+__global__ __launch_bounds__(256) void k_batch_first(StreamStitchArgs a) {
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  if (u > a.n_units) return;
+  const int b0 = u == 0 ? 0 : a.units[u - 1].batch + 1;
+  const int b1 = min(a.units[u].batch, a.n_batches);
+  for (int b = b0; b <= b1; ++b) a.batch_first[b] = u;
 }
 
 hipError_t launch_stream_units(const StreamStitchArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_stream_units, dim3(ceil_div(a.n_units + 1, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_batch_first, dim3(ceil_div(a.n_units + 1, 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
-// Every unit of batch a.batch: a persistent grid takes the units' items
-// (one plane, kStitchRows rows) in turn; per pixel the arithmetic and its
-// order are those of the plane-wise stitch.
+static_assert(kStitchCols == 4 * 256, "one pass of four pixels per thread covers an item's columns");
+
+// Every unit of batch a.batch: a fixed grid takes the units' items
+// (one plane, kStitchRows rows, kStitchCols columns) in turn; per pixel the
+// arithmetic and its order are those of the plane-wise stitch.
 __global__ __launch_bounds__(256) void k_stitch_stream(StreamStitchArgs a) {
-  __shared__ int s_u[3];
-  if (threadIdx.x == 0) {
-    s_u[0] = first_unit_of_batch(a.units, a.n_units, a.batch);
-    s_u[1] = first_unit_of_batch(a.units, a.n_units, a.batch + 1);
-  }
-  __syncthreads();
-  const int u_lo = s_u[0], u_hi = s_u[1];
+  __shared__ int s_u;
+  const int u_lo = a.batch_first[a.batch], u_hi = a.batch_first[a.batch + 1];
   if (u_lo >= u_hi) return;
   const int64_t i_hi = a.units[u_hi].item_base;
   int cur = u_lo;
   for (int64_t it = a.units[u_lo].item_base + blockIdx.x; it < i_hi; it += gridDim.x) {
-    __syncthreads();  // every thread has read s_u[2] of the previous item
+    __syncthreads();  // every thread has read s_u of the previous item
     if (threadIdx.x == 0) {
       // the item's unit: the last one in [cur, u_hi) whose first item is <= it
       int lo = cur, hi = u_hi - 1;
@@ -358,15 +417,18 @@ __global__ __launch_bounds__(256) void k_stitch_stream(StreamStitchArgs a) {
         if (a.units[m].item_base <= it) lo = m;
         else hi = m - 1;
       }
-      s_u[2] = lo;
+      s_u = lo;
     }
     __syncthreads();
-    cur = s_u[2];
+    cur = s_u;
     const StreamUnit un = a.units[cur];
     const StreamGroup& G = a.groups[un.g];
     const int nblk = (un.y1 - un.y0 + kStitchRows - 1) / kStitchRows;
     const int local = (int)(it - un.item_base);
-    const StreamPlane& P = a.planes[G.plane_first + local / nblk];
+    const int per_plane = nblk * G.nxc;
+    const StreamPlane& P = a.planes[G.plane_first + local / per_plane];
+    const int rem = local % per_plane;
+    const int xa = (rem % G.nxc) * kStitchCols, xb = min(G.Wk, xa + kStitchCols);
     StitchArgs sa;
     sa.logits = a.logits;
     sa.tile_stride = a.tile_stride;
@@ -389,19 +451,33 @@ __global__ __launch_bounds__(256) void k_stitch_stream(StreamStitchArgs a) {
     sa.coverage = 0;
     sa.vote = G.vote;
     sa.ring = a.ring;
-    const int r0 = un.y0 + (local % nblk) * kStitchRows, r1 = min(un.y1, r0 + kStitchRows);
+    const int r0 = un.y0 + (rem / G.nxc) * kStitchRows, r1 = min(un.y1, r0 + kStitchRows);
+    // rows of one tile-row band share their covering tiles
+    const bool band = P.mode == 2 && (r0 < a.T ? 0 : (r0 - a.T) / sa.s + 1) ==
+                                         (r1 - 1 < a.T ? 0 : (r1 - 1 - a.T) / sa.s + 1) &&
+                      min(sa.ny - 1, r0 / sa.s) == min(sa.ny - 1, (r1 - 1) / sa.s);
+    if (band) {
+      const int x0 = xa + threadIdx.x * 4;
+      if (x0 + 3 < xb) {
+        stitch_rows4_2x2(sa, x0, r0, r1);
+      } else {
+        for (int y = r0; y < r1; ++y)
+          for (int x = x0; x < xb; ++x) stitch_pixel(sa, x, y);
+      }
+      continue;
+    }
     for (int y = r0; y < r1; ++y) {
       if (P.mode == 0) {
-        for (int x = threadIdx.x; x < sa.Wk; x += 256) stitch_pixel(sa, x, y);
+        for (int x = xa + threadIdx.x; x < xb; x += 256) stitch_pixel(sa, x, y);
         continue;
       }
-      for (int x0 = threadIdx.x * 4; x0 < sa.Wk; x0 += 1024) {
-        if (x0 + 3 < sa.Wk) {
-          if (P.mode == 2) stitch_span4_2x2(sa, x0, y);
-          else stitch_span4(sa, x0, y);
-        } else {
-          for (int x = x0; x < sa.Wk; ++x) stitch_pixel(sa, x, y);
-        }
+      // four pixels per thread: kStitchCols = 4 x 256 columns in one pass
+      const int x0 = xa + threadIdx.x * 4;
+      if (x0 + 3 < xb) {
+        if (P.mode == 2) stitch_span4_2x2(sa, x0, y);
+        else stitch_span4(sa, x0, y);
+      } else {
+        for (int x = x0; x < xb; ++x) stitch_pixel(sa, x, y);
       }
     }
   }

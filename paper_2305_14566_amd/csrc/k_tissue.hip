@@ -117,11 +117,34 @@ __global__ __launch_bounds__(256) void k_hist256(const uint8_t* __restrict__ g, 
 }
 
 // One block of 256 threads: thread t scores the split {<= t} / {> t}.
-// stats[0] receives the threshold, or -1 when every pixel has one value.
+// Otsu's score of the split {<= t} / {> t} is n0 n1 (mu0 - mu1)^2 =
+// (N s0 - n0 S)^2 / (n0 n1).  With fewer than 2^28 pixels |N s0 - n0 S| <
+// 2^64 and n0 n1 < 2^56, so two scores compare exactly as 192-bit products
+// A_a^2 D_b against A_b^2 D_a; no floating point is involved.
+struct U192 {
+  uint64_t w0, w1, w2;  // least significant first
+};
+
+__device__ __forceinline__ U192 mul_u128_u64(unsigned __int128 a, uint64_t b) {
+  const unsigned __int128 p0 = (unsigned __int128)(uint64_t)a * b;
+  const unsigned __int128 p1 = (unsigned __int128)(uint64_t)(a >> 64) * b + (p0 >> 64);
+  return U192{(uint64_t)p0, (uint64_t)p1, (uint64_t)(p1 >> 64)};
+}
+
+// score(a2a, da) > score(a2b, db), scores a2 / d with d > 0
+__device__ __forceinline__ bool score_greater(unsigned __int128 a2a, uint64_t da, unsigned __int128 a2b, uint64_t db) {
+  const U192 x = mul_u128_u64(a2a, db), y = mul_u128_u64(a2b, da);
+  if (x.w2 != y.w2) return x.w2 > y.w2;
+  if (x.w1 != y.w1) return x.w1 > y.w1;
+  return x.w0 > y.w0;
+}
+
+// stats[0] receives the threshold (the first t of the largest score), or -1
+// when every pixel has one value.
 __global__ __launch_bounds__(256) void k_otsu(const uint32_t* __restrict__ hist, int32_t* stats) {
-#pragma clang fp contract(off)
   __shared__ int64_t cn[256], cs[256];
-  __shared__ double best_s[256];
+  __shared__ unsigned __int128 best_a2[256];
+  __shared__ uint64_t best_d[256];  // 0: no split at this t
   __shared__ int best_t[256];
   const int t = threadIdx.x;
   cn[t] = hist[t];
@@ -136,32 +159,41 @@ __global__ __launch_bounds__(256) void k_otsu(const uint32_t* __restrict__ hist,
     __syncthreads();
   }
   const int64_t N = cn[255], S = cs[255], n0 = cn[t], s0 = cs[t], n1 = N - n0;
-  double score = -1.0;
+  unsigned __int128 a2 = 0;
+  uint64_t dd = 0;
   if (n0 > 0 && n1 > 0) {
-    // operands are exact in FP64 (counts < 2^31, sums < 2^39); then one
-    // rounding per operation, in this order
-    const double mu0 = (double)s0 / (double)n0;
-    const double mu1 = (double)(S - s0) / (double)n1;
-    const double diff = mu0 - mu1;
-    const double w = (double)n0 * (double)n1;
-    score = (w * diff) * diff;
+    const __int128 A = (__int128)N * s0 - (__int128)n0 * S;
+    const unsigned __int128 absA = (unsigned __int128)(A < 0 ? -A : A);
+    a2 = absA * absA;
+    dd = (uint64_t)n0 * (uint64_t)n1;
   }
-  best_s[t] = score;
+  best_a2[t] = a2;
+  best_d[t] = dd;
   best_t[t] = t;
   __syncthreads();
-  // argmax, first index on ties
+  // argmax, first index on ties; t without a split loses to any split
   for (int d = 128; d > 0; d >>= 1) {
     if (t < d) {
-      const double o = best_s[t + d];
-      const int ot = best_t[t + d];
-      if (o > best_s[t] || (o == best_s[t] && ot < best_t[t])) {
-        best_s[t] = o;
-        best_t[t] = ot;
+      const uint64_t od = best_d[t + d], cd = best_d[t];
+      bool take = false;
+      if (od != 0) {
+        if (cd == 0) {
+          take = true;
+        } else {
+          const bool gt = score_greater(best_a2[t + d], od, best_a2[t], cd);
+          const bool lt = score_greater(best_a2[t], cd, best_a2[t + d], od);
+          take = gt || (!lt && best_t[t + d] < best_t[t]);
+        }
+      }
+      if (take) {
+        best_a2[t] = best_a2[t + d];
+        best_d[t] = od;
+        best_t[t] = best_t[t + d];
       }
     }
     __syncthreads();
   }
-  if (t == 0) stats[0] = best_s[0] < 0.0 ? -1 : best_t[0];
+  if (t == 0) stats[0] = best_d[0] == 0 ? -1 : best_t[0];
 }
 
 // ---- 4-5. tissue pixels and connected components ------------------------------
