@@ -514,14 +514,12 @@ int32_t read_kept(const Layout& lay, int32_t n_slides, const char* ws, hipStream
 
 // Stitch form of a plane (as launch_stitch chooses it): four pixels per
 // thread needs shared covering tiles (s, T multiples of 4) and aligned
-// vector accesses; the 2 x 2 form also needs T <= 2 s and 32-bit byte
-// offsets inside a logit slot.
-int stitch_mode(int T, int s, int64_t tile_stride, int64_t slot_off, const float* logits, const uint8_t* mask,
-                int64_t mask_pitch, const float* logit, int64_t logit_pitch) {
+// vector reads of the tile logits (output rows may have any alignment); the
+// 2 x 2 form also needs T <= 2 s and 32-bit byte offsets inside a logit slot.
+int stitch_mode(int T, int s, int64_t tile_stride, int64_t slot_off, const float* logits, const float* logit) {
   const bool span4 = s % 4 == 0 && T % 4 == 0 && tile_stride % 4 == 0 && slot_off % 4 == 0 &&
-                     reinterpret_cast<uintptr_t>(logits) % 16 == 0 && mask_pitch % 4 == 0 &&
-                     reinterpret_cast<uintptr_t>(mask) % 4 == 0 &&
-                     (!logit || (logit_pitch % 4 == 0 && reinterpret_cast<uintptr_t>(logit) % 16 == 0));
+                     reinterpret_cast<uintptr_t>(logits) % 16 == 0 &&
+                     (!logit || reinterpret_cast<uintptr_t>(logit) % 4 == 0);
   if (!span4) return 0;
   return (T <= 2 * s && tile_stride * 4 <= INT32_MAX) ? 2 : 1;
 }
@@ -1040,8 +1038,7 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
       pl.logit = emit ? o.logit : nullptr;
       pl.logit_pitch = emit ? o.logit_pitch : 0;
       pl.slot_off = (int64_t)lay.pair_slot[p] * T * T;
-      pl.mode = stitch_mode(T, sg.s, tile_stride, pl.slot_off, logits, pl.mask, pl.mask_pitch, pl.logit,
-                            pl.logit_pitch);
+      pl.mode = stitch_mode(T, sg.s, tile_stride, pl.slot_off, logits, pl.logit);
       pl.pad_ = 0;
     }
   }

@@ -68,6 +68,36 @@ __device__ __forceinline__ void stitch_pixel(const StitchArgs& a, int x, int y) 
   if (a.logit) a.logit[(int64_t)y * a.logit_pitch + x] = den > 0 ? n / (float)den : 0.f;
 }
 
+// Four consecutive outputs of row y at x0 (x0 a multiple of 4), gated by the
+// tissue mask.  Output rows need no alignment: with an odd pitch, say, every
+// other row starts off a 4-byte boundary, and such a row is written byte by
+// byte (a float logit plane: element by element off a 16-byte boundary).
+// The test is per row, so it is uniform across a wave.
+__device__ __forceinline__ void store4(const StitchArgs& a, int x0, int y, bool (&m)[4], const float (&out)[4]) {
+  if (a.fg) {
+    const uint8_t* fr = a.fg + (int64_t)(y >> a.fg_shift) * a.Wc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = m[q] && fr[(x0 + q) >> a.fg_shift];
+  }
+  uint8_t* mp = a.mask + (int64_t)y * a.mask_pitch + x0;
+  if ((reinterpret_cast<uintptr_t>(mp) & 3) == 0) {
+    *reinterpret_cast<uint32_t*>(mp) =
+        (m[0] ? 1u : 0u) | (m[1] ? 1u << 8 : 0u) | (m[2] ? 1u << 16 : 0u) | (m[3] ? 1u << 24 : 0u);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) mp[q] = m[q] ? 1 : 0;
+  }
+  if (a.logit) {
+    float* lp = a.logit + (int64_t)y * a.logit_pitch + x0;
+    if ((reinterpret_cast<uintptr_t>(lp) & 15) == 0) {
+      *reinterpret_cast<float4*>(lp) = make_float4(out[0], out[1], out[2], out[3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) lp[q] = out[q];
+    }
+  }
+}
+
 // Four consecutive pixels x0 .. x0 + 3 (x0 a multiple of 4, all inside the
 // row) when the stride and the tile size are multiples of 4: the four share
 // their covering tiles, and each tile's four logits are one aligned 16-byte
@@ -131,15 +161,7 @@ __device__ __forceinline__ void stitch_span4(const StitchArgs& a, int x0, int y)
       out[q] = den[q] > 0 ? n / (float)den[q] : 0.f;
     }
   }
-  if (a.fg) {
-    const uint8_t* fr = a.fg + (int64_t)(y >> a.fg_shift) * a.Wc;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) m[q] = m[q] && fr[(x0 + q) >> a.fg_shift];
-  }
-  *reinterpret_cast<uint32_t*>(a.mask + (int64_t)y * a.mask_pitch + x0) =
-      (m[0] ? 1u : 0u) | (m[1] ? 1u << 8 : 0u) | (m[2] ? 1u << 16 : 0u) | (m[3] ? 1u << 24 : 0u);
-  if (a.logit)
-    *reinterpret_cast<float4*>(a.logit + (int64_t)y * a.logit_pitch + x0) = make_float4(out[0], out[1], out[2], out[3]);
+  store4(a, x0, y, m, out);
 }
 
 // Buffer resource of `bytes` bytes at p (raw buffer loads, 32-bit offsets).
@@ -257,15 +279,7 @@ __device__ __forceinline__ void finish_2x2(const StitchArgs& a, const Cover2x2& 
       out[q] = den[q] > 0 ? n / (float)den[q] : 0.f;
     }
   }
-  if (a.fg) {
-    const uint8_t* fr = a.fg + (int64_t)(y >> a.fg_shift) * a.Wc;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) m[q] = m[q] && fr[(x0 + q) >> a.fg_shift];
-  }
-  *reinterpret_cast<uint32_t*>(a.mask + (int64_t)y * a.mask_pitch + x0) =
-      (m[0] ? 1u : 0u) | (m[1] ? 1u << 8 : 0u) | (m[2] ? 1u << 16 : 0u) | (m[3] ? 1u << 24 : 0u);
-  if (a.logit)
-    *reinterpret_cast<float4*>(a.logit + (int64_t)y * a.logit_pitch + x0) = make_float4(out[0], out[1], out[2], out[3]);
+  store4(a, x0, y, m, out);
 }
 
 // stitch_span4 when T <= 2 s, so at most 2 x 2 tiles cover a pixel: the four
@@ -325,11 +339,11 @@ __global__ __launch_bounds__(256) void k_stitch4(StitchArgs a) {
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t st) {
   if (a.Hk <= 0 || a.Wk <= 0) return hipSuccess;
   // the four-pixel form needs shared covering tiles (s, T multiples of 4) and
-  // aligned vector accesses (tile logits, mask rows, logit rows)
+  // aligned vector reads of the tile logits (output rows may have any
+  // alignment, see store4)
   const bool span4 = a.s % 4 == 0 && a.T % 4 == 0 && a.tile_stride % 4 == 0 && a.slot_off % 4 == 0 &&
-                     reinterpret_cast<uintptr_t>(a.logits) % 16 == 0 && a.mask_pitch % 4 == 0 &&
-                     reinterpret_cast<uintptr_t>(a.mask) % 4 == 0 &&
-                     (!a.logit || (a.logit_pitch % 4 == 0 && reinterpret_cast<uintptr_t>(a.logit) % 16 == 0));
+                     reinterpret_cast<uintptr_t>(a.logits) % 16 == 0 &&
+                     (!a.logit || reinterpret_cast<uintptr_t>(a.logit) % 4 == 0);
   if (span4) {
     dim3 grid(ceil_div(a.Wk, 1024), std::min(a.Hk, kMaxGridY));
     // a logit plane's float offsets inside a tile must fit the 32-bit byte
