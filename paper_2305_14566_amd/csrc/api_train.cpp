@@ -38,12 +38,11 @@ struct TrainLayout {
   int64_t total = 0;
 };
 
-constexpr int kBiasSplits = 64;
-constexpr int64_t kWgradPartBudget = 160LL << 20;  // bytes of split-K partials per conv
+constexpr int64_t kWgradPartBudget = 64LL << 20;  // bytes of split-K partials per conv
 
 int wgrad_splits(int cout_p, int cin_p, int n_chunks) {
   const int blocks = (cout_p / wgrad_bo(cout_p)) * (cin_p / 32);
-  int s = std::max(1, (2048 + blocks - 1) / blocks);
+  int s = std::max(1, (1024 + blocks - 1) / blocks);
   const int64_t per = (int64_t)cout_p * 9 * cin_p * 4;
   s = (int)std::min<int64_t>(s, std::max<int64_t>(1, kWgradPartBudget / per));
   return std::min(s, std::max(1, n_chunks));
@@ -156,7 +155,7 @@ void train_layout(const omniseg_plan* plan, TrainLayout& lay) {
   }
   lay.sz_wpart = wmax;
   lay.off_wpart = take(wmax);
-  lay.off_bpart = take((int64_t)kBiasSplits * 4096 * 4);
+  lay.off_bpart = take((int64_t)kBiasGradSplits * 4096 * 4);
   lay.total = off;
 }
 
@@ -527,7 +526,8 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
     return OMNISEG_OK;
   };
   auto bias = [&](const ConvDesc& d, const void* dy, int h, float* dst) -> int32_t {
-    HIP_TRY(launch_bias_grad(prec, dy, (int64_t)n * h * h, d.cout_p, d.cout, bpart, kBiasSplits, dst, sm));
+    HIP_TRY(launch_bias_grad(prec, dy, (int64_t)n * h * h, d.cout_p, d.cout, bpart,
+                             bias_grad_splits((int64_t)n * h * h), dst, sm));
     return OMNISEG_OK;
   };
 #define OMNISEG_CALL(x)      \

@@ -214,18 +214,39 @@ __global__ __launch_bounds__(256) void k_head_bwd(HeadBwdArgs a) {
       for (int o = 0; o < 8; ++o) s = fmaf(W1[o * 8 + i], dh1[o], s);
       dF[i] += s;
     }
-    // per-pixel parameter gradient, reduced over the block: W1, W2, W3, b1, b2, b3
+    // per-pixel parameter gradient, reduced over the block: W1, W2, W3, b1,
+    // b2, b3.  Each group of 64 parameters is reduce-scattered over the wave
+    // (at mask m = 32 .. 1 a lane keeps the half of its values its lane bit m
+    // selects and adds the partner's copy), so lane l ends with the wave sum
+    // of parameter 64 g + l: the same pairs added in the same order as a
+    // full xor-shuffle sum, with 63 shuffles per 64 parameters instead of 384.
     float* dst = a.dtheta_part + (((int64_t)b * a.max_slots + j) * per + pblk) * P;
-    for (int p = 0; p < P; ++p) {
-      float v;
-      if (p < 64) v = dh1[p / 8] * F[p % 8];
-      else if (p < 128) v = dh2[(p - 64) / 8] * h1[(p - 64) % 8];
-      else if (p < 128 + 8 * O) v = dz[(p - 128) / 8] * h2[(p - 128) % 8];
-      else if (p < 136 + 8 * O) v = dh1[p - 128 - 8 * O];
-      else if (p < 144 + 8 * O) v = dh2[p - 136 - 8 * O];
-      else v = dz[p - 144 - 8 * O];
-      v = wave_sum(v);
-      if (lane == 0) red[wave][p] = v;
+#pragma unroll
+    for (int g = 0; g < (P + 63) / 64; ++g) {
+      float vals[64];
+#pragma unroll
+      for (int q = 0; q < 64; ++q) {
+        const int p = 64 * g + q;
+        float v = 0.f;
+        if (p < 64) v = dh1[p / 8] * F[p % 8];
+        else if (p < 128) v = dh2[(p - 64) / 8] * h1[(p - 64) % 8];
+        else if (p < 128 + 8 * O) v = dz[(p - 128) / 8] * h2[(p - 128) % 8];
+        else if (p < 136 + 8 * O) v = dh1[p - 128 - 8 * O];
+        else if (p < 144 + 8 * O) v = dh2[p - 136 - 8 * O];
+        else if (p < P) v = dz[p - 144 - 8 * O];
+        vals[q] = v;
+      }
+#pragma unroll
+      for (int m = 32, n = 32; m >= 1; m >>= 1, n >>= 1) {
+        const bool up = (lane & m) != 0;
+#pragma unroll
+        for (int q = 0; q < n; ++q) {
+          const float lo = vals[q], hi = vals[q + n];
+          const float send = up ? lo : hi, keep = up ? hi : lo;
+          vals[q] = keep + __shfl_xor(send, m);
+        }
+      }
+      if (64 * g + lane < P) red[wave][64 * g + lane] = vals[0];
     }
     __syncthreads();
     for (int p = threadIdx.x; p < P; p += 256) dst[p] = (red[0][p] + red[1][p]) + (red[2][p] + red[3][p]);
@@ -814,23 +835,61 @@ hipError_t launch_wgrad(int precision_x, int precision_g, int loader, const Wgra
   return hipGetLastError();
 }
 
-// bias gradient: per-channel sum of dY over all pixels; split over pixel
-// ranges into part[split][c], then a fixed-order reduce into dst[c < cout]
+// bias gradient: per-channel sum of dY over all pixels.  Split `split` of
+// `splits` takes an equal pixel range; its threads read 16-byte vectors (V
+// channels of one pixel): VL vector lanes cover a channel block of the
+// pixel and the PL = 256 / VL pixel lanes of the workgroup take every PL-th
+// pixel, four pixels in flight per thread.  The pixel lanes' sums are then
+// added in LDS in lane order into part[split][c]; a second kernel adds the
+// splits in order (deterministic).
 template <typename T>
 __global__ __launch_bounds__(256) void k_colsum(const T* dy, int64_t npix, int c_p, int splits, float* part) {
-  __shared__ float red[4][64];
-  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int lane4 = threadIdx.x >> 6;
+  constexpr int V = 16 / (int)sizeof(T);
+  __shared__ float red[256 * V];
+  const int nvec = c_p / V;                 // vectors per pixel
+  const int VL = nvec < 32 ? nvec : 32;     // vector lanes of a workgroup
+  const int PL = 256 / VL;                  // pixel lanes
+  const int t = threadIdx.x, vl = t % VL, pl = t / VL;
   const int split = blockIdx.y;
+  const int c = (blockIdx.x * VL + vl) * V;
   const int64_t per = (npix + splits - 1) / splits;
   const int64_t p0 = split * per, p1 = min(npix, p0 + per);
-  float s = 0.f;
-  if (c < c_p)
-    for (int64_t p = p0 + lane4; p < p1; p += 4) s += ldf(dy + p * c_p + c);
-  red[lane4][threadIdx.x & 63] = s;
+  float acc[4][V];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[u][j] = 0.f;
+  const bool live = pl < PL && c < c_p;
+  if (live) {
+    int64_t p = p0 + pl;
+    for (; p + 3 * PL < p1; p += 4 * PL) {
+      uint4 q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = *reinterpret_cast<const uint4*>(dy + (p + u * PL) * c_p + c);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < V; ++j) acc[u][j] += ldf(reinterpret_cast<const T*>(&q[u]) + j);
+    }
+    for (; p < p1; p += PL) {
+      const uint4 q = *reinterpret_cast<const uint4*>(dy + p * c_p + c);
+#pragma unroll
+      for (int j = 0; j < V; ++j) acc[0][j] += ldf(reinterpret_cast<const T*>(&q) + j);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j) red[t * V + j] = (acc[0][j] + acc[1][j]) + (acc[2][j] + acc[3][j]);
   __syncthreads();
-  if (lane4 == 0 && c < c_p)
-    part[(int64_t)split * c_p + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  if (pl == 0 && c < c_p) {
+    float sv[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) sv[j] = red[vl * V + j];
+    for (int q = 1; q < PL; ++q)
+#pragma unroll
+      for (int j = 0; j < V; ++j) sv[j] += red[(q * VL + vl) * V + j];
+#pragma unroll
+    for (int j = 0; j < V; ++j) part[(int64_t)split * c_p + c + j] = sv[j];
+  }
 }
 
 __global__ void k_colsum_reduce(const float* part, int splits, int c_p, int cout, float* dst) {
@@ -841,9 +900,14 @@ __global__ void k_colsum_reduce(const float* part, int splits, int c_p, int cout
   dst[c] = s;
 }
 
+int bias_grad_splits(int64_t npix) { return (int)std::max<int64_t>(1, std::min<int64_t>(kBiasGradSplits, npix / 1024)); }
+
 hipError_t launch_bias_grad(int precision, const void* dy, int64_t npix, int c_p, int cout, float* part,
                             int splits, float* dst, hipStream_t st) {
-  dim3 grid((c_p + 63) / 64, splits);
+  if (c_p % 8 || (precision != OMNISEG_BF16 && c_p % 4)) return hipErrorInvalidValue;
+  const int V = precision == OMNISEG_BF16 ? 8 : 4;
+  const int VL = std::min(c_p / V, 32);
+  dim3 grid(ceil_div(c_p / V, VL), splits);
   if (precision == OMNISEG_BF16)
     hipLaunchKernelGGL(k_colsum<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)dy, npix, c_p, splits, part);
   else

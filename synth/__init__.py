@@ -9,6 +9,7 @@ from here, so the only thing they share is the input itself.
 from .slides import (
     ellipse_slide,
     strip_slide,
+    strip_crop_origin,
     tiny_slide,
     batch_slide_specs,
     soft_targets,
@@ -19,6 +20,7 @@ from .weights import weight_layout, he_normal_weights, head_param_count, trainin
 __all__ = [
     "ellipse_slide",
     "strip_slide",
+    "strip_crop_origin",
     "tiny_slide",
     "batch_slide_specs",
     "soft_targets",

@@ -208,6 +208,23 @@ def strip_slide(seed, H, W, fg_frac=0.30, with_gt=True, density=1.0):
     return _finish(canvas, rng), gt
 
 
+def strip_crop_origin(seed, H, W, size, align=128):
+    """Top-left corner of a size x size window of strip_slide(seed, H, W)
+    centred on the tissue band at the slide's middle column, rounded to a
+    multiple of `align` and kept inside the slide.  Repeats the generator's
+    first draws (background level, band amplitude, period, phase)."""
+    rng = np.random.default_rng(seed)
+    rng.integers(235, 246)
+    amp = rng.uniform(0.05, 0.15) * H
+    period = rng.uniform(0.5, 1.5) * W
+    phase = rng.uniform(0, 2 * np.pi)
+    xc = W / 2.0
+    yc = H / 2.0 + amp * np.sin(2 * np.pi * xc / period + phase)
+    y0 = int(round((yc - size / 2.0) / align)) * align
+    x0 = int(round((xc - size / 2.0) / align)) * align
+    return min(max(0, y0), H - size), min(max(0, x0), W - size)
+
+
 def batch_slide_specs(seed=99, n=16, h_range=(2000, 8000), w_range=(4000, 40000),
                       fg_range=(0.10, 0.60)):
     """Sizes and foreground fractions of an uneven multi-slide batch.
