@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the slide-wise segmentation path on one MI355X.
 
-Workload: one seeded synthetic 8192 x 8192 RGB slide at 40x (needle-biopsy
-strip, ~30% tissue), 4 scales (40/20/10/5x), 6 classes (24 class-scale
-pairs), 256 x 256 tiles at stride 128 with foreground-only tile lists, a
-base-64 5-level residual U-Net with a controller-generated 8-8-8-2 dynamic
-head, ramp-weighted stitch into 24 whole-slide masks.
+Headline workload (the batching configuration): 16 seeded synthetic slides
+of uneven size (heights 2000-8000 px, widths 4000-40000 px, 10-60% tissue),
+4 scales (40/20/10/5x) x 6 classes (24 class-scale pairs), 256 x 256 tiles
+at stride 128 with foreground-only tile lists, a base-64 5-level residual
+U-Net with a controller-generated 8-8-8-2 dynamic head, ramp-weighted stitch
+into whole-slide masks.  A step is one omniseg_segment_slide call over all 16
+slides (pad, pyramid, tissue map, tile list, BF16 backbone, controller, head,
+streamed stitch into a ring logit store), replayed as one HIP graph, with
+the slides already in HBM and the masks written to HBM.
+value = total slide pixels x pairs / step time, in Mpixel/s per class-scale.
 
-A step is one omniseg_segment_slide call (pad, pyramid, tissue map, tile
-list, backbone, controller, head, stitch) with the slide already in HBM and
-the masks written to HBM.  value = slide pixels x pairs / step time, in
-Mpixel/s per class-scale, for the BF16 backbone; the FP32 backbone is timed
-on the same GPU for the speed-up and the mask agreement.
+Beside it: the same 16 slides one call per slide; the plain FP32 backbone
+and FP8 on one 8192 x 8192 slide; the training step; masks of BF16 and FP8
+against FP32 and against the FP64 oracle (1024^2 crop) with trained weights;
+the paper's tiling and majority vote; merge and colour mapping; the FP64
+oracle timed on the host cores (cpu_baseline).
 
 Prints one JSON line.  --gpus N > 1 is refused: this path runs on one GPU.
 """
@@ -19,7 +24,9 @@ Prints one JSON line.  --gpus N > 1 is refused: this path runs on one GPU.
 import argparse
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -34,6 +41,7 @@ HBM_PEAK_GBS = 8000.0
 
 CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 1, 2, 3), tile=256, stride=128,
            fg_filter=True)
+PAIRS = [(c, si) for si in range(4) for c in range(6)]
 # The tiling of the paper's experiments (Section 3.2): 512^2 tiles at 40x with
 # stride 256 and vote threshold 1, at 10x and 5x with stride 64 and threshold 4.
 PAPER_CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 2, 3), tile=512, stride=256,
@@ -44,6 +52,11 @@ PAPER_CFG = dict(base=64, levels=5, head_out=2, n_classes=6, scales=(0, 2, 3), t
 # TUFT, CAP, PT, DT, PTC, VES.
 CLASS_SLOT = (3, 3, 2, 2, 0, 2)
 CLASS_COLOURS = ((230, 25, 75), (60, 180, 75), (255, 225, 25), (0, 130, 200), (245, 130, 48), (145, 30, 180))
+SLIDE = 8192          # side of the single-slide workload (slide seed 2)
+CROP = 1024           # precision crop of that slide, a stand-alone slide
+REGION = 2048         # training region (slide seed 3, with ground truth)
+TRAIN_LR = 1e-3       # Adam, cosine decay to 0 over the steps
+TRAIN_BATCH = 32
 
 # HBM bytes per launch of the BF16 conv kernels that can dominate this
 # workload, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
@@ -175,72 +188,113 @@ def stage_summary(records):
     return out
 
 
-def _plan(om, prec, batch_tiles, cfg=CFG, emit_logits=False):
+def _plan(om, prec, batch_tiles, cfg=CFG, emit_logits=False, graph=False, ring=0):
     vote = "vote_thresholds" in cfg
     otsu = cfg.get("tissue_method") == "otsu"
     return om.Plan(base=cfg["base"], levels=cfg["levels"], head_out=cfg["head_out"],
                    n_classes=cfg["n_classes"], scales=cfg["scales"], tile=cfg["tile"],
                    stride=cfg["stride"], fg_filter=cfg["fg_filter"],
                    precision={"bf16": om.BF16, "fp32": om.FP32, "fp8": om.FP8}[prec], emit_logits=emit_logits,
-                   batch_tiles=batch_tiles, scale_strides=cfg.get("scale_strides"),
+                   batch_tiles=batch_tiles, scale_strides=cfg.get("scale_strides"), graph=graph,
+                   logit_ring_tiles=ring,
                    merge=om.MERGE_VOTE if vote else om.MERGE_RAMP, vote_thresholds=cfg.get("vote_thresholds"),
                    tissue_method=om.TISSUE_OTSU if otsu else om.TISSUE_GRAY,
                    median_kernel=cfg.get("median_kernel", 1), min_tissue_area=cfg.get("min_tissue_area", 0))
 
 
-def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles, calib_tiles=64, cfg=CFG, pin=None):
-    plan = _plan(om, prec, batch_tiles, cfg)
+def _timed(torch, fn, n, stream):
+    """Mean ms of n back-to-back calls, by events on `stream`."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(n):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / max(1, n)
+
+
+def _kept(om, plan, slides, pairs, ws):
+    import torch
+
+    off, _ = plan.region(slides, pairs, om.REGION_TILE_COUNT)
+    return int(ws[off:off + 4].view(torch.int32).item())
+
+
+def run_leg(om, torch, dslide, flat_dev, pairs, prec, steps, warmup, batch_tiles, calib_tiles=64, cfg=CFG,
+            emit_logits=False, amax=None, tune=True):
+    """One slide, one precision: `steps` timed calls back to back (no
+    profiling), then one profiled call for the per-launch records."""
+    plan = _plan(om, prec, batch_tiles, cfg, emit_logits=emit_logits)
     ws = torch.empty(plan.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
     extra = {}
     if prec == "fp8":
-        # per-channel activation scales from the FP32 path on the first kept tiles
-        p32 = _plan(om, "fp32", batch_tiles, cfg)
-        ws32 = torch.empty(p32.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
-        t_cal = time.perf_counter()
-        amax = p32.calibrate_fp8([dslide], pairs, p32.pack(flat_dev), ws32, n_tiles=calib_tiles)
-        torch.cuda.synchronize()
-        extra["calibration_s"] = time.perf_counter() - t_cal
-        extra["calibration_tiles"] = calib_tiles
-        del ws32, p32
+        if amax is None:
+            # per-channel activation scales from the FP32 path on the first kept tiles
+            p32 = _plan(om, "fp32", batch_tiles, cfg)
+            ws32 = torch.empty(p32.workspace_bytes([dslide], pairs), dtype=torch.uint8, device=dslide.device)
+            t_cal = time.perf_counter()
+            amax = p32.calibrate_fp8([dslide], pairs, p32.pack(flat_dev), ws32, n_tiles=calib_tiles)
+            torch.cuda.synchronize()
+            extra["calibration_s"] = time.perf_counter() - t_cal
+            extra["calibration_tiles"] = calib_tiles
+            del ws32, p32
         packed = plan.pack_fp8(flat_dev, amax)
     else:
         packed = plan.pack(flat_dev)
     outs = plan.alloc_outputs([dslide], pairs)
     t_tune = time.perf_counter()
-    plan.autotune([dslide], pairs, packed, ws)
+    if tune:
+        plan.autotune([dslide], pairs, packed, ws)
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t_tune
-    if pin is not None:  # one configuration for every conv layer (where it is valid)
-        for stage in range(4):
-            for level in range(cfg["levels"]):
-                plan.set_conv_tuning(stage, level, pin)
+    call = lambda: plan.segment([dslide], pairs, packed, workspace=ws, outputs=outs)
     for _ in range(warmup):
-        plan.segment([dslide], pairs, packed, workspace=ws, outputs=outs)
-    torch.cuda.synchronize()
-    plan.set_profiling(True)
-    records = []
+        call()
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(steps):  # back to back; the records accumulate in the plan
-        plan.segment([dslide], pairs, packed, workspace=ws, outputs=outs)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    ms = _timed(torch, call, steps, stream)
+    plan.set_profiling(True)
+    call()
     records = plan.read_profile()
     plan.set_profiling(False)
-    ms = ev0.elapsed_time(ev1) / steps
-    off, _ = plan.region([dslide], pairs, om.REGION_TILE_COUNT)
-    kept = int(ws[off:off + 4].view(torch.int32).item())
+    kept = _kept(om, plan, [dslide], pairs, ws)
     masks = [m.cpu().numpy().astype(bool) for m in outs[0][0]]
+    logits = [lg.cpu().numpy() for lg in outs[1][0]] if emit_logits else None
     tuned = sorted({(r["stage"], r["level"], r["config"]) for r in records if r["config"] >= 0})
     if cfg.get("tissue_method") == "otsu":
         off, nb = plan.region([dslide], pairs, om.REGION_TISSUE_STATS)
         extra["tissue_stats"] = [int(v) for v in ws[off:off + nb].view(torch.int32).cpu()]
-    return dict(ms=ms, wall_ms=wall * 1e3 / steps, records=records, kept=kept, masks=masks,
+    if emit_logits:
+        # coverage of every plane: pixels under a kept tile (Lambda is exactly 0 elsewhere)
+        extra["covered"] = _coverage(om, plan, [dslide], pairs, ws, cfg)[0]
+    return dict(ms=ms, records=records, kept=kept, masks=masks, logits=logits,
                 tuned={f"{st}{l}": list(om.conv_config(c)) for st, l, c in tuned}, tune_s=t_tune, **extra)
+
+
+def _coverage(om, plan, slides, pairs, ws, cfg):
+    """Per (slide, pair): boolean map of the pixels some kept tile covers."""
+    import torch
+
+    T = cfg["tile"]
+    out = []
+    for i, s in enumerate(slides):
+        H, W = s.shape[0], s.shape[1]
+        row = []
+        for (c, si) in pairs:
+            k = cfg["scales"][si]
+            st = (cfg.get("scale_strides") or [cfg["stride"]] * 4)[si]
+            Hk, Wk = -(-H // (1 << k)), -(-W // (1 << k))
+            off, nb = plan.region(slides, pairs, om.REGION_TILE_INDEX, i * len(cfg["scales"]) + si)
+            idx = ws[off:off + nb].view(torch.int32).cpu().numpy()
+            ny = 1 if Hk <= T else -(-(Hk - T) // st) + 1
+            nx = 1 if Wk <= T else -(-(Wk - T) // st) + 1
+            idx = idx.reshape(ny, nx)
+            cov = np.zeros((Hk, Wk), bool)
+            for jy, jx in zip(*np.nonzero(idx >= 0)):
+                cov[jy * st:jy * st + T, jx * st:jx * st + T] = True
+            row.append(cov)
+        out.append(row)
+    return out
 
 
 def paper_leg(om, torch, M, dslide, size, steps, batch_tiles):
@@ -258,8 +312,7 @@ def paper_leg(om, torch, M, dslide, size, steps, batch_tiles):
     fp = run_leg(om, torch, dslide, flat_dev, pairs, "fp32", 1, 0, batch_tiles, cfg=PAPER_CFG)
     px = size * size * len(pairs)
     dices = [M.dice(a, b) for a, b in zip(bf["masks"], fp["masks"])]
-    stages = stage_summary([dict(r, ms=r["ms"] / steps, flops=r["flops"] / steps, bytes=r["bytes"] / steps)
-                            for r in bf["records"]])
+    stages = stage_summary(bf["records"])
     return {"value": px / (bf["ms"] * 1e-3) / 1e6, "unit": UNIT, "ms_per_step": bf["ms"], "steps": steps,
             "dtype": "bf16", "kept_tiles": bf["kept"], "pairs": len(pairs),
             "workload": f"the {size}x{size} slide, 512 tiles, scales 40x/10x/5x at strides 256/64/64, "
@@ -274,19 +327,18 @@ def paper_leg(om, torch, M, dslide, size, steps, batch_tiles):
 
 
 def mapping_leg(om, torch, dslide, flat_dev, size, reps, batch_tiles):
-    """Slide-wise aggregation and mapping on the bench slide: each class's
+    """Slide-wise aggregation and mapping on the single slide: each class's
     stitched logits at its best scale merged to a 40x mask (bilinear), then
     the six-colour overlay on the 40x slide and its 10x map.  Timed with HIP
     events on the launch stream over `reps` repetitions."""
-    pairs = [(c, si) for si in range(4) for c in range(6)]
     plan = _plan(om, "bf16", batch_tiles, emit_logits=True)
     packed = plan.pack(flat_dev)
-    masks, logits, _ = plan.segment([dslide], pairs, packed)
+    masks, logits, _ = plan.segment([dslide], PAIRS, packed)
     torch.cuda.synchronize()
     H = W = size
     planes = []
     for c, si in enumerate(CLASS_SLOT):
-        p = pairs.index((c, si))
+        p = PAIRS.index((c, si))
         planes.append((CFG["scales"][si], om.UPSAMPLE_BILINEAR, logits[0][p]))
     out = torch.empty((H, W, 3), dtype=torch.uint8, device=dslide.device)
     stream = torch.cuda.current_stream()
@@ -320,376 +372,581 @@ def mapping_leg(om, torch, dslide, flat_dev, size, reps, batch_tiles):
             "class_pixels_40x": [int(m.sum().item()) for m in m40]}
 
 
-def train_leg(om, torch, steps, warmup, batch=32):
-    """Training step on the 2048^2 region: 32 random tiles of 40x/20x (256^2,
-    stride 128), 6 classes x 2 scales, BF16 backbone: forward, stitch, BCE,
-    hand-written backward and a plain SGD update of the canonical weights."""
+# ---------------------------------------------------------------------------
+# inputs (seeded; generated in worker processes)
+# ---------------------------------------------------------------------------
+
+def _gen_input(job):
+    import synth
+
+    kind, arg = job
+    if kind == "batch":
+        rgb, _ = synth.strip_slide(arg["seed"], arg["H"], arg["W"], fg_frac=arg["fg_frac"], with_gt=False)
+        return rgb
+    if kind == "slide":
+        rgb, _ = synth.strip_slide(2, arg, arg, fg_frac=0.30, with_gt=False)
+        return rgb
+    rgb, gt = synth.strip_slide(3, REGION, REGION, fg_frac=0.30)
+    return rgb, gt
+
+
+# ---------------------------------------------------------------------------
+# training step (and the trained weights of the precision leg)
+# ---------------------------------------------------------------------------
+
+def train_leg(om, torch, rgb, gt, steps, batch=TRAIN_BATCH):
+    """The bench network (4 scales x 6 classes) trained on the 2048^2 region:
+    each step 32 random tiles of the region's 284 grid tiles (all scales), a
+    BF16 forward through backbone, head and stitch, the loss on the stitched
+    logits, the library's hand-written backward and an Adam update of the
+    FP32 canonical weights (lr TRAIN_LR after 25 warm-up steps, cosine decay).  Start: the
+    He-normal draw with every block's residual conv zeroed
+    (synth.training_init_weights); the loss weights each class's positive
+    pixels by its negative/positive ratio in the region, at most 10 (the
+    classes cover 0.2-1 % of the pixels).  Returns the report and the
+    trained FP32 weights."""
     import synth
 
     dev = torch.device("cuda:0")
-    rgb, gt = synth.strip_slide(3, 2048, 2048, fg_frac=0.30)
-    base, L, C, scales = 64, 5, 6, (0, 1)
-    flat = synth.he_normal_weights(13, base, L, C, len(scales), 2)
-    pairs = [(c, si) for si in range(len(scales)) for c in range(C)]
-    plan = om.Plan(base=base, levels=L, head_out=2, n_classes=C, scales=scales, tile=256, stride=128,
-                   precision=om.BF16, training=True)
+    C, scales = CFG["n_classes"], CFG["scales"]
+    flat = synth.training_init_weights(13, CFG["base"], CFG["levels"], C, len(scales), CFG["head_out"])
+    plan = om.Plan(base=CFG["base"], levels=CFG["levels"], head_out=CFG["head_out"], n_classes=C, scales=scales,
+                   tile=CFG["tile"], stride=CFG["stride"], precision=om.BF16, training=True)
     slide = torch.from_numpy(rgb).to(dev)
-    y = torch.from_numpy(synth.soft_targets(gt, scales, pairs)).to(dev)
-    w = torch.from_numpy(flat).to(dev)
-    grid = [(si, jy, jx) for si, k in enumerate(scales)
-            for jy in range(-(-(-(-2048 // (1 << k)) - 256) // 128) + 1)
-            for jx in range(-(-(-(-2048 // (1 << k)) - 256) // 128) + 1)]
+    y = torch.from_numpy(synth.soft_targets(gt, scales, PAIRS)).to(dev)
+    offs = plan.plane_offsets(slide, PAIRS)
+    pw = torch.empty_like(y)
+    for p in range(len(PAIRS)):
+        pos = float(y[offs[p]:offs[p + 1]].mean())
+        pw[offs[p]:offs[p + 1]] = float(np.clip((1 - pos) / max(pos, 1e-6), 1.0, 10.0))
+    w = torch.from_numpy(flat).to(dev).requires_grad_(True)
+    opt = torch.optim.Adam([w], lr=TRAIN_LR)
+    T, s = CFG["tile"], CFG["stride"]
+    ng = lambda n: 1 if n <= T else -(-(n - T) // s) + 1
+    grid = [(si, jy, jx) for si, k in enumerate(scales) for jy in range(ng(-(-REGION // (1 << k))))
+            for jx in range(ng(-(-REGION // (1 << k))))]
     rng = np.random.default_rng(14)
+    sp = torch.nn.functional.softplus
+    losses = []
 
-    def step():
-        idx = rng.choice(len(grid), size=batch, replace=False)
-        tiles = [grid[i] for i in sorted(idx)]
-        wt = w.detach().requires_grad_(True)
-        logit, covered = om.OmniSegFn.apply(wt, plan, slide, tiles, pairs)
-        loss = om.BCELossFn.apply(logit, y, covered)
+    def step(it):
+        for g in opt.param_groups:  # 25 warm-up steps, then cosine decay
+            g["lr"] = TRAIN_LR * min(1.0, (it + 1) / 25.0) * 0.5 * (1.0 + np.cos(np.pi * it / steps))
+        tiles = [grid[i] for i in sorted(rng.choice(len(grid), size=batch, replace=False))]
+        opt.zero_grad()
+        logit, covered = om.OmniSegFn.apply(w, plan, slide, tiles, PAIRS)
+        v = covered.to(torch.float32)  # mean over covered entries, without data-dependent indexing
+        loss = ((pw * y * sp(-logit) + (1 - y) * sp(logit)) * v).sum() / v.sum()
         loss.backward()
-        g = wt.grad
-        # SGD step of length lr (the random-weight network's gradients are huge)
-        w.sub_(g * (1e-3 / torch.clamp(g.norm(), min=1.0)))
-        return loss.detach()
+        opt.step()
+        losses.append(loss.detach())
 
-    losses = [step() for _ in range(warmup)]
+    step(0)  # untimed: loads the code objects
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    losses += [step() for _ in range(steps)]
+    for it in range(1, steps):
+        step(it)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    fwd_flops = 18.0 * base * base * 256 * 256 * (3.0 / base + 1 + 5.5 * (L - 1)) * batch
-    return {"ms_per_step": ms, "tiles_per_step": batch, "grid_tiles": len(grid), "steps": steps,
-            "dtype": "bf16", "tiles_per_s": batch / (ms * 1e-3),
-            "algorithmic_tflop_per_step": 3 * fwd_flops / 1e12,
-            "achieved_tflops": 3 * fwd_flops / (ms * 1e-3) / 1e12,
-            "loss_first_last": [float(losses[0]), float(losses[-1])],
-            "workload": "2048x2048 synthetic region, 32 random 256^2 tiles of 40x/20x per step, 6 classes x "
-                        "2 scales, base-64 5-level U-Net, BCE vs soft masks, backward + SGD update"}
+    ms = e0.elapsed_time(e1) / max(1, steps - 1)
+    lv = [float(x) for x in losses]
+    fwd_flops = 18.0 * CFG["base"] ** 2 * T * T * (3.0 / CFG["base"] + 1 + 5.5 * (CFG["levels"] - 1)) * batch
+    rep = {"ms_per_step": ms, "tiles_per_step": batch, "grid_tiles": len(grid), "steps": steps,
+           "dtype": "bf16 (FP32 master weights, Adam)", "tiles_per_s": batch / (ms * 1e-3),
+           "algorithmic_tflop_per_step": 3 * fwd_flops / 1e12,
+           "achieved_tflops": 3 * fwd_flops / (ms * 1e-3) / 1e12,
+           "achieved_frac_bf16_peak": 3 * fwd_flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"],
+           "loss_first10_last10": [float(np.mean(lv[:10])), float(np.mean(lv[-10:]))],
+           "workload": f"{REGION}x{REGION} synthetic region with ground truth, {batch} random 256^2 tiles of "
+                       "40x/20x/10x/5x per step, 6 classes x 4 scales, base-64 5-level U-Net, class-weighted BCE "
+                       "on the stitched logits, hand-written backward, Adam (lr 1e-3, cosine)"}
+    return rep, w.detach().contiguous()
 
 
-def trained_dice_leg(om, torch, M, steps, lr=3e-4):
-    """Masks from trained weights: the training-step network (2048^2 region,
-    6 classes x 2 scales) trained in FP32 with the library's forward and
-    hand-written backward for `steps` Adam steps of 32 tiles, then the whole
-    region segmented at FP32, BF16 and FP8 and their masks and logits
-    compared.  The classes cover 0.2-1 % of the pixels, so the training loss
-    weights positive pixels by (1 - p) / p (p: the batch's positive share),
-    computed by torch on the stitched logits; plain BCE would learn empty
-    masks."""
-    import synth
+# ---------------------------------------------------------------------------
+# the headline: 16 slides in one call, one HIP graph
+# ---------------------------------------------------------------------------
 
-    dev = torch.device("cuda:0")
-    rgb, gt = synth.strip_slide(3, 2048, 2048, fg_frac=0.30)
-    base, L, C, scales = 64, 5, 6, (0, 1)
-    flat = synth.he_normal_weights(13, base, L, C, len(scales), 2)
-    pairs = [(c, si) for si in range(len(scales)) for c in range(C)]
-    mk = lambda prec, **kw: om.Plan(base=base, levels=L, head_out=2, n_classes=C, scales=scales, tile=256, stride=128,
-                                    precision=prec, **kw)
-    plan = mk(om.FP32, training=True)
-    slide = torch.from_numpy(rgb).to(dev)
-    y = torch.from_numpy(synth.soft_targets(gt, scales, pairs)).to(dev)
-    w = torch.from_numpy(flat).to(dev).requires_grad_(True)
-    opt = torch.optim.Adam([w], lr=lr)
-    grid = [(si, jy, jx) for si, k in enumerate(scales)
-            for jy in range(-(-(-(-2048 // (1 << k)) - 256) // 128) + 1)
-            for jx in range(-(-(-(-2048 // (1 << k)) - 256) // 128) + 1)]
-    rng = np.random.default_rng(14)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        tiles = [grid[i] for i in sorted(rng.choice(len(grid), size=32, replace=False))]
-        opt.zero_grad()
-        logit, covered = om.OmniSegFn.apply(w, plan, slide, tiles, pairs)
-        v = covered.bool()
-        pos = (y * v).sum() / v.sum()
-        pw = ((1 - pos) / pos.clamp(min=1e-4)).detach()
-        torch.nn.functional.binary_cross_entropy_with_logits(logit[v], y[v], pos_weight=pw).backward()
-        opt.step()
+def batch16_leg(om, torch, slides, specs, flat_dev, steps, warmup, batch_tiles, autotune):
+    """All kept tiles of 16 uneven slides, 4 scales and 6 classes through one
+    omniseg_segment_slide call (graph-captured, ring logit store), against
+    the same call without the graph and against one call per slide."""
+    dev = slides[0].device
+    plan = _plan(om, "bf16", batch_tiles, graph=True, ring=1)
+    eager = _plan(om, "bf16", batch_tiles, ring=1)
+    packed = plan.pack(flat_dev)
+    ws = torch.empty(plan.workspace_bytes(slides, PAIRS), dtype=torch.uint8, device=dev)
+    print(f"# 16-slide workspace {ws.numel() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    outs = plan.alloc_outputs(slides, PAIRS)
+    t_tune = time.perf_counter()
+    if autotune:
+        plan.autotune(slides, PAIRS, packed, ws)
+    else:
+        for stage in range(4):
+            for level in range(CFG["levels"]):
+                plan.set_conv_tuning(stage, level, BENCH_CONV_CONFIG)
     torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    wt = w.detach().contiguous()
-    out = {}
-    for name, prec in (("fp32", om.FP32), ("bf16", om.BF16), ("fp8", om.FP8)):
-        p = mk(prec, emit_logits=True)
-        if prec == om.FP8:
-            p32 = mk(om.FP32)
-            ws = torch.empty(p32.workspace_bytes([slide], pairs), dtype=torch.uint8, device=dev)
-            packed = p.pack_fp8(wt, p32.calibrate_fp8([slide], pairs, p32.pack(wt), ws, n_tiles=64))
-        else:
-            packed = p.pack(wt)
-        masks, logits, _ = p.segment([slide], pairs, packed)
-        out[name] = ([m.cpu().numpy().astype(bool) for m in masks[0]],
-                     [lg.cpu().numpy().astype(np.float64) for lg in logits[0]])
-    res = {"steps": steps, "train_s": train_s, "lr": lr,
-           "fp32_positive_fraction_mean": float(np.mean([m.mean() for m in out["fp32"][0]])),
-           "fp32_abs_logit_below_1": float(np.mean([np.mean(np.abs(lg) < 1) for lg in out["fp32"][1]]))}
-    for name in ("bf16", "fp8"):
-        d = [M.dice(a, b) for a, b in zip(out[name][0], out["fp32"][0])]
-        e = [M.normwise_error(a, b) for a, b in zip(out[name][1], out["fp32"][1])]
-        res[f"{name}_vs_fp32"] = {"dice_min": min(d), "dice_mean": float(np.mean(d)),
-                                  "disagreement_max": max(M.disagreement(a, b) for a, b in
-                                                          zip(out[name][0], out["fp32"][0])),
-                                  "logit_error_max": max(e)}
-    return res
-
-
-def _gen_batch_slide(spec):
-    import synth
-
-    rgb, _ = synth.strip_slide(spec["seed"], spec["H"], spec["W"], fg_frac=spec["fg_frac"], with_gt=False)
-    return rgb
-
-
-def batch_workload(om, torch, steps, warmup, max_kept):
-    """16 uneven slides (heights 2000-8000, widths 4000-40000, 10-60% tissue):
-    all kept tiles of all slides, scales and classes in one call, against one
-    call per slide, BF16 backbone."""
-    import concurrent.futures
-
-    import synth
-
-    dev = torch.device("cuda:0")
-    specs = synth.batch_slide_specs(99, 16)
-    t0 = time.perf_counter()
-    slides = [None] * len(specs)
-    with concurrent.futures.ProcessPoolExecutor(max_workers=8) as ex:
-        futs = {ex.submit(_gen_batch_slide, sp): i for i, sp in enumerate(specs)}
-        for f in concurrent.futures.as_completed(futs):
-            i = futs[f]
-            slides[i] = torch.from_numpy(f.result()).to(dev)
-            print(f"# slide {i} {specs[i]['H']}x{specs[i]['W']} ready ({time.perf_counter() - t0:.0f} s)",
-                  file=sys.stderr, flush=True)
-    flat = synth.he_normal_weights(12, CFG["base"], CFG["levels"], CFG["n_classes"], len(CFG["scales"]),
-                                   CFG["head_out"])
-    pairs = [(c, si) for si in range(4) for c in range(6)]
-    plan = om.Plan(base=CFG["base"], levels=CFG["levels"], head_out=CFG["head_out"], n_classes=CFG["n_classes"],
-                   scales=CFG["scales"], tile=CFG["tile"], stride=CFG["stride"], fg_filter=True,
-                   precision=om.BF16, max_kept_tiles=max_kept)
-    packed = plan.pack(torch.from_numpy(flat).to(dev))
-    ws = torch.empty(plan.workspace_bytes(slides, pairs), dtype=torch.uint8, device=dev)
-    print(f"# workspace {ws.numel() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
-    outs = plan.alloc_outputs(slides, pairs)
-    plan.autotune(slides, pairs, packed, ws)
-
-    def timed(fn, n):
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(n):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / n
-
-    batched = lambda: plan.segment(slides, pairs, packed, workspace=ws, outputs=outs)
+    t_tune = time.perf_counter() - t_tune
+    for st in range(4):
+        for lv in range(CFG["levels"]):
+            eager.set_conv_tuning(st, lv, plan.get_conv_tuning(st, lv))
+    side = torch.cuda.Stream()  # graphs are captured on a created stream
+    batched = lambda: plan.segment(slides, PAIRS, packed, workspace=ws, outputs=outs, stream=side)
     for _ in range(warmup):
         batched()
-    ms_b = timed(batched, steps)
-    off, _ = plan.region(slides, pairs, om.REGION_TILE_COUNT)
-    kept = int(ws[off:off + 4].view(torch.int32).item())
-    print(f"# batched: {ms_b:.0f} ms for {kept} kept tiles", file=sys.stderr, flush=True)
+    ms = _timed(torch, batched, steps, side)
+    kept = _kept(om, plan, slides, PAIRS, ws)
+    print(f"# batched (graph): {ms:.0f} ms for {kept} kept tiles", file=sys.stderr, flush=True)
+    ref = [[m.clone() for m in row] for row in outs[0]]
+    ms_eager = _timed(torch, lambda: eager.segment(slides, PAIRS, packed, workspace=ws, outputs=outs, stream=side),
+                      1, side)
+    same_eager = all(torch.equal(a, b) for ra, rb in zip(ref, outs[0]) for a, b in zip(ra, rb))
 
     def sequential():
         for i, sl in enumerate(slides):
-            plan.segment([sl], pairs, packed, workspace=ws, outputs=([outs[0][i]], [outs[1][i]]))
+            eager.segment([sl], PAIRS, packed, workspace=ws, outputs=([outs[0][i]], [outs[1][i]]), stream=side)
 
-    ms_s = timed(sequential, 1)
-    px = sum(sp["H"] * sp["W"] for sp in specs) * len(pairs)
-    return {"workload": "16 synthetic slides, heights 2000-8000, widths 4000-40000, 10-60% tissue; 4 scales x 6 "
-                        "classes; base-64 5-level U-Net; BF16",
-            "slides": len(specs), "gigapixels_40x": sum(sp["H"] * sp["W"] for sp in specs) / 1e9,
-            "kept_tiles": kept, "batched_ms": ms_b, "sequential_ms": ms_s,
-            "batched_value": px / (ms_b * 1e-3) / 1e6, "sequential_value": px / (ms_s * 1e-3) / 1e6,
-            "unit": UNIT, "speedup_batched_vs_sequential": ms_s / ms_b, "steps": steps}
+    ms_seq = _timed(torch, sequential, 1, side)
+    same_seq = all(torch.equal(a, b) for ra, rb in zip(ref, outs[0]) for a, b in zip(ra, rb))
+    print(f"# eager {ms_eager:.0f} ms, one call per slide {ms_seq:.0f} ms", file=sys.stderr, flush=True)
+    eager.set_profiling(True)
+    eager.segment(slides, PAIRS, packed, workspace=ws, outputs=outs, stream=side)
+    records = eager.read_profile()
+    eager.set_profiling(False)
+    torch.cuda.synchronize()
+    px = sum(sp["H"] * sp["W"] for sp in specs) * len(PAIRS)
+    tuned = sorted({(r["stage"], r["level"], r["config"]) for r in records if r["config"] >= 0})
+    st = stage_summary(records)
+    r = {"workload": "16 synthetic slides (seeds 100-115), heights 2000-8000, widths 4000-40000, 10-60% tissue; "
+                     "4 scales x 6 classes; 256 tiles at stride 128, foreground only; base-64 5-level U-Net + "
+                     "dynamic head, ramp stitch; BF16; one call, one HIP graph, ring logit store",
+         "slides": len(specs), "gigapixels_40x": sum(sp["H"] * sp["W"] for sp in specs) / 1e9,
+         "pairs": len(PAIRS), "kept_tiles": kept, "workspace_gib": ws.numel() / 2**30,
+         "graph_ms": ms, "eager_ms": ms_eager, "per_slide_calls_ms": ms_seq,
+         "speedup_batched_vs_per_slide": ms_seq / ms, "speedup_graph_vs_eager": ms_eager / ms,
+         "masks_equal": {"eager_vs_graph": same_eager, "per_slide_vs_graph": same_seq},
+         "value": px / (ms * 1e-3) / 1e6, "per_slide_value": px / (ms_seq * 1e-3) / 1e6,
+         "tflop_per_step": sum(x["flops"] for x in records) / 1e12,
+         "conv_table": "autotuned on this workload" if autotune else f"pinned: configuration {BENCH_CONV_CONFIG}",
+         "tune_s": t_tune, "stages": st, "roofline": roofline(om, records, "bf16"),
+         "layers": layer_summary(records, 1),
+         "conv_tiles": {f"{s_}{l}": list(om.conv_config(c)) for s_, l, c in tuned}}
+    if "stitch" in st:
+        r["roofline_stitch"] = dict(bound="hbm", achieved=st["stitch"]["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                                    frac=st["stitch"]["gbs"] / HBM_PEAK_GBS, traffic=None)
+        sl = sorted(((x["ms"], x["bytes"]) for x in records if x["stage"] == "stitch"), reverse=True)
+        r["stitch_launches"] = {"n": len(sl), "with_work": sum(1 for _, b in sl if b > 0),
+                                "median_ms": sl[len(sl) // 2][0], "slowest_ms_gb": [[m, b / 1e9] for m, b in sl[:8]],
+                                "empty_ms_total": sum(m for m, b in sl if b == 0)}
+    del ws
+    return r
 
 
-def cpu_baseline(rgb, flat, pairs, kept, seconds):
-    """The FP64 oracle on a bounded sample of the same workload, extrapolated."""
+# ---------------------------------------------------------------------------
+# precision: trained weights, BF16 / FP8 against FP32 (whole slide) and the
+# FP64 oracle (1024^2 crop)
+# ---------------------------------------------------------------------------
+
+def _cmp(M, masks, logits, ref_masks, ref_logits, covered):
+    """Max logit error (normwise and absolute), per-plane Dice, the largest
+    disagreement and the largest at-risk fraction: covered pixels whose
+    reference logit lies within the plane's largest absolute error of the
+    threshold (either mask value is correct there)."""
+    dice, dis, risk, nerr, aerr = [], [], [], [], []
+    for m, lg, rm, rl, cv in zip(masks, logits, ref_masks, ref_logits, covered):
+        lg = np.asarray(lg, np.float64)
+        rl = np.asarray(rl, np.float64)
+        e = float(np.abs(lg - rl).max()) if lg.size else 0.0
+        dice.append(M.dice(m, rm))
+        dis.append(M.disagreement(m, rm))
+        risk.append(float((np.abs(rl[cv]) <= e).mean()) if cv.any() else 0.0)
+        nerr.append(M.normwise_error(lg, rl, cv))
+        aerr.append(e)
+    return {"dice_min": min(dice), "dice_mean": float(np.mean(dice)), "dice": [round(d, 6) for d in dice],
+            "disagreement_max": max(dis), "at_risk_max": max(risk), "at_risk": [round(r, 6) for r in risk],
+            "logit_error_normwise_max": max(nerr), "logit_abs_error_max": max(aerr)}
+
+
+def precision_gpu(om, torch, M, dslide, dcrop, wt, batch_tiles):
+    """GPU side of the precision leg with the trained weights: FP32, BF16
+    and FP8 masks and logits of the whole slide and of the crop."""
+    res, crop = {}, {}
+    fp = run_leg(om, torch, dslide, wt, PAIRS, "fp32", 1, 0, batch_tiles, emit_logits=True, tune=False)
+    bf = run_leg(om, torch, dslide, wt, PAIRS, "bf16", 1, 0, batch_tiles, emit_logits=True, tune=False)
+    f8 = run_leg(om, torch, dslide, wt, PAIRS, "fp8", 1, 0, batch_tiles, emit_logits=True, tune=False)
+    cov = fp["covered"]
+    res["fp32_positive_fraction_mean"] = float(np.mean([m.mean() for m in fp["masks"]]))
+    res["fp32_abs_logit_median_covered"] = float(np.median(np.concatenate(
+        [np.abs(lg[c]) for lg, c in zip(fp["logits"], cov)])))
+    res["bf16_vs_fp32"] = _cmp(M, bf["masks"], bf["logits"], fp["masks"], fp["logits"], cov)
+    res["fp8_vs_fp32"] = _cmp(M, f8["masks"], f8["logits"], fp["masks"], fp["logits"], cov)
+    for name, prec in (("fp32", "fp32"), ("bf16", "bf16"), ("fp8", "fp8")):
+        r = run_leg(om, torch, dcrop, wt, PAIRS, prec, 1, 0, batch_tiles, emit_logits=True, tune=False)
+        crop[name] = (r["masks"], r["logits"], r["covered"])
+    return res, crop
+
+
+def precision_vs_oracle(M, crop, ref):
+    out = {}
+    cov = crop["fp32"][2]
+    for name in ("fp32", "bf16", "fp8"):
+        masks, logits, _ = crop[name]
+        out[f"{name}_vs_fp64"] = _cmp(M, masks, logits, ref["mask"], ref["logit"], cov)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# cpu_baseline: the FP64 oracle on the host cores, in a child process started
+# before this process touches the GPU; it also supplies the FP64 reference
+# planes of the precision crop
+# ---------------------------------------------------------------------------
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_worker(workdir):
+    """Child process: the FP64 oracle on the 1024^2 crop (a stand-alone
+    slide) with the trained weights the parent writes to workdir."""
+    import synth
     from oracle import omniseg_oracle as O
 
     try:
         import threadpoolctl
-        threads = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or 1
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+    except ImportError:  # pragma: no cover
+        threadpoolctl = None
+    big, _ = synth.strip_slide(2, SLIDE, SLIDE, fg_frac=0.30, with_gt=False)
+    y0, x0 = synth.strip_crop_origin(2, SLIDE, SLIDE, CROP)
+    crop = np.ascontiguousarray(big[y0:y0 + CROP, x0:x0 + CROP])
+    del big
+    wpath = os.path.join(workdir, "weights.npy")
+    t_wait = time.time()
+    while not os.path.exists(wpath):
+        if time.time() - t_wait > 1800 or os.getppid() == 1:
+            sys.exit(3)
+        time.sleep(0.2)
+    flat = np.load(wpath)
     cfg = O.make_config(**CFG)
+    threads = None
+    if threadpoolctl is not None:
+        threads = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or None
+    # single thread: one 40x tile (backbone, controller, 6-class head)
     wts = O.unpack_weights(flat, cfg)
-    fg = O.tissue_map(rgb, 3)
-    tl = O.tile_list([rgb.shape[:2]], cfg, [fg])
-    rng = np.random.default_rng(0)
-    order = rng.permutation(len(tl))
-    done, t_tiles = 0, 0.0
-    t_start = time.perf_counter()
-    for i in order:
-        n, si, jy, jx = tl[i]
-        t0 = time.perf_counter()
-        x = O.tile_input(rgb, cfg["scales"][si], 256, 128, jy, jx)
-        O.tile_logits(x, wts, cfg, si, list(range(6)))
-        t_tiles += time.perf_counter() - t0
-        done += 1
-        if time.perf_counter() - t_start > seconds:
-            break
-    per_tile = t_tiles / done
-    # stitch: one plane at 5x of the sampled kind, timed, scaled by tile pixels
-    ts = [(jy, jx) for (_, si, jy, jx) in tl if si == 3]
+    t1 = time.perf_counter()
+    if threadpoolctl is not None:
+        with threadpoolctl.threadpool_limits(1):
+            O.tile_logits(O.tile_input(crop, 0, CFG["tile"], CFG["stride"], 1, 1), wts, cfg, 0, list(range(6)))
+    else:  # pragma: no cover
+        O.tile_logits(O.tile_input(crop, 0, CFG["tile"], CFG["stride"], 1, 1), wts, cfg, 0, list(range(6)))
+    t_tile1 = time.perf_counter() - t1
     t0 = time.perf_counter()
-    O.stitch(ts, [np.zeros((256, 256))] * len(ts), 1024, 1024, 256, 128)
-    per_tile_stitch = (time.perf_counter() - t0) / max(1, len(ts))
-    t_slide = per_tile * kept + per_tile_stitch * kept * 6
-    value = rgb.shape[0] * rgb.shape[1] * len(pairs) / (t_slide * 1e6)
-    return dict(value=value, unit=UNIT, cores=int(threads), kind="oracle",
-                sample=f"{done} of {kept} kept tiles through the FP64 oracle backbone, controller and "
-                       f"6-class head ({per_tile:.2f} s/tile) plus one 5x stitch plane, extrapolated "
-                       f"to the whole slide ({t_slide:.0f} s)")
+    ref = O.segment([crop], flat, cfg, PAIRS)
+    t_all = time.perf_counter() - t0
+    arrays = {}
+    for p in range(len(PAIRS)):
+        arrays[f"logit{p}"] = ref["logit"][0][p]
+        arrays[f"mask{p}"] = ref["mask"][0][p]
+    np.savez(os.path.join(workdir, "ref.npz"), **arrays)
+    info = {"seconds": t_all, "tiles": len(ref["tiles"]), "threads": threads, "single_thread_tile_s": t_tile1,
+            "crop_origin": [y0, x0]}
+    with open(os.path.join(workdir, "ref.json.tmp"), "w") as f:
+        json.dump(info, f)
+    os.replace(os.path.join(workdir, "ref.json.tmp"), os.path.join(workdir, "ref.json"))
+
+
+def start_oracle_worker(workdir):
+    env = dict(os.environ)
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker", workdir], env=env)
+
+
+def finish_cpu_baseline(proc, workdir, timeout_s):
+    try:
+        rc = proc.wait(timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        return None, None
+    if rc != 0 or not os.path.exists(os.path.join(workdir, "ref.json")):
+        return None, None
+    with open(os.path.join(workdir, "ref.json")) as f:
+        info = json.load(f)
+    z = np.load(os.path.join(workdir, "ref.npz"))
+    ref = {"logit": [z[f"logit{p}"] for p in range(len(PAIRS))], "mask": [z[f"mask{p}"] for p in range(len(PAIRS))]}
+    px = CROP * CROP * len(PAIRS)
+    base = {"value": px / info["seconds"] / 1e6, "unit": UNIT, "cores": info["threads"], "kind": "oracle",
+            "sample": f"the whole {CROP}x{CROP} crop of the {SLIDE}^2 slide ({info['tiles']} kept tiles of 4 "
+                      f"scales, 24 class-scale pairs) through the FP64 oracle with the trained weights: "
+                      f"{info['seconds']:.1f} s, timed alongside the GPU legs",
+            "cpu_model": _cpu_model(), "blas_threads": info["threads"], "host_cpus": os.cpu_count(),
+            "single_thread": {"one_40x_tile_s": info["single_thread_tile_s"],
+                              "value": CROP * CROP * len(PAIRS) / (info["single_thread_tile_s"] * info["tiles"]) / 1e6,
+                              "note": "one tile timed at 1 BLAS thread, scaled by the crop's tile count"}}
+    return base, ref
+
+
+# Conv tile configuration of every backbone layer of the 16-slide workload:
+# omniseg_autotune picks the eight-wave row-reuse configuration
+# (ROWS8_16x16_64) for most layers and swaps a few between it and the
+# four-wave one on timing noise from run to run; pinning it makes every run
+# launch the same kernels as the counter runs behind MEASURED_TRAFFIC.
+BENCH_CONV_CONFIG = 10
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--size", type=int, default=8192, help="slide side in pixels")
+    ap.add_argument("--steps", type=int, default=3, help="timed steps of the 16-slide call")
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch-tiles", type=int, default=0)
+    ap.add_argument("--slide-steps", type=int, default=5, help="timed BF16 steps on the single slide")
     ap.add_argument("--fp32-steps", type=int, default=2)
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--train-steps", type=int, default=3, help="training-step leg (0 = skip)")
-    ap.add_argument("--fp8-steps", type=int, default=3, help="FP8 backbone leg (0 = skip)")
+    ap.add_argument("--fp8-steps", type=int, default=3, help="FP8 leg on the single slide (0 = skip)")
+    ap.add_argument("--train-steps", type=int, default=400,
+                    help="training steps (the training-step timing and the trained weights of the precision leg)")
     ap.add_argument("--paper-steps", type=int, default=2,
                     help="leg with the paper's tiling (512 tiles, 40x/10x/5x, strides 256/64/64, "
                          "majority vote 1/4/4), BF16 and one FP32 step for the masks (0 = skip)")
     ap.add_argument("--map-reps", type=int, default=5,
                     help="aggregation and mapping leg (merge to 40x + overlay) repetitions (0 = skip)")
-    ap.add_argument("--trained-dice-steps", type=int, default=0,
-                    help="train the training-step network this many FP32 steps and compare BF16/FP8 masks "
-                         "with FP32 on it (0 = skip)")
+    ap.add_argument("--no-batch16", action="store_true", help="skip the 16-slide workload (headline: the slide)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the trained-weights precision leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle (cpu_baseline, FP64 crop)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the 16-slide call's conv tiles instead of the pinned table")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device to device (a plain copy of known size for "
                          "scaling profiler byte counters)")
-    ap.add_argument("--pin-config", type=int, default=None,
-                    help="after autotuning, run every conv layer of the BF16 leg with this tile configuration "
-                         "where it is valid (repeatable launch sets for counter runs)")
-    ap.add_argument("--dump-launches", action="store_true",
-                    help="add the (stage, level, config) of every timed BF16 conv launch to the JSON line")
-    ap.add_argument("--workload", choices=["slide", "batch16"], default="slide",
-                    help="slide: the 8192^2 slide (default); batch16: 16 uneven slides, batched vs per slide")
+    ap.add_argument("--counters", action="store_true",
+                    help="profiler counter run: a 1 GiB device copy (the byte counters' scale), then one eager "
+                         "16-slide call and one single-slide call with the pinned conv configuration, and the "
+                         "merge and overlay of the mapping leg; prints their launch lists")
+    ap.add_argument("--oracle-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_worker:
+        oracle_worker(args.oracle_worker)
+        return
+    if args.counters:
+        counters_run(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
                                    "supported: the path runs on one GPU (--gpus must be 1)"}))
         sys.exit(2)
+    t_start = time.perf_counter()
+    log = lambda msg: print(f"# [{time.perf_counter() - t_start:6.1f} s] {msg}", file=sys.stderr, flush=True)
+
+    # the CPU oracle runs in a child process started before this process
+    # touches the GPU; it waits for the weights file
+    workdir = tempfile.mkdtemp(prefix="omniseg_bench_")
+    proc = None if args.no_cpu else start_oracle_worker(workdir)
+    try:
+        result = run(args, workdir, proc, log)
+    finally:
+        if proc is not None and proc.poll() is None:
+            proc.kill()
+    print(json.dumps(result))
+
+
+def counters_run(args):
+    """The launches behind profiles/ counter summaries, each kernel once per
+    call, in a fixed order: copy, 16-slide call, single-slide call, merge and
+    overlay."""
+    import concurrent.futures
+
+    import synth
+    specs = synth.batch_slide_specs(99, 16)
+    with concurrent.futures.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        made = list(ex.map(_gen_input, [("batch", sp) for sp in specs] + [("slide", SLIDE)]))
+    import torch
+
+    from paper_2305_14566_amd import omniseg as om
+    om.lib()
+    dev = torch.device("cuda:0")
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    flat = synth.he_normal_weights(12, CFG["base"], CFG["levels"], CFG["n_classes"], len(CFG["scales"]),
+                                   CFG["head_out"])
+    flat_dev = torch.from_numpy(flat).to(dev)
+    out = {"copy_bytes": 1 << 30}
+    for name, slides, ring in (("batch16", [torch.from_numpy(r).to(dev) for r in made[:-1]], 1),
+                               ("slide", [torch.from_numpy(made[-1]).to(dev)], 0)):
+        plan = _plan(om, "bf16", args.batch_tiles, ring=ring)
+        for stage in range(4):
+            for level in range(CFG["levels"]):
+                plan.set_conv_tuning(stage, level, BENCH_CONV_CONFIG)
+        packed = plan.pack(flat_dev)
+        ws = torch.empty(plan.workspace_bytes(slides, PAIRS), dtype=torch.uint8, device=dev)
+        outs = plan.alloc_outputs(slides, PAIRS)
+        plan.set_profiling(True)
+        plan.segment(slides, PAIRS, packed, workspace=ws, outputs=outs)
+        recs = plan.read_profile()
+        torch.cuda.synchronize()
+        out[name] = {"kept_tiles": _kept(om, plan, slides, PAIRS, ws),
+                     "launches": [[r["stage"], r["level"], r["config"], r["tiles"], r["flops"], r["bytes"]]
+                                  for r in recs]}
+        del ws, outs, slides
+        torch.cuda.empty_cache()
+    dslide = torch.from_numpy(made[-1]).to(dev)
+    out["mapping"] = mapping_leg(om, torch, dslide, flat_dev, SLIDE, 1, args.batch_tiles)
+    print(json.dumps(out))
+
+
+def run(args, workdir, proc, log):
+    import concurrent.futures
+
+    import synth
+
+    specs = synth.batch_slide_specs(99, 16)
+    jobs = ([] if args.no_batch16 else [("batch", sp) for sp in specs]) + [("slide", SLIDE), ("region", None)]
+    t0 = time.perf_counter()
+    with concurrent.futures.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        made = list(ex.map(_gen_input, jobs))
+    gen_s = time.perf_counter() - t0
+    batch_rgb = made[:-2]
+    rgb, (region_rgb, region_gt) = made[-2], made[-1]
+    log(f"inputs generated in {gen_s:.1f} s")
 
     import torch
 
-    import synth
     from paper_2305_14566_amd import metrics as M
     from paper_2305_14566_amd import omniseg as om
 
-    om.lib()
-    if args.workload == "batch16":
-        r = batch_workload(om, torch, args.steps, args.warmup, max_kept=70000)
-        print(json.dumps({"metric": METRIC, "value": r["batched_value"], "unit": UNIT, "n_gpus": 1,
-                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["batched_ms"],
-                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
-                          "data": "synthetic", "config": {"workload": r["workload"]}, "batch": r}))
-        return
+    om.lib()  # fails loudly without the HIP library
     dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    rgb, _ = synth.strip_slide(2, args.size, args.size, fg_frac=0.30, with_gt=False)
-    flat = synth.he_normal_weights(12, CFG["base"], CFG["levels"], CFG["n_classes"], len(CFG["scales"]),
-                                   CFG["head_out"])
-    gen_s = time.perf_counter() - t0
-    dslide = torch.from_numpy(rgb).to(dev)
-    flat_dev = torch.from_numpy(flat).to(dev)
-    pairs = [(c, si) for si in range(4) for c in range(6)]
     if args.copy_gib > 0:
         n = int(args.copy_gib * 2 ** 30) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"# copied {n * 4} bytes device to device", file=sys.stderr, flush=True)
+        log(f"copied {n * 4} bytes device to device")
         del src, dst
-    print(f"# slide {args.size}^2 generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    flat = synth.he_normal_weights(12, CFG["base"], CFG["levels"], CFG["n_classes"], len(CFG["scales"]),
+                                   CFG["head_out"])
+    flat_dev = torch.from_numpy(flat).to(dev)
+    dslide = torch.from_numpy(rgb).to(dev)
+    y0, x0 = synth.strip_crop_origin(2, SLIDE, SLIDE, CROP)
+    dcrop = torch.from_numpy(np.ascontiguousarray(rgb[y0:y0 + CROP, x0:x0 + CROP])).to(dev)
+    out = {}
 
-    bf = run_leg(om, torch, dslide, flat_dev, pairs, "bf16", args.steps, args.warmup, args.batch_tiles,
-                 pin=args.pin_config)
-    print(f"# bf16: {bf['ms']:.1f} ms/step, {bf['kept']} kept tiles", file=sys.stderr, flush=True)
-    px = args.size * args.size * len(pairs)
-    result = {
-        "metric": METRIC, "value": px / (bf["ms"] * 1e-3) / 1e6, "unit": UNIT, "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": bf["ms"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
-        "config": {"workload": f"one {args.size}x{args.size} synthetic 40x slide (strip, ~30% tissue), "
-                               "4 scales x 6 classes, 256 tiles at stride 128, foreground tiles only, "
-                               "base-64 5-level residual U-Net + dynamic head, ramp stitch",
-                   "slides": 1, "pairs": len(pairs), "kept_tiles": bf["kept"],
-                   "tflop_per_step": sum(r["flops"] for r in bf["records"]) / args.steps / 1e12},
-        "stages_bf16": stage_summary([dict(r, ms=r["ms"] / args.steps, flops=r["flops"] / args.steps,
-                                           bytes=r["bytes"] / args.steps) for r in bf["records"]]),
-        "roofline": roofline(om, bf["records"], "bf16"),
-        "layers_bf16": layer_summary(bf["records"], args.steps),
-        "autotuned_conv_tiles_bf16": bf["tuned"],
-    }
-    if args.pin_config is not None:
-        result["pinned_conv_config_bf16"] = args.pin_config
-    if args.dump_launches:
-        result["launches_bf16"] = [[r["stage"], r["level"], r["config"]] for r in bf["records"]
-                                   if r["stage"] in ("enc_a", "enc_b", "dec_a", "dec_b")]
-    st = result["stages_bf16"].get("stitch")
-    if st:
-        result["roofline_stitch"] = dict(bound="hbm", achieved=st["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                                         frac=st["gbs"] / HBM_PEAK_GBS, traffic=None)
-    if not args.no_fp32:
-        fp = run_leg(om, torch, dslide, flat_dev, pairs, "fp32", args.fp32_steps, 1, args.batch_tiles)
-        print(f"# fp32: {fp['ms']:.1f} ms/step", file=sys.stderr, flush=True)
-        dices = [M.dice(a, b) for a, b in zip(bf["masks"], fp["masks"])]
-        dis = [M.disagreement(a, b) for a, b in zip(bf["masks"], fp["masks"])]
-        result["fp32"] = {"value": px / (fp["ms"] * 1e-3) / 1e6, "ms_per_step": fp["ms"],
-                          "steps": args.fp32_steps, "roofline": roofline(om, fp["records"], "fp32"),
-                          "autotuned_conv_tiles": fp["tuned"]}
-        result["speedup_bf16_vs_fp32"] = fp["ms"] / bf["ms"]
-        result["bf16_vs_fp32_masks"] = {"dice_min": min(dices), "dice_mean": float(np.mean(dices)),
-                                        "disagreement_max": max(dis)}
-    if args.fp8_steps > 0:
-        f8 = run_leg(om, torch, dslide, flat_dev, pairs, "fp8", args.fp8_steps, 1, args.batch_tiles)
-        print(f"# fp8: {f8['ms']:.1f} ms/step", file=sys.stderr, flush=True)
-        r8 = {"value": px / (f8["ms"] * 1e-3) / 1e6, "ms_per_step": f8["ms"], "steps": args.fp8_steps,
-              "dtype": "fp8 e4m3 (per-channel power-of-two scales), FP32 accumulation",
-              "calibration": f"{f8['calibration_tiles']} first kept tiles on the FP32 path "
-                             f"({f8['calibration_s']:.1f} s)",
-              "roofline": roofline(om, f8["records"], "fp8"), "autotuned_conv_tiles": f8["tuned"],
-              "layers": layer_summary(f8["records"], args.fp8_steps),
-              "speedup_vs_bf16": bf["ms"] / f8["ms"],
-              "stages": stage_summary([dict(r, ms=r["ms"] / args.fp8_steps, flops=r["flops"] / args.fp8_steps,
-                                            bytes=r["bytes"] / args.fp8_steps) for r in f8["records"]])}
-        if "fp32" in result:
-            d8 = [M.dice(a, b) for a, b in zip(f8["masks"], fp["masks"])]
-            r8["fp8_vs_fp32_masks"] = {"dice_min": min(d8), "dice_mean": float(np.mean(d8)),
-                                       "disagreement_max": max(M.disagreement(a, b)
-                                                               for a, b in zip(f8["masks"], fp["masks"]))}
-        result["fp8"] = r8
-    if args.map_reps > 0:
-        result["mapping"] = mapping_leg(om, torch, dslide, flat_dev, args.size, args.map_reps, args.batch_tiles)
-        print(f"# mapping: merge {result['mapping']['merge_ms']:.2f} ms, overlay {result['mapping']['overlay_ms']:.2f} ms",
-              file=sys.stderr, flush=True)
-    if args.paper_steps > 0:
-        result["paper_tiling"] = paper_leg(om, torch, M, dslide, args.size, args.paper_steps, args.batch_tiles)
-        print(f"# paper tiling: {result['paper_tiling']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
-    if args.trained_dice_steps > 0:
-        result["trained_weights_masks"] = trained_dice_leg(om, torch, M, args.trained_dice_steps)
-        print(f"# trained-weights masks: {result['trained_weights_masks']}", file=sys.stderr, flush=True)
+    # 1. training step; its weights feed the precision leg and the CPU oracle
+    wt = None
     if args.train_steps > 0:
-        result["train_step"] = train_leg(om, torch, args.train_steps, 1)
-        print(f"# train: {result['train_step']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
-    if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(rgb, flat, pairs, bf["kept"], args.cpu_seconds)
-    print(json.dumps(result))
+        out["train_step"], wt = train_leg(om, torch, region_rgb, region_gt, args.train_steps)
+        log(f"train: {out['train_step']['ms_per_step']:.1f} ms/step, loss {out['train_step']['loss_first10_last10']}")
+    w_cpu = (wt.cpu().numpy() if wt is not None else flat).astype(np.float32)
+    if proc is not None:
+        np.save(os.path.join(workdir, "weights.tmp.npy"), w_cpu)
+        os.replace(os.path.join(workdir, "weights.tmp.npy"), os.path.join(workdir, "weights.npy"))
+
+    # 2. the headline: 16 slides in one graph-captured call
+    if not args.no_batch16:
+        dslides = [torch.from_numpy(r).to(dev) for r in batch_rgb]
+        del batch_rgb
+        b16 = batch16_leg(om, torch, dslides, specs, flat_dev, args.steps, args.warmup, args.batch_tiles,
+                          args.autotune)
+        del dslides
+        torch.cuda.empty_cache()
+        log(f"16 slides: {b16['graph_ms']:.0f} ms per call, {b16['value']:.0f} {UNIT}")
+
+    # 3. the single 8192^2 slide: BF16, plain FP32, FP8 (He-normal weights)
+    bf = run_leg(om, torch, dslide, flat_dev, PAIRS, "bf16", args.slide_steps, 1, args.batch_tiles)
+    fp = run_leg(om, torch, dslide, flat_dev, PAIRS, "fp32", args.fp32_steps, 1, args.batch_tiles)
+    px1 = SLIDE * SLIDE * len(PAIRS)
+    fp32_value = px1 / (fp["ms"] * 1e-3) / 1e6
+    log(f"slide: bf16 {bf['ms']:.1f} ms, fp32 {fp['ms']:.1f} ms")
+    slide = {"workload": f"one {SLIDE}x{SLIDE} synthetic 40x slide (strip, ~30% tissue), 4 scales x 6 classes, "
+                         "256 tiles at stride 128, foreground tiles only, base-64 5-level U-Net + dynamic head, "
+                         "ramp stitch; He-normal weights (seed 12)",
+             "kept_tiles": bf["kept"],
+             "bf16": {"value": px1 / (bf["ms"] * 1e-3) / 1e6, "ms_per_step": bf["ms"], "steps": args.slide_steps,
+                      "stages": stage_summary(bf["records"]), "roofline": roofline(om, bf["records"], "bf16"),
+                      "conv_tiles": bf["tuned"]},
+             "fp32_plain": {"value": fp32_value, "ms_per_step": fp["ms"], "steps": args.fp32_steps,
+                            "roofline": roofline(om, fp["records"], "fp32"), "conv_tiles": fp["tuned"]},
+             "speedup_bf16_vs_fp32": fp["ms"] / bf["ms"],
+             "bf16_vs_fp32_masks_he_normal": {
+                 "dice_min": min(M.dice(a, b) for a, b in zip(bf["masks"], fp["masks"])),
+                 "disagreement_max": max(M.disagreement(a, b) for a, b in zip(bf["masks"], fp["masks"]))}}
+    if args.fp8_steps > 0:
+        f8 = run_leg(om, torch, dslide, flat_dev, PAIRS, "fp8", args.fp8_steps, 1, args.batch_tiles)
+        slide["fp8"] = {"value": px1 / (f8["ms"] * 1e-3) / 1e6, "ms_per_step": f8["ms"], "steps": args.fp8_steps,
+                        "dtype": "fp8 e4m3 (per-channel power-of-two scales), FP32 accumulation",
+                        "calibration": f"{f8['calibration_tiles']} first kept tiles on the FP32 path",
+                        "roofline": roofline(om, f8["records"], "fp8"), "speedup_vs_bf16": bf["ms"] / f8["ms"],
+                        "stages": stage_summary(f8["records"])}
+        log(f"slide: fp8 {f8['ms']:.1f} ms")
+    out["slide"] = slide
+
+    # 4. precision with trained weights (GPU side)
+    crop = None
+    if not args.no_precision and wt is not None:
+        out["precision"], crop = precision_gpu(om, torch, M, dslide, dcrop, wt, args.batch_tiles)
+        log("precision: GPU side done")
+
+    # 5. the paper's tiling, and mapping
+    if args.paper_steps > 0:
+        out["paper_tiling"] = paper_leg(om, torch, M, dslide, SLIDE, args.paper_steps, args.batch_tiles)
+        log(f"paper tiling: {out['paper_tiling']['ms_per_step']:.1f} ms/step")
+    if args.map_reps > 0:
+        out["mapping"] = mapping_leg(om, torch, dslide, flat_dev, SLIDE, args.map_reps, args.batch_tiles)
+        log(f"mapping: merge {out['mapping']['merge_ms']:.2f} ms, overlay {out['mapping']['overlay_ms']:.2f} ms")
+
+    # 6. the CPU oracle: cpu_baseline and the FP64 crop
+    cpu = None
+    if proc is not None:
+        log("waiting for the CPU oracle")
+        cpu, ref = finish_cpu_baseline(proc, workdir, 1500)
+        log("CPU oracle done" if cpu else "CPU oracle failed")
+        if cpu and crop is not None:
+            out["precision"].update({"crop": f"{CROP}x{CROP} window at {list(synth.strip_crop_origin(2, SLIDE, SLIDE, CROP))} "
+                                             "of the slide, a stand-alone slide (60 tiles over 4 scales)"})
+            out["precision"].update(precision_vs_oracle(M, crop, ref))
+
+    # the JSON line
+    if not args.no_batch16:
+        head = b16
+        value, ms, cfgd = b16["value"], b16["graph_ms"], {
+            "workload": b16["workload"], "slides": 16, "pairs": len(PAIRS), "kept_tiles": b16["kept_tiles"],
+            "gigapixels_40x": b16["gigapixels_40x"], "tflop_per_step": b16["tflop_per_step"]}
+        steps, warm = args.steps, args.warmup
+    else:
+        head = None
+        value, ms, cfgd = slide["bf16"]["value"], bf["ms"], {"workload": slide["workload"], "slides": 1,
+                                                            "pairs": len(PAIRS), "kept_tiles": bf["kept"]}
+        steps, warm = args.slide_steps, 1
+    result = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": steps, "warmup": warm,
+              "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "dtype": "bf16", "data": "synthetic", "config": cfgd,
+              "roofline": head["roofline"] if head else slide["bf16"]["roofline"],
+              "fp32_plain": {"value": fp32_value, "workload": f"the single {SLIDE}^2 slide, FP32 backbone",
+                             "bf16_batched_over_fp32_plain": value / fp32_value}}
+    prec = out.get("precision", {})
+    if "bf16_vs_fp64" in prec:
+        q = prec["bf16_vs_fp64"]
+        result["qualifier"] = {"dice_target": 0.999, "bf16_dice_min_vs_fp64": q["dice_min"],
+                               "bf16_at_risk_max": q["at_risk_max"],
+                               "bf16_logit_error_normwise": q["logit_error_normwise_max"],
+                               "met": q["dice_min"] >= 0.999,
+                               "on": f"the {CROP}^2 crop, trained weights ({args.train_steps} steps)"}
+    if head:
+        result["batch16"] = {k: v for k, v in head.items() if k not in ("roofline",)}
+    result.update(out)
+    if cpu:
+        result["cpu_baseline"] = cpu
+    return result
 
 
 if __name__ == "__main__":
