@@ -703,6 +703,388 @@ void k_conv3x3_rows(ConvArgs a) {
   }
 }
 
+// Direct global -> LDS staging of one BF16 chunk for k_conv3x3_rows2: buffer
+// loads with the LDS bit write 64 consecutive 16-byte LDS slots per wave
+// instruction, lane l the slot 64 j + l of group j, so each lane loads the
+// vector that belongs in its slot under the rotated layout of vslot<true>
+// (slot 4 p + s of row p holds vector (s - (p >> 1)) & 3).  Wave w issues
+// groups w, w + NWAVE, ...; the halo groups come first (padded to whole
+// groups; slots past the halo, and pixels outside the image, load zeros
+// through an offset outside the buffer range), then the weight groups.  The
+// loads complete asynchronously (vmcnt); a wait and a barrier make the
+// chunk visible.
+template <int LOADER, int NPIX, int BN, int NT>
+struct DmaStager {
+  using T = uint16_t;
+  static constexpr int KC = 32, NV = 4, VEC = 8, PX = 18;
+  static constexpr int HALO_G = (NPIX * NV + 63) / 64;
+  static constexpr int W_G = 9 * BN * NV / 64;
+  static constexpr int NWAVE = NT / 64;
+  static constexpr int GPW = (HALO_G + W_G + NWAVE - 1) / NWAVE;
+  static constexpr int X_ELEMS = HALO_G * 64 * VEC;  // halo region of a stage (elements)
+  static constexpr int STAGE = X_ELEMS + 9 * BN * KC;
+  static_assert(9 * BN * NV % 64 == 0, "whole weight groups");
+  static_assert(LOADER != LOAD_POOL, "the pooled loader reduces in registers");
+  const T* x0b;
+  const T* x1b;
+  uint32_t bytes0, bytes1;
+  uint32_t o0[GPW], o1[GPW];  // halo: offsets in source 0 and 1; weights: offset in o0
+  int cu_p, cin_p, chunk_w, wave;
+
+  __device__ __forceinline__ DmaStager(const ConvArgs& a, int b, int wave_, int lane, int y0, int x0, int n0) {
+    const int H = a.H, W = a.W;
+    wave = wave_;
+    cu_p = a.cu_p;
+    cin_p = a.cin_p;
+    chunk_w = 9 * a.cout_p * KC;
+    const int64_t tile0 =
+        LOADER == LOAD_UPCAT ? (int64_t)(H >> 1) * (W >> 1) * a.cu_p : (int64_t)H * W * a.cin_p;
+    x0b = (const T*)a.x0 + (int64_t)b * tile0;
+    bytes0 = (uint32_t)(tile0 * sizeof(T));
+    const int64_t tile1 = (int64_t)H * W * (a.cin_p - a.cu_p);
+    x1b = LOADER == LOAD_UPCAT ? (const T*)a.x1 + (int64_t)b * tile1 : nullptr;
+    bytes1 = (uint32_t)(tile1 * sizeof(T));
+#pragma unroll
+    for (int i = 0; i < GPW; ++i) {
+      const int j = wave + i * NWAVE;
+      o0[i] = o1[i] = kOutside;
+      if (j < HALO_G) {
+        const int sl = 64 * j + lane, p = sl >> 2;
+        const uint32_t vb = (uint32_t)((((sl & 3) - (p >> 1)) & 3) * VEC * sizeof(T));
+        const int y = y0 + p / PX - 1, x = x0 + p % PX - 1;
+        const bool in = p < NPIX && y >= 0 && y < H && x >= 0 && x < W;
+        if (LOADER == LOAD_UPCAT) {
+          o0[i] = in ? (uint32_t)(((y >> 1) * (W >> 1) + (x >> 1)) * a.cu_p) * sizeof(T) + vb : kOutside;
+          o1[i] = in ? (uint32_t)((y * W + x) * (a.cin_p - a.cu_p)) * sizeof(T) + vb : kOutside;
+        } else {
+          o0[i] = in ? (uint32_t)((y * W + x) * a.cin_p) * sizeof(T) + vb : kOutside;
+        }
+      } else if (j < HALO_G + W_G) {
+        const int sl = 64 * (j - HALO_G) + lane, r = sl >> 2;
+        const int v = ((sl & 3) - (r >> 1)) & 3;
+        const int tap = r / BN, n = r % BN;
+        o0[i] = (uint32_t)(((tap * a.cout_p + n0 + n) * KC + v * VEC) * sizeof(T));
+      }
+    }
+  }
+
+  // Loads of chunk ch into the stage at `stage` (an LDS array).
+  __device__ __forceinline__ void issue(const ConvArgs& a, int ch, T* stage) const {
+    const int c = ch * KC;
+    const bool second = LOADER == LOAD_UPCAT && c >= cu_p;
+    const __amdgpu_buffer_rsrc_t rh =
+        second ? buffer_rsrc(x1b + (c - cu_p), bytes1 - (uint32_t)((c - cu_p) * sizeof(T)))
+               : buffer_rsrc(x0b + c, bytes0 - (uint32_t)(c * sizeof(T)));
+    const __amdgpu_buffer_rsrc_t rw = buffer_rsrc((const T*)a.w + (int64_t)ch * chunk_w, (uint32_t)(chunk_w * sizeof(T)));
+#pragma unroll
+    for (int i = 0; i < GPW; ++i) {
+      const int j = wave + i * NWAVE;
+      if (j < HALO_G) {
+        // a blend rather than a select of the two arrays, which would keep
+        // the stager out of registers
+        const uint32_t off = o0[i] + ((o1[i] - o0[i]) & (0u - (uint32_t)second));
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rh, (__attribute__((address_space(3))) void*)(stage + j * 64 * VEC),
+                                                 16, (int)off, 0, 0, 0);
+      } else if (j < HALO_G + W_G) {
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rw, (__attribute__((address_space(3))) void*)(stage + X_ELEMS + (j - HALO_G) * 64 * VEC), 16, (int)o0[i],
+            0, 0, 0);
+      }
+    }
+  }
+};
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Lane byte offsets of the MFMA operand reads of k_conv3x3_rows2 inside a
+// stage.  A halo read of fragment row r at horizontal offset dx addresses
+// pixel px = xrow + r PX + dx at slot (g + (px >> 1)) & 3 of its 64-byte row;
+// with PX = 18 and FM even that slot is (c_dx + r) & 3, so the reads of rows
+// r and r + 4 differ by the constant 4 PX 64 bytes and twelve per-lane bases
+// xo[dx][r % 4] cover every read.  A weight read of row wr = tap BN + wrow +
+// 16 fn has slot (g + (l16 >> 1)) & 3 for every tap and fragment (BN and NW
+// multiples of 8), so one base wo covers them.  Writing the addresses this
+// way keeps the compiler from holding one address register per read.
+struct RowsOffsets {
+  uint32_t xo[3][4];
+  uint32_t wo;
+};
+
+template <int FM>
+__device__ __forceinline__ RowsOffsets rows_offsets(int xrow, int wrow, int g, int l16, int wm) {
+  constexpr int PX = 18;
+  RowsOffsets o;
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx) {
+    const int c = g + wm * FM + ((l16 + dx) >> 1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o.xo[dx][k] = (uint32_t)((xrow + k * PX + dx) * 64 + ((c + k) & 3) * 16);
+  }
+  o.wo = (uint32_t)(wrow * 64 + ((g + (l16 >> 1)) & 3) * 16);
+  return o;
+}
+
+// Operand reads of horizontal offset dx of one chunk: the FM + 2 halo rows
+// and the weights of the three taps (dy = 0..2) of that offset, issued in
+// the order the MFMAs of rows_mfma consume them (the weights of tap dy
+// before the first row that tap adds), so the first MFMA of a chunk waits
+// for three reads, not the whole group.
+template <int FM, int FN, int BN>
+__device__ __forceinline__ void rows_load(uint4 (&xv)[FM + 2], uint4 (&wv)[3][FN], const char* sX, const char* sW,
+                                          const RowsOffsets& o, int dx) {
+  constexpr int PX = 18;
+  auto row = [&](int r) { xv[r] = *reinterpret_cast<const uint4*>(sX + o.xo[dx][r & 3] + (r >> 2) * (4 * PX * 64)); };
+  auto wts = [&](int dy) {
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+      wv[dy][fn] = *reinterpret_cast<const uint4*>(sW + o.wo + ((dy * 3 + dx) * BN + fn * 16) * 64);
+  };
+  wts(0);
+#pragma unroll
+  for (int r = 0; r < FM; ++r) row(r);
+  wts(1);
+  row(FM);
+  wts(2);
+  row(FM + 1);
+}
+
+template <int FM, int FN>
+__device__ __forceinline__ void rows_mfma(f32x4 (&acc)[FM][FN], const uint4 (&xv)[FM + 2], const uint4 (&wv)[3][FN]) {
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn) mma(acc[fm][fn], wv[dy][fn], xv[fm + dy], uint16_t());
+}
+
+// Interleave the MFMAs of a group with the operand reads of the next one:
+// `reads` groups of (MFMAs, one LDS read).
+template <int MFMAS, int READS>
+__device__ __forceinline__ void interleave_reads() {
+  constexpr int PER = MFMAS / READS;
+#pragma unroll
+  for (int i = 0; i < READS; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, PER, 0);  // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);    // LDS read
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, MFMAS - PER * READS, 0);
+}
+
+// One chunk of the row-reuse MFMA loop (k_conv3x3_rows's order: dx, then
+// dy, then the fragments) from a stage whose halo starts at sX and whose
+// weights start at sW (byte pointers into LDS).  The reads of offset dx + 1
+// go into a second register set while the MFMAs of offset dx issue.
+template <int FM, int FN, int BN>
+__device__ __forceinline__ void rows_chunk(f32x4 (&acc)[FM][FN], const char* sX, const char* sW,
+                                           const RowsOffsets& o) {
+  static_assert(BN % 8 == 0, "weight reads share one slot rotation");
+  constexpr int NM = 3 * FM * FN, NR = FM + 2 + 3 * FN;
+  uint4 xa[FM + 2], xb[FM + 2];
+  uint4 wa[3][FN], wb[3][FN];
+  rows_load<FM, FN, BN>(xa, wa, sX, sW, o, 0);
+  __builtin_amdgcn_sched_barrier(0);
+  rows_load<FM, FN, BN>(xb, wb, sX, sW, o, 1);
+  rows_mfma<FM, FN>(acc, xa, wa);
+  interleave_reads<NM, NR>();
+  __builtin_amdgcn_sched_barrier(0);
+  rows_load<FM, FN, BN>(xa, wa, sX, sW, o, 2);
+  rows_mfma<FM, FN>(acc, xb, wb);
+  interleave_reads<NM, NR>();
+  __builtin_amdgcn_sched_barrier(0);
+  rows_mfma<FM, FN>(acc, xa, wa);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// BF16 row-reuse form for large blocks: BY rows x 16 pixels x BN channels
+// with eight waves, one workgroup per CU.  The compute of a chunk is
+// k_conv3x3_rows's (same taps, same order, same MFMAs), so the results are
+// bit for bit those of the smaller blocks.  The staging is double-buffered
+// in LDS, one barrier per chunk: the plain and upsampling loaders load the
+// next chunk straight into the other buffer (DmaStager) while this one is
+// computed; the pooling loader, which reduces four raw vectors per halo
+// vector, goes through registers and writes the other buffer after this
+// chunk's MFMAs are issued.  The epilogue works on the accumulators in
+// registers (each lane holds four consecutive channels of one pixel) and
+// writes 8-byte pieces of the output, with no LDS staging; the 2x2 max-pool
+// takes the vertical pair from the lane's own rows and the horizontal one
+// from the neighbouring lane.
+template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
+__global__ __launch_bounds__(64 * WM * WN, 2) void k_conv3x3_rows2(ConvArgs a) {
+  using T = uint16_t;
+  using TR = ConvTraits<T>;
+  constexpr int KC = TR::KC, VEC = TR::VEC;
+  constexpr int NV = KC / VEC;
+  constexpr int ROW = KC;
+  constexpr int BX = 16, PX = BX + 2, NPIX = (BY + 2) * PX;
+  constexpr int FM = BY / WM;
+  constexpr int NW = BN / WN, FN = NW / 16;
+  constexpr int NT = 64 * WM * WN;
+  static_assert(WM * WN == 8 && BY % WM == 0 && NW % 16 == 0 && FM % 2 == 0, "wave layout");
+  static_assert(PX == 18 && ROW * (int)sizeof(T) == 64, "rows_offsets assumes 18-pixel halo rows of 64 bytes");
+  constexpr bool DMA = LOADER != LOAD_POOL;
+  using DS = DmaStager<DMA ? LOADER : LOAD_PLAIN, NPIX, BN, NT>;
+  constexpr int XR = DMA ? DS::X_ELEMS : NPIX * ROW;  // halo region of a stage (elements)
+  constexpr int STAGE = XR + 9 * BN * ROW;
+  static_assert(2 * STAGE * (int)sizeof(T) <= 160 * 1024, "two staging buffers fit the LDS");
+  // two arrays, so that the LDS accesses of either stage are known not to
+  // touch the other
+  __shared__ __attribute__((aligned(16))) T sA[STAGE];
+  __shared__ __attribute__((aligned(16))) T sB[STAGE];
+
+  int rest = xcd_remap(blockIdx.x, gridDim.x);
+  const int nb = rest % a.n_nblk;
+  rest /= a.n_nblk;
+  const int sxb = rest % a.tiles_x;
+  rest /= a.tiles_x;
+  const int syb = rest % a.tiles_y;
+  const int b = rest / a.tiles_y;
+  if (a.chunk_base + b >= *a.count) return;
+  const int y0 = syb * BY, x0 = sxb * BX, n0 = nb * BN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WN, wn = wave % WN;
+  const int g = lane >> 4;
+  const int l16 = lane & 15;
+  const int xrow = wm * FM * PX + l16;
+  const int wrow = wn * NW + l16;
+  const RowsOffsets ro = rows_offsets<FM>(xrow, wrow, g, l16, wm);
+  const char* cA = reinterpret_cast<const char*>(sA);
+  const char* cB = reinterpret_cast<const char*>(sB);
+  constexpr int XB = XR * (int)sizeof(T);  // bytes of a stage's halo region
+
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nchunks = a.cin_p / KC;
+  if constexpr (DMA) {
+    const DS ds(a, b, wave, lane, y0, x0, n0);
+    ds.issue(a, 0, sA);
+    wait_vmem();
+    __syncthreads();
+    // chunk ch is in sA for even ch, in sB for odd ch
+    for (int ch = 0; ch < nchunks; ch += 2) {
+      if (ch + 1 < nchunks) ds.issue(a, ch + 1, sB);
+      if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(1);
+      rows_chunk<FM, FN, BN>(acc, cA, cA + XB, ro);
+      if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(0);
+      wait_vmem();
+      __syncthreads();
+      if (ch + 1 >= nchunks) break;
+      if (ch + 2 < nchunks) ds.issue(a, ch + 2, sA);
+      if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(1);
+      rows_chunk<FM, FN, BN>(acc, cB, cB + XB, ro);
+      if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(0);
+      wait_vmem();
+      __syncthreads();
+    }
+  } else {
+    constexpr int HALO_V = NPIX * NV, W_V = 9 * BN * NV;
+    constexpr int HPT = (HALO_V + NT - 1) / NT, WPT = (W_V + NT - 1) / NT;
+    constexpr int LPV = (LOADER == LOAD_POOL) ? 4 : 1;
+    uint4 hreg[HPT][LPV];
+    uint4 wreg[WPT];
+    using ST = RowStager<T, LOADER, HALO_V, W_V, LPV, NV, VEC, KC, ROW, PX, BN, true, NT>;
+    const ST st(a, b, tid, y0, x0, n0);
+    st.fetch(a, 0, hreg, wreg);
+    ST::commit(tid, hreg, wreg, sA, sA + XR);
+    st.fetch(a, min(1, nchunks - 1), hreg, wreg, nchunks > 1);
+    __syncthreads();
+    for (int ch = 0; ch < nchunks; ch += 2) {
+      // chunk ch + 1 (fetched during the previous pass) goes into the other
+      // stage, which every wave finished reading before the last barrier;
+      // then the loads of chunk ch + 2 (empty past the last chunk)
+      rows_chunk<FM, FN, BN>(acc, cA, cA + XB, ro);
+      ST::commit(tid, hreg, wreg, sB, sB + XR);
+      st.fetch(a, min(ch + 2, nchunks - 1), hreg, wreg, ch + 2 < nchunks);
+      __syncthreads();
+      if (ch + 1 >= nchunks) break;
+      rows_chunk<FM, FN, BN>(acc, cB, cB + XB, ro);
+      ST::commit(tid, hreg, wreg, sA, sA + XR);
+      st.fetch(a, min(ch + 3, nchunks - 1), hreg, wreg, ch + 3 < nchunks);
+      __syncthreads();
+    }
+  }
+
+  // Epilogue on the accumulators: lane (g, l16) of fragment (fm, fn) holds
+  // channels c .. c + 3 of pixel (y0 + wm FM + fm, x0 + l16).
+  T* out = (T*)a.y;
+  const T* res = (const T*)a.x0;
+  const int x = x0 + l16;
+#pragma unroll
+  for (int fn = 0; fn < FN; ++fn) {
+    const int c = n0 + wn * NW + fn * 16 + g * 4;
+    float4 bb = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (EPI == EPI_RELU || EPI == EPI_RES_RELU) bb = *reinterpret_cast<const float4*>(a.bias + c);
+#pragma unroll
+    for (int fm = 0; fm < FM; fm += 2) {
+      float v[2][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int y = y0 + wm * FM + fm + h;
+        const int64_t o = (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + c;
+        const f32x4 s = acc[fm + h][fn];
+        float* vv = v[h];
+        vv[0] = s[0];
+        vv[1] = s[1];
+        vv[2] = s[2];
+        vv[3] = s[3];
+        if (EPI == EPI_RELU || EPI == EPI_RES_RELU) {
+          vv[0] += bb.x;
+          vv[1] += bb.y;
+          vv[2] += bb.z;
+          vv[3] += bb.w;
+        }
+        if (EPI == EPI_RES_RELU || EPI == EPI_RES_MASK) {
+          const uint2 r = *reinterpret_cast<const uint2*>(res + o);
+          vv[0] += bf2f(r.x & 0xffff);
+          vv[1] += bf2f(r.x >> 16);
+          vv[2] += bf2f(r.y & 0xffff);
+          vv[3] += bf2f(r.y >> 16);
+        }
+        if (EPI == EPI_RES_MASK) {
+          const uint2 q = *reinterpret_cast<const uint2*>((const T*)a.aux + o);
+          if (!(bf2f(q.x & 0xffff) > 0.f)) vv[0] = 0.f;
+          if (!(bf2f(q.x >> 16) > 0.f)) vv[1] = 0.f;
+          if (!(bf2f(q.y & 0xffff) > 0.f)) vv[2] = 0.f;
+          if (!(bf2f(q.y >> 16) > 0.f)) vv[3] = 0.f;
+        }
+        if (EPI == EPI_RELU || EPI == EPI_RES_RELU) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) vv[j] = fmaxf(vv[j], 0.f);
+        }
+        uint2 u;
+        u.x = (uint32_t)f2bf(vv[0]) | ((uint32_t)f2bf(vv[1]) << 16);
+        u.y = (uint32_t)f2bf(vv[2]) | ((uint32_t)f2bf(vv[3]) << 16);
+        *reinterpret_cast<uint2*>(out + o) = u;
+      }
+      if (a.pool_out) {
+        // rows y and y + 1 (y even: y0, wm FM and fm are even) in this lane,
+        // columns x and x ^ 1 in lanes l16 and l16 ^ 1; max commutes with the
+        // monotonic BF16 rounding, so this is the pool of the stored output
+        float m[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float t = fmaxf(v[0][j], v[1][j]);
+          m[j] = fmaxf(t, __shfl_xor(t, 1));
+        }
+        if ((l16 & 1) == 0) {
+          const int py = (y0 + wm * FM + fm) >> 1, px = x >> 1;
+          const int64_t o = (((int64_t)b * (a.H >> 1) + py) * (a.W >> 1) + px) * a.cout_p + c;
+          uint2 u;
+          u.x = (uint32_t)f2bf(m[0]) | ((uint32_t)f2bf(m[1]) << 16);
+          u.y = (uint32_t)f2bf(m[2]) | ((uint32_t)f2bf(m[3]) << 16);
+          *reinterpret_cast<uint2*>((T*)a.pool_out + o) = u;
+        }
+      }
+    }
+  }
+}
+
 // FP8 (E4M3) row-reuse form on v_mfma_scale_f32_32x32x64_f8f6f4 (unit block
 // scales): one MFMA is one tap of a 64-channel chunk for 32 output channels
 // (A, weights) x 32 pixels (B).  A pixel fragment is two 16-pixel rows; lane
@@ -963,6 +1345,35 @@ static hipError_t launch_conv_rows_t(const ConvLayer& L, int H, int W, int batch
   return hipGetLastError();
 }
 
+template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
+static hipError_t launch_conv_rows2_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
+                                      int chunk_base, const void* x0, const void* x1, const void* aux,
+                                      void* y, hipStream_t st) {
+  ConvArgs a{};
+  a.x0 = x0;
+  a.x1 = x1;
+  a.aux = aux;
+  a.y = y;
+  a.w = L.w;
+  a.bias = L.b;
+  a.H = H;
+  a.W = W;
+  a.cin_p = L.cin_p;
+  a.cu_p = L.cu_p;
+  a.cout_p = L.cout_p;
+  a.count = count;
+  a.chunk_base = chunk_base;
+  a.tiles_y = H / BY;
+  a.tiles_x = W / 16;
+  a.n_nblk = L.cout_p / BN;
+  a.pool_out = L.pool_out;
+  if (L.pool_out && EPI != EPI_RES_RELU) return hipErrorInvalidValue;
+  const int64_t blocks = (int64_t)batch * a.tiles_y * a.tiles_x * a.n_nblk;
+  hipLaunchKernelGGL((k_conv3x3_rows2<BY, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks), dim3(64 * WM * WN), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
 template <typename T, int BY, int BX, int BN, int WM, int WN, int LOADER, int EPI>
 static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
                                 int chunk_base, const void* x0, const void* x1, const void* aux,
@@ -994,7 +1405,7 @@ static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, con
 
 // Tile configurations: pixel block BY x BX, BN output channels, and the
 // 4-wave layout WM x WN (each wave owns (BY BX / WM) x (BN / WN) outputs).
-#define OMNISEG_CONV_CONFIGS(X)  \
+#define OMNISEG_CONV_TILE_CONFIGS(X)  \
   X(CONV_CFG_8x16_32, 8, 16, 32, 4, 1)    \
   X(CONV_CFG_8x16_64, 8, 16, 64, 2, 2)    \
   X(CONV_CFG_16x16_64, 16, 16, 64, 4, 1)  \
@@ -1009,10 +1420,13 @@ static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, con
   X(CONV_CFG_ROWS_16x16_32, 16, 16, 32, 4, 1)
 // Eight-wave row-reuse configuration (BF16 only)
 #define OMNISEG_CONV_ROW8_CONFIGS(X) X(CONV_CFG_ROWS8_16x16_64, 16, 16, 64, 4, 2)
+// Eight-wave large-block row-reuse configuration (BF16 only; k_conv3x3_rows2)
+#define OMNISEG_CONV_ROW2_CONFIGS(X) X(CONV_CFG_ROWS2_32x16_64, 32, 16, 64, 4, 2)
 
 static const int kCfgShape[][5] = {
 #define OMNISEG_SHAPE(id, by, bx, bn, wm, wn) {by, bx, bn, wm, wn},
-    OMNISEG_CONV_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW8_CONFIGS(OMNISEG_SHAPE)
+    OMNISEG_CONV_TILE_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW8_CONFIGS(OMNISEG_SHAPE)
+        OMNISEG_CONV_ROW2_CONFIGS(OMNISEG_SHAPE)
 #undef OMNISEG_SHAPE
 };
 static_assert(sizeof(kCfgShape) / sizeof(kCfgShape[0]) == CONV_CFG_COUNT, "one shape per configuration");
@@ -1039,7 +1453,9 @@ bool conv_config_valid(int cfg, int precision, int H, int W, int cout_p) {
 }
 
 int conv_default_config(int precision, int H, int W, int cout_p) {
-  const int order_bf16[] = {CONV_CFG_16x16_64, CONV_CFG_8x16_64, CONV_CFG_8x16_32, CONV_CFG_8x8_64, CONV_CFG_8x8_32};
+  // row-reuse forms first (the training path runs these defaults untuned)
+  const int order_bf16[] = {CONV_CFG_ROWS8_16x16_64, CONV_CFG_ROWS_16x16_64, CONV_CFG_ROWS_16x16_32, CONV_CFG_16x16_64,
+                            CONV_CFG_8x16_64, CONV_CFG_8x16_32, CONV_CFG_8x8_64, CONV_CFG_8x8_32};
   const int order_f32[] = {CONV_CFG_8x16_64, CONV_CFG_8x16_32, CONV_CFG_8x8_64, CONV_CFG_8x8_32};
   const int order_fp8[] = {CONV_CFG_ROWS_16x16_64, CONV_CFG_ROWS_16x16_32};
   if (precision == OMNISEG_FP8) {
@@ -1063,7 +1479,7 @@ static hipError_t launch_conv_cfg(int cfg, const ConvLayer& L, int H, int W, int
 #define OMNISEG_CASE(id, by, bx, bn, wm, wn) \
   case id:                                   \
     return launch_conv_t<T, by, bx, bn, wm, wn, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
-    OMNISEG_CONV_CONFIGS(OMNISEG_CASE)
+    OMNISEG_CONV_TILE_CONFIGS(OMNISEG_CASE)
 #undef OMNISEG_CASE
     default:
       break;
@@ -1075,6 +1491,11 @@ static hipError_t launch_conv_cfg(int cfg, const ConvLayer& L, int H, int W, int
     return launch_conv_rows_t<by, bn, wm, wn, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
       OMNISEG_CONV_ROW_CONFIGS(OMNISEG_CASE)
       OMNISEG_CONV_ROW8_CONFIGS(OMNISEG_CASE)
+#undef OMNISEG_CASE
+#define OMNISEG_CASE(id, by, bx, bn, wm, wn) \
+  case id:                                   \
+    return launch_conv_rows2_t<by, bn, wm, wn, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+      OMNISEG_CONV_ROW2_CONFIGS(OMNISEG_CASE)
 #undef OMNISEG_CASE
       default:
         break;

@@ -171,6 +171,46 @@ def test_every_tile_configuration(prec, config, mode):
                                   for g, a in zip(G, A)], prec)
 
 
+@pytest.mark.parametrize("mode", ["relu", "res", "pool_out", "upcat", "pool_in", "dgrad", "dgrad_res"])
+def test_large_block_form_equals_row_reuse_bit_for_bit(mode):
+    """The double-buffered large-block form (32 rows x 16 pixels x 64
+    channels, register epilogue) sums the same taps of the same chunks in
+    the same order as the eight-wave row-reuse form, so its outputs, and the
+    fused pooled copy, equal that form's bit for bit: here over 6 chunks,
+    two channel blocks and several pixel blocks per tile."""
+    big, ref_cfg = 11, 10
+    assert om.conv_config_info(big)[:5] == (32, 16, 64, 4, 2) and om.conv_config_info(ref_cfg)[:5] == (16, 16, 64, 4, 2)
+    rng = np.random.default_rng(seed_of("large-block", mode))
+    n, H, W, C = 3, 64, 96, 128
+    dev = lambda a: torch.from_numpy(np.asarray(a, np.float32)).to(DEV)
+    Wt = q(rng.standard_normal((C, 192 if mode == "upcat" else C, 3, 3)) * np.sqrt(2.0 / (9 * C)), om.BF16)
+    b = dev(rng.standard_normal(C) * 0.1)
+    kw = {}
+    if mode == "upcat":
+        x0 = to_nhwc([q(rng.standard_normal((128, H // 2, W // 2)), om.BF16) for _ in range(n)], om.BF16)
+        kw = dict(x1=to_nhwc([q(rng.standard_normal((64, H, W)), om.BF16) for _ in range(n)], om.BF16), cu=128)
+        m = om.CONV_UPCAT_RELU
+    elif mode == "pool_in":
+        x0 = to_nhwc([q(np.abs(rng.standard_normal((C, 2 * H, 2 * W))), om.BF16) for _ in range(n)], om.BF16)
+        m = om.CONV_POOL_RELU
+    else:
+        x0 = to_nhwc([q(rng.standard_normal((C, H, W)), om.BF16) for _ in range(n)], om.BF16)
+        m = {"relu": om.CONV_RELU, "res": om.CONV_RES_RELU, "pool_out": om.CONV_RES_RELU,
+             "dgrad": om.CONV_DGRAD, "dgrad_res": om.CONV_DGRAD_RES_MASK}[mode]
+        if mode == "dgrad_res":
+            kw = dict(aux=to_nhwc([q(rng.standard_normal((C, H, W)), om.BF16) for _ in range(n)], om.BF16))
+    pool = mode == "pool_out"
+    outs = []
+    for cfg in (ref_cfg, big):
+        r = om.conv3x3(om.BF16, m, x0, dev(Wt), None if mode.startswith("dgrad") else b, config=cfg, pool=pool,
+                       height=H, width=W, **kw)
+        outs.append(r if pool else (r,))
+    torch.cuda.synchronize()
+    for a, c in zip(outs[0], outs[1]):
+        assert torch.equal(a.view(torch.int16), c.view(torch.int16))
+    assert outs[0][0].float().abs().sum() > 0
+
+
 # ------------------------------------------------------------------ FP8 (E4M3)
 
 def _e4m3_values():
