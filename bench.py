@@ -58,42 +58,43 @@ REGION = 2048         # training region (slide seed 3, with ground truth)
 TRAIN_LR = 1e-3       # Adam, cosine decay to 0 over the steps
 TRAIN_BATCH = 32
 
-# HBM bytes per launch of the BF16 conv kernels that can dominate this
-# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
-#   bench.py --steps 1 --warmup 0 --no-fp32 --no-cpu --train-steps 0 --fp8-steps 0 --paper-steps 0
-#            --map-reps 0 --copy-gib 1
-# over each kernel's launches in the timed step, each counter scaled by its
-# reading for the 1 GiB device copy that command makes first (FETCH_SIZE read
-# 0.5 GiB, WRITE_SIZE 1 GiB).  They describe the conv source whose SHA-256 is
-# stored here; any other source, or another kernel, reports null.
+# HBM bytes of one launch of each conv layer of the bench network on a full
+# batch of 256 tiles, with the configuration BENCH_CONV_TABLE pins, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE) of
+#   bench.py --counters
+# summarised by bench.py --summarize-counters: each counter scaled by its
+# reading for the 1 GiB device copy the command makes first.  They describe
+# the conv source whose SHA-256 is stored here; any other source reports
+# null.
 MEASURED_TRAFFIC = {
-    "conv_source_sha256": "9373b094653b0de5bd22e6ae2ba30ace2a78156783c8f23b0799b6618e01ffc7",
-    # bytes per launch of each layer (stage + level) for the kernels that can
-    # dominate the BF16 step: FETCH_SIZE x 2 and WRITE_SIZE x 1 (scales from a
-    # 1 GiB device copy), over the 8 tile batches of one step
+    "conv_source_sha256": "d58682a5ef8d0a5e299575fc1249cb45a78dadd0420dd2cece464fce2071eab9",
+    "batch": 256,
+    # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000) bytes of one full-batch launch per layer
     "kernels": {
+        "omniseg::k_conv3x3_rows2<32, 64, 4, 2, 2, 0>": {
+            "dec_a1": (2004806672, 1088543968),
+            "dec_a2": (1711742802, 541514272),
+            "dec_a3": (2215041415, 268934400),
+        },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 0>": {
-            "enc_a1": (492553859, 982515712),
-            "enc_a2": (250478734, 491257856),
-            "enc_a3": (216487558, 245628928),
-            "enc_a4": (1149381933, 122814464),
+            "enc_a1": (538147984, 1073741824),
+            "enc_a2": (273263914, 536870912),
+            "enc_a3": (246497821, 268435456),
+            "enc_a4": (1394219953, 134217728),
         },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 1>": {
-            "dec_b0": (1986183956, 1965031424),
-            "dec_b1": (1027233028, 982515712),
-            "dec_b2": (760075083, 491257856),
-            "dec_b3": (1485243558, 245628928),
-            "enc_b0": (2001483692, 2456289280),
-            "enc_b1": (1071330923, 1228144640),
-            "enc_b2": (874798686, 614072320),
-            "enc_b3": (1484162039, 307036160),
-            "enc_b4": (2427513772, 122814464),
+            "dec_b0": (2193811753, 2147483648),
+            "dec_b1": (1130616091, 1073741824),
+            "dec_b2": (776209132, 536870912),
+            "dec_b3": (1622806387, 268435456),
+            "enc_b0": (2192874829, 2684354560),
+            "enc_b1": (1168120082, 1342177280),
+            "enc_b2": (970975531, 671088640),
+            "enc_b3": (1623691730, 335544320),
+            "enc_b4": (2656267237, 134217728),
         },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 2, 0>": {
-            "dec_a0": (2951068077, 1965031424),
-            "dec_a1": (1497860790, 982515712),
-            "dec_a2": (2388600431, 491257856),
-            "dec_a3": (3659643962, 245628928),
+            "dec_a0": (3224653310, 2147483648),
         },
     },
 }
@@ -101,8 +102,11 @@ MEASURED_TRAFFIC = {
 
 def measured_traffic(kernel, records):
     """HBM bytes per launch of `kernel` averaged over its launches in
-    `records`, from the per-layer counter measurements; None when the conv
-    source changed since, or a layer it ran for was not measured."""
+    `records`: each launch's layer as measured on a full batch (FETCH_SIZE +
+    WRITE_SIZE, MEASURED_TRAFFIC), scaled by the tiles the launch processed
+    over the batch size (a launch past the kept-tile count reads only the
+    count).  None when the conv source changed since the measurement, or a
+    layer the kernel ran for was not measured."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_2305_14566_amd", "csrc", "k_conv.hip")
@@ -114,7 +118,8 @@ def measured_traffic(kernel, records):
     per = [k.get(f"{r['stage']}{r['level']}") for r in records]
     if any(v is None for v in per):
         return None
-    return sum(f + w for f, w in per) / len(per)
+    B = MEASURED_TRAFFIC["batch"]
+    return sum((f + w) * r["tiles"] / B for (f, w), r in zip(per, records)) / len(per)
 
 
 def conv_symbol(om, prec, stage, config):
@@ -736,11 +741,20 @@ def main():
                     help="first copy this many GiB device to device (a plain copy of known size for "
                          "scaling profiler byte counters)")
     ap.add_argument("--counters", action="store_true",
-                    help="profiler counter run: a 1 GiB device copy (the byte counters' scale), then one eager "
-                         "16-slide call and one single-slide call with the pinned conv configuration, and the "
-                         "merge and overlay of the mapping leg; prints their launch lists")
+                    help="profiler counter run through the stand-alone entry points: a 1 GiB device copy (the "
+                         "byte counters' scale), one launch of every conv layer of the bench network on a full "
+                         "256-tile batch with its pinned configuration, the stitch of one 8192^2 plane, the "
+                         "merge and overlay of six classes; prints the launch list")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PATH",
+                    help="FETCH_CSV WRITE_CSV COUNTERS_JSON [MFMA_CSV]: bytes per launch from FETCH_SIZE and "
+                         "WRITE_SIZE passes of rocprofv3 --pmc over bench.py --counters (whose stdout is "
+                         "COUNTERS_JSON), and MFMA busy per conv layer from a pass with SQ_VALU_MFMA_BUSY_CYCLES "
+                         "and GRBM_GUI_ACTIVE; prints JSON")
     ap.add_argument("--oracle-worker", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(*args.summarize_counters)))
+        return
     if args.oracle_worker:
         oracle_worker(args.oracle_worker)
         return
@@ -767,50 +781,171 @@ def main():
     print(json.dumps(result))
 
 
-def counters_run(args):
-    """The launches behind profiles/ counter summaries, each kernel once per
-    call, in a fixed order: copy, 16-slide call, single-slide call, merge and
-    overlay."""
-    import concurrent.futures
+def bench_conv_layers():
+    """The 17 backbone convs of the bench network in forward order: (name,
+    stage id, level, mode, cin, cu, cout, side, pooled copy)."""
+    from paper_2305_14566_amd import omniseg as om
 
-    import synth
-    specs = synth.batch_slide_specs(99, 16)
-    with concurrent.futures.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-        made = list(ex.map(_gen_input, [("batch", sp) for sp in specs] + [("slide", SLIDE)]))
+    C = [CFG["base"] << l for l in range(CFG["levels"])]
+    S = [CFG["tile"] >> l for l in range(CFG["levels"])]
+    out = []
+    for l in range(CFG["levels"]):
+        if l > 0:  # reads the pooled copy of the level above
+            out.append((f"enc_a{l}", 0, l, om.CONV_RELU, C[l - 1], C[l - 1], C[l], S[l], False))
+        out.append((f"enc_b{l}", 1, l, om.CONV_RES_RELU, C[l], C[l], C[l], S[l], l < CFG["levels"] - 1))
+    for l in range(CFG["levels"] - 2, -1, -1):
+        out.append((f"dec_a{l}", 2, l, om.CONV_UPCAT_RELU, 3 * C[l], 2 * C[l], C[l], S[l], False))
+        out.append((f"dec_b{l}", 3, l, om.CONV_RES_RELU, C[l], C[l], C[l], S[l], False))
+    return out
+
+
+def counters_run(args, batch=256):
+    """The launches behind the counter summaries in profiles/, through the
+    stand-alone entry points: a 1 GiB device copy (the byte counters'
+    scale); then, after a fill kernel that marks the phase, one launch of
+    every backbone conv of the bench network on a full batch of 256 tiles
+    (random non-negative BF16 activations, He-normal weights) with the
+    configuration BENCH_CONV_TABLE pins (each preceded by its weight-packing
+    kernel); the stitch of one 8192^2 40x plane from 30 % of its 63^2
+    tiles; the merge to 40x and the overlay of six classes on an 8192^2
+    slide.  Prints the launch list as JSON."""
     import torch
 
     from paper_2305_14566_amd import omniseg as om
     om.lib()
     dev = torch.device("cuda:0")
+    g = torch.Generator(device="cpu").manual_seed(5)
     n = (1 << 30) // 4
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    flat = synth.he_normal_weights(12, CFG["base"], CFG["levels"], CFG["n_classes"], len(CFG["scales"]),
-                                   CFG["head_out"])
-    flat_dev = torch.from_numpy(flat).to(dev)
-    out = {"copy_bytes": 1 << 30}
-    for name, slides, ring in (("batch16", [torch.from_numpy(r).to(dev) for r in made[:-1]], 1),
-                               ("slide", [torch.from_numpy(made[-1]).to(dev)], 0)):
-        plan = _plan(om, "bf16", args.batch_tiles, ring=ring)
-        pin_conv_table(plan)
-        packed = plan.pack(flat_dev)
-        ws = torch.empty(plan.workspace_bytes(slides, PAIRS), dtype=torch.uint8, device=dev)
-        outs = plan.alloc_outputs(slides, PAIRS)
-        plan.set_profiling(True)
-        plan.segment(slides, PAIRS, packed, workspace=ws, outputs=outs)
-        recs = plan.read_profile()
+    out = {"copy_bytes": 1 << 30, "batch": batch, "layers": []}
+    for name, stage, level, mode, cin, cu, cout, side, pool in bench_conv_layers():
+        cfg = BENCH_CONV_TABLE.get((stage, level), BENCH_CONV_DEFAULT)
+        if mode == om.CONV_UPCAT_RELU:
+            x0 = torch.rand((batch, side // 2, side // 2, cu), generator=g).to(torch.bfloat16).to(dev)
+            x1 = torch.rand((batch, side, side, cin - cu), generator=g).to(torch.bfloat16).to(dev)
+        else:
+            x0 = torch.rand((batch, side, side, cin), generator=g).to(torch.bfloat16).to(dev)
+            x1 = None
+        w = (torch.randn((cout, cin, 3, 3), generator=g) * (2.0 / (9 * cin)) ** 0.5).to(dev)
+        b = torch.zeros(cout, device=dev)
+        om.conv3x3(om.BF16, mode, x0, w, b, x1=x1, cu=cu if x1 is not None else None, config=cfg,
+                   height=side, width=side, pool=pool)
         torch.cuda.synchronize()
-        out[name] = {"kept_tiles": _kept(om, plan, slides, PAIRS, ws),
-                     "launches": [[r["stage"], r["level"], r["config"], r["tiles"], r["flops"], r["bytes"]]
-                                  for r in recs]}
-        del ws, outs, slides
-        torch.cuda.empty_cache()
-    dslide = torch.from_numpy(made[-1]).to(dev)
-    out["mapping"] = mapping_leg(om, torch, dslide, flat_dev, SLIDE, 1, args.batch_tiles)
+        px = batch * side * side
+        src_bytes = (batch * (side // 2) ** 2 * cu + px * (cin - cu)) * 2 if x1 is not None else px * cin * 2
+        alg = src_bytes + px * cout * 2 + 9 * cin * cout * 2 + (px // 4 * cout * 2 if pool else 0)
+        out["layers"].append([name, stage, level, cfg, 2.0 * 9 * cin * cout * px, float(alg)])
+        del x0, x1
+    torch.cuda.empty_cache()
+    T, s_, H = CFG["tile"], CFG["stride"], SLIDE
+    ny = (H - T + s_ - 1) // s_ + 1
+    keep = torch.rand(ny * ny, generator=g) < 0.3
+    yx = torch.tensor([(j // ny, j % ny) for j in range(ny * ny) if keep[j]], dtype=torch.int32).to(dev)
+    tl = torch.randn((yx.shape[0], T, T), generator=g).to(dev)
+    om.stitch_tiles(T, s_, H, H, tl, yx, emit_logits=False)
+    torch.cuda.synchronize()
+    out["stitch"] = {"tiles": int(yx.shape[0]), "T": T, "s": s_, "side": H,
+                     "alg_bytes": float(4 * yx.shape[0] * T * T + H * H)}
+    del tl
+    planes = []
+    for c, si in enumerate(CLASS_SLOT):
+        k = CFG["scales"][si]
+        hk = (H + (1 << k) - 1) >> k
+        planes.append((k, om.UPSAMPLE_BILINEAR, torch.randn((hk, hk), generator=g).to(dev)))
+    rgb = torch.randint(0, 256, (H, H, 3), generator=g, dtype=torch.uint8).to(dev)
+    m40 = om.merge_to_base(H, H, planes)
+    om.overlay(rgb, [(m, 0, col, 128) for m, col in zip(m40, CLASS_COLOURS)])
+    torch.cuda.synchronize()
+    out["mapping"] = {"merge_alg_bytes": float(sum(4 * ((H + (1 << k) - 1) >> k) ** 2 + H * H for k, _, _ in planes)),
+                      "overlay_alg_bytes": float(3 * H * H + 6 * H * H + 3 * H * H + 3 * ((H + 3) // 4) ** 2)}
     print(json.dumps(out))
+
+
+def _counter_rows(path, counter):
+    """Per-dispatch (kernel name, value) of one counter from a rocprofv3 CSV,
+    in dispatch order."""
+    import csv
+
+    rows = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                rows[int(r["Dispatch_Id"])] = (r["Kernel_Name"].split("(")[0].replace("void ", ""),
+                                               float(r["Counter_Value"]))
+    return [rows[k] for k in sorted(rows)]
+
+
+def _mfma_rows(path):
+    """Per-dispatch (kernel, MFMA busy cycles summed over SIMDs, GUI active
+    cycles summed over XCDs, elapsed ns) from a rocprofv3 CSV."""
+    import csv
+
+    rows = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            d = rows.setdefault(int(r["Dispatch_Id"]), {"k": r["Kernel_Name"].split("(")[0].replace("void ", ""),
+                                                         "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+    return [rows[k] for k in sorted(rows)]
+
+
+def summarize_counters(fetch_csv, write_csv, launches_json, mfma_csv=None):
+    """Bytes per launch from a FETCH_SIZE and a WRITE_SIZE pass over
+    `bench.py --counters` (whose stdout is launches_json): each counter
+    scaled by its reading for the leading 1 GiB device copy; the conv
+    launches matched in order with the layer list, the stitch and the merge
+    and overlay kernels by name.  With mfma_csv (a
+    pass with SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE over the same
+    command) also the MFMA busy fraction of every conv layer."""
+    import hashlib
+
+    with open(launches_json) as f:
+        L = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    fetch = _counter_rows(fetch_csv, "FETCH_SIZE")
+    write = _counter_rows(write_csv, "WRITE_SIZE")
+    assert [k for k, _ in fetch] == [k for k, _ in write], "the two passes saw different dispatches"
+    names = [k for k, _ in fetch]
+    copy = max(range(len(names)), key=lambda i: fetch[i][1] if "omniseg" not in names[i] else -1)
+    f_scale = L["copy_bytes"] / (fetch[copy][1] * 1024)
+    w_scale = L["copy_bytes"] / (write[copy][1] * 1024)
+    nb = lambda i: (fetch[i][1] * 1024 * f_scale, write[i][1] * 1024 * w_scale)
+    out = {"scale": {"fetch": f_scale, "write": w_scale, "copy_kernel": names[copy]}, "batch": L["batch"]}
+    convs = [i for i in range(len(names)) if "k_conv3x3" in names[i]]
+    assert len(convs) == len(L["layers"]), (len(convs), len(L["layers"]))
+    out["conv_layers"] = {}
+    for (name, stage, level, cfg, flops, alg), i in zip(L["layers"], convs):
+        f, w = nb(i)
+        out["conv_layers"][name] = dict(kernel=names[i], config=cfg, fetch=f, write=w, alg=alg)
+    for ph, keys in (("stitch", ("k_stitch", "k_grid")), ("mapping", ("k_merge", "k_overlay"))):
+        kern = {}
+        for i in range(len(names)):
+            if not any(k in names[i] for k in keys):
+                continue
+            f, w = nb(i)
+            g = kern.setdefault(names[i], dict(n=0, fetch=0.0, write=0.0))
+            g["n"] += 1
+            g["fetch"] += f
+            g["write"] += w
+        out[ph] = {"kernels": kern, **L[ph]}
+    if mfma_csv:
+        m = _mfma_rows(mfma_csv)
+        mconvs = [i for i, d in enumerate(m) if "k_conv3x3" in d["k"]]
+        assert len(mconvs) == len(L["layers"]), ("mfma", len(mconvs), len(L["layers"]))
+        for (name, stage, level, cfg, flops, alg), i in zip(L["layers"], mconvs):
+            d = m[i]
+            gui = d["GRBM_GUI_ACTIVE"] / 8  # summed over the 8 XCDs
+            out["conv_layers"][name].update(
+                mfma_busy_nominal=d["SQ_VALU_MFMA_BUSY_CYCLES"] / (d["ns"] * 2.4 * 1024),
+                mfma_busy_active=d["SQ_VALU_MFMA_BUSY_CYCLES"] / (gui * 1024),
+                clock_ghz=gui / d["ns"], tflops_profiled=flops / d["ns"] / 1e3)
+    src = os.path.join(ROOT, "paper_2305_14566_amd", "csrc", "k_conv.hip")
+    with open(src, "rb") as f:
+        out["conv_source_sha256"] = hashlib.sha256(f.read()).hexdigest()
+    return out
 
 
 def run(args, workdir, proc, log):

@@ -32,7 +32,7 @@ struct TrainLayout {
   int n = 0;  // tiles
   int64_t off_tab, off_pad, off_pyr[OMNISEG_MAX_SCALES], off_list, off_count, off_grid[OMNISEG_MAX_SCALES];
   int64_t off_x, off_E[8], off_D[8], off_A, off_g, off_theta, off_logits;
-  int64_t off_dl, off_dth_part, off_dth, off_dwp_part, off_dg, off_dE[8], off_P, off_Q, off_Z, off_Dg[2];
+  int64_t off_dl, off_dth_part, off_dth, off_dwp_part, off_sum_part, off_dg, off_dE[8], off_P, off_Q, off_Z, off_Dg[2];
   int64_t off_wpart, off_bpart, off_dd0;
   int64_t sz_level0, sz_wpart;
   int64_t total = 0;
@@ -122,6 +122,8 @@ void train_layout(const omniseg_plan* plan, TrainLayout& lay) {
   lay.off_dth_part = take((int64_t)n * lay.max_slots * per * plan->P * 4);
   lay.off_dth = take((int64_t)n * lay.max_slots * plan->P * 4);
   lay.off_dwp_part = take((int64_t)n * per * (8 * plan->C[0] + 8) * 4);
+  lay.off_sum_part = take(4 * std::max(sum_mid_part_floats(n * lay.max_slots, per, plan->P),
+                                       sum_mid_part_floats(1, n * per, 8 * plan->C[0] + 8)));
   lay.off_dg = take((int64_t)n * plan->Cp[L - 1] * 4);
   lay.off_dd0 = take(lay.sz_level0);
   for (int l = 0; l < L; ++l) lay.off_dE[l] = take(px0 / (1LL << (2 * l)) * plan->Cp[l] * es);
@@ -475,9 +477,10 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
   hb.dd0 = ws + lay.off_dd0;
   HIP_TRY(launch_head_bwd(prec, hb, sm));
   float* dtheta = reinterpret_cast<float*>(ws + lay.off_dth);
-  HIP_TRY(launch_sum_mid(hb.dtheta_part, n * lay.max_slots, per, plan->P, dtheta, sm));
+  float* sum_part = reinterpret_cast<float*>(ws + lay.off_sum_part);
+  HIP_TRY(launch_sum_mid(hb.dtheta_part, n * lay.max_slots, per, plan->P, dtheta, sum_part, sm));
   if (plan->canon_pre_w >= 0)  // precls W then b are contiguous in canonical order
-    HIP_TRY(launch_sum_mid(hb.dwp_part, 1, n * per, 8 * plan->C[0] + 8, gw + plan->canon_pre_w, sm));
+    HIP_TRY(launch_sum_mid(hb.dwp_part, 1, n * per, 8 * plan->C[0] + 8, gw + plan->canon_pre_w, sum_part, sm));
 
   // 3. controller backward
   CtrlBwdArgs cb{};

@@ -379,7 +379,8 @@ struct HeadBwdArgs {
   void* dd0;              // dL/dD_0 [tile][T][T][c0_p]
 };
 hipError_t launch_head_bwd(int precision, const HeadBwdArgs& a, hipStream_t st);
-hipError_t launch_sum_mid(const float* in, int R, int K, int I, float* out, hipStream_t st);
+hipError_t launch_sum_mid(const float* in, int R, int K, int I, float* out, float* part, hipStream_t st);
+int64_t sum_mid_part_floats(int R, int K, int I);  // scratch launch_sum_mid needs
 
 struct CtrlBwdArgs {
   const float* dtheta;  // [tile][max_slots][P]

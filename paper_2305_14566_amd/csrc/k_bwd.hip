@@ -268,10 +268,40 @@ __global__ __launch_bounds__(256) void k_head_bwd(HeadBwdArgs a) {
     }
     const int NP = 8 * c0 + 8;
     float* dst = a.dwp_part + ((int64_t)b * per + pblk) * NP;
-    for (int p = 0; p < NP; ++p) {
-      float v = (p < 8 * c0) ? dpre[p / c0] * ldf(px + p % c0) : dpre[p - 8 * c0];
-      v = wave_sum(v);
-      if (lane == 0) red[wave][p] = v;
+    if (c0 % 8 == 0) {
+      // 64 parameters at a time, 8 output channels x 8 input channels, wave
+      // sums by the butterfly reduce-scatter of the theta gradient (the same
+      // sums as wave_sum); lane l ends with parameter (l / 8, cc + l % 8)
+      for (int cc = 0; cc < c0; cc += 8) {
+        float x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = ldf(px + cc + q);
+        float vals[64];
+#pragma unroll
+        for (int q = 0; q < 64; ++q) vals[q] = dpre[q >> 3] * x[q & 7];
+#pragma unroll
+        for (int m = 32, n = 32; m >= 1; m >>= 1, n >>= 1) {
+          const bool up = (lane & m) != 0;
+#pragma unroll
+          for (int q = 0; q < n; ++q) {
+            const float lo = vals[q], hi = vals[q + n];
+            const float send = up ? lo : hi, keep = up ? hi : lo;
+            vals[q] = keep + __shfl_xor(send, m);
+          }
+        }
+        red[wave][(lane >> 3) * c0 + cc + (lane & 7)] = vals[0];
+      }
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const float v = wave_sum(dpre[o]);
+        if (lane == 0) red[wave][8 * c0 + o] = v;
+      }
+    } else {
+      for (int p = 0; p < NP; ++p) {
+        float v = (p < 8 * c0) ? dpre[p / c0] * ldf(px + p % c0) : dpre[p - 8 * c0];
+        v = wave_sum(v);
+        if (lane == 0) red[wave][p] = v;
+      }
     }
     __syncthreads();
     for (int p = threadIdx.x; p < NP; p += 256) dst[p] = (red[0][p] + red[1][p]) + (red[2][p] + red[3][p]);
@@ -294,22 +324,53 @@ hipError_t launch_head_bwd(int precision, const HeadBwdArgs& a, hipStream_t st) 
   return hipGetLastError();
 }
 
-// out[r][i] = sum_k in[r][k][i] for k = 0..K-1 (fixed order); optional scatter
-// of each row into the canonical vector at dst[r * dst_stride + i]
-__global__ void k_sum_mid(const float* __restrict__ in, int R, int K, int I, float* __restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)R * I) return;
-  const int r = (int)(idx / I), i = (int)(idx % I);
+// out[r][kb][i] = sum of in[r][k][i] over the rows k of block kb (kc rows
+// each): a workgroup takes 64 columns i of one row r and one block of kc
+// rows k, wave w the rows k = w mod 4 in increasing order, then the four
+// partial sums in a fixed order (deterministic).
+constexpr int kSumRows = 256;
+__global__ __launch_bounds__(256) void k_sum_mid(const float* __restrict__ in, int R, int K, int I, int kc,
+                                                 float* __restrict__ out) {
+  __shared__ float red[4][64];
+  const int nib = (I + 63) / 64, nkb = (K + kc - 1) / kc;
+  int blk = blockIdx.x;
+  const int kb = blk % nkb;
+  blk /= nkb;
+  const int ib = blk % nib, r = blk / nib;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = ib * 64 + lane;
+  const int k0 = kb * kc, k1 = min(K, k0 + kc);
   float s = 0.f;
-  for (int k = 0; k < K; ++k) s += in[((int64_t)r * K + k) * I + i];
-  out[idx] = s;
+  if (i < I) {
+    const float* src = in + (int64_t)r * K * I + i;
+#pragma unroll 8
+    for (int k = k0 + w; k < k1; k += 4) s += src[(int64_t)k * I];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && i < I) out[((int64_t)r * nkb + kb) * I + i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
-hipError_t launch_sum_mid(const float* in, int R, int K, int I, float* out, hipStream_t st) {
-  const int64_t n = (int64_t)R * I;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sum_mid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, R, K, I, out);
+// out[r][i] = sum_k in[r][k][i] for k = 0..K-1 (fixed order).  K > 256 goes
+// through `part` (R * ceil(K / 256) * I floats): block sums, then their sum.
+hipError_t launch_sum_mid(const float* in, int R, int K, int I, float* out, float* part, hipStream_t st) {
+  if ((int64_t)R * I == 0) return hipSuccess;
+  if (K > kSumRows * kSumRows || (K > kSumRows && !part)) return hipErrorInvalidValue;
+  const int nib = (I + 63) / 64;
+  if (K <= kSumRows) {
+    hipLaunchKernelGGL(k_sum_mid, dim3((unsigned)((int64_t)R * nib)), dim3(256), 0, st, in, R, K, I, K, out);
+    return hipGetLastError();
+  }
+  const int nkb = (K + kSumRows - 1) / kSumRows;
+  hipLaunchKernelGGL(k_sum_mid, dim3((unsigned)((int64_t)R * nib * nkb)), dim3(256), 0, st, in, R, K, I, kSumRows,
+                     part);
+  hipLaunchKernelGGL(k_sum_mid, dim3((unsigned)((int64_t)R * nib)), dim3(256), 0, st, (const float*)part, R, nkb, I,
+                     nkb, out);
   return hipGetLastError();
+}
+
+int64_t sum_mid_part_floats(int R, int K, int I) {
+  return K > kSumRows ? (int64_t)R * ((K + kSumRows - 1) / kSumRows) * I : 0;
 }
 
 // ---------------------------------------------------------------------------

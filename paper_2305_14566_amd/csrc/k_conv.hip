@@ -76,6 +76,7 @@ struct ConvArgs {
   const float* rscale;
   const float* oinv;
   void* pool_out;  // row-reuse epilogues: also write the 2x2 max-pool of y here (or null)
+  int batch;       // tiles the launch covers (the persistent form loops over them)
 };
 
 __device__ __forceinline__ uint4 vmax(uint4 a, uint4 b, float) {
@@ -796,6 +797,13 @@ struct DmaStager {
 
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// s_waitcnt vmcnt(N), N < 16: all but the last N vector memory instructions
+// of the wave done (the counter retires them in issue order)
+template <int N>
+__device__ __forceinline__ void wait_vmem_but() {
+  static_assert(N >= 0 && N < 16, "four-bit count");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
 
 // Lane byte offsets of the MFMA operand reads of k_conv3x3_rows2 inside a
 // stage.  A halo read of fragment row r at horizontal offset dx addresses
@@ -1085,6 +1093,214 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_conv3x3_rows2(ConvArgs a) {
   }
 }
 
+// Weight-stationary persistent form of the eight-wave row-reuse conv for
+// layers with 64 input channels (two 32-channel chunks), plain loader, bias
+// + ReLU or bias + residual + ReLU epilogue: in the bench network the
+// level-0 residual convs and the level-1 encoder conv_a, whose short K (two
+// chunks) leaves a one-block-per-item kernel paying its first load and its
+// epilogue for every 16 x 16 pixel block.  One workgroup per CU keeps the
+// 64-channel weight block of its output channels in LDS (both chunks,
+// 72 KB, loaded once) and walks pixel blocks; the halo of the next block
+// (both chunks, 42 KB) is loaded straight into the other of two LDS stages
+// while the current block is computed and written.  The residual is read
+// from the halo in LDS (the block's own input).  Per pixel block the MFMAs,
+// their order and the epilogue arithmetic are the eight-wave form's, so the
+// outputs equal it bit for bit.
+template <int EPI>
+__global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
+  constexpr int PX = 18, NPIX = 18 * 18, WM = 4, WN = 2, FM = 4, NW = 32, FN = 2, BN = 64, NCH = 2;
+  constexpr int HG = (NPIX * 4 + 63) / 64;  // 64-slot groups of one halo chunk plane
+  constexpr int PLANE = HG * 64 * 16;       // bytes of a halo chunk plane
+  constexpr int STAGE = NCH * PLANE;        // bytes of a halo stage (both chunks)
+  constexpr int WG = 9 * BN * 4 / 64;       // 64-slot groups of one weight chunk plane
+  constexpr int WPLANE = WG * 64 * 16;      // bytes of a weight chunk plane
+  static_assert(NCH * WPLANE + 2 * STAGE <= 160 * 1024, "weights and two halo stages fit the LDS");
+  static_assert(EPI == EPI_RELU || EPI == EPI_RES_RELU, "forward epilogues");
+  __shared__ __attribute__((aligned(16))) char sWt[NCH * WPLANE];
+  __shared__ __attribute__((aligned(16))) char sH0[STAGE];
+  __shared__ __attribute__((aligned(16))) char sH1[STAGE];
+  using T = uint16_t;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WN, wn = wave % WN;
+  const int g = lane >> 4, l16 = lane & 15;
+  // workgroup -> output-channel block and its place among that block's
+  // workgroups; the workgroups of one pixel block's channel blocks share an XCD
+  const int n_nblk = a.n_nblk;
+  const int nb = (blockIdx.x / 8) % n_nblk;
+  const int per_nb = gridDim.x / n_nblk;
+  const int q = (blockIdx.x / (8 * n_nblk)) * 8 + blockIdx.x % 8;
+  const int n0 = nb * BN;
+  const int bpt = a.tiles_y * a.tiles_x;
+  const int valid = max(0, min(a.batch, *a.count - a.chunk_base));
+  const int total = valid * bpt;
+  if (q >= total) return;
+  const int64_t tile_px = (int64_t)a.H * a.W;
+  const uint32_t tile_bytes = (uint32_t)(tile_px * 64 * sizeof(T));
+
+  // the weight block, both chunks, once
+  {
+    const int chunk_w = 9 * a.cout_p * 32;
+    for (int j = wave; j < NCH * WG; j += 8) {
+      const int ch = j / WG, jj = j % WG;
+      const int sl = 64 * jj + lane, r = sl >> 2;
+      const int v = ((sl & 3) - (r >> 1)) & 3;
+      const int tap = r / BN, n = r % BN;
+      const __amdgpu_buffer_rsrc_t rw =
+          buffer_rsrc((const T*)a.w + (int64_t)ch * chunk_w, (uint32_t)(chunk_w * sizeof(T)));
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rw, (__attribute__((address_space(3))) void*)(sWt + ch * WPLANE + jj * 1024), 16,
+          (int)(((tap * a.cout_p + n0 + n) * 32 + v * 8) * sizeof(T)), 0, 0, 0);
+    }
+  }
+  // halo of pixel block i into `stage`
+  auto halo = [&](int i, char* stage) {
+    const int b = i / bpt, rem = i % bpt;
+    const int y0 = (rem / a.tiles_x) * 16, x0 = (rem % a.tiles_x) * 16;
+    const __amdgpu_buffer_rsrc_t rh = buffer_rsrc((const T*)a.x0 + (int64_t)b * tile_px * 64, tile_bytes);
+#pragma unroll
+    for (int k = 0; k < (NCH * HG + 7) / 8; ++k) {
+      const int j = wave + 8 * k;
+      if (j < NCH * HG) {
+        const int ch = j / HG, jj = j % HG;
+        const int sl = 64 * jj + lane, p = sl >> 2;
+        const int v = ((sl & 3) - (p >> 1)) & 3;
+        const int y = y0 + p / PX - 1, x = x0 + p % PX - 1;
+        const bool in = p < NPIX && y >= 0 && y < a.H && x >= 0 && x < a.W;
+        const uint32_t off = in ? (uint32_t)((y * a.W + x) * 64 + ch * 32 + v * 8) * sizeof(T) : kOutside;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rh, (__attribute__((address_space(3))) void*)(stage + ch * PLANE + jj * 1024),
+                                                 16, (int)off, 0, 0, 0);
+      }
+    }
+  };
+
+  const int xrow = wm * FM * PX + l16;
+  const int wrow = wn * NW + l16;
+  const RowsOffsets ro = rows_offsets<FM>(xrow, wrow, g, l16, wm);
+  f32x4 acc[FM][FN];
+  T* out = (T*)a.y;
+  float4 bb[FN];
+#pragma unroll
+  for (int fn = 0; fn < FN; ++fn) bb[fn] = *reinterpret_cast<const float4*>(a.bias + n0 + wn * NW + fn * 16 + g * 4);
+
+  // the residual of pixel block i (RES): input channels c .. c + 3 (cin =
+  // cout) of the block's own pixels, halo pixel (row + 1, l16 + 1), chunk
+  // c / 32, vector (c % 32) / 8.  Read into registers before the next
+  // block's halo loads are issued, so that no LDS read of the epilogue
+  // follows a load into LDS it could be taken to overlap.
+  uint2 res[FM][FN];
+  auto residual = [&](const char* stage) {
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) {
+      const int c = wn * NW + fn * 16 + g * 4;
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) {
+        const int px = (wm * FM + fm + 1) * PX + l16 + 1, cv = (c % 32) >> 3;
+        res[fm][fn] =
+            *reinterpret_cast<const uint2*>(stage + (c / 32) * PLANE + px * 64 + ((cv + (px >> 1)) & 3) * 16 + (c & 4) * 2);
+      }
+    }
+  };
+
+  // compute pixel block i from `stage` and write it
+  auto block = [&](int i, const char* stage) {
+#pragma unroll
+    for (int r = 0; r < FM; ++r)
+#pragma unroll
+      for (int f = 0; f < FN; ++f) acc[r][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) rows_chunk<FM, FN, BN>(acc, stage + ch * PLANE, sWt + ch * WPLANE, ro);
+    const int b = i / bpt, rem = i % bpt;
+    const int y0 = (rem / a.tiles_x) * 16, x0 = (rem % a.tiles_x) * 16;
+    const int x = x0 + l16;
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) {
+      const int c = wn * NW + fn * 16 + g * 4;  // channel inside the block
+#pragma unroll
+      for (int fm = 0; fm < FM; fm += 2) {
+        float v[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int row = wm * FM + fm + h;
+          const int64_t o = (((int64_t)b * a.H + y0 + row) * a.W + x) * a.cout_p + n0 + c;
+          const f32x4 s = acc[fm + h][fn];
+          float* vv = v[h];
+          vv[0] = s[0] + bb[fn].x;
+          vv[1] = s[1] + bb[fn].y;
+          vv[2] = s[2] + bb[fn].z;
+          vv[3] = s[3] + bb[fn].w;
+          if (EPI == EPI_RES_RELU) {
+            const uint2 rr = res[fm + h][fn];
+            vv[0] += bf2f(rr.x & 0xffff);
+            vv[1] += bf2f(rr.x >> 16);
+            vv[2] += bf2f(rr.y & 0xffff);
+            vv[3] += bf2f(rr.y >> 16);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) vv[j] = fmaxf(vv[j], 0.f);
+          uint2 u;
+          u.x = (uint32_t)f2bf(vv[0]) | ((uint32_t)f2bf(vv[1]) << 16);
+          u.y = (uint32_t)f2bf(vv[2]) | ((uint32_t)f2bf(vv[3]) << 16);
+          *reinterpret_cast<uint2*>(out + o) = u;
+        }
+        if (a.pool_out) {
+          float m[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float t = fmaxf(v[0][j], v[1][j]);
+            m[j] = fmaxf(t, __shfl_xor(t, 1));
+          }
+          if ((l16 & 1) == 0) {
+            const int py = (y0 + wm * FM + fm) >> 1, ppx = x >> 1;
+            const int64_t o = (((int64_t)b * (a.H >> 1) + py) * (a.W >> 1) + ppx) * a.cout_p + n0 + c;
+            uint2 u;
+            u.x = (uint32_t)f2bf(m[0]) | ((uint32_t)f2bf(m[1]) << 16);
+            u.y = (uint32_t)f2bf(m[2]) | ((uint32_t)f2bf(m[3]) << 16);
+            *reinterpret_cast<uint2*>((T*)a.pool_out + o) = u;
+          }
+        }
+      }
+    }
+  };
+
+  halo(q, sH0);
+  wait_vmem();
+  __syncthreads();
+  // The wait after a block is for the next block's halo, issued before the
+  // block's output stores (FM FN, and FM FN / 2 for the pooled copy): those
+  // stay in flight across the barrier.
+  constexpr int ST = FM * FN, STP = FM * FN + FM * FN / 2;
+  auto wait_halo = [&]() {
+    if (a.pool_out) wait_vmem_but<STP>();
+    else wait_vmem_but<ST>();
+  };
+  // blocks q, q + per_nb, ... alternate between the stages (two arrays, so
+  // that the loads into one are known not to touch the other)
+  for (int i = q; i < total; i += 2 * per_nb) {
+    if (EPI == EPI_RES_RELU) residual(sH0);
+    if (i + per_nb < total) halo(i + per_nb, sH1);
+    block(i, sH0);
+    wait_halo();
+    __syncthreads();
+    if (i + per_nb >= total) break;
+    if (EPI == EPI_RES_RELU) residual(sH1);
+    if (i + 2 * per_nb < total) halo(i + 2 * per_nb, sH0);
+    block(i + per_nb, sH1);
+    wait_halo();
+    __syncthreads();
+  }
+}
+
+// The weight-stationary form applies to an eight-wave row-reuse launch with
+// 64 input channels, a plain loader, a forward epilogue and enough pixel
+// blocks to keep one workgroup per CU busy.
+constexpr int kWsGrid = 256;
+inline bool ws_applies(int loader, int epi, const ConvLayer& L, int H, int W, int batch) {
+  return loader == LOAD_PLAIN && (epi == EPI_RELU || epi == EPI_RES_RELU) && L.cin_p == 64 && L.cout_p % 64 == 0 &&
+         L.cout_p / 64 <= 2 && (epi != EPI_RES_RELU || L.cout_p == 64) && H % 16 == 0 && W % 16 == 0 &&
+         (int64_t)batch * (H / 16) * (W / 16) >= 8 * kWsGrid;
+}
+
 // FP8 (E4M3) row-reuse form on v_mfma_scale_f32_32x32x64_f8f6f4 (unit block
 // scales): one MFMA is one tap of a 64-channel chunk for 32 output channels
 // (A, weights) x 32 pixels (B).  A pixel fragment is two 16-pixel rows; lane
@@ -1338,7 +1554,16 @@ static hipError_t launch_conv_rows_t(const ConvLayer& L, int H, int W, int batch
   a.tiles_x = W / 16;
   a.n_nblk = L.cout_p / BN;
   a.pool_out = L.pool_out;
+  a.batch = batch;
   if (L.pool_out && EPI != EPI_RES_RELU) return hipErrorInvalidValue;
+  if constexpr (BY == 16 && BN == 64 && WM == 4 && WN == 2 && LOADER == LOAD_PLAIN &&
+                (EPI == EPI_RELU || EPI == EPI_RES_RELU)) {
+    if (ws_applies(LOADER, EPI, L, H, W, batch)) {
+      a.tiles_y = H / 16;
+      hipLaunchKernelGGL((k_conv3x3_ws<EPI>), dim3(kWsGrid), dim3(512), 0, st, a);
+      return hipGetLastError();
+    }
+  }
   const int64_t blocks = (int64_t)batch * a.tiles_y * a.tiles_x * a.n_nblk;
   hipLaunchKernelGGL((k_conv3x3_rows<BY, BN, WM, WN, LOADER, EPI>), dim3((unsigned)blocks), dim3(64 * WM * WN), 0, st,
                      a);

@@ -283,8 +283,12 @@ __global__ __launch_bounds__(1024) void k_compact(int32_t* idx, int total, TileG
   }
 }
 
-// launch_put: one workgroup per payload of kPutWords words.
-constexpr int kPutWords = 896;
+// launch_put: one workgroup per payload of kPutWords words.  The payload
+// travels in the kernel arguments (so a captured graph holds the data, not a
+// host pointer); 224 words keep the argument segment near 1 KB, well inside
+// the 4 KB limit (a 3.5 KB payload crashed rocprofv3's counter collection
+// on the host).
+constexpr int kPutWords = 224;
 struct PutPayload {
   uint32_t w[kPutWords];
 };

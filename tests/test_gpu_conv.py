@@ -211,6 +211,31 @@ def test_large_block_form_equals_row_reuse_bit_for_bit(mode):
     assert outs[0][0].float().abs().sum() > 0
 
 
+@pytest.mark.parametrize("case", ["res_pool", "relu_two_blocks", "relu_one_block"])
+def test_weight_stationary_form_equals_row_reuse_bit_for_bit(case):
+    """Eight-wave launches with 64 input channels, a forward epilogue and at
+    least 2048 pixel blocks run the persistent weight-stationary form (a
+    workgroup per CU walking pixel blocks, weights kept in LDS, residual read
+    from the staged halo).  Its sums are the row-reuse forms' in the same
+    order, so it equals the four-wave form (configuration 6) bit for bit,
+    including the fused pooled copy."""
+    rng = np.random.default_rng(seed_of("ws", case))
+    n, H, W = (8, 256, 256) if case != "relu_two_blocks" else (32, 128, 128)
+    cin, cout = (64, 64) if case != "relu_two_blocks" else (64, 128)
+    dev = lambda a: torch.from_numpy(np.asarray(a, np.float32)).to(DEV)
+    Wt = q(rng.standard_normal((cout, cin, 3, 3)) * np.sqrt(2.0 / (9 * cin)), om.BF16)
+    b = dev(rng.standard_normal(cout) * 0.1)
+    x = torch.from_numpy(rng.standard_normal((n, H, W, cin)).astype(np.float32)).to(torch.bfloat16).to(DEV)
+    mode = om.CONV_RES_RELU if case == "res_pool" else om.CONV_RELU
+    pool = case == "res_pool"
+    outs = [om.conv3x3(om.BF16, mode, x, dev(Wt), b, config=c, pool=pool) for c in (10, 6)]
+    torch.cuda.synchronize()
+    outs = [o if isinstance(o, tuple) else (o,) for o in outs]
+    for a_, c_ in zip(outs[0], outs[1]):
+        assert torch.equal(a_.view(torch.int16), c_.view(torch.int16))
+    assert outs[0][0].float().abs().sum() > 0
+
+
 # ------------------------------------------------------------------ FP8 (E4M3)
 
 def _e4m3_values():
