@@ -67,34 +67,38 @@ TRAIN_BATCH = 32
 # the conv source whose SHA-256 is stored here; any other source reports
 # null.
 MEASURED_TRAFFIC = {
-    "conv_source_sha256": "d58682a5ef8d0a5e299575fc1249cb45a78dadd0420dd2cece464fce2071eab9",
+    "conv_source_sha256": "14ee15043eb3295817aea9f6174f94f7eeec70d0285ae884a7de18b2ca372943",
     "batch": 256,
     # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000) bytes of one full-batch launch per layer
     "kernels": {
         "omniseg::k_conv3x3_rows2<32, 64, 4, 2, 2, 0>": {
-            "dec_a1": (2004806672, 1088543968),
-            "dec_a2": (1711742802, 541514272),
-            "dec_a3": (2215041415, 268934400),
+            "dec_a1": (1995169311, 1087446432),
+            "dec_a2": (1711748134, 544311360),
+            "dec_a3": (2215045950, 268809344),
         },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 0>": {
-            "enc_a1": (538147984, 1073741824),
-            "enc_a2": (273263914, 536870912),
-            "enc_a3": (246497821, 268435456),
-            "enc_a4": (1394219953, 134217728),
+            "enc_a2": (273261828, 536870912),
+            "enc_a3": (258067539, 268435456),
+            "enc_a4": (1259921597, 134217728),
         },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 1>": {
-            "dec_b0": (2193811753, 2147483648),
-            "dec_b1": (1130616091, 1073741824),
-            "dec_b2": (776209132, 536870912),
-            "dec_b3": (1622806387, 268435456),
-            "enc_b0": (2192874829, 2684354560),
-            "enc_b1": (1168120082, 1342177280),
-            "enc_b2": (970975531, 671088640),
-            "enc_b3": (1623691730, 335544320),
-            "enc_b4": (2656267237, 134217728),
+            "dec_b1": (1127035881, 1073741824),
+            "dec_b2": (814911179, 536870912),
+            "dec_b3": (1621904457, 268435456),
+            "enc_b1": (1166830174, 1342177280),
+            "enc_b2": (954728209, 671088640),
+            "enc_b3": (1622721705, 335544320),
+            "enc_b4": (2654726271, 134217728),
         },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 2, 0>": {
-            "dec_a0": (3224653310, 2147483648),
+            "dec_a0": (3224801525, 2147483648),
+        },
+        "omniseg::k_conv3x3_ws<0>": {
+            "enc_a1": (597070429, 1073741824),
+        },
+        "omniseg::k_conv3x3_ws<1>": {
+            "dec_b0": (2414587636, 2147493600),
+            "enc_b0": (2418291172, 2684740096),
         },
     },
 }
@@ -122,14 +126,20 @@ def measured_traffic(kernel, records):
     return sum((f + w) * r["tiles"] / B for (f, w), r in zip(per, records)) / len(per)
 
 
-def conv_symbol(om, prec, stage, config):
-    """Kernel symbol (as rocprofv3 prints it) that a conv launch uses."""
+def conv_symbol(om, prec, stage, config, level=None):
+    """Kernel symbol (as rocprofv3 prints it) that a conv launch of the bench
+    network uses."""
     # BF16 and FP8 fuse the max-pool into the encoder's residual conv, so
     # conv_a then reads the pooled tensor with the plain loader
     loader, epi = {"enc_a": (1 if prec == "fp32" else 0, 0), "enc_b": (0, 1), "dec_a": (2, 0), "dec_b": (0, 1)}[stage]
     by, bx, bn, wm, wn = om.conv_config(config)
     if prec == "fp8":
         return f"omniseg::k_conv3x3_fp8<{by}, {bn}, {wm}, {wn}, {loader}, {epi}>"
+    # the eight-wave configuration runs the layers with 64 input channels
+    # (level-0 residual convs, level-1 conv_a) in its weight-stationary form
+    if prec == "bf16" and config == 10 and ((stage in ("enc_b", "dec_b") and level == 0) or
+                                            (stage == "enc_a" and level == 1)):
+        return f"omniseg::k_conv3x3_ws<{epi}>"
     if prec == "bf16" and config == 11:  # large-block row-reuse configuration
         return f"omniseg::k_conv3x3_rows2<{by}, {bn}, {wm}, {wn}, {loader}, {epi}>"
     if prec == "bf16" and config >= 6:  # row-reuse configurations
@@ -144,7 +154,7 @@ def roofline(om, records, prec):
     for r in records:
         if r["stage"] not in ("enc_a", "enc_b", "dec_a", "dec_b"):
             continue
-        sym = conv_symbol(om, prec, r["stage"], r["config"])
+        sym = conv_symbol(om, prec, r["stage"], r["config"], r["level"])
         g = groups.setdefault(sym, dict(n=0, flops=0.0, ms=0.0, bytes=0.0, recs=[]))
         g["recs"].append(r)
         g["n"] += 1
