@@ -475,6 +475,7 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
   hb.dtheta_part = reinterpret_cast<float*>(ws + lay.off_dth_part);
   hb.dwp_part = reinterpret_cast<float*>(ws + lay.off_dwp_part);
   hb.dd0 = ws + lay.off_dd0;
+  hb.mask_d0 = L >= 2 ? 1 : 0;  // D_0 is the decoder's ReLU output: its gradient leaves masked
   HIP_TRY(launch_head_bwd(prec, hb, sm));
   float* dtheta = reinterpret_cast<float*>(ws + lay.off_dth);
   float* sum_part = reinterpret_cast<float*>(ws + lay.off_sum_part);
@@ -543,21 +544,23 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
   const void* dcur = ws + lay.off_dd0;
   for (int l = 0; l + 1 < L; ++l) {
     const int tl = T >> l;
-    const int64_t npx = (int64_t)n * tl * tl;
     const ConvDesc& da = plan->dec_a[l];
     const ConvDesc& db = plan->dec_b[l];
     const void* below = (l + 1 == L - 1) ? E[L - 1] : D[l + 1];
     HIP_TRY(launch_conv3x3(prec, LOAD_UPCAT, EPI_RELU, fwd_layer(pk, da), tl, tl, n, count, 0, below, E[l], A, sm));
-    HIP_TRY(launch_relu_mask(prec, dcur, D[l], npx * plan->Cp[l], bufP, sm));
-    OMNISEG_CALL(wgrad(db, LOAD_PLAIN, prec, A, nullptr, bufP, tl, db.cin, db.cin_p, db.cu, db.cu_p, gw + db.canon_w));
-    OMNISEG_CALL(bias(db, bufP, tl, gw + db.canon_b));
-    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_MASK, bwd_layer(pk, db), tl, tl, n, count, 0, bufP, nullptr, bufQ, sm, A));
+    // dcur is already the gradient through the ReLU of D_l (the head's
+    // backward or the level below's concat backward applied the mask)
+    const void* gD = dcur;
+    OMNISEG_CALL(wgrad(db, LOAD_PLAIN, prec, A, nullptr, gD, tl, db.cin, db.cin_p, db.cu, db.cu_p, gw + db.canon_w));
+    OMNISEG_CALL(bias(db, gD, tl, gw + db.canon_b));
+    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_MASK, bwd_layer(pk, db), tl, tl, n, count, 0, gD, nullptr, bufQ, sm, A));
     OMNISEG_CALL(wgrad(da, LOAD_UPCAT, prec, below, E[l], bufQ, tl, da.cin, da.cin_p, da.cu, da.cu_p, gw + da.canon_w));
     OMNISEG_CALL(bias(da, bufQ, tl, gw + da.canon_b));
     HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_NONE, bwd_layer(pk, da), tl, tl, n, count, 0, bufQ, nullptr, bufZ, sm));
     const bool last = (l + 1 == L - 1);
     void* dnext = last ? dE[L - 1] : bufD[(l + 1) & 1];
-    HIP_TRY(launch_concat_bwd(prec, bufZ, n, tl, tl, da.cu_p, plan->Cp[l], dE[l], dnext, last ? 1 : 0, sm));
+    HIP_TRY(launch_concat_bwd(prec, bufZ, n, tl, tl, da.cu_p, plan->Cp[l], dE[l], dnext, last ? 1 : 0,
+                              last ? nullptr : D[l + 1], sm));
     dcur = dnext;
   }
   // 6. encoder levels, from the bottleneck outwards
@@ -571,10 +574,16 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
     } else {
       HIP_TRY(launch_conv3x3(prec, LOAD_POOL, EPI_RELU, fwd_layer(pk, plan->enc_a[l]), tl, tl, n, count, 0, E[l - 1], nullptr, A, sm));
     }
-    HIP_TRY(launch_relu_mask(prec, dE[l], E[l], npx * plan->Cp[l], bufP, sm));
-    OMNISEG_CALL(wgrad(eb, LOAD_PLAIN, prec, A, nullptr, bufP, tl, eb.cin, eb.cin_p, eb.cu, eb.cu_p, gw + eb.canon_w));
-    OMNISEG_CALL(bias(eb, bufP, tl, gw + eb.canon_b));
-    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_MASK, bwd_layer(pk, eb), tl, tl, n, count, 0, bufP, nullptr, bufQ, sm, A));
+    // below the bottleneck the max-pool backward of level l + 1 stored dE_l
+    // through the ReLU of E_l already
+    const void* gE = dE[l];
+    if (l == L - 1) {
+      HIP_TRY(launch_relu_mask(prec, dE[l], E[l], npx * plan->Cp[l], bufP, sm));
+      gE = bufP;
+    }
+    OMNISEG_CALL(wgrad(eb, LOAD_PLAIN, prec, A, nullptr, gE, tl, eb.cin, eb.cin_p, eb.cu, eb.cu_p, gw + eb.canon_w));
+    OMNISEG_CALL(bias(eb, gE, tl, gw + eb.canon_b));
+    HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_MASK, bwd_layer(pk, eb), tl, tl, n, count, 0, gE, nullptr, bufQ, sm, A));
     if (l == 0) {
       ConvDesc d0{};
       d0.cout = plan->C[0];
@@ -587,7 +596,7 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
       OMNISEG_CALL(wgrad(ea, LOAD_POOL, prec, E[l - 1], nullptr, bufQ, tl, ea.cin, ea.cin_p, ea.cu, ea.cu_p, gw + ea.canon_w));
       OMNISEG_CALL(bias(ea, bufQ, tl, gw + ea.canon_b));
       HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_NONE, bwd_layer(pk, ea), tl, tl, n, count, 0, bufQ, nullptr, bufZ, sm));
-      HIP_TRY(launch_maxpool_bwd(prec, E[l - 1], bufZ, n, 2 * tl, 2 * tl, plan->Cp[l - 1], dE[l - 1], sm));
+      HIP_TRY(launch_maxpool_bwd(prec, E[l - 1], bufZ, n, 2 * tl, 2 * tl, plan->Cp[l - 1], dE[l - 1], sm, 1));
     }
   }
 #undef OMNISEG_CALL

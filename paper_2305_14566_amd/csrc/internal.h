@@ -377,6 +377,7 @@ struct HeadBwdArgs {
   float* dtheta_part;     // [tile][max_slots][T*T/256][P]
   float* dwp_part;        // [tile][T*T/256][8 c0 + 8]
   void* dd0;              // dL/dD_0 [tile][T][T][c0_p]
+  int mask_d0;            // store dd0 through the ReLU that produced D_0 (zero where D_0 <= 0)
 };
 hipError_t launch_head_bwd(int precision, const HeadBwdArgs& a, hipStream_t st);
 hipError_t launch_sum_mid(const float* in, int R, int K, int I, float* out, float* part, hipStream_t st);
@@ -400,9 +401,9 @@ hipError_t launch_gap_bwd(int precision, const float* dg, int g_stride, int G, i
                           void* dE, hipStream_t st);
 hipError_t launch_relu_mask(int precision, const void* dy, const void* y, int64_t n, void* out, hipStream_t st);
 hipError_t launch_concat_bwd(int precision, const void* dZ, int n_tiles, int H, int W, int cu_p, int ce_p,
-                             void* dE, void* dD, int accumulate, hipStream_t st);
+                             void* dE, void* dD, int accumulate, const void* ymask, hipStream_t st);
 hipError_t launch_maxpool_bwd(int precision, const void* E, const void* dX, int n_tiles, int H, int W, int c_p,
-                              void* dE, hipStream_t st);
+                              void* dE, hipStream_t st, int relu);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);
 

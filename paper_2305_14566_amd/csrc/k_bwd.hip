@@ -263,6 +263,7 @@ __global__ __launch_bounds__(256) void k_head_bwd(HeadBwdArgs a) {
       if (c < c0) {
 #pragma unroll
         for (int o = 0; o < 8; ++o) s = fmaf(swp[o * c0 + c], dpre[o], s);
+        if (a.mask_d0 && !(ldf(px + c) > 0.f)) s = 0.f;
       }
       stf(dd0 + c, s);
     }
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(256) void k_head_bwd(HeadBwdArgs a) {
     __syncthreads();
     for (int p = threadIdx.x; p < NP; p += 256) dst[p] = (red[0][p] + red[1][p]) + (red[2][p] + red[3][p]);
   } else {
-    for (int c = 0; c < a.c0_p; ++c) stf(dd0 + c, c < 8 ? dF[c] : 0.f);
+    for (int c = 0; c < a.c0_p; ++c) stf(dd0 + c, c < 8 && !(a.mask_d0 && !(F[c] > 0.f)) ? dF[c] : 0.f);
   }
 }
 
@@ -463,10 +464,13 @@ hipError_t launch_relu_mask(int precision, const void* dy, const void* y, int64_
 
 // Split the data gradient of the decoder's concat input dZ [pix][cu_p + ce_p]:
 // skip part added into dE [pix][ce_p]; upsampled part summed over each 2x2
-// block into dD [pix/4][cu_p] (set, or added when `accumulate`).
+// block into dD [pix/4][cu_p] (set, or added when `accumulate`).  With
+// `ymask` (the coarse decoder output the upsampled part came from, a ReLU
+// output) the stored dD is zero where ymask <= 0: the gradient through that
+// ReLU, as a separate mask pass would give it.
 template <typename T>
 __global__ void k_concat_bwd(const T* dZ, int n_tiles, int H, int W, int cu_p, int ce_p, T* dE, T* dD,
-                             int accumulate) {
+                             int accumulate, const T* ymask) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int cz = cu_p + ce_p;
   const int64_t n_skip = (int64_t)n_tiles * H * W * ce_p;
@@ -486,27 +490,31 @@ __global__ void k_concat_bwd(const T* dZ, int n_tiles, int H, int W, int cu_p, i
     const T* z = dZ + ((t * H + 2 * Y) * W + 2 * X) * cz + c;
     float s = (ldf(z) + ldf(z + cz)) + (ldf(z + (int64_t)W * cz) + ldf(z + (int64_t)W * cz + cz));
     if (accumulate) s += ldf(dD + k);
+    if (ymask && !(ldf(ymask + k) > 0.f)) s = 0.f;
     stf(dD + k, s);
   }
 }
 
 hipError_t launch_concat_bwd(int precision, const void* dZ, int n_tiles, int H, int W, int cu_p, int ce_p,
-                             void* dE, void* dD, int accumulate, hipStream_t st) {
+                             void* dE, void* dD, int accumulate, const void* ymask, hipStream_t st) {
   const int64_t n = (int64_t)n_tiles * H * W * ce_p + (int64_t)n_tiles * (H / 2) * (W / 2) * cu_p;
   dim3 grid((unsigned)((n + 255) / 256));
   if (precision == OMNISEG_BF16)
     hipLaunchKernelGGL(k_concat_bwd<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)dZ, n_tiles, H, W, cu_p,
-                       ce_p, (uint16_t*)dE, (uint16_t*)dD, accumulate);
+                       ce_p, (uint16_t*)dE, (uint16_t*)dD, accumulate, (const uint16_t*)ymask);
   else
     hipLaunchKernelGGL(k_concat_bwd<float>, grid, dim3(256), 0, st, (const float*)dZ, n_tiles, H, W, cu_p, ce_p,
-                       (float*)dE, (float*)dD, accumulate);
+                       (float*)dE, (float*)dD, accumulate, (const float*)ymask);
   return hipGetLastError();
 }
 
 // 2x2 max-pool backward: each window's gradient goes to its first maximum
-// (row-major); added into dE of the finer level.
+// (row-major); added into dE of the finer level.  With `relu` (E a ReLU
+// output, and this the last contribution to dE) all four entries of the
+// window are also stored as zero where E <= 0: the gradient through that
+// ReLU, as a separate mask pass over dE would give it.
 template <typename T>
-__global__ void k_maxpool_bwd(const T* E, const T* dX, int n_tiles, int H, int W, int c_p, T* dE) {
+__global__ void k_maxpool_bwd(const T* E, const T* dX, int n_tiles, int H, int W, int c_p, T* dE, int relu) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;  // coarse element
   const int Hh = H / 2, Wh = W / 2;
   if (i >= (int64_t)n_tiles * Hh * Wh * c_p) return;
@@ -532,21 +540,32 @@ __global__ void k_maxpool_bwd(const T* E, const T* dX, int n_tiles, int H, int W
     }
   }
   const float g = ldf(dX + i);
+  if (relu) {
+    float e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = ldf(E + off[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k == best) stf(dE + off[k], ldf(dE + off[k]) + g);  // rounded as without the mask
+      if (!(e[k] > 0.f)) stf(dE + off[k], 0.f);
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     if (k == best) stf(dE + off[k], ldf(dE + off[k]) + g);
 }
 
 hipError_t launch_maxpool_bwd(int precision, const void* E, const void* dX, int n_tiles, int H, int W, int c_p,
-                              void* dE, hipStream_t st) {
+                              void* dE, hipStream_t st, int relu) {
   const int64_t n = (int64_t)n_tiles * (H / 2) * (W / 2) * c_p;
   dim3 grid((unsigned)((n + 255) / 256));
   if (precision == OMNISEG_BF16)
     hipLaunchKernelGGL(k_maxpool_bwd<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)E, (const uint16_t*)dX,
-                       n_tiles, H, W, c_p, (uint16_t*)dE);
+                       n_tiles, H, W, c_p, (uint16_t*)dE, relu);
   else
     hipLaunchKernelGGL(k_maxpool_bwd<float>, grid, dim3(256), 0, st, (const float*)E, (const float*)dX, n_tiles,
-                       H, W, c_p, (float*)dE);
+                       H, W, c_p, (float*)dE, relu);
   return hipGetLastError();
 }
 
