@@ -751,6 +751,20 @@ __device__ __forceinline__ uint4 wg_load_x_bf16(const WgradArgs& a, int b, int y
   }
 }
 
+// Element-wise maximum of two words of two BF16 values each, as values (the
+// result is one of the inputs, so exact), in the order of the pooling loader.
+__device__ __forceinline__ uint32_t bf16_max2(uint32_t a, uint32_t b) {
+  const uint32_t lo = __float_as_uint(fmaxf(__uint_as_float(a << 16), __uint_as_float(b << 16))) >> 16;
+  const uint32_t hi = __float_as_uint(fmaxf(__uint_as_float(a & 0xffff0000u), __uint_as_float(b & 0xffff0000u)));
+  return (hi & 0xffff0000u) | lo;
+}
+
+// 16-bit element j (0..7) of a 16-byte vector
+__device__ __forceinline__ uint32_t elem16(const uint4& v, int j) {
+  const uint32_t w = j < 2 ? v.x : j < 4 ? v.y : j < 6 ? v.z : v.w;
+  return (j & 1) ? (w >> 16) : (w & 0xffffu);
+}
+
 template <int BX, int BO, int LOADER>
 __global__ __launch_bounds__(256) void k_wgrad3x3_bf16(WgradArgs a) {
   constexpr int BY = 8, BM = BY * BX;  // pixels per chunk
@@ -760,6 +774,14 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_bf16(WgradArgs a) {
   constexpr int HR = BY + 2, HX = BX + 2;
   constexpr int XP = BX + 8;           // sXt row (elements), 16-byte rows
   constexpr int CP = HR * XP + 8;      // sXt channel plane (elements): rotates the banks between channels
+  // staging tasks: dY as quads of pixels x 8 channels, the halo as groups of
+  // four pixels of one row x 8 channels; at most one of each per thread
+  constexpr int NQ = (BM / 4) * (BO / 8);
+  constexpr int NG = (HX + 3) / 4;
+  constexpr int NXT = HR * NG * (BC / 8);
+  constexpr int LPV = (LOADER == LOAD_POOL) ? 4 : 1;
+  static_assert(NQ <= 256 && NXT <= 256, "one staging task of each kind per thread");
+  static_assert((GP * 2) % 8 == 0 && (XP * 2) % 8 == 0 && (CP * 2) % 8 == 0, "aligned packed stores");
   __shared__ __align__(16) uint16_t sGt[BO * GP];
   __shared__ __align__(16) uint16_t sXt[3 * BC * CP];
   const int n_ob = a.cout_p / BO, n_cb = a.cin_p / BC;
@@ -780,36 +802,98 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_bf16(WgradArgs a) {
 #pragma unroll
     for (int f = 0; f < FO; ++f) acc[t][f] = f32x4{0.f, 0.f, 0.f, 0.f};
   const uint16_t* G = (const uint16_t*)a.dy;
-  for (int ch = split; ch < n_chunks; ch += a.splits) {
+  // this thread's staging tasks
+  const int q_m = (tid / (BO / 8)) * 4, q_og = (tid % (BO / 8)) * 8;  // dY: pixels q_m..q_m+3, channels q_og..+7
+  const bool q_on = tid < NQ;
+  const int x_cv = (tid % (BC / 8)) * 8, x_g = (tid / (BC / 8)) % NG, x_hr = tid / ((BC / 8) * NG);
+  const bool x_on = tid < NXT;
+  const int x_hx0 = x_g * 4;
+  uint4 gq[4];
+  uint4 xr[4][LPV];
+
+  auto fetch = [&](int ch) {
     const int b = ch / (tiles_y * tiles_x);
     const int sy = (ch / tiles_x) % tiles_y, sx = ch % tiles_x;
     const int y0 = sy * BY, x0 = sx * BX;
-    // dY of the chunk, transposed: sGt[o][pixel]
-    for (int i = tid; i < BM * (BO / 8); i += 256) {
-      const int m = i / (BO / 8), og = (i % (BO / 8)) * 8;
-      const int y = y0 + m / BX, x = x0 + m % BX;
-      const uint4 v = *reinterpret_cast<const uint4*>(G + (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + o0 + og);
-      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+    if (q_on) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sGt[(og + j) * GP + m] = e[j];
-    }
-    // the input halo, transposed, one copy per dx: sXt[dx][c][row][x] = X(row - 1, x + dx - 1)
-    for (int i = tid; i < HR * HX * (BC / 8); i += 256) {
-      const int p = i / (BC / 8), cv = (i % (BC / 8)) * 8;
-      const int hr = p / HX, hx = p % HX;
-      const int y = y0 + hr - 1, x = x0 + hx - 1;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (y >= 0 && y < a.H && x >= 0 && x < a.W) v = wg_load_x_bf16<LOADER>(a, b, y, x, c0 + cv);
-      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int xq = hx - d;
-        if (xq < 0 || xq >= BX) continue;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) sXt[(d * BC + cv + j) * CP + hr * XP + xq] = e[j];
+      for (int k = 0; k < 4; ++k) {
+        const int m = q_m + k;
+        const int y = y0 + m / BX, x = x0 + m % BX;
+        gq[k] = *reinterpret_cast<const uint4*>(G + (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + o0 + q_og);
       }
     }
+    if (x_on) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int y = y0 + x_hr - 1, x = x0 + x_hx0 + k - 1;
+        const bool in = x_hx0 + k < HX && y >= 0 && y < a.H && x >= 0 && x < a.W;
+#pragma unroll
+        for (int l = 0; l < LPV; ++l) xr[k][l] = make_uint4(0u, 0u, 0u, 0u);
+        if (in) {
+          if (LOADER == LOAD_POOL) {
+            const uint16_t* p = (const uint16_t*)a.x0 + (((int64_t)b * 2 * a.H + 2 * y) * (2 * a.W) + 2 * x) * a.cin_p + c0 + x_cv;
+            xr[k][0] = *reinterpret_cast<const uint4*>(p);
+            xr[k][LPV > 1 ? 1 : 0] = *reinterpret_cast<const uint4*>(p + a.cin_p);
+            xr[k][LPV > 2 ? 2 : 0] = *reinterpret_cast<const uint4*>(p + (int64_t)2 * a.W * a.cin_p);
+            xr[k][LPV > 3 ? 3 : 0] = *reinterpret_cast<const uint4*>(p + (int64_t)2 * a.W * a.cin_p + a.cin_p);
+          } else {
+            xr[k][0] = wg_load_x_bf16<LOADER>(a, b, y, x, c0 + x_cv);
+          }
+        }
+      }
+    }
+  };
+  auto commit = [&]() {
+    if (q_on) {
+      // sGt[o][pixel]: four pixels of channel q_og + j in one 8-byte store
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint2 v = make_uint2(elem16(gq[0], j) | (elem16(gq[1], j) << 16), elem16(gq[2], j) | (elem16(gq[3], j) << 16));
+        *reinterpret_cast<uint2*>(&sGt[(q_og + j) * GP + q_m]) = v;
+      }
+    }
+    if (x_on) {
+      uint4 xv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xv[k] = xr[k][0];
+        if (LOADER == LOAD_POOL) {
+          // 2x2 max, element by element, in the pooling loader's order
+#pragma unroll
+          for (int l = 1; l < LPV; ++l) {
+            const uint4 o = xr[k][l < LPV ? l : 0];
+            xv[k] = make_uint4(bf16_max2(xv[k].x, o.x), bf16_max2(xv[k].y, o.y), bf16_max2(xv[k].z, o.z),
+                               bf16_max2(xv[k].w, o.w));
+          }
+        }
+      }
+      // sXt[dx][c][row][x] = X(row - 1, x + dx - 1): pixel hx0 + k of the halo
+      // lands at x = hx0 + k - dx of copy dx
+      const int h0 = x_hx0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        uint32_t e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = elem16(xv[k], j);
+        uint16_t* r0 = &sXt[(0 * BC + x_cv + j) * CP + x_hr * XP];
+        uint16_t* r1 = &sXt[(1 * BC + x_cv + j) * CP + x_hr * XP];
+        uint16_t* r2 = &sXt[(2 * BC + x_cv + j) * CP + x_hr * XP];
+        if (h0 + 3 < BX) *reinterpret_cast<uint2*>(r0 + h0) = make_uint2(e[0] | (e[1] << 16), e[2] | (e[3] << 16));
+        if (h0 >= 1 && h0 - 1 < BX) r1[h0 - 1] = (uint16_t)e[0];
+        if (h0 + 1 < BX) *reinterpret_cast<uint32_t*>(r1 + h0) = e[1] | (e[2] << 16);
+        if (h0 + 2 < BX) r1[h0 + 2] = (uint16_t)e[3];
+        if (h0 >= 2 && h0 - 1 < BX) *reinterpret_cast<uint32_t*>(r2 + h0 - 2) = e[0] | (e[1] << 16);
+        if (h0 + 1 < BX) *reinterpret_cast<uint32_t*>(r2 + h0) = e[2] | (e[3] << 16);
+      }
+    }
+  };
+
+  if (split < n_chunks) fetch(split);
+  for (int ch = split; ch < n_chunks; ch += a.splits) {
+    commit();
     __syncthreads();
+    if (ch + a.splits < n_chunks) fetch(ch + a.splits);  // in flight during the MFMAs
 #pragma unroll
     for (int ks = 0; ks < BM / 32; ++ks) {
       const int pix0 = ks * 32 + kg * 8;  // this lane's 8 pixels (MFMA K index)
