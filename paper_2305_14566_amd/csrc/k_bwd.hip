@@ -19,6 +19,34 @@ __device__ __forceinline__ void stf(uint16_t* p, float v) {
   *p = (uint16_t)(u >> 16);
 }
 
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+// Eight consecutive values (p 16-byte aligned for BF16, 32-byte for FP32).
+__device__ __forceinline__ void ld8(const float* p, float (&v)[8]) {
+  const float4 a = *reinterpret_cast<const float4*>(p), b = *reinterpret_cast<const float4*>(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__device__ __forceinline__ void ld8(const uint16_t* p, float (&v)[8]) {
+  const uint4 q = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[2 * k] = __uint_as_float(w[k] << 16);
+    v[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+  }
+}
+__device__ __forceinline__ void st8(float* p, const float (&v)[8]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  *reinterpret_cast<float4*>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+}
+__device__ __forceinline__ void st8(uint16_t* p, const float (&v)[8]) {
+  *reinterpret_cast<uint4*>(p) = make_uint4(bf16_bits(v[0]) | (bf16_bits(v[1]) << 16), bf16_bits(v[2]) | (bf16_bits(v[3]) << 16),
+                                            bf16_bits(v[4]) | (bf16_bits(v[5]) << 16), bf16_bits(v[6]) | (bf16_bits(v[7]) << 16));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -146,7 +174,16 @@ __global__ __launch_bounds__(256) void k_head_bwd(HeadBwdArgs a) {
   if (pre) {
 #pragma unroll
     for (int o = 0; o < 8; ++o) Fpre[o] = swp[8 * c0 + o];
-    for (int c = 0; c < c0; ++c) {
+    int c = 0;
+    for (; c + 8 <= c0; c += 8) {  // eight channels per load, the same FMA order
+      float v[8];
+      ld8(px + c, v);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int o = 0; o < 8; ++o) Fpre[o] = fmaf(swp[o * c0 + c + q], v[q], Fpre[o]);
+    }
+    for (; c < c0; ++c) {
       const float v = ldf(px + c);
 #pragma unroll
       for (int o = 0; o < 8; ++o) Fpre[o] = fmaf(swp[o * c0 + c], v, Fpre[o]);
@@ -258,14 +295,21 @@ __global__ __launch_bounds__(256) void k_head_bwd(HeadBwdArgs a) {
     float dpre[8];
 #pragma unroll
     for (int o = 0; o < 8; ++o) dpre[o] = Fpre[o] > 0.f ? dF[o] : 0.f;
-    for (int c = 0; c < a.c0_p; ++c) {
-      float s = 0.f;
-      if (c < c0) {
+    for (int c8 = 0; c8 < a.c0_p; c8 += 8) {  // c0_p is a multiple of 32
+      float d[8], sv[8];
+      if (a.mask_d0) ld8(px + c8, d);
 #pragma unroll
-        for (int o = 0; o < 8; ++o) s = fmaf(swp[o * c0 + c], dpre[o], s);
-        if (a.mask_d0 && !(ldf(px + c) > 0.f)) s = 0.f;
+      for (int q = 0; q < 8; ++q) {
+        const int c = c8 + q;
+        float s = 0.f;
+        if (c < c0) {
+#pragma unroll
+          for (int o = 0; o < 8; ++o) s = fmaf(swp[o * c0 + c], dpre[o], s);
+          if (a.mask_d0 && !(d[q] > 0.f)) s = 0.f;
+        }
+        sv[q] = s;
       }
-      stf(dd0 + c, s);
+      st8(dd0 + c8, sv);
     }
     const int NP = 8 * c0 + 8;
     float* dst = a.dwp_part + ((int64_t)b * per + pblk) * NP;
@@ -275,8 +319,7 @@ __global__ __launch_bounds__(256) void k_head_bwd(HeadBwdArgs a) {
       // sums as wave_sum); lane l ends with parameter (l / 8, cc + l % 8)
       for (int cc = 0; cc < c0; cc += 8) {
         float x[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = ldf(px + cc + q);
+        ld8(px + cc, x);
         float vals[64];
 #pragma unroll
         for (int q = 0; q < 64; ++q) vals[q] = dpre[q >> 3] * x[q & 7];
@@ -927,20 +970,30 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_bf16(WgradArgs a) {
       }
 }
 
-// canonical[w_off + (o cin + c) 9 + tap] = sum_s part[s][o][tap][cp(c)]
-__global__ void k_wgrad_reduce(const float* part, int splits, int cout, int cin, int cu, int cu_p, int cout_p,
-                               int cin_p, float* dst) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)cout * cin * 9) return;
-  const int tap = (int)(idx % 9);
-  const int c = (int)((idx / 9) % cin);
-  const int o = (int)(idx / (9LL * cin));
-  const int cp = c < cu ? c : cu_p + (c - cu);
+// canonical[(o cin + c) 9 + tap] = sum_s part[s][o][tap][cp(c)]: a workgroup
+// takes 64 consecutive part entries (so the reads are coalesced), wave w the
+// splits s = w mod 4 in order, then the four partial sums in a fixed order;
+// padded input channels are dropped.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* part, int splits, int cout, int cin, int cu,
+                                                      int cu_p, int cout_p, int cin_p, float* dst) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;  // (o, tap, cp) in [cout][9][cin_p]
+  const int64_t n = (int64_t)cout * 9 * cin_p;
   const int64_t stride = (int64_t)cout_p * 9 * cin_p;
-  const int64_t src = ((int64_t)o * 9 + tap) * cin_p + cp;
   float s = 0.f;
-  for (int k = 0; k < splits; ++k) s += part[k * stride + src];
-  dst[idx] = s;
+  if (j < n) {
+#pragma unroll 8
+    for (int k = w; k < splits; k += 4) s += part[k * stride + j];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < n) {
+    const int cp = (int)(j % cin_p), tap = (int)((j / cin_p) % 9), o = (int)(j / (9LL * cin_p));
+    // the upsampled channels first, then the skip channels, padding dropped
+    const int c = cp < cu ? cp : (cp >= cu_p && cp - cu_p < cin - cu) ? cu + (cp - cu_p) : -1;
+    if (c >= 0) dst[((int64_t)o * cin + c) * 9 + tap] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  }
 }
 
 int wgrad_bo(int cout_p) { return cout_p % 64 == 0 ? 64 : 32; }
@@ -993,8 +1046,8 @@ hipError_t launch_wgrad(int precision_x, int precision_g, int loader, const Wgra
 #undef OMNISEG_WG
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t n = (int64_t)cout * cin * 9;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.part, a.splits, cout,
+  const int64_t n = (int64_t)cout * 9 * a.cin_p;  // part entries of the real output channels
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, a.part, a.splits, cout,
                      cin, cu, a.cu_p, a.cout_p, a.cin_p, dst);
   return hipGetLastError();
 }
@@ -1056,12 +1109,20 @@ __global__ __launch_bounds__(256) void k_colsum(const T* dy, int64_t npix, int c
   }
 }
 
-__global__ void k_colsum_reduce(const float* part, int splits, int c_p, int cout, float* dst) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= cout) return;
+// dst[c] = sum_s part[s][c]: 64 channels per workgroup, wave w the splits
+// s = w mod 4 in order, then the four partial sums in a fixed order.
+__global__ __launch_bounds__(256) void k_colsum_reduce(const float* part, int splits, int c_p, int cout, float* dst) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int k = 0; k < splits; ++k) s += part[(int64_t)k * c_p + c];
-  dst[c] = s;
+  if (c < cout) {
+#pragma unroll 8
+    for (int k = w; k < splits; k += 4) s += part[(int64_t)k * c_p + c];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && c < cout) dst[c] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 int bias_grad_splits(int64_t npix) { return (int)std::max<int64_t>(1, std::min<int64_t>(kBiasGradSplits, npix / 1024)); }
@@ -1076,7 +1137,7 @@ hipError_t launch_bias_grad(int precision, const void* dy, int64_t npix, int c_p
     hipLaunchKernelGGL(k_colsum<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)dy, npix, c_p, splits, part);
   else
     hipLaunchKernelGGL(k_colsum<float>, grid, dim3(256), 0, st, (const float*)dy, npix, c_p, splits, part);
-  hipLaunchKernelGGL(k_colsum_reduce, dim3((cout + 255) / 256), dim3(256), 0, st, part, splits, c_p, cout, dst);
+  hipLaunchKernelGGL(k_colsum_reduce, dim3((cout + 63) / 64), dim3(256), 0, st, part, splits, c_p, cout, dst);
   return hipGetLastError();
 }
 
