@@ -1094,9 +1094,9 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_conv3x3_rows2(ConvArgs a) {
 }
 
 // Weight-stationary persistent form of the eight-wave row-reuse conv for
-// layers with 64 input channels (two 32-channel chunks), plain loader, bias
-// + ReLU or bias + residual + ReLU epilogue: in the bench network the
-// level-0 residual convs and the level-1 encoder conv_a, whose short K (two
+// layers with 64 input channels (two 32-channel chunks) and the plain
+// loader, any epilogue: in the bench network the level-0 residual convs, the
+// level-1 encoder conv_a and the level-0 data-gradient convs, whose short K (two
 // chunks) leaves a one-block-per-item kernel paying its first load and its
 // epilogue for every 16 x 16 pixel block.  One workgroup per CU keeps the
 // 64-channel weight block of its output channels in LDS (both chunks,
@@ -1115,7 +1115,8 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
   constexpr int WG = 9 * BN * 4 / 64;       // 64-slot groups of one weight chunk plane
   constexpr int WPLANE = WG * 64 * 16;      // bytes of a weight chunk plane
   static_assert(NCH * WPLANE + 2 * STAGE <= 160 * 1024, "weights and two halo stages fit the LDS");
-  static_assert(EPI == EPI_RELU || EPI == EPI_RES_RELU, "forward epilogues");
+  constexpr bool RES = EPI == EPI_RES_RELU || EPI == EPI_RES_MASK;  // residual = the conv's own input
+  constexpr bool BIAS_RELU = EPI == EPI_RELU || EPI == EPI_RES_RELU;
   __shared__ __attribute__((aligned(16))) char sWt[NCH * WPLANE];
   __shared__ __attribute__((aligned(16))) char sH0[STAGE];
   __shared__ __attribute__((aligned(16))) char sH1[STAGE];
@@ -1181,9 +1182,11 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
   T* out = (T*)a.y;
   float4 bb[FN];
 #pragma unroll
-  for (int fn = 0; fn < FN; ++fn) bb[fn] = *reinterpret_cast<const float4*>(a.bias + n0 + wn * NW + fn * 16 + g * 4);
+  for (int fn = 0; fn < FN; ++fn)
+    bb[fn] = BIAS_RELU ? *reinterpret_cast<const float4*>(a.bias + n0 + wn * NW + fn * 16 + g * 4)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
 
-  // the residual of pixel block i (RES): input channels c .. c + 3 (cin =
+  // the residual of pixel block i (RES, RES_MASK): input channels c .. c + 3 (cin =
   // cout) of the block's own pixels, halo pixel (row + 1, l16 + 1), chunk
   // c / 32, vector (c % 32) / 8.  Read into registers before the next
   // block's halo loads are issued, so that no LDS read of the epilogue
@@ -1225,19 +1228,34 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
           const int64_t o = (((int64_t)b * a.H + y0 + row) * a.W + x) * a.cout_p + n0 + c;
           const f32x4 s = acc[fm + h][fn];
           float* vv = v[h];
-          vv[0] = s[0] + bb[fn].x;
-          vv[1] = s[1] + bb[fn].y;
-          vv[2] = s[2] + bb[fn].z;
-          vv[3] = s[3] + bb[fn].w;
-          if (EPI == EPI_RES_RELU) {
+          vv[0] = s[0];
+          vv[1] = s[1];
+          vv[2] = s[2];
+          vv[3] = s[3];
+          if (BIAS_RELU) {
+            vv[0] += bb[fn].x;
+            vv[1] += bb[fn].y;
+            vv[2] += bb[fn].z;
+            vv[3] += bb[fn].w;
+          }
+          if (RES) {
             const uint2 rr = res[fm + h][fn];
             vv[0] += bf2f(rr.x & 0xffff);
             vv[1] += bf2f(rr.x >> 16);
             vv[2] += bf2f(rr.y & 0xffff);
             vv[3] += bf2f(rr.y >> 16);
           }
+          if (EPI == EPI_RES_MASK) {
+            const uint2 q = *reinterpret_cast<const uint2*>((const T*)a.aux + o);
+            if (!(bf2f(q.x & 0xffff) > 0.f)) vv[0] = 0.f;
+            if (!(bf2f(q.x >> 16) > 0.f)) vv[1] = 0.f;
+            if (!(bf2f(q.y & 0xffff) > 0.f)) vv[2] = 0.f;
+            if (!(bf2f(q.y >> 16) > 0.f)) vv[3] = 0.f;
+          }
+          if (BIAS_RELU) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) vv[j] = fmaxf(vv[j], 0.f);
+            for (int j = 0; j < 4; ++j) vv[j] = fmaxf(vv[j], 0.f);
+          }
           uint2 u;
           u.x = (uint32_t)f2bf(vv[0]) | ((uint32_t)f2bf(vv[1]) << 16);
           u.y = (uint32_t)f2bf(vv[2]) | ((uint32_t)f2bf(vv[3]) << 16);
@@ -1277,13 +1295,13 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
   // blocks q, q + per_nb, ... alternate between the stages (two arrays, so
   // that the loads into one are known not to touch the other)
   for (int i = q; i < total; i += 2 * per_nb) {
-    if (EPI == EPI_RES_RELU) residual(sH0);
+    if (RES) residual(sH0);
     if (i + per_nb < total) halo(i + per_nb, sH1);
     block(i, sH0);
     wait_halo();
     __syncthreads();
     if (i + per_nb >= total) break;
-    if (EPI == EPI_RES_RELU) residual(sH1);
+    if (RES) residual(sH1);
     if (i + 2 * per_nb < total) halo(i + 2 * per_nb, sH0);
     block(i + per_nb, sH1);
     wait_halo();
@@ -1296,10 +1314,12 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
 // blocks to keep one workgroup per CU busy.
 constexpr int kWsGrid = 256;
 inline bool ws_applies(int loader, int epi, const ConvLayer& L, int H, int W, int batch) {
-  return loader == LOAD_PLAIN && (epi == EPI_RELU || epi == EPI_RES_RELU) && L.cin_p == 64 && L.cout_p % 64 == 0 &&
-         L.cout_p / 64 <= 2 && (epi != EPI_RES_RELU || L.cout_p == 64) && H % 16 == 0 && W % 16 == 0 &&
-         (int64_t)batch * (H / 16) * (W / 16) >= 8 * kWsGrid;
+  const bool res = epi == EPI_RES_RELU || epi == EPI_RES_MASK;
+  return loader == LOAD_PLAIN && L.cin_p == 64 && L.cout_p % 64 == 0 && L.cout_p / 64 <= 4 &&
+         (!res || L.cout_p == 64) && H % 16 == 0 && W % 16 == 0 && (int64_t)batch * (H / 16) * (W / 16) >= 8 * kWsGrid;
 }
+// Workgroups of the weight-stationary form: a multiple of 8 per output-channel block, at most one per CU.
+inline int ws_grid(int n_nblk) { return 8 * n_nblk * (kWsGrid / (8 * n_nblk)); }
 
 // FP8 (E4M3) row-reuse form on v_mfma_scale_f32_32x32x64_f8f6f4 (unit block
 // scales): one MFMA is one tap of a 64-channel chunk for 32 output channels
@@ -1556,11 +1576,10 @@ static hipError_t launch_conv_rows_t(const ConvLayer& L, int H, int W, int batch
   a.pool_out = L.pool_out;
   a.batch = batch;
   if (L.pool_out && EPI != EPI_RES_RELU) return hipErrorInvalidValue;
-  if constexpr (BY == 16 && BN == 64 && WM == 4 && WN == 2 && LOADER == LOAD_PLAIN &&
-                (EPI == EPI_RELU || EPI == EPI_RES_RELU)) {
+  if constexpr (BY == 16 && BN == 64 && WM == 4 && WN == 2 && LOADER == LOAD_PLAIN) {
     if (ws_applies(LOADER, EPI, L, H, W, batch)) {
       a.tiles_y = H / 16;
-      hipLaunchKernelGGL((k_conv3x3_ws<EPI>), dim3(kWsGrid), dim3(512), 0, st, a);
+      hipLaunchKernelGGL((k_conv3x3_ws<EPI>), dim3(ws_grid(a.n_nblk)), dim3(512), 0, st, a);
       return hipGetLastError();
     }
   }

@@ -211,24 +211,38 @@ def test_large_block_form_equals_row_reuse_bit_for_bit(mode):
     assert outs[0][0].float().abs().sum() > 0
 
 
-@pytest.mark.parametrize("case", ["res_pool", "relu_two_blocks", "relu_one_block"])
+@pytest.mark.parametrize("case", ["res_pool", "relu_two_blocks", "relu_one_block", "dgrad_res_mask",
+                                  "dgrad_three_blocks"])
 def test_weight_stationary_form_equals_row_reuse_bit_for_bit(case):
-    """Eight-wave launches with 64 input channels, a forward epilogue and at
-    least 2048 pixel blocks run the persistent weight-stationary form (a
-    workgroup per CU walking pixel blocks, weights kept in LDS, residual read
-    from the staged halo).  Its sums are the row-reuse forms' in the same
-    order, so it equals the four-wave form (configuration 6) bit for bit,
-    including the fused pooled copy."""
+    """Eight-wave launches with 64 input channels and at least 2048 pixel
+    blocks run the persistent weight-stationary form (a workgroup per CU
+    walking pixel blocks, weights kept in LDS, residual read from the staged
+    halo), for forward and data-gradient epilogues and up to four 64-channel
+    output blocks.  Its sums are the row-reuse forms' in the same order, so it
+    equals the four-wave form (configuration 6) bit for bit, including the
+    fused pooled copy."""
     rng = np.random.default_rng(seed_of("ws", case))
-    n, H, W = (8, 256, 256) if case != "relu_two_blocks" else (32, 128, 128)
-    cin, cout = (64, 64) if case != "relu_two_blocks" else (64, 128)
+    n, H, W = (32, 128, 128) if case in ("relu_two_blocks", "dgrad_three_blocks") else (8, 256, 256)
+    cin, cout = {"relu_two_blocks": (64, 128), "dgrad_three_blocks": (192, 64)}.get(case, (64, 64))
     dev = lambda a: torch.from_numpy(np.asarray(a, np.float32)).to(DEV)
     Wt = q(rng.standard_normal((cout, cin, 3, 3)) * np.sqrt(2.0 / (9 * cin)), om.BF16)
     b = dev(rng.standard_normal(cout) * 0.1)
-    x = torch.from_numpy(rng.standard_normal((n, H, W, cin)).astype(np.float32)).to(torch.bfloat16).to(DEV)
-    mode = om.CONV_RES_RELU if case == "res_pool" else om.CONV_RELU
+    kw = {}
+    if case.startswith("dgrad"):
+        # the data gradient: input = the output gradient (cout = 64 channels)
+        x = torch.from_numpy(rng.standard_normal((n, H, W, cout)).astype(np.float32)).to(torch.bfloat16).to(DEV)
+        if case == "dgrad_res_mask":
+            mode = om.CONV_DGRAD_RES_MASK
+            kw = dict(aux=torch.from_numpy(rng.standard_normal((n, H, W, cin)).astype(np.float32)).to(torch.bfloat16).to(DEV))
+        else:
+            mode = om.CONV_DGRAD
+            kw = dict(cu=128)
+        b = None
+    else:
+        x = torch.from_numpy(rng.standard_normal((n, H, W, cin)).astype(np.float32)).to(torch.bfloat16).to(DEV)
+        mode = om.CONV_RES_RELU if case == "res_pool" else om.CONV_RELU
     pool = case == "res_pool"
-    outs = [om.conv3x3(om.BF16, mode, x, dev(Wt), b, config=c, pool=pool) for c in (10, 6)]
+    outs = [om.conv3x3(om.BF16, mode, x, dev(Wt), b, config=c, pool=pool, height=H, width=W, **kw) for c in (10, 6)]
     torch.cuda.synchronize()
     outs = [o if isinstance(o, tuple) else (o,) for o in outs]
     for a_, c_ in zip(outs[0], outs[1]):
