@@ -41,6 +41,10 @@ int32_t omniseg_merge_to_base(int32_t height, int32_t width, const omniseg_base_
     m.out = p.out;
     m.out_pitch = p.out_pitch;
     m.vec4 = (reinterpret_cast<uintptr_t>(p.out) % 4 == 0 && p.out_pitch % 4 == 0) ? 1 : 0;
+    m.vec16 = (reinterpret_cast<uintptr_t>(p.out) % 16 == 0 && p.out_pitch % 16 == 0) ? 1 : 0;
+    const uintptr_t src = bil ? reinterpret_cast<uintptr_t>(p.logit) : reinterpret_cast<uintptr_t>(p.mask);
+    const int64_t row_bytes = bil ? p.pitch * 4 : p.pitch;
+    m.vec_src = (src % 16 == 0 && row_bytes % 16 == 0) ? 1 : 0;
   }
   (void)hipGetLastError();
   HIP_TRY(launch_merge_base(a, n_planes, reinterpret_cast<hipStream_t>(stream)));

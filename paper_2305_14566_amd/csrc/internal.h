@@ -100,6 +100,8 @@ struct MergePlane {
   uint8_t* out;          // the 40x mask
   int64_t out_pitch;
   int vec4;              // out and out_pitch are multiples of 4: 4-byte stores
+  int vec16;             // out and out_pitch are multiples of 16: 16-byte stores
+  int vec_src;           // source rows start 16-byte aligned: vector loads
 };
 struct MergeArgs {
   int H, W;

@@ -463,15 +463,19 @@ def stitch_tiles_noalloc(tile, stride, height, width, tile_logits, tile_yx, mask
     return mask, logit
 
 
-def merge_to_base(height, width, planes, stream=None):
+def merge_to_base(height, width, planes, stream=None, outs=None):
     """Merge per-class planes to 40x masks.  planes: list of (k, mode, src)
     with src the scale-k uint8 mask (NEAREST) or float32 logit plane
-    (BILINEAR), 2-D device tensors.  Returns the 40x uint8 masks."""
+    (BILINEAR), 2-D device tensors.  outs: optional (height, width) uint8
+    device tensors (views with any row stride) to write into.  Returns the
+    40x uint8 masks."""
     n = len(planes)
     arr = (BasePlane * n)()
-    outs = []
+    given, outs = outs, []
     for i, (k, mode, src) in enumerate(planes):
-        out = torch.empty((height, width), dtype=torch.uint8, device=src.device)
+        out = torch.empty((height, width), dtype=torch.uint8, device=src.device) if given is None else given[i]
+        if tuple(out.shape) != (height, width) or out.dtype != torch.uint8 or out.stride(1) != 1:
+            raise ValueError("each output must be a (height, width) uint8 tensor with unit column stride")
         if mode == UPSAMPLE_BILINEAR:
             arr[i].logit = src.data_ptr()
         else:

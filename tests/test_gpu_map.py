@@ -45,6 +45,34 @@ def test_merge_to_base(H, W):
             assert np.array_equal(g[~risky], want[~risky])
 
 
+@pytest.mark.parametrize("H,W", [(64, 512), (97, 1000), (200, 4160), (1500, 96)])
+def test_merge_run_form_equals_pixel_form(H, W):
+    """Sixteen-pixel run form (contiguous outputs, aligned sources) against
+    the per-pixel form (outputs with an odd row stride), bit for bit, for
+    bilinear and nearest planes at k = 0..3, with aligned and unaligned
+    source rows; the comparison includes the pixels whose value is ~0.
+    At 1500 rows each workgroup takes a band of six rows, so the run form
+    carries source rows from one output row to the next."""
+    print(f"merge run vs pixel H={H} W={W}", flush=True)
+    rng = np.random.default_rng(3 * H + W)
+    planes = []
+    for k in range(4):
+        Hk, Wk = O.level_size(H, k), O.level_size(W, k)
+        for pad in (0, 3):  # pad 3: source rows not 16-byte aligned
+            lam = rng.standard_normal((Hk, Wk + pad)).astype(np.float32)
+            lam[rng.uniform(size=lam.shape) < 0.05] = 0.0
+            planes.append((k, om.UPSAMPLE_BILINEAR, torch.from_numpy(lam).to(DEV)[:, :Wk]))
+            m = (rng.uniform(size=(Hk, Wk + pad)) < 0.4).astype(np.uint8)
+            planes.append((k, om.UPSAMPLE_NEAREST, torch.from_numpy(m).to(DEV)[:, :Wk]))
+    fast = om.merge_to_base(H, W, planes)
+    wide = torch.zeros((len(planes), H, W + 1), dtype=torch.uint8, device=DEV)
+    slow = om.merge_to_base(H, W, planes, outs=[wide[i, :, :W] for i in range(len(planes))])
+    torch.cuda.synchronize()
+    for i, (f, s) in enumerate(zip(fast, slow)):
+        assert torch.equal(f, s), i
+    assert not wide[:, :, W].any()
+
+
 @pytest.mark.parametrize("H,W,in_place", [(64, 64, False), (203, 131, False), (5, 3, False), (130, 97, True),
                                            (130, 100, True), (37, 256, False)])
 def test_overlay_bit_exact(H, W, in_place):
