@@ -142,6 +142,8 @@ def conv_symbol(om, prec, stage, config, level=None):
         return f"omniseg::k_conv3x3_ws<{epi}>"
     if prec == "bf16" and config == 11:  # large-block row-reuse configuration
         return f"omniseg::k_conv3x3_rows2<{by}, {bn}, {wm}, {wn}, {loader}, {epi}>"
+    if prec == "bf16" and config == 12:  # its persistent form
+        return f"omniseg::k_conv3x3_rows2p<{by}, {bn}, {wm}, {wn}, {loader}, {epi}>"
     if prec == "bf16" and config >= 6:  # row-reuse configurations
         return f"omniseg::k_conv3x3_rows<{by}, {bn}, {wm}, {wn}, {loader}, {epi}>"
     t = "unsigned short" if prec == "bf16" else "float"
@@ -713,14 +715,18 @@ def finish_cpu_baseline(proc, workdir, timeout_s):
 # pinned so that every run launches the same kernels as the counter runs
 # behind MEASURED_TRAFFIC (omniseg_autotune swaps near-equal configurations
 # on timing noise).  Chosen per layer from this workload's own per-layer
-# profile (BF16 TFLOP/s in the 16-slide call, eight-wave 16 x 16 x 64 form
-# -> large-block 32 x 16 x 64 form): dec_a1 1267 -> 1302, dec_a2 1344 ->
-# 1402, dec_a3 1369 -> 1431; the large-block form loses on the residual
-# convs (enc_b2 1136 -> 1000, enc_b3 1258 -> 1214, dec_b2 1162 -> 1101) and
-# ties on dec_a0 and dec_b3, which keep the eight-wave form.
+# profile (BF16 TFLOP/s in the 16-slide call): the persistent large-block
+# form (32 x 16 x 64, configuration 12) against the eight-wave 16 x 16 x 64
+# form (10) and the one-block-per-workgroup large-block form (11): dec_a0
+# 1142 (10) -> 1328, dec_a1 1347 (11) -> 1482, dec_a3 1485 (11) -> 1560,
+# enc_a2 1004 -> 1091, enc_b2 1118 -> 1154, dec_b3 1319 -> 1374.  Configuration
+# 10 keeps the layers with 64 input channels (enc_b0, dec_b0, enc_a1: its
+# weight-stationary form) and level 4, whose 16-row tiles the 32-row block
+# does not fit.
 # Keys: (stage, level), stage 0 enc_a, 1 enc_b, 2 dec_a, 3 dec_b.
 BENCH_CONV_DEFAULT = 10
-BENCH_CONV_TABLE = {(2, 1): 11, (2, 2): 11, (2, 3): 11}
+BENCH_CONV_TABLE = {(2, 0): 12, (2, 1): 12, (2, 2): 12, (2, 3): 12, (1, 1): 12, (1, 2): 12, (1, 3): 12,
+                    (0, 2): 12, (0, 3): 12, (3, 1): 12, (3, 2): 12, (3, 3): 12}
 
 
 def pin_conv_table(plan):

@@ -653,11 +653,13 @@ int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable);
  * runs at.
  * Configurations 0..OMNISEG_CONV_CONFIGS-1 exist; ERR_ARG for any other id.
  * 0-5 run at FP32 and BF16; 6-9 (row-reuse forms) at BF16 and FP8; 10 (the
- * eight-wave row-reuse form) and 11 (the large-block row-reuse form: 32 x 16
+ * eight-wave row-reuse form), 11 (the large-block row-reuse form: 32 x 16
  * pixels x 64 channels, double-buffered direct-to-LDS staging, one workgroup
- * per CU) at BF16 only.  Every configuration sums the taps of a chunk in the
- * same order, so 6-11 give bit-identical BF16 results. */
-#define OMNISEG_CONV_CONFIGS 12
+ * per CU) and 12 (11 as a persistent launch: one workgroup per CU walks the
+ * blocks, the next block's first load and this block's epilogue overlapped)
+ * at BF16 only.  Every configuration sums the taps of a chunk in the same
+ * order, so 6-12 give bit-identical BF16 results. */
+#define OMNISEG_CONV_CONFIGS 13
 int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* bn, int32_t* wm,
                             int32_t* wn, int32_t* precisions);
 /*

@@ -197,6 +197,7 @@ enum ConvConfig {
   CONV_CFG_ROWS_16x16_32,
   CONV_CFG_ROWS8_16x16_64,  // eight waves (BF16)
   CONV_CFG_ROWS2_32x16_64,  // eight waves, double-buffered staging, register epilogue (BF16)
+  CONV_CFG_ROWS2P_32x16_64, // the same, persistent: one workgroup per CU walks the blocks (BF16)
   CONV_CFG_COUNT
 };
 bool conv_config_valid(int cfg, int precision, int H, int W, int cout_p);

@@ -905,6 +905,117 @@ __device__ __forceinline__ void rows_chunk(f32x4 (&acc)[FM][FN], const char* sX,
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// Epilogue of the eight-wave large-block forms on the accumulators: lane
+// (g, l16) of fragment (fm, fn) holds channels c .. c + 3 of pixel
+// (y0 + wm FM + fm, x0 + l16).  Bias, residual, sign gate and ReLU in that
+// order, BF16 rounding, 8-byte stores; the 2x2 max-pool takes the vertical
+// pair from the lane's own rows and the horizontal one from the
+// neighbouring lane.
+template <int FN, int NW, int EPI>
+__device__ __forceinline__ void rows2_bias(const ConvArgs& a, int n0, int wn, int g, float4 (&bb)[FN]) {
+#pragma unroll
+  for (int fn = 0; fn < FN; ++fn)
+    bb[fn] = (EPI == EPI_RELU || EPI == EPI_RES_RELU)
+                 ? *reinterpret_cast<const float4*>(a.bias + n0 + wn * NW + fn * 16 + g * 4)
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// The residual of every output piece of the lane (RES_RELU, RES_MASK: the
+// conv's own input at the output pixel and channels), read ahead of the
+// epilogue so that the loads are in flight together rather than each waited
+// for between the stores.
+template <int FM, int FN, int NW, int EPI>
+__device__ __forceinline__ void rows2_residual(const ConvArgs& a, int b, int y0, int x0, int n0, int wm, int wn,
+                                               int g, int l16, uint2 (&r)[FM][FN]) {
+  if constexpr (EPI == EPI_RES_RELU || EPI == EPI_RES_MASK) {
+    const uint16_t* res = (const uint16_t*)a.x0;
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) {
+        const int64_t o =
+            (((int64_t)b * a.H + y0 + wm * FM + fm) * a.W + x0 + l16) * a.cout_p + n0 + wn * NW + fn * 16 + g * 4;
+        r[fm][fn] = *reinterpret_cast<const uint2*>(res + o);
+      }
+  }
+}
+
+template <int FM, int FN, int NW, int EPI>
+__device__ __forceinline__ void rows2_epilogue(const ConvArgs& a, const f32x4 (&acc)[FM][FN], const float4 (&bias)[FN],
+                                               const uint2 (&resid)[FM][FN], int b, int y0, int x0, int n0, int wm,
+                                               int wn, int g, int l16) {
+  using T = uint16_t;
+  T* out = (T*)a.y;
+  const int x = x0 + l16;
+#pragma unroll
+  for (int fn = 0; fn < FN; ++fn) {
+    const int c = n0 + wn * NW + fn * 16 + g * 4;
+    const float4 bb = bias[fn];
+#pragma unroll
+    for (int fm = 0; fm < FM; fm += 2) {
+      float v[2][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int y = y0 + wm * FM + fm + h;
+        const int64_t o = (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + c;
+        const f32x4 s = acc[fm + h][fn];
+        float* vv = v[h];
+        vv[0] = s[0];
+        vv[1] = s[1];
+        vv[2] = s[2];
+        vv[3] = s[3];
+        if (EPI == EPI_RELU || EPI == EPI_RES_RELU) {
+          vv[0] += bb.x;
+          vv[1] += bb.y;
+          vv[2] += bb.z;
+          vv[3] += bb.w;
+        }
+        if (EPI == EPI_RES_RELU || EPI == EPI_RES_MASK) {
+          const uint2 r = resid[fm + h][fn];
+          vv[0] += bf2f(r.x & 0xffff);
+          vv[1] += bf2f(r.x >> 16);
+          vv[2] += bf2f(r.y & 0xffff);
+          vv[3] += bf2f(r.y >> 16);
+        }
+        if (EPI == EPI_RES_MASK) {
+          const uint2 q = *reinterpret_cast<const uint2*>((const T*)a.aux + o);
+          if (!(bf2f(q.x & 0xffff) > 0.f)) vv[0] = 0.f;
+          if (!(bf2f(q.x >> 16) > 0.f)) vv[1] = 0.f;
+          if (!(bf2f(q.y & 0xffff) > 0.f)) vv[2] = 0.f;
+          if (!(bf2f(q.y >> 16) > 0.f)) vv[3] = 0.f;
+        }
+        if (EPI == EPI_RELU || EPI == EPI_RES_RELU) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) vv[j] = fmaxf(vv[j], 0.f);
+        }
+        uint2 u;
+        u.x = (uint32_t)f2bf(vv[0]) | ((uint32_t)f2bf(vv[1]) << 16);
+        u.y = (uint32_t)f2bf(vv[2]) | ((uint32_t)f2bf(vv[3]) << 16);
+        *reinterpret_cast<uint2*>(out + o) = u;
+      }
+      if (a.pool_out) {
+        // rows y and y + 1 (y even: y0, wm FM and fm are even) in this lane,
+        // columns x and x ^ 1 in lanes l16 and l16 ^ 1; max commutes with the
+        // monotonic BF16 rounding, so this is the pool of the stored output
+        float m[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float t = fmaxf(v[0][j], v[1][j]);
+          m[j] = fmaxf(t, __shfl_xor(t, 1));
+        }
+        if ((l16 & 1) == 0) {
+          const int py = (y0 + wm * FM + fm) >> 1, px = x >> 1;
+          const int64_t o = (((int64_t)b * (a.H >> 1) + py) * (a.W >> 1) + px) * a.cout_p + c;
+          uint2 u;
+          u.x = (uint32_t)f2bf(m[0]) | ((uint32_t)f2bf(m[1]) << 16);
+          u.y = (uint32_t)f2bf(m[2]) | ((uint32_t)f2bf(m[3]) << 16);
+          *reinterpret_cast<uint2*>((T*)a.pool_out + o) = u;
+        }
+      }
+    }
+  }
+}
+
 // BF16 row-reuse form for large blocks: BY rows x 16 pixels x BN channels
 // with eight waves, one workgroup per CU.  The compute of a chunk is
 // k_conv3x3_rows's (same taps, same order, same MFMAs), so the results are
@@ -1018,78 +1129,147 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_conv3x3_rows2(ConvArgs a) {
     }
   }
 
-  // Epilogue on the accumulators: lane (g, l16) of fragment (fm, fn) holds
-  // channels c .. c + 3 of pixel (y0 + wm FM + fm, x0 + l16).
-  T* out = (T*)a.y;
-  const T* res = (const T*)a.x0;
-  const int x = x0 + l16;
+  float4 bb[FN];
+  rows2_bias<FN, NW, EPI>(a, n0, wn, g, bb);
+  uint2 resid[FM][FN];
+  rows2_residual<FM, FN, NW, EPI>(a, b, y0, x0, n0, wm, wn, g, l16, resid);
+  rows2_epilogue<FM, FN, NW, EPI>(a, acc, bb, resid, b, y0, x0, n0, wm, wn, g, l16);
+}
+
+// s_waitcnt vmcnt(N) for N < 64 (the count's two high bits sit at 15:14)
+template <int N>
+__device__ __forceinline__ void wait_vmem_below() {
+  static_assert(N >= 0 && N < 64, "six-bit count");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+}
+
+// Persistent form of k_conv3x3_rows2 for the loaders that stage by DMA and
+// an even number of input-channel chunks.  A fixed grid of one workgroup
+// per CU walks the launch's blocks (the XCD of workgroup w, w mod 8, takes a
+// contiguous range of them, so neighbouring blocks share its L2), and the
+// chunk pipeline runs on across blocks: the first chunk of a workgroup's next
+// block is loaded into the free stage while the last chunk of the current
+// one is computed, and the current block's epilogue runs while that load is
+// in flight.  A one-block-per-workgroup launch pays that load and that
+// epilogue with the CU otherwise idle.  Per block the MFMAs, their order and
+// the epilogue are k_conv3x3_rows2's, so the outputs equal it bit for bit.
+template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
+__global__ __launch_bounds__(64 * WM * WN, 2) void k_conv3x3_rows2p(ConvArgs a) {
+  using T = uint16_t;
+  constexpr int KC = 32;
+  constexpr int BX = 16, PX = BX + 2, NPIX = (BY + 2) * PX;
+  constexpr int FM = BY / WM;
+  constexpr int NW = BN / WN, FN = NW / 16;
+  constexpr int NT = 64 * WM * WN;
+  static_assert(WM * WN == 8 && BY % WM == 0 && NW % 16 == 0 && FM % 2 == 0, "wave layout");
+  static_assert(LOADER != LOAD_POOL, "the persistent form stages by DMA");
+  using DS = DmaStager<LOADER, NPIX, BN, NT>;
+  constexpr int XR = DS::X_ELEMS;
+  constexpr int STAGE = XR + 9 * BN * KC;
+  static_assert(2 * STAGE * (int)sizeof(T) <= 160 * 1024, "two staging buffers fit the LDS");
+  // Epilogue memory instructions issued after the next block's loads: its
+  // stores, its residual loads (waited for before use), and with a sign gate
+  // the gate's loads as well (then the wait covers everything).
+  constexpr bool EPI_LOADS = EPI == EPI_RES_MASK;
+  constexpr int EPI_STORES = FM * FN + FM / 2 * FN;  // outputs, and the pooled copy (fewer without one)
+  __shared__ __attribute__((aligned(16))) T sA[STAGE];
+  __shared__ __attribute__((aligned(16))) T sB[STAGE];
+
+  const int per_tile = a.tiles_y * a.tiles_x * a.n_nblk;
+  const int valid = max(0, min(a.batch, *a.count - a.chunk_base));
+  const int total = valid * per_tile;
+  const int per_xcd = gridDim.x / 8;
+  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const int lo = (int)((int64_t)xcd * total / 8), hi = (int)((int64_t)(xcd + 1) * total / 8);
+  int i = lo + slot;
+  if (i >= hi) return;
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WN, wn = wave % WN;
+  const int g = lane >> 4;
+  const int l16 = lane & 15;
+  const RowsOffsets ro = rows_offsets<FM>(wm * FM * PX + l16, wn * NW + l16, g, l16, wm);
+  const char* cA = reinterpret_cast<const char*>(sA);
+  const char* cB = reinterpret_cast<const char*>(sB);
+  constexpr int XB = XR * (int)sizeof(T);
+  const int nchunks = a.cin_p / KC;  // even (checked by the launch)
+
+  auto decode = [&](int j, int& b, int& y0, int& x0, int& n0) {
+    int rest = j;
+    n0 = (rest % a.n_nblk) * BN;
+    rest /= a.n_nblk;
+    x0 = (rest % a.tiles_x) * BX;
+    rest /= a.tiles_x;
+    y0 = (rest % a.tiles_y) * BY;
+    b = rest / a.tiles_y;
+  };
+  int b, y0, x0, n0;
+  decode(i, b, y0, x0, n0);
+  DS ds(a, b, wave, lane, y0, x0, n0);
+  ds.issue(a, 0, sA);
+  wait_vmem();
+  __syncthreads();
+  f32x4 acc[FM][FN];
+  while (true) {
 #pragma unroll
-  for (int fn = 0; fn < FN; ++fn) {
-    const int c = n0 + wn * NW + fn * 16 + g * 4;
-    float4 bb = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (EPI == EPI_RELU || EPI == EPI_RES_RELU) bb = *reinterpret_cast<const float4*>(a.bias + c);
+    for (int r = 0; r < FM; ++r)
 #pragma unroll
-    for (int fm = 0; fm < FM; fm += 2) {
-      float v[2][4];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int y = y0 + wm * FM + fm + h;
-        const int64_t o = (((int64_t)b * a.H + y) * a.W + x) * a.cout_p + c;
-        const f32x4 s = acc[fm + h][fn];
-        float* vv = v[h];
-        vv[0] = s[0];
-        vv[1] = s[1];
-        vv[2] = s[2];
-        vv[3] = s[3];
-        if (EPI == EPI_RELU || EPI == EPI_RES_RELU) {
-          vv[0] += bb.x;
-          vv[1] += bb.y;
-          vv[2] += bb.z;
-          vv[3] += bb.w;
-        }
-        if (EPI == EPI_RES_RELU || EPI == EPI_RES_MASK) {
-          const uint2 r = *reinterpret_cast<const uint2*>(res + o);
-          vv[0] += bf2f(r.x & 0xffff);
-          vv[1] += bf2f(r.x >> 16);
-          vv[2] += bf2f(r.y & 0xffff);
-          vv[3] += bf2f(r.y >> 16);
-        }
-        if (EPI == EPI_RES_MASK) {
-          const uint2 q = *reinterpret_cast<const uint2*>((const T*)a.aux + o);
-          if (!(bf2f(q.x & 0xffff) > 0.f)) vv[0] = 0.f;
-          if (!(bf2f(q.x >> 16) > 0.f)) vv[1] = 0.f;
-          if (!(bf2f(q.y & 0xffff) > 0.f)) vv[2] = 0.f;
-          if (!(bf2f(q.y >> 16) > 0.f)) vv[3] = 0.f;
-        }
-        if (EPI == EPI_RELU || EPI == EPI_RES_RELU) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) vv[j] = fmaxf(vv[j], 0.f);
-        }
-        uint2 u;
-        u.x = (uint32_t)f2bf(vv[0]) | ((uint32_t)f2bf(vv[1]) << 16);
-        u.y = (uint32_t)f2bf(vv[2]) | ((uint32_t)f2bf(vv[3]) << 16);
-        *reinterpret_cast<uint2*>(out + o) = u;
-      }
-      if (a.pool_out) {
-        // rows y and y + 1 (y even: y0, wm FM and fm are even) in this lane,
-        // columns x and x ^ 1 in lanes l16 and l16 ^ 1; max commutes with the
-        // monotonic BF16 rounding, so this is the pool of the stored output
-        float m[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float t = fmaxf(v[0][j], v[1][j]);
-          m[j] = fmaxf(t, __shfl_xor(t, 1));
-        }
-        if ((l16 & 1) == 0) {
-          const int py = (y0 + wm * FM + fm) >> 1, px = x >> 1;
-          const int64_t o = (((int64_t)b * (a.H >> 1) + py) * (a.W >> 1) + px) * a.cout_p + c;
-          uint2 u;
-          u.x = (uint32_t)f2bf(m[0]) | ((uint32_t)f2bf(m[1]) << 16);
-          u.y = (uint32_t)f2bf(m[2]) | ((uint32_t)f2bf(m[3]) << 16);
-          *reinterpret_cast<uint2*>((T*)a.pool_out + o) = u;
-        }
+      for (int f = 0; f < FN; ++f) acc[r][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int next = i + per_xcd;
+    const bool more = next < hi;
+    // the block's bias, read here so that the chunk loop's waits cover it
+    // and the epilogue need not wait for the next block's loads
+    float4 bb[FN];
+    rows2_bias<FN, NW, EPI>(a, n0, wn, g, bb);
+    // chunk ch is in sA for even ch, in sB for odd ch
+    __builtin_assume(nchunks >= 2);
+    for (int ch = 0; ch < nchunks; ch += 2) {
+      ds.issue(a, ch + 1, sB);
+      if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(1);
+      rows_chunk<FM, FN, BN>(acc, cA, cA + XB, ro);
+      if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(0);
+      wait_vmem();
+      __syncthreads();
+      if (ch + 2 < nchunks) {
+        ds.issue(a, ch + 2, sA);
+        if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(1);
+        rows_chunk<FM, FN, BN>(acc, cB, cB + XB, ro);
+        if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(0);
+        wait_vmem();
+        __syncthreads();
       }
     }
+    // the last chunk (in sB): the next block's first chunk goes into sA
+    // meanwhile, then this block's epilogue
+    int nb_, ny0, nx0, nn0;
+    if (more) {
+      decode(next, nb_, ny0, nx0, nn0);
+      ds = DS(a, nb_, wave, lane, ny0, nx0, nn0);
+      ds.issue(a, 0, sA);
+    }
+    if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(1);
+    rows_chunk<FM, FN, BN>(acc, cB, cB + XB, ro);
+    if (LOADER == LOAD_UPCAT) __builtin_amdgcn_s_setprio(0);
+    // a residual is read after the MFMAs (holding it through a chunk would
+    // spill); waiting for it waits for the loads issued above as well, which
+    // have had the chunk's compute to land
+    uint2 resid[FM][FN];
+    rows2_residual<FM, FN, NW, EPI>(a, b, y0, x0, n0, wm, wn, g, l16, resid);
+    rows2_epilogue<FM, FN, NW, EPI>(a, acc, bb, resid, b, y0, x0, n0, wm, wn, g, l16);
+    if (!more) break;
+    if (EPI_LOADS) {
+      wait_vmem();
+    } else {
+      if (a.pool_out) wait_vmem_below<EPI_STORES>();
+      else wait_vmem_below<FM * FN>();
+    }
+    __syncthreads();
+    i = next;
+    b = nb_;
+    y0 = ny0;
+    x0 = nx0;
+    n0 = nn0;
   }
 }
 
@@ -1618,6 +1798,46 @@ static hipError_t launch_conv_rows2_t(const ConvLayer& L, int H, int W, int batc
   return hipGetLastError();
 }
 
+// Workgroups of the persistent large-block form: one per CU.
+constexpr int kRows2pGrid = 256;
+
+template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
+static hipError_t launch_conv_rows2p_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
+                                       int chunk_base, const void* x0, const void* x1, const void* aux,
+                                       void* y, hipStream_t st) {
+  // the pooling loader, and an odd number of input-channel chunks, take the
+  // one-block-per-workgroup form
+  if constexpr (LOADER == LOAD_POOL) {
+    return launch_conv_rows2_t<BY, BN, WM, WN, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+  } else {
+    if ((L.cin_p / 32) % 2 != 0)
+      return launch_conv_rows2_t<BY, BN, WM, WN, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+    ConvArgs a{};
+    a.x0 = x0;
+    a.x1 = x1;
+    a.aux = aux;
+    a.y = y;
+    a.w = L.w;
+    a.bias = L.b;
+    a.H = H;
+    a.W = W;
+    a.cin_p = L.cin_p;
+    a.cu_p = L.cu_p;
+    a.cout_p = L.cout_p;
+    a.count = count;
+    a.chunk_base = chunk_base;
+    a.tiles_y = H / BY;
+    a.tiles_x = W / 16;
+    a.n_nblk = L.cout_p / BN;
+    a.pool_out = L.pool_out;
+    a.batch = batch;
+    if (L.pool_out && EPI != EPI_RES_RELU) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_conv3x3_rows2p<BY, BN, WM, WN, LOADER, EPI>), dim3(kRows2pGrid), dim3(64 * WM * WN), 0, st,
+                       a);
+    return hipGetLastError();
+  }
+}
+
 template <typename T, int BY, int BX, int BN, int WM, int WN, int LOADER, int EPI>
 static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
                                 int chunk_base, const void* x0, const void* x1, const void* aux,
@@ -1666,11 +1886,13 @@ static hipError_t launch_conv_t(const ConvLayer& L, int H, int W, int batch, con
 #define OMNISEG_CONV_ROW8_CONFIGS(X) X(CONV_CFG_ROWS8_16x16_64, 16, 16, 64, 4, 2)
 // Eight-wave large-block row-reuse configuration (BF16 only; k_conv3x3_rows2)
 #define OMNISEG_CONV_ROW2_CONFIGS(X) X(CONV_CFG_ROWS2_32x16_64, 32, 16, 64, 4, 2)
+// its persistent form (k_conv3x3_rows2p)
+#define OMNISEG_CONV_ROW2P_CONFIGS(X) X(CONV_CFG_ROWS2P_32x16_64, 32, 16, 64, 4, 2)
 
 static const int kCfgShape[][5] = {
 #define OMNISEG_SHAPE(id, by, bx, bn, wm, wn) {by, bx, bn, wm, wn},
     OMNISEG_CONV_TILE_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW8_CONFIGS(OMNISEG_SHAPE)
-        OMNISEG_CONV_ROW2_CONFIGS(OMNISEG_SHAPE)
+        OMNISEG_CONV_ROW2_CONFIGS(OMNISEG_SHAPE) OMNISEG_CONV_ROW2P_CONFIGS(OMNISEG_SHAPE)
 #undef OMNISEG_SHAPE
 };
 static_assert(sizeof(kCfgShape) / sizeof(kCfgShape[0]) == CONV_CFG_COUNT, "one shape per configuration");
@@ -1740,6 +1962,11 @@ static hipError_t launch_conv_cfg(int cfg, const ConvLayer& L, int H, int W, int
   case id:                                   \
     return launch_conv_rows2_t<by, bn, wm, wn, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
       OMNISEG_CONV_ROW2_CONFIGS(OMNISEG_CASE)
+#undef OMNISEG_CASE
+#define OMNISEG_CASE(id, by, bx, bn, wm, wn) \
+  case id:                                   \
+    return launch_conv_rows2p_t<by, bn, wm, wn, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+      OMNISEG_CONV_ROW2P_CONFIGS(OMNISEG_CASE)
 #undef OMNISEG_CASE
       default:
         break;

@@ -28,7 +28,7 @@ TISSUE_GRAY, TISSUE_OTSU = 0, 1
 ABI_VERSION = 7
 
 CONV_RELU, CONV_RES_RELU, CONV_POOL_RELU, CONV_UPCAT_RELU, CONV_DGRAD, CONV_DGRAD_RES_MASK = range(6)
-N_CONV_CONFIGS = 12
+N_CONV_CONFIGS = 13
 
 _lib = None
 

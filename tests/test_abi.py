@@ -380,7 +380,7 @@ def test_conv_config_query_and_precision_gate():
     configurations are BF16 only, and the stand-alone conv refuses a
     configuration at a precision it does not run at, or one that does not
     fit the shape, before any HIP call."""
-    assert om.N_CONV_CONFIGS == 12
+    assert om.N_CONV_CONFIGS == 13
     for c in range(om.N_CONV_CONFIGS):
         by, bx, bn, wm, wn, precs = om.conv_config_info(c)
         assert wm * wn in (4, 8) and by % 8 == 0 and bx in (8, 16) and bn % 32 == 0

@@ -172,16 +172,22 @@ def test_every_tile_configuration(prec, config, mode):
 
 
 @pytest.mark.parametrize("mode", ["relu", "res", "pool_out", "upcat", "pool_in", "dgrad", "dgrad_res"])
-def test_large_block_form_equals_row_reuse_bit_for_bit(mode):
+@pytest.mark.parametrize("size", ["small", "many_blocks"])
+def test_large_block_form_equals_row_reuse_bit_for_bit(mode, size):
     """The double-buffered large-block form (32 rows x 16 pixels x 64
-    channels, register epilogue) sums the same taps of the same chunks in
-    the same order as the eight-wave row-reuse form, so its outputs, and the
-    fused pooled copy, equal that form's bit for bit: here over 6 chunks,
-    two channel blocks and several pixel blocks per tile."""
-    big, ref_cfg = 11, 10
+    channels, register epilogue) and its persistent launch sum the same taps
+    of the same chunks in the same order as the eight-wave row-reuse form,
+    so their outputs, and the fused pooled copy, equal that form's bit for
+    bit: over 6 chunks, two channel blocks and several pixel blocks per tile.
+    "many_blocks" gives the persistent form's 256 workgroups 2-3 blocks each
+    (a number of blocks that the eight XCD ranges do not divide evenly), so
+    the next block's first chunk is loaded during the last chunk and the
+    epilogue of the current one."""
+    big, ref_cfg, pers = 11, 10, 12
     assert om.conv_config_info(big)[:5] == (32, 16, 64, 4, 2) and om.conv_config_info(ref_cfg)[:5] == (16, 16, 64, 4, 2)
-    rng = np.random.default_rng(seed_of("large-block", mode))
-    n, H, W, C = 3, 64, 96, 128
+    assert om.conv_config_info(pers)[:5] == (32, 16, 64, 4, 2)
+    rng = np.random.default_rng(seed_of("large-block", mode + size))
+    n, H, W, C = (3, 64, 96, 128) if size == "small" else (13, 96, 128, 128)
     dev = lambda a: torch.from_numpy(np.asarray(a, np.float32)).to(DEV)
     Wt = q(rng.standard_normal((C, 192 if mode == "upcat" else C, 3, 3)) * np.sqrt(2.0 / (9 * C)), om.BF16)
     b = dev(rng.standard_normal(C) * 0.1)
@@ -201,13 +207,14 @@ def test_large_block_form_equals_row_reuse_bit_for_bit(mode):
             kw = dict(aux=to_nhwc([q(rng.standard_normal((C, H, W)), om.BF16) for _ in range(n)], om.BF16))
     pool = mode == "pool_out"
     outs = []
-    for cfg in (ref_cfg, big):
+    for cfg in (ref_cfg, big, pers):
         r = om.conv3x3(om.BF16, m, x0, dev(Wt), None if mode.startswith("dgrad") else b, config=cfg, pool=pool,
                        height=H, width=W, **kw)
         outs.append(r if pool else (r,))
     torch.cuda.synchronize()
-    for a, c in zip(outs[0], outs[1]):
-        assert torch.equal(a.view(torch.int16), c.view(torch.int16))
+    for other in outs[1:]:
+        for a, c in zip(outs[0], other):
+            assert torch.equal(a.view(torch.int16), c.view(torch.int16))
     assert outs[0][0].float().abs().sum() > 0
 
 
