@@ -434,6 +434,7 @@ def train_leg(om, torch, rgb, gt, steps, batch=TRAIN_BATCH):
     flat = synth.training_init_weights(13, CFG["base"], CFG["levels"], C, len(scales), CFG["head_out"])
     plan = om.Plan(base=CFG["base"], levels=CFG["levels"], head_out=CFG["head_out"], n_classes=C, scales=scales,
                    tile=CFG["tile"], stride=CFG["stride"], precision=om.BF16, training=True)
+    pin_conv_table(plan)  # the forward convs; the backward's take the library's default per layer
     slide = torch.from_numpy(rgb).to(dev)
     y = torch.from_numpy(synth.soft_targets(gt, scales, PAIRS)).to(dev)
     offs = plan.plane_offsets(slide, PAIRS)

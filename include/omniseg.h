@@ -656,9 +656,11 @@ int32_t omniseg_set_profiling(omniseg_plan* plan, int32_t enable);
  * eight-wave row-reuse form), 11 (the large-block row-reuse form: 32 x 16
  * pixels x 64 channels, double-buffered direct-to-LDS staging, one workgroup
  * per CU) and 12 (11 as a persistent launch: one workgroup per CU walks the
- * blocks, the next block's first load and this block's epilogue overlapped)
- * at BF16 only.  Every configuration sums the taps of a chunk in the same
- * order, so 6-12 give bit-identical BF16 results. */
+ * blocks, the next block's first load and this block's epilogue overlapped;
+ * the max-pooling loader runs as 10) at BF16 only.  Every configuration sums
+ * the taps of a chunk in the same order, so 6-12 give bit-identical BF16
+ * results.  Without a configuration (-1) a BF16 conv takes 12 where it fits
+ * and the layer has other than 64 input channels, else 10. */
 #define OMNISEG_CONV_CONFIGS 13
 int32_t omniseg_conv_config(int32_t config, int32_t* by, int32_t* bx, int32_t* bn, int32_t* wm,
                             int32_t* wn, int32_t* precisions);

@@ -1805,10 +1805,11 @@ template <int BY, int BN, int WM, int WN, int LOADER, int EPI>
 static hipError_t launch_conv_rows2p_t(const ConvLayer& L, int H, int W, int batch, const int32_t* count,
                                        int chunk_base, const void* x0, const void* x1, const void* aux,
                                        void* y, hipStream_t st) {
-  // the pooling loader, and an odd number of input-channel chunks, take the
-  // one-block-per-workgroup form
+  // the pooling loader (whose register staging does not fit beside the
+  // large block's accumulators) takes the eight-wave 16-row form, an odd
+  // number of input-channel chunks the one-block-per-workgroup large block
   if constexpr (LOADER == LOAD_POOL) {
-    return launch_conv_rows2_t<BY, BN, WM, WN, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
+    return launch_conv_rows_t<16, BN, WM, WN, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
   } else {
     if ((L.cin_p / 32) % 2 != 0)
       return launch_conv_rows2_t<BY, BN, WM, WN, LOADER, EPI>(L, H, W, batch, count, chunk_base, x0, x1, aux, y, st);
@@ -2023,7 +2024,16 @@ static hipError_t launch_fp8_mode(int cfg, int loader, int epi, const ConvLayer&
 hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L, int H, int W,
                           int batch, const int32_t* count, int chunk_base, const void* x0,
                           const void* x1, void* y, hipStream_t st, const void* aux, int cfg) {
-  if (cfg < 0 || !conv_config_valid(cfg, precision, H, W, L.cout_p)) cfg = conv_default_config(precision, H, W, L.cout_p);
+  if (cfg < 0 || !conv_config_valid(cfg, precision, H, W, L.cout_p)) {
+    cfg = conv_default_config(precision, H, W, L.cout_p);
+    // BF16 launches that come with no configuration (the training backward,
+    // the stand-alone call with -1) take the persistent large-block form
+    // where it fits, except for 64 input channels, where the eight-wave
+    // configuration's weight-stationary form is faster
+    if (precision == OMNISEG_BF16 && loader != LOAD_POOL && L.cin_p != 64 &&
+        conv_config_valid(CONV_CFG_ROWS2P_32x16_64, precision, H, W, L.cout_p))
+      cfg = CONV_CFG_ROWS2P_32x16_64;
+  }
   if (cfg < 0) return hipErrorInvalidValue;
   if (precision == OMNISEG_FP8) return launch_fp8_mode(cfg, loader, epi, L, H, W, batch, count, chunk_base, x0, x1, y, st);
   if (precision == OMNISEG_BF16)
