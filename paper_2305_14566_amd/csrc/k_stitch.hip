@@ -320,21 +320,46 @@ __global__ __launch_bounds__(256) void k_stitch(StitchArgs a) {
   for (int y = blockIdx.y; y < a.Hk; y += gridDim.y) stitch_pixel(a, x, y);
 }
 
-// One thread per four pixels (see stitch_span4); the row's ragged end goes
-// pixel by pixel.  TWO: at most 2 x 2 covering tiles (T <= 2 s).
+// The first row after y at which the covering tiles of a row can change:
+// the next multiple of s (the last covering tile row, y / s) or the next
+// T + k s (the first, (y - T) / s + 1).
+__device__ __forceinline__ int cover_change(int y, int T, int s) {
+  const int a = (y / s + 1) * s;
+  const int b = y < T ? T : T + ((y - T) / s + 1) * s;
+  return min(a, b);
+}
+
+// One thread per four pixels (see stitch_span4) in each row of a band of
+// consecutive rows (blockIdx.y picks the band); the row's ragged end goes
+// pixel by pixel.  TWO: at most 2 x 2 covering tiles (T <= 2 s); the band is
+// then cut where the covering tiles change, and each piece reads its tile
+// indices once (stitch_rows4_2x2).
 template <bool TWO>
 __global__ __launch_bounds__(256) void k_stitch4(StitchArgs a) {
   const int x0 = (blockIdx.x * 256 + threadIdx.x) * 4;
   if (x0 >= a.Wk) return;
-  for (int y = blockIdx.y; y < a.Hk; y += gridDim.y) {
-    if (x0 + 3 < a.Wk) {
-      if (TWO) stitch_span4_2x2(a, x0, y);
-      else stitch_span4(a, x0, y);
+  const int rows = (a.Hk + gridDim.y - 1) / gridDim.y;
+  const int ylo = blockIdx.y * rows, yhi = min(a.Hk, ylo + rows);
+  if (x0 + 3 < a.Wk) {
+    if (TWO) {
+      for (int y = ylo; y < yhi;) {
+        const int ye = min(yhi, cover_change(y, a.T, a.s));
+        stitch_rows4_2x2(a, x0, y, ye);
+        y = ye;
+      }
     } else {
-      for (int x = x0; x < a.Wk; ++x) stitch_pixel(a, x, y);
+      for (int y = ylo; y < yhi; ++y) stitch_span4(a, x0, y);
     }
+  } else {
+    for (int y = ylo; y < yhi; ++y)
+      for (int x = x0; x < a.Wk; ++x) stitch_pixel(a, x, y);
   }
 }
+
+// Bands of up to eight rows, as long as the launch keeps at least about
+// four thousand workgroups (a small plane goes row by row).
+constexpr int kStitchMinBlocks = 4096;
+constexpr int kStitchBandRows = 8;
 
 hipError_t launch_stitch(const StitchArgs& a, hipStream_t st) {
   if (a.Hk <= 0 || a.Wk <= 0) return hipSuccess;
@@ -345,7 +370,9 @@ hipError_t launch_stitch(const StitchArgs& a, hipStream_t st) {
                      reinterpret_cast<uintptr_t>(a.logits) % 16 == 0 &&
                      (!a.logit || reinterpret_cast<uintptr_t>(a.logit) % 4 == 0);
   if (span4) {
-    dim3 grid(ceil_div(a.Wk, 1024), std::min(a.Hk, kMaxGridY));
+    const int gx = ceil_div(a.Wk, 1024);
+    const int gy = std::min(a.Hk, std::max(ceil_div(a.Hk, kStitchBandRows), ceil_div(kStitchMinBlocks, gx)));
+    dim3 grid(gx, gy);
     // a logit plane's float offsets inside a tile must fit the 32-bit byte
     // offsets of the buffer loads
     if (a.T <= 2 * a.s && a.tile_stride * 4 <= INT32_MAX)
