@@ -8,7 +8,9 @@
 // theta split as W1 (8x8), W2 (8x8), W3 (o x 8), b1, b2, b3.  The class logit
 // is z_0 for one output and z_1 - z_0 for two.  F = ReLU(W_p D_0 + b_p) when
 // the decoder's last level has C_0 != 8 channels, else D_0 itself.  All head
-// arithmetic is FP32.  The precls weights and a tile's generated head
+// arithmetic is FP32 (with BF16 D_0 and C_0 <= 64 the precls product runs on
+// MFMA with each weight split into three exact BF16 terms, see
+// precls_bf16_mfma).  The precls weights and a tile's generated head
 // parameters are the same for every thread of a workgroup, so the head reads
 // them as scalar (constant-cache) loads and uses them as FMA operands.
 #include "internal.h"
@@ -162,6 +164,74 @@ hipError_t launch_controller(const float* g, int batch, int G, const float* wc, 
   return hipGetLastError();
 }
 
+typedef __attribute__((ext_vector_type(4))) float hf32x4;
+typedef __attribute__((ext_vector_type(8))) __bf16 hbf16x8;
+
+// BF16 code of f, rounded to nearest even (f finite).
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// BF16 precls F = ReLU(W_p D_0 + b_p) on MFMA (C_0 padded to 32 or 64).
+// Each FP32 weight is split into three BF16 terms, w = hi + mid + lo
+// exactly (hi = bf16(w), mid = bf16(w - hi), lo = w - hi - mid, which has at
+// most eight significant bits), so the products with the BF16 D_0 are exact
+// and the sum runs in FP32 inside v_mfma_f32_16x16x32_bf16: A = the weights
+// (row o < 8, zero rows 8-15), B = 16 pixels' 32 channels.  Wave w takes
+// the block's pixels 64 w .. 64 w + 63 in four 16-pixel groups; lane
+// (g, l16) of a group's result holds outputs 4 g .. 4 g + 3 of pixel l16,
+// which go through LDS to the pixel's own thread.
+__device__ __forceinline__ void precls_bf16_mfma(const uint16_t* __restrict__ blk, int c0, int c0_p,
+                                                 const float* __restrict__ wp, const float* bp, float (&F)[8]) {
+  __shared__ hf32x4 sF[256 * 2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nk = c0_p / 32;
+  uint4 A[2][3];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    uint32_t t[3][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = 32 * h + 8 * g + j;
+      const float w = (h < nk && l16 < 8 && c < c0) ? wp[l16 * c0 + c] : 0.f;
+      const uint32_t hi = bf16_rne(w);
+      const float r1 = w - __uint_as_float(hi << 16);
+      const uint32_t mid = bf16_rne(r1);
+      t[0][j] = hi;
+      t[1][j] = mid;
+      t[2][j] = bf16_rne(r1 - __uint_as_float(mid << 16));
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      A[h][q] = make_uint4(t[q][0] | (t[q][1] << 16), t[q][2] | (t[q][3] << 16), t[q][4] | (t[q][5] << 16),
+                           t[q][6] | (t[q][7] << 16));
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint16_t* p = blk + (int64_t)(wave * 64 + r * 16 + l16) * c0_p + 8 * g;
+    uint4 B[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) B[h] = h < nk ? *reinterpret_cast<const uint4*>(p + 32 * h) : make_uint4(0, 0, 0, 0);
+    hf32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(hbf16x8, A[h][q]),
+                                                      __builtin_bit_cast(hbf16x8, B[h]), acc, 0, 0, 0);
+    if (g < 2) sF[(wave * 64 + r * 16 + l16) * 2 + g] = acc;
+  }
+  const hf32x4 f0 = sF[threadIdx.x * 2], f1 = sF[threadIdx.x * 2 + 1];
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    F[o] = fmaxf(f0[o] + bp[o], 0.f);
+    F[o + 4] = fmaxf(f1[o] + bp[o + 4], 0.f);
+  }
+}
+
 // One thread per pixel of one tile; all the tile's slots in one pass.
 constexpr int kHeadChunk = 128;  // bytes of D_0 per pixel staged at a time
 
@@ -193,7 +263,15 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
   const T* px = d0 + ((int64_t)b * T2 + pix) * c0_p;
   constexpr int V = 16 / sizeof(T);
   float F[8];
-  if (pre && sizeof(T) < 4) {
+  bool done = false;
+  if constexpr (std::is_same<T, uint16_t>::value) {
+    if (pre && c0_p <= 64) {
+      precls_bf16_mfma(d0 + ((int64_t)b * T2 + (blockIdx.x % per_tile) * 256) * c0_p, c0, c0_p, wp, bp, F);
+      done = true;
+    }
+  }
+  if (done) {
+  } else if (pre && sizeof(T) < 4) {
 #pragma unroll
     for (int o = 0; o < 8; ++o) F[o] = bpc[o];
     // Whole 16-byte vectors first, the next one loaded while this one's FMAs
