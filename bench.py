@@ -350,8 +350,9 @@ def paper_leg(om, torch, M, dslide, size, steps, batch_tiles):
 def mapping_leg(om, torch, dslide, flat_dev, size, reps, batch_tiles):
     """Slide-wise aggregation and mapping on the single slide: each class's
     stitched logits at its best scale merged to a 40x mask (bilinear), then
-    the six-colour overlay on the 40x slide and its 10x map.  Timed with HIP
-    events on the launch stream over `reps` repetitions."""
+    the six-colour overlay on the 40x slide and its 10x map; and the
+    stand-alone stitch of one 40x plane from all its grid tiles.  Timed with
+    HIP events on the launch stream over `reps` back-to-back repetitions."""
     plan = _plan(om, "bf16", batch_tiles, emit_logits=True)
     packed = plan.pack(flat_dev)
     masks, logits, _ = plan.segment([dslide], PAIRS, packed)
@@ -380,6 +381,24 @@ def mapping_leg(om, torch, dslide, flat_dev, size, reps, batch_tiles):
     torch.cuda.synchronize()
     t_merge = ev[0].elapsed_time(ev[1]) / reps
     t_over = ev[1].elapsed_time(ev[2]) / reps
+    # the stand-alone stitch of one 40x plane from all its grid tiles (random
+    # logits), the plane-wise form of the segment call's streamed stitch
+    T, s_ = CFG["tile"], CFG["stride"]
+    ny = (H - T + s_ - 1) // s_ + 1
+    yx = torch.tensor([(j // ny, j % ny) for j in range(ny * ny)], dtype=torch.int32, device=dslide.device)
+    g = torch.Generator(device=dslide.device)
+    g.manual_seed(17)
+    tl = torch.randn((ny * ny, T, T), generator=g, device=dslide.device)
+    om.stitch_tiles(T, s_, H, W, tl, yx, emit_logits=True)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(reps):
+        om.stitch_tiles(T, s_, H, W, tl, yx, emit_logits=True)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_stitch = ev[0].elapsed_time(ev[1]) / reps
+    stitch_bytes = 4 * ny * ny * T * T + 5 * H * W  # every tile logit once; mask and logit out
+    del tl
     px = H * W
     merge_bytes = sum(4 * ((H + (1 << k) - 1) >> k) * ((W + (1 << k) - 1) >> k) + px for k, _, _ in planes)
     over_bytes = 3 * px + len(m40) * px + 3 * px + 3 * ((H + 3) // 4) * ((W + 3) // 4)
@@ -393,6 +412,13 @@ def mapping_leg(om, torch, dslide, flat_dev, size, reps, batch_tiles):
             "overlay_roofline": dict(bound="hbm", achieved=over_bytes / (t_over * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
                                      unit="GB/s", frac=over_bytes / (t_over * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                      traffic=None, algorithmic_bytes=over_bytes),
+            "stitch_standalone": {"workload": f"omniseg_stitch_tiles: one {H}x{W} 40x plane from all its {ny * ny} "
+                                              f"grid tiles ({T}^2 at stride {s_}, random logits), mask and logit out",
+                                  "ms": t_stitch,
+                                  "roofline": dict(bound="hbm", achieved=stitch_bytes / (t_stitch * 1e-3) / 1e9,
+                                                   peak=HBM_PEAK_GBS, unit="GB/s",
+                                                   frac=stitch_bytes / (t_stitch * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                                   traffic=None, algorithmic_bytes=stitch_bytes)},
             "class_pixels_40x": [int(m.sum().item()) for m in m40]}
 
 
@@ -1069,7 +1095,8 @@ def run(args, workdir, proc, log):
         log(f"paper tiling: {out['paper_tiling']['ms_per_step']:.1f} ms/step")
     if args.map_reps > 0:
         out["mapping"] = mapping_leg(om, torch, dslide, flat_dev, SLIDE, args.map_reps, args.batch_tiles)
-        log(f"mapping: merge {out['mapping']['merge_ms']:.2f} ms, overlay {out['mapping']['overlay_ms']:.2f} ms")
+        log(f"mapping: merge {out['mapping']['merge_ms']:.2f} ms, overlay {out['mapping']['overlay_ms']:.2f} ms, "
+            f"stand-alone stitch {out['mapping']['stitch_standalone']['ms']:.3f} ms")
 
     # 6. the CPU oracle: cpu_baseline and the FP64 crop
     cpu = None
