@@ -207,7 +207,7 @@ def test_large_block_form_equals_row_reuse_bit_for_bit(mode, size):
             kw = dict(aux=to_nhwc([q(rng.standard_normal((C, H, W)), om.BF16) for _ in range(n)], om.BF16))
     pool = mode == "pool_out"
     outs = []
-    for cfg in (ref_cfg, big, pers):
+    for cfg in (ref_cfg, big, pers, -1):  # -1: the library's default for the layer
         r = om.conv3x3(om.BF16, m, x0, dev(Wt), None if mode.startswith("dgrad") else b, config=cfg, pool=pool,
                        height=H, width=W, **kw)
         outs.append(r if pool else (r,))

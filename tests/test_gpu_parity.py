@@ -62,8 +62,13 @@ def _compare_planes(gpu_mask, gpu_logit, ref_mask, ref_logit, tol, ref_N=None):
 @pytest.mark.parametrize("H,W,T,s,keep", [(300, 217, 64, 32, 0.7), (128, 128, 128, 64, 1.0),
                                           (97, 250, 32, 16, 0.5), (64, 64, 64, 64, 1.0),
                                           (200, 130, 64, 64, 0.8), (5, 3, 16, 8, 1.0),
-                                          (150, 133, 32, 7, 0.8), (66, 70, 16, 6, 0.9)])
+                                          (150, 133, 32, 7, 0.8), (66, 70, 16, 6, 0.9),
+                                          (36002, 22, 16, 12, 0.9)])
 def test_stitch_tiles_matches_oracle(H, W, T, s, keep):
+    """The last shape is tall enough that the four-pixel form takes bands of
+    eight rows per workgroup, cut where the covering tiles change (every 12
+    rows, offset by 16): pieces shorter than a band, a ragged last band and a
+    ragged last column group."""
     rng = np.random.default_rng(H * 1000 + W)
     ny, nx = O.grid_count(H, T, s), O.grid_count(W, T, s)
     tiles = [(jy, jx) for jy in range(ny) for jx in range(nx) if rng.uniform() < keep]
