@@ -40,6 +40,10 @@ struct TrainLayout {
 
 constexpr int64_t kWgradPartBudget = 64LL << 20;  // bytes of split-K partials per conv
 
+// Split count of the first conv's weight gradient over the batch's tile
+// rows (a few rows per split).
+int first_wgrad_splits(int64_t rows) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, rows / 4)); }
+
 int wgrad_splits(int cout_p, int cin_p, int n_chunks) {
   const int blocks = (cout_p / wgrad_bo(cout_p)) * (cin_p / 32);
   int s = std::max(1, (1024 + blocks - 1) / blocks);
@@ -142,11 +146,8 @@ void train_layout(const omniseg_plan* plan, TrainLayout& lay) {
     const int s = wgrad_splits(d.cout_p, d.cin_p, chunks);
     wmax = std::max(wmax, (int64_t)s * d.cout_p * 9 * d.cin_p * 4);
   };
-  {
-    const int chunks = n * (T / 8) * (T / 16);
-    const int s = wgrad_splits(plan->Cp[0], 32, chunks);
-    wmax = std::max(wmax, (int64_t)s * plan->Cp[0] * 9 * 32 * 4);
-  }
+  // the first conv: splits x cout_p x 9 taps x 4 (3 channels padded)
+  wmax = std::max(wmax, (int64_t)first_wgrad_splits((int64_t)n * T) * plan->Cp[0] * 9 * 4 * 4);
   for (int l = 0; l < L; ++l) {
     if (l > 0) acc_w(plan->enc_a[l], T >> l);
     acc_w(plan->enc_b[l], T >> l);
@@ -588,8 +589,10 @@ int32_t omniseg_backward(const omniseg_plan* plan, const void* packed, const omn
       ConvDesc d0{};
       d0.cout = plan->C[0];
       d0.cout_p = plan->Cp[0];
-      OMNISEG_CALL(wgrad(d0, LOAD_PLAIN, OMNISEG_FP32, ws + lay.off_x, nullptr, bufQ, T, 3, 32, 3, 32,
-                         gw + plan->canon_first_w));
+      // 3 input channels: a kernel of its own rather than the 32-channel one
+      HIP_TRY(launch_wgrad_first(prec, reinterpret_cast<const float*>(ws + lay.off_x), 32, bufQ, n, T, d0.cout,
+                                 d0.cout_p, wpart, first_wgrad_splits((int64_t)n * T),
+                                 gw + plan->canon_first_w, sm));
       OMNISEG_CALL(bias(d0, bufQ, T, gw + plan->canon_first_b));
     } else {
       const ConvDesc& ea = plan->enc_a[l];

@@ -420,6 +420,11 @@ struct WgradArgs {
 int wgrad_bo(int cout_p);
 hipError_t launch_wgrad(int precision_x, int precision_g, int loader, const WgradArgs& a, int cout, int cin,
                         int cu, float* dst, hipStream_t st);
+// The first conv's weight gradient (3 input channels in FP32, padded to x_cp
+// per pixel; dY in precision_g with cout_p channels) into dst[cout][3][9],
+// through `splits` partials of cout_p * 36 floats each.
+hipError_t launch_wgrad_first(int precision_g, const float* x, int x_cp, const void* dy, int n, int T, int cout,
+                              int cout_p, float* part, int splits, float* dst, hipStream_t st);
 // Split count of the bias gradient over npix pixels (at most kBiasGradSplits).
 constexpr int kBiasGradSplits = 512;
 int bias_grad_splits(int64_t npix);

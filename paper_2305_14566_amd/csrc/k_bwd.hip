@@ -998,6 +998,127 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* part, int spl
 
 int wgrad_bo(int cout_p) { return cout_p % 64 == 0 ? 64 : 32; }
 
+// Weight gradient of the first conv (3 input channels, stored padded to
+// x_cp): dW[o][c][ky][kx] = sum over pixels of dY[p][o] X[p + (ky - 1,
+// kx - 1)][c], zero outside the tile.  The general kernel would run it as
+// 32 input channels.  Here split `blockIdx.x` takes an equal range of the
+// batch's tile rows and blockIdx.y a block of 64 output channels.  A row is
+// taken in segments of 64 pixels: the segment's dY (64 pixels x 64
+// channels, as FP32) and the three X rows around it (66 pixels x 3
+// channels, zero outside the tile) are staged in LDS, then thread (ky, o)
+// of wave ky runs along the segment with a three-pixel window of X row ky,
+// nine FMAs per pixel, in pixel order.  part[split][o][tap][c] (c padded to
+// 4) is reduced over the splits in order by k_wgrad_reduce.
+constexpr int kFirstSeg = 64;
+
+template <typename TG>
+__global__ __launch_bounds__(256) void k_wgrad_first(const float* __restrict__ x, int x_cp, const TG* __restrict__ dy,
+                                                     int cout_p, int T, int64_t rows, float* part) {
+  constexpr int S = kFirstSeg, VEC = 16 / (int)sizeof(TG), NV = 64 / VEC;
+  __shared__ float sG[S][64];
+  __shared__ float sX[3][S + 2][3];
+  const int tid = threadIdx.x, lane = tid & 63, ky = tid >> 6;
+  const int ob = blockIdx.y * 64, o = ob + lane;
+  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(rows, r0 + per);
+  float acc[3][3];
+#pragma unroll
+  for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[kx][c] = 0.f;
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t b = r / T;
+    const int y = (int)(r % T);
+    for (int x0 = 0; x0 < T; x0 += S) {
+      const int len = min(S, T - x0);
+      __syncthreads();  // the previous segment has been read
+      for (int v = tid; v < S * NV; v += 256) {
+        const int px = v / NV, j = v % NV;
+        float g[VEC];
+        if (px < len && ob + j * VEC < cout_p) {
+          const uint4 u = *reinterpret_cast<const uint4*>(dy + ((b * T + y) * T + x0 + px) * cout_p + ob + j * VEC);
+          if constexpr (VEC == 8) {
+            const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              g[2 * k] = __uint_as_float(w[k] << 16);
+              g[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+            }
+          } else {
+            g[0] = __uint_as_float(u.x);
+            g[1] = __uint_as_float(u.y);
+            g[2] = __uint_as_float(u.z);
+            g[3] = __uint_as_float(u.w);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) g[k] = 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) sG[px][j * VEC + k] = g[k];
+      }
+      for (int v = tid; v < 3 * (S + 2) * 3; v += 256) {
+        const int rr = v / ((S + 2) * 3), i = (v / 3) % (S + 2), c = v % 3;
+        const int yy = y + rr - 1, xx = x0 + i - 1;
+        float val = 0.f;
+        if (yy >= 0 && yy < T && xx >= 0 && xx < T) val = x[((b * T + yy) * T + xx) * x_cp + c];
+        sX[rr][i][c] = val;
+      }
+      __syncthreads();
+      if (ky < 3) {
+        float w0[3], w1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          w0[c] = sX[ky][0][c];
+          w1[c] = sX[ky][1][c];
+        }
+#pragma unroll 8
+        for (int i = 0; i < len; ++i) {
+          const float g = sG[i][lane];
+          float w2[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            w2[c] = sX[ky][i + 2][c];
+            acc[0][c] = fmaf(g, w0[c], acc[0][c]);
+            acc[1][c] = fmaf(g, w1[c], acc[1][c]);
+            acc[2][c] = fmaf(g, w2[c], acc[2][c]);
+            w0[c] = w1[c];
+            w1[c] = w2[c];
+          }
+        }
+      }
+    }
+  }
+  if (ky < 3 && o < cout_p) {
+    float* dst = part + ((int64_t)blockIdx.x * cout_p + o) * 9 * 4;
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) {
+      const int tap = ky * 3 + kx;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dst[tap * 4 + c] = acc[kx][c];
+      dst[tap * 4 + 3] = 0.f;
+    }
+  }
+}
+
+hipError_t launch_wgrad_first(int precision_g, const float* x, int x_cp, const void* dy, int n, int T, int cout,
+                              int cout_p, float* part, int splits, float* dst, hipStream_t st) {
+  if (splits < 1 || x_cp < 3 || cout_p % 8) return hipErrorInvalidValue;
+  const int64_t rows = (int64_t)n * T;
+  const dim3 grid(splits, ceil_div(cout_p, 64));
+  if (precision_g == OMNISEG_BF16)
+    hipLaunchKernelGGL(k_wgrad_first<uint16_t>, grid, dim3(256), 0, st, x, x_cp, (const uint16_t*)dy, cout_p, T, rows,
+                       part);
+  else
+    hipLaunchKernelGGL(k_wgrad_first<float>, grid, dim3(256), 0, st, x, x_cp, (const float*)dy, cout_p, T, rows, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t m = (int64_t)cout * 9 * 4;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, st, part, splits, cout, 3, 3, 4,
+                     cout_p, 4, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_wgrad(int precision_x, int precision_g, int loader, const WgradArgs& a, int cout, int cin,
                         int cu, float* dst, hipStream_t st) {
   if (a.cout_p % 32 || a.cin_p % 32) return hipErrorInvalidValue;
