@@ -471,7 +471,7 @@ def train_leg(om, torch, rgb, gt, steps, batch=TRAIN_BATCH):
         pos = float(y[offs[p]:offs[p + 1]].mean())
         pw[offs[p]:offs[p + 1]] = float(np.clip((1 - pos) / max(pos, 1e-6), 1.0, 10.0))
     w = torch.from_numpy(flat).to(dev).requires_grad_(True)
-    opt = torch.optim.Adam([w], lr=TRAIN_LR)
+    opt = torch.optim.Adam([w], lr=TRAIN_LR, fused=True)  # one kernel per update
     T, s = CFG["tile"], CFG["stride"]
     ng = lambda n: 1 if n <= T else -(-(n - T) // s) + 1
     grid = [(si, jy, jx) for si, k in enumerate(scales) for jy in range(ng(-(-REGION // (1 << k))))
