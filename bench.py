@@ -72,38 +72,62 @@ MEASURED_TRAFFIC = {
     # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000) bytes of one full-batch launch per layer
     "kernels": {
         "omniseg::k_conv3x3_rows2p<32, 64, 4, 2, 0, 0>": {
-            "enc_a2": (277339750, 537116224),
-            "enc_a3": (433644460, 268515840),
+            "enc_a2": (276994353, 537428064),
+            "enc_a3": (434127665, 268459680),
         },
         "omniseg::k_conv3x3_rows2p<32, 64, 4, 2, 0, 1>": {
-            "dec_b1": (1911654733, 1089816960),
-            "dec_b2": (1082344498, 545077856),
-            "dec_b3": (1066107945, 272602464),
-            "enc_b1": (2019649640, 1447473568),
-            "enc_b2": (1099602451, 737979200),
-            "enc_b3": (1069631776, 372905760),
+            "dec_b1": (1915163004, 1089012256),
+            "dec_b2": (1067041286, 540044160),
+            "dec_b3": (1069069623, 273255808),
+            "enc_b1": (2038166962, 1439072928),
+            "enc_b2": (1097386339, 756117088),
+            "enc_b3": (1069790363, 376854304),
         },
         "omniseg::k_conv3x3_rows2p<32, 64, 4, 2, 2, 0>": {
-            "dec_a0": (3335146805, 2147787520),
-            "dec_a1": (2038015518, 1074693536),
-            "dec_a2": (1711877153, 537618048),
-            "dec_a3": (2215174969, 268559488),
+            "dec_a0": (3335038494, 2147864608),
+            "dec_a1": (2059314295, 1074798880),
+            "dec_a2": (1711876745, 538196640),
+            "dec_a3": (2215174441, 268572288),
         },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 0>": {
-            "enc_a4": (1258486132, 134217728),
+            "enc_a4": (1259384101, 134217728),
         },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 1>": {
-            "enc_b4": (2661320447, 134217728),
+            "enc_b4": (2655742431, 134217728),
         },
         "omniseg::k_conv3x3_ws<0>": {
-            "enc_a1": (597050845, 1073743296),
+            "enc_a1": (597102413, 1073741888),
         },
         "omniseg::k_conv3x3_ws<1>": {
-            "dec_b0": (2414228482, 2147656768),
-            "enc_b0": (2417922418, 2686461440),
+            "dec_b0": (2413820242, 2147497760),
+            "enc_b0": (2416644068, 2684763488),
         },
     },
 }
+
+# HBM bytes (FETCH_SIZE x 2 + WRITE_SIZE, the same passes) of one launch of
+# the mapping leg's kernels on the 8192^2 slide: the merge to 40x and the
+# overlay of the six classes, and the stand-alone stitch of one 40x plane from
+# all its grid tiles with mask and logit out; each for the source file whose
+# SHA-256 is stored with it (any other source reports null).
+MEASURED_MAP_TRAFFIC = {
+    "k_merge_base": ("k_map.hip", "723d3d48b11ebff318d67407ddd621026d9124b71440febff24b3913129a3aae", 848036646),
+    "k_overlay": ("k_map.hip", "723d3d48b11ebff318d67407ddd621026d9124b71440febff24b3913129a3aae", 818003836),
+    "k_stitch4": ("k_stitch.hip", "4a162bdf1593cbb7e1c9f3e33bc44fc20234b7656d30e202a52b94375bf330d3", 1376357644),
+}
+
+
+def measured_map_traffic(kernel):
+    """Measured HBM bytes of one mapping-leg launch of `kernel`, or None when
+    its source changed since the measurement."""
+    import hashlib
+
+    if kernel not in MEASURED_MAP_TRAFFIC:
+        return None
+    src, want, nbytes = MEASURED_MAP_TRAFFIC[kernel]
+    with open(os.path.join(ROOT, "paper_2305_14566_amd", "csrc", src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return nbytes if sha == want else None
 
 
 def measured_traffic(kernel, records):
@@ -408,17 +432,18 @@ def mapping_leg(om, torch, dslide, flat_dev, size, reps, batch_tiles):
             "merge_ms": t_merge, "overlay_ms": t_over, "reps": reps,
             "merge_roofline": dict(bound="hbm", achieved=merge_bytes / (t_merge * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
                                    unit="GB/s", frac=merge_bytes / (t_merge * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                   traffic=None, algorithmic_bytes=merge_bytes),
+                                   traffic=measured_map_traffic("k_merge_base"), algorithmic_bytes=merge_bytes),
             "overlay_roofline": dict(bound="hbm", achieved=over_bytes / (t_over * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
                                      unit="GB/s", frac=over_bytes / (t_over * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                     traffic=None, algorithmic_bytes=over_bytes),
+                                     traffic=measured_map_traffic("k_overlay"), algorithmic_bytes=over_bytes),
             "stitch_standalone": {"workload": f"omniseg_stitch_tiles: one {H}x{W} 40x plane from all its {ny * ny} "
                                               f"grid tiles ({T}^2 at stride {s_}, random logits), mask and logit out",
                                   "ms": t_stitch,
                                   "roofline": dict(bound="hbm", achieved=stitch_bytes / (t_stitch * 1e-3) / 1e9,
                                                    peak=HBM_PEAK_GBS, unit="GB/s",
                                                    frac=stitch_bytes / (t_stitch * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                                   traffic=None, algorithmic_bytes=stitch_bytes)},
+                                                   traffic=measured_map_traffic("k_stitch4"),
+                                                   algorithmic_bytes=stitch_bytes)},
             "class_pixels_40x": [int(m.sum().item()) for m in m40]}
 
 
@@ -854,9 +879,10 @@ def counters_run(args, batch=256):
     every backbone conv of the bench network on a full batch of 256 tiles
     (random non-negative BF16 activations, He-normal weights) with the
     configuration BENCH_CONV_TABLE pins (each preceded by its weight-packing
-    kernel); the stitch of one 8192^2 40x plane from 30 % of its 63^2
-    tiles; the merge to 40x and the overlay of six classes on an 8192^2
-    slide.  Prints the launch list as JSON."""
+    kernel); the stitch of one 8192^2 40x plane from all its 63^2 tiles,
+    mask and logit out (the mapping leg's stand-alone stitch); the merge to
+    40x and the overlay of six classes on an 8192^2 slide.  Prints the
+    launch list as JSON."""
     import torch
 
     from paper_2305_14566_amd import omniseg as om
@@ -891,13 +917,12 @@ def counters_run(args, batch=256):
     torch.cuda.empty_cache()
     T, s_, H = CFG["tile"], CFG["stride"], SLIDE
     ny = (H - T + s_ - 1) // s_ + 1
-    keep = torch.rand(ny * ny, generator=g) < 0.3
-    yx = torch.tensor([(j // ny, j % ny) for j in range(ny * ny) if keep[j]], dtype=torch.int32).to(dev)
+    yx = torch.tensor([(j // ny, j % ny) for j in range(ny * ny)], dtype=torch.int32).to(dev)
     tl = torch.randn((yx.shape[0], T, T), generator=g).to(dev)
-    om.stitch_tiles(T, s_, H, H, tl, yx, emit_logits=False)
+    om.stitch_tiles(T, s_, H, H, tl, yx, emit_logits=True)
     torch.cuda.synchronize()
     out["stitch"] = {"tiles": int(yx.shape[0]), "T": T, "s": s_, "side": H,
-                     "alg_bytes": float(4 * yx.shape[0] * T * T + H * H)}
+                     "alg_bytes": float(4 * yx.shape[0] * T * T + 5 * H * H)}
     del tl
     planes = []
     for c, si in enumerate(CLASS_SLOT):
