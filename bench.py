@@ -165,7 +165,8 @@ def conv_symbol(om, prec, stage, config, level=None):
     # (level-0 residual convs, level-1 conv_a) in its weight-stationary form
     if prec == "bf16" and config == 10 and ((stage in ("enc_b", "dec_b") and level == 0) or
                                             (stage == "enc_a" and level == 1)):
-        return f"omniseg::k_conv3x3_ws<{epi}>"
+        # the last decoder conv also computes the head's precls (epilogue 4)
+        return f"omniseg::k_conv3x3_ws<{4 if stage == 'dec_b' else epi}>"
     if prec == "bf16" and config == 11:  # large-block row-reuse configuration
         return f"omniseg::k_conv3x3_rows2<{by}, {bn}, {wm}, {wn}, {loader}, {epi}>"
     if prec == "bf16" and config == 12:  # its persistent form

@@ -1127,6 +1127,14 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
       // encoder; with the fused pool, enc_b writes E_l and its pooled copy P
       // and the next conv_a reads P with the plain loader
       const bool fp = fuse_pool(plan);
+      // BF16 with a 64-channel D_0 whose last conv runs weight-stationary
+      // (configuration 10 with enough pixel blocks): that conv computes the
+      // head's precls as well, and D_0 never reaches memory.  The precls
+      // arithmetic is the head's own, so the logits are the same either way.
+      auto fuse_precls = [&](int cf, int nbatch) {
+        return prec == OMNISEG_BF16 && L >= 2 && plan->canon_pre_w >= 0 && plan->C[0] == 64 && plan->Cp[0] == 64 &&
+               cf == CONV_CFG_ROWS8_16x16_64 && conv_precls_fusable(layer(plan->dec_b[0]), T, T, nbatch);
+      };
       void* P = ws + lay.off_P;
       for (int l = 0; l < L; ++l) {
         const int tl = T >> l;
@@ -1175,24 +1183,39 @@ int32_t omniseg_segment_slide(const omniseg_plan* plan, const void* packed,
                          cf));
         HIP_TRY(prof.begin());
         cf = layer_config(plan, 3, l, tl, tl, plan->dec_b[l].cout_p);
+        if (l == 0 && fuse_precls(cf, nb)) {
+          // the last decoder conv writes the head's precls output F (8 FP32
+          // per pixel) into D_0's buffer instead of D_0
+          HIP_TRY(launch_conv_ws_precls(layer(plan->dec_b[0]), T, T, nb, count, base, A,
+                                        reinterpret_cast<const float*>(pk + plan->pk_pre_w),
+                                        reinterpret_cast<const float*>(pk + plan->pk_pre_b),
+                                        reinterpret_cast<float*>(E[0]), sm));
+          const double px = (double)T * T * nk;
+          HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, 0, nk, conv_flops(plan->dec_b[0], T) + px * 2.0 * 8 * plan->C[0],
+                           conv_bytes(plan->dec_b[0], T, 1.0) - px * plan->dec_b[0].cout * es + px * 32.0, cf));
+          continue;
+        }
         HIP_TRY(launch_conv3x3(prec, LOAD_PLAIN, EPI_RES_RELU, layer(plan->dec_b[l]), tl, tl, nb, count, base, A,
                                nullptr, E[l], sm, nullptr, cf));
         HIP_TRY(prof.end(OMNISEG_STAGE_DEC_B, l, nk, conv_flops(plan->dec_b[l], tl), conv_bytes(plan->dec_b[l], tl, 1.0),
                          cf));
       }
+      const bool fused = L >= 2 && fuse_precls(layer_config(plan, 3, 0, T, T, plan->dec_b[0].cout_p), nb);
       HIP_TRY(prof.begin());
       HIP_TRY(launch_head(prec, E[0], nb, T, plan->C[0], plan->Cp[0],
                           plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_w) : nullptr,
                           plan->canon_pre_w >= 0 ? reinterpret_cast<const float*>(pk + plan->pk_pre_b) : nullptr,
                           theta, plan->P, c.head_out, lay.slots, lay.max_slots, list, count, base,
                           lay.resident ? base : base % lay.ring, logits, sm,
-                          L >= 2 ? fp8_scale_of(plan, pk, OMNISEG_ACT_DEC_D, 0) : fp8_scale_of(plan, pk, OMNISEG_ACT_ENC_E, 0)));
+                          L >= 2 ? fp8_scale_of(plan, pk, OMNISEG_ACT_DEC_D, 0) : fp8_scale_of(plan, pk, OMNISEG_ACT_ENC_E, 0),
+                          fused ? reinterpret_cast<const float*>(E[0]) : nullptr));
       {
         const double px = (double)T * T * nk;
-        const double pre = plan->canon_pre_w >= 0 ? 2.0 * 8 * plan->C[0] : 0.0;
+        const double pre = plan->canon_pre_w >= 0 && !fused ? 2.0 * 8 * plan->C[0] : 0.0;
         // slots per tile vary with the tile's scale; count the largest
         const double head = lay.max_slots * (2.0 * 64 + 2.0 * 64 + 2.0 * 8 * c.head_out);
-        HIP_TRY(prof.end(OMNISEG_STAGE_HEAD, 0, nk, px * (pre + head), px * (plan->C[0] * es + 4.0 * lay.max_slots)));
+        HIP_TRY(prof.end(OMNISEG_STAGE_HEAD, 0, nk, px * (pre + head),
+                         px * ((fused ? 32.0 : plan->C[0] * es) + 4.0 * lay.max_slots)));
       }
       // 4. stitch the tile rows this batch completed
       sargs.batch = bi;

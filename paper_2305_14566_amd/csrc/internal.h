@@ -176,7 +176,7 @@ enum Loader { LOAD_PLAIN = 0, LOAD_POOL = 1, LOAD_UPCAT = 2 };
 // RELU: ReLU(acc + bias).  RES_RELU: ReLU(acc + bias + x0).  NONE: acc (data
 // gradients).  RES_MASK: (acc + x0) where aux > 0, else 0 (the data gradient
 // of a residual conv block, through the ReLU of its first conv).
-enum Epilogue { EPI_RELU = 0, EPI_RES_RELU = 1, EPI_NONE = 2, EPI_RES_MASK = 3 };
+enum Epilogue { EPI_RELU = 0, EPI_RES_RELU = 1, EPI_NONE = 2, EPI_RES_MASK = 3, EPI_RES_RELU_PRECLS = 4 };
 
 // 3x3 conv on a batch of tiles (NHWC, padded channels), output H x W per tile.
 // Conv tile configurations (pixel block, output channels, wave layout).  The
@@ -206,6 +206,14 @@ void conv_config_shape(int cfg, int* by, int* bx, int* bn, int* wm, int* wn);
 int conv_config_precisions(int cfg);
 int conv_default_config(int precision, int H, int W, int cout_p);
 
+// The decoder's last residual conv fused with the head's precls (BF16,
+// 64 -> 64 channels, weight-stationary form): writes F = ReLU(W_p D + b_p)
+// (FP32, [tile][H W][8]) instead of D.  The launch applies when
+// conv_precls_fusable holds (else hipErrorInvalidValue).
+bool conv_precls_fusable(const ConvLayer& L, int H, int W, int batch);
+hipError_t launch_conv_ws_precls(const ConvLayer& L, int H, int W, int batch, const int32_t* count, int chunk_base,
+                                 const void* x0, const float* pre_w, const float* pre_b, float* fpre,
+                                 hipStream_t st);
 // cfg < 0 (or not valid for the shape) picks the default configuration.
 hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L, int H, int W,
                           int batch, const int32_t* count, int chunk_base, const void* x0,
@@ -247,11 +255,68 @@ hipError_t launch_controller(const float* g, int batch, int G, const float* wc, 
 
 // Tile chunk_base + b of the list writes its logits to slot out_base + b of
 // tile_logits.  d0_scale: FP8 channel scales of d0 (null otherwise).
+// fpre: the precls output F (8 FP32 values per pixel, [tile][T^2][8]) already
+// computed by the decoder's last conv (see launch_conv_ws_precls); d0 is then
+// not read.
 hipError_t launch_head(int precision, const void* d0, int batch, int T, int c0, int c0_p,
                        const float* wp, const float* bp, const float* theta, int P, int o,
                        const SlotTable& slots, int max_slots, const int32_t* list,
                        const int32_t* count, int chunk_base, int out_base, float* tile_logits,
-                       hipStream_t st, const float* d0_scale = nullptr);
+                       hipStream_t st, const float* d0_scale = nullptr, const float* fpre = nullptr);
+
+// ---- BF16 precls on MFMA (shared by the head and the fused conv epilogue) ----
+//
+// F = ReLU((P_0 + P_1) + b_p) with P_h = W_p[:, 32 h .. 32 h + 31] D_0[32 h ..
+// 32 h + 31] for C_0 = 64 (P_1 = 0 for C_0 <= 32), each P_h one chain of
+// three v_mfma_f32_16x16x32_bf16: every FP32 weight is split into three BF16
+// terms, w = hi + mid + lo exactly (hi = bf16(w), mid = bf16(w - hi), and the
+// remainder has at most eight significant bits), so with BF16 D_0 each
+// product is exact and the sums run in FP32.  Operand layout of half h: lane
+// (g, l16) of the A operand holds output row o = l16 (rows 8-15 zero) and of
+// the B operand pixel l16; K slot 8 g + j holds channel 32 h + 4 g + j for
+// j < 4 and 32 h + 16 + 4 g + (j - 4) for j >= 4 (the channels a lane of the
+// conv epilogue holds as its two 16-channel fragments).  Result lane (g, l16),
+// g < 2, holds outputs 4 g .. 4 g + 3 of pixel l16.
+typedef __attribute__((ext_vector_type(4))) float pf32x4;
+typedef __attribute__((ext_vector_type(8))) __bf16 pbf16x8;
+
+__device__ __forceinline__ uint32_t precls_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+  return u >> 16;
+}
+
+// The three A operands (hi, mid, lo) of half h for this lane.
+__device__ __forceinline__ void precls_weights(const float* __restrict__ wp, int c0, int h, int lane,
+                                               uint4 (&A)[3]) {
+  const int g = lane >> 4, o = lane & 15;
+  uint32_t t[3][8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int c = 32 * h + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+    const float w = (o < 8 && c < c0) ? wp[o * c0 + c] : 0.f;
+    const uint32_t hi = precls_bf16_rne(w);
+    const float r1 = w - __uint_as_float(hi << 16);
+    const uint32_t mid = precls_bf16_rne(r1);
+    t[0][j] = hi;
+    t[1][j] = mid;
+    t[2][j] = precls_bf16_rne(r1 - __uint_as_float(mid << 16));
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    A[q] = make_uint4(t[q][0] | (t[q][1] << 16), t[q][2] | (t[q][3] << 16), t[q][4] | (t[q][5] << 16),
+                      t[q][6] | (t[q][7] << 16));
+}
+
+// P_h for 16 pixels: B = the lane's eight BF16 values in the K-slot order above.
+__device__ __forceinline__ pf32x4 precls_half(const uint4 (&A)[3], uint4 B) {
+  pf32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(pbf16x8, A[q]), __builtin_bit_cast(pbf16x8, B),
+                                                  acc, 0, 0, 0);
+  return acc;
+}
 
 // ---- FP8 calibration and packing --------------------------------------------
 

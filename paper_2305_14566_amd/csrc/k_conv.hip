@@ -77,6 +77,9 @@ struct ConvArgs {
   const float* oinv;
   void* pool_out;  // row-reuse epilogues: also write the 2x2 max-pool of y here (or null)
   int batch;       // tiles the launch covers (the persistent form loops over them)
+  const float* pre_w;  // EPI_RES_RELU_PRECLS: precls weights [8][64] and bias [8];
+  const float* pre_b;  // F = ReLU(W_p D + b_p) goes to fpre [tile][H W][8] instead
+  float* fpre;         // of D to y
 };
 
 __device__ __forceinline__ uint4 vmax(uint4 a, uint4 b, float) {
@@ -1295,8 +1298,12 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
   constexpr int WG = 9 * BN * 4 / 64;       // 64-slot groups of one weight chunk plane
   constexpr int WPLANE = WG * 64 * 16;      // bytes of a weight chunk plane
   static_assert(NCH * WPLANE + 2 * STAGE <= 160 * 1024, "weights and two halo stages fit the LDS");
-  constexpr bool RES = EPI == EPI_RES_RELU || EPI == EPI_RES_MASK;  // residual = the conv's own input
-  constexpr bool BIAS_RELU = EPI == EPI_RELU || EPI == EPI_RES_RELU;
+  // PRECLS: the residual conv with bias and ReLU whose output D only feeds
+  // the head's precls; the epilogue computes F = ReLU(W_p D + b_p) from the
+  // BF16-rounded D instead of storing D
+  constexpr bool PRECLS = EPI == EPI_RES_RELU_PRECLS;
+  constexpr bool RES = EPI == EPI_RES_RELU || EPI == EPI_RES_MASK || PRECLS;  // residual = the conv's own input
+  constexpr bool BIAS_RELU = EPI == EPI_RELU || EPI == EPI_RES_RELU || PRECLS;
   __shared__ __attribute__((aligned(16))) char sWt[NCH * WPLANE];
   __shared__ __attribute__((aligned(16))) char sH0[STAGE];
   __shared__ __attribute__((aligned(16))) char sH1[STAGE];
@@ -1385,8 +1392,18 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
     }
   };
 
-  // compute pixel block i from `stage` and write it
-  auto block = [&](int i, const char* stage) {
+  // PRECLS: this wave's half of the precls weights (channels 32 wn .. 32 wn
+  // + 31) and, for lanes g < 2, the bias of outputs 4 g .. 4 g + 3
+  uint4 Apre[3];
+  float4 bpre = make_float4(0.f, 0.f, 0.f, 0.f);
+  if constexpr (PRECLS) {
+    precls_weights(a.pre_w, 64, wn, lane, Apre);
+    if (g < 2) bpre = *reinterpret_cast<const float4*>(a.pre_b + 4 * g);
+  }
+
+  // compute pixel block i from `stage` and write it (PRECLS: the stage is
+  // then free and carries the precls halves between the waves)
+  auto block = [&](int i, char* stage) {
 #pragma unroll
     for (int r = 0; r < FM; ++r)
 #pragma unroll
@@ -1396,6 +1413,7 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
     const int b = i / bpt, rem = i % bpt;
     const int y0 = (rem / a.tiles_x) * 16, x0 = (rem % a.tiles_x) * 16;
     const int x = x0 + l16;
+    uint2 dq[FM][FN];  // PRECLS: the BF16 output pieces
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {
       const int c = wn * NW + fn * 16 + g * 4;  // channel inside the block
@@ -1439,9 +1457,10 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
           uint2 u;
           u.x = (uint32_t)f2bf(vv[0]) | ((uint32_t)f2bf(vv[1]) << 16);
           u.y = (uint32_t)f2bf(vv[2]) | ((uint32_t)f2bf(vv[3]) << 16);
-          *reinterpret_cast<uint2*>(out + o) = u;
+          if constexpr (PRECLS) dq[fm + h][fn] = u;
+          else *reinterpret_cast<uint2*>(out + o) = u;
         }
-        if (a.pool_out) {
+        if (!PRECLS && a.pool_out) {
           float m[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
@@ -1459,18 +1478,48 @@ __global__ __launch_bounds__(512, 2) void k_conv3x3_ws(ConvArgs a) {
         }
       }
     }
+    if constexpr (PRECLS) {
+      // a row's two 16-channel pieces are this wave's half of the precls K
+      pf32x4 P[FM];
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+        P[fm] = precls_half(Apre, make_uint4(dq[fm][0].x, dq[fm][0].y, dq[fm][1].x, dq[fm][1].y));
+      __syncthreads();  // every wave has finished reading the stage
+      pf32x4* xch = reinterpret_cast<pf32x4*>(stage);  // [wm][fm][l16][g < 2]
+      if (wn == 1 && g < 2) {
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) xch[((wm * FM + fm) * 16 + l16) * 2 + g] = P[fm];
+      }
+      __syncthreads();
+      if (wn == 0 && g < 2) {
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) {
+          const pf32x4 s = P[fm] + xch[((wm * FM + fm) * 16 + l16) * 2 + g];
+          const int64_t o = (((int64_t)b * a.H + y0 + wm * FM + fm) * a.W + x) * 8 + 4 * g;
+          *reinterpret_cast<float4*>(a.fpre + o) =
+              make_float4(fmaxf(s[0] + bpre.x, 0.f), fmaxf(s[1] + bpre.y, 0.f), fmaxf(s[2] + bpre.z, 0.f),
+                          fmaxf(s[3] + bpre.w, 0.f));
+        }
+      }
+    }
   };
 
   halo(q, sH0);
   wait_vmem();
   __syncthreads();
   // The wait after a block is for the next block's halo, issued before the
-  // block's output stores (FM FN, and FM FN / 2 for the pooled copy): those
-  // stay in flight across the barrier.
+  // block's output stores (FM FN, and FM FN / 2 for the pooled copy; with
+  // PRECLS the FM stores of F, by the waves of the first channel half only):
+  // those stay in flight across the barrier.
   constexpr int ST = FM * FN, STP = FM * FN + FM * FN / 2;
   auto wait_halo = [&]() {
-    if (a.pool_out) wait_vmem_but<STP>();
-    else wait_vmem_but<ST>();
+    if constexpr (PRECLS) {
+      if (wn == 0) wait_vmem_but<FM>();
+      else wait_vmem();
+    } else {
+      if (a.pool_out) wait_vmem_but<STP>();
+      else wait_vmem_but<ST>();
+    }
   };
   // blocks q, q + per_nb, ... alternate between the stages (two arrays, so
   // that the loads into one are known not to touch the other)
@@ -1500,6 +1549,36 @@ inline bool ws_applies(int loader, int epi, const ConvLayer& L, int H, int W, in
 }
 // Workgroups of the weight-stationary form: a multiple of 8 per output-channel block, at most one per CU.
 inline int ws_grid(int n_nblk) { return 8 * n_nblk * (kWsGrid / (8 * n_nblk)); }
+
+bool conv_precls_fusable(const ConvLayer& L, int H, int W, int batch) {
+  return L.cin_p == 64 && L.cout_p == 64 && !L.pool_out && ws_applies(LOAD_PLAIN, EPI_RES_RELU, L, H, W, batch);
+}
+
+hipError_t launch_conv_ws_precls(const ConvLayer& L, int H, int W, int batch, const int32_t* count, int chunk_base,
+                                 const void* x0, const float* pre_w, const float* pre_b, float* fpre,
+                                 hipStream_t st) {
+  if (!conv_precls_fusable(L, H, W, batch) || !pre_w || !pre_b || !fpre) return hipErrorInvalidValue;
+  ConvArgs a{};
+  a.x0 = x0;
+  a.w = L.w;
+  a.bias = L.b;
+  a.H = H;
+  a.W = W;
+  a.cin_p = L.cin_p;
+  a.cu_p = L.cu_p;
+  a.cout_p = L.cout_p;
+  a.count = count;
+  a.chunk_base = chunk_base;
+  a.tiles_y = H / 16;
+  a.tiles_x = W / 16;
+  a.n_nblk = 1;
+  a.batch = batch;
+  a.pre_w = pre_w;
+  a.pre_b = pre_b;
+  a.fpre = fpre;
+  hipLaunchKernelGGL((k_conv3x3_ws<EPI_RES_RELU_PRECLS>), dim3(ws_grid(1)), dim3(512), 0, st, a);
+  return hipGetLastError();
+}
 
 // FP8 (E4M3) row-reuse form on v_mfma_scale_f32_32x32x64_f8f6f4 (unit block
 // scales): one MFMA is one tap of a 64-channel chunk for 32 output channels

@@ -164,67 +164,37 @@ hipError_t launch_controller(const float* g, int batch, int G, const float* wc, 
   return hipGetLastError();
 }
 
-typedef __attribute__((ext_vector_type(4))) float hf32x4;
-typedef __attribute__((ext_vector_type(8))) __bf16 hbf16x8;
-
-// BF16 code of f, rounded to nearest even (f finite).
-__device__ __forceinline__ uint32_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-
-// BF16 precls F = ReLU(W_p D_0 + b_p) on MFMA (C_0 padded to 32 or 64).
-// Each FP32 weight is split into three BF16 terms, w = hi + mid + lo
-// exactly (hi = bf16(w), mid = bf16(w - hi), lo = w - hi - mid, which has at
-// most eight significant bits), so the products with the BF16 D_0 are exact
-// and the sum runs in FP32 inside v_mfma_f32_16x16x32_bf16: A = the weights
-// (row o < 8, zero rows 8-15), B = 16 pixels' 32 channels.  Wave w takes
-// the block's pixels 64 w .. 64 w + 63 in four 16-pixel groups; lane
-// (g, l16) of a group's result holds outputs 4 g .. 4 g + 3 of pixel l16,
-// which go through LDS to the pixel's own thread.
+// BF16 precls F = ReLU(W_p D_0 + b_p) on MFMA (C_0 padded to 32 or 64), in
+// the two half chains of precls_half, so that it equals the fused conv
+// epilogue's bit for bit.  Wave w takes the block's pixels 64 w .. 64 w + 63
+// in four 16-pixel groups; a group's results go through LDS to the pixels'
+// own threads.
 __device__ __forceinline__ void precls_bf16_mfma(const uint16_t* __restrict__ blk, int c0, int c0_p,
                                                  const float* __restrict__ wp, const float* bp, float (&F)[8]) {
-  __shared__ hf32x4 sF[256 * 2];
+  __shared__ pf32x4 sF[256 * 2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int nk = c0_p / 32;
   uint4 A[2][3];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    uint32_t t[3][8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int c = 32 * h + 8 * g + j;
-      const float w = (h < nk && l16 < 8 && c < c0) ? wp[l16 * c0 + c] : 0.f;
-      const uint32_t hi = bf16_rne(w);
-      const float r1 = w - __uint_as_float(hi << 16);
-      const uint32_t mid = bf16_rne(r1);
-      t[0][j] = hi;
-      t[1][j] = mid;
-      t[2][j] = bf16_rne(r1 - __uint_as_float(mid << 16));
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      A[h][q] = make_uint4(t[q][0] | (t[q][1] << 16), t[q][2] | (t[q][3] << 16), t[q][4] | (t[q][5] << 16),
-                           t[q][6] | (t[q][7] << 16));
-  }
+  precls_weights(wp, c0, 0, lane, A[0]);
+  precls_weights(wp, c0, 1, lane, A[1]);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const uint16_t* p = blk + (int64_t)(wave * 64 + r * 16 + l16) * c0_p + 8 * g;
-    uint4 B[2];
+    const uint16_t* p = blk + (int64_t)(wave * 64 + r * 16 + l16) * c0_p + 4 * g;
+    pf32x4 P[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) B[h] = h < nk ? *reinterpret_cast<const uint4*>(p + 32 * h) : make_uint4(0, 0, 0, 0);
-    hf32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(hbf16x8, A[h][q]),
-                                                      __builtin_bit_cast(hbf16x8, B[h]), acc, 0, 0, 0);
-    if (g < 2) sF[(wave * 64 + r * 16 + l16) * 2 + g] = acc;
+    for (int h = 0; h < 2; ++h) {
+      if (h < nk) {
+        const uint2 lo = *reinterpret_cast<const uint2*>(p + 32 * h);
+        const uint2 hi = *reinterpret_cast<const uint2*>(p + 32 * h + 16);
+        P[h] = precls_half(A[h], make_uint4(lo.x, lo.y, hi.x, hi.y));
+      } else {
+        P[h] = pf32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+    if (g < 2) sF[(wave * 64 + r * 16 + l16) * 2 + g] = P[0] + P[1];
   }
-  const hf32x4 f0 = sF[threadIdx.x * 2], f1 = sF[threadIdx.x * 2 + 1];
+  const pf32x4 f0 = sF[threadIdx.x * 2], f1 = sF[threadIdx.x * 2 + 1];
 #pragma unroll
   for (int o = 0; o < 4; ++o) {
     F[o] = fmaxf(f0[o] + bp[o], 0.f);
@@ -243,7 +213,7 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
                                               SlotTable slots, int max_slots,
                                               const int32_t* list, const int32_t* count,
                                               int chunk_base, int out_base, float* __restrict__ out,
-                                              const float* __restrict__ dscale) {
+                                              const float* __restrict__ dscale, const float* __restrict__ fpre) {
   const int per_tile = T2 / 256;
   const int b = blockIdx.x / per_tile;
   const int pix = (blockIdx.x % per_tile) * 256 + threadIdx.x;
@@ -264,8 +234,22 @@ __global__ __launch_bounds__(256) void k_head(const T* __restrict__ d0, int T2, 
   constexpr int V = 16 / sizeof(T);
   float F[8];
   bool done = false;
+  if (fpre) {
+    // F from the decoder's last conv
+    const float4* f = reinterpret_cast<const float4*>(fpre + ((int64_t)b * T2 + pix) * 8);
+    const float4 f0 = f[0], f1 = f[1];
+    F[0] = f0.x;
+    F[1] = f0.y;
+    F[2] = f0.z;
+    F[3] = f0.w;
+    F[4] = f1.x;
+    F[5] = f1.y;
+    F[6] = f1.z;
+    F[7] = f1.w;
+    done = true;
+  }
   if constexpr (std::is_same<T, uint16_t>::value) {
-    if (pre && c0_p <= 64) {
+    if (!done && pre && c0_p <= 64) {
       precls_bf16_mfma(d0 + ((int64_t)b * T2 + (blockIdx.x % per_tile) * 256) * c0_p, c0, c0_p, wp, bp, F);
       done = true;
     }
@@ -400,14 +384,14 @@ hipError_t launch_head(int precision, const void* d0, int batch, int T, int c0, 
                        const float* wp, const float* bp, const float* theta, int P, int o,
                        const SlotTable& slots, int max_slots, const int32_t* list,
                        const int32_t* count, int chunk_base, int out_base, float* tile_logits,
-                       hipStream_t st, const float* d0_scale) {
+                       hipStream_t st, const float* d0_scale, const float* fpre) {
   const int T2 = T * T;
   if (T2 % 256 || c0 > 256 || max_slots > OMNISEG_MAX_CLASSES) return hipErrorInvalidValue;
   if ((precision == OMNISEG_FP8) != (d0_scale != nullptr)) return hipErrorInvalidValue;
   dim3 grid(batch * (T2 / 256));
 #define OMNISEG_HEAD(TY, O)                                                                                      \
   hipLaunchKernelGGL((k_head<TY, O>), grid, dim3(256), 0, st, (const TY*)d0, T2, c0, c0_p, wp, bp, theta, P, \
-                     slots, max_slots, list, count, chunk_base, out_base, tile_logits, d0_scale)
+                     slots, max_slots, list, count, chunk_base, out_base, tile_logits, d0_scale, fpre)
   if (precision == OMNISEG_FP8) {
     if (o == 1) OMNISEG_HEAD(uint8_t, 1); else OMNISEG_HEAD(uint8_t, 2);
   } else if (precision == OMNISEG_BF16) {

@@ -304,6 +304,32 @@ def test_wide_network_sampled_tiles(precision, tol):
             assert err <= max(tol, 2.0 * emu_vs_ref), (li, err)
 
 
+def test_precls_fused_into_last_conv_equals_unfused():
+    """BF16 with a 64-channel D_0: when the last decoder conv runs
+    weight-stationary (configuration 10, enough pixel blocks) it also computes
+    the head's precls and stores F instead of D_0; the head's own precls does
+    the same arithmetic, so pinning that conv to another configuration (no
+    fusion) must give the same tile logits and masks bit for bit."""
+    rgb, cfg, flat, pairs = _wide_case()
+    dslide = torch.from_numpy(np.ascontiguousarray(rgb)).to(DEV)
+    outs, recs = [], []
+    for dec_b0 in (10, 6):
+        plan = _plan(cfg, om.BF16)
+        plan.set_conv_tuning(3, 0, dec_b0)
+        packed = plan.pack(torch.from_numpy(flat).to(DEV))
+        plan.set_profiling(True)
+        masks, logits, ws = plan.segment([dslide], pairs, packed)
+        torch.cuda.synchronize()
+        recs.append([r for r in plan.read_profile() if r["stage"] == "dec_b" and r["level"] == 0])
+        tl = _region(plan, [dslide], pairs, ws, om.REGION_TILE_LOGITS)
+        outs.append((tl, [m.cpu().numpy() for m in masks[0]]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    for a_, b_ in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a_, b_)
+    # the fused launch stores 32 bytes of F per pixel instead of 128 of D_0
+    assert sum(r["bytes"] for r in recs[0]) < sum(r["bytes"] for r in recs[1])
+
+
 def test_graph_replay_matches_eager():
     """With OMNISEG_FLAG_GRAPH the work after the tile list is captured once
     and replayed; every replay must equal the eager result bit for bit."""
