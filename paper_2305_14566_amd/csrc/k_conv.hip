@@ -2123,10 +2123,11 @@ hipError_t launch_conv3x3(int precision, int loader, int epi, const ConvLayer& L
 // ---------------------------------------------------------------------------
 // First conv, 3 -> C_0, from the slide (40x) or the box-sum pyramid.  One
 // workgroup per 16-pixel-wide column of BH rows of one tile; the
-// (BH + 2) x 18 x 3 input patch is normalised to [0, 1] (value / (255 * 4^k))
-// in FP32 in LDS, with the pad
-// colour outside the slide and zeros outside the tile.  FP32 arithmetic for
-// every precision; the output is stored in the backbone's storage type.
+// (BH + 2) x 18 x 3 input patch is staged in FP32 in LDS, with the pad
+// colour outside the slide and zeros outside the tile, and the input is
+// normalised to [0, 1] (value / (255 * 4^k)).  FP32 sums of exact products
+// for every precision (FP32 MFMA for the FP32 path, exact BF16 splits on BF16
+// MFMA for BF16 and FP8); the output is stored in the backbone's storage type.
 // ---------------------------------------------------------------------------
 
 constexpr int kFirstMaxC0 = 128;
@@ -2161,28 +2162,15 @@ __device__ __forceinline__ void store_vec(uint16_t* p, const float* v) {
   *reinterpret_cast<uint4*>(p) = u;
 }
 
-// BH output rows (64 when the tile allows, else 16) of a 16-pixel-wide column
-// per workgroup; a wave owns BH / 4 rows and loads its weight fragments once.
-template <typename T, int BH>
-__global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
-  constexpr int RPW = BH / 4;                           // output rows per wave
-  constexpr int OPAD = 16 / (int)sizeof(T);             // one 16-byte slot per staged pixel row
-  constexpr int OPITCH = kFirstMaxC0 + OPAD;            // staged values per pixel (at most)
-  __shared__ float sIn[3][BH + 2][19];
-  __shared__ float sBias[kFirstMaxC0], sOinv[kFirstMaxC0];  // zero / one beyond c0
-  __shared__ __attribute__((aligned(16))) T sOut[4][16 * OPITCH];
-  const int nbx = a.T / 16, nby = a.T / BH;
-  int rest = blockIdx.x;
-  const int sx = rest % nbx;
-  rest /= nbx;
-  const int sy = rest % nby;
-  const int b = rest / nby;
-  if (a.chunk_base + b >= *a.count) return;
-  const int4 t = reinterpret_cast<const int4*>(a.list)[a.chunk_base + b];
+// The (BH + 2) x 18 input patch of column block (sy, sx) of tile t at scale k,
+// channel-major in sp[c][py][px]: each raw value (a colour, or a box sum of
+// the pyramid) times `mul`, the pad colour beyond the slide and zeros beyond
+// the tile.
+template <int BH>
+__device__ __forceinline__ void first_stage_patch(const FirstConvArgs& a, const int4 t, int k, int sy, int sx,
+                                                  float mul, float (&sp)[3][BH + 2][19]) {
   const SlideDev& sd = a.slides[t.x];
-  const int k = a.scale_k[t.y];
   const int oy = t.z * a.scale_s[t.y], ox = t.w * a.scale_s[t.y];  // tile origin at scale k
-  const float scale = 1.0f / (255.0f * (float)(1 << (2 * k)));
   for (int i = threadIdx.x; i < (BH + 2) * 18; i += 256) {
     const int py = i / 18, px = i % 18;
     const int ty = sy * BH + py - 1, tx = sx * 16 + px - 1;
@@ -2201,20 +2189,43 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
           g = sd.pad[1];
           bb = sd.pad[2];
         }
-        v0 = r * scale;
-        v1 = g * scale;
-        v2 = bb * scale;
+        v0 = r * mul;
+        v1 = g * mul;
+        v2 = bb * mul;
       } else {
         const ushort4 s4 = reinterpret_cast<const ushort4*>(sd.pyr[t.y])[(int64_t)Y * sd.pyr_ex[t.y] + X];
-        v0 = s4.x * scale;
-        v1 = s4.y * scale;
-        v2 = s4.z * scale;
+        v0 = s4.x * mul;
+        v1 = s4.y * mul;
+        v2 = s4.z * mul;
       }
     }
-    sIn[0][py][px] = v0;
-    sIn[1][py][px] = v1;
-    sIn[2][py][px] = v2;
+    sp[0][py][px] = v0;
+    sp[1][py][px] = v1;
+    sp[2][py][px] = v2;
   }
+}
+
+// BH output rows (64 when the tile allows, else 16) of a 16-pixel-wide column
+// per workgroup; a wave owns BH / 4 rows and loads its weight fragments once.
+template <typename T, int BH>
+__global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
+  constexpr int RPW = BH / 4;                           // output rows per wave
+  constexpr int OPAD = 16 / (int)sizeof(T);             // one 16-byte slot per staged pixel row
+  constexpr int OPITCH = kFirstMaxC0 + OPAD;            // staged values per pixel (at most)
+  __shared__ float sIn[3][BH + 2][19];
+  __shared__ float sBias[kFirstMaxC0], sOinv[kFirstMaxC0];  // zero / one beyond c0
+  __shared__ __attribute__((aligned(16))) T sOut[4][16 * OPITCH];
+  const int nbx = a.T / 16, nby = a.T / BH;
+  int rest = blockIdx.x;
+  const int sx = rest % nbx;
+  rest /= nbx;
+  const int sy = rest % nby;
+  const int b = rest / nby;
+  if (a.chunk_base + b >= *a.count) return;
+  const int4 t = reinterpret_cast<const int4*>(a.list)[a.chunk_base + b];
+  const int k = a.scale_k[t.y];
+  const float scale = 1.0f / (255.0f * (float)(1 << (2 * k)));
+  first_stage_patch<BH>(a, t, k, sy, sx, scale, sIn);
   if (threadIdx.x < kFirstMaxC0) {
     const int o = threadIdx.x;
     sBias[o] = o < a.c0 ? a.b[o] : 0.f;
@@ -2297,18 +2308,156 @@ __global__ __launch_bounds__(256) void k_first_conv(FirstConvArgs a) {
   }
 }
 
+// BF16 and FP8 storage: the same conv on BF16 MFMA (v_mfma_f32_16x16x32_bf16)
+// with every product exact, so that the sums are FP32 sums of exact products
+// as on the FP32 MFMA above.  The patch holds the raw integers (colours, or
+// box sums below 2^14 since k <= 3), each split into hi = v & ~255 and
+// lo = v & 255, both exact in BF16; each FP32 weight is split into three BF16
+// terms, w = hi + mid + lo exactly (hi = bf16(w), mid = bf16(w - hi), and the
+// remainder has at most eight significant bits).  The normalisation
+// 1 / (255 * 4^k) multiplies the sum; at 40x the inputs' hi parts are zero and
+// their three MFMAs are skipped.  K slot 8 g + j of lane (g, l16) is tap
+// t = 8 g + j (c * 9 + dy * 3 + dx; slots from 27 on are zero) of pixel l16,
+// and a lane's result holds channels 16 m + 4 g .. + 3 of pixel l16 as above.
+template <typename T, int BH, int NMX>
+__global__ __launch_bounds__(256) void k_first_conv_split(FirstConvArgs a) {
+  constexpr int RPW = BH / 4;
+  constexpr int OPAD = 16 / (int)sizeof(T);
+  constexpr int OPITCH = NMX * 16 + OPAD;
+  __shared__ float sIn[3][BH + 2][19];
+  __shared__ float sBias[NMX * 16], sOinv[NMX * 16];  // zero / one beyond c0
+  __shared__ __attribute__((aligned(16))) T sOut[4][16 * OPITCH];
+  const int nbx = a.T / 16, nby = a.T / BH;
+  int rest = blockIdx.x;
+  const int sx = rest % nbx;
+  rest /= nbx;
+  const int sy = rest % nby;
+  const int b = rest / nby;
+  if (a.chunk_base + b >= *a.count) return;
+  const int4 t = reinterpret_cast<const int4*>(a.list)[a.chunk_base + b];
+  const int k = a.scale_k[t.y];
+  const float scale = 1.0f / (255.0f * (float)(1 << (2 * k)));
+  first_stage_patch<BH>(a, t, k, sy, sx, 1.0f, sIn);
+  if (threadIdx.x < NMX * 16) {
+    const int o = threadIdx.x;
+    sBias[o] = o < a.c0 ? a.b[o] : 0.f;
+    sOinv[o] = (std::is_same<T, uint8_t>::value && o < a.c0) ? a.oinv[o] : 1.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nm = a.c0_p / 16;
+  // A operands: wa[m][q] = term q (0 hi, 1 mid, 2 lo) of the weights of
+  // output channel 16 m + l16 at taps 8 g .. 8 g + 7.  Branch-free loads (an
+  // out-of-range entry loads element 0 and is replaced by zero).
+  uint4 wa[NMX][3];
+#pragma unroll
+  for (int m = 0; m < NMX; ++m) {
+    uint32_t tq[3][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int o = m * 16 + l16, tap = 8 * g + j;
+      const bool ok = m < nm && o < a.c0 && tap < 27;
+      const float v = a.w[ok ? o * 27 + tap : 0];
+      const float w = ok ? v : 0.f;
+      const uint32_t hi = precls_bf16_rne(w);
+      const float r1 = w - __uint_as_float(hi << 16);
+      const uint32_t mid = precls_bf16_rne(r1);
+      tq[0][j] = hi;
+      tq[1][j] = mid;
+      tq[2][j] = precls_bf16_rne(r1 - __uint_as_float(mid << 16));
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      wa[m][q] = make_uint4(tq[q][0] | (tq[q][1] << 16), tq[q][2] | (tq[q][3] << 16), tq[q][4] | (tq[q][5] << 16),
+                            tq[q][6] | (tq[q][7] << 16));
+  }
+  // patch offsets of this lane's taps
+  int koff[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int tap = 8 * g + j;
+    const int c = tap / 9, dy = (tap % 9) / 3, dx = tap % 3;
+    koff[j] = tap < 27 ? (c * (BH + 2) + dy) * 19 + dx : -1;
+  }
+  const float* sflat = &sIn[0][0][0];
+  T* srow = sOut[wave];
+  const int pitch = a.c0_p + OPAD;
+  const int vpp = a.c0_p * (int)sizeof(T) / 16;
+  constexpr int VE = 16 / (int)sizeof(T);
+  const bool two = k > 0;  // uniform across the block
+  for (int r = 0; r < RPW; ++r) {
+    const int py = wave * RPW + r;
+    uint32_t lo[8], hi[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t iv = koff[j] >= 0 ? (uint32_t)sflat[koff[j] + py * 19 + l16] : 0u;
+      // integers below 2^14: each part has at most eight significant bits,
+      // so its FP32 pattern's upper half is its BF16 value
+      lo[j] = __float_as_uint((float)(iv & 255u)) >> 16;
+      hi[j] = __float_as_uint((float)(iv & ~255u)) >> 16;
+    }
+    const uint4 blo = make_uint4(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16), lo[4] | (lo[5] << 16),
+                                 lo[6] | (lo[7] << 16));
+    const uint4 bhi = make_uint4(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16), hi[4] | (hi[5] << 16),
+                                 hi[6] | (hi[7] << 16));
+#pragma unroll
+    for (int m = 0; m < NMX; ++m) {
+      if (m >= nm) break;
+      pf32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 2; q >= 0; --q)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(pbf16x8, wa[m][q]),
+                                                      __builtin_bit_cast(pbf16x8, blo), acc, 0, 0, 0);
+      if (two) {
+#pragma unroll
+        for (int q = 2; q >= 0; --q)
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(pbf16x8, wa[m][q]),
+                                                        __builtin_bit_cast(pbf16x8, bhi), acc, 0, 0, 0);
+      }
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = m * 16 + 4 * g + q;
+        float u = acc[q] * scale + sBias[o];
+        u = u > 0.f ? u : 0.f;
+        if (std::is_same<T, uint8_t>::value) u *= sOinv[o];
+        v[q] = u;
+      }
+      store4(srow + l16 * pitch + m * 16 + 4 * g, v);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int y = sy * BH + py;
+    T* out = (T*)a.y + (((int64_t)b * a.T + y) * a.T + sx * 16) * a.c0_p;
+    for (int v = lane; v < 16 * vpp; v += 64) {
+      const int px = v / vpp, j = v % vpp;
+      *reinterpret_cast<uint4*>(out + v * VE) = *reinterpret_cast<const uint4*>(srow + px * pitch + j * VE);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 hipError_t launch_first_conv(int precision, const FirstConvArgs& a, hipStream_t st) {
   if (a.c0 > kFirstMaxC0 || a.T % 16 || a.c0_p % 16) return hipErrorInvalidValue;
   const bool tall = a.T % 64 == 0;
   const int64_t blocks = (int64_t)a.batch * (a.T / 16) * (a.T / (tall ? 64 : 16));
   const dim3 grid((unsigned)blocks);
+  const bool narrow = a.c0_p <= 64;  // at most four 16-channel fragments
   if (precision == OMNISEG_FP8) {
     if (!a.oinv) return hipErrorInvalidValue;
-    if (tall) hipLaunchKernelGGL((k_first_conv<uint8_t, 64>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_first_conv<uint8_t, 16>), grid, dim3(256), 0, st, a);
+    if (tall && narrow) hipLaunchKernelGGL((k_first_conv_split<uint8_t, 64, 4>), grid, dim3(256), 0, st, a);
+    else if (tall) hipLaunchKernelGGL((k_first_conv_split<uint8_t, 64, 8>), grid, dim3(256), 0, st, a);
+    else if (narrow) hipLaunchKernelGGL((k_first_conv_split<uint8_t, 16, 4>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_first_conv_split<uint8_t, 16, 8>), grid, dim3(256), 0, st, a);
   } else if (precision == OMNISEG_BF16) {
-    if (tall) hipLaunchKernelGGL((k_first_conv<uint16_t, 64>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_first_conv<uint16_t, 16>), grid, dim3(256), 0, st, a);
+    if (tall && narrow) hipLaunchKernelGGL((k_first_conv_split<uint16_t, 64, 4>), grid, dim3(256), 0, st, a);
+    else if (tall) hipLaunchKernelGGL((k_first_conv_split<uint16_t, 64, 8>), grid, dim3(256), 0, st, a);
+    else if (narrow) hipLaunchKernelGGL((k_first_conv_split<uint16_t, 16, 4>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_first_conv_split<uint16_t, 16, 8>), grid, dim3(256), 0, st, a);
   } else {
     if (tall) hipLaunchKernelGGL((k_first_conv<float, 64>), grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_first_conv<float, 16>), grid, dim3(256), 0, st, a);
