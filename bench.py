@@ -67,40 +67,40 @@ TRAIN_BATCH = 32
 # the conv source whose SHA-256 is stored here; any other source reports
 # null.
 MEASURED_TRAFFIC = {
-    "conv_source_sha256": "e8c27bf451191db573a3117f091ae9b807fe156cbf46677a48b8d395e6975204",
+    "conv_source_sha256": "af1b7ff352d6f758bb0f1fb5fe0d3878c9a3211e3b8937ffaed7b5d8550a4cd7",
     "batch": 256,
     # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000) bytes of one full-batch launch per layer
     "kernels": {
         "omniseg::k_conv3x3_rows2p<32, 64, 4, 2, 0, 0>": {
-            "enc_a2": (276786259, 537451616),
-            "enc_a3": (433168621, 268468864),
+            "enc_a2": (277461444, 537328896),
+            "enc_a3": (433181913, 268464896),
         },
         "omniseg::k_conv3x3_rows2p<32, 64, 4, 2, 0, 1>": {
-            "dec_b1": (1919386261, 1089437056),
-            "dec_b2": (1070641788, 540565344),
-            "dec_b3": (1068552911, 272192608),
-            "enc_b1": (2007608530, 1445874272),
-            "enc_b2": (1096117762, 756049824),
-            "enc_b3": (1067595765, 373681728),
+            "dec_b1": (1909318610, 1087182176),
+            "dec_b2": (1065358019, 540254080),
+            "dec_b3": (1066830218, 273384992),
+            "enc_b1": (2013380524, 1441024160),
+            "enc_b2": (1094047346, 760669152),
+            "enc_b3": (1069392807, 374582816),
         },
         "omniseg::k_conv3x3_rows2p<32, 64, 4, 2, 2, 0>": {
-            "dec_a0": (3329434399, 2147768992),
-            "dec_a1": (2055998661, 1075075584),
-            "dec_a2": (1711863029, 538650848),
-            "dec_a3": (2215160305, 268515712),
+            "dec_a0": (3332663357, 2147897760),
+            "dec_a1": (2055258207, 1074858176),
+            "dec_a2": (1711877637, 537401920),
+            "dec_a3": (2215174866, 268813472),
         },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 0>": {
-            "enc_a4": (1259304974, 134217728),
+            "enc_a4": (1259464721, 134217728),
         },
         "omniseg::k_conv3x3_rows<16, 64, 4, 2, 0, 1>": {
-            "enc_b4": (2652387261, 134217728),
+            "enc_b4": (2654240968, 134217728),
         },
         "omniseg::k_conv3x3_ws<0>": {
-            "enc_a1": (597044829, 1073742016),
+            "enc_a1": (597060402, 1073742560),
         },
         "omniseg::k_conv3x3_ws<1>": {
-            "dec_b0": (2417247851, 2147500896),
-            "enc_b0": (2418724016, 2684771744),
+            "dec_b0": (2414780364, 2147496832),
+            "enc_b0": (2421045979, 2684709440),
         },
     },
 }
@@ -111,9 +111,9 @@ MEASURED_TRAFFIC = {
 # all its grid tiles with mask and logit out; each for the source file whose
 # SHA-256 is stored with it (any other source reports null).
 MEASURED_MAP_TRAFFIC = {
-    "k_merge_base": ("k_map.hip", "723d3d48b11ebff318d67407ddd621026d9124b71440febff24b3913129a3aae", 848070867),
-    "k_overlay": ("k_map.hip", "723d3d48b11ebff318d67407ddd621026d9124b71440febff24b3913129a3aae", 818003972),
-    "k_stitch4": ("k_stitch.hip", "4a162bdf1593cbb7e1c9f3e33bc44fc20234b7656d30e202a52b94375bf330d3", 1376353319),
+    "k_merge_base": ("k_map.hip", "723d3d48b11ebff318d67407ddd621026d9124b71440febff24b3913129a3aae", 848068366),
+    "k_overlay": ("k_map.hip", "723d3d48b11ebff318d67407ddd621026d9124b71440febff24b3913129a3aae", 818004708),
+    "k_stitch4": ("k_stitch.hip", "4a162bdf1593cbb7e1c9f3e33bc44fc20234b7656d30e202a52b94375bf330d3", 1376365176),
 }
 
 
