@@ -246,7 +246,8 @@ int32_t omniseg_pack_weights(const omniseg_plan* plan, const float* canonical,
  * and the epilogue forms w_o acc + b_o (+ the residual decoded with its
  * scales), applies ReLU and encodes the result with the output's scales.
  * The first conv (from the RGB tile), the controller and the head compute in
- * FP32.  A scale is 2^ceil(log2(amax / 448)) of the channel's maximum over
+ * FP32 (the first conv as FP32 sums of exact products: its MFMAs take exact
+ * BF16 splits of the FP32 weights and of the integer inputs).  A scale is 2^ceil(log2(amax / 448)) of the channel's maximum over
  * calibration tiles (1 if that maximum is 0).
  *
  * Activation table: one float per padded channel (pad32(C_l)) of every
