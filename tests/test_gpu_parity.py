@@ -244,6 +244,37 @@ def test_bf16_damped_network_meets_target(damp):
     assert err_emu <= 0.25 * emu_vs_ref, (err_emu, emu_vs_ref)
 
 
+@pytest.mark.parametrize("base,tile", [(80, 48), (80, 64), (16, 48)])
+def test_first_conv_launch_forms(base, tile):
+    """The first conv in each of its launch forms, end to end at 40x and 20x
+    (whose box-sum inputs exceed eight bits, so the BF16-MFMA form adds the
+    inputs' upper parts): 16-row blocks (tile side not a multiple of 64) and
+    64-row blocks, with more than four 16-channel fragments (C_0 = 80) and
+    with one (C_0 = 16).  The weights are damped (x 0.3) so the network does
+    not amplify rounding: the FP32 path must be within 1e-4 of FP64, and the
+    BF16 path within a quarter of exact BF16 arithmetic's own error of the
+    oracle's BF16 emulation (measured: under a tenth; a dropped or misplaced
+    operand part would be off by far more)."""
+    rgb, _ = synth.strip_slide(81, 80, 112, fg_frac=0.5)
+    cfg = O.make_config(base=base, levels=2, head_out=2, n_classes=2, scales=(0, 1), tile=tile, stride=tile // 2)
+    flat = (synth.he_normal_weights(82, base, 2, 2, 2, 2, bias_std=0.05) * 0.3).astype(np.float32)
+    pairs = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    ref = O.segment([rgb], flat, cfg, pairs)
+    emu = O.segment([rgb], flat, cfg, pairs, emulate="bf16")
+    _, _, m32, l32, _ = _run(cfg, [rgb], flat, pairs, om.FP32)
+    _, _, m16, l16, _ = _run(cfg, [rgb], flat, pairs, om.BF16)
+    for p in range(len(pairs)):
+        _compare_planes(m32[0][p], l32[0][p], ref["mask"][0][p], ref["logit"][0][p], FP32_TOL)
+        lg = l16[0][p].cpu().numpy().astype(np.float64)
+        err_emu = M.normwise_error(lg, emu["logit"][0][p])
+        emu_vs_ref = M.normwise_error(emu["logit"][0][p], ref["logit"][0][p])
+        print(f"base {base} tile {tile} pair {pairs[p]}: bf16 vs emulation {err_emu:.3e}, "
+              f"emulation vs fp64 {emu_vs_ref:.3e}")
+        assert err_emu <= 0.25 * emu_vs_ref, (pairs[p], err_emu, emu_vs_ref)
+        _compare_planes(m16[0][p], l16[0][p], ref["mask"][0][p], ref["logit"][0][p],
+                        max(BF16_TOL, 2.0 * emu_vs_ref))
+
+
 def test_batching_and_determinism():
     """Several slides in one call equal per-slide calls, bit for bit, and a
     second run is bitwise identical (no atomics on the forward path)."""
