@@ -314,27 +314,33 @@ def test_conv_against_torch_float64():
 
 # ---------------------------------------------------------------- O6 U-Net, independent torch model
 
-def _torch_unet(x, flat, base, L, n_classes, n_scales, o):
-    """Test-only float64 torch model of the same network (torch ops only)."""
+def _torch_unet(x, flat, base, L, n_classes, n_scales, o, bf16=False):
+    """Test-only float64 torch model of the same network (torch ops only).
+    With bf16, the 3x3 weights but the first conv's and every conv output are
+    rounded through torch's bfloat16 type, the storage points of a BF16
+    backbone."""
     lay = synth.weight_layout(base, L, n_classes, n_scales, o)
     t = torch.from_numpy(np.asarray(flat, np.float64))
+    rnd = (lambda v: v.to(torch.bfloat16).to(torch.float64)) if bf16 else (lambda v: v)
     p, W = 0, {}
     for name, shape, _ in lay:
         n = int(np.prod(shape))
         W[name] = t[p:p + n].reshape(shape)
+        if name.endswith(".w") and name.startswith(("enc", "dec")) and name != "enc0.a.w":
+            W[name] = rnd(W[name])
         p += n
     X = torch.from_numpy(x)[None]
     E = []
     for l in range(L):
         if l > 0:
             X = tF.max_pool2d(E[-1], 2)
-        A = torch.relu(tF.conv2d(X, W[f"enc{l}.a.w"], W[f"enc{l}.a.b"], padding=1))
-        E.append(torch.relu(tF.conv2d(A, W[f"enc{l}.b.w"], W[f"enc{l}.b.b"], padding=1) + A))
+        A = rnd(torch.relu(tF.conv2d(X, W[f"enc{l}.a.w"], W[f"enc{l}.a.b"], padding=1)))
+        E.append(rnd(torch.relu(tF.conv2d(A, W[f"enc{l}.b.w"], W[f"enc{l}.b.b"], padding=1) + A)))
     D = E[-1]
     for l in range(L - 2, -1, -1):
         Z = torch.cat([tF.interpolate(D, scale_factor=2, mode="nearest"), E[l]], dim=1)
-        A = torch.relu(tF.conv2d(Z, W[f"dec{l}.a.w"], W[f"dec{l}.a.b"], padding=1))
-        D = torch.relu(tF.conv2d(A, W[f"dec{l}.b.w"], W[f"dec{l}.b.b"], padding=1) + A)
+        A = rnd(torch.relu(tF.conv2d(Z, W[f"dec{l}.a.w"], W[f"dec{l}.a.b"], padding=1)))
+        D = rnd(torch.relu(tF.conv2d(A, W[f"dec{l}.b.w"], W[f"dec{l}.b.b"], padding=1) + A))
     F = torch.relu(tF.conv2d(D, W["precls.w"], W["precls.b"])) if base != 8 else D
     g = E[-1].mean(dim=(2, 3))[0]
     return F[0], g, W
@@ -351,6 +357,42 @@ def test_unet_against_torch_float64():
         Ft, gt, _ = _torch_unet(x, flat, base, L, 3, 2, 2)
         assert np.max(np.abs(F - Ft.numpy())) < 1e-10 * max(1.0, np.abs(F).max())
         assert np.max(np.abs(g - gt.numpy())) < 1e-10 * max(1.0, np.abs(g).max())
+
+
+def test_bf16_emulation_against_torch_bfloat16_model():
+    """The oracle's BF16 emulation as a whole path: the torch model with its
+    storage points rounded by torch's own bfloat16 conversion.  Both sum in
+    FP64, so their pre-rounding values agree to ~1e-16 and no rounding can
+    fall differently in practice; a missed storage point, or a weight rounded
+    that a BF16 backbone keeps in FP32, moves F by BF16 steps (the test makes
+    each of these two mistakes in the oracle and sees it caught)."""
+    rng = np.random.default_rng(18)
+    for base, L in [(4, 3), (8, 2), (6, 4)]:
+        cfg = O.make_config(base=base, levels=L, head_out=2, n_classes=3, scales=(0, 1))
+        flat = synth.he_normal_weights(19, base, L, 3, 2, 2, bias_std=0.1)
+        x = rng.uniform(size=(3, 16, 16))
+        wts = O.unpack_weights(flat, cfg)
+        F, g = O.unet_forward(x, O.bf16_weights(wts), cfg, store=O.round_bf16)
+        Ft, gt, _ = _torch_unet(x, flat, base, L, 3, 2, 2, bf16=True)
+        scale = max(1.0, np.abs(F).max())
+        assert np.max(np.abs(F - Ft.numpy())) < 1e-10 * scale
+        assert np.max(np.abs(g - gt.numpy())) < 1e-10 * max(1.0, np.abs(g).max())
+        # the comparison is sharp: the unrounded model is far from both
+        F64, _ = O.unet_forward(x, wts, cfg)
+        assert np.max(np.abs(F64 - F)) > 1e-6 * scale
+        # a single missing storage point (the first conv's output) is caught
+        skip = {"n": 0}
+
+        def store_all_but_first(v):
+            skip["n"] += 1
+            return v if skip["n"] == 1 else O.round_bf16(v)
+
+        Fm, _ = O.unet_forward(x, O.bf16_weights(wts), cfg, store=store_all_but_first)
+        assert np.max(np.abs(Fm - Ft.numpy())) > 1e-6 * scale
+        # and so is rounding the first conv's weights, which stay FP32
+        w_all = dict(O.bf16_weights(wts), **{"enc0.a.w": O.round_bf16(wts["enc0.a.w"])})
+        Fw, _ = O.unet_forward(x, w_all, cfg, store=O.round_bf16)
+        assert np.max(np.abs(Fw - Ft.numpy())) > 1e-6 * scale
 
 
 def test_bias_only_network_closed_form():
